@@ -1,0 +1,250 @@
+/*
+ * hra.h - hemispherical ray-casting accessibility on MI355X (gfx950).
+ *
+ * C ABI of libhra.so.  Every entry point follows the method of
+ * "Hemispherical Ray-Casting Analysis for Milling Configuration
+ * Classification and Machinability Assessment" (Baltadouros, Lauwers,
+ * Duflou); the section of the paper that defines each operation is cited
+ * beside it.
+ *
+ * Conventions shared by all calls
+ *  - Return value: hra_status, 0 (HRA_OK) on success, negative on error.
+ *    Calls never throw and never exit.  hra_last_error() gives the text of
+ *    the last error of a context.
+ *  - Pointers prefixed d_ are device pointers (HIP global memory on the
+ *    context's device).  Other pointers are host pointers.
+ *  - Ownership: the caller owns every array passed in or out and keeps it
+ *    alive until the work enqueued on `stream` has finished.  hra_ctx and
+ *    hra_bvh are opaque and owned by the library (create/destroy pairs).
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls enqueue their kernels on it and return without waiting,
+ *    except the ones marked "synchronises", which wait for the stream.
+ *  - Errors found by kernels (an index out of range, a traversal stack
+ *    overflow) are recorded in a per-context device error word and reported
+ *    as HRA_ERR_BAD_MESH or HRA_ERR_DEVICE by the next synchronising call.
+ *  - A context is not thread-safe; use one per host thread.
+ *  - Layouts: float [n][3] arrays are packed xyz triples.  Direction bitmask
+ *    rows have W = ceil(n_dirs / 32) uint32 words; bit (j % 32) of word
+ *    (j / 32) is direction j; 1 = unobstructed.
+ */
+#ifndef HRA_H
+#define HRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HRA_OK = 0,
+    HRA_ERR_INVALID_ARG = -1,
+    HRA_ERR_OUT_OF_MEMORY = -2,
+    HRA_ERR_DEVICE = -3,
+    HRA_ERR_BAD_MESH = -4,
+    HRA_ERR_OVER_BUDGET = -5,
+    HRA_ERR_NOT_READY = -6
+} hra_status;
+
+typedef struct hra_ctx hra_ctx;
+typedef struct hra_bvh hra_bvh;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  Allocates the device error word
+ * and the direction-table cache.  *out is set on success. */
+hra_status hra_ctx_create(int32_t device, hra_ctx **out);
+void hra_ctx_destroy(hra_ctx *ctx);
+/* Text of the last error on this context ("" if none).  Valid until the next
+ * call on the context. */
+const char *hra_last_error(const hra_ctx *ctx);
+/* Library version string. */
+const char *hra_version(void);
+
+/* -------------------------------------------------------------- mesh + BVH */
+
+typedef struct {
+    int32_t leaf_size; /* triangles per BVH leaf: 1..8; 0 = default (4) */
+} hra_bvh_opts;
+
+/* Mesh ingest and acceleration structure (Section 3.1: the part is a
+ * triangulated mesh; for each face its centroid, normal and area are
+ * computed).  d_verts: float [n_verts][3] in mm; d_tris: int32 [n_tris][3]
+ * vertex indices, counter-clockwise seen from outside.  The library copies
+ * what it needs; the inputs may be freed once the stream passes the call.
+ * Zero-area triangles are kept out of the hierarchy (never sampled, never
+ * hit) and counted.  Enqueues the build on `stream`.  Index errors surface
+ * as HRA_ERR_BAD_MESH at the next synchronising call; a mesh without any
+ * nonzero-area triangle fails there too. */
+hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t n_verts, const int32_t *d_tris,
+                         int64_t n_tris, const hra_bvh_opts *opts, void *stream, hra_bvh **out);
+
+typedef struct {
+    float bbox[6];         /* min xyz, max xyz of the vertices (the stock box) */
+    double diag;           /* |max - min| */
+    int64_t n_tris;        /* triangles given */
+    int64_t n_degenerate;  /* zero-area triangles (not in the hierarchy) */
+    int64_t n_nodes;       /* interior nodes of the hierarchy */
+    int64_t bytes;         /* device bytes held by the handle */
+    int32_t depth;         /* longest root-to-leaf path of interior nodes */
+    int32_t leaf_size;
+} hra_bvh_info;
+
+/* Copy the handle's summary to the host.  Synchronises `stream`. */
+hra_status hra_bvh_get_info(hra_bvh *bvh, void *stream, hra_bvh_info *out);
+void hra_bvh_release(hra_bvh *bvh);
+
+/* ----------------------------------------------------------------- samples */
+
+typedef struct {
+    float *point;   /* device float [n][3]: surface point p */
+    float *normal;  /* device float [n][3]: unit geometric normal of its face */
+    float *origin;  /* device float [n][3]: ray origin p + eps * normal */
+    int32_t *tri;   /* device int32 [n]: index of its face in the input mesh */
+    int64_t n;      /* number of samples */
+} hra_samples;
+
+enum { HRA_SAMPLE_AREA = 0, HRA_SAMPLE_CENTROID = 1 };
+
+/* Surface points to cast from (Section 3.1: rays leave a slightly offset
+ * face centroid).  mode HRA_SAMPLE_CENTROID: one sample per nonzero-area
+ * face, in face order (out->n must equal n_tris - n_degenerate).
+ * mode HRA_SAMPLE_AREA: out->n i.i.d. points with density proportional to
+ * area, drawn with the counter-based SplitMix64 stream `seed`.  The offset is
+ * eps = offset_frac x bbox diagonal (offset_frac in (0, 0.01]; 1e-4 is the
+ * usual value) along the face normal.  Caller allocates the four arrays. */
+hra_status hra_sample_surface(hra_ctx *ctx, const hra_bvh *bvh, int32_t mode, uint64_t seed,
+                              float offset_frac, const hra_samples *out, void *stream);
+
+/* -------------------------------------------------------------- directions */
+
+enum { HRA_DIRS_HEMI_FIBONACCI = 0, HRA_DIRS_AXES6 = 1 };
+
+typedef struct {
+    int32_t kind; /* HRA_DIRS_HEMI_FIBONACCI or HRA_DIRS_AXES6 */
+    int32_t n;    /* number of directions: 1..65536 (AXES6: 6) */
+} hra_dirs;
+
+/* Direction set (Section 3.1, Fig. 1: uniformly sampled hemisphere;
+ * Section 3.2: the six principal directions).  Writes the exact FP32 values
+ * the cast kernel uses to host_out[n][3]: local hemisphere points
+ * (x, y, z > 0) for the Fibonacci set, world +X,-X,+Y,-Y,+Z,-Z for AXES6.
+ * Synchronises the context's internal stream. */
+hra_status hra_dirs_table(hra_ctx *ctx, hra_dirs dirs, float *host_out);
+
+/* ------------------------------------------------------------------ casting */
+
+/* Any-hit accessibility cast (Section 3.1: rays over the hemisphere rotated
+ * onto each face normal, from the offset point; a ray obstructed by any
+ * triangle is not counted; Section 3.2: rays along the six principal
+ * directions with the same kernel).  For HEMI_FIBONACCI the local direction
+ * l is rotated onto the sample normal with the orthonormal basis of Duff et
+ * al. (2017); for AXES6 the world direction is used and a direction with
+ * normal . D < 0 is not cast (bit 0).  Triangles block from both sides; rays
+ * extend over t in (0, inf).
+ * d_bits: uint32 [samples->n][W] (written in full); d_counts: uint32
+ * [samples->n] popcount of each row, or NULL. */
+hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
+                               uint32_t *d_bits, uint32_t *d_counts, void *stream);
+
+typedef struct {
+    int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
+    int32_t stack_depth;   /* traversal stack entries per lane held in LDS: 16, 24 or 32
+                              (deeper paths overflow into private memory) */
+} hra_cast_config;
+
+/* Launch shape of hra_cast_hemisphere for this context (defaults 64 / 24).
+ * Results do not depend on it; only speed does. */
+hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *cfg);
+hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
+
+/* The rays exactly as the cast kernel forms them, for checking: for the
+ * samples listed in d_sample_idx (int64 [n_idx]) writes
+ * d_out float [n_idx][n_dirs][6] = (origin xyz, direction xyz). */
+hra_status hra_debug_rays(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const int64_t *d_sample_idx,
+                          int64_t n_idx, float *d_out, void *stream);
+
+/* ------------------------------------------------- directional statistics */
+
+typedef struct {
+    float *mean;      /* device float [n][3]: signed mean of unobstructed world directions */
+    float *absmean;   /* device float [n][3]: mean of their absolute components */
+    int8_t *axis;     /* device int8 [n]: dominant axis 0/1/2, -1 if no ray is unobstructed */
+    float *conc;      /* device float [n]: axis concentration absmean[axis] / sum(absmean) */
+    uint32_t *hist;   /* device uint32 [8192]: world-direction histogram of unobstructed rays */
+    void *totals;     /* device scratch of hra_dirstats_bytes() bytes: part totals */
+} hra_dirstats;
+
+/* Bytes needed for hra_dirstats.totals for n samples. */
+int64_t hra_dirstats_bytes(int64_t n);
+
+/* Directional variability (Section 3.3: dominant axis alignment and
+ * directional concentration of each face from its unobstructed rays).
+ * Per sample with set U of unobstructed directions d_j (world frame, as
+ * cast): mean m = sum d_j / |U|, absmean A_k = sum |d_jk| / |U|; dominant
+ * axis = smallest k with |m_k| >= (1 - 1e-5) max |m|; concentration
+ * A_axis / (A_x + A_y + A_z).  Sums in FP64.  Histogram bin =
+ * zb * 128 + az with zb = min(63, floor((d_z/|d| + 1) 32)) and
+ * az = min(127, floor((atan2(d_y, d_x) + pi) 128 / (2 pi))), FP64.
+ * Part totals (counts per axis, blind samples, total unobstructed rays, sum
+ * of concentrations in a fixed order) go to out->totals for hra_classify. */
+hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
+                             const hra_dirstats *out, void *stream);
+
+typedef struct {
+    double min_access; /* multi-axis if overall accessibility < this (default 0.60) */
+    double min_share;  /* multi-axis if the largest dominant-axis share < this (default 0.45) */
+    double max_conc;   /* multi-axis if the mean axis concentration > this (default 0.40) */
+} hra_thresholds;
+
+typedef struct {
+    double access;          /* overall accessibility: unobstructed / (n * n_dirs) */
+    double share[3];        /* fraction of non-blind samples per dominant axis (sums to 1) */
+    double mean_conc;       /* mean concentration over non-blind samples */
+    int64_t n_samples;
+    int64_t n_blind;        /* samples with no unobstructed ray */
+    uint64_t n_unobstructed;
+    int32_t multi_axis;     /* 1 = multi-axis, 0 = 3-axis */
+    int32_t tripped;        /* bit 0 access, bit 1 share, bit 2 concentration */
+    int32_t near_tie;       /* an indicator lies within 1e-9 of its threshold */
+} hra_class_report;
+
+/* 3-axis versus multi-axis (Section 3.3: three indicators; if any
+ * threshold is exceeded the part needs multi-axis machining).  thresholds
+ * NULL = defaults.  Reads the totals written by hra_dominant_axes for the
+ * same n and n_dirs.  Synchronises `stream`. */
+hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int64_t n, int32_t n_dirs,
+                        const hra_thresholds *thresholds, hra_class_report *out, void *stream);
+
+/* ------------------------------------------------------------------ setups */
+
+enum { HRA_CLASS_VIABLE = 0, HRA_CLASS_OVER = 1, HRA_CLASS_INACCESSIBLE = 2, HRA_CLASS_FIXTURE = 3 };
+
+typedef struct {
+    int32_t min_count;   /* exact minimum number of setup directions */
+    int32_t min_mask;    /* its directions, bit k: +X,-X,+Y,-Y,+Z,-Z; smallest mask on ties */
+    int32_t greedy_count;/* the greedy set cover's count */
+    int32_t greedy_mask;
+    int64_t n_class[4];  /* samples per class: viable, over-threshold, inaccessible, fixture */
+    uint32_t code_hist[64]; /* viable samples per 6-bit reachable-direction code */
+} hra_setup_report;
+
+/* Reachability and minimum setups (Section 3.3, last paragraph: for each
+ * accessible principal direction the tool travel is checked against the
+ * usable tool length; bounding-box faces are fixture faces; remaining faces
+ * are viable, over-threshold or inaccessible; a set cover over viable faces
+ * gives the setup count).  d_axes_bits: uint32 [n] from hra_cast_hemisphere
+ * with HRA_DIRS_AXES6.  Travel along +k is bbox_max_k - p_k, along -k
+ * p_k - bbox_min_k (FP64); reachable iff accessible and travel <= tool
+ * length.  A fixture face has all three vertices on one bbox plane within
+ * 1e-6 x diag.  The minimum is exact (all 63 subsets); the greedy count is
+ * reported beside it.  d_class: uint8 [n] or NULL.  Synchronises. */
+hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples,
+                          const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
+                          hra_setup_report *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRA_H */

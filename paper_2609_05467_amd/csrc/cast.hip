@@ -1,0 +1,394 @@
+// Any-hit accessibility cast: BVH traversal with a short per-lane stack in
+// LDS, robust slab tests, FP32 edge functions with an error bound and an FP64
+// fallback, and wave-ballot packing of direction bits.
+//
+// Decision per (ray, triangle), origin o, direction d, a,b,c = v - o:
+//   e0 = d.(b x c), e1 = d.(c x a), e2 = d.(a x b)   (side of each edge)
+//   h  = a.(b x c)                                  (side of the plane)
+// The ray meets the triangle at t > 0 iff all e_i share a sign s (edges
+// inclusive) and h has the sign s.  Each FP32 value is trusted only when its
+// magnitude exceeds K times the sum of the magnitudes of its terms (K covers
+// the rounding of the translated vertices, products and sums); otherwise it is
+// recomputed in FP64 from the FP32 inputs.  A sign trusted this way is the
+// exact sign, so a ray whose verdict is not on a knife edge gets the exact
+// answer.  The trust test and the FP64 value are antisymmetric in the two
+// vertices of an edge, so two triangles sharing an edge see it on opposite
+// sides and no ray slips between them.
+#include "common.hpp"
+
+namespace hra {
+
+constexpr float EDGE_K = 1.0e-6f;   // ~16.8 units of FP32 roundoff
+constexpr int SPILL = 64;           // private overflow entries per lane beyond the LDS stack
+
+struct CastArgs {
+    const Node *nodes;
+    const float4 *tris;
+    const BvhMeta *meta;
+    const float *origin;
+    const float *normal;
+    const float4 *dirs;
+    uint32_t *bits;
+    uint32_t *counter;
+    uint32_t *err;
+    int64_t n_samples;
+    int32_t n_dirs;
+    int32_t kind;       // 0: rotate hemisphere onto the normal, 1: world axes (cull n.D < 0)
+    int32_t W;          // words per row
+    int32_t chunks;     // work items per sample
+    uint32_t n_items;
+    int32_t n_nodes_alloc;  // node array length (bounds guard)
+    int32_t n_tris_alloc;   // leaf-ordered triangles (bounds guard)
+};
+
+__device__ __noinline__ int edge_sign64(float ox, float oy, float oz, float dx, float dy, float dz, float4 P, float4 Q) {
+    const double bx = (double)P.x - (double)ox, by = (double)P.y - (double)oy, bz = (double)P.z - (double)oz;
+    const double cx = (double)Q.x - (double)ox, cy = (double)Q.y - (double)oy, cz = (double)Q.z - (double)oz;
+    const double p1 = by * cz, p2 = bz * cy, p3 = bz * cx, p4 = bx * cz, p5 = bx * cy, p6 = by * cx;
+    const double X = p1 - p2, Y = p3 - p4, Z = p5 - p6;
+    const double t0 = (double)dx * X, t1 = (double)dy * Y, t2 = (double)dz * Z;
+    const double e = (t0 + t1) + t2;
+    return (e > 0.0) - (e < 0.0);
+}
+
+__device__ __noinline__ int plane_sign64(float ox, float oy, float oz, float4 A, float4 B, float4 C) {
+    const double ax = (double)A.x - (double)ox, ay = (double)A.y - (double)oy, az = (double)A.z - (double)oz;
+    const double bx = (double)B.x - (double)ox, by = (double)B.y - (double)oy, bz = (double)B.z - (double)oz;
+    const double cx = (double)C.x - (double)ox, cy = (double)C.y - (double)oy, cz = (double)C.z - (double)oz;
+    const double X = by * cz - bz * cy, Y = bz * cx - bx * cz, Z = bx * cy - by * cx;
+    const double h = (ax * X + ay * Y) + az * Z;
+    return (h > 0.0) - (h < 0.0);
+}
+
+// FP32 edge function of edge (P, Q) with its trust bound.  Returns +1/-1 when
+// the sign is certain, 2 when it is not.
+__device__ inline int edge_sign32(float dx, float dy, float dz, float px, float py, float pz, float qx, float qy,
+                                  float qz) {
+    const float p1 = py * qz, p2 = pz * qy, p3 = pz * qx, p4 = px * qz, p5 = px * qy, p6 = py * qx;
+    const float X = p1 - p2, Y = p3 - p4, Z = p5 - p6;
+    const float e = fmaf(dz, Z, fmaf(dy, Y, dx * X));
+    const float m = fmaf(fabsf(dz), fabsf(p5) + fabsf(p6),
+                         fmaf(fabsf(dy), fabsf(p3) + fabsf(p4), fabsf(dx) * (fabsf(p1) + fabsf(p2))));
+    const float bound = EDGE_K * m;
+    if (e > bound) return 1;
+    if (e < -bound) return -1;
+    return 2;
+}
+
+__device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy, float dz, float4 A, float4 B, float4 C) {
+    const float ax = A.x - ox, ay = A.y - oy, az = A.z - oz;
+    const float bx = B.x - ox, by = B.y - oy, bz = B.z - oz;
+    const float cx = C.x - ox, cy = C.y - oy, cz = C.z - oz;
+    int s0 = edge_sign32(dx, dy, dz, bx, by, bz, cx, cy, cz);
+    int s1 = edge_sign32(dx, dy, dz, cx, cy, cz, ax, ay, az);
+    // certain opposite signs: the line misses the triangle
+    if ((s0 == 1 && s1 == -1) || (s0 == -1 && s1 == 1)) return false;
+    int s2 = edge_sign32(dx, dy, dz, ax, ay, az, bx, by, bz);
+    if ((s2 == 1 && (s0 == -1 || s1 == -1)) || (s2 == -1 && (s0 == 1 || s1 == 1))) return false;
+    if (s0 == 2) s0 = edge_sign64(ox, oy, oz, dx, dy, dz, B, C);
+    if (s1 == 2) s1 = edge_sign64(ox, oy, oz, dx, dy, dz, C, A);
+    if (s2 == 2) s2 = edge_sign64(ox, oy, oz, dx, dy, dz, A, B);
+    int s;
+    if (s0 >= 0 && s1 >= 0 && s2 >= 0 && (s0 | s1 | s2)) s = 1;
+    else if (s0 <= 0 && s1 <= 0 && s2 <= 0 && (s0 | s1 | s2)) s = -1;
+    else return false;
+    // plane side: h = a.(b x c)
+    const float p1 = by * cz, p2 = bz * cy, p3 = bz * cx, p4 = bx * cz, p5 = bx * cy, p6 = by * cx;
+    const float X = p1 - p2, Y = p3 - p4, Z = p5 - p6;
+    const float h = fmaf(az, Z, fmaf(ay, Y, ax * X));
+    const float m = fmaf(fabsf(az), fabsf(p5) + fabsf(p6),
+                         fmaf(fabsf(ay), fabsf(p3) + fabsf(p4), fabsf(ax) * (fabsf(p1) + fabsf(p2))));
+    const float bound = EDGE_K * m;
+    int hs;
+    if (h > bound) hs = 1;
+    else if (h < -bound) hs = -1;
+    else hs = plane_sign64(ox, oy, oz, A, B, C);
+    return hs == s;
+}
+
+// Slab test, conservative: exact-ray intersections are never rejected.  A
+// zero direction component is replaced by +-1e30 in the inverse so no NaN
+// arises; the far distance is widened by 4e-7 relative (more than the
+// rounding of (bound - o) * inv, cf. Ize 2013, "Robust BVH Ray Traversal").
+__device__ inline bool slab(float lx, float ly, float lz, float hx, float hy, float hz, float ox, float oy, float oz,
+                            float ix, float iy, float iz, float &tn) {
+    const float tx0 = (lx - ox) * ix, tx1 = (hx - ox) * ix;
+    const float ty0 = (ly - oy) * iy, ty1 = (hy - oy) * iy;
+    const float tz0 = (lz - oz) * iz, tz1 = (hz - oz) * iz;
+    const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+    tn = tmin;
+    return tmin <= tmax * 1.0000004f;
+}
+
+__device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, float ox, float oy, float oz, float dx,
+                                float dy, float dz, int32_t n_tris_alloc, uint32_t *err) {
+    const int first = leaf_first(code), cnt = leaf_count(code);
+    if (first + cnt > n_tris_alloc) {
+        atomicOr(err, ERR_STACK);
+        return true;
+    }
+    for (int k = 0; k < cnt; ++k) {
+        const float4 *t = tris + 3 * (int64_t)(first + k);
+        if (tri_hit(ox, oy, oz, dx, dy, dz, t[0], t[1], t[2])) return true;
+    }
+    return false;
+}
+
+// true if some triangle blocks the ray
+// Guards: a node index outside the array, a leaf run outside the triangle
+// array, or more node visits than twice the node count set the error word
+// and end the ray, so a malformed hierarchy cannot fault or spin.
+template <int STACK>
+__device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
+                                float oy, float oz, float dx, float dy, float dz, int *lds, int lane, uint32_t *err,
+                                int32_t n_nodes_alloc, int32_t n_tris_alloc) {
+    if (is_leaf(root)) return leaf_hit(tris, root, ox, oy, oz, dx, dy, dz, n_tris_alloc, err);
+    const float ix = dx != 0.0f ? 1.0f / dx : copysignf(1e30f, dx);
+    const float iy = dy != 0.0f ? 1.0f / dy : copysignf(1e30f, dy);
+    const float iz = dz != 0.0f ? 1.0f / dz : copysignf(1e30f, dz);
+    int spill[SPILL];
+    int sp = 0;
+    int32_t node = root;
+    int64_t budget = 2 * (int64_t)n_nodes_alloc + 64;
+    while (true) {
+        if ((uint32_t)node >= (uint32_t)n_nodes_alloc || --budget < 0) {
+            atomicOr(err, ERR_STACK);
+            return true;
+        }
+        const Node *nd = nodes + node;
+        const float4 A = nd->a, B = nd->b, C = nd->c;
+        const int4 D = nd->d;
+        float t0, t1;
+        const bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, ox, oy, oz, ix, iy, iz, t0);
+        const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, ox, oy, oz, ix, iy, iz, t1);
+        const int32_t c0 = D.x, c1 = D.y;
+        if (h0 && is_leaf(c0) && leaf_hit(tris, c0, ox, oy, oz, dx, dy, dz, n_tris_alloc, err)) return true;
+        if (h1 && is_leaf(c1) && leaf_hit(tris, c1, ox, oy, oz, dx, dy, dz, n_tris_alloc, err)) return true;
+        const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
+        if (g0 && g1) {
+            const int32_t nearc = t0 <= t1 ? c0 : c1, farc = t0 <= t1 ? c1 : c0;
+            if (sp < STACK) lds[sp * 64 + lane] = farc;
+            else if (sp < STACK + SPILL) spill[sp - STACK] = farc;
+            else {
+                atomicOr(err, ERR_STACK);
+                return true;
+            }
+            ++sp;
+            node = nearc;
+        } else if (g0) {
+            node = c0;
+        } else if (g1) {
+            node = c1;
+        } else {
+            if (sp == 0) return false;
+            --sp;
+            node = sp < STACK ? lds[sp * 64 + lane] : spill[sp - STACK];
+        }
+    }
+}
+
+template <int RPW, int STACK>
+__global__ __launch_bounds__(256) void k_cast(CastArgs a) {
+    __shared__ int stk[4][STACK * 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int *lds = stk[wv];
+    const int32_t root = a.meta->root;
+    const int32_t n_valid = a.meta->n_valid;
+    const bool empty = n_valid <= 0;
+    const int32_t n_tris_alloc = n_valid < a.n_tris_alloc ? n_valid : a.n_tris_alloc;
+    while (true) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(a.counter, 1u);
+        item = __shfl(item, 0);
+        if (item >= a.n_items) break;
+        const int64_t s = item / (uint32_t)a.chunks;
+        const int32_t ch = (int32_t)(item % (uint32_t)a.chunks);
+        const float ox = a.origin[3 * s], oy = a.origin[3 * s + 1], oz = a.origin[3 * s + 2];
+        const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
+        float3 t, b;
+        onb_frame(nx, ny, nz, t, b);
+        uint32_t *row = a.bits + s * a.W;
+#pragma unroll 1
+        for (int r = 0; r < RPW / 64; ++r) {
+            const int32_t jb = ch * RPW + r * 64;
+            if (jb >= a.n_dirs) break;
+            const int32_t j = jb + lane;
+            bool free_ray = false;
+            if (j < a.n_dirs) {
+                const float4 l = a.dirs[j];
+                float dx, dy, dz;
+                bool cast = true;
+                if (a.kind == 0) {
+                    const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+                    dx = d.x;
+                    dy = d.y;
+                    dz = d.z;
+                } else {
+                    dx = l.x;
+                    dy = l.y;
+                    dz = l.z;
+                    const float q0 = nx * dx, q1 = ny * dy, q2 = nz * dz;
+                    const float nd = (q0 + q1) + q2;
+                    cast = !(nd < 0.0f);
+                }
+                if (cast) free_ray = empty || !occluded<STACK>(a.nodes, a.tris, root, ox, oy, oz, dx, dy, dz, lds, lane, a.err,
+                                                                   a.n_nodes_alloc, n_tris_alloc);
+            }
+            const uint64_t m = __ballot(free_ray);
+            if (lane == 0) {
+                const int32_t w = jb >> 5;
+                row[w] = (uint32_t)m;
+                if (w + 1 < a.W) row[w + 1] = (uint32_t)(m >> 32);
+            }
+        }
+    }
+}
+
+__global__ void k_zero_counter(uint32_t *c) {
+    if (threadIdx.x == 0) c[0] = 0;
+}
+
+__global__ void k_popcount_rows(const uint32_t *bits, int64_t n, int32_t W, uint32_t *counts) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    uint32_t c = 0;
+    for (int32_t w = 0; w < W; ++w) c += __popc(bits[s * W + w]);
+    counts[s] = c;
+}
+
+template <int RPW, int STACK>
+static hipError_t launch_cast(hra_ctx *ctx, const CastArgs &args, hipStream_t s) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cast<RPW, STACK>, 256, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t blocks = (int64_t)ctx->n_cu * per_cu;
+    const int64_t need = ((int64_t)args.n_items + 3) / 4;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    k_zero_counter<<<1, 64, 0, s>>>(args.counter);
+    k_cast<RPW, STACK><<<(unsigned)blocks, 256, 0, s>>>(args);
+    return hipGetLastError();
+}
+
+template <int RPW>
+static hipError_t launch_rpw(hra_ctx *ctx, const CastArgs &a, int stack, hipStream_t s) {
+    switch (stack) {
+        case 16: return launch_cast<RPW, 16>(ctx, a, s);
+        case 32: return launch_cast<RPW, 32>(ctx, a, s);
+        default: return launch_cast<RPW, 24>(ctx, a, s);
+    }
+}
+
+hipError_t launch_cast_any(hra_ctx *ctx, const CastArgs &a, int rpw, int stack, hipStream_t s) {
+    switch (rpw) {
+        case 128: return launch_rpw<128>(ctx, a, stack, s);
+        case 256: return launch_rpw<256>(ctx, a, stack, s);
+        default: return launch_rpw<64>(ctx, a, stack, s);
+    }
+}
+
+// The rays as the cast forms them: out[i][j] = (o, d).
+__global__ void k_debug_rays(const float *origin, const float *normal, const int64_t *idx, int64_t n_idx, int64_t n_samples,
+                             const float4 *dirs, int32_t n_dirs, int32_t kind, float *out) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_idx * n_dirs) return;
+    const int64_t k = g / n_dirs;
+    const int32_t j = (int32_t)(g % n_dirs);
+    const int64_t s = idx[k];
+    float *o6 = out + 6 * g;
+    if (s < 0 || s >= n_samples) {
+        for (int q = 0; q < 6; ++q) o6[q] = __int_as_float(0x7fc00000);
+        return;
+    }
+    const float nx = normal[3 * s], ny = normal[3 * s + 1], nz = normal[3 * s + 2];
+    float3 t, b;
+    onb_frame(nx, ny, nz, t, b);
+    const float4 l = dirs[j];
+    float3 d = kind == 0 ? rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z) : make_float3(l.x, l.y, l.z);
+    o6[0] = origin[3 * s];
+    o6[1] = origin[3 * s + 1];
+    o6[2] = origin[3 * s + 2];
+    o6[3] = d.x;
+    o6[4] = d.y;
+    o6[5] = d.z;
+}
+
+}  // namespace hra
+
+using namespace hra;
+
+extern "C" hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *cfg) {
+    if (!ctx || !cfg) return HRA_ERR_INVALID_ARG;
+    if (cfg->rays_per_wave != 64 && cfg->rays_per_wave != 128 && cfg->rays_per_wave != 256)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "rays_per_wave must be 64, 128 or 256");
+    if (cfg->stack_depth != 16 && cfg->stack_depth != 24 && cfg->stack_depth != 32)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth must be 16, 24 or 32");
+    ctx->cast_rpw = cfg->rays_per_wave;
+    ctx->cast_stack = cfg->stack_depth;
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg) {
+    if (!ctx || !cfg) return HRA_ERR_INVALID_ARG;
+    cfg->rays_per_wave = ctx->cast_rpw;
+    cfg->stack_depth = ctx->cast_stack;
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
+                                          uint32_t *d_bits, uint32_t *d_counts, void *stream) {
+    if (!ctx || !bvh || !samples) return HRA_ERR_INVALID_ARG;
+    if (!d_bits || !samples->origin || !samples->normal || samples->n < 0)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "bits, origins and normals must be non-null");
+    const float4 *table = nullptr;
+    hra_status st = dir_table(ctx, dirs, &table);
+    if (st != HRA_OK) return st;
+    if (samples->n == 0) return HRA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(hipSetDevice(ctx->device));
+    CastArgs a;
+    a.nodes = bvh->nodes;
+    a.tris = bvh->tris;
+    a.meta = bvh->meta;
+    a.origin = samples->origin;
+    a.normal = samples->normal;
+    a.dirs = table;
+    a.bits = d_bits;
+    a.counter = ctx->d_counter;
+    a.err = ctx->d_err;
+    a.n_samples = samples->n;
+    a.n_dirs = dirs.n;
+    a.kind = dirs.kind == HRA_DIRS_AXES6 ? 1 : 0;
+    a.W = (dirs.n + 31) / 32;
+    a.n_nodes_alloc = (int32_t)(bvh->n_tris > 1 ? bvh->n_tris - 1 : 1);
+    a.n_tris_alloc = (int32_t)bvh->n_tris;
+    const int rpw = ctx->cast_rpw;
+    a.chunks = (dirs.n + rpw - 1) / rpw;
+    const int64_t items = samples->n * (int64_t)a.chunks;
+    if (items >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call (split the samples)");
+    a.n_items = (uint32_t)items;
+    HRA_HIP(launch_cast_any(ctx, a, rpw, ctx->cast_stack, s));
+    if (d_counts) {
+        k_popcount_rows<<<blocks_for(samples->n, 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);
+        HRA_HIP(hipGetLastError());
+    }
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_debug_rays(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const int64_t *d_sample_idx,
+                                     int64_t n_idx, float *d_out, void *stream) {
+    if (!ctx || !samples || !d_sample_idx || !d_out || n_idx < 0) return HRA_ERR_INVALID_ARG;
+    const float4 *table = nullptr;
+    hra_status st = dir_table(ctx, dirs, &table);
+    if (st != HRA_OK) return st;
+    if (n_idx == 0) return HRA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(hipSetDevice(ctx->device));
+    const int64_t total = n_idx * dirs.n;
+    k_debug_rays<<<blocks_for(total, 256), 256, 0, s>>>(samples->origin, samples->normal, d_sample_idx, n_idx, samples->n,
+                                                       table, dirs.n, dirs.kind == HRA_DIRS_AXES6 ? 1 : 0, d_out);
+    HRA_HIP(hipGetLastError());
+    return HRA_OK;
+}

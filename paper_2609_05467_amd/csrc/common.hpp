@@ -1,0 +1,159 @@
+// Internal declarations shared by the libhra translation units.
+//
+// All device code here is compiled with -ffp-contract=off and correctly
+// rounded FP32 division and square root, so every FP32 expression below is
+// the sequence of IEEE operations it spells out; fused multiply-adds appear
+// only where written as fmaf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+
+#include "../../include/hra.h"
+
+namespace hra {
+
+// ---------------------------------------------------------------- errors
+enum : uint32_t {
+    ERR_BAD_INDEX = 1u << 0,     // a triangle index outside [0, n_verts)
+    ERR_EMPTY_MESH = 1u << 1,    // no triangle with nonzero area
+    ERR_STACK = 1u << 2,         // traversal stack exhausted
+    ERR_BAD_SAMPLE_TRI = 1u << 3 // a sample names a face that is not in the mesh
+};
+
+#define HRA_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- node layout
+// Binary node, 64 bytes = four 16-byte loads: both child boxes and both
+// child references.  A child reference >= 0 is an interior node index;
+// with bit 31 set it is a leaf: bits 27..30 hold count-1, bits 0..26 the
+// first triangle of a contiguous run in the leaf-ordered triangle array.
+struct alignas(16) Node {
+    float4 a;  // lo0.x lo0.y lo0.z hi0.x
+    float4 b;  // hi0.y hi0.z lo1.x lo1.y
+    float4 c;  // lo1.z hi1.x hi1.y hi1.z
+    int4 d;    // child0 child1 (unused) (unused)
+};
+static_assert(sizeof(Node) == 64, "node is 64 bytes");
+
+__host__ __device__ inline int32_t leaf_code(int32_t first, int32_t count) {
+    return (int32_t)(0x80000000u | ((uint32_t)(count - 1) << 27) | (uint32_t)first);
+}
+__host__ __device__ inline bool is_leaf(int32_t c) { return c < 0; }
+__host__ __device__ inline int32_t leaf_first(int32_t c) { return c & 0x07FFFFFF; }
+__host__ __device__ inline int32_t leaf_count(int32_t c) { return (int32_t)(((uint32_t)c >> 27) & 15u) + 1; }
+
+// Per-mesh facts written by the build kernels and read by later kernels,
+// so that no host round trip is needed between stages.
+struct BvhMeta {
+    float bbox[6];       // vertex bbox: min xyz, max xyz
+    double diag;         // |max - min| in FP64
+    double amax;         // largest triangle area
+    uint64_t total_w;    // sum of the integer area weights
+    int32_t k_scale;     // weights = floor(area * 2^k_scale)
+    int32_t n_valid;     // nonzero-area triangles
+    int32_t root;        // root reference (interior index or leaf code)
+    int32_t depth;       // interior-node depth of the emitted hierarchy
+    int32_t n_nodes;     // emitted interior nodes
+    int32_t pad;
+};
+
+}  // namespace hra
+
+// ---------------------------------------------------------------- handles
+struct hra_ctx {
+    int32_t device = 0;
+    int32_t n_cu = 0;
+    uint32_t *d_err = nullptr;        // device error word
+    uint32_t *d_counter = nullptr;    // work counters for persistent kernels (64 words)
+    hipStream_t own = nullptr;        // internal stream for table builds
+    int32_t cast_rpw = 64;            // directions per wave work item
+    int32_t cast_stack = 24;          // LDS stack entries per lane
+    std::string err;
+    std::map<std::pair<int, int>, float4 *> dir_tables;  // (kind, n) -> device float4 [n]
+    std::mutex mu;
+
+    hra_status fail(hra_status s, const char *what, const char *detail = nullptr) {
+        err = what ? what : "";
+        if (detail) {
+            err += ": ";
+            err += detail;
+        }
+        return s;
+    }
+    hra_status ok() { return HRA_OK; }
+};
+
+struct hra_bvh {
+    hra_ctx *ctx = nullptr;
+    int64_t n_tris = 0;
+    int64_t n_verts = 0;
+    int32_t leaf_size = 4;
+    hra::Node *nodes = nullptr;      // [max(1, n_valid - 1)]
+    float4 *tris = nullptr;          // [n_valid][3], leaf order, w = original index
+    int32_t *leaf_pos = nullptr;     // [n_tris] position in leaf order, -1 if degenerate
+    int32_t *valid_rank = nullptr;   // [n_tris] rank among nonzero-area faces, -1 if degenerate
+    uint64_t *prefix = nullptr;      // [n_tris] inclusive prefix of integer area weights
+    hra::BvhMeta *meta = nullptr;    // device
+    int64_t bytes = 0;
+};
+
+namespace hra {
+
+// ---------------------------------------------------------------- helpers
+hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out);
+hra_status check_error_word(hra_ctx *ctx, hipStream_t s);
+int blocks_for(int64_t n, int threads);
+
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based stream: output
+// c of stream `seed` mixes seed + (c + 1) * golden gamma.
+__host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Orthonormal basis (t, b, n) from a unit normal: Duff, Burgess,
+// Christensen, Hery, Kensler, Liani, Villemin, "Building an Orthonormal
+// Basis, Revisited" (JCGT 2017), branchless form, FP32, in a fixed order.
+__device__ inline void onb_frame(float nx, float ny, float nz, float3 &t, float3 &b) {
+    const float sign = copysignf(1.0f, nz);
+    const float a = -1.0f / (sign + nz);
+    const float nxny = nx * ny;
+    const float bb = nxny * a;
+    const float snx = sign * nx;
+    const float snxnx = snx * nx;
+    const float snxnxa = snxnx * a;
+    t.x = 1.0f + snxnxa;
+    t.y = sign * bb;
+    t.z = -(sign * nx);
+    const float nyny = ny * ny;
+    const float nynya = nyny * a;
+    b.x = bb;
+    b.y = sign + nynya;
+    b.z = -ny;
+}
+
+// World direction of the local hemisphere point l: d_c = l.x t_c + l.y b_c
+// + l.z n_c evaluated as fma(l.x, t_c, fma(l.y, b_c, l.z * n_c)).
+__device__ inline float3 rotate_dir(const float3 &t, const float3 &b, float nx, float ny, float nz, float lx,
+                                    float ly, float lz) {
+    float3 d;
+    const float zx = lz * nx, zy = lz * ny, zz = lz * nz;
+    d.x = fmaf(lx, t.x, fmaf(ly, b.x, zx));
+    d.y = fmaf(lx, t.y, fmaf(ly, b.y, zy));
+    d.z = fmaf(lx, t.z, fmaf(ly, b.z, zz));
+    return d;
+}
+
+}  // namespace hra

@@ -1,0 +1,151 @@
+// Context, error word, direction tables.
+#include "common.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace hra {
+
+int blocks_for(int64_t n, int threads) {
+    int64_t b = (n + threads - 1) / threads;
+    return (int)(b < 1 ? 1 : b);
+}
+
+// Spherical Fibonacci points on the open upper hemisphere (a uniformly
+// sampled hemisphere, Section 3.1 and Fig. 1):
+//   z_j = 1 - (2j+1)/(2N), r_j = sqrt(1 - z_j^2), phi_j = 2 pi frac(j g),
+//   g = (3 - sqrt 5)/2, evaluated in FP64 and rounded once to FP32.
+__global__ void k_fibonacci(int32_t n, float4 *out) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double g = (3.0 - sqrt(5.0)) / 2.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double z = 1.0 - (2.0 * (double)j + 1.0) / (2.0 * (double)n);
+    const double zz = z * z;
+    const double r = sqrt(1.0 - zz);
+    const double jg = (double)j * g;
+    const double f = jg - floor(jg);
+    const double phi = two_pi * f;
+    const double c = cos(phi), s = sin(phi);
+    out[j] = make_float4((float)(r * c), (float)(r * s), (float)z, 0.0f);
+}
+
+// Section 3.2: the six principal directions of the machining frame.
+__global__ void k_axes6(float4 *out) {
+    const int j = threadIdx.x;
+    if (j >= 6) return;
+    const float s = (j & 1) ? -1.0f : 1.0f;
+    const int ax = j >> 1;
+    out[j] = make_float4(ax == 0 ? s : 0.0f, ax == 1 ? s : 0.0f, ax == 2 ? s : 0.0f, 0.0f);
+}
+
+hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out) {
+    if (dirs.kind == HRA_DIRS_AXES6) {
+        if (dirs.n != 6) return ctx->fail(HRA_ERR_INVALID_ARG, "AXES6 needs n = 6");
+    } else if (dirs.kind == HRA_DIRS_HEMI_FIBONACCI) {
+        if (dirs.n < 1 || dirs.n > 65536) return ctx->fail(HRA_ERR_INVALID_ARG, "direction count must be in [1, 65536]");
+    } else {
+        return ctx->fail(HRA_ERR_INVALID_ARG, "unknown direction kind");
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto key = std::make_pair((int)dirs.kind, (int)dirs.n);
+    auto it = ctx->dir_tables.find(key);
+    if (it != ctx->dir_tables.end()) {
+        *out = it->second;
+        return HRA_OK;
+    }
+    float4 *p = nullptr;
+    HRA_HIP(hipMalloc(&p, sizeof(float4) * dirs.n));
+    if (dirs.kind == HRA_DIRS_AXES6)
+        k_axes6<<<1, 64, 0, ctx->own>>>(p);
+    else
+        k_fibonacci<<<blocks_for(dirs.n, 256), 256, 0, ctx->own>>>(dirs.n, p);
+    HRA_HIP(hipGetLastError());
+    // tables are built once per context on its own stream; later work on any
+    // stream may read them, so wait here
+    HRA_HIP(hipStreamSynchronize(ctx->own));
+    ctx->dir_tables[key] = p;
+    *out = p;
+    return HRA_OK;
+}
+
+hra_status check_error_word(hra_ctx *ctx, hipStream_t s) {
+    HRA_HIP(hipStreamSynchronize(s));
+    uint32_t w = 0;
+    HRA_HIP(hipMemcpy(&w, ctx->d_err, sizeof(w), hipMemcpyDeviceToHost));
+    if (w == 0) return HRA_OK;
+    HRA_HIP(hipMemset(ctx->d_err, 0, sizeof(uint32_t)));
+    if (w & ERR_BAD_INDEX) return ctx->fail(HRA_ERR_BAD_MESH, "triangle index out of range");
+    if (w & ERR_EMPTY_MESH) return ctx->fail(HRA_ERR_BAD_MESH, "mesh has no triangle with nonzero area");
+    if (w & ERR_BAD_SAMPLE_TRI) return ctx->fail(HRA_ERR_INVALID_ARG, "a sample names a face outside the mesh");
+    if (w & ERR_STACK) return ctx->fail(HRA_ERR_DEVICE, "traversal stack exhausted");
+    return ctx->fail(HRA_ERR_DEVICE, "device error word set");
+}
+
+}  // namespace hra
+
+using namespace hra;
+
+extern "C" {
+
+const char *hra_version(void) { return "hra 0.1 (gfx950)"; }
+
+hra_status hra_ctx_create(int32_t device, hra_ctx **out) {
+    if (!out) return HRA_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HRA_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return HRA_ERR_DEVICE;
+    hra_ctx *ctx = new hra_ctx();
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete ctx;
+        return HRA_ERR_DEVICE;
+    }
+    ctx->n_cu = prop.multiProcessorCount;
+    if (hipMalloc(&ctx->d_err, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ctx->d_counter, 64 * sizeof(uint32_t)) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) {
+        hra_ctx_destroy(ctx);
+        return HRA_ERR_OUT_OF_MEMORY;
+    }
+    if (hipMemset(ctx->d_err, 0, sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(ctx->d_counter, 0, 64 * sizeof(uint32_t)) != hipSuccess) {
+        hra_ctx_destroy(ctx);
+        return HRA_ERR_DEVICE;
+    }
+    *out = ctx;
+    return HRA_OK;
+}
+
+void hra_ctx_destroy(hra_ctx *ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    if (ctx->own) hipStreamSynchronize(ctx->own);
+    for (auto &kv : ctx->dir_tables) hipFree(kv.second);
+    if (ctx->d_err) hipFree(ctx->d_err);
+    if (ctx->d_counter) hipFree(ctx->d_counter);
+    if (ctx->own) hipStreamDestroy(ctx->own);
+    delete ctx;
+}
+
+const char *hra_last_error(const hra_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+hra_status hra_dirs_table(hra_ctx *ctx, hra_dirs dirs, float *host_out) {
+    if (!ctx || !host_out) return HRA_ERR_INVALID_ARG;
+    const float4 *d = nullptr;
+    hra_status st = dir_table(ctx, dirs, &d);
+    if (st != HRA_OK) return st;
+    std::vector<float4> h(dirs.n);
+    HRA_HIP(hipMemcpy(h.data(), d, sizeof(float4) * dirs.n, hipMemcpyDeviceToHost));
+    for (int32_t j = 0; j < dirs.n; ++j) {
+        host_out[3 * j + 0] = h[j].x;
+        host_out[3 * j + 1] = h[j].y;
+        host_out[3 * j + 2] = h[j].z;
+    }
+    return HRA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,333 @@
+// Directional statistics, classification, reachability and setups
+// (Section 3.3).
+#include "common.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace hra {
+
+struct DirTotals {
+    unsigned long long n_axis[3];
+    unsigned long long n_blind;
+    unsigned long long n_unob;
+    double conc_sum;
+    double pad[2];
+};
+
+constexpr int HIST_BINS = 8192;
+
+// One wavefront per sample: lanes stride over the directions, FP64 sums,
+// wave reduction, LDS-privatised integer histogram flushed at block end.
+__global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n, const float4 *dirs, int32_t N,
+                                                  int32_t W, const uint32_t *bits, hra_dirstats out, double *conc64,
+                                                  DirTotals *tot) {
+    __shared__ uint32_t h[HIST_BINS];
+    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const double pi = 3.14159265358979323846264338327950288;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < n; s += nwaves) {
+        const float nx = normal[3 * s], ny = normal[3 * s + 1], nz = normal[3 * s + 2];
+        float3 t, b;
+        onb_frame(nx, ny, nz, t, b);
+        double sm0 = 0, sm1 = 0, sm2 = 0, sa0 = 0, sa1 = 0, sa2 = 0;
+        uint32_t cnt = 0;
+        for (int32_t j = lane; j < N; j += 64) {
+            if (!((bits[s * W + (j >> 5)] >> (j & 31)) & 1u)) continue;
+            const float4 l = dirs[j];
+            const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+            const double dx = d.x, dy = d.y, dz = d.z;
+            sm0 += dx;
+            sm1 += dy;
+            sm2 += dz;
+            sa0 += fabs(dx);
+            sa1 += fabs(dy);
+            sa2 += fabs(dz);
+            ++cnt;
+            const double len = sqrt(dx * dx + dy * dy + dz * dz);
+            const double zh = dz / len;
+            int zb = (int)floor((zh + 1.0) * 32.0);
+            zb = zb > 63 ? 63 : (zb < 0 ? 0 : zb);
+            int az = (int)floor((atan2(dy, dx) + pi) * 128.0 / (2.0 * pi));
+            az = az > 127 ? 127 : (az < 0 ? 0 : az);
+            atomicAdd(&h[zb * 128 + az], 1u);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            sm0 += __shfl_xor(sm0, off);
+            sm1 += __shfl_xor(sm1, off);
+            sm2 += __shfl_xor(sm2, off);
+            sa0 += __shfl_xor(sa0, off);
+            sa1 += __shfl_xor(sa1, off);
+            sa2 += __shfl_xor(sa2, off);
+            cnt += __shfl_xor(cnt, off);
+        }
+        if (lane == 0) {
+            if (cnt == 0) {
+                for (int c = 0; c < 3; ++c) out.mean[3 * s + c] = out.absmean[3 * s + c] = 0.0f;
+                out.axis[s] = -1;
+                out.conc[s] = 0.0f;
+                conc64[s] = 0.0;
+                atomicAdd(&tot->n_blind, 1ull);
+            } else {
+                const double c = (double)cnt;
+                const double m[3] = {sm0 / c, sm1 / c, sm2 / c}, A[3] = {sa0 / c, sa1 / c, sa2 / c};
+                const double am[3] = {fabs(m[0]), fabs(m[1]), fabs(m[2])};
+                const double mx = fmax(am[0], fmax(am[1], am[2]));
+                int k = 0;
+                while (k < 2 && !(am[k] >= (1.0 - 1e-5) * mx)) ++k;
+                const double den = A[0] + A[1] + A[2];
+                const double cc = A[k] / den;
+                for (int q = 0; q < 3; ++q) {
+                    out.mean[3 * s + q] = (float)m[q];
+                    out.absmean[3 * s + q] = (float)A[q];
+                }
+                out.axis[s] = (int8_t)k;
+                out.conc[s] = (float)cc;
+                conc64[s] = cc;
+                atomicAdd(&tot->n_axis[k], 1ull);
+                atomicAdd(&tot->n_unob, (unsigned long long)cnt);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x)
+        if (h[k]) atomicAdd(&out.hist[k], h[k]);
+}
+
+__global__ void k_zero_stats(uint32_t *hist, DirTotals *tot) {
+    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) hist[k] = 0;
+    if (threadIdx.x == 0) {
+        tot->n_axis[0] = tot->n_axis[1] = tot->n_axis[2] = 0;
+        tot->n_blind = tot->n_unob = 0;
+        tot->conc_sum = 0.0;
+    }
+}
+
+// Fixed-order FP64 sum: thread t sums a contiguous chunk in order, then a
+// fixed tree over the 1024 partial sums.
+__global__ void k_sum_fixed(const double *x, int64_t n, double *out) {
+    __shared__ double s[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    double acc = 0.0;
+    for (int64_t i = t * chunk; i < n && i < (t + 1) * chunk; ++i) acc += x[i];
+    s[t] = acc;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (t < off) s[t] += s[t + off];
+        __syncthreads();
+    }
+    if (t == 0) *out = s[0];
+}
+
+// Reach, fixture faces, classes and the histogram of reachable-direction codes.
+__global__ void k_setups(const float *point, const int32_t *tri, int64_t n, const uint32_t *axes_bits, const float4 *tri4,
+                         const int32_t *leaf_pos, int64_t n_tris, const BvhMeta *meta, double tool, uint8_t *cls_out,
+                         unsigned long long *class_count, uint32_t *code_hist, uint32_t *err) {
+    __shared__ uint32_t hc[64];
+    __shared__ unsigned long long cc[4];
+    if (threadIdx.x < 64) hc[threadIdx.x] = 0;
+    if (threadIdx.x < 4) cc[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int32_t f = tri[i];
+        int32_t p = -1;
+        if (f >= 0 && f < n_tris) p = leaf_pos[f];
+        if (p < 0) {
+            atomicOr(err, ERR_BAD_SAMPLE_TRI);
+        } else {
+            double lo[3], hi[3];
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = meta->bbox[c];
+                hi[c] = meta->bbox[3 + c];
+            }
+            const double tol = 1e-6 * meta->diag;
+            const float4 v[3] = {tri4[3 * (int64_t)p], tri4[3 * (int64_t)p + 1], tri4[3 * (int64_t)p + 2]};
+            bool fixture = false;
+            for (int c = 0; c < 3 && !fixture; ++c) {
+                for (int side = 0; side < 2 && !fixture; ++side) {
+                    const double lim = side ? hi[c] : lo[c];
+                    bool all = true;
+                    for (int k = 0; k < 3; ++k) {
+                        const double x = c == 0 ? v[k].x : (c == 1 ? v[k].y : v[k].z);
+                        all = all && fabs(x - lim) <= tol;
+                    }
+                    fixture = all;
+                }
+            }
+            const double px = point[3 * i], py = point[3 * i + 1], pz = point[3 * i + 2];
+            const double travel[6] = {hi[0] - px, px - lo[0], hi[1] - py, py - lo[1], hi[2] - pz, pz - lo[2]};
+            const uint32_t acc = axes_bits[i] & 63u;
+            uint32_t code = 0;
+            for (int k = 0; k < 6; ++k)
+                if (((acc >> k) & 1u) && travel[k] <= tool) code |= 1u << k;
+            uint8_t cl;
+            if (fixture) cl = HRA_CLASS_FIXTURE;
+            else if (code) cl = HRA_CLASS_VIABLE;
+            else if (acc) cl = HRA_CLASS_OVER;
+            else cl = HRA_CLASS_INACCESSIBLE;
+            if (cls_out) cls_out[i] = cl;
+            atomicAdd(&cc[cl], 1ull);
+            if (cl == HRA_CLASS_VIABLE) atomicAdd(&hc[code], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && hc[threadIdx.x]) atomicAdd(&code_hist[threadIdx.x], hc[threadIdx.x]);
+    if (threadIdx.x < 4 && cc[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cc[threadIdx.x]);
+}
+
+__global__ void k_zero_setups(unsigned long long *cc, uint32_t *hist) {
+    if (threadIdx.x < 4) cc[threadIdx.x] = 0;
+    if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+}
+
+// Exact minimum hitting set over the 63 nonempty direction subsets; ties go
+// to the numerically smallest mask.
+void solve_setups(const uint32_t *hist, int32_t *min_count, int32_t *min_mask, int32_t *g_count, int32_t *g_mask) {
+    int best = -1, bestc = 7;
+    bool any = false;
+    for (int c = 1; c < 64; ++c) any = any || hist[c] > 0;
+    if (!any) {
+        *min_count = *min_mask = *g_count = *g_mask = 0;
+        return;
+    }
+    for (int m = 1; m < 64; ++m) {
+        bool ok = true;
+        for (int c = 1; c < 64 && ok; ++c)
+            if (hist[c] && !(c & m)) ok = false;
+        if (!ok) continue;
+        const int pc = __builtin_popcount(m);
+        if (pc < bestc || (pc == bestc && m < best)) {
+            bestc = pc;
+            best = m;
+        }
+    }
+    *min_count = bestc;
+    *min_mask = best;
+    // greedy set cover (the paper's strategy)
+    std::vector<uint64_t> left(hist, hist + 64);
+    int gm = 0, gc = 0;
+    while (true) {
+        uint64_t rem = 0;
+        for (int c = 1; c < 64; ++c) rem += left[c];
+        if (!rem) break;
+        int bk = -1;
+        uint64_t bg = 0;
+        for (int k = 0; k < 6; ++k) {
+            if (gm >> k & 1) continue;
+            uint64_t g = 0;
+            for (int c = 1; c < 64; ++c)
+                if (c >> k & 1) g += left[c];
+            if (g > bg) {
+                bg = g;
+                bk = k;
+            }
+        }
+        if (bk < 0) break;
+        gm |= 1 << bk;
+        ++gc;
+        for (int c = 1; c < 64; ++c)
+            if (c >> bk & 1) left[c] = 0;
+    }
+    *g_count = gc;
+    *g_mask = gm;
+}
+
+}  // namespace hra
+
+using namespace hra;
+
+extern "C" int64_t hra_dirstats_bytes(int64_t n) { return (int64_t)sizeof(DirTotals) + 8 * (n > 0 ? n : 0) + 64; }
+
+extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
+                                        const hra_dirstats *out, void *stream) {
+    if (!ctx || !samples || !d_bits || !out) return HRA_ERR_INVALID_ARG;
+    if (!out->mean || !out->absmean || !out->axis || !out->conc || !out->hist || !out->totals)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "all hra_dirstats arrays must be non-null");
+    if (dirs.kind != HRA_DIRS_HEMI_FIBONACCI)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "directional statistics need the hemisphere set");
+    const float4 *table = nullptr;
+    hra_status st = dir_table(ctx, dirs, &table);
+    if (st != HRA_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(hipSetDevice(ctx->device));
+    DirTotals *tot = (DirTotals *)out->totals;
+    double *c64 = (double *)((char *)out->totals + sizeof(DirTotals));
+    k_zero_stats<<<1, 256, 0, s>>>(out->hist, tot);
+    if (samples->n > 0) {
+        int64_t blocks = (samples->n + 3) / 4;
+        const int64_t cap = (int64_t)ctx->n_cu * 8;
+        if (blocks > cap) blocks = cap;
+        k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(samples->normal, samples->n, table, dirs.n, (dirs.n + 31) / 32, d_bits,
+                                                    *out, c64, tot);
+        k_sum_fixed<<<1, 1024, 0, s>>>(c64, samples->n, &tot->conc_sum);
+    }
+    HRA_HIP(hipGetLastError());
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int64_t n, int32_t n_dirs,
+                                   const hra_thresholds *th, hra_class_report *out, void *stream) {
+    if (!ctx || !stats || !stats->totals || !out || n < 0 || n_dirs < 1) return HRA_ERR_INVALID_ARG;
+    hra_status st = check_error_word(ctx, (hipStream_t)stream);
+    if (st != HRA_OK) return st;
+    DirTotals t;
+    HRA_HIP(hipMemcpy(&t, stats->totals, sizeof(t), hipMemcpyDeviceToHost));
+    const hra_thresholds def = {0.60, 0.45, 0.40};
+    const hra_thresholds &T = th ? *th : def;
+    const int64_t inc = n - (int64_t)t.n_blind;
+    out->n_samples = n;
+    out->n_blind = (int64_t)t.n_blind;
+    out->n_unobstructed = t.n_unob;
+    out->access = n ? (double)t.n_unob / ((double)n * (double)n_dirs) : 0.0;
+    for (int k = 0; k < 3; ++k) out->share[k] = inc ? (double)t.n_axis[k] / (double)inc : 0.0;
+    out->mean_conc = inc ? t.conc_sum / (double)inc : 0.0;
+    const double smax = fmax(out->share[0], fmax(out->share[1], out->share[2]));
+    int tr = 0;
+    if (out->access < T.min_access) tr |= 1;
+    if (smax < T.min_share) tr |= 2;
+    if (out->mean_conc > T.max_conc) tr |= 4;
+    out->tripped = tr;
+    out->multi_axis = tr ? 1 : 0;
+    out->near_tie = (fabs(out->access - T.min_access) <= 1e-9 || fabs(smax - T.min_share) <= 1e-9 ||
+                     fabs(out->mean_conc - T.max_conc) <= 1e-9)
+                        ? 1
+                        : 0;
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples,
+                                     const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
+                                     hra_setup_report *out, void *stream) {
+    if (!ctx || !bvh || !samples || !d_axes_bits || !out) return HRA_ERR_INVALID_ARG;
+    if (!samples->point || !samples->tri || samples->n < 0)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "sample points and faces must be non-null");
+    if (!(tool_length >= 0.0)) return ctx->fail(HRA_ERR_INVALID_ARG, "tool length must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(hipSetDevice(ctx->device));
+    unsigned long long *cc = nullptr;
+    uint32_t *hist = nullptr;
+    HRA_HIP(hipMallocAsync((void **)&cc, 4 * sizeof(unsigned long long) + 64 * sizeof(uint32_t), s));
+    hist = (uint32_t *)(cc + 4);
+    k_zero_setups<<<1, 64, 0, s>>>(cc, hist);
+    if (samples->n > 0)
+        k_setups<<<blocks_for(samples->n, 256), 256, 0, s>>>(samples->point, samples->tri, samples->n, d_axes_bits,
+                                                            bvh->tris, bvh->leaf_pos, bvh->n_tris, bvh->meta,
+                                                            tool_length, d_class, cc, hist, ctx->d_err);
+    unsigned long long hcc[4];
+    uint32_t hh[64];
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(hcc, cc, sizeof(hcc), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s);
+    hipFreeAsync(cc, s);
+    if (e != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, "min_setups launch failed", hipGetErrorString(e));
+    hra_status st = check_error_word(ctx, s);
+    if (st != HRA_OK) return st;
+    for (int k = 0; k < 4; ++k) out->n_class[k] = (int64_t)hcc[k];
+    for (int c = 0; c < 64; ++c) out->code_hist[c] = hh[c];
+    solve_setups(hh, &out->min_count, &out->min_mask, &out->greedy_count, &out->greedy_mask);
+    return HRA_OK;
+}

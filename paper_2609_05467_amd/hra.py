@@ -1,0 +1,293 @@
+"""Python binding of libhra.so (ctypes).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step runs in the library's HIP kernels.  The library must be
+built (`python -m paper_2609_05467_amd.build`); importing this module fails
+loudly if it is missing or if no GPU is present when a context is made.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhra.so")
+
+HRA_OK = 0
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "BAD_MESH", -5: "OVER_BUDGET",
+          -6: "NOT_READY"}
+SAMPLE_AREA, SAMPLE_CENTROID = 0, 1
+DIRS_HEMI, DIRS_AXES6 = 0, 1
+CLASS_VIABLE, CLASS_OVER, CLASS_INACCESSIBLE, CLASS_FIXTURE = 0, 1, 2, 3
+
+
+class HraError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hra error {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BvhOpts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32)]
+
+
+class BvhInfo(C.Structure):
+    _fields_ = [("bbox", C.c_float * 6), ("diag", C.c_double), ("n_tris", C.c_int64), ("n_degenerate", C.c_int64),
+                ("n_nodes", C.c_int64), ("bytes", C.c_int64), ("depth", C.c_int32), ("leaf_size", C.c_int32)]
+
+
+class Samples(C.Structure):
+    _fields_ = [("point", C.c_void_p), ("normal", C.c_void_p), ("origin", C.c_void_p), ("tri", C.c_void_p),
+                ("n", C.c_int64)]
+
+
+class Dirs(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32)]
+
+
+class CastConfig(C.Structure):
+    _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32)]
+
+
+class DirStats(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("absmean", C.c_void_p), ("axis", C.c_void_p), ("conc", C.c_void_p),
+                ("hist", C.c_void_p), ("totals", C.c_void_p)]
+
+
+class Thresholds(C.Structure):
+    _fields_ = [("min_access", C.c_double), ("min_share", C.c_double), ("max_conc", C.c_double)]
+
+
+class ClassReport(C.Structure):
+    _fields_ = [("access", C.c_double), ("share", C.c_double * 3), ("mean_conc", C.c_double),
+                ("n_samples", C.c_int64), ("n_blind", C.c_int64), ("n_unobstructed", C.c_uint64),
+                ("multi_axis", C.c_int32), ("tripped", C.c_int32), ("near_tie", C.c_int32)]
+
+
+class SetupReport(C.Structure):
+    _fields_ = [("min_count", C.c_int32), ("min_mask", C.c_int32), ("greedy_count", C.c_int32),
+                ("greedy_mask", C.c_int32), ("n_class", C.c_int64 * 4), ("code_hist", C.c_uint32 * 64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2609_05467_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, u64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_float, C.c_double
+        sig = {
+            "hra_ctx_create": ([i32, C.POINTER(P)], C.c_int),
+            "hra_ctx_destroy": ([P], None),
+            "hra_last_error": ([P], C.c_char_p),
+            "hra_version": ([], C.c_char_p),
+            "hra_build_bvh": ([P, P, i64, P, i64, C.POINTER(BvhOpts), P, C.POINTER(P)], C.c_int),
+            "hra_bvh_get_info": ([P, P, C.POINTER(BvhInfo)], C.c_int),
+            "hra_bvh_release": ([P], None),
+            "hra_sample_surface": ([P, P, i32, u64, f32, C.POINTER(Samples), P], C.c_int),
+            "hra_dirs_table": ([P, Dirs, P], C.c_int),
+            "hra_cast_hemisphere": ([P, P, C.POINTER(Samples), Dirs, P, P, P], C.c_int),
+            "hra_set_cast_config": ([P, C.POINTER(CastConfig)], C.c_int),
+            "hra_get_cast_config": ([P, C.POINTER(CastConfig)], C.c_int),
+            "hra_debug_rays": ([P, C.POINTER(Samples), Dirs, P, i64, P, P], C.c_int),
+            "hra_dirstats_bytes": ([i64], i64),
+            "hra_dominant_axes": ([P, C.POINTER(Samples), Dirs, P, C.POINTER(DirStats), P], C.c_int),
+            "hra_classify": ([P, C.POINTER(DirStats), i64, i32, C.POINTER(Thresholds), C.POINTER(ClassReport), P],
+                             C.c_int),
+            "hra_min_setups": ([P, P, C.POINTER(Samples), P, f64, P, C.POINTER(SetupReport), P], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version", "hra_build_bvh",
+           "hra_bvh_get_info", "hra_bvh_release", "hra_sample_surface", "hra_dirs_table", "hra_cast_hemisphere",
+           "hra_set_cast_config", "hra_get_cast_config", "hra_debug_rays", "hra_dirstats_bytes",
+           "hra_dominant_axes", "hra_classify", "hra_min_setups"]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(x, dtype, device):
+    t = torch.as_tensor(x)
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class Context:
+    """A library context on one GPU (one per host thread)."""
+
+    def __init__(self, device=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("hra needs a ROCm GPU; none is visible")
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        p = C.c_void_p()
+        st = lib().hra_ctx_create(device, C.byref(p))
+        if st != HRA_OK:
+            raise HraError(st, f"context creation on device {device} failed")
+        self.ptr = p
+
+    def _check(self, st):
+        if st != HRA_OK:
+            msg = lib().hra_last_error(self.ptr)
+            raise HraError(st, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().hra_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- mesh
+    def build_bvh(self, verts, tris, leaf_size=0, stream=None):
+        v = _dev_tensor(verts, torch.float32, self.device)
+        t = _dev_tensor(tris, torch.int32, self.device)
+        out = C.c_void_p()
+        opts = BvhOpts(leaf_size)
+        self._check(lib().hra_build_bvh(self.ptr, _ptr(v), v.shape[0], _ptr(t), t.shape[0], C.byref(opts),
+                                        _stream(stream), C.byref(out)))
+        return Bvh(self, out, (v, t), stream)
+
+    def dirs_table(self, n, kind=DIRS_HEMI):
+        import numpy as np
+        out = np.empty((n, 3), np.float32)
+        self._check(lib().hra_dirs_table(self.ptr, Dirs(kind, n), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_cast_config(self, rays_per_wave=64, stack_depth=24):
+        self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth))))
+
+    def cast_config(self):
+        c = CastConfig()
+        self._check(lib().hra_get_cast_config(self.ptr, C.byref(c)))
+        return c.rays_per_wave, c.stack_depth
+
+    # ---------------------------------------------------------------- samples
+    def alloc_samples(self, n):
+        d = self.device
+        return {"point": torch.empty((n, 3), dtype=torch.float32, device=d),
+                "normal": torch.empty((n, 3), dtype=torch.float32, device=d),
+                "origin": torch.empty((n, 3), dtype=torch.float32, device=d),
+                "tri": torch.empty((n,), dtype=torch.int32, device=d)}
+
+    @staticmethod
+    def _samples_struct(s):
+        n = s["origin"].shape[0]
+        for k in ("point", "normal", "origin"):
+            if k in s and s[k] is not None:
+                assert s[k].is_contiguous() and s[k].dtype == torch.float32 and s[k].shape == (n, 3), k
+        return Samples(_ptr(s.get("point")), _ptr(s.get("normal")), _ptr(s.get("origin")), _ptr(s.get("tri")), n)
+
+    def sample_surface(self, bvh, n, seed, mode=SAMPLE_AREA, offset_frac=1e-4, stream=None):
+        if mode == SAMPLE_CENTROID:
+            info = bvh.info(stream)
+            n = info.n_tris - info.n_degenerate
+        s = self.alloc_samples(n)
+        st = self._samples_struct(s)
+        self._check(lib().hra_sample_surface(self.ptr, bvh.ptr, mode, seed, offset_frac, C.byref(st), _stream(stream)))
+        return s
+
+    # ---------------------------------------------------------------- cast
+    def cast(self, bvh, samples, n_dirs, kind=DIRS_HEMI, counts=True, stream=None, bits=None):
+        n = samples["origin"].shape[0]
+        W = (n_dirs + 31) // 32
+        if bits is None:
+            bits = torch.empty((n, W), dtype=torch.int32, device=self.device)
+        cnt = torch.empty((n,), dtype=torch.int32, device=self.device) if counts else None
+        st = self._samples_struct(samples)
+        self._check(lib().hra_cast_hemisphere(self.ptr, bvh.ptr, C.byref(st), Dirs(kind, n_dirs), _ptr(bits),
+                                              _ptr(cnt), _stream(stream)))
+        return bits, cnt
+
+    def debug_rays(self, samples, n_dirs, idx, kind=DIRS_HEMI, stream=None):
+        idx = _dev_tensor(idx, torch.int64, self.device)
+        out = torch.empty((idx.shape[0], n_dirs, 6), dtype=torch.float32, device=self.device)
+        st = self._samples_struct(samples)
+        self._check(lib().hra_debug_rays(self.ptr, C.byref(st), Dirs(kind, n_dirs), _ptr(idx), idx.shape[0], _ptr(out),
+                                         _stream(stream)))
+        return out
+
+    # ---------------------------------------------------------------- stats
+    def dominant_axes(self, samples, n_dirs, bits, stream=None):
+        n = samples["origin"].shape[0]
+        d = self.device
+        out = {"mean": torch.empty((n, 3), dtype=torch.float32, device=d),
+               "absmean": torch.empty((n, 3), dtype=torch.float32, device=d),
+               "axis": torch.empty((n,), dtype=torch.int8, device=d),
+               "conc": torch.empty((n,), dtype=torch.float32, device=d),
+               "hist": torch.empty((8192,), dtype=torch.int32, device=d),
+               "totals": torch.empty((int(lib().hra_dirstats_bytes(n)),), dtype=torch.uint8, device=d)}
+        ds = DirStats(*[_ptr(out[k]) for k in ("mean", "absmean", "axis", "conc", "hist", "totals")])
+        st = self._samples_struct(samples)
+        self._check(lib().hra_dominant_axes(self.ptr, C.byref(st), Dirs(DIRS_HEMI, n_dirs), _ptr(bits), C.byref(ds),
+                                            _stream(stream)))
+        out["_struct"] = ds
+        return out
+
+    def classify(self, stats, n, n_dirs, thresholds=None, stream=None):
+        rep = ClassReport()
+        th = C.byref(Thresholds(*thresholds)) if thresholds is not None else None
+        self._check(lib().hra_classify(self.ptr, C.byref(stats["_struct"]), n, n_dirs, th, C.byref(rep),
+                                       _stream(stream)))
+        return {"access": rep.access, "shares": list(rep.share), "conc": rep.mean_conc, "n_blind": rep.n_blind,
+                "n_unobstructed": rep.n_unobstructed, "multi_axis": bool(rep.multi_axis), "tripped": rep.tripped,
+                "near_tie": bool(rep.near_tie)}
+
+    def min_setups(self, bvh, samples, axes_bits, tool_length, want_class=True, stream=None):
+        n = samples["origin"].shape[0]
+        cls = torch.empty((n,), dtype=torch.uint8, device=self.device) if want_class else None
+        rep = SetupReport()
+        st = self._samples_struct(samples)
+        ab = axes_bits.reshape(-1).contiguous()
+        self._check(lib().hra_min_setups(self.ptr, bvh.ptr, C.byref(st), _ptr(ab), float(tool_length), _ptr(cls),
+                                         C.byref(rep), _stream(stream)))
+        return {"min_count": rep.min_count, "min_mask": rep.min_mask, "greedy_count": rep.greedy_count,
+                "greedy_mask": rep.greedy_mask, "n_class": list(rep.n_class), "code_hist": list(rep.code_hist),
+                "class": cls}
+
+
+class Bvh:
+    def __init__(self, ctx, ptr, keep, stream):
+        self.ctx, self.ptr = ctx, ptr
+        self._keep = keep   # inputs stay alive until the build has run
+        self._stream = stream
+
+    def info(self, stream=None):
+        inf = BvhInfo()
+        self.ctx._check(lib().hra_bvh_get_info(self.ptr, _stream(stream), C.byref(inf)))
+        self._keep = None
+        return inf
+
+    def release(self):
+        if self.ptr:
+            lib().hra_bvh_release(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            if self._keep is not None:
+                torch.cuda.synchronize(self.ctx.device)
+            self.release()
+        except Exception:
+            pass
