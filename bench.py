@@ -1,0 +1,189 @@
+"""Benchmark: any-hit hemisphere rays/s of the whole accessibility path.
+
+One step = one pass of the hot path over one part whose mesh is already in
+HBM: build the BVH, draw the surface samples, cast the hemisphere, the
+directional statistics and classification, the six-axis cast and the setup
+search.  `value` is hemisphere rays per second over the timed steps.
+
+Default workload: the single part at interactive size (seeded procedural
+block with pockets, holes and fillets, ~200k triangles), 100k area-weighted
+samples, 4096 Fibonacci-hemisphere directions (4.1e8 rays per step).
+
+Prints one JSON line.  Extra keys: parts/s, per-stage milliseconds, BVH
+facts, the traversal work per ray, the roofline of the cast kernel (HIP
+events over the timed region) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (part builder, samples, directions)
+    "interactive_200k": ("interactive_200k", 100_000, 4096),
+    "single_block_1k5": ("single_block_1k5", 1_000, 512),
+    "multiaxis_1m": ("multiaxis_1m", 250_000, 2048),
+}
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+NODE_BYTES, TRI_BYTES = 64, 48  # one interior-node record, one leaf triangle
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(mesh, samples_np, n_dirs, budget_s=15.0):
+    """The oracle (brute force, FP64 decisions) on a bounded sample of the
+    same workload: the first rows of the same samples, all directions."""
+    from oracle import oracle as orc
+    threads = orc.max_threads()
+    dirs = orc.fibonacci_dirs(n_dirs)
+    rows = max(1, threads)
+    sub = {k: v[:rows] for k, v in samples_np.items()}
+    t0 = time.perf_counter()
+    orc.cast(mesh.verts, mesh.tris, sub, dirs, threads=threads)
+    dt = time.perf_counter() - t0
+    # grow the sample to fill about budget_s of CPU time
+    if dt < budget_s / 4:
+        rows = int(min(len(samples_np["origin"]), max(rows, rows * budget_s / max(dt, 1e-3) / 2)))
+        rows = max(threads, (rows // threads) * threads)
+        sub = {k: v[:rows] for k, v in samples_np.items()}
+        t0 = time.perf_counter()
+        orc.cast(mesh.verts, mesh.tris, sub, dirs, threads=threads)
+        dt = time.perf_counter() - t0
+    return {"value": rows * n_dirs / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows} samples x {n_dirs} directions of the same part ({mesh.n_tris} triangles), brute force",
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="interactive_200k", choices=sorted(WORKLOADS))
+    ap.add_argument("--tool-length", type=float, default=50.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rays-per-wave", type=int, default=64)
+    ap.add_argument("--stack", type=int, default=24)
+    ap.add_argument("--leaf", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by part and "
+              "by samples with no exchange, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2609_05467_amd import hra
+    from synth import parts
+
+    part_name, S, N = WORKLOADS[args.workload]
+    log(f"[bench] generating {part_name}")
+    mesh = parts.workload_parts(part_name)[0]
+    ctx = hra.Context(0)
+    ctx.set_cast_config(args.rays_per_wave, args.stack)
+    dev = ctx.device
+    verts = torch.tensor(mesh.verts, device=dev)
+    tris = torch.tensor(mesh.tris, device=dev)
+    # outputs reused across steps (allocated outside the timed region)
+    W = (N + 31) // 32
+    bits = torch.empty((S, W), dtype=torch.int32, device=dev)
+    bits6 = torch.empty((S, 1), dtype=torch.int32, device=dev)
+    samples = ctx.alloc_samples(S)
+    stream = torch.cuda.current_stream()
+
+    ev = {k: [] for k in ("build", "sample", "cast", "stats", "axes", "setups")}
+
+    def step(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        e[0].record()
+        bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
+        e[1].record()
+        ctx.sample_surface(bvh, S, 2, out=samples)
+        e[2].record()
+        ctx.cast(bvh, samples, N, counts=False, bits=bits)
+        e[3].record()
+        ds = ctx.dominant_axes(samples, N, bits)
+        rep = ctx.classify(ds, S, N)
+        e[4].record()
+        ctx.cast(bvh, samples, 6, kind=hra.DIRS_AXES6, counts=False, bits=bits6)
+        e[5].record()
+        su = ctx.min_setups(bvh, samples, bits6, args.tool_length, want_class=False)
+        e[6].record()
+        if record:
+            torch.cuda.synchronize()
+            for k, (a, b) in zip(ev, zip(e[:-1], e[1:])):
+                ev[k].append(a.elapsed_time(b))
+        bvh.release()
+        return rep, su
+
+    log(f"[bench] {mesh.n_tris} triangles, {S} samples x {N} directions; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep, su = step(True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = dt / args.steps * 1e3
+    rays = S * N
+    value = rays * args.steps / dt
+
+    # traversal work per ray (instrumented build of the same kernel, outside the timed region)
+    bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
+    info = bvh.info()
+    ctx.sample_surface(bvh, S, 2, out=samples)
+    wbits, nodes, tests = ctx.cast_work(bvh, samples, N)
+    same = bool(torch.equal(wbits, bits))
+    bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
+    cast_ms = float(np.mean(ev["cast"]))
+    achieved = bytes_per_ray * rays / (cast_ms * 1e-3) / 1e9
+    samples_np = {k: v.cpu().numpy() for k, v in samples.items()}
+    bvh.release()
+
+    out = {
+        "metric": "any-hit hemisphere rays/s",
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "triangles": mesh.n_tris, "samples": S, "directions": N,
+                   "rays_per_step": rays, "leaf_size": args.leaf, "rays_per_wave": args.rays_per_wave,
+                   "stack_depth": args.stack, "tool_length_mm": args.tool_length},
+        "parts_per_s": args.steps / dt,
+        "stage_ms": {k: round(float(np.mean(v)), 3) for k, v in ev.items()},
+        "cast_rays_per_s": rays / (cast_ms * 1e-3),
+        "bvh": {"depth": info.depth, "nodes": info.n_nodes, "bytes": info.bytes},
+        "work_per_ray": {"node_fetches": nodes / rays, "tri_tests": tests / rays, "bytes": bytes_per_ray,
+                         "instrumented_bits_identical": same},
+        "result": {"access": rep["access"], "multi_axis": rep["multi_axis"], "shares": rep["shares"],
+                   "mean_conc": rep["conc"], "min_setups": su["min_count"], "greedy_setups": su["greedy_count"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_cast", "avg_launch_ms": cast_ms},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(mesh, samples_np, N)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

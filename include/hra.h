@@ -92,6 +92,17 @@ typedef struct {
 
 /* Copy the handle's summary to the host.  Synchronises `stream`. */
 hra_status hra_bvh_get_info(hra_bvh *bvh, void *stream, hra_bvh_info *out);
+
+/* Copy the hierarchy to host memory, for inspection and invariant checks.
+ * host_nodes: n_tris - 1 (at least 1) records of 64 bytes: float lo0[3],
+ * hi0.x | hi0.yz, lo1.xy | lo1.z, hi1[3] | int32 child0, child1, 0, 0; a
+ * child >= 0 is a node index, < 0 a leaf: bits 27..30 = count - 1, bits
+ * 0..26 = first triangle; slots that are not part of the tree hold children
+ * 0x7fffffff.  host_tris: n_tris x 48 bytes, the first n_valid used: float4
+ * v0, v1, v2 in leaf order, w = face index (int32 bits).  *root: the root
+ * reference; *n_valid: triangles in the hierarchy.  Synchronises. */
+hra_status hra_bvh_export(hra_bvh *bvh, void *stream, void *host_nodes, void *host_tris, int32_t *root,
+                          int32_t *n_valid);
 void hra_bvh_release(hra_bvh *bvh);
 
 /* ----------------------------------------------------------------- samples */
@@ -157,6 +168,14 @@ typedef struct {
  * Results do not depend on it; only speed does. */
 hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *cfg);
 hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
+
+/* The same cast as hra_cast_hemisphere (identical bits) in an instrumented
+ * build of the traversal that also counts, over all rays, the interior
+ * nodes fetched and the ray-triangle tests made.  These counts give the
+ * algorithmic memory traffic per ray (64 bytes per node, 48 per triangle).
+ * Synchronises `stream`. */
+hra_status hra_cast_work(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
+                         uint32_t *d_bits, uint64_t *node_fetches, uint64_t *tri_tests, void *stream);
 
 /* The rays exactly as the cast kernel forms them, for checking: for the
  * samples listed in d_sample_idx (int64 [n_idx]) writes

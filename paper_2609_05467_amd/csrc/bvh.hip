@@ -458,17 +458,20 @@ __global__ void k_refit(const float4 *tri4, const int32_t *parent_leaf, const in
 }
 
 // ---------------------------------------------------------------- emit
-// Every node slot starts as a node with two empty boxes (lo = +inf,
-// hi = -inf): no ray enters it, so an unwritten slot ends a traversal.
-__global__ void k_fill_empty_nodes(Node *nodes, int64_t n) {
+// Every node slot starts as a sentinel: boxes spanning all space and both
+// children 0x7fffffff, an index past any node array.  A traversal that ever
+// reaches an unwritten slot steps to that index, which the traversal's
+// bounds guard reports as an error instead of reading out of bounds.
+constexpr int32_t SENTINEL_CHILD = 0x7fffffff;
+__global__ void k_fill_sentinel_nodes(Node *nodes, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float inf = INFINITY;
     Node nd;
-    nd.a = make_float4(inf, inf, inf, -inf);
-    nd.b = make_float4(-inf, -inf, inf, inf);
-    nd.c = make_float4(inf, -inf, -inf, -inf);
-    nd.d = make_int4(0, 0, 0, 0);
+    nd.a = make_float4(-inf, -inf, -inf, inf);
+    nd.b = make_float4(inf, inf, -inf, -inf);
+    nd.c = make_float4(-inf, inf, inf, inf);
+    nd.d = make_int4(SENTINEL_CHILD, SENTINEL_CHILD, 0, 0);
     nodes[i] = nd;
 }
 
@@ -576,7 +579,7 @@ extern "C" hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t 
         int rb = blocks_for(std::max(n_verts, T), TB);
         rb = std::min(rb, RED_BLOCKS);
         k_fill_i32<<<gT, TB, 0, s>>>(b->leaf_pos, T, -1);
-        k_fill_empty_nodes<<<gN, TB, 0, s>>>(b->nodes, nn);
+        k_fill_sentinel_nodes<<<gN, TB, 0, s>>>(b->nodes, nn);
         k_fill_u32<<<gN, TB, 0, s>>>(flags, nn, 0u);
         k_fill_i32<<<gN, TB, 0, s>>>(PI, nn, -1);
         k_tri_prep<<<gT, TB, 0, s>>>(d_verts, n_verts, d_tris, T, area, valid, ctx->d_err);
@@ -629,6 +632,22 @@ extern "C" hra_status hra_bvh_get_info(hra_bvh *b, void *stream, hra_bvh_info *o
     out->bytes = b->bytes;
     out->depth = m.depth;
     out->leaf_size = b->leaf_size;
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_bvh_export(hra_bvh *b, void *stream, void *host_nodes, void *host_tris, int32_t *root,
+                                     int32_t *n_valid) {
+    if (!b || !host_nodes || !host_tris || !root || !n_valid) return HRA_ERR_INVALID_ARG;
+    hra_ctx *ctx = b->ctx;
+    hra_status st = check_error_word(ctx, (hipStream_t)stream);
+    if (st != HRA_OK) return st;
+    BvhMeta m;
+    HRA_HIP(hipMemcpy(&m, b->meta, sizeof(m), hipMemcpyDeviceToHost));
+    const int64_t nn = b->n_tris > 1 ? b->n_tris - 1 : 1;
+    HRA_HIP(hipMemcpy(host_nodes, b->nodes, sizeof(Node) * nn, hipMemcpyDeviceToHost));
+    HRA_HIP(hipMemcpy(host_tris, b->tris, sizeof(float4) * 3 * b->n_tris, hipMemcpyDeviceToHost));
+    *root = m.root;
+    *n_valid = m.n_valid;
     return HRA_OK;
 }
 

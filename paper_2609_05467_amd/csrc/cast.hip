@@ -39,6 +39,7 @@ struct CastArgs {
     uint32_t n_items;
     int32_t n_nodes_alloc;  // node array length (bounds guard)
     int32_t n_tris_alloc;   // leaf-ordered triangles (bounds guard)
+    unsigned long long *work;  // instrumented variant: {node fetches, triangle tests}
 };
 
 __device__ __noinline__ int edge_sign64(float ox, float oy, float oz, float dx, float dy, float dz, float4 P, float4 Q) {
@@ -121,8 +122,14 @@ __device__ inline bool slab(float lx, float ly, float lz, float hx, float hy, fl
     return tmin <= tmax * 1.0000004f;
 }
 
+struct WorkCount {
+    uint32_t nodes = 0;   // interior nodes fetched
+    uint32_t tris = 0;    // triangle tests
+};
+
+template <bool STATS>
 __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, float ox, float oy, float oz, float dx,
-                                float dy, float dz, int32_t n_tris_alloc, uint32_t *err) {
+                                float dy, float dz, int32_t n_tris_alloc, uint32_t *err, WorkCount &wc) {
     const int first = leaf_first(code), cnt = leaf_count(code);
     if (first + cnt > n_tris_alloc) {
         atomicOr(err, ERR_STACK);
@@ -130,6 +137,7 @@ __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, f
     }
     for (int k = 0; k < cnt; ++k) {
         const float4 *t = tris + 3 * (int64_t)(first + k);
+        if (STATS) ++wc.tris;
         if (tri_hit(ox, oy, oz, dx, dy, dz, t[0], t[1], t[2])) return true;
     }
     return false;
@@ -139,11 +147,11 @@ __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, f
 // Guards: a node index outside the array, a leaf run outside the triangle
 // array, or more node visits than twice the node count set the error word
 // and end the ray, so a malformed hierarchy cannot fault or spin.
-template <int STACK>
+template <int STACK, bool STATS>
 __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
                                 float oy, float oz, float dx, float dy, float dz, int *lds, int lane, uint32_t *err,
-                                int32_t n_nodes_alloc, int32_t n_tris_alloc) {
-    if (is_leaf(root)) return leaf_hit(tris, root, ox, oy, oz, dx, dy, dz, n_tris_alloc, err);
+                                int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
+    if (is_leaf(root)) return leaf_hit<STATS>(tris, root, ox, oy, oz, dx, dy, dz, n_tris_alloc, err, wc);
     const float ix = dx != 0.0f ? 1.0f / dx : copysignf(1e30f, dx);
     const float iy = dy != 0.0f ? 1.0f / dy : copysignf(1e30f, dy);
     const float iz = dz != 0.0f ? 1.0f / dz : copysignf(1e30f, dz);
@@ -157,14 +165,15 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
             return true;
         }
         const Node *nd = nodes + node;
+        if (STATS) ++wc.nodes;
         const float4 A = nd->a, B = nd->b, C = nd->c;
         const int4 D = nd->d;
         float t0, t1;
         const bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, ox, oy, oz, ix, iy, iz, t0);
         const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, ox, oy, oz, ix, iy, iz, t1);
         const int32_t c0 = D.x, c1 = D.y;
-        if (h0 && is_leaf(c0) && leaf_hit(tris, c0, ox, oy, oz, dx, dy, dz, n_tris_alloc, err)) return true;
-        if (h1 && is_leaf(c1) && leaf_hit(tris, c1, ox, oy, oz, dx, dy, dz, n_tris_alloc, err)) return true;
+        if (h0 && is_leaf(c0) && leaf_hit<STATS>(tris, c0, ox, oy, oz, dx, dy, dz, n_tris_alloc, err, wc)) return true;
+        if (h1 && is_leaf(c1) && leaf_hit<STATS>(tris, c1, ox, oy, oz, dx, dy, dz, n_tris_alloc, err, wc)) return true;
         const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
         if (g0 && g1) {
             const int32_t nearc = t0 <= t1 ? c0 : c1, farc = t0 <= t1 ? c1 : c0;
@@ -188,65 +197,72 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
     }
 }
 
-template <int RPW, int STACK>
+// One work item = (sample, RPW consecutive directions) per wavefront; the
+// item index comes from the launch grid, so it is wave-uniform by
+// construction and no cross-lane broadcast is needed.  The ballot masks stay
+// in wave-uniform registers and are written once, after the last cross-lane
+// operation of the kernel, so no lane-dependent branch ever precedes a
+// ballot.
+template <int RPW, int STACK, bool STATS>
 __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
     __shared__ int stk[4][STACK * 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t item = blockIdx.x * 4u + (uint32_t)wv;
+    if (item >= a.n_items) return;  // the whole wavefront leaves together
     int *lds = stk[wv];
     const int32_t root = a.meta->root;
     const int32_t n_valid = a.meta->n_valid;
     const bool empty = n_valid <= 0;
     const int32_t n_tris_alloc = n_valid < a.n_tris_alloc ? n_valid : a.n_tris_alloc;
-    while (true) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1u);
-        item = __shfl(item, 0);
-        if (item >= a.n_items) break;
-        const int64_t s = item / (uint32_t)a.chunks;
-        const int32_t ch = (int32_t)(item % (uint32_t)a.chunks);
-        const float ox = a.origin[3 * s], oy = a.origin[3 * s + 1], oz = a.origin[3 * s + 2];
-        const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
-        float3 t, b;
-        onb_frame(nx, ny, nz, t, b);
-        uint32_t *row = a.bits + s * a.W;
-#pragma unroll 1
-        for (int r = 0; r < RPW / 64; ++r) {
-            const int32_t jb = ch * RPW + r * 64;
-            if (jb >= a.n_dirs) break;
-            const int32_t j = jb + lane;
-            bool free_ray = false;
-            if (j < a.n_dirs) {
-                const float4 l = a.dirs[j];
-                float dx, dy, dz;
-                bool cast = true;
-                if (a.kind == 0) {
-                    const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
-                    dx = d.x;
-                    dy = d.y;
-                    dz = d.z;
-                } else {
-                    dx = l.x;
-                    dy = l.y;
-                    dz = l.z;
-                    const float q0 = nx * dx, q1 = ny * dy, q2 = nz * dz;
-                    const float nd = (q0 + q1) + q2;
-                    cast = !(nd < 0.0f);
-                }
-                if (cast) free_ray = empty || !occluded<STACK>(a.nodes, a.tris, root, ox, oy, oz, dx, dy, dz, lds, lane, a.err,
-                                                                   a.n_nodes_alloc, n_tris_alloc);
+    const int64_t s = item / (uint32_t)a.chunks;
+    const int32_t ch = (int32_t)(item % (uint32_t)a.chunks);
+    const float ox = a.origin[3 * s], oy = a.origin[3 * s + 1], oz = a.origin[3 * s + 2];
+    const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
+    float3 t, b;
+    onb_frame(nx, ny, nz, t, b);
+    uint64_t mk[RPW / 64];
+    WorkCount wc;
+#pragma unroll
+    for (int r = 0; r < RPW / 64; ++r) {
+        const int32_t j = ch * RPW + r * 64 + lane;
+        bool free_ray = false;
+        if (j < a.n_dirs) {
+            const float4 l = a.dirs[j];
+            float dx, dy, dz;
+            bool cast = true;
+            if (a.kind == 0) {
+                const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+                dx = d.x;
+                dy = d.y;
+                dz = d.z;
+            } else {
+                dx = l.x;
+                dy = l.y;
+                dz = l.z;
+                const float q0 = nx * dx, q1 = ny * dy, q2 = nz * dz;
+                const float nd = (q0 + q1) + q2;
+                cast = !(nd < 0.0f);
             }
-            const uint64_t m = __ballot(free_ray);
-            if (lane == 0) {
-                const int32_t w = jb >> 5;
-                row[w] = (uint32_t)m;
-                if (w + 1 < a.W) row[w + 1] = (uint32_t)(m >> 32);
-            }
+            if (cast)
+                free_ray = empty || !occluded<STACK, STATS>(a.nodes, a.tris, root, ox, oy, oz, dx, dy, dz, lds, lane,
+                                                            a.err, a.n_nodes_alloc, n_tris_alloc, wc);
         }
+        mk[r] = __ballot(free_ray);
     }
-}
-
-__global__ void k_zero_counter(uint32_t *c) {
-    if (threadIdx.x == 0) c[0] = 0;
+    // words of this item: [ch * RPW/32, min(W, (ch + 1) * RPW/32))
+    const int32_t w0 = ch * (RPW / 32);
+    const int32_t nw = a.W - w0 < RPW / 32 ? a.W - w0 : RPW / 32;
+    if (lane < nw) {
+        uint64_t m = mk[0];
+#pragma unroll
+        for (int r = 1; r < RPW / 64; ++r)
+            if ((lane >> 1) == r) m = mk[r];
+        a.bits[s * a.W + w0 + lane] = (lane & 1) ? (uint32_t)(m >> 32) : (uint32_t)m;
+    }
+    if (STATS) {
+        atomicAdd(a.work, (unsigned long long)wc.nodes);
+        atomicAdd(a.work + 1, (unsigned long long)wc.tris);
+    }
 }
 
 __global__ void k_popcount_rows(const uint32_t *bits, int64_t n, int32_t W, uint32_t *counts) {
@@ -257,35 +273,28 @@ __global__ void k_popcount_rows(const uint32_t *bits, int64_t n, int32_t W, uint
     counts[s] = c;
 }
 
-template <int RPW, int STACK>
-static hipError_t launch_cast(hra_ctx *ctx, const CastArgs &args, hipStream_t s) {
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cast<RPW, STACK>, 256, 0);
-    if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    int64_t blocks = (int64_t)ctx->n_cu * per_cu;
-    const int64_t need = ((int64_t)args.n_items + 3) / 4;
-    if (blocks > need) blocks = need;
-    if (blocks < 1) blocks = 1;
-    k_zero_counter<<<1, 64, 0, s>>>(args.counter);
-    k_cast<RPW, STACK><<<(unsigned)blocks, 256, 0, s>>>(args);
+template <int RPW, int STACK, bool STATS>
+static hipError_t launch_cast(const CastArgs &args, hipStream_t s) {
+    const int64_t blocks = ((int64_t)args.n_items + 3) / 4;
+    k_cast<RPW, STACK, STATS><<<(unsigned)blocks, 256, 0, s>>>(args);
     return hipGetLastError();
 }
 
-template <int RPW>
-static hipError_t launch_rpw(hra_ctx *ctx, const CastArgs &a, int stack, hipStream_t s) {
+template <int RPW, bool STATS>
+static hipError_t launch_rpw(const CastArgs &a, int stack, hipStream_t s) {
     switch (stack) {
-        case 16: return launch_cast<RPW, 16>(ctx, a, s);
-        case 32: return launch_cast<RPW, 32>(ctx, a, s);
-        default: return launch_cast<RPW, 24>(ctx, a, s);
+        case 16: return launch_cast<RPW, 16, STATS>(a, s);
+        case 32: return launch_cast<RPW, 32, STATS>(a, s);
+        default: return launch_cast<RPW, 24, STATS>(a, s);
     }
 }
 
-hipError_t launch_cast_any(hra_ctx *ctx, const CastArgs &a, int rpw, int stack, hipStream_t s) {
+hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, bool stats, hipStream_t s) {
+    if (stats) return launch_rpw<64, true>(a, stack, s);
     switch (rpw) {
-        case 128: return launch_rpw<128>(ctx, a, stack, s);
-        case 256: return launch_rpw<256>(ctx, a, stack, s);
-        default: return launch_rpw<64>(ctx, a, stack, s);
+        case 128: return launch_rpw<128, false>(a, stack, s);
+        case 256: return launch_rpw<256, false>(a, stack, s);
+        default: return launch_rpw<64, false>(a, stack, s);
     }
 }
 
@@ -337,16 +346,16 @@ extern "C" hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *c
     return HRA_OK;
 }
 
-extern "C" hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
-                                          uint32_t *d_bits, uint32_t *d_counts, void *stream) {
+static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
+                              uint32_t *d_bits, uint32_t *d_counts, unsigned long long *work, int rpw, hipStream_t s) {
     if (!ctx || !bvh || !samples) return HRA_ERR_INVALID_ARG;
-    if (!d_bits || !samples->origin || !samples->normal || samples->n < 0)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "bits, origins and normals must be non-null");
+    if (samples->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
     const float4 *table = nullptr;
     hra_status st = dir_table(ctx, dirs, &table);
     if (st != HRA_OK) return st;
-    if (samples->n == 0) return HRA_OK;
-    hipStream_t s = (hipStream_t)stream;
+    if (samples->n == 0) return HRA_OK;   // nothing to cast; arrays may be null
+    if (!d_bits || !samples->origin || !samples->normal)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "bits, origins and normals must be non-null");
     HRA_HIP(hipSetDevice(ctx->device));
     CastArgs a;
     a.nodes = bvh->nodes;
@@ -364,16 +373,46 @@ extern "C" hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, cons
     a.W = (dirs.n + 31) / 32;
     a.n_nodes_alloc = (int32_t)(bvh->n_tris > 1 ? bvh->n_tris - 1 : 1);
     a.n_tris_alloc = (int32_t)bvh->n_tris;
-    const int rpw = ctx->cast_rpw;
+    a.work = work;
     a.chunks = (dirs.n + rpw - 1) / rpw;
     const int64_t items = samples->n * (int64_t)a.chunks;
     if (items >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call (split the samples)");
     a.n_items = (uint32_t)items;
-    HRA_HIP(launch_cast_any(ctx, a, rpw, ctx->cast_stack, s));
+    HRA_HIP(launch_cast_any(a, rpw, ctx->cast_stack, work != nullptr, s));
     if (d_counts) {
         k_popcount_rows<<<blocks_for(samples->n, 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);
         HRA_HIP(hipGetLastError());
     }
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
+                                          uint32_t *d_bits, uint32_t *d_counts, void *stream) {
+    if (!ctx) return HRA_ERR_INVALID_ARG;
+    return cast_common(ctx, bvh, samples, dirs, d_bits, d_counts, nullptr, ctx->cast_rpw, (hipStream_t)stream);
+}
+
+__global__ void k_zero_work(unsigned long long *w) {
+    if (threadIdx.x < 2) w[threadIdx.x] = 0;
+}
+
+extern "C" hra_status hra_cast_work(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
+                                    uint32_t *d_bits, uint64_t *node_fetches, uint64_t *tri_tests, void *stream) {
+    if (!ctx || !node_fetches || !tri_tests) return HRA_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *w = nullptr;
+    HRA_HIP(hipMallocAsync((void **)&w, 2 * sizeof(unsigned long long), s));
+    k_zero_work<<<1, 64, 0, s>>>(w);
+    hra_status st = cast_common(ctx, bvh, samples, dirs, d_bits, nullptr, w, 64, s);
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, s);
+    hipFreeAsync(w, s);
+    if (st != HRA_OK) return st;
+    if (e != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, "work counter copy failed", hipGetErrorString(e));
+    st = check_error_word(ctx, s);
+    if (st != HRA_OK) return st;
+    *node_fetches = h[0];
+    *tri_tests = h[1];
     return HRA_OK;
 }
 

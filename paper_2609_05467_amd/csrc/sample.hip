@@ -97,11 +97,12 @@ using namespace hra;
 extern "C" hra_status hra_sample_surface(hra_ctx *ctx, const hra_bvh *bvh, int32_t mode, uint64_t seed,
                                          float offset_frac, const hra_samples *out, void *stream) {
     if (!ctx || !bvh || !out) return HRA_ERR_INVALID_ARG;
-    if (!out->point || !out->normal || !out->origin || !out->tri || out->n < 0)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "sample arrays must be non-null");
+    if (out->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
     if (!(offset_frac > 0.0f && offset_frac <= 0.01f))
         return ctx->fail(HRA_ERR_INVALID_ARG, "offset_frac must be in (0, 0.01]");
     if (out->n == 0) return HRA_OK;
+    if (!out->point || !out->normal || !out->origin || !out->tri)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "sample arrays must be non-null");
     hipStream_t s = (hipStream_t)stream;
     HRA_HIP(hipSetDevice(ctx->device));
     if (mode == HRA_SAMPLE_AREA) {

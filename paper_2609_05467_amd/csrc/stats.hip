@@ -63,33 +63,27 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
             sa2 += __shfl_xor(sa2, off);
             cnt += __shfl_xor(cnt, off);
         }
-        if (lane == 0) {
-            if (cnt == 0) {
-                for (int c = 0; c < 3; ++c) out.mean[3 * s + c] = out.absmean[3 * s + c] = 0.0f;
-                out.axis[s] = -1;
-                out.conc[s] = 0.0f;
-                conc64[s] = 0.0;
-                atomicAdd(&tot->n_blind, 1ull);
-            } else {
-                const double c = (double)cnt;
-                const double m[3] = {sm0 / c, sm1 / c, sm2 / c}, A[3] = {sa0 / c, sa1 / c, sa2 / c};
-                const double am[3] = {fabs(m[0]), fabs(m[1]), fabs(m[2])};
-                const double mx = fmax(am[0], fmax(am[1], am[2]));
-                int k = 0;
-                while (k < 2 && !(am[k] >= (1.0 - 1e-5) * mx)) ++k;
-                const double den = A[0] + A[1] + A[2];
-                const double cc = A[k] / den;
-                for (int q = 0; q < 3; ++q) {
-                    out.mean[3 * s + q] = (float)m[q];
-                    out.absmean[3 * s + q] = (float)A[q];
-                }
-                out.axis[s] = (int8_t)k;
-                out.conc[s] = (float)cc;
-                conc64[s] = cc;
-                atomicAdd(&tot->n_axis[k], 1ull);
-                atomicAdd(&tot->n_unob, (unsigned long long)cnt);
-            }
-        }
+        // every lane holds the totals after the butterfly; all lanes store the
+        // same values and only lane 0 contributes to the counters, with no
+        // lane-dependent branch ahead of the next iteration's shuffles
+        const bool blind = cnt == 0;
+        const double c = blind ? 1.0 : (double)cnt;
+        const double m[3] = {sm0 / c, sm1 / c, sm2 / c}, A[3] = {sa0 / c, sa1 / c, sa2 / c};
+        const double am[3] = {fabs(m[0]), fabs(m[1]), fabs(m[2])};
+        const double mx = fmax(am[0], fmax(am[1], am[2]));
+        int k = 0;
+        while (k < 2 && !(am[k] >= (1.0 - 1e-5) * mx)) ++k;
+        const double den = A[0] + A[1] + A[2];
+        const double cc = blind ? 0.0 : A[k] / den;
+        const int q = lane % 3;
+        out.mean[3 * s + q] = blind ? 0.0f : (float)m[q];
+        out.absmean[3 * s + q] = blind ? 0.0f : (float)A[q];
+        out.axis[s] = blind ? (int8_t)-1 : (int8_t)k;
+        out.conc[s] = (float)cc;
+        conc64[s] = cc;
+        const unsigned long long one = lane == 0 ? 1ull : 0ull;
+        atomicAdd(blind ? &tot->n_blind : &tot->n_axis[k], one);
+        atomicAdd(&tot->n_unob, lane == 0 ? (unsigned long long)cnt : 0ull);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x)
@@ -244,8 +238,9 @@ extern "C" int64_t hra_dirstats_bytes(int64_t n) { return (int64_t)sizeof(DirTot
 
 extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
                                         const hra_dirstats *out, void *stream) {
-    if (!ctx || !samples || !d_bits || !out) return HRA_ERR_INVALID_ARG;
-    if (!out->mean || !out->absmean || !out->axis || !out->conc || !out->hist || !out->totals)
+    if (!ctx || !samples || !out) return HRA_ERR_INVALID_ARG;
+    if (!out->hist || !out->totals) return ctx->fail(HRA_ERR_INVALID_ARG, "histogram and totals must be non-null");
+    if (samples->n > 0 && (!d_bits || !out->mean || !out->absmean || !out->axis || !out->conc || !samples->normal))
         return ctx->fail(HRA_ERR_INVALID_ARG, "all hra_dirstats arrays must be non-null");
     if (dirs.kind != HRA_DIRS_HEMI_FIBONACCI)
         return ctx->fail(HRA_ERR_INVALID_ARG, "directional statistics need the hemisphere set");
@@ -302,9 +297,10 @@ extern "C" hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int6
 extern "C" hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples,
                                      const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
                                      hra_setup_report *out, void *stream) {
-    if (!ctx || !bvh || !samples || !d_axes_bits || !out) return HRA_ERR_INVALID_ARG;
-    if (!samples->point || !samples->tri || samples->n < 0)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "sample points and faces must be non-null");
+    if (!ctx || !bvh || !samples || !out) return HRA_ERR_INVALID_ARG;
+    if (samples->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
+    if (samples->n > 0 && (!samples->point || !samples->tri || !d_axes_bits))
+        return ctx->fail(HRA_ERR_INVALID_ARG, "sample points, faces and axis bits must be non-null");
     if (!(tool_length >= 0.0)) return ctx->fail(HRA_ERR_INVALID_ARG, "tool length must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     HRA_HIP(hipSetDevice(ctx->device));

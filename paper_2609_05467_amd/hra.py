@@ -89,10 +89,13 @@ def lib():
             "hra_build_bvh": ([P, P, i64, P, i64, C.POINTER(BvhOpts), P, C.POINTER(P)], C.c_int),
             "hra_bvh_get_info": ([P, P, C.POINTER(BvhInfo)], C.c_int),
             "hra_bvh_release": ([P], None),
+            "hra_bvh_export": ([P, P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "hra_sample_surface": ([P, P, i32, u64, f32, C.POINTER(Samples), P], C.c_int),
             "hra_dirs_table": ([P, Dirs, P], C.c_int),
             "hra_cast_hemisphere": ([P, P, C.POINTER(Samples), Dirs, P, P, P], C.c_int),
             "hra_set_cast_config": ([P, C.POINTER(CastConfig)], C.c_int),
+            "hra_cast_work": ([P, P, C.POINTER(Samples), Dirs, P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P],
+                              C.c_int),
             "hra_get_cast_config": ([P, C.POINTER(CastConfig)], C.c_int),
             "hra_debug_rays": ([P, C.POINTER(Samples), Dirs, P, i64, P, P], C.c_int),
             "hra_dirstats_bytes": ([i64], i64),
@@ -110,8 +113,8 @@ def lib():
 
 
 EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version", "hra_build_bvh",
-           "hra_bvh_get_info", "hra_bvh_release", "hra_sample_surface", "hra_dirs_table", "hra_cast_hemisphere",
-           "hra_set_cast_config", "hra_get_cast_config", "hra_debug_rays", "hra_dirstats_bytes",
+           "hra_bvh_get_info", "hra_bvh_release", "hra_bvh_export", "hra_sample_surface", "hra_dirs_table", "hra_cast_hemisphere",
+           "hra_set_cast_config", "hra_get_cast_config", "hra_cast_work", "hra_debug_rays", "hra_dirstats_bytes",
            "hra_dominant_axes", "hra_classify", "hra_min_setups"]
 
 
@@ -199,11 +202,12 @@ class Context:
                 assert s[k].is_contiguous() and s[k].dtype == torch.float32 and s[k].shape == (n, 3), k
         return Samples(_ptr(s.get("point")), _ptr(s.get("normal")), _ptr(s.get("origin")), _ptr(s.get("tri")), n)
 
-    def sample_surface(self, bvh, n, seed, mode=SAMPLE_AREA, offset_frac=1e-4, stream=None):
+    def sample_surface(self, bvh, n, seed, mode=SAMPLE_AREA, offset_frac=1e-4, stream=None, out=None):
         if mode == SAMPLE_CENTROID:
             info = bvh.info(stream)
             n = info.n_tris - info.n_degenerate
-        s = self.alloc_samples(n)
+        s = out if out is not None else self.alloc_samples(n)
+        assert s["origin"].shape[0] == n
         st = self._samples_struct(s)
         self._check(lib().hra_sample_surface(self.ptr, bvh.ptr, mode, seed, offset_frac, C.byref(st), _stream(stream)))
         return s
@@ -219,6 +223,16 @@ class Context:
         self._check(lib().hra_cast_hemisphere(self.ptr, bvh.ptr, C.byref(st), Dirs(kind, n_dirs), _ptr(bits),
                                               _ptr(cnt), _stream(stream)))
         return bits, cnt
+
+    def cast_work(self, bvh, samples, n_dirs, kind=DIRS_HEMI, stream=None):
+        """Instrumented cast: (bits, node fetches, triangle tests) over all rays."""
+        n = samples["origin"].shape[0]
+        bits = torch.empty((n, (n_dirs + 31) // 32), dtype=torch.int32, device=self.device)
+        nf, nt = C.c_uint64(), C.c_uint64()
+        st = self._samples_struct(samples)
+        self._check(lib().hra_cast_work(self.ptr, bvh.ptr, C.byref(st), Dirs(kind, n_dirs), _ptr(bits), C.byref(nf),
+                                        C.byref(nt), _stream(stream)))
+        return bits, nf.value, nt.value
 
     def debug_rays(self, samples, n_dirs, idx, kind=DIRS_HEMI, stream=None):
         idx = _dev_tensor(idx, torch.int64, self.device)
@@ -278,6 +292,19 @@ class Bvh:
         self.ctx._check(lib().hra_bvh_get_info(self.ptr, _stream(stream), C.byref(inf)))
         self._keep = None
         return inf
+
+    def export(self, stream=None):
+        """Host copy of the hierarchy: (nodes float32 [nn,16] with int32
+        children in columns 12-13, tris float32 [n_valid,3,4], root, n_valid)."""
+        import numpy as np
+        inf = self.info(stream)
+        nn = max(1, inf.n_tris - 1)
+        nodes = np.empty((nn, 16), np.float32)
+        tris = np.empty((inf.n_tris, 3, 4), np.float32)
+        root, nv = C.c_int32(), C.c_int32()
+        self.ctx._check(lib().hra_bvh_export(self.ptr, _stream(stream), nodes.ctypes.data_as(C.c_void_p),
+                                             tris.ctypes.data_as(C.c_void_p), C.byref(root), C.byref(nv)))
+        return nodes, tris[:nv.value], root.value, nv.value
 
     def release(self):
         if self.ptr:

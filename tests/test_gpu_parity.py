@@ -359,3 +359,12 @@ def test_interactive_full_size_sampled_rows(ctx, orc, interactive):
     assert np.array_equal(sn["origin"], o["origin"]) and np.array_equal(sn["tri"], o["tri"])
     c = _u32(cnt)
     assert np.all(c <= N) and c.sum() > 0
+
+
+def test_cast_work_counts(ctx, cfg1):
+    m, b = cfg1
+    s = ctx.sample_surface(b, 200, 4)
+    bits, _ = ctx.cast(b, s, 512)
+    wbits, nodes, tests = ctx.cast_work(b, s, 512)
+    assert np.array_equal(_u32(wbits), _u32(bits))
+    assert nodes >= 200 * 512 and tests > 0
