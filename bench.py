@@ -62,6 +62,23 @@ def cpu_baseline(mesh, samples_np, n_dirs, budget_s=15.0):
             "seconds": round(dt, 3)}
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the cast kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has changed
+    since those counters were taken (or none were taken for this workload)."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", f"k_cast_{workload}_traffic.txt")
+    if not os.path.exists(f):
+        return None, None
+    kv = dict(l.strip().split("=", 1) for l in open(f) if "=" in l and not l.startswith("#"))
+    h = hashlib.sha256()
+    for src in ("paper_2609_05467_amd/csrc/cast.hip", "paper_2609_05467_amd/csrc/common.hpp"):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != kv.get("source_sha256"):
+        return None, None
+    return float(kv["traffic_bytes"]), float(kv.get("l2_hit_rate", "nan"))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +90,9 @@ def main():
     ap.add_argument("--rays-per-wave", type=int, default=64)
     ap.add_argument("--stack", type=int, default=24)
     ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before timing, copy this many MiB device to device (a kernel of known traffic for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by part and "
@@ -124,6 +144,12 @@ def main():
         bvh.release()
         return rep, su
 
+    if args.copy_calibration_mib:
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"[bench] {mesh.n_tris} triangles, {S} samples x {N} directions; warmup {args.warmup}")
     for _ in range(args.warmup):
         step(False)
@@ -149,6 +175,7 @@ def main():
     achieved = bytes_per_ray * rays / (cast_ms * 1e-3) / 1e9
     samples_np = {k: v.cpu().numpy() for k, v in samples.items()}
     bvh.release()
+    traffic, l2_hit = measured_traffic(args.workload)
 
     out = {
         "metric": "any-hit hemisphere rays/s",
@@ -175,8 +202,9 @@ def main():
         "result": {"access": rep["access"], "multi_axis": rep["multi_axis"], "shares": rep["shares"],
                    "mean_conc": rep["conc"], "min_setups": su["min_count"], "greedy_setups": su["greedy_count"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_cast", "avg_launch_ms": cast_ms},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_cast", "avg_launch_ms": cast_ms, "algorithmic_bytes": bytes_per_ray * rays,
+                     "l2_hit_rate": l2_hit},
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")

@@ -18,16 +18,20 @@ struct DirTotals {
 constexpr int HIST_BINS = 8192;
 
 // One wavefront per sample: lanes stride over the directions, FP64 sums,
-// wave reduction, LDS-privatised integer histogram flushed at block end.
+// wave butterfly reduction.  The histogram is privatised in LDS per block
+// and written out without atomics to a per-block slice; k_hist_reduce sums
+// the slices in a fixed order.  Part counters stay in registers per
+// wavefront and reach memory once per wavefront.
 __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n, const float4 *dirs, int32_t N,
                                                   int32_t W, const uint32_t *bits, hra_dirstats out, double *conc64,
-                                                  DirTotals *tot) {
+                                                  DirTotals *tot, uint32_t *hist_part) {
     __shared__ uint32_t h[HIST_BINS];
     for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) h[k] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const double pi = 3.14159265358979323846264338327950288;
+    unsigned long long n_axis0 = 0, n_axis1 = 0, n_axis2 = 0, n_blind = 0, n_unob = 0;
     for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < n; s += nwaves) {
         const float nx = normal[3 * s], ny = normal[3 * s + 1], nz = normal[3 * s + 2];
         float3 t, b;
@@ -64,8 +68,8 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
             cnt += __shfl_xor(cnt, off);
         }
         // every lane holds the totals after the butterfly; all lanes store the
-        // same values and only lane 0 contributes to the counters, with no
-        // lane-dependent branch ahead of the next iteration's shuffles
+        // same values, with no lane-dependent branch ahead of the next
+        // iteration's shuffles
         const bool blind = cnt == 0;
         const double c = blind ? 1.0 : (double)cnt;
         const double m[3] = {sm0 / c, sm1 / c, sm2 / c}, A[3] = {sa0 / c, sa1 / c, sa2 / c};
@@ -81,13 +85,31 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
         out.axis[s] = blind ? (int8_t)-1 : (int8_t)k;
         out.conc[s] = (float)cc;
         conc64[s] = cc;
-        const unsigned long long one = lane == 0 ? 1ull : 0ull;
-        atomicAdd(blind ? &tot->n_blind : &tot->n_axis[k], one);
-        atomicAdd(&tot->n_unob, lane == 0 ? (unsigned long long)cnt : 0ull);
+        n_blind += blind ? 1 : 0;
+        n_axis0 += (!blind && k == 0) ? 1 : 0;
+        n_axis1 += (!blind && k == 1) ? 1 : 0;
+        n_axis2 += (!blind && k == 2) ? 1 : 0;
+        n_unob += cnt;
     }
+    // wave-uniform counters: lane 0 adds them, other lanes add zero
+    const unsigned long long z = lane == 0 ? 1ull : 0ull;
+    atomicAdd(&tot->n_axis[0], z * n_axis0);
+    atomicAdd(&tot->n_axis[1], z * n_axis1);
+    atomicAdd(&tot->n_axis[2], z * n_axis2);
+    atomicAdd(&tot->n_blind, z * n_blind);
+    atomicAdd(&tot->n_unob, z * n_unob);
     __syncthreads();
-    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x)
-        if (h[k]) atomicAdd(&out.hist[k], h[k]);
+    uint32_t *dst = hist_part + (int64_t)blockIdx.x * HIST_BINS;
+    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) dst[k] = h[k];
+}
+
+// hist[b] = sum over blocks of hist_part[block][b], in block order.
+__global__ void k_hist_reduce(const uint32_t *hist_part, int nblocks, uint32_t *hist) {
+    const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bin >= HIST_BINS) return;
+    uint32_t acc = 0;
+    for (int b = 0; b < nblocks; ++b) acc += hist_part[(int64_t)b * HIST_BINS + bin];
+    hist[bin] = acc;
 }
 
 __global__ void k_zero_stats(uint32_t *hist, DirTotals *tot) {
@@ -254,11 +276,15 @@ extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples
     k_zero_stats<<<1, 256, 0, s>>>(out->hist, tot);
     if (samples->n > 0) {
         int64_t blocks = (samples->n + 3) / 4;
-        const int64_t cap = (int64_t)ctx->n_cu * 8;
+        const int64_t cap = (int64_t)ctx->n_cu * 4;
         if (blocks > cap) blocks = cap;
+        uint32_t *part = nullptr;
+        HRA_HIP(hipMallocAsync((void **)&part, sizeof(uint32_t) * HIST_BINS * (size_t)blocks, s));
         k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(samples->normal, samples->n, table, dirs.n, (dirs.n + 31) / 32, d_bits,
-                                                    *out, c64, tot);
+                                                    *out, c64, tot, part);
+        k_hist_reduce<<<HIST_BINS / 256, 256, 0, s>>>(part, (int)blocks, out->hist);
         k_sum_fixed<<<1, 1024, 0, s>>>(c64, samples->n, &tot->conc_sum);
+        hipFreeAsync(part, s);
     }
     HRA_HIP(hipGetLastError());
     return HRA_OK;
