@@ -235,6 +235,22 @@ typedef struct {
 hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int64_t n, int32_t n_dirs,
                         const hra_thresholds *thresholds, hra_class_report *out, void *stream);
 
+typedef struct {
+    int32_t n_peaks;        /* local maxima found (<= k requested) */
+    int32_t bin[16];        /* their bins, largest mass first */
+    uint32_t mass[16];
+    float dir[16][3];       /* bin-centre world directions */
+    uint64_t axis_mass[6];  /* histogram mass within 45 degrees of +X,-X,+Y,-Y,+Z,-Z */
+} hra_hist_peaks;
+
+/* Dominant directions of a part from its direction histogram (host
+ * function, no device work): the k (<= 16) largest local maxima of the
+ * 64 x 128 (z band x azimuth) bins, a bin counting as a maximum when no
+ * neighbour in the 3 x 3 window (azimuth wraps) holds more (ties: the lower
+ * bin index wins), and the mass inside 45-degree cones about the six axes.
+ * host_hist: uint32 [8192] as written by hra_dominant_axes. */
+hra_status hra_histogram_peaks(const uint32_t *host_hist, int32_t k, hra_hist_peaks *out);
+
 /* ------------------------------------------------------------------ setups */
 
 enum { HRA_CLASS_VIABLE = 0, HRA_CLASS_OVER = 1, HRA_CLASS_INACCESSIBLE = 2, HRA_CLASS_FIXTURE = 3 };

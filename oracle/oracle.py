@@ -344,3 +344,61 @@ def min_setups_greedy(hist):
 
 def max_threads():
     return int(lib().orc_max_threads())
+
+
+# --------------------------------------------------------------------------
+# dominant directions from the direction histogram (the multi-axis workload)
+# --------------------------------------------------------------------------
+def bin_centre(b):
+    """Centre direction of histogram bin b (64 equal-area z bands x 128 sectors)."""
+    zb, az = b // 128, b % 128
+    z = (zb + 0.5) / 32.0 - 1.0
+    phi = (az + 0.5) * (2 * np.pi / 128) - np.pi
+    r = np.sqrt(max(0.0, 1 - z * z))
+    return np.array([r * np.cos(phi), r * np.sin(phi), z])
+
+
+def histogram_bin(d):
+    """Bin of a world direction, FP64 (the definition the statistics use)."""
+    d = np.asarray(d, np.float64)
+    zh = d[2] / np.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+    zb = min(63, max(0, int(np.floor((zh + 1.0) * 32.0))))
+    az = min(127, max(0, int(np.floor((np.arctan2(d[1], d[0]) + np.pi) * 128.0 / (2 * np.pi)))))
+    return zb * 128 + az
+
+
+def histogram_peaks(hist, k=8):
+    """Local maxima over the 3x3 bin window (azimuth wraps, lower bin wins
+    ties), largest first; and the mass within 45 degrees of each axis."""
+    h = np.asarray(hist, np.int64).reshape(64, 128)
+    peaks = []
+    for zb in range(64):
+        for az in range(128):
+            v = h[zb, az]
+            if v == 0:
+                continue
+            b = zb * 128 + az
+            ok = True
+            for dz in (-1, 0, 1):
+                z2 = zb + dz
+                if z2 < 0 or z2 > 63:
+                    continue
+                for da in (-1, 0, 1):
+                    if dz == 0 and da == 0:
+                        continue
+                    a2 = (az + da) % 128
+                    b2 = z2 * 128 + a2
+                    if h[z2, a2] > v or (h[z2, a2] == v and b2 < b):
+                        ok = False
+            if ok:
+                peaks.append((-int(v), b))
+    peaks.sort()
+    peaks = peaks[:k]
+    axis_mass = [0] * 6
+    for b in np.nonzero(h.reshape(-1))[0]:
+        c = bin_centre(b)
+        for a in range(6):
+            comp = -c[a // 2] if a % 2 else c[a // 2]
+            if comp > np.sqrt(0.5):
+                axis_mass[a] += int(h.reshape(-1)[b])
+    return {"bins": [b for _, b in peaks], "mass": [-m for m, _ in peaks], "axis_mass": axis_mass}

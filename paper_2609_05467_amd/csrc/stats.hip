@@ -2,6 +2,7 @@
 // (Section 3.3).
 #include "common.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -351,5 +352,66 @@ extern "C" hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra
     for (int k = 0; k < 4; ++k) out->n_class[k] = (int64_t)hcc[k];
     for (int c = 0; c < 64; ++c) out->code_hist[c] = hh[c];
     solve_setups(hh, &out->min_count, &out->min_mask, &out->greedy_count, &out->greedy_mask);
+    return HRA_OK;
+}
+
+// Bin centre of histogram bin b: z band zb = b / 128 covers z in
+// [zb/32 - 1, (zb+1)/32 - 1), azimuth sector az = b % 128 covers
+// [az 2pi/128 - pi, (az+1) 2pi/128 - pi).
+static void bin_centre(int b, double *d) {
+    const double pi = 3.14159265358979323846264338327950288;
+    const int zb = b / 128, az = b % 128;
+    const double z = (zb + 0.5) / 32.0 - 1.0;
+    const double phi = (az + 0.5) * (2.0 * pi / 128.0) - pi;
+    const double r = std::sqrt(std::fmax(0.0, 1.0 - z * z));
+    d[0] = r * std::cos(phi);
+    d[1] = r * std::sin(phi);
+    d[2] = z;
+}
+
+extern "C" hra_status hra_histogram_peaks(const uint32_t *h, int32_t k, hra_hist_peaks *out) {
+    if (!h || !out || k < 0 || k > 16) return HRA_ERR_INVALID_ARG;
+    std::vector<std::pair<uint32_t, int>> peaks;
+    for (int b = 0; b < HIST_BINS; ++b) {
+        const uint32_t v = h[b];
+        if (!v) continue;
+        const int zb = b / 128, az = b % 128;
+        bool is_max = true;
+        for (int dz = -1; dz <= 1 && is_max; ++dz) {
+            const int z2 = zb + dz;
+            if (z2 < 0 || z2 > 63) continue;
+            for (int da = -1; da <= 1; ++da) {
+                if (!dz && !da) continue;
+                const int b2 = z2 * 128 + ((az + da + 128) % 128);
+                if (h[b2] > v || (h[b2] == v && b2 < b)) {
+                    is_max = false;
+                    break;
+                }
+            }
+        }
+        if (is_max) peaks.push_back({v, b});
+    }
+    std::sort(peaks.begin(), peaks.end(), [](const std::pair<uint32_t, int> &x, const std::pair<uint32_t, int> &y) {
+        return x.first != y.first ? x.first > y.first : x.second < y.second;
+    });
+    out->n_peaks = (int32_t)std::min<size_t>(peaks.size(), (size_t)k);
+    for (int i = 0; i < out->n_peaks; ++i) {
+        out->bin[i] = peaks[i].second;
+        out->mass[i] = peaks[i].first;
+        double d[3];
+        bin_centre(peaks[i].second, d);
+        for (int c = 0; c < 3; ++c) out->dir[i][c] = (float)d[c];
+    }
+    const double c45 = std::sqrt(0.5);
+    for (int a = 0; a < 6; ++a) out->axis_mass[a] = 0;
+    for (int b = 0; b < HIST_BINS; ++b) {
+        if (!h[b]) continue;
+        double d[3];
+        bin_centre(b, d);
+        for (int a = 0; a < 6; ++a) {
+            const double comp = (a & 1) ? -d[a >> 1] : d[a >> 1];
+            if (comp > c45) out->axis_mass[a] += h[b];
+        }
+    }
     return HRA_OK;
 }

@@ -66,6 +66,11 @@ class ClassReport(C.Structure):
                 ("multi_axis", C.c_int32), ("tripped", C.c_int32), ("near_tie", C.c_int32)]
 
 
+class HistPeaks(C.Structure):
+    _fields_ = [("n_peaks", C.c_int32), ("bin", C.c_int32 * 16), ("mass", C.c_uint32 * 16),
+                ("dir", (C.c_float * 3) * 16), ("axis_mass", C.c_uint64 * 6)]
+
+
 class SetupReport(C.Structure):
     _fields_ = [("min_count", C.c_int32), ("min_mask", C.c_int32), ("greedy_count", C.c_int32),
                 ("greedy_mask", C.c_int32), ("n_class", C.c_int64 * 4), ("code_hist", C.c_uint32 * 64)]
@@ -103,6 +108,7 @@ def lib():
             "hra_classify": ([P, C.POINTER(DirStats), i64, i32, C.POINTER(Thresholds), C.POINTER(ClassReport), P],
                              C.c_int),
             "hra_min_setups": ([P, P, C.POINTER(Samples), P, f64, P, C.POINTER(SetupReport), P], C.c_int),
+            "hra_histogram_peaks": ([P, i32, C.POINTER(HistPeaks)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -115,7 +121,7 @@ def lib():
 EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version", "hra_build_bvh",
            "hra_bvh_get_info", "hra_bvh_release", "hra_bvh_export", "hra_sample_surface", "hra_dirs_table", "hra_cast_hemisphere",
            "hra_set_cast_config", "hra_get_cast_config", "hra_cast_work", "hra_debug_rays", "hra_dirstats_bytes",
-           "hra_dominant_axes", "hra_classify", "hra_min_setups"]
+           "hra_dominant_axes", "hra_classify", "hra_min_setups", "hra_histogram_peaks"]
 
 
 def _ptr(t):
@@ -279,6 +285,21 @@ class Context:
         return {"min_count": rep.min_count, "min_mask": rep.min_mask, "greedy_count": rep.greedy_count,
                 "greedy_mask": rep.greedy_mask, "n_class": list(rep.n_class), "code_hist": list(rep.code_hist),
                 "class": cls}
+
+
+def histogram_peaks(hist, k=8):
+    """Top-k local maxima of an 8192-bin direction histogram and the six
+    45-degree axis-cone masses (library host function)."""
+    import numpy as np
+    h = np.ascontiguousarray(np.asarray(hist).reshape(-1).view(np.uint32) if hasattr(hist, "view") and
+                             np.asarray(hist).dtype != np.uint32 else np.asarray(hist, np.uint32))
+    out = HistPeaks()
+    st = lib().hra_histogram_peaks(h.ctypes.data_as(C.c_void_p), k, C.byref(out))
+    if st != HRA_OK:
+        raise HraError(st, "histogram_peaks")
+    n = out.n_peaks
+    return {"bins": [out.bin[i] for i in range(n)], "mass": [out.mass[i] for i in range(n)],
+            "dirs": [list(out.dir[i]) for i in range(n)], "axis_mass": list(out.axis_mass)}
 
 
 class Bvh:

@@ -35,6 +35,8 @@ class MeshBuilder:
         self._v: list[np.ndarray] = []
         self._t: list[np.ndarray] = []
         self.nv = 0
+        self.nt = 0
+        self.notes: list[dict] = []   # feature records (e.g. bore axes) for tests
 
     def add_verts(self, p) -> np.ndarray:
         p = np.asarray(p, dtype=np.float64).reshape(-1, 3)
@@ -47,6 +49,7 @@ class MeshBuilder:
         t = np.asarray(t, dtype=np.int64).reshape(-1, 3)
         if len(t):
             self._t.append(t)
+            self.nt += len(t)
 
     def arrays(self):
         """float32 vertices (unused ones dropped) and int32 triangles."""
@@ -481,7 +484,15 @@ class Bore:
         bot = mb.add_verts(f.pos(bot_l[:, 0], bot_l[:, 1], s.h + bot_l[:, 2]))
         mb.add_tris(strip(rim, bot))
         c = np.array([self.cu, self.cv, 0.0]) + self.length * a
+        t0 = mb.nt
         mb.add_tris(fan(mb, bot, f.pos(c[0], c[1], s.h + c[2])))
+        out_axis = -(a[0] * f.eu + a[1] * f.ev + a[2] * f.en)
+        mb.notes.append({"kind": "bore", "floor_tris": (t0, mb.nt), "axis": out_axis.tolist(),
+                         "floor_centre": f.pos(c[0], c[1], s.h + c[2]).tolist(), "r": self.r,
+                         "tilt": self.tilt, "length": self.length,
+                         "rim": f.pos(rim_uv[:, 0], rim_uv[:, 1], s.h).tolist(),
+                         "face_normal": f.en.tolist(), "face_point": f.pos(0.0, 0.0, s.h).tolist(),
+                         "face_axes": [f.eu.tolist(), f.ev.tolist()]})
 
 
 def _perp(a):
@@ -551,7 +562,9 @@ class Block:
         for s in self.faces.values():
             s.emit()
         v, t = self.mb.arrays()
-        return Mesh(v, t, name, meta or {})
+        meta = dict(meta or {})
+        meta["features"] = self.mb.notes
+        return Mesh(v, t, name, meta)
 
 
 # ----------------------------------------------------------------------------
@@ -833,6 +846,34 @@ def _procedural(seed, density, family, dims, n_features):
                 return c0, d0
         return None
 
+    if family == "multiaxis":   # inclined bores first, before holes take the room
+        nb = int(rng.integers(16, 29))
+        for _ in range(nb):        # inclined bores
+            face = "+Z" if rng.random() < 0.75 else ["+X", "-X", "+Y", "-Y"][int(rng.integers(4))]
+            s = F[face]
+            r = rng.uniform(2, 6)
+            tilt = math.radians(rng.uniform(10, 60))
+            azim = rng.uniform(0, 2 * math.pi)
+            maxd = (H - 8.0) if face == "+Z" else side_depth - 2.0
+            length = rng.uniform(2.5 * r, 6 * r)
+            bore = Bore(0.0, 0.0, r, length, tilt, azim, _kgon(r, seg))
+            while bore.max_depth() > maxd and bore.length > r:
+                bore.length *= 0.8
+            if bore.max_depth() > maxd:
+                continue
+            fu0, fv0, fu1, fv1, _ = bore.footprint()
+            wmm, hmm = fu1 - fu0 + 2.5, fv1 - fv0 + 2.5
+            wc, hc = int(math.ceil(wmm / cs)) + 1, int(math.ceil(hmm / cs)) + 1
+            at = try_place(s, wc, hc, region(face), tries=200)
+            if at is None:
+                continue
+            c0, d0 = at
+            u0, v0 = s.uv(c0 * M, d0 * M)
+            u1, v1 = s.uv((c0 + wc) * M, (d0 + hc) * M)
+            # centre the footprint in the macro cell
+            bore.cu = (u0 + u1) / 2 - (fu0 + fu1) / 2
+            bore.cv = (v0 + v1) / 2 - (fv0 + fv1) / 2
+            s.add(c0, d0, c0 + wc, d0 + hc, bore)
     for item in plan:
         if item[0] != "hole":
             continue
@@ -912,33 +953,6 @@ def _procedural(seed, density, family, dims, n_features):
             rim = (u0 + fl + 1.0, v0 + fl + 1.0, u1 - fl - 1.0, v1 - fl - 1.0)
             depth = rng.uniform(4, 12) if face == "+Z" else rng.uniform(4, side_depth - 2)
             s.add(c0, d0, c0 + wc, d0 + hc, Dovetail(rim, depth, fl, seg=max(2, int(density * 6))))
-        nb = int(rng.integers(12, 25))
-        for _ in range(nb):        # inclined bores
-            face = "+Z" if rng.random() < 0.75 else ["+X", "-X", "+Y", "-Y"][int(rng.integers(4))]
-            s = F[face]
-            r = rng.uniform(2, 6)
-            tilt = math.radians(rng.uniform(10, 60))
-            azim = rng.uniform(0, 2 * math.pi)
-            maxd = (H - 8.0) if face == "+Z" else side_depth - 2.0
-            length = rng.uniform(2 * r, 5 * r)
-            bore = Bore(0.0, 0.0, r, length, tilt, azim, _kgon(r, seg))
-            while bore.max_depth() > maxd and bore.length > r:
-                bore.length *= 0.8
-            if bore.max_depth() > maxd:
-                continue
-            fu0, fv0, fu1, fv1, _ = bore.footprint()
-            wmm, hmm = fu1 - fu0 + 2.5, fv1 - fv0 + 2.5
-            wc, hc = int(math.ceil(wmm / cs)) + 1, int(math.ceil(hmm / cs)) + 1
-            at = try_place(s, wc, hc, region(face))
-            if at is None:
-                continue
-            c0, d0 = at
-            u0, v0 = s.uv(c0 * M, d0 * M)
-            u1, v1 = s.uv((c0 + wc) * M, (d0 + hc) * M)
-            # centre the footprint in the macro cell
-            bore.cu = (u0 + u1) / 2 - (fu0 + fu1) / 2
-            bore.cv = (v0 + v1) / 2 - (fv0 + fv1) / 2
-            s.add(c0, d0, c0 + wc, d0 + hc, bore)
     return b.build(f"{family}-{seed}", {"seed": seed, "family": family, "dims": (W, D, H), "density": density})
 
 

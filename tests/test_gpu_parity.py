@@ -368,3 +368,57 @@ def test_cast_work_counts(ctx, cfg1):
     wbits, nodes, tests = ctx.cast_work(b, s, 512)
     assert np.array_equal(_u32(wbits), _u32(bits))
     assert nodes >= 200 * 512 and tests > 0
+
+
+# ---------------------------------------------------------------- full size (multi-axis stress part)
+def test_multiaxis_full_size(ctx, orc):
+    """1M-triangle part, 250k samples x 2048 directions in one cast: sampled
+    rows against brute force; the histogram of each inclined bore's floor
+    samples has the same peak as the oracle's on the same bits, and
+    the rays from each bore's floor centre escape exactly when they cross
+    the face plane inside the rim polygon (convex cavity closed form)."""
+    import torch
+    from paper_2609_05467_amd import hra
+    m = P.workload_parts("multiaxis_1m")[0]
+    S, N = 250_000, 2048
+    _say("multiaxis full", m.n_tris, S, N)
+    b = ctx.build_bvh(m.verts, m.tris)
+    inf = b.info()
+    assert inf.n_degenerate == 0
+    s = ctx.sample_surface(b, S, 3)
+    bits, cnt = ctx.cast(b, s, N)
+    got = _u32(bits)
+    sn = _np_samples(s)
+    rows = np.sort(np.random.default_rng(3).choice(S, 8, replace=False))
+    ob, og, _ = orc.cast(m.verts, m.tris, {k: v[rows] for k, v in sn.items()}, orc.fibonacci_dirs(N))
+    assert not ((got[rows] ^ ob) & ~og).any()
+    st = ctx.dominant_axes(s, N, bits)
+    h = st["hist"].cpu().numpy().view(np.uint32)
+    assert int(h.astype(np.int64).sum()) == int(_u32(cnt).astype(np.int64).sum())
+    dirs = orc.fibonacci_dirs(N)
+    checked = 0
+    for f in m.meta["features"]:
+        if f["kind"] != "bore":
+            continue
+        t0, t1 = f["floor_tris"]
+        sel = np.nonzero((sn["tri"] >= t0) & (sn["tri"] < t1))[0]
+        if len(sel) < 5:
+            continue
+        idx = torch.tensor(sel, device=ctx.device)
+        sub = {k: v[idx].contiguous() for k, v in s.items()}
+        sbits = bits[idx].contiguous()
+        hs = ctx.dominant_axes(sub, N, sbits)["hist"].cpu().numpy().view(np.uint32)
+        pk = hra.histogram_peaks(hs, 1)
+        o = orc.dirstats({k: v[sel] for k, v in sn.items()}, dirs, got[sel])
+        opk = orc.histogram_peaks(o["hist"], 1)
+        assert pk["bins"] == opk["bins"]
+        # exact visibility from the floor centre (convex cavity, oblique rim)
+        from closed_forms import bore_closed_form, bore_floor_sample
+        fs = bore_floor_sample(orc, m, f)
+        ts = {k: torch.tensor(v, device=ctx.device) for k, v in fs.items()}
+        fb, _ = ctx.cast(b, ts, N)
+        want, keep = bore_closed_form(f, fs["origin"][0], orc.ray_dirs(fs["normal"], dirs)[0])
+        gotf = orc.unpack_bits(_u32(fb), N)[0]
+        assert keep.sum() >= N - 3 and np.array_equal(gotf[keep], want[keep]) and want.sum() > 0
+        checked += 1
+    assert checked >= 3

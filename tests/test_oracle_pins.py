@@ -629,3 +629,25 @@ def test_dirstats_tilted_open_face(orc):
     assert np.allclose(st["absmean"], A, atol=2e-3)
     assert np.all(np.abs(st["conc"] - c) < 2e-3)
     assert A[2] - 0.4 > 0.05      # the tilted face's |d_z| mean is not |m_z|
+
+
+# ---------------------------------------------------------------- inclined bores
+from closed_forms import bore_closed_form, bore_floor_sample  # noqa: E402
+
+
+def test_inclined_bore_floor_closed_form(orc):
+    # same seed and layout as the 1M-triangle multi-axis part, coarse tessellation
+    m = P._procedural(3, 1.0, "multiaxis", None, None)
+    bores = [f for f in m.meta["features"] if f["kind"] == "bore"]
+    assert len(bores) >= 3
+    N = 1024
+    d = orc.fibonacci_dirs(N)
+    for f in bores:
+        s = bore_floor_sample(orc, m, f)
+        assert np.allclose(s["normal"][0], np.array(f["axis"]) / np.linalg.norm(f["axis"]), atol=1e-5)
+        bits, gr, _ = orc.cast(m.verts, m.tris, s, d)
+        got = orc.unpack_bits(bits, N)[0]
+        want, keep = bore_closed_form(f, s["origin"][0], orc.ray_dirs(s["normal"], d)[0])
+        assert keep.sum() >= N - 3
+        assert np.array_equal(got[keep], want[keep])
+        assert want.sum() > 0
