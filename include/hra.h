@@ -79,6 +79,24 @@ typedef struct {
 hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t n_verts, const int32_t *d_tris,
                          int64_t n_tris, const hra_bvh_opts *opts, void *stream, hra_bvh **out);
 
+/* One input mesh: device vertex and triangle arrays as for hra_build_bvh. */
+typedef struct {
+    const float *d_verts;   /* float [n_verts][3], mm */
+    int64_t n_verts;
+    const int32_t *d_tris;  /* int32 [n_tris][3], counter-clockwise seen from outside */
+    int64_t n_tris;
+} hra_mesh;
+
+/* Build one hierarchy over several parts at once (1..255 parts, at most
+ * 2^27 triangles in all): one sort and one tree, each part a subtree of its
+ * own.  Part p of the handle is meshes[p]; every per-part entry point takes
+ * the part index.  Same ownership, errors and stream rules as
+ * hra_build_bvh (which is this call with one part). */
+hra_status hra_build_bvh_batch(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, const hra_bvh_opts *opts,
+                               void *stream, hra_bvh **out);
+/* Number of parts in a hierarchy. */
+int32_t hra_bvh_parts(const hra_bvh *bvh);
+
 typedef struct {
     float bbox[6];         /* min xyz, max xyz of the vertices (the stock box) */
     double diag;           /* |max - min| */
@@ -90,8 +108,10 @@ typedef struct {
     int32_t leaf_size;
 } hra_bvh_info;
 
-/* Copy the handle's summary to the host.  Synchronises `stream`. */
+/* Copy the summary of part 0 (hra_bvh_get_info) or of part `part` to the
+ * host.  Synchronises `stream`. */
 hra_status hra_bvh_get_info(hra_bvh *bvh, void *stream, hra_bvh_info *out);
+hra_status hra_bvh_part_info(hra_bvh *bvh, int32_t part, void *stream, hra_bvh_info *out);
 
 /* Copy the hierarchy to host memory, for inspection and invariant checks.
  * host_nodes: n_tris - 1 (at least 1) records of 64 bytes: float lo0[3],
@@ -100,7 +120,8 @@ hra_status hra_bvh_get_info(hra_bvh *bvh, void *stream, hra_bvh_info *out);
  * 0..26 = first triangle; slots that are not part of the tree hold children
  * 0x7fffffff.  host_tris: n_tris x 48 bytes, the first n_valid used: float4
  * v0, v1, v2 in leaf order, w = face index (int32 bits).  *root: the root
- * reference; *n_valid: triangles in the hierarchy.  Synchronises. */
+ * reference; *n_valid: triangles in the hierarchy (part 0 of a batch
+ * hierarchy; its other parts follow in the same arrays).  Synchronises. */
 hra_status hra_bvh_export(hra_bvh *bvh, void *stream, void *host_nodes, void *host_tris, int32_t *root,
                           int32_t *n_valid);
 void hra_bvh_release(hra_bvh *bvh);
@@ -126,6 +147,10 @@ enum { HRA_SAMPLE_AREA = 0, HRA_SAMPLE_CENTROID = 1 };
  * usual value) along the face normal.  Caller allocates the four arrays. */
 hra_status hra_sample_surface(hra_ctx *ctx, const hra_bvh *bvh, int32_t mode, uint64_t seed,
                               float offset_frac, const hra_samples *out, void *stream);
+/* The same for part `part` of a batch hierarchy (face indices are the
+ * part's own). */
+hra_status hra_sample_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, int32_t mode, uint64_t seed,
+                           float offset_frac, const hra_samples *out, void *stream);
 
 /* -------------------------------------------------------------- directions */
 
@@ -157,6 +182,9 @@ hra_status hra_dirs_table(hra_ctx *ctx, hra_dirs dirs, float *host_out);
  * [samples->n] popcount of each row, or NULL. */
 hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
                                uint32_t *d_bits, uint32_t *d_counts, void *stream);
+/* The same against part `part` of a batch hierarchy. */
+hra_status hra_cast_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples, hra_dirs dirs,
+                         uint32_t *d_bits, uint32_t *d_counts, void *stream);
 
 typedef struct {
     int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
@@ -277,6 +305,43 @@ typedef struct {
 hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples,
                           const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
                           hra_setup_report *out, void *stream);
+/* The same for part `part` of a batch hierarchy. */
+hra_status hra_min_setups_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                               const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
+                               hra_setup_report *out, void *stream);
+
+/* ------------------------------------------------------------- batches */
+
+typedef struct {
+    hra_mesh mesh;          /* the part's mesh (device arrays, caller-owned) */
+    int64_t n_samples;      /* area-weighted samples to draw (>= 1) */
+    uint64_t seed;          /* their SplitMix64 stream */
+    double tool_length;     /* usable tool length for the setup search, mm */
+} hra_part_request;
+
+typedef struct {
+    int32_t n_dirs;                     /* hemisphere directions for every part */
+    int32_t leaf_size;                  /* 0 = default (4) */
+    float offset_frac;                  /* 0 = 1e-4 */
+    const hra_thresholds *thresholds;   /* NULL = defaults */
+} hra_batch_opts;
+
+typedef struct {
+    hra_class_report cls;
+    hra_setup_report setups;
+} hra_part_result;
+
+/* The whole path for many parts at once: one hierarchy for all meshes
+ * (hra_build_bvh_batch), then one launch each for sampling, the hemisphere
+ * cast, the directional statistics, the part totals, the six-axis cast and
+ * the setup counts, every launch covering all parts.  Per part, the
+ * results equal those of the single-part calls on the same inputs (the same
+ * samples, bits, statistics, class and setups).  results: host
+ * [n_parts].  Synchronises `stream`.  If d_bits_out is not NULL it receives
+ * the hemisphere bitmasks of all parts, part after part: uint32
+ * [sum n_samples][ceil(n_dirs / 32)]. */
+hra_status hra_batch_run(hra_ctx *ctx, const hra_part_request *parts, int32_t n_parts, const hra_batch_opts *opts,
+                         hra_part_result *results, uint32_t *d_bits_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -197,8 +197,9 @@ static inline void offset_origin(const float *p, const float *n, float eps, floa
 }
 
 /* Area weights as integers so the choice of triangle is exact integer work:
- * w_f = floor(area_f * 2^k), k = 62 - (ilogb(max area) + 1) - bitlen(T),
- * which keeps sum(w) < 2^62. Zero-area triangles get weight 0. */
+ * w_f = floor(area_f * 2^k), k = 54 - (ilogb(max area) + 1) - bitlen(T),
+ * which keeps sum(w) < 2^54 (room for many parts' weights in one 64-bit
+ * running sum). Zero-area triangles get weight 0. */
 int orc_area_weights(const float *V, const int32_t *T, int64_t nt, uint64_t *w, int32_t *k_out) {
     double amax = 0.0;
     double *area = (double *)malloc(sizeof(double) * (nt > 0 ? nt : 1));
@@ -214,7 +215,7 @@ int orc_area_weights(const float *V, const int32_t *T, int64_t nt, uint64_t *w, 
     int E = ilogb(amax);
     int tb = 0;
     while (tb < 63 && ((int64_t)1 << tb) <= nt) ++tb;
-    int k = 62 - (E + 1) - tb;
+    int k = 54 - (E + 1) - tb;
     for (int64_t f = 0; f < nt; ++f) w[f] = (uint64_t)floor(ldexp(area[f], k));
     free(area);
     *k_out = k;

@@ -1,20 +1,30 @@
-// Mesh ingest and LBVH construction, all on the device.
+// Mesh ingest and LBVH construction for one or many parts at once, all on
+// the device.
+//
+// Every part's triangles are concatenated; a 64-bit key puts the part index
+// in the top 8 bits and a 54-bit Morton code (18 bits per axis, in the part's
+// own bounding box) below, so one global sort lays every part out as a
+// contiguous run, and in the binary radix tree over the sorted keys each
+// run is exactly one subtree (the keys of a part share its 8-bit prefix, so
+// their lowest common ancestor holds no other key).  Traversal of part p
+// starts at that subtree's root; nodes spanning two parts are never used.
 //
 // Stages (one stream, no host round trip):
-//   1. per-triangle prep: index check, FP64 doubled-area-squared, area,
-//      nonzero-area flag;
-//   2. vertex bbox, largest area (two-pass reductions) -> BvhMeta;
-//   3. integer area weights and their inclusive prefix (for the sampler),
-//      ranks of nonzero-area faces (for centroid samples);
-//   4. 63-bit Morton codes of centroids; zero-area faces get the largest key;
+//   1. per-triangle prep: part lookup, index check, FP64 doubled area
+//      squared, area, nonzero-area flag, a copy of the three vertices;
+//   2. per-part vertex bbox, diagonal, largest area, weight scale;
+//   3. integer area weights, their global inclusive prefix (the sampler
+//      searches a part's range), ranks of nonzero-area faces;
+//   4. keys (part, Morton of the centroid); zero-area faces get the
+//      largest key;
 //   5. LSD radix sort, 8 passes of 8 bits, LDS digit counts and a stable
 //      LDS-ranked scatter;
-//   6. binary radix tree over the sorted codes (Karras, "Maximizing
+//   6. binary radix tree over the sorted keys (Karras, "Maximizing
 //      Parallelism in the Construction of BVHs, Octrees, and k-d Trees", HPG
-//      2012), ties between equal codes broken by position;
+//      2012), ties between equal keys broken by position; part roots;
 //   7. bottom-up box refit: the second thread to reach a node merges it;
-//   8. leaf collapse (subtrees with <= leaf_size triangles become one leaf
-//      over a contiguous run) and emission of 64-byte nodes.
+//   8. leaf collapse (subtrees of one part with <= leaf_size triangles become
+//      one leaf over a contiguous run) and emission of 64-byte nodes.
 #include "common.hpp"
 
 #include <algorithm>
@@ -98,6 +108,17 @@ static hipError_t scan(const T *in, T *out, int64_t n, bool inclusive, hipStream
 }
 
 // ---------------------------------------------------------------- ingest
+// Part of global triangle g: the last part whose tri_start <= g.
+__device__ inline int part_of(const MeshIn *mesh, int n_parts, int64_t g) {
+    int lo = 0, hi = n_parts - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (mesh[mid].tri_start <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // FP64 doubled area squared, fixed order (twice the area is |(v1-v0)x(v2-v0)|).
 __device__ inline double tri_q64(const float *a, const float *b, const float *c) {
     const double e1x = (double)b[0] - (double)a[0], e1y = (double)b[1] - (double)a[1], e1z = (double)b[2] - (double)a[2];
@@ -113,46 +134,58 @@ __device__ inline double tri_q64(const float *a, const float *b, const float *c)
     return sxy + sz;
 }
 
-__global__ void k_tri_prep(const float *verts, int64_t nv, const int32_t *tris, int64_t nt, double *area,
-                           uint32_t *valid, uint32_t *err) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nt) return;
-    const int32_t i0 = tris[3 * f], i1 = tris[3 * f + 1], i2 = tris[3 * f + 2];
-    if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+// tv: the triangle's three vertices (9 floats), tpart: its part.
+__global__ void k_tri_prep(const MeshIn *mesh, int n_parts, int64_t T, double *area, uint32_t *valid, float *tv,
+                           uint8_t *tpart, uint32_t *err) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= T) return;
+    const int p = part_of(mesh, n_parts, g);
+    const MeshIn m = mesh[p];
+    const int64_t f = g - m.tri_start;
+    tpart[g] = (uint8_t)p;
+    const int32_t i0 = m.t[3 * f], i1 = m.t[3 * f + 1], i2 = m.t[3 * f + 2];
+    if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= m.nv || i1 >= m.nv || i2 >= m.nv) {
         atomicOr(err, ERR_BAD_INDEX);
-        area[f] = 0.0;
-        valid[f] = 0;
+        area[g] = 0.0;
+        valid[g] = 0;
+        for (int k = 0; k < 9; ++k) tv[9 * g + k] = 0.0f;
         return;
     }
-    const double q = tri_q64(verts + 3 * (int64_t)i0, verts + 3 * (int64_t)i1, verts + 3 * (int64_t)i2);
+    const float *a = m.v + 3 * (int64_t)i0, *b = m.v + 3 * (int64_t)i1, *c = m.v + 3 * (int64_t)i2;
+    for (int k = 0; k < 3; ++k) {
+        tv[9 * g + k] = a[k];
+        tv[9 * g + 3 + k] = b[k];
+        tv[9 * g + 6 + k] = c[k];
+    }
+    const double q = tri_q64(a, b, c);
     const bool ok = q > 0.0;
-    area[f] = ok ? 0.5 * sqrt(q) : 0.0;
-    valid[f] = ok ? 1u : 0u;
+    area[g] = ok ? 0.5 * sqrt(q) : 0.0;
+    valid[g] = ok ? 1u : 0u;
 }
 
-constexpr int RED_BLOCKS = 256;
-
-// partial[b] = {min xyz, max xyz, max area}
-__global__ void k_reduce_partial(const float *verts, int64_t nv, const double *area, int64_t nt, double *partial) {
-    __shared__ double s[7][TB];
+// One block per part: vertex bbox, diagonal, largest area, weight scale
+// k = 54 - (ilogb(amax) + 1) - bitlen(n_tris), which keeps each part's weight
+// sum below 2^54 and the sum over up to 1024 parts below 2^64.
+__global__ void k_part_facts(const MeshIn *mesh, const double *area, PartMeta *meta) {
+    __shared__ double s[7][256];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const MeshIn m = mesh[p];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double amax = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride)
+    for (int64_t i = t; i < m.nv; i += blockDim.x)
         for (int c = 0; c < 3; ++c) {
-            const float x = verts[3 * i + c];
+            const float x = m.v[3 * i + c];
             lo[c] = fminf(lo[c], x);
             hi[c] = fmaxf(hi[c], x);
         }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) amax = fmax(amax, area[i]);
-    const int t = threadIdx.x;
+    for (int64_t i = t; i < m.nt; i += blockDim.x) amax = fmax(amax, area[m.tri_start + i]);
     for (int c = 0; c < 3; ++c) {
         s[c][t] = lo[c];
         s[3 + c][t] = hi[c];
     }
     s[6][t] = amax;
     __syncthreads();
-    for (int off = TB / 2; off > 0; off >>= 1) {
+    for (int off = 128; off > 0; off >>= 1) {
         if (t < off) {
             for (int c = 0; c < 3; ++c) {
                 s[c][t] = fmin(s[c][t], s[c][t + off]);
@@ -162,61 +195,65 @@ __global__ void k_reduce_partial(const float *verts, int64_t nv, const double *a
         }
         __syncthreads();
     }
-    if (t == 0)
-        for (int k = 0; k < 7; ++k) partial[7 * blockIdx.x + k] = s[k][0];
-}
-
-__global__ void k_reduce_final(const double *partial, int nparts, int64_t nt, BvhMeta *meta) {
-    if (threadIdx.x != 0) return;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, amax = 0.0;
-    for (int b = 0; b < nparts; ++b) {
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = fmin(lo[c], partial[7 * b + c]);
-            hi[c] = fmax(hi[c], partial[7 * b + 3 + c]);
-        }
-        amax = fmax(amax, partial[7 * b + 6]);
-    }
+    if (t != 0) return;
+    PartMeta &P = meta[p];
     for (int c = 0; c < 3; ++c) {
-        meta->bbox[c] = (float)lo[c];
-        meta->bbox[3 + c] = (float)hi[c];
+        P.bbox[c] = (float)s[c][0];
+        P.bbox[3 + c] = (float)s[3 + c][0];
     }
-    const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    const double dx = s[3][0] - s[0][0], dy = s[4][0] - s[1][0], dz = s[5][0] - s[2][0];
     const double sx = dx * dx, sy = dy * dy, sz = dz * dz;
     const double sxy = sx + sy;
-    meta->diag = sqrt(sxy + sz);
-    meta->amax = amax;
-    // weights floor(area * 2^k) with k = 62 - (ilogb(amax) + 1) - bitlen(nt)
-    // keep the weight sum below 2^62
+    P.diag = sqrt(sxy + sz);
+    P.amax = s[6][0];
     int tb = 0;
-    while (tb < 63 && ((int64_t)1 << tb) <= nt) ++tb;
-    meta->k_scale = amax > 0.0 ? 62 - (ilogb(amax) + 1) - tb : 0;
-    meta->root = 0;
-    meta->depth = 0;
-    meta->n_nodes = 0;
+    while (tb < 63 && ((int64_t)1 << tb) <= m.nt) ++tb;
+    P.k_scale = P.amax > 0.0 ? 54 - (ilogb(P.amax) + 1) - tb : 0;
+    P.tri_start = m.tri_start;
+    P.n_tris = (int32_t)m.nt;
+    P.n_verts = m.nv;
+    P.root = 0;
+    P.depth = 0;
+    P.n_nodes = 0;
 }
 
-__global__ void k_weights(const double *area, int64_t nt, const BvhMeta *meta, uint64_t *w) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nt) return;
-    w[f] = (uint64_t)floor(ldexp(area[f], meta->k_scale));
+__global__ void k_weights(const double *area, const uint8_t *tpart, int64_t T, const PartMeta *meta, uint64_t *w) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= T) return;
+    w[g] = (uint64_t)floor(ldexp(area[g], meta[tpart[g]].k_scale));
 }
 
-__global__ void k_ranks(const uint32_t *valid, const uint32_t *excl, int64_t nt, int32_t *rank, const uint64_t *prefix,
-                        BvhMeta *meta, uint32_t *err) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nt) return;
-    rank[f] = valid[f] ? (int32_t)excl[f] : -1;
-    if (f == nt - 1) {
-        const int32_t nvld = (int32_t)(excl[f] + valid[f]);
-        meta->n_valid = nvld;
-        meta->total_w = prefix[f];
-        if (nvld == 0) atomicOr(err, ERR_EMPTY_MESH);
+// Per part: weight base and total, nonzero-area count, first leaf position.
+// Single thread: at most MAX_PARTS parts.
+__global__ void k_part_counts(const uint64_t *prefix, const uint32_t *excl, const uint32_t *valid, int n_parts,
+                              int64_t T, PartMeta *meta, int32_t *n_valid_total, uint32_t *err) {
+    if (threadIdx.x != 0) return;
+    int32_t leaf = 0;
+    for (int p = 0; p < n_parts; ++p) {
+        PartMeta &P = meta[p];
+        const int64_t a = P.tri_start, b = P.tri_start + P.n_tris;
+        P.base_w = a > 0 ? prefix[a - 1] : 0;
+        P.total_w = prefix[b - 1] - P.base_w;
+        const uint32_t ea = excl[a], eb = b < T ? excl[b] : excl[T - 1] + valid[T - 1];
+        P.n_valid = (int32_t)(eb - ea);
+        P.leaf_lo = leaf;
+        leaf += P.n_valid;
+        if (P.n_valid == 0) atomicOr(err, ERR_EMPTY_MESH);
     }
+    *n_valid_total = leaf;
 }
 
-// ---------------------------------------------------------------- Morton
-__device__ inline uint64_t spread21(uint32_t x) {
-    uint64_t v = x & 0x1FFFFFu;
+__global__ void k_ranks(const uint32_t *valid, const uint32_t *excl, const uint8_t *tpart, int64_t T,
+                        const PartMeta *meta, int32_t *rank) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= T) return;
+    const PartMeta &P = meta[tpart[g]];
+    rank[g] = valid[g] ? (int32_t)(excl[g] - excl[P.tri_start]) : -1;
+}
+
+// ---------------------------------------------------------------- keys
+__device__ inline uint64_t spread18(uint32_t x) {
+    uint64_t v = x & 0x3FFFFu;
     v = (v | (v << 32)) & 0x001F00000000FFFFull;
     v = (v | (v << 16)) & 0x001F0000FF0000FFull;
     v = (v | (v << 8)) & 0x100F00F00F00F00Full;
@@ -225,33 +262,33 @@ __device__ inline uint64_t spread21(uint32_t x) {
     return v;
 }
 
-__device__ inline uint32_t quant21(float c, float lo, float hi) {
+__device__ inline uint32_t quant18(float c, float lo, float hi) {
     const float ext = hi - lo;
     float x = ext > 0.0f ? (c - lo) / ext : 0.5f;
     x = fminf(fmaxf(x, 0.0f), 1.0f);
-    const uint32_t q = (uint32_t)(x * 2097152.0f);
-    return q > 2097151u ? 2097151u : q;
+    const uint32_t q = (uint32_t)(x * 262144.0f);
+    return q > 262143u ? 262143u : q;
 }
 
-__global__ void k_morton(const float *verts, const int32_t *tris, int64_t nt, const uint32_t *valid,
-                         const BvhMeta *meta, uint64_t *keys, uint32_t *vals) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nt) return;
-    vals[f] = (uint32_t)f;
-    if (!valid[f]) {
-        keys[f] = ~0ull;
+__global__ void k_keys(const float *tv, const uint8_t *tpart, const uint32_t *valid, int64_t T, const PartMeta *meta,
+                       uint64_t *keys, uint32_t *vals) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= T) return;
+    vals[g] = (uint32_t)g;
+    if (!valid[g]) {
+        keys[g] = ~0ull;
         return;
     }
-    const float *a = verts + 3 * (int64_t)tris[3 * f];
-    const float *b = verts + 3 * (int64_t)tris[3 * f + 1];
-    const float *c = verts + 3 * (int64_t)tris[3 * f + 2];
+    const int p = tpart[g];
+    const PartMeta &P = meta[p];
+    const float *v = tv + 9 * g;
     uint64_t code = 0;
     for (int k = 0; k < 3; ++k) {
-        const float s = (a[k] + b[k]) + c[k];
+        const float s = (v[k] + v[3 + k]) + v[6 + k];
         const float m = s * (1.0f / 3.0f);
-        code |= spread21(quant21(m, meta->bbox[k], meta->bbox[3 + k])) << (2 - k);
+        code |= spread18(quant18(m, P.bbox[k], P.bbox[3 + k])) << (2 - k);
     }
-    keys[f] = code;
+    keys[g] = ((uint64_t)p << 56) | code;
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -343,46 +380,51 @@ static hipError_t radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t 
 }
 
 // ---------------------------------------------------------------- gather
-__global__ void k_gather(const float *verts, const int32_t *tris, const uint32_t *sorted_vals, const BvhMeta *meta,
-                         float4 *tri4, int32_t *leaf_pos) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= meta->n_valid) return;
-    const uint32_t f = sorted_vals[p];
-    for (int k = 0; k < 3; ++k) {
-        const float *v = verts + 3 * (int64_t)tris[3 * (int64_t)f + k];
-        tri4[3 * p + k] = make_float4(v[0], v[1], v[2], __int_as_float((int)f));
-    }
-    leaf_pos[f] = (int32_t)p;
+__global__ void k_gather(const float *tv, const uint32_t *sorted_vals, const uint8_t *tpart, const PartMeta *meta,
+                         const int32_t *n_valid_total, float4 *tri4, int32_t *leaf_pos) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= *n_valid_total) return;
+    const uint32_t g = sorted_vals[q];
+    const int32_t f = (int32_t)(g - meta[tpart[g]].tri_start);   // face index within its part
+    const float *v = tv + 9 * (int64_t)g;
+    for (int k = 0; k < 3; ++k) tri4[3 * q + k] = make_float4(v[3 * k], v[3 * k + 1], v[3 * k + 2], __int_as_float(f));
+    leaf_pos[g] = (int32_t)q;
 }
 
 // ---------------------------------------------------------------- Karras
 constexpr uint32_t KLEAF = 0x80000000u;
 
-__device__ inline int kdelta(const uint64_t *keys, int n, int i, int j) {
+// Common-prefix length of keys i and j (-1 outside [0, n)).  Equal keys
+// (same part, same cell) fall back to the indices within the part, so a
+// part's subtree is the same whether it is built alone or in a batch.
+__device__ inline int kdelta(const uint64_t *keys, const PartMeta *meta, int n, int i, int j) {
     if (j < 0 || j >= n) return -1;
     const uint64_t a = keys[i], b = keys[j];
-    if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+    if (a == b) {
+        const int s = meta[a >> 56].leaf_lo;
+        return 64 + __clz((uint32_t)((i - s) ^ (j - s)));
+    }
     return __clzll(a ^ b);
 }
 
-__global__ void k_karras(const uint64_t *keys, const BvhMeta *meta, int32_t *left, int32_t *right, int32_t *first,
-                         int32_t *last, int32_t *parent_int, int32_t *parent_leaf) {
-    const int n = meta->n_valid;
+__global__ void k_karras(const uint64_t *keys, const int32_t *n_valid_total, int32_t *left, int32_t *right,
+                         int32_t *first, int32_t *last, int32_t *parent_int, int32_t *parent_leaf, PartMeta *meta) {
+    const int n = *n_valid_total;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
-    const int d = (kdelta(keys, n, i, i + 1) - kdelta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
-    const int dmin = kdelta(keys, n, i, i - d);
+    const int d = (kdelta(keys, meta, n, i, i + 1) - kdelta(keys, meta, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = kdelta(keys, meta, n, i, i - d);
     int lmax = 2;
-    while (kdelta(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    while (kdelta(keys, meta, n, i, i + lmax * d) > dmin) lmax <<= 1;
     int l = 0;
     for (int t = lmax >> 1; t >= 1; t >>= 1)
-        if (kdelta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+        if (kdelta(keys, meta, n, i, i + (l + t) * d) > dmin) l += t;
     const int j = i + l * d;
-    const int dnode = kdelta(keys, n, i, j);
+    const int dnode = kdelta(keys, meta, n, i, j);
     int s = 0, t = l;
     do {
         t = (t + 1) >> 1;
-        if (kdelta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+        if (kdelta(keys, meta, n, i, i + (s + t) * d) > dnode) s += t;
     } while (t > 1);
     const int g = i + s * d + (d < 0 ? d : 0);
     const int lo = i < j ? i : j, hi = i < j ? j : i;
@@ -406,6 +448,12 @@ __global__ void k_karras(const uint64_t *keys, const BvhMeta *meta, int32_t *lef
     first[i] = lo;
     last[i] = hi;
     if (i == 0) parent_int[0] = -1;
+    // the node holding exactly one part's run is that part's subtree root
+    const int p = (int)(keys[lo] >> 56);
+    if ((int)(keys[hi] >> 56) == p && keys[lo] != ~0ull) {
+        PartMeta &P = meta[p];
+        if (lo == P.leaf_lo && hi == P.leaf_lo + P.n_valid - 1) P.root = i;
+    }
 }
 
 // ---------------------------------------------------------------- refit
@@ -433,8 +481,8 @@ __device__ inline void child_box(const float4 *tri4, const float *box_int, int32
 }
 
 __global__ void k_refit(const float4 *tri4, const int32_t *parent_leaf, const int32_t *parent_int, const int32_t *left,
-                        const int32_t *right, float *box_int, uint32_t *flags, const BvhMeta *meta) {
-    const int n = meta->n_valid;
+                        const int32_t *right, float *box_int, uint32_t *flags, const int32_t *n_valid_total) {
+    const int n = *n_valid_total;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n || n < 2) return;
     int node = parent_leaf[p];
@@ -475,23 +523,32 @@ __global__ void k_fill_sentinel_nodes(Node *nodes, int64_t n) {
     nodes[i] = nd;
 }
 
-__global__ void k_emit(const float4 *tri4, const int32_t *left, const int32_t *right, const int32_t *first,
-                       const int32_t *last, const int32_t *parent_int, const float *box_int, int leaf_size,
-                       Node *nodes, BvhMeta *meta) {
-    const int n = meta->n_valid;
+// Roots of parts too small for an interior node of their own: one leaf.
+__global__ void k_small_roots(PartMeta *meta, int n_parts, int leaf_size) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_parts) return;
+    PartMeta &P = meta[p];
+    if (P.n_valid >= 1 && P.n_valid <= leaf_size) P.root = leaf_code(P.leaf_lo, P.n_valid);
+}
+
+__global__ void k_emit(const float4 *tri4, const uint64_t *keys, const int32_t *left, const int32_t *right,
+                       const int32_t *first, const int32_t *last, const int32_t *parent_int, const float *box_int,
+                       int leaf_size, const int32_t *n_valid_total, Node *nodes, PartMeta *meta) {
+    const int n = *n_valid_total;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) meta->root = (n <= leaf_size) ? leaf_code(0, n) : 0;
     if (i >= n - 1) return;
     if (last[i] - first[i] + 1 <= leaf_size) return;
+    const int p = (int)(keys[first[i]] >> 56);
+    if ((int)(keys[last[i]] >> 56) != p) return;   // spans two parts: never traversed
     float bx[2][6];
     int32_t code[2];
     const int32_t ch[2] = {left[i], right[i]};
     for (int k = 0; k < 2; ++k) {
         const int32_t c = ch[k];
         if ((uint32_t)c & KLEAF) {
-            const int p = (int)((uint32_t)c & ~KLEAF);
-            tri_box(tri4, p, bx[k]);
-            code[k] = leaf_code(p, 1);
+            const int q = (int)((uint32_t)c & ~KLEAF);
+            tri_box(tri4, q, bx[k]);
+            code[k] = leaf_code(q, 1);
         } else {
             load_box(box_int, c, bx[k]);
             const int cnt = last[c] - first[c] + 1;
@@ -504,35 +561,47 @@ __global__ void k_emit(const float4 *tri4, const int32_t *left, const int32_t *r
     nd.c = make_float4(bx[1][2], bx[1][3], bx[1][4], bx[1][5]);
     nd.d = make_int4(code[0], code[1], 0, 0);
     nodes[i] = nd;
-    atomicAdd(&meta->n_nodes, 1);
+    atomicAdd(&meta[p].n_nodes, 1);
+    // depth within the part: emitted ancestors up to the part root
     int depth = 1;
-    for (int a = parent_int[i]; a >= 0 && a < n - 1 && depth <= n; a = parent_int[a]) ++depth;
-    atomicMax(&meta->depth, depth);
+    const int32_t root = meta[p].root;
+    for (int a = i; a != root && a >= 0 && a < n - 1 && depth <= n; a = parent_int[a]) ++depth;
+    atomicMax(&meta[p].depth, depth);
 }
 
 }  // namespace hra
 
 using namespace hra;
 
-extern "C" hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t n_verts, const int32_t *d_tris,
-                                    int64_t n_tris, const hra_bvh_opts *opts, void *stream, hra_bvh **out) {
-    if (!ctx || !out) return HRA_ERR_INVALID_ARG;
+static hra_status build_parts(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, const hra_bvh_opts *opts,
+                              hipStream_t s, hra_bvh **out) {
+    if (!ctx || !out || !meshes) return HRA_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!d_verts || !d_tris || n_verts < 3 || n_tris < 1)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "mesh needs at least 3 vertices and 1 triangle");
-    if (n_tris >= (int64_t)1 << 27 || n_verts >= (int64_t)1 << 31)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "mesh too large (max 2^27 triangles)");
+    if (n_parts < 1 || n_parts > MAX_PARTS) return ctx->fail(HRA_ERR_INVALID_ARG, "1..255 parts per hierarchy");
+    int64_t T = 0;
+    std::vector<MeshIn> hm(n_parts);
+    for (int p = 0; p < n_parts; ++p) {
+        const hra_mesh &m = meshes[p];
+        if (!m.d_verts || !m.d_tris || m.n_verts < 3 || m.n_tris < 1)
+            return ctx->fail(HRA_ERR_INVALID_ARG, "each mesh needs at least 3 vertices and 1 triangle");
+        if (m.n_verts >= (int64_t)1 << 31) return ctx->fail(HRA_ERR_INVALID_ARG, "too many vertices in a mesh");
+        hm[p] = MeshIn{m.d_verts, m.d_tris, m.n_verts, m.n_tris, T};
+        T += m.n_tris;
+    }
+    if (T >= (int64_t)1 << 27) return ctx->fail(HRA_ERR_INVALID_ARG, "too many triangles (max 2^27 per hierarchy)");
     int leaf = opts && opts->leaf_size ? opts->leaf_size : 4;
     if (leaf < 1 || leaf > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 1..8");
-    hipStream_t s = (hipStream_t)stream;
     HRA_HIP(hipSetDevice(ctx->device));
 
     hra_bvh *b = new hra_bvh();
     b->ctx = ctx;
-    b->n_tris = n_tris;
-    b->n_verts = n_verts;
+    b->n_parts = n_parts;
+    b->n_tris = T;
     b->leaf_size = leaf;
-    const int64_t T = n_tris;
+    for (int p = 0; p < n_parts; ++p) {
+        b->part_tris.push_back(meshes[p].n_tris);
+        b->part_start.push_back(hm[p].tri_start);
+    }
     const int64_t nn = T > 1 ? T - 1 : 1;
     size_t bytes = 0;
     auto alloc = [&](void **p, size_t n) -> bool {
@@ -541,23 +610,25 @@ extern "C" hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t 
     };
     if (!alloc((void **)&b->nodes, sizeof(Node) * nn) || !alloc((void **)&b->tris, sizeof(float4) * 3 * T) ||
         !alloc((void **)&b->leaf_pos, sizeof(int32_t) * T) || !alloc((void **)&b->valid_rank, sizeof(int32_t) * T) ||
-        !alloc((void **)&b->prefix, sizeof(uint64_t) * T) || !alloc((void **)&b->meta, sizeof(BvhMeta))) {
+        !alloc((void **)&b->prefix, sizeof(uint64_t) * T) || !alloc((void **)&b->parts, sizeof(PartMeta) * n_parts)) {
         hra_bvh_release(b);
         return ctx->fail(HRA_ERR_OUT_OF_MEMORY, "BVH allocation failed");
     }
     b->bytes = (int64_t)bytes;
 
     // temporaries, stream ordered
-    double *area = nullptr, *partial = nullptr;
+    double *area = nullptr;
     uint32_t *valid = nullptr, *excl = nullptr, *vals0 = nullptr, *vals1 = nullptr, *flags = nullptr;
     uint64_t *w = nullptr, *keys0 = nullptr, *keys1 = nullptr;
-    int32_t *L = nullptr, *R = nullptr, *F = nullptr, *La = nullptr, *PI = nullptr, *PL = nullptr;
-    float *box = nullptr;
+    int32_t *L = nullptr, *R = nullptr, *F = nullptr, *La = nullptr, *PI = nullptr, *PL = nullptr, *nvt = nullptr;
+    float *box = nullptr, *tv = nullptr;
+    uint8_t *tpart = nullptr;
+    MeshIn *dmesh = nullptr;
     hipError_t e = hipSuccess;
 #define TMP(p, n)                                                   \
     if (e == hipSuccess) e = hipMallocAsync((void **)&(p), (n), s);
+    TMP(dmesh, sizeof(MeshIn) * n_parts);
     TMP(area, sizeof(double) * T);
-    TMP(partial, sizeof(double) * 7 * RED_BLOCKS);
     TMP(valid, sizeof(uint32_t) * T);
     TMP(excl, sizeof(uint32_t) * T);
     TMP(w, sizeof(uint64_t) * T);
@@ -565,6 +636,8 @@ extern "C" hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t 
     TMP(keys1, sizeof(uint64_t) * T);
     TMP(vals0, sizeof(uint32_t) * T);
     TMP(vals1, sizeof(uint32_t) * T);
+    TMP(tv, sizeof(float) * 9 * T);
+    TMP(tpart, sizeof(uint8_t) * T);
     TMP(L, sizeof(int32_t) * nn);
     TMP(R, sizeof(int32_t) * nn);
     TMP(F, sizeof(int32_t) * nn);
@@ -573,40 +646,41 @@ extern "C" hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t 
     TMP(PL, sizeof(int32_t) * T);
     TMP(flags, sizeof(uint32_t) * nn);
     TMP(box, sizeof(float) * 6 * nn);
+    TMP(nvt, sizeof(int32_t));
 #undef TMP
+    if (e == hipSuccess) e = hipMemcpyAsync(dmesh, hm.data(), sizeof(MeshIn) * n_parts, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         const int gT = blocks_for(T, TB), gN = blocks_for(nn, TB);
-        int rb = blocks_for(std::max(n_verts, T), TB);
-        rb = std::min(rb, RED_BLOCKS);
         k_fill_i32<<<gT, TB, 0, s>>>(b->leaf_pos, T, -1);
         k_fill_sentinel_nodes<<<gN, TB, 0, s>>>(b->nodes, nn);
         k_fill_u32<<<gN, TB, 0, s>>>(flags, nn, 0u);
         k_fill_i32<<<gN, TB, 0, s>>>(PI, nn, -1);
-        k_tri_prep<<<gT, TB, 0, s>>>(d_verts, n_verts, d_tris, T, area, valid, ctx->d_err);
-        k_reduce_partial<<<rb, TB, 0, s>>>(d_verts, n_verts, area, T, partial);
-        k_reduce_final<<<1, 64, 0, s>>>(partial, rb, T, b->meta);
-        k_weights<<<gT, TB, 0, s>>>(area, T, b->meta, w);
+        k_tri_prep<<<gT, TB, 0, s>>>(dmesh, n_parts, T, area, valid, tv, tpart, ctx->d_err);
+        k_part_facts<<<n_parts, 256, 0, s>>>(dmesh, area, b->parts);
+        k_weights<<<gT, TB, 0, s>>>(area, tpart, T, b->parts, w);
         e = scan<uint64_t>(w, b->prefix, T, true, s);
         if (e == hipSuccess) e = scan<uint32_t>(valid, excl, T, false, s);
         if (e == hipSuccess) {
-            k_ranks<<<gT, TB, 0, s>>>(valid, excl, T, b->valid_rank, b->prefix, b->meta, ctx->d_err);
-            k_morton<<<gT, TB, 0, s>>>(d_verts, d_tris, T, valid, b->meta, keys0, vals0);
+            k_part_counts<<<1, 64, 0, s>>>(b->prefix, excl, valid, n_parts, T, b->parts, nvt, ctx->d_err);
+            k_ranks<<<gT, TB, 0, s>>>(valid, excl, tpart, T, b->parts, b->valid_rank);
+            k_keys<<<gT, TB, 0, s>>>(tv, tpart, valid, T, b->parts, keys0, vals0);
             bool in1 = false;
             e = radix_sort(keys0, vals0, keys1, vals1, T, s, &in1);
             uint64_t *ks = in1 ? keys1 : keys0;
             uint32_t *vs = in1 ? vals1 : vals0;
             if (e == hipSuccess) {
-                k_gather<<<gT, TB, 0, s>>>(d_verts, d_tris, vs, b->meta, b->tris, b->leaf_pos);
-                k_karras<<<gN, TB, 0, s>>>(ks, b->meta, L, R, F, La, PI, PL);
-                k_refit<<<gT, TB, 0, s>>>(b->tris, PL, PI, L, R, box, flags, b->meta);
-                k_emit<<<gN, TB, 0, s>>>(b->tris, L, R, F, La, PI, box, leaf, b->nodes, b->meta);
+                k_gather<<<gT, TB, 0, s>>>(tv, vs, tpart, b->parts, nvt, b->tris, b->leaf_pos);
+                k_karras<<<gN, TB, 0, s>>>(ks, nvt, L, R, F, La, PI, PL, b->parts);
+                k_small_roots<<<blocks_for(n_parts, 64), 64, 0, s>>>(b->parts, n_parts, leaf);
+                k_refit<<<gT, TB, 0, s>>>(b->tris, PL, PI, L, R, box, flags, nvt);
+                k_emit<<<gN, TB, 0, s>>>(b->tris, ks, L, R, F, La, PI, box, leaf, nvt, b->nodes, b->parts);
                 e = hipGetLastError();
             }
         }
     }
-    for (void *p : {(void *)area, (void *)partial, (void *)valid, (void *)excl, (void *)w, (void *)keys0,
-                    (void *)keys1, (void *)vals0, (void *)vals1, (void *)L, (void *)R, (void *)F, (void *)La,
-                    (void *)PI, (void *)PL, (void *)flags, (void *)box})
+    for (void *p : {(void *)dmesh, (void *)area, (void *)valid, (void *)excl, (void *)w, (void *)keys0, (void *)keys1,
+                    (void *)vals0, (void *)vals1, (void *)tv, (void *)tpart, (void *)L, (void *)R, (void *)F,
+                    (void *)La, (void *)PI, (void *)PL, (void *)flags, (void *)box, (void *)nvt})
         if (p) hipFreeAsync(p, s);
     if (e != hipSuccess) {
         hipStreamSynchronize(s);
@@ -617,22 +691,41 @@ extern "C" hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t 
     return HRA_OK;
 }
 
-extern "C" hra_status hra_bvh_get_info(hra_bvh *b, void *stream, hra_bvh_info *out) {
-    if (!b || !out) return HRA_ERR_INVALID_ARG;
+extern "C" hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t n_verts, const int32_t *d_tris,
+                                    int64_t n_tris, const hra_bvh_opts *opts, void *stream, hra_bvh **out) {
+    if (!ctx || !out) return HRA_ERR_INVALID_ARG;
+    const hra_mesh m = {d_verts, n_verts, d_tris, n_tris};
+    return build_parts(ctx, &m, 1, opts, (hipStream_t)stream, out);
+}
+
+extern "C" hra_status hra_build_bvh_batch(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts,
+                                          const hra_bvh_opts *opts, void *stream, hra_bvh **out) {
+    if (!ctx) return HRA_ERR_INVALID_ARG;
+    return build_parts(ctx, meshes, n_parts, opts, (hipStream_t)stream, out);
+}
+
+extern "C" int32_t hra_bvh_parts(const hra_bvh *b) { return b ? b->n_parts : 0; }
+
+extern "C" hra_status hra_bvh_part_info(hra_bvh *b, int32_t part, void *stream, hra_bvh_info *out) {
+    if (!b || !out || part < 0 || part >= b->n_parts) return HRA_ERR_INVALID_ARG;
     hra_ctx *ctx = b->ctx;
     hra_status st = check_error_word(ctx, (hipStream_t)stream);
     if (st != HRA_OK) return st;
-    BvhMeta m;
-    HRA_HIP(hipMemcpy(&m, b->meta, sizeof(m), hipMemcpyDeviceToHost));
+    PartMeta m;
+    HRA_HIP(hipMemcpy(&m, b->parts + part, sizeof(m), hipMemcpyDeviceToHost));
     for (int k = 0; k < 6; ++k) out->bbox[k] = m.bbox[k];
     out->diag = m.diag;
-    out->n_tris = b->n_tris;
-    out->n_degenerate = b->n_tris - m.n_valid;
+    out->n_tris = m.n_tris;
+    out->n_degenerate = m.n_tris - m.n_valid;
     out->n_nodes = m.n_nodes;
     out->bytes = b->bytes;
     out->depth = m.depth;
     out->leaf_size = b->leaf_size;
     return HRA_OK;
+}
+
+extern "C" hra_status hra_bvh_get_info(hra_bvh *b, void *stream, hra_bvh_info *out) {
+    return hra_bvh_part_info(b, 0, stream, out);
 }
 
 extern "C" hra_status hra_bvh_export(hra_bvh *b, void *stream, void *host_nodes, void *host_tris, int32_t *root,
@@ -641,8 +734,8 @@ extern "C" hra_status hra_bvh_export(hra_bvh *b, void *stream, void *host_nodes,
     hra_ctx *ctx = b->ctx;
     hra_status st = check_error_word(ctx, (hipStream_t)stream);
     if (st != HRA_OK) return st;
-    BvhMeta m;
-    HRA_HIP(hipMemcpy(&m, b->meta, sizeof(m), hipMemcpyDeviceToHost));
+    PartMeta m;
+    HRA_HIP(hipMemcpy(&m, b->parts, sizeof(m), hipMemcpyDeviceToHost));
     const int64_t nn = b->n_tris > 1 ? b->n_tris - 1 : 1;
     HRA_HIP(hipMemcpy(host_nodes, b->nodes, sizeof(Node) * nn, hipMemcpyDeviceToHost));
     HRA_HIP(hipMemcpy(host_tris, b->tris, sizeof(float4) * 3 * b->n_tris, hipMemcpyDeviceToHost));
@@ -659,6 +752,6 @@ extern "C" void hra_bvh_release(hra_bvh *b) {
     hipFree(b->leaf_pos);
     hipFree(b->valid_rank);
     hipFree(b->prefix);
-    hipFree(b->meta);
+    hipFree(b->parts);
     delete b;
 }

@@ -21,27 +21,6 @@ namespace hra {
 constexpr float EDGE_K = 1.0e-6f;   // ~16.8 units of FP32 roundoff
 constexpr int SPILL = 64;           // private overflow entries per lane beyond the LDS stack
 
-struct CastArgs {
-    const Node *nodes;
-    const float4 *tris;
-    const BvhMeta *meta;
-    const float *origin;
-    const float *normal;
-    const float4 *dirs;
-    uint32_t *bits;
-    uint32_t *counter;
-    uint32_t *err;
-    int64_t n_samples;
-    int32_t n_dirs;
-    int32_t kind;       // 0: rotate hemisphere onto the normal, 1: world axes (cull n.D < 0)
-    int32_t W;          // words per row
-    int32_t chunks;     // work items per sample
-    uint32_t n_items;
-    int32_t n_nodes_alloc;  // node array length (bounds guard)
-    int32_t n_tris_alloc;   // leaf-ordered triangles (bounds guard)
-    unsigned long long *work;  // instrumented variant: {node fetches, triangle tests}
-};
-
 __device__ __noinline__ int edge_sign64(float ox, float oy, float oz, float dx, float dy, float dz, float4 P, float4 Q) {
     const double bx = (double)P.x - (double)ox, by = (double)P.y - (double)oy, bz = (double)P.z - (double)oz;
     const double cx = (double)Q.x - (double)ox, cy = (double)Q.y - (double)oy, cz = (double)Q.z - (double)oz;
@@ -207,17 +186,30 @@ template <int RPW, int STACK, bool STATS>
 __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
     __shared__ int stk[4][STACK * 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t item = blockIdx.x * 4u + (uint32_t)wv;
+    const int64_t item = (int64_t)blockIdx.x * 4 + wv;
     if (item >= a.n_items) return;  // the whole wavefront leaves together
+    // job of this item (wave-uniform): last job whose item_base <= item
+    CastJob J = a.job0;
+    if (a.jobs) {
+        int lo = 0, hi = a.n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.jobs[mid].item_base <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        J = a.jobs[lo];
+    }
     int *lds = stk[wv];
-    const int32_t root = a.meta->root;
-    const int32_t n_valid = a.meta->n_valid;
+    const PartMeta &P = *J.meta;
+    const int32_t root = P.root;
+    const int32_t n_valid = P.n_valid;
     const bool empty = n_valid <= 0;
-    const int32_t n_tris_alloc = n_valid < a.n_tris_alloc ? n_valid : a.n_tris_alloc;
-    const int64_t s = item / (uint32_t)a.chunks;
-    const int32_t ch = (int32_t)(item % (uint32_t)a.chunks);
-    const float ox = a.origin[3 * s], oy = a.origin[3 * s + 1], oz = a.origin[3 * s + 2];
-    const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
+    const int32_t n_tris_alloc = P.leaf_lo + n_valid;   // end of this part's leaf run
+    const int64_t li = item - J.item_base;
+    const int64_t s = li / a.chunks;
+    const int32_t ch = (int32_t)(li % a.chunks);
+    const float ox = J.origin[3 * s], oy = J.origin[3 * s + 1], oz = J.origin[3 * s + 2];
+    const float nx = J.normal[3 * s], ny = J.normal[3 * s + 1], nz = J.normal[3 * s + 2];
     float3 t, b;
     onb_frame(nx, ny, nz, t, b);
     uint64_t mk[RPW / 64];
@@ -244,8 +236,8 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
                 cast = !(nd < 0.0f);
             }
             if (cast)
-                free_ray = empty || !occluded<STACK, STATS>(a.nodes, a.tris, root, ox, oy, oz, dx, dy, dz, lds, lane,
-                                                            a.err, a.n_nodes_alloc, n_tris_alloc, wc);
+                free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, dx, dy, dz, lds, lane,
+                                                            a.err, J.n_nodes_alloc, n_tris_alloc, wc);
         }
         mk[r] = __ballot(free_ray);
     }
@@ -257,7 +249,7 @@ __global__ __launch_bounds__(256) void k_cast(CastArgs a) {
 #pragma unroll
         for (int r = 1; r < RPW / 64; ++r)
             if ((lane >> 1) == r) m = mk[r];
-        a.bits[s * a.W + w0 + lane] = (lane & 1) ? (uint32_t)(m >> 32) : (uint32_t)m;
+        J.bits[s * a.W + w0 + lane] = (lane & 1) ? (uint32_t)(m >> 32) : (uint32_t)m;
     }
     if (STATS) {
         atomicAdd(a.work, (unsigned long long)wc.nodes);
@@ -275,7 +267,8 @@ __global__ void k_popcount_rows(const uint32_t *bits, int64_t n, int32_t W, uint
 
 template <int RPW, int STACK, bool STATS>
 static hipError_t launch_cast(const CastArgs &args, hipStream_t s) {
-    const int64_t blocks = ((int64_t)args.n_items + 3) / 4;
+    const int64_t blocks = (args.n_items + 3) / 4;
+    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     k_cast<RPW, STACK, STATS><<<(unsigned)blocks, 256, 0, s>>>(args);
     return hipGetLastError();
 }
@@ -346,9 +339,26 @@ extern "C" hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *c
     return HRA_OK;
 }
 
-static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
+CastJob hra::make_cast_job(const hra_bvh *bvh, int32_t part, const float *origin, const float *normal, uint32_t *bits,
+                      int64_t n_samples, int64_t item_base) {
+    CastJob J;
+    J.nodes = bvh->nodes;
+    J.tris = bvh->tris;
+    J.meta = bvh->parts + part;
+    J.origin = origin;
+    J.normal = normal;
+    J.bits = bits;
+    J.n_samples = n_samples;
+    J.item_base = item_base;
+    J.n_nodes_alloc = (int32_t)(bvh->n_tris > 1 ? bvh->n_tris - 1 : 1);
+    J.pad = 0;
+    return J;
+}
+
+static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples, hra_dirs dirs,
                               uint32_t *d_bits, uint32_t *d_counts, unsigned long long *work, int rpw, hipStream_t s) {
     if (!ctx || !bvh || !samples) return HRA_ERR_INVALID_ARG;
+    if (part < 0 || part >= bvh->n_parts) return ctx->fail(HRA_ERR_INVALID_ARG, "part index out of range");
     if (samples->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
     const float4 *table = nullptr;
     hra_status st = dir_table(ctx, dirs, &table);
@@ -358,26 +368,18 @@ static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, const hra_sample
         return ctx->fail(HRA_ERR_INVALID_ARG, "bits, origins and normals must be non-null");
     HRA_HIP(hipSetDevice(ctx->device));
     CastArgs a;
-    a.nodes = bvh->nodes;
-    a.tris = bvh->tris;
-    a.meta = bvh->meta;
-    a.origin = samples->origin;
-    a.normal = samples->normal;
+    a.jobs = nullptr;
+    a.n_jobs = 1;
+    a.job0 = make_cast_job(bvh, part, samples->origin, samples->normal, d_bits, samples->n, 0);
     a.dirs = table;
-    a.bits = d_bits;
-    a.counter = ctx->d_counter;
-    a.err = ctx->d_err;
-    a.n_samples = samples->n;
     a.n_dirs = dirs.n;
     a.kind = dirs.kind == HRA_DIRS_AXES6 ? 1 : 0;
     a.W = (dirs.n + 31) / 32;
-    a.n_nodes_alloc = (int32_t)(bvh->n_tris > 1 ? bvh->n_tris - 1 : 1);
-    a.n_tris_alloc = (int32_t)bvh->n_tris;
-    a.work = work;
     a.chunks = (dirs.n + rpw - 1) / rpw;
-    const int64_t items = samples->n * (int64_t)a.chunks;
-    if (items >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call (split the samples)");
-    a.n_items = (uint32_t)items;
+    a.n_items = samples->n * (int64_t)a.chunks;
+    a.err = ctx->d_err;
+    a.work = work;
+    if ((a.n_items + 3) / 4 >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call");
     HRA_HIP(launch_cast_any(a, rpw, ctx->cast_stack, work != nullptr, s));
     if (d_counts) {
         k_popcount_rows<<<blocks_for(samples->n, 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);
@@ -386,10 +388,15 @@ static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, const hra_sample
     return HRA_OK;
 }
 
+extern "C" hra_status hra_cast_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                                    hra_dirs dirs, uint32_t *d_bits, uint32_t *d_counts, void *stream) {
+    if (!ctx) return HRA_ERR_INVALID_ARG;
+    return cast_common(ctx, bvh, part, samples, dirs, d_bits, d_counts, nullptr, ctx->cast_rpw, (hipStream_t)stream);
+}
+
 extern "C" hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
                                           uint32_t *d_bits, uint32_t *d_counts, void *stream) {
-    if (!ctx) return HRA_ERR_INVALID_ARG;
-    return cast_common(ctx, bvh, samples, dirs, d_bits, d_counts, nullptr, ctx->cast_rpw, (hipStream_t)stream);
+    return hra_cast_part(ctx, bvh, 0, samples, dirs, d_bits, d_counts, stream);
 }
 
 __global__ void k_zero_work(unsigned long long *w) {
@@ -403,7 +410,7 @@ extern "C" hra_status hra_cast_work(hra_ctx *ctx, const hra_bvh *bvh, const hra_
     unsigned long long *w = nullptr;
     HRA_HIP(hipMallocAsync((void **)&w, 2 * sizeof(unsigned long long), s));
     k_zero_work<<<1, 64, 0, s>>>(w);
-    hra_status st = cast_common(ctx, bvh, samples, dirs, d_bits, nullptr, w, 64, s);
+    hra_status st = cast_common(ctx, bvh, 0, samples, dirs, d_bits, nullptr, w, 64, s);
     unsigned long long h[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, s);
     hipFreeAsync(w, s);

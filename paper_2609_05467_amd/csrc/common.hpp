@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "../../include/hra.h"
 
@@ -52,20 +53,42 @@ __host__ __device__ inline bool is_leaf(int32_t c) { return c < 0; }
 __host__ __device__ inline int32_t leaf_first(int32_t c) { return c & 0x07FFFFFF; }
 __host__ __device__ inline int32_t leaf_count(int32_t c) { return (int32_t)(((uint32_t)c >> 27) & 15u) + 1; }
 
-// Per-mesh facts written by the build kernels and read by later kernels,
-// so that no host round trip is needed between stages.
-struct BvhMeta {
+// Per-part facts written by the build kernels and read by later kernels,
+// so that no host round trip is needed between stages.  A hierarchy holds
+// one or more parts; part p's input triangles are [tri_start, tri_start +
+// n_tris) of the concatenated input, its nonzero-area triangles occupy
+// [leaf_lo, leaf_lo + n_valid) of the leaf-ordered triangle array, and its
+// own subtree starts at `root`.
+struct PartMeta {
     float bbox[6];       // vertex bbox: min xyz, max xyz
     double diag;         // |max - min| in FP64
     double amax;         // largest triangle area
-    uint64_t total_w;    // sum of the integer area weights
+    uint64_t base_w;     // inclusive weight prefix just before the part
+    uint64_t total_w;    // sum of the part's integer area weights
+    int64_t tri_start;   // first triangle in the concatenated input
+    int64_t n_verts;
+    int32_t n_tris;
     int32_t k_scale;     // weights = floor(area * 2^k_scale)
     int32_t n_valid;     // nonzero-area triangles
+    int32_t leaf_lo;     // first leaf-order position
     int32_t root;        // root reference (interior index or leaf code)
-    int32_t depth;       // interior-node depth of the emitted hierarchy
-    int32_t n_nodes;     // emitted interior nodes
+    int32_t depth;       // interior-node depth of the part's subtree
+    int32_t n_nodes;     // emitted interior nodes of the part
     int32_t pad;
 };
+
+// Device view of one input mesh of a build.
+struct MeshIn {
+    const float *v;
+    const int32_t *t;
+    int64_t nv;
+    int64_t nt;
+    int64_t tri_start;
+};
+
+// Largest number of parts in one hierarchy (the part index takes the top
+// 8 bits of the 64-bit Morton key).
+constexpr int MAX_PARTS = 255;
 
 }  // namespace hra
 
@@ -95,19 +118,86 @@ struct hra_ctx {
 
 struct hra_bvh {
     hra_ctx *ctx = nullptr;
-    int64_t n_tris = 0;
-    int64_t n_verts = 0;
+    int32_t n_parts = 0;
+    int64_t n_tris = 0;              // all parts
     int32_t leaf_size = 4;
-    hra::Node *nodes = nullptr;      // [max(1, n_valid - 1)]
-    float4 *tris = nullptr;          // [n_valid][3], leaf order, w = original index
-    int32_t *leaf_pos = nullptr;     // [n_tris] position in leaf order, -1 if degenerate
-    int32_t *valid_rank = nullptr;   // [n_tris] rank among nonzero-area faces, -1 if degenerate
-    uint64_t *prefix = nullptr;      // [n_tris] inclusive prefix of integer area weights
-    hra::BvhMeta *meta = nullptr;    // device
+    hra::Node *nodes = nullptr;      // [max(1, n_tris - 1)]
+    float4 *tris = nullptr;          // [n_tris][3], leaf order, w = face index within its part
+    int32_t *leaf_pos = nullptr;     // [n_tris] position in leaf order, -1 if zero area
+    int32_t *valid_rank = nullptr;   // [n_tris] rank among the part's nonzero-area faces, -1 if zero area
+    uint64_t *prefix = nullptr;      // [n_tris] inclusive prefix of the integer area weights
+    hra::PartMeta *parts = nullptr;  // device [n_parts]
+    std::vector<int64_t> part_tris;  // host: triangles per part
+    std::vector<int64_t> part_start; // host: first triangle per part
     int64_t bytes = 0;
 };
 
 namespace hra {
+
+// ---------------------------------------------------------------- job tables
+// A sampling job: one part of a hierarchy, a mode, a seed and an output
+// range; one launch runs any number of them (k_sample, sample.hip).
+struct SampleJob {
+    const PartMeta *meta;      // the part (device)
+    const float4 *tris;        // hierarchy arrays
+    const int32_t *leaf_pos;
+    const uint64_t *prefix;
+    const int32_t *valid_rank;
+    int64_t thread_base;       // first global thread of this job
+    int64_t n_threads;         // area mode: samples; centroid mode: the part's triangles
+    int64_t out_base;          // first output row
+    int64_t n_out;             // output rows of this job
+    uint64_t seed;
+    float offset_frac;
+    int32_t mode;
+};
+
+struct SampleArgs {
+    const SampleJob *jobs;     // device table, or null: job0 only
+    int32_t n_jobs;
+    SampleJob job0;
+    int64_t n_threads;
+    float *point, *normal, *origin;
+    int32_t *tri;
+};
+
+// A cast job: the samples of one part against that part's subtree (k_cast,
+// cast.hip).  Work item = (sample, chunk of directions); jobs are laid out
+// back to back in item space.
+struct CastJob {
+    const Node *nodes;
+    const float4 *tris;
+    const PartMeta *meta;
+    const float *origin;       // this job's first sample
+    const float *normal;
+    uint32_t *bits;            // this job's first row
+    int64_t n_samples;
+    int64_t item_base;         // first global item of this job
+    int32_t n_nodes_alloc;     // node array length (bounds guard)
+    int32_t pad;
+};
+
+struct CastArgs {
+    const CastJob *jobs;       // device table, or null: job0 only
+    int32_t n_jobs;
+    CastJob job0;
+    const float4 *dirs;
+    int32_t n_dirs;
+    int32_t kind;              // 0: rotate hemisphere onto the normal, 1: world axes (cull n.D < 0)
+    int32_t W;                 // words per row
+    int32_t chunks;            // work items per sample
+    int64_t n_items;
+    uint32_t *err;
+    unsigned long long *work;  // instrumented variant: {node fetches, triangle tests}
+};
+
+SampleJob make_sample_job(const hra_bvh *bvh, int32_t part, int32_t mode, uint64_t seed, float frac, int64_t n_out,
+                          int64_t thread_base, int64_t out_base);
+hipError_t launch_sample(const SampleJob *d_jobs, int32_t n_jobs, const SampleJob &job0, int64_t n_threads,
+                         float *point, float *normal, float *origin, int32_t *tri, hipStream_t s);
+CastJob make_cast_job(const hra_bvh *bvh, int32_t part, const float *origin, const float *normal, uint32_t *bits,
+                      int64_t n_samples, int64_t item_base);
+hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, bool stats, hipStream_t s);
 
 // ---------------------------------------------------------------- helpers
 hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out);

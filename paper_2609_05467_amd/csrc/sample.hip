@@ -1,6 +1,9 @@
 // Surface samples (Section 3.1: per-face centroid, normal and area; rays
 // leave a slightly offset point).  FP32 throughout, in a fixed order of
 // single IEEE operations; the triangle choice is exact integer work.
+//
+// One launch serves any number of sampling jobs (a part of a hierarchy, a
+// mode, a seed, an output range), so a batch of parts is sampled at once.
 #include "common.hpp"
 
 namespace hra {
@@ -21,12 +24,7 @@ __device__ inline float3 face_normal32(float4 a, float4 b, float4 c) {
     return make_float3(nx / len, ny / len, nz / len);
 }
 
-__device__ inline float offset_eps(const BvhMeta *meta, float offset_frac) {
-    const double e = (double)offset_frac * meta->diag;
-    return (float)e;
-}
-
-__device__ inline void write_sample(const hra_samples &S, int64_t i, float3 p, float3 n, float eps, int32_t f) {
+__device__ inline void write_sample(const SampleArgs &S, int64_t i, float3 p, float3 n, float eps, int32_t f) {
     S.point[3 * i + 0] = p.x;
     S.point[3 * i + 1] = p.y;
     S.point[3 * i + 2] = p.z;
@@ -39,81 +37,130 @@ __device__ inline void write_sample(const hra_samples &S, int64_t i, float3 p, f
     S.tri[i] = f;
 }
 
-// Area-weighted i.i.d. points.  Face: first f whose inclusive weight prefix
-// exceeds r = floor(x0 * total / 2^64); point: the area-uniform square-root
-// parametrisation with u1, u2 the top 24 bits of the next two outputs.
-__global__ void k_sample_area(const float4 *tri4, const int32_t *leaf_pos, const uint64_t *prefix, int64_t nt,
-                              const BvhMeta *meta, uint64_t seed, float offset_frac, hra_samples S) {
+// Area mode: face = first f of the part whose inclusive weight prefix
+// exceeds r = floor(x0 * total / 2^64) (searched as base + r in the global
+// prefix); point = the area-uniform square-root parametrisation with u1, u2
+// the top 24 bits of the next two generator outputs.
+// Centroid mode: one sample per nonzero-area face at ((v0 + v1) + v2) / 3,
+// in face order.
+__global__ void k_sample(SampleArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.n || meta->total_w == 0) return;  // empty mesh: reported by the build
-    const uint64_t x0 = splitmix64_at(seed, 3ull * (uint64_t)i);
-    const uint64_t x1 = splitmix64_at(seed, 3ull * (uint64_t)i + 1);
-    const uint64_t x2 = splitmix64_at(seed, 3ull * (uint64_t)i + 2);
-    const uint64_t r = __umul64hi(x0, meta->total_w);
-    int64_t lo = 0, hi = nt - 1;
-    while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (prefix[mid] > r) hi = mid;
-        else lo = mid + 1;
+    if (i >= a.n_threads) return;
+    SampleJob J = a.job0;
+    if (a.jobs) {
+        int lo = 0, hi = a.n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.jobs[mid].thread_base <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        J = a.jobs[lo];
     }
-    const int32_t f = (int32_t)lo;
-    const int32_t p = leaf_pos[f];
-    if (p < 0) return;
-    const float4 a = tri4[3 * (int64_t)p], b = tri4[3 * (int64_t)p + 1], c = tri4[3 * (int64_t)p + 2];
-    const float u1 = (float)(uint32_t)(x1 >> 40) * 0x1p-24f;
-    const float u2 = (float)(uint32_t)(x2 >> 40) * 0x1p-24f;
-    const float su = sqrtf(u1);
-    const float w0 = 1.0f - su;
-    const float omu2 = 1.0f - u2;
-    const float w1 = su * omu2;
-    const float w2 = su * u2;
-    float3 pt;
-    pt.x = fmaf(w2, c.x, fmaf(w1, b.x, w0 * a.x));
-    pt.y = fmaf(w2, c.y, fmaf(w1, b.y, w0 * a.y));
-    pt.z = fmaf(w2, c.z, fmaf(w1, b.z, w0 * a.z));
-    write_sample(S, i, pt, face_normal32(a, b, c), offset_eps(meta, offset_frac), f);
+    const int64_t li = i - J.thread_base;
+    if (li < 0 || li >= J.n_threads) return;
+    const PartMeta &P = *J.meta;
+    const double e = (double)J.offset_frac * P.diag;
+    const float eps = (float)e;
+    if (J.mode == HRA_SAMPLE_AREA) {
+        if (P.total_w == 0 || li >= J.n_out) return;  // empty part: reported by the build
+        const uint64_t x0 = splitmix64_at(J.seed, 3ull * (uint64_t)li);
+        const uint64_t x1 = splitmix64_at(J.seed, 3ull * (uint64_t)li + 1);
+        const uint64_t x2 = splitmix64_at(J.seed, 3ull * (uint64_t)li + 2);
+        const uint64_t r = P.base_w + __umul64hi(x0, P.total_w);
+        int64_t lo = P.tri_start, hi = P.tri_start + P.n_tris - 1;
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (J.prefix[mid] > r) hi = mid;
+            else lo = mid + 1;
+        }
+        const int32_t p = J.leaf_pos[lo];
+        if (p < 0) return;
+        const float4 A = J.tris[3 * (int64_t)p], B = J.tris[3 * (int64_t)p + 1], C = J.tris[3 * (int64_t)p + 2];
+        const float u1 = (float)(uint32_t)(x1 >> 40) * 0x1p-24f;
+        const float u2 = (float)(uint32_t)(x2 >> 40) * 0x1p-24f;
+        const float su = sqrtf(u1);
+        const float w0 = 1.0f - su;
+        const float omu2 = 1.0f - u2;
+        const float w1 = su * omu2;
+        const float w2 = su * u2;
+        float3 pt;
+        pt.x = fmaf(w2, C.x, fmaf(w1, B.x, w0 * A.x));
+        pt.y = fmaf(w2, C.y, fmaf(w1, B.y, w0 * A.y));
+        pt.z = fmaf(w2, C.z, fmaf(w1, B.z, w0 * A.z));
+        write_sample(a, J.out_base + li, pt, face_normal32(A, B, C), eps, (int32_t)(lo - P.tri_start));
+    } else {
+        const int64_t g = P.tri_start + li;
+        const int32_t rk = J.valid_rank[g];
+        if (rk < 0 || rk >= J.n_out) return;
+        const int32_t p = J.leaf_pos[g];
+        if (p < 0) return;
+        const float4 A = J.tris[3 * (int64_t)p], B = J.tris[3 * (int64_t)p + 1], C = J.tris[3 * (int64_t)p + 2];
+        float3 pt;
+        pt.x = ((A.x + B.x) + C.x) / 3.0f;
+        pt.y = ((A.y + B.y) + C.y) / 3.0f;
+        pt.z = ((A.z + B.z) + C.z) / 3.0f;
+        write_sample(a, J.out_base + rk, pt, face_normal32(A, B, C), eps, (int32_t)li);
+    }
 }
 
-// One sample per nonzero-area face, at its centroid ((v0 + v1) + v2) / 3.
-__global__ void k_sample_centroid(const float4 *tri4, const int32_t *leaf_pos, const int32_t *valid_rank, int64_t nt,
-                                  const BvhMeta *meta, float offset_frac, hra_samples S) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nt) return;
-    const int32_t rk = valid_rank[f];
-    if (rk < 0 || rk >= S.n) return;
-    const int32_t p = leaf_pos[f];
-    const float4 a = tri4[3 * (int64_t)p], b = tri4[3 * (int64_t)p + 1], c = tri4[3 * (int64_t)p + 2];
-    float3 pt;
-    pt.x = ((a.x + b.x) + c.x) / 3.0f;
-    pt.y = ((a.y + b.y) + c.y) / 3.0f;
-    pt.z = ((a.z + b.z) + c.z) / 3.0f;
-    write_sample(S, rk, pt, face_normal32(a, b, c), offset_eps(meta, offset_frac), (int32_t)f);
+SampleJob make_sample_job(const hra_bvh *bvh, int32_t part, int32_t mode, uint64_t seed, float frac, int64_t n_out,
+                          int64_t thread_base, int64_t out_base) {
+    SampleJob J;
+    J.meta = bvh->parts + part;
+    J.tris = bvh->tris;
+    J.leaf_pos = bvh->leaf_pos;
+    J.prefix = bvh->prefix;
+    J.valid_rank = bvh->valid_rank;
+    J.thread_base = thread_base;
+    J.n_threads = mode == HRA_SAMPLE_AREA ? n_out : bvh->part_tris[part];
+    J.out_base = out_base;
+    J.n_out = n_out;
+    J.seed = seed;
+    J.offset_frac = frac;
+    J.mode = mode;
+    return J;
+}
+
+hipError_t launch_sample(const SampleJob *d_jobs, int32_t n_jobs, const SampleJob &job0, int64_t n_threads,
+                         float *point, float *normal, float *origin, int32_t *tri, hipStream_t s) {
+    if (n_threads <= 0) return hipSuccess;
+    SampleArgs a;
+    a.jobs = d_jobs;
+    a.n_jobs = n_jobs;
+    a.job0 = job0;
+    a.n_threads = n_threads;
+    a.point = point;
+    a.normal = normal;
+    a.origin = origin;
+    a.tri = tri;
+    k_sample<<<blocks_for(n_threads, 256), 256, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 }  // namespace hra
 
 using namespace hra;
 
-extern "C" hra_status hra_sample_surface(hra_ctx *ctx, const hra_bvh *bvh, int32_t mode, uint64_t seed,
-                                         float offset_frac, const hra_samples *out, void *stream) {
+extern "C" hra_status hra_sample_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, int32_t mode, uint64_t seed,
+                                      float offset_frac, const hra_samples *out, void *stream) {
     if (!ctx || !bvh || !out) return HRA_ERR_INVALID_ARG;
+    if (part < 0 || part >= bvh->n_parts) return ctx->fail(HRA_ERR_INVALID_ARG, "part index out of range");
     if (out->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
     if (!(offset_frac > 0.0f && offset_frac <= 0.01f))
         return ctx->fail(HRA_ERR_INVALID_ARG, "offset_frac must be in (0, 0.01]");
+    if (mode != HRA_SAMPLE_AREA && mode != HRA_SAMPLE_CENTROID)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "unknown sampling mode");
     if (out->n == 0) return HRA_OK;
     if (!out->point || !out->normal || !out->origin || !out->tri)
         return ctx->fail(HRA_ERR_INVALID_ARG, "sample arrays must be non-null");
-    hipStream_t s = (hipStream_t)stream;
     HRA_HIP(hipSetDevice(ctx->device));
-    if (mode == HRA_SAMPLE_AREA) {
-        k_sample_area<<<blocks_for(out->n, 256), 256, 0, s>>>(bvh->tris, bvh->leaf_pos, bvh->prefix, bvh->n_tris,
-                                                             bvh->meta, seed, offset_frac, *out);
-    } else if (mode == HRA_SAMPLE_CENTROID) {
-        k_sample_centroid<<<blocks_for(bvh->n_tris, 256), 256, 0, s>>>(bvh->tris, bvh->leaf_pos, bvh->valid_rank,
-                                                                      bvh->n_tris, bvh->meta, offset_frac, *out);
-    } else {
-        return ctx->fail(HRA_ERR_INVALID_ARG, "unknown sampling mode");
-    }
-    HRA_HIP(hipGetLastError());
+    const SampleJob J = make_sample_job(bvh, part, mode, seed, offset_frac, out->n, 0, 0);
+    HRA_HIP(launch_sample(nullptr, 1, J, J.n_threads, out->point, out->normal, out->origin, out->tri,
+                          (hipStream_t)stream));
     return HRA_OK;
+}
+
+extern "C" hra_status hra_sample_surface(hra_ctx *ctx, const hra_bvh *bvh, int32_t mode, uint64_t seed,
+                                         float offset_frac, const hra_samples *out, void *stream) {
+    return hra_sample_part(ctx, bvh, 0, mode, seed, offset_frac, out, stream);
 }

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace hra {
@@ -19,20 +20,21 @@ struct DirTotals {
 constexpr int HIST_BINS = 8192;
 
 // One wavefront per sample: lanes stride over the directions, FP64 sums,
-// wave butterfly reduction.  The histogram is privatised in LDS per block
-// and written out without atomics to a per-block slice; k_hist_reduce sums
-// the slices in a fixed order.  Part counters stay in registers per
-// wavefront and reach memory once per wavefront.
+// wave butterfly reduction.  The histogram (when asked for) is privatised in
+// LDS per block and written out without atomics to a per-block slice;
+// k_hist_reduce sums the slices in a fixed order.  Part totals are formed
+// afterwards from the per-sample outputs by k_part_totals.
 __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n, const float4 *dirs, int32_t N,
                                                   int32_t W, const uint32_t *bits, hra_dirstats out, double *conc64,
-                                                  DirTotals *tot, uint32_t *hist_part) {
+                                                  uint32_t *cnt_out, uint32_t *hist_part) {
     __shared__ uint32_t h[HIST_BINS];
-    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) h[k] = 0;
-    __syncthreads();
+    if (hist_part) {
+        for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) h[k] = 0;
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const double pi = 3.14159265358979323846264338327950288;
-    unsigned long long n_axis0 = 0, n_axis1 = 0, n_axis2 = 0, n_blind = 0, n_unob = 0;
     for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < n; s += nwaves) {
         const float nx = normal[3 * s], ny = normal[3 * s + 1], nz = normal[3 * s + 2];
         float3 t, b;
@@ -51,13 +53,15 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
             sa1 += fabs(dy);
             sa2 += fabs(dz);
             ++cnt;
-            const double len = sqrt(dx * dx + dy * dy + dz * dz);
-            const double zh = dz / len;
-            int zb = (int)floor((zh + 1.0) * 32.0);
-            zb = zb > 63 ? 63 : (zb < 0 ? 0 : zb);
-            int az = (int)floor((atan2(dy, dx) + pi) * 128.0 / (2.0 * pi));
-            az = az > 127 ? 127 : (az < 0 ? 0 : az);
-            atomicAdd(&h[zb * 128 + az], 1u);
+            if (hist_part) {
+                const double len = sqrt(dx * dx + dy * dy + dz * dz);
+                const double zh = dz / len;
+                int zb = (int)floor((zh + 1.0) * 32.0);
+                zb = zb > 63 ? 63 : (zb < 0 ? 0 : zb);
+                int az = (int)floor((atan2(dy, dx) + pi) * 128.0 / (2.0 * pi));
+                az = az > 127 ? 127 : (az < 0 ? 0 : az);
+                atomicAdd(&h[zb * 128 + az], 1u);
+            }
         }
         for (int off = 32; off > 0; off >>= 1) {
             sm0 += __shfl_xor(sm0, off);
@@ -86,22 +90,60 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
         out.axis[s] = blind ? (int8_t)-1 : (int8_t)k;
         out.conc[s] = (float)cc;
         conc64[s] = cc;
-        n_blind += blind ? 1 : 0;
-        n_axis0 += (!blind && k == 0) ? 1 : 0;
-        n_axis1 += (!blind && k == 1) ? 1 : 0;
-        n_axis2 += (!blind && k == 2) ? 1 : 0;
-        n_unob += cnt;
+        cnt_out[s] = cnt;
     }
-    // wave-uniform counters: lane 0 adds them, other lanes add zero
-    const unsigned long long z = lane == 0 ? 1ull : 0ull;
-    atomicAdd(&tot->n_axis[0], z * n_axis0);
-    atomicAdd(&tot->n_axis[1], z * n_axis1);
-    atomicAdd(&tot->n_axis[2], z * n_axis2);
-    atomicAdd(&tot->n_blind, z * n_blind);
-    atomicAdd(&tot->n_unob, z * n_unob);
+    if (hist_part) {
+        __syncthreads();
+        uint32_t *dst = hist_part + (int64_t)blockIdx.x * HIST_BINS;
+        for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) dst[k] = h[k];
+    }
+}
+
+// Part totals, one block per part over its sample range [base, base + n)
+// (base == NULL: one part, range [0, n_one)): integer counts, and the FP64
+// sum of concentrations in a fixed order (thread t sums a contiguous chunk
+// in order, then a fixed tree).
+__global__ void k_part_totals(const int8_t *axis, const uint32_t *cnt, const double *conc64, const int64_t *base,
+                              const int64_t *count, int64_t n_one, DirTotals *tot) {
+    __shared__ double sc[256];
+    __shared__ unsigned long long si[5][256];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const int64_t b0 = base ? base[p] : 0, n = base ? count[p] : n_one;
+    const int64_t chunk = (n + 255) / 256;
+    double acc = 0.0;
+    unsigned long long a0 = 0, a1 = 0, a2 = 0, bl = 0, un = 0;
+    for (int64_t i = b0 + t * chunk; i < b0 + n && i < b0 + (t + 1) * chunk; ++i) {
+        acc += conc64[i];
+        const int k = axis[i];
+        a0 += k == 0;
+        a1 += k == 1;
+        a2 += k == 2;
+        bl += k < 0;
+        un += cnt[i];
+    }
+    sc[t] = acc;
+    si[0][t] = a0;
+    si[1][t] = a1;
+    si[2][t] = a2;
+    si[3][t] = bl;
+    si[4][t] = un;
     __syncthreads();
-    uint32_t *dst = hist_part + (int64_t)blockIdx.x * HIST_BINS;
-    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) dst[k] = h[k];
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            sc[t] += sc[t + off];
+            for (int q = 0; q < 5; ++q) si[q][t] += si[q][t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        DirTotals &T = tot[p];
+        T.n_axis[0] = si[0][0];
+        T.n_axis[1] = si[1][0];
+        T.n_axis[2] = si[2][0];
+        T.n_blind = si[3][0];
+        T.n_unob = si[4][0];
+        T.conc_sum = sc[0];
+    }
 }
 
 // hist[b] = sum over blocks of hist_part[block][b], in block order.
@@ -113,56 +155,70 @@ __global__ void k_hist_reduce(const uint32_t *hist_part, int nblocks, uint32_t *
     hist[bin] = acc;
 }
 
-__global__ void k_zero_stats(uint32_t *hist, DirTotals *tot) {
-    for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) hist[k] = 0;
-    if (threadIdx.x == 0) {
-        tot->n_axis[0] = tot->n_axis[1] = tot->n_axis[2] = 0;
-        tot->n_blind = tot->n_unob = 0;
-        tot->conc_sum = 0.0;
+// Reach, fixture faces, classes and the histogram of reachable-direction
+// codes.  Samples of several jobs (parts) may share a launch; each block
+// keeps LDS counters for the job of its first sample and sends samples of
+// any other job straight to that job's global counters.
+struct SetupJob {
+    const PartMeta *meta;
+    const float4 *tris;
+    const int32_t *leaf_pos;
+    int64_t sample_base;
+    int64_t n;
+    double tool;
+};
+
+struct SetupArgs {
+    const SetupJob *jobs;   // device table, or null: job0 only
+    int32_t n_jobs;
+    SetupJob job0;
+    int64_t n_total;
+    const float *point;
+    const int32_t *tri;
+    const uint32_t *axes_bits;
+    uint8_t *cls_out;                  // [n_total] or null
+    unsigned long long *class_count;   // [n_jobs][4]
+    uint32_t *code_hist;               // [n_jobs][64]
+    uint32_t *err;
+};
+
+__device__ inline int setup_job_of(const SetupArgs &a, int64_t i) {
+    if (!a.jobs) return 0;
+    int lo = 0, hi = a.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.jobs[mid].sample_base <= i) lo = mid;
+        else hi = mid - 1;
     }
+    return lo;
 }
 
-// Fixed-order FP64 sum: thread t sums a contiguous chunk in order, then a
-// fixed tree over the 1024 partial sums.
-__global__ void k_sum_fixed(const double *x, int64_t n, double *out) {
-    __shared__ double s[1024];
-    const int t = threadIdx.x;
-    const int64_t chunk = (n + 1023) / 1024;
-    double acc = 0.0;
-    for (int64_t i = t * chunk; i < n && i < (t + 1) * chunk; ++i) acc += x[i];
-    s[t] = acc;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if (t < off) s[t] += s[t + off];
-        __syncthreads();
-    }
-    if (t == 0) *out = s[0];
-}
-
-// Reach, fixture faces, classes and the histogram of reachable-direction codes.
-__global__ void k_setups(const float *point, const int32_t *tri, int64_t n, const uint32_t *axes_bits, const float4 *tri4,
-                         const int32_t *leaf_pos, int64_t n_tris, const BvhMeta *meta, double tool, uint8_t *cls_out,
-                         unsigned long long *class_count, uint32_t *code_hist, uint32_t *err) {
+__global__ void k_setups(SetupArgs a) {
     __shared__ uint32_t hc[64];
     __shared__ unsigned long long cc[4];
     if (threadIdx.x < 64) hc[threadIdx.x] = 0;
     if (threadIdx.x < 4) cc[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        const int32_t f = tri[i];
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int jb = setup_job_of(a, i0 < a.n_total ? i0 : a.n_total - 1);
+    const int64_t i = i0 + threadIdx.x;
+    if (i < a.n_total) {
+        const int jj = setup_job_of(a, i);
+        const SetupJob J = a.jobs ? a.jobs[jj] : a.job0;
+        const PartMeta &P = *J.meta;
+        const int32_t f = a.tri[i];
         int32_t p = -1;
-        if (f >= 0 && f < n_tris) p = leaf_pos[f];
+        if (f >= 0 && f < P.n_tris) p = J.leaf_pos[P.tri_start + f];
         if (p < 0) {
-            atomicOr(err, ERR_BAD_SAMPLE_TRI);
+            atomicOr(a.err, ERR_BAD_SAMPLE_TRI);
         } else {
             double lo[3], hi[3];
             for (int c = 0; c < 3; ++c) {
-                lo[c] = meta->bbox[c];
-                hi[c] = meta->bbox[3 + c];
+                lo[c] = P.bbox[c];
+                hi[c] = P.bbox[3 + c];
             }
-            const double tol = 1e-6 * meta->diag;
-            const float4 v[3] = {tri4[3 * (int64_t)p], tri4[3 * (int64_t)p + 1], tri4[3 * (int64_t)p + 2]};
+            const double tol = 1e-6 * P.diag;
+            const float4 v[3] = {J.tris[3 * (int64_t)p], J.tris[3 * (int64_t)p + 1], J.tris[3 * (int64_t)p + 2]};
             bool fixture = false;
             for (int c = 0; c < 3 && !fixture; ++c) {
                 for (int side = 0; side < 2 && !fixture; ++side) {
@@ -175,30 +231,39 @@ __global__ void k_setups(const float *point, const int32_t *tri, int64_t n, cons
                     fixture = all;
                 }
             }
-            const double px = point[3 * i], py = point[3 * i + 1], pz = point[3 * i + 2];
+            const double px = a.point[3 * i], py = a.point[3 * i + 1], pz = a.point[3 * i + 2];
             const double travel[6] = {hi[0] - px, px - lo[0], hi[1] - py, py - lo[1], hi[2] - pz, pz - lo[2]};
-            const uint32_t acc = axes_bits[i] & 63u;
+            const uint32_t acc = a.axes_bits[i] & 63u;
             uint32_t code = 0;
             for (int k = 0; k < 6; ++k)
-                if (((acc >> k) & 1u) && travel[k] <= tool) code |= 1u << k;
+                if (((acc >> k) & 1u) && travel[k] <= J.tool) code |= 1u << k;
             uint8_t cl;
             if (fixture) cl = HRA_CLASS_FIXTURE;
             else if (code) cl = HRA_CLASS_VIABLE;
             else if (acc) cl = HRA_CLASS_OVER;
             else cl = HRA_CLASS_INACCESSIBLE;
-            if (cls_out) cls_out[i] = cl;
-            atomicAdd(&cc[cl], 1ull);
-            if (cl == HRA_CLASS_VIABLE) atomicAdd(&hc[code], 1u);
+            if (a.cls_out) a.cls_out[i] = cl;
+            if (jj == jb) {
+                atomicAdd(&cc[cl], 1ull);
+                if (cl == HRA_CLASS_VIABLE) atomicAdd(&hc[code], 1u);
+            } else {
+                atomicAdd(&a.class_count[4 * jj + cl], 1ull);
+                if (cl == HRA_CLASS_VIABLE) atomicAdd(&a.code_hist[64 * jj + code], 1u);
+            }
         }
     }
     __syncthreads();
-    if (threadIdx.x < 64 && hc[threadIdx.x]) atomicAdd(&code_hist[threadIdx.x], hc[threadIdx.x]);
-    if (threadIdx.x < 4 && cc[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cc[threadIdx.x]);
+    if (threadIdx.x < 64 && hc[threadIdx.x]) atomicAdd(&a.code_hist[64 * jb + threadIdx.x], hc[threadIdx.x]);
+    if (threadIdx.x < 4 && cc[threadIdx.x]) atomicAdd(&a.class_count[4 * jb + threadIdx.x], cc[threadIdx.x]);
 }
 
-__global__ void k_zero_setups(unsigned long long *cc, uint32_t *hist) {
-    if (threadIdx.x < 4) cc[threadIdx.x] = 0;
-    if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+__global__ void k_zero_u32(uint32_t *p, int n) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) p[k] = 0;
+}
+
+__global__ void k_zero_setups(unsigned long long *cc, uint32_t *hist, int n_jobs) {
+    for (int k = threadIdx.x; k < 4 * n_jobs; k += blockDim.x) cc[k] = 0;
+    for (int k = threadIdx.x; k < 64 * n_jobs; k += blockDim.x) hist[k] = 0;
 }
 
 // Exact minimum hitting set over the 63 nonempty direction subsets; ties go
@@ -257,47 +322,42 @@ void solve_setups(const uint32_t *hist, int32_t *min_count, int32_t *min_mask, i
 
 using namespace hra;
 
-extern "C" int64_t hra_dirstats_bytes(int64_t n) { return (int64_t)sizeof(DirTotals) + 8 * (n > 0 ? n : 0) + 64; }
-
-extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
-                                        const hra_dirstats *out, void *stream) {
-    if (!ctx || !samples || !out) return HRA_ERR_INVALID_ARG;
-    if (!out->hist || !out->totals) return ctx->fail(HRA_ERR_INVALID_ARG, "histogram and totals must be non-null");
-    if (samples->n > 0 && (!d_bits || !out->mean || !out->absmean || !out->axis || !out->conc || !samples->normal))
-        return ctx->fail(HRA_ERR_INVALID_ARG, "all hra_dirstats arrays must be non-null");
-    if (dirs.kind != HRA_DIRS_HEMI_FIBONACCI)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "directional statistics need the hemisphere set");
-    const float4 *table = nullptr;
-    hra_status st = dir_table(ctx, dirs, &table);
-    if (st != HRA_OK) return st;
-    hipStream_t s = (hipStream_t)stream;
-    HRA_HIP(hipSetDevice(ctx->device));
-    DirTotals *tot = (DirTotals *)out->totals;
-    double *c64 = (double *)((char *)out->totals + sizeof(DirTotals));
-    k_zero_stats<<<1, 256, 0, s>>>(out->hist, tot);
-    if (samples->n > 0) {
-        int64_t blocks = (samples->n + 3) / 4;
-        const int64_t cap = (int64_t)ctx->n_cu * 4;
-        if (blocks > cap) blocks = cap;
-        uint32_t *part = nullptr;
-        HRA_HIP(hipMallocAsync((void **)&part, sizeof(uint32_t) * HIST_BINS * (size_t)blocks, s));
-        k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(samples->normal, samples->n, table, dirs.n, (dirs.n + 31) / 32, d_bits,
-                                                    *out, c64, tot, part);
-        k_hist_reduce<<<HIST_BINS / 256, 256, 0, s>>>(part, (int)blocks, out->hist);
-        k_sum_fixed<<<1, 1024, 0, s>>>(c64, samples->n, &tot->conc_sum);
-        hipFreeAsync(part, s);
-    }
-    HRA_HIP(hipGetLastError());
-    return HRA_OK;
+// totals scratch of hra_dirstats: DirTotals, then conc64 [n], then counts [n]
+extern "C" int64_t hra_dirstats_bytes(int64_t n) {
+    const int64_t m = n > 0 ? n : 0;
+    return (int64_t)sizeof(DirTotals) + 8 * m + 4 * m + 64;
 }
 
-extern "C" hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int64_t n, int32_t n_dirs,
-                                   const hra_thresholds *th, hra_class_report *out, void *stream) {
-    if (!ctx || !stats || !stats->totals || !out || n < 0 || n_dirs < 1) return HRA_ERR_INVALID_ARG;
-    hra_status st = check_error_word(ctx, (hipStream_t)stream);
-    if (st != HRA_OK) return st;
-    DirTotals t;
-    HRA_HIP(hipMemcpy(&t, stats->totals, sizeof(t), hipMemcpyDeviceToHost));
+namespace hra {
+
+hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const float4 *table, int32_t N,
+                           const uint32_t *bits, const hra_dirstats &out, double *c64, uint32_t *cnt, bool hist,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    const int64_t cap = (int64_t)ctx->n_cu * 4;
+    if (blocks > cap) blocks = cap;
+    uint32_t *part = nullptr;
+    hipError_t e = hipSuccess;
+    if (hist) {
+        e = hipMallocAsync((void **)&part, sizeof(uint32_t) * HIST_BINS * (size_t)blocks, s);
+        if (e != hipSuccess) return e;
+    }
+    k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(normal, n, table, N, (N + 31) / 32, bits, out, c64, cnt, part);
+    if (hist) {
+        k_hist_reduce<<<HIST_BINS / 256, 256, 0, s>>>(part, (int)blocks, out.hist);
+        hipFreeAsync(part, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_part_totals(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,
+                              const int64_t *d_count, int n_parts, DirTotals *tot, hipStream_t s) {
+    k_part_totals<<<n_parts, 256, 0, s>>>(axis, cnt, c64, d_base, d_count, 0, tot);
+    return hipGetLastError();
+}
+
+void classify_totals(const DirTotals &t, int64_t n, int32_t n_dirs, const hra_thresholds *th, hra_class_report *out) {
     const hra_thresholds def = {0.60, 0.45, 0.40};
     const hra_thresholds &T = th ? *th : def;
     const int64_t inc = n - (int64_t)t.n_blind;
@@ -318,13 +378,114 @@ extern "C" hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int6
                      fabs(out->mean_conc - T.max_conc) <= 1e-9)
                         ? 1
                         : 0;
+}
+
+hipError_t launch_setups(const SetupJob *d_jobs, int n_jobs, const SetupJob &job0, int64_t n_total, const float *point,
+                         const int32_t *tri, const uint32_t *axes_bits, uint8_t *cls_out, unsigned long long *cc,
+                         uint32_t *hist, uint32_t *err, hipStream_t s) {
+    k_zero_setups<<<1, 256, 0, s>>>(cc, hist, n_jobs);
+    if (n_total > 0) {
+        SetupArgs a;
+        a.jobs = d_jobs;
+        a.n_jobs = n_jobs;
+        a.job0 = job0;
+        a.n_total = n_total;
+        a.point = point;
+        a.tri = tri;
+        a.axes_bits = axes_bits;
+        a.cls_out = cls_out;
+        a.class_count = cc;
+        a.code_hist = hist;
+        a.err = err;
+        k_setups<<<blocks_for(n_total, 256), 256, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+SetupJob make_setup_job(const hra_bvh *bvh, int32_t part, int64_t sample_base, int64_t n, double tool) {
+    SetupJob J;
+    J.meta = bvh->parts + part;
+    J.tris = bvh->tris;
+    J.leaf_pos = bvh->leaf_pos;
+    J.sample_base = sample_base;
+    J.n = n;
+    J.tool = tool;
+    return J;
+}
+
+}  // namespace hra
+
+namespace hra {
+// thin wrappers for the batch orchestrator (batch.hip)
+size_t dir_totals_size() { return sizeof(DirTotals); }
+size_t setup_job_size() { return sizeof(SetupJob); }
+void fill_setup_job(void *dst, const hra_bvh *bvh, int32_t part, int64_t sample_base, int64_t n, double tool) {
+    *(SetupJob *)dst = make_setup_job(bvh, part, sample_base, n, tool);
+}
+hipError_t launch_part_totals_raw(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,
+                                  const int64_t *d_count, int n_parts, void *tot, hipStream_t s) {
+    return launch_part_totals(axis, cnt, c64, d_base, d_count, n_parts, (DirTotals *)tot, s);
+}
+hipError_t launch_setups_raw(const void *d_jobs, int n_jobs, int64_t n_total, const float *point, const int32_t *tri,
+                             const uint32_t *axes_bits, unsigned long long *cc, uint32_t *hist, uint32_t *err,
+                             hipStream_t s) {
+    SetupJob j0;
+    std::memset(&j0, 0, sizeof(j0));
+    return launch_setups((const SetupJob *)d_jobs, n_jobs, j0, n_total, point, tri, axes_bits, nullptr, cc, hist, err, s);
+}
+void classify_from_device_totals(const void *host_totals, int64_t n, int32_t n_dirs, const hra_thresholds *th,
+                                 hra_class_report *out) {
+    classify_totals(*(const DirTotals *)host_totals, n, n_dirs, th, out);
+}
+}  // namespace hra
+
+extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
+                                        const hra_dirstats *out, void *stream) {
+    if (!ctx || !samples || !out) return HRA_ERR_INVALID_ARG;
+    if (!out->hist || !out->totals) return ctx->fail(HRA_ERR_INVALID_ARG, "histogram and totals must be non-null");
+    if (samples->n > 0 && (!d_bits || !out->mean || !out->absmean || !out->axis || !out->conc || !samples->normal))
+        return ctx->fail(HRA_ERR_INVALID_ARG, "all hra_dirstats arrays must be non-null");
+    if (dirs.kind != HRA_DIRS_HEMI_FIBONACCI)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "directional statistics need the hemisphere set");
+    const float4 *table = nullptr;
+    hra_status st = dir_table(ctx, dirs, &table);
+    if (st != HRA_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(hipSetDevice(ctx->device));
+    const int64_t n = samples->n;
+    DirTotals *tot = (DirTotals *)out->totals;
+    double *c64 = (double *)((char *)out->totals + sizeof(DirTotals));
+    uint32_t *cnt = (uint32_t *)(c64 + (n > 0 ? n : 0));
+    if (n == 0) {
+        // no samples: an empty histogram and zero totals (fill kernels, so
+        // the call can be captured in a graph)
+        k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out->hist, HIST_BINS);
+        k_part_totals<<<1, 256, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nullptr, 0, tot);
+        HRA_HIP(hipGetLastError());
+        return HRA_OK;
+    }
+    HRA_HIP(launch_dirstats(ctx, samples->normal, n, table, dirs.n, d_bits, *out, c64, cnt, true, s));
+    k_part_totals<<<1, 256, 0, s>>>(out->axis, cnt, c64, nullptr, nullptr, n, tot);
+    HRA_HIP(hipGetLastError());
     return HRA_OK;
 }
 
-extern "C" hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples,
-                                     const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
-                                     hra_setup_report *out, void *stream) {
+extern "C" hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int64_t n, int32_t n_dirs,
+                                   const hra_thresholds *th, hra_class_report *out, void *stream) {
+    if (!ctx || !stats || !stats->totals || !out || n < 0 || n_dirs < 1) return HRA_ERR_INVALID_ARG;
+    hra_status st = check_error_word(ctx, (hipStream_t)stream);
+    if (st != HRA_OK) return st;
+    DirTotals t;
+    HRA_HIP(hipMemcpy(&t, stats->totals, sizeof(t), hipMemcpyDeviceToHost));
+    classify_totals(t, n, n_dirs, th, out);
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_min_setups_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                                          const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
+                                          hra_setup_report *out, void *stream) {
     if (!ctx || !bvh || !samples || !out) return HRA_ERR_INVALID_ARG;
+    if (part < 0 || part >= bvh->n_parts) return ctx->fail(HRA_ERR_INVALID_ARG, "part index out of range");
     if (samples->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
     if (samples->n > 0 && (!samples->point || !samples->tri || !d_axes_bits))
         return ctx->fail(HRA_ERR_INVALID_ARG, "sample points, faces and axis bits must be non-null");
@@ -332,17 +493,13 @@ extern "C" hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra
     hipStream_t s = (hipStream_t)stream;
     HRA_HIP(hipSetDevice(ctx->device));
     unsigned long long *cc = nullptr;
-    uint32_t *hist = nullptr;
     HRA_HIP(hipMallocAsync((void **)&cc, 4 * sizeof(unsigned long long) + 64 * sizeof(uint32_t), s));
-    hist = (uint32_t *)(cc + 4);
-    k_zero_setups<<<1, 64, 0, s>>>(cc, hist);
-    if (samples->n > 0)
-        k_setups<<<blocks_for(samples->n, 256), 256, 0, s>>>(samples->point, samples->tri, samples->n, d_axes_bits,
-                                                            bvh->tris, bvh->leaf_pos, bvh->n_tris, bvh->meta,
-                                                            tool_length, d_class, cc, hist, ctx->d_err);
+    uint32_t *hist = (uint32_t *)(cc + 4);
+    const SetupJob J = make_setup_job(bvh, part, 0, samples->n, tool_length);
     unsigned long long hcc[4];
     uint32_t hh[64];
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_setups(nullptr, 1, J, samples->n, samples->point, samples->tri, d_axes_bits, d_class, cc, hist,
+                                 ctx->d_err, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hcc, cc, sizeof(hcc), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s);
     hipFreeAsync(cc, s);
@@ -353,6 +510,12 @@ extern "C" hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra
     for (int c = 0; c < 64; ++c) out->code_hist[c] = hh[c];
     solve_setups(hh, &out->min_count, &out->min_mask, &out->greedy_count, &out->greedy_mask);
     return HRA_OK;
+}
+
+extern "C" hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples,
+                                     const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
+                                     hra_setup_report *out, void *stream) {
+    return hra_min_setups_part(ctx, bvh, 0, samples, d_axes_bits, tool_length, d_class, out, stream);
 }
 
 // Bin centre of histogram bin b: z band zb = b / 128 covers z in

@@ -76,6 +76,23 @@ class SetupReport(C.Structure):
                 ("greedy_mask", C.c_int32), ("n_class", C.c_int64 * 4), ("code_hist", C.c_uint32 * 64)]
 
 
+class Mesh(C.Structure):
+    _fields_ = [("d_verts", C.c_void_p), ("n_verts", C.c_int64), ("d_tris", C.c_void_p), ("n_tris", C.c_int64)]
+
+
+class PartRequest(C.Structure):
+    _fields_ = [("mesh", Mesh), ("n_samples", C.c_int64), ("seed", C.c_uint64), ("tool_length", C.c_double)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("n_dirs", C.c_int32), ("leaf_size", C.c_int32), ("offset_frac", C.c_float),
+                ("thresholds", C.POINTER(Thresholds))]
+
+
+class PartResult(C.Structure):
+    _fields_ = [("cls", ClassReport), ("setups", SetupReport)]
+
+
 _lib = None
 
 
@@ -109,6 +126,15 @@ def lib():
                              C.c_int),
             "hra_min_setups": ([P, P, C.POINTER(Samples), P, f64, P, C.POINTER(SetupReport), P], C.c_int),
             "hra_histogram_peaks": ([P, i32, C.POINTER(HistPeaks)], C.c_int),
+            "hra_build_bvh_batch": ([P, C.POINTER(Mesh), i32, C.POINTER(BvhOpts), P, C.POINTER(P)], C.c_int),
+            "hra_bvh_parts": ([P], i32),
+            "hra_bvh_part_info": ([P, i32, P, C.POINTER(BvhInfo)], C.c_int),
+            "hra_sample_part": ([P, P, i32, i32, u64, f32, C.POINTER(Samples), P], C.c_int),
+            "hra_cast_part": ([P, P, i32, C.POINTER(Samples), Dirs, P, P, P], C.c_int),
+            "hra_min_setups_part": ([P, P, i32, C.POINTER(Samples), P, f64, P, C.POINTER(SetupReport), P],
+                                    C.c_int),
+            "hra_batch_run": ([P, C.POINTER(PartRequest), i32, C.POINTER(BatchOpts), C.POINTER(PartResult), P, P],
+                              C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -121,7 +147,9 @@ def lib():
 EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version", "hra_build_bvh",
            "hra_bvh_get_info", "hra_bvh_release", "hra_bvh_export", "hra_sample_surface", "hra_dirs_table", "hra_cast_hemisphere",
            "hra_set_cast_config", "hra_get_cast_config", "hra_cast_work", "hra_debug_rays", "hra_dirstats_bytes",
-           "hra_dominant_axes", "hra_classify", "hra_min_setups", "hra_histogram_peaks"]
+           "hra_dominant_axes", "hra_classify", "hra_min_setups", "hra_histogram_peaks", "hra_build_bvh_batch",
+           "hra_bvh_parts", "hra_bvh_part_info", "hra_sample_part", "hra_cast_part", "hra_min_setups_part",
+           "hra_batch_run"]
 
 
 def _ptr(t):
@@ -178,6 +206,38 @@ class Context:
                                         _stream(stream), C.byref(out)))
         return Bvh(self, out, (v, t), stream)
 
+    def build_bvh_batch(self, meshes, leaf_size=0, stream=None):
+        """One hierarchy over several parts; `meshes` is a list of (verts, tris)."""
+        keep, arr = [], (Mesh * len(meshes))()
+        for i, (verts, tris) in enumerate(meshes):
+            v = _dev_tensor(verts, torch.float32, self.device)
+            t = _dev_tensor(tris, torch.int32, self.device)
+            keep += [v, t]
+            arr[i] = Mesh(_ptr(v), v.shape[0], _ptr(t), t.shape[0])
+        out = C.c_void_p()
+        self._check(lib().hra_build_bvh_batch(self.ptr, arr, len(meshes), C.byref(BvhOpts(leaf_size)),
+                                              _stream(stream), C.byref(out)))
+        return Bvh(self, out, keep, stream)
+
+    def batch_run(self, parts, n_dirs, leaf_size=0, offset_frac=0.0, thresholds=None, bits=None, stream=None):
+        """The whole path for many parts: `parts` is a list of dicts with
+        verts, tris (device or host), n_samples, seed, tool_length.  Returns
+        one result dict per part (classification and setups)."""
+        n = len(parts)
+        reqs = (PartRequest * n)()
+        keep = []
+        for i, q in enumerate(parts):
+            v = _dev_tensor(q["verts"], torch.float32, self.device)
+            t = _dev_tensor(q["tris"], torch.int32, self.device)
+            keep += [v, t]
+            reqs[i] = PartRequest(Mesh(_ptr(v), v.shape[0], _ptr(t), t.shape[0]), int(q["n_samples"]),
+                                  int(q["seed"]), float(q["tool_length"]))
+        th = Thresholds(*thresholds) if thresholds is not None else None
+        opts = BatchOpts(n_dirs, leaf_size, offset_frac, C.pointer(th) if th is not None else None)
+        res = (PartResult * n)()
+        self._check(lib().hra_batch_run(self.ptr, reqs, n, C.byref(opts), res, _ptr(bits), _stream(stream)))
+        return [{"class": _class_dict(r.cls), "setups": _setup_dict(r.setups)} for r in res]
+
     def dirs_table(self, n, kind=DIRS_HEMI):
         import numpy as np
         out = np.empty((n, 3), np.float32)
@@ -208,26 +268,27 @@ class Context:
                 assert s[k].is_contiguous() and s[k].dtype == torch.float32 and s[k].shape == (n, 3), k
         return Samples(_ptr(s.get("point")), _ptr(s.get("normal")), _ptr(s.get("origin")), _ptr(s.get("tri")), n)
 
-    def sample_surface(self, bvh, n, seed, mode=SAMPLE_AREA, offset_frac=1e-4, stream=None, out=None):
+    def sample_surface(self, bvh, n, seed, mode=SAMPLE_AREA, offset_frac=1e-4, stream=None, out=None, part=0):
         if mode == SAMPLE_CENTROID:
-            info = bvh.info(stream)
+            info = bvh.info(stream, part)
             n = info.n_tris - info.n_degenerate
         s = out if out is not None else self.alloc_samples(n)
         assert s["origin"].shape[0] == n
         st = self._samples_struct(s)
-        self._check(lib().hra_sample_surface(self.ptr, bvh.ptr, mode, seed, offset_frac, C.byref(st), _stream(stream)))
+        self._check(lib().hra_sample_part(self.ptr, bvh.ptr, part, mode, seed, offset_frac, C.byref(st),
+                                          _stream(stream)))
         return s
 
     # ---------------------------------------------------------------- cast
-    def cast(self, bvh, samples, n_dirs, kind=DIRS_HEMI, counts=True, stream=None, bits=None):
+    def cast(self, bvh, samples, n_dirs, kind=DIRS_HEMI, counts=True, stream=None, bits=None, part=0):
         n = samples["origin"].shape[0]
         W = (n_dirs + 31) // 32
         if bits is None:
             bits = torch.empty((n, W), dtype=torch.int32, device=self.device)
         cnt = torch.empty((n,), dtype=torch.int32, device=self.device) if counts else None
         st = self._samples_struct(samples)
-        self._check(lib().hra_cast_hemisphere(self.ptr, bvh.ptr, C.byref(st), Dirs(kind, n_dirs), _ptr(bits),
-                                              _ptr(cnt), _stream(stream)))
+        self._check(lib().hra_cast_part(self.ptr, bvh.ptr, part, C.byref(st), Dirs(kind, n_dirs), _ptr(bits),
+                                        _ptr(cnt), _stream(stream)))
         return bits, cnt
 
     def cast_work(self, bvh, samples, n_dirs, kind=DIRS_HEMI, stream=None):
@@ -270,21 +331,30 @@ class Context:
         th = C.byref(Thresholds(*thresholds)) if thresholds is not None else None
         self._check(lib().hra_classify(self.ptr, C.byref(stats["_struct"]), n, n_dirs, th, C.byref(rep),
                                        _stream(stream)))
-        return {"access": rep.access, "shares": list(rep.share), "conc": rep.mean_conc, "n_blind": rep.n_blind,
-                "n_unobstructed": rep.n_unobstructed, "multi_axis": bool(rep.multi_axis), "tripped": rep.tripped,
-                "near_tie": bool(rep.near_tie)}
+        return _class_dict(rep)
 
-    def min_setups(self, bvh, samples, axes_bits, tool_length, want_class=True, stream=None):
+    def min_setups(self, bvh, samples, axes_bits, tool_length, want_class=True, stream=None, part=0):
         n = samples["origin"].shape[0]
         cls = torch.empty((n,), dtype=torch.uint8, device=self.device) if want_class else None
         rep = SetupReport()
         st = self._samples_struct(samples)
         ab = axes_bits.reshape(-1).contiguous()
-        self._check(lib().hra_min_setups(self.ptr, bvh.ptr, C.byref(st), _ptr(ab), float(tool_length), _ptr(cls),
-                                         C.byref(rep), _stream(stream)))
-        return {"min_count": rep.min_count, "min_mask": rep.min_mask, "greedy_count": rep.greedy_count,
-                "greedy_mask": rep.greedy_mask, "n_class": list(rep.n_class), "code_hist": list(rep.code_hist),
-                "class": cls}
+        self._check(lib().hra_min_setups_part(self.ptr, bvh.ptr, part, C.byref(st), _ptr(ab), float(tool_length),
+                                              _ptr(cls), C.byref(rep), _stream(stream)))
+        out = _setup_dict(rep)
+        out["class"] = cls
+        return out
+
+
+def _class_dict(rep):
+    return {"access": rep.access, "shares": list(rep.share), "conc": rep.mean_conc, "n_blind": rep.n_blind,
+            "n_unobstructed": rep.n_unobstructed, "multi_axis": bool(rep.multi_axis), "tripped": rep.tripped,
+            "near_tie": bool(rep.near_tie)}
+
+
+def _setup_dict(rep):
+    return {"min_count": rep.min_count, "min_mask": rep.min_mask, "greedy_count": rep.greedy_count,
+            "greedy_mask": rep.greedy_mask, "n_class": list(rep.n_class), "code_hist": list(rep.code_hist)}
 
 
 def histogram_peaks(hist, k=8):
@@ -308,16 +378,23 @@ class Bvh:
         self._keep = keep   # inputs stay alive until the build has run
         self._stream = stream
 
-    def info(self, stream=None):
+    @property
+    def n_parts(self):
+        return int(lib().hra_bvh_parts(self.ptr))
+
+    def info(self, stream=None, part=0):
         inf = BvhInfo()
-        self.ctx._check(lib().hra_bvh_get_info(self.ptr, _stream(stream), C.byref(inf)))
+        self.ctx._check(lib().hra_bvh_part_info(self.ptr, part, _stream(stream), C.byref(inf)))
         self._keep = None
         return inf
 
     def export(self, stream=None):
-        """Host copy of the hierarchy: (nodes float32 [nn,16] with int32
-        children in columns 12-13, tris float32 [n_valid,3,4], root, n_valid)."""
+        """Host copy of a one-part hierarchy: (nodes float32 [nn,16] with
+        int32 children in columns 12-13, tris float32 [n_valid,3,4], root,
+        n_valid)."""
         import numpy as np
+        if self.n_parts != 1:
+            raise ValueError("export covers one-part hierarchies")
         inf = self.info(stream)
         nn = max(1, inf.n_tris - 1)
         nodes = np.empty((nn, 16), np.float32)

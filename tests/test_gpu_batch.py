@@ -1,0 +1,163 @@
+"""Batches of parts: every per-part result of a batch hierarchy and of the
+one-call batch path equals the result of the same part alone (bit for bit:
+hierarchy shape, samples, bitmasks, statistics, class, setups), and the
+batch bitmasks agree with the oracle directly."""
+import sys
+
+import numpy as np
+import pytest
+
+from synth import parts as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2609_05467_amd import hra
+    assert torch.cuda.is_available()
+    c = hra.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def meshes():
+    return [P.config1_part(), P.box_part(), P.blind_hole_part(),
+            P._procedural(11, 1.0, "multiaxis", (100.0, 80.0, 50.0), (4, 8)), P.tetrahedron(), P.pocket_part(),
+            P._procedural(12, 1.0, "pockets", (120.0, 90.0, 60.0), (6, 10))]
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _np(s):
+    return {k: v.cpu().numpy() for k, v in s.items()}
+
+
+def test_batch_hierarchy_parts_match_alone(ctx, meshes):
+    from paper_2609_05467_amd import hra
+    _say("batch hierarchy", [m.n_tris for m in meshes])
+    bb = ctx.build_bvh_batch([(m.verts, m.tris) for m in meshes], leaf_size=4)
+    assert bb.n_parts == len(meshes)
+    for p, m in enumerate(meshes):
+        _say("part", p, m.n_tris)
+        ba = ctx.build_bvh(m.verts, m.tris, leaf_size=4)
+        ia, ib = ba.info(), bb.info(part=p)
+        for f in ("diag", "n_tris", "n_degenerate", "n_nodes", "depth", "leaf_size"):
+            assert getattr(ia, f) == getattr(ib, f), (p, f)
+        assert list(ia.bbox) == list(ib.bbox)
+        n = 700 + 97 * p
+        sa = ctx.sample_surface(ba, n, 5 + p)
+        sb = ctx.sample_surface(bb, n, 5 + p, part=p)
+        for k in ("point", "normal", "origin", "tri"):
+            assert np.array_equal(sa[k].cpu().numpy(), sb[k].cpu().numpy()), (p, k)
+        ca = ctx.sample_surface(ba, 0, 0, mode=hra.SAMPLE_CENTROID)
+        cb = ctx.sample_surface(bb, 0, 0, mode=hra.SAMPLE_CENTROID, part=p)
+        for k in ("point", "normal", "origin", "tri"):
+            assert np.array_equal(ca[k].cpu().numpy(), cb[k].cpu().numpy()), (p, "centroid", k)
+        for N in (300, 1024):
+            xa, na = ctx.cast(ba, sa, N)
+            xb, nb = ctx.cast(bb, sa, N, part=p)
+            assert np.array_equal(_u32(xa), _u32(xb)), (p, N)
+            assert np.array_equal(na.cpu().numpy(), nb.cpu().numpy()), (p, N)
+        a6, _ = ctx.cast(ba, sa, 6, kind=hra.DIRS_AXES6)
+        b6, _ = ctx.cast(bb, sa, 6, kind=hra.DIRS_AXES6, part=p)
+        assert np.array_equal(_u32(a6), _u32(b6)), p
+        ra = ctx.min_setups(ba, sa, a6, 30.0)
+        rb = ctx.min_setups(bb, sa, b6, 30.0, part=p)
+        for k in ("min_count", "min_mask", "greedy_count", "greedy_mask", "n_class", "code_hist"):
+            assert ra[k] == rb[k], (p, k)
+        assert np.array_equal(ra["class"].cpu().numpy(), rb["class"].cpu().numpy()), p
+        ba.release()
+    bb.release()
+
+
+def test_batch_part_index_checked(ctx, meshes):
+    from paper_2609_05467_amd import hra
+    bb = ctx.build_bvh_batch([(m.verts, m.tris) for m in meshes[:2]])
+    s = ctx.alloc_samples(10)
+    with pytest.raises(hra.HraError):
+        ctx.sample_surface(bb, 10, 1, part=2, out=s)
+    with pytest.raises(hra.HraError):
+        ctx.cast(bb, s, 64, part=-1)
+    with pytest.raises(hra.HraError):
+        bb.info(part=5)
+    with pytest.raises(ValueError):
+        bb.export()
+    bb.release()
+
+
+def _single(ctx, m, n, seed, N, tool, leaf=4):
+    from paper_2609_05467_amd import hra
+    b = ctx.build_bvh(m.verts, m.tris, leaf_size=leaf)
+    s = ctx.sample_surface(b, n, seed)
+    bits, _ = ctx.cast(b, s, N, counts=False)
+    ds = ctx.dominant_axes(s, N, bits)
+    rep = ctx.classify(ds, n, N)
+    b6, _ = ctx.cast(b, s, 6, kind=hra.DIRS_AXES6, counts=False)
+    su = ctx.min_setups(b, s, b6, tool, want_class=False)
+    b.release()
+    return s, bits, rep, su
+
+
+@pytest.mark.parametrize("N", [256, 1000])
+def test_batch_run_matches_single_calls(ctx, meshes, N):
+    import torch
+    reqs = [{"verts": m.verts, "tris": m.tris, "n_samples": 500 + 311 * p, "seed": 100 + p,
+             "tool_length": 20.0 + 5 * p} for p, m in enumerate(meshes)]
+    _say("batch_run", N, [r["n_samples"] for r in reqs])
+    W = (N + 31) // 32
+    S = sum(r["n_samples"] for r in reqs)
+    bits = torch.empty((S, W), dtype=torch.int32, device=ctx.device)
+    res = ctx.batch_run(reqs, N, leaf_size=4, bits=bits)
+    got = _u32(bits)
+    off = 0
+    for p, (m, r) in enumerate(zip(meshes, reqs)):
+        _say("compare part", p)
+        _, b1, rep, su = _single(ctx, m, r["n_samples"], r["seed"], N, r["tool_length"])
+        n = r["n_samples"]
+        assert np.array_equal(got[off:off + n], _u32(b1)), p
+        assert res[p]["class"] == rep, p
+        for k in ("min_count", "min_mask", "greedy_count", "greedy_mask", "n_class", "code_hist"):
+            assert res[p]["setups"][k] == su[k], (p, k)
+        off += n
+
+
+def test_batch_run_bits_vs_oracle(ctx, orc, meshes):
+    """Direct check of the batch bitmasks against the oracle (grazing rays
+    excluded) for two parts of different size in one batch."""
+    import torch
+    ms = [meshes[0], meshes[3]]
+    N = 512
+    reqs = [{"verts": m.verts, "tris": m.tris, "n_samples": 400, "seed": 9 + p, "tool_length": 40.0}
+            for p, m in enumerate(ms)]
+    bits = torch.empty((800, N // 32), dtype=torch.int32, device=ctx.device)
+    ctx.batch_run(reqs, N, bits=bits)
+    got = _u32(bits)
+    dirs = orc.fibonacci_dirs(N)
+    for p, m in enumerate(ms):
+        o = orc.sample_area(m.verts, m.tris, 400, 9 + p)
+        ob, og, _ = orc.cast(m.verts, m.tris, o, dirs)
+        bad = (got[400 * p:400 * (p + 1)] ^ ob) & ~og
+        assert not bad.any(), p
+
+
+def test_batch_run_single_part_and_limits(ctx, meshes):
+    from paper_2609_05467_amd import hra
+    m = meshes[0]
+    r = ctx.batch_run([{"verts": m.verts, "tris": m.tris, "n_samples": 300, "seed": 4, "tool_length": 50.0}], 128)
+    _, _, rep, su = _single(ctx, m, 300, 4, 128, 50.0)
+    assert r[0]["class"] == rep and r[0]["setups"]["min_count"] == su["min_count"]
+    with pytest.raises(hra.HraError):
+        ctx.batch_run([{"verts": m.verts, "tris": m.tris, "n_samples": 0, "seed": 4, "tool_length": 50.0}], 128)
+    with pytest.raises(hra.HraError):
+        ctx.batch_run([], 128)
