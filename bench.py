@@ -29,6 +29,8 @@ WORKLOADS = {
     "interactive_200k": ("interactive_200k", 100_000, 4096),
     "single_block_1k5": ("single_block_1k5", 1_000, 512),
     "multiaxis_1m": ("multiaxis_1m", 250_000, 2048),
+    # 64 uneven parts (2k-500k triangles), samples by area in [1k, 50k]
+    "batch64": ("batch64", None, 1024),
 }
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 NODE_BYTES, TRI_BYTES = 64, 48  # one interior-node record, one leaf triangle
@@ -90,6 +92,9 @@ def main():
     ap.add_argument("--rays-per-wave", type=int, default=64)
     ap.add_argument("--stack", type=int, default=24)
     ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--autotune", action="store_true", help="batch64: sweep the launch shape first")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes generating the batch parts (before any GPU work)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -98,6 +103,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by part and "
               "by samples with no exchange, see the design notes)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        return run_batch(args)
 
     import numpy as np
     import torch
@@ -209,6 +217,133 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, samples_np, N)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def run_batch(args):
+    """64 uneven parts: the plain path (one part after another, each stage
+    its own launches, synchronising per part) against the batch plan (one
+    hierarchy, one launch per stage for all parts) eager and as a replayed
+    HIP graph.  value = hemisphere rays/s of the graph runs."""
+    import numpy as np
+    from synth import parts
+    N = WORKLOADS["batch64"][2]
+    log(f"[bench] generating 64 parts with {args.workers} processes")
+    t0 = time.perf_counter()
+    meshes = parts.batch_parts(workers=args.workers)   # before any GPU work (fork)
+    counts = parts.batch_samples(meshes)
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s: {sum(m.n_tris for m in meshes)} triangles, "
+        f"{sum(counts)} samples")
+    import torch
+    from paper_2609_05467_amd import hra
+    ctx = hra.Context(0)
+    dev = ctx.device
+    ctx.set_cast_config(args.rays_per_wave, args.stack, args.leaf)
+    dm = [(torch.tensor(m.verts, device=dev), torch.tensor(m.tris, device=dev)) for m in meshes]
+    reqs = [{"verts": v, "tris": t, "n_samples": c, "seed": 400 + i, "tool_length": args.tool_length}
+            for i, ((v, t), c) in enumerate(zip(dm, counts))]
+    S = sum(counts)
+    rays = S * N
+    tune = None
+    if args.autotune:
+        log("[bench] autotune sweep (27 points)")
+        tune = ctx.autotune(reqs, N, reps=1)
+        log(f"[bench] best {tune['best']}")
+    rpw, stack, leaf = ctx.cast_config()
+
+    # plain: one part after another
+    W = (N + 31) // 32
+    bufs = [(ctx.alloc_samples(c), torch.empty((c, W), dtype=torch.int32, device=dev),
+             torch.empty((c, 1), dtype=torch.int32, device=dev)) for c in counts]
+
+    def plain_pass():
+        out = []
+        for i, ((v, t), c) in enumerate(zip(dm, counts)):
+            smp, bits, b6 = bufs[i]
+            b = ctx.build_bvh(v, t, leaf_size=leaf)
+            ctx.sample_surface(b, c, 400 + i, out=smp)
+            ctx.cast(b, smp, N, counts=False, bits=bits)
+            ds = ctx.dominant_axes(smp, N, bits)
+            rep = ctx.classify(ds, c, N)
+            ctx.cast(b, smp, 6, kind=hra.DIRS_AXES6, counts=False, bits=b6)
+            su = ctx.min_setups(b, smp, b6, args.tool_length, want_class=False)
+            b.release()
+            out.append((rep, su))
+        return out
+
+    log("[bench] plain warmup")
+    plain_res = plain_pass()
+    torch.cuda.synchronize()
+    log(f"[bench] plain timing {args.steps} passes")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_pass()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / args.steps
+
+    pl = ctx.plan(reqs, N)
+    log(f"[bench] plan holds {pl.bytes / 2**30:.2f} GiB; eager warmup")
+    res = pl.run(graph=False)
+    same_plain = all(r["class"] == p[0] and all(r["setups"][k] == p[1][k] for k in
+                                                  ("min_count", "min_mask", "n_class", "code_hist"))
+                     for r, p in zip(res, plain_res))
+    stage = {k: [] for k in ("build", "sample", "cast", "stats", "axes", "setups")}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pl.run(graph=False)
+        for k, v in pl.stage_ms().items():
+            stage[k].append(v)
+    eager_s = (time.perf_counter() - t0) / args.steps
+    log("[bench] graph capture + replays")
+    res_g = pl.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res_g = pl.run(graph=True)
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / args.steps
+    same_graph = res_g == res
+    pl.destroy()
+
+    # traversal work per ray (instrumented single-part casts, outside the timed region)
+    nodes = tests = 0
+    for i, ((v, t), c) in enumerate(zip(dm, counts)):
+        smp = bufs[i][0]
+        b = ctx.build_bvh(v, t, leaf_size=leaf)
+        ctx.sample_surface(b, c, 400 + i, out=smp)
+        _, nf, nt = ctx.cast_work(b, smp, N)
+        nodes += nf
+        tests += nt
+        b.release()
+    bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
+    cast_ms = float(np.mean(stage["cast"]))
+    achieved = bytes_per_ray * rays / (cast_ms * 1e-3) / 1e9
+    out = {
+        "metric": "any-hit hemisphere rays/s",
+        "value": rays / graph_s,
+        "unit": "rays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": graph_s * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch64", "parts": len(meshes), "triangles": int(sum(m.n_tris for m in meshes)),
+                   "triangles_min_max": [int(min(m.n_tris for m in meshes)), int(max(m.n_tris for m in meshes))],
+                   "samples": S, "samples_min_max": [min(counts), max(counts)], "directions": N,
+                   "rays_per_step": rays, "leaf_size": leaf, "rays_per_wave": rpw, "stack_depth": stack,
+                   "tool_length_mm": args.tool_length},
+        "parts_per_s": len(meshes) / graph_s,
+        "batched_graph": {"ms": graph_s * 1e3, "parts_per_s": len(meshes) / graph_s, "rays_per_s": rays / graph_s},
+        "batched_eager": {"ms": eager_s * 1e3, "parts_per_s": len(meshes) / eager_s, "rays_per_s": rays / eager_s},
+        "plain": {"ms": plain_s * 1e3, "parts_per_s": len(meshes) / plain_s, "rays_per_s": rays / plain_s},
+        "speedup_vs_plain": plain_s / graph_s,
+        "results_identical": {"batch_vs_plain": bool(same_plain), "graph_vs_eager": bool(same_graph)},
+        "stage_ms": {k: round(float(np.mean(v)), 3) for k, v in stage.items()},
+        "work_per_ray": {"node_fetches": nodes / rays, "tri_tests": tests / rays, "bytes": bytes_per_ray},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("batch64")[0],
+                     "kernel": "k_cast", "avg_launch_ms": cast_ms, "algorithmic_bytes": bytes_per_ray * rays},
+    }
+    if tune is not None:
+        out["autotune"] = tune
     print(json.dumps(out), flush=True)
     ctx.close()
 

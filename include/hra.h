@@ -190,10 +190,13 @@ typedef struct {
     int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
     int32_t stack_depth;   /* traversal stack entries per lane held in LDS: 16, 24 or 32
                               (deeper paths overflow into private memory) */
+    int32_t leaf_size;     /* triangles per leaf of builds whose options give 0: 1..8
+                              (0 in hra_set_cast_config: keep the current value) */
 } hra_cast_config;
 
-/* Launch shape of hra_cast_hemisphere for this context (defaults 64 / 24).
- * Results do not depend on it; only speed does. */
+/* Launch shape of hra_cast_hemisphere and default leaf size for this
+ * context (defaults 64 / 24 / 4).  Results do not depend on it; only speed
+ * does. */
 hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *cfg);
 hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
 
@@ -322,6 +325,8 @@ typedef struct {
 typedef struct {
     int32_t n_dirs;                     /* hemisphere directions for every part */
     int32_t leaf_size;                  /* 0 = default (4) */
+    int32_t rays_per_wave;              /* 0 = the context's cast configuration */
+    int32_t stack_depth;                /* 0 = the context's cast configuration */
     float offset_frac;                  /* 0 = 1e-4 */
     const hra_thresholds *thresholds;   /* NULL = defaults */
 } hra_batch_opts;
@@ -339,9 +344,59 @@ typedef struct {
  * samples, bits, statistics, class and setups).  results: host
  * [n_parts].  Synchronises `stream`.  If d_bits_out is not NULL it receives
  * the hemisphere bitmasks of all parts, part after part: uint32
- * [sum n_samples][ceil(n_dirs / 32)]. */
+ * [sum n_samples][ceil(n_dirs / 32)].  Equivalent to hra_plan_create,
+ * hra_plan_run without a graph, hra_plan_destroy. */
 hra_status hra_batch_run(hra_ctx *ctx, const hra_part_request *parts, int32_t n_parts, const hra_batch_opts *opts,
                          hra_part_result *results, uint32_t *d_bits_out, void *stream);
+
+/* A batch plan: every device buffer of one batch (hierarchy, build
+ * scratch, samples, bitmasks, statistics, job tables) and pinned host
+ * slots for its results, allocated once.  The part meshes are read at each
+ * run, so they must stay allocated (their contents may change, their sizes
+ * may not) until the plan is destroyed.  The launch shape (rays per wave,
+ * stack depth, leaf size) is fixed at creation. */
+typedef struct hra_plan hra_plan;
+hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *parts, int32_t n_parts, const hra_batch_opts *opts,
+                           hra_plan **out);
+/* Run the plan after the work already on `stream`: build, sample, cast,
+ * statistics, six-axis cast, setups; results as for hra_batch_run.  With
+ * use_graph != 0 the first call captures the sequence (kernels and three
+ * copies into pinned memory; no allocation, memset or host callback) in a
+ * HIP graph on the plan's own stream and every call replays it.  Without a
+ * graph the per-stage times are kept (hra_plan_stage_ms).  Runs of one plan
+ * must not overlap: the call synchronises before it returns. */
+hra_status hra_plan_run(hra_plan *plan, int32_t use_graph, hra_part_result *results, uint32_t *d_bits_out,
+                        void *stream);
+/* Milliseconds of the last run without a graph: build, sample, cast,
+ * statistics and totals, six-axis cast, setups. */
+hra_status hra_plan_stage_ms(const hra_plan *plan, float *ms6);
+/* Device bytes the plan holds. */
+int64_t hra_plan_bytes(const hra_plan *plan);
+/* The plan's own bitmask array (valid until the next run or destroy). */
+const uint32_t *hra_plan_bits(const hra_plan *plan);
+void hra_plan_destroy(hra_plan *plan);
+
+typedef struct {
+    int32_t rays_per_wave;
+    int32_t stack_depth;
+    int32_t leaf_size;
+    float ms;              /* mean time of one whole run of the batch (build to setups) */
+} hra_tune_point;
+
+typedef struct {
+    int32_t n_points;
+    int32_t best;          /* index of the fastest point */
+    hra_tune_point points[27];
+} hra_tune_report;
+
+/* Autotuner for a batch: sweeps rays per wave {64, 128, 256} x stack depth
+ * {16, 24, 32} x leaf size {2, 4, 8}, times `reps` runs of a plan for each
+ * point after one warm-up run, checks that every point gives the same
+ * results, and stores the fastest point in the context's cast
+ * configuration (hra_get_cast_config).  opts: as for hra_plan_create (its
+ * launch-shape fields are overridden).  Synchronises `stream`. */
+hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, int32_t n_parts, const hra_batch_opts *opts,
+                        int32_t reps, hra_tune_report *out, void *stream);
 
 #ifdef __cplusplus
 }

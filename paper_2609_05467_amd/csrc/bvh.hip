@@ -28,6 +28,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <vector>
 
 namespace hra {
 
@@ -86,24 +87,29 @@ __global__ void k_scan_add(T *out, int64_t n, const T *block_prefix) {
     }
 }
 
+// Elements of scratch a scan of n elements needs (block sums, recursively).
+static int64_t scan_ws_elems(int64_t n) {
+    if (n <= SCAN_TILE) return 0;
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    return nb + scan_ws_elems(nb);
+}
+
+// Exclusive or inclusive prefix sum; `ws` holds scan_ws_elems(n) elements.
 template <typename T>
-static hipError_t scan(const T *in, T *out, int64_t n, bool inclusive, hipStream_t s) {
+static hipError_t scan(const T *in, T *out, int64_t n, bool inclusive, T *ws, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 1) {
         k_scan_tile<T><<<1, TB, 0, s>>>(in, out, n, (T *)nullptr, inclusive ? 1 : 0);
         return hipGetLastError();
     }
-    T *sums = nullptr;
-    hipError_t e = hipMallocAsync((void **)&sums, sizeof(T) * nb, s);
-    if (e != hipSuccess) return e;
+    T *sums = ws;
     k_scan_tile<T><<<(unsigned)nb, TB, 0, s>>>(in, out, n, sums, inclusive ? 1 : 0);
-    e = scan<T>(sums, sums, nb, false, s);
+    hipError_t e = scan<T>(sums, sums, nb, false, ws + nb, s);
     if (e == hipSuccess) {
         k_scan_add<T><<<(unsigned)nb, TB, 0, s>>>(out, n, sums);
         e = hipGetLastError();
     }
-    hipFreeAsync(sums, s);
     return e;
 }
 
@@ -356,24 +362,28 @@ __global__ void k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t 
     }
 }
 
-static hipError_t radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, hipStream_t s,
-                             bool *result_in_k1) {
+static int64_t radix_ws_elems(int64_t n) {
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    return 256 * nb + scan_ws_elems(256 * nb);
+}
+
+// `ws` holds radix_ws_elems(n) uint32 elements.
+static hipError_t radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws,
+                             hipStream_t s, bool *result_in_k1) {
     const int nb = (int)((n + RS_TILE - 1) / RS_TILE);
-    uint32_t *hist = nullptr;
-    hipError_t e = hipMallocAsync((void **)&hist, sizeof(uint32_t) * 256 * (size_t)nb, s);
-    if (e != hipSuccess) return e;
+    uint32_t *hist = ws, *sws = ws + 256 * (int64_t)nb;
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
+    hipError_t e = hipSuccess;
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
         k_rs_hist<<<nb, TB, 0, s>>>(ka, n, shift, hist, nb);
-        e = scan<uint32_t>(hist, hist, (int64_t)256 * nb, false, s);
+        e = scan<uint32_t>(hist, hist, (int64_t)256 * nb, false, sws, s);
         if (e != hipSuccess) break;
         k_rs_scatter<<<nb, TB, 0, s>>>(ka, va, kb, vb, n, shift, hist, nb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    hipFreeAsync(hist, s);
     *result_in_k1 = (ka == k1);
     if (e == hipSuccess) e = hipGetLastError();
     return e;
@@ -573,33 +583,95 @@ __global__ void k_emit(const float4 *tri4, const uint64_t *keys, const int32_t *
 
 using namespace hra;
 
-static hra_status build_parts(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, const hra_bvh_opts *opts,
-                              hipStream_t s, hra_bvh **out) {
-    if (!ctx || !out || !meshes) return HRA_ERR_INVALID_ARG;
-    *out = nullptr;
+namespace hra {
+
+// Scratch of one build, carved from one allocation (256-byte aligned
+// pieces), so a build can run in memory the caller set aside (graphs).
+struct BuildWs {
+    MeshIn *mesh;
+    double *area;
+    uint32_t *valid, *excl, *vals0, *vals1, *flags, *rs_ws;
+    uint64_t *w, *keys0, *keys1, *scan64_ws;
+    uint32_t *scan32_ws;
+    int32_t *L, *R, *F, *La, *PI, *PL, *nvt;
+    float *box, *tv;
+    uint8_t *tpart;
+};
+
+static size_t carve(char *base, int64_t T, int n_parts, BuildWs *w) {
+    const int64_t nn = T > 1 ? T - 1 : 1;
+    size_t off = 0;
+    auto take = [&](void **p, size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        if (base) *p = base + off;
+        off += bytes;
+    };
+    BuildWs d;
+    take((void **)&d.mesh, sizeof(MeshIn) * n_parts);
+    take((void **)&d.area, sizeof(double) * T);
+    take((void **)&d.valid, sizeof(uint32_t) * T);
+    take((void **)&d.excl, sizeof(uint32_t) * T);
+    take((void **)&d.w, sizeof(uint64_t) * T);
+    take((void **)&d.keys0, sizeof(uint64_t) * T);
+    take((void **)&d.keys1, sizeof(uint64_t) * T);
+    take((void **)&d.vals0, sizeof(uint32_t) * T);
+    take((void **)&d.vals1, sizeof(uint32_t) * T);
+    take((void **)&d.tv, sizeof(float) * 9 * T);
+    take((void **)&d.tpart, sizeof(uint8_t) * T);
+    take((void **)&d.L, sizeof(int32_t) * nn);
+    take((void **)&d.R, sizeof(int32_t) * nn);
+    take((void **)&d.F, sizeof(int32_t) * nn);
+    take((void **)&d.La, sizeof(int32_t) * nn);
+    take((void **)&d.PI, sizeof(int32_t) * nn);
+    take((void **)&d.PL, sizeof(int32_t) * T);
+    take((void **)&d.flags, sizeof(uint32_t) * nn);
+    take((void **)&d.box, sizeof(float) * 6 * nn);
+    take((void **)&d.nvt, sizeof(int32_t));
+    take((void **)&d.scan64_ws, sizeof(uint64_t) * (scan_ws_elems(T) + 1));
+    take((void **)&d.scan32_ws, sizeof(uint32_t) * (scan_ws_elems(T) + 1));
+    take((void **)&d.rs_ws, sizeof(uint32_t) * radix_ws_elems(T));
+    if (w) *w = d;
+    return (off + 255) & ~(size_t)255;
+}
+
+size_t build_ws_bytes(int64_t T, int n_parts) { return carve(nullptr, T, n_parts, nullptr); }
+
+MeshIn *build_ws_mesh_table(void *ws, int64_t T, int n_parts) {
+    BuildWs w;
+    carve((char *)ws, T, n_parts, &w);
+    return w.mesh;
+}
+
+// Check the meshes and lay out the concatenated triangle ranges.
+hra_status check_meshes(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, int32_t leaf,
+                        std::vector<MeshIn> *hm, int64_t *T_out) {
     if (n_parts < 1 || n_parts > MAX_PARTS) return ctx->fail(HRA_ERR_INVALID_ARG, "1..255 parts per hierarchy");
+    if (leaf < 1 || leaf > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 1..8");
     int64_t T = 0;
-    std::vector<MeshIn> hm(n_parts);
+    hm->resize(n_parts);
     for (int p = 0; p < n_parts; ++p) {
         const hra_mesh &m = meshes[p];
         if (!m.d_verts || !m.d_tris || m.n_verts < 3 || m.n_tris < 1)
             return ctx->fail(HRA_ERR_INVALID_ARG, "each mesh needs at least 3 vertices and 1 triangle");
         if (m.n_verts >= (int64_t)1 << 31) return ctx->fail(HRA_ERR_INVALID_ARG, "too many vertices in a mesh");
-        hm[p] = MeshIn{m.d_verts, m.d_tris, m.n_verts, m.n_tris, T};
+        (*hm)[p] = MeshIn{m.d_verts, m.d_tris, m.n_verts, m.n_tris, T};
         T += m.n_tris;
     }
     if (T >= (int64_t)1 << 27) return ctx->fail(HRA_ERR_INVALID_ARG, "too many triangles (max 2^27 per hierarchy)");
-    int leaf = opts && opts->leaf_size ? opts->leaf_size : 4;
-    if (leaf < 1 || leaf > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 1..8");
-    HRA_HIP(hipSetDevice(ctx->device));
+    *T_out = T;
+    return HRA_OK;
+}
 
+// The hierarchy's own arrays (no kernel work).
+hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out) {
+    const int n_parts = (int)hm.size();
     hra_bvh *b = new hra_bvh();
     b->ctx = ctx;
     b->n_parts = n_parts;
     b->n_tris = T;
     b->leaf_size = leaf;
     for (int p = 0; p < n_parts; ++p) {
-        b->part_tris.push_back(meshes[p].n_tris);
+        b->part_tris.push_back(hm[p].nt);
         b->part_start.push_back(hm[p].tri_start);
     }
     const int64_t nn = T > 1 ? T - 1 : 1;
@@ -615,73 +687,68 @@ static hra_status build_parts(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_pa
         return ctx->fail(HRA_ERR_OUT_OF_MEMORY, "BVH allocation failed");
     }
     b->bytes = (int64_t)bytes;
+    *out = b;
+    return HRA_OK;
+}
 
-    // temporaries, stream ordered
-    double *area = nullptr;
-    uint32_t *valid = nullptr, *excl = nullptr, *vals0 = nullptr, *vals1 = nullptr, *flags = nullptr;
-    uint64_t *w = nullptr, *keys0 = nullptr, *keys1 = nullptr;
-    int32_t *L = nullptr, *R = nullptr, *F = nullptr, *La = nullptr, *PI = nullptr, *PL = nullptr, *nvt = nullptr;
-    float *box = nullptr, *tv = nullptr;
-    uint8_t *tpart = nullptr;
-    MeshIn *dmesh = nullptr;
-    hipError_t e = hipSuccess;
-#define TMP(p, n)                                                   \
-    if (e == hipSuccess) e = hipMallocAsync((void **)&(p), (n), s);
-    TMP(dmesh, sizeof(MeshIn) * n_parts);
-    TMP(area, sizeof(double) * T);
-    TMP(valid, sizeof(uint32_t) * T);
-    TMP(excl, sizeof(uint32_t) * T);
-    TMP(w, sizeof(uint64_t) * T);
-    TMP(keys0, sizeof(uint64_t) * T);
-    TMP(keys1, sizeof(uint64_t) * T);
-    TMP(vals0, sizeof(uint32_t) * T);
-    TMP(vals1, sizeof(uint32_t) * T);
-    TMP(tv, sizeof(float) * 9 * T);
-    TMP(tpart, sizeof(uint8_t) * T);
-    TMP(L, sizeof(int32_t) * nn);
-    TMP(R, sizeof(int32_t) * nn);
-    TMP(F, sizeof(int32_t) * nn);
-    TMP(La, sizeof(int32_t) * nn);
-    TMP(PI, sizeof(int32_t) * nn);
-    TMP(PL, sizeof(int32_t) * T);
-    TMP(flags, sizeof(uint32_t) * nn);
-    TMP(box, sizeof(float) * 6 * nn);
-    TMP(nvt, sizeof(int32_t));
-#undef TMP
-    if (e == hipSuccess) e = hipMemcpyAsync(dmesh, hm.data(), sizeof(MeshIn) * n_parts, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) {
-        const int gT = blocks_for(T, TB), gN = blocks_for(nn, TB);
-        k_fill_i32<<<gT, TB, 0, s>>>(b->leaf_pos, T, -1);
-        k_fill_sentinel_nodes<<<gN, TB, 0, s>>>(b->nodes, nn);
-        k_fill_u32<<<gN, TB, 0, s>>>(flags, nn, 0u);
-        k_fill_i32<<<gN, TB, 0, s>>>(PI, nn, -1);
-        k_tri_prep<<<gT, TB, 0, s>>>(dmesh, n_parts, T, area, valid, tv, tpart, ctx->d_err);
-        k_part_facts<<<n_parts, 256, 0, s>>>(dmesh, area, b->parts);
-        k_weights<<<gT, TB, 0, s>>>(area, tpart, T, b->parts, w);
-        e = scan<uint64_t>(w, b->prefix, T, true, s);
-        if (e == hipSuccess) e = scan<uint32_t>(valid, excl, T, false, s);
-        if (e == hipSuccess) {
-            k_part_counts<<<1, 64, 0, s>>>(b->prefix, excl, valid, n_parts, T, b->parts, nvt, ctx->d_err);
-            k_ranks<<<gT, TB, 0, s>>>(valid, excl, tpart, T, b->parts, b->valid_rank);
-            k_keys<<<gT, TB, 0, s>>>(tv, tpart, valid, T, b->parts, keys0, vals0);
-            bool in1 = false;
-            e = radix_sort(keys0, vals0, keys1, vals1, T, s, &in1);
-            uint64_t *ks = in1 ? keys1 : keys0;
-            uint32_t *vs = in1 ? vals1 : vals0;
-            if (e == hipSuccess) {
-                k_gather<<<gT, TB, 0, s>>>(tv, vs, tpart, b->parts, nvt, b->tris, b->leaf_pos);
-                k_karras<<<gN, TB, 0, s>>>(ks, nvt, L, R, F, La, PI, PL, b->parts);
-                k_small_roots<<<blocks_for(n_parts, 64), 64, 0, s>>>(b->parts, n_parts, leaf);
-                k_refit<<<gT, TB, 0, s>>>(b->tris, PL, PI, L, R, box, flags, nvt);
-                k_emit<<<gN, TB, 0, s>>>(b->tris, ks, L, R, F, La, PI, box, leaf, nvt, b->nodes, b->parts);
-                e = hipGetLastError();
-            }
-        }
-    }
-    for (void *p : {(void *)dmesh, (void *)area, (void *)valid, (void *)excl, (void *)w, (void *)keys0, (void *)keys1,
-                    (void *)vals0, (void *)vals1, (void *)tv, (void *)tpart, (void *)L, (void *)R, (void *)F,
-                    (void *)La, (void *)PI, (void *)PL, (void *)flags, (void *)box, (void *)nvt})
-        if (p) hipFreeAsync(p, s);
+// Enqueue the whole build on `s`: kernels only (no allocation, copy or
+// memset), reading the mesh table already in the workspace.
+hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s) {
+    const int64_t T = b->n_tris;
+    const int n_parts = b->n_parts;
+    const int leaf = b->leaf_size;
+    const int64_t nn = T > 1 ? T - 1 : 1;
+    BuildWs W;
+    carve((char *)ws_base, T, n_parts, &W);
+    const int gT = blocks_for(T, TB), gN = blocks_for(nn, TB);
+    k_fill_i32<<<gT, TB, 0, s>>>(b->leaf_pos, T, -1);
+    k_fill_sentinel_nodes<<<gN, TB, 0, s>>>(b->nodes, nn);
+    k_fill_u32<<<gN, TB, 0, s>>>(W.flags, nn, 0u);
+    k_fill_i32<<<gN, TB, 0, s>>>(W.PI, nn, -1);
+    k_tri_prep<<<gT, TB, 0, s>>>(W.mesh, n_parts, T, W.area, W.valid, W.tv, W.tpart, ctx->d_err);
+    k_part_facts<<<n_parts, 256, 0, s>>>(W.mesh, W.area, b->parts);
+    k_weights<<<gT, TB, 0, s>>>(W.area, W.tpart, T, b->parts, W.w);
+    hipError_t e = scan<uint64_t>(W.w, b->prefix, T, true, W.scan64_ws, s);
+    if (e == hipSuccess) e = scan<uint32_t>(W.valid, W.excl, T, false, W.scan32_ws, s);
+    if (e != hipSuccess) return e;
+    k_part_counts<<<1, 64, 0, s>>>(b->prefix, W.excl, W.valid, n_parts, T, b->parts, W.nvt, ctx->d_err);
+    k_ranks<<<gT, TB, 0, s>>>(W.valid, W.excl, W.tpart, T, b->parts, b->valid_rank);
+    k_keys<<<gT, TB, 0, s>>>(W.tv, W.tpart, W.valid, T, b->parts, W.keys0, W.vals0);
+    bool in1 = false;
+    e = radix_sort(W.keys0, W.vals0, W.keys1, W.vals1, T, W.rs_ws, s, &in1);
+    if (e != hipSuccess) return e;
+    uint64_t *ks = in1 ? W.keys1 : W.keys0;
+    uint32_t *vs = in1 ? W.vals1 : W.vals0;
+    k_gather<<<gT, TB, 0, s>>>(W.tv, vs, W.tpart, b->parts, W.nvt, b->tris, b->leaf_pos);
+    k_karras<<<gN, TB, 0, s>>>(ks, W.nvt, W.L, W.R, W.F, W.La, W.PI, W.PL, b->parts);
+    k_small_roots<<<blocks_for(n_parts, 64), 64, 0, s>>>(b->parts, n_parts, leaf);
+    k_refit<<<gT, TB, 0, s>>>(b->tris, W.PL, W.PI, W.L, W.R, W.box, W.flags, W.nvt);
+    k_emit<<<gN, TB, 0, s>>>(b->tris, ks, W.L, W.R, W.F, W.La, W.PI, W.box, leaf, W.nvt, b->nodes, b->parts);
+    return hipGetLastError();
+}
+
+}  // namespace hra
+
+static hra_status build_parts(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, const hra_bvh_opts *opts,
+                              hipStream_t s, hra_bvh **out) {
+    if (!ctx || !out || !meshes) return HRA_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int leaf = opts && opts->leaf_size ? opts->leaf_size : ctx->leaf_default;
+    std::vector<MeshIn> hm;
+    int64_t T = 0;
+    hra_status st = check_meshes(ctx, meshes, n_parts, leaf, &hm, &T);
+    if (st != HRA_OK) return st;
+    HRA_HIP(hipSetDevice(ctx->device));
+    hra_bvh *b = nullptr;
+    st = alloc_bvh(ctx, hm, T, leaf, &b);
+    if (st != HRA_OK) return st;
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, build_ws_bytes(T, n_parts), s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(build_ws_mesh_table(ws, T, n_parts), hm.data(), sizeof(MeshIn) * n_parts,
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = enqueue_build(ctx, b, ws, s);
+    if (ws) hipFreeAsync(ws, s);
     if (e != hipSuccess) {
         hipStreamSynchronize(s);
         hra_bvh_release(b);

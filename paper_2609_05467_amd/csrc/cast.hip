@@ -176,81 +176,111 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
     }
 }
 
-// One work item = (sample, RPW consecutive directions) per wavefront; the
-// item index comes from the launch grid, so it is wave-uniform by
-// construction and no cross-lane broadcast is needed.  The ballot masks stay
-// in wave-uniform registers and are written once, after the last cross-lane
-// operation of the kernel, so no lane-dependent branch ever precedes a
-// ballot.
-template <int RPW, int STACK, bool STATS>
-__global__ __launch_bounds__(256) void k_cast(CastArgs a) {
-    __shared__ int stk[4][STACK * 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t item = (int64_t)blockIdx.x * 4 + wv;
-    if (item >= a.n_items) return;  // the whole wavefront leaves together
-    // job of this item (wave-uniform): last job whose item_base <= item
-    CastJob J = a.job0;
-    if (a.jobs) {
-        int lo = 0, hi = a.n_jobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.jobs[mid].item_base <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        J = a.jobs[lo];
+// Job of a wave-uniform work item: the last job whose item_base <= item.
+__device__ inline CastJob job_of(const CastArgs &a, int64_t item) {
+    if (!a.jobs) return a.job0;
+    int lo = 0, hi = a.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.jobs[mid].item_base <= item) lo = mid;
+        else hi = mid - 1;
     }
-    int *lds = stk[wv];
+    return a.jobs[lo];
+}
+
+// Hemisphere cast.  One work item = one sample, all N directions, on one
+// workgroup of four wavefronts.  The directions are walked in the table's
+// traversal order (a space-filling curve over the hemisphere) in steps of
+// 256: the four waves take four neighbouring 64-direction patches, so every
+// ray in flight in the workgroup starts at the same origin with a nearby
+// direction and they traverse nearly the same nodes (shared in L1, little
+// divergence).  Each lane ORs its verdict into the sample's bit row in LDS
+// at the direction's canonical index; the finished row is stored with
+// coalesced writes.  The item index is the block index, uniform over the
+// workgroup, so both barriers are reached by every thread, and the kernel
+// has no cross-lane operation.
+template <int RPW, int STACK, bool STATS>
+__global__ __launch_bounds__(256) void k_cast_rows(CastArgs a) {
+    extern __shared__ int dyn_lds[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t item = blockIdx.x;
+    if (item >= a.n_items) return;  // the whole workgroup leaves together
+    int *lds = dyn_lds + wv * (STACK * 64);
+    uint32_t *row = (uint32_t *)(dyn_lds + 4 * STACK * 64);
+    const CastJob J = job_of(a, item);
     const PartMeta &P = *J.meta;
     const int32_t root = P.root;
     const int32_t n_valid = P.n_valid;
     const bool empty = n_valid <= 0;
     const int32_t n_tris_alloc = P.leaf_lo + n_valid;   // end of this part's leaf run
-    const int64_t li = item - J.item_base;
-    const int64_t s = li / a.chunks;
-    const int32_t ch = (int32_t)(li % a.chunks);
+    const int64_t s = item - J.item_base;
     const float ox = J.origin[3 * s], oy = J.origin[3 * s + 1], oz = J.origin[3 * s + 2];
     const float nx = J.normal[3 * s], ny = J.normal[3 * s + 1], nz = J.normal[3 * s + 2];
     float3 t, b;
     onb_frame(nx, ny, nz, t, b);
-    uint64_t mk[RPW / 64];
+    for (int32_t w = threadIdx.x; w < a.W; w += 256) row[w] = 0u;
+    __syncthreads();
     WorkCount wc;
+    for (int32_t c = 0; c < a.n_dirs; c += 4 * RPW) {
 #pragma unroll
-    for (int r = 0; r < RPW / 64; ++r) {
-        const int32_t j = ch * RPW + r * 64 + lane;
-        bool free_ray = false;
-        if (j < a.n_dirs) {
-            const float4 l = a.dirs[j];
-            float dx, dy, dz;
-            bool cast = true;
-            if (a.kind == 0) {
+        for (int r = 0; r < RPW / 64; ++r) {
+            const int32_t j = c + r * 256 + wv * 64 + lane;
+            uint32_t bit = 0u;
+            int32_t idx = 0;
+            if (j < a.n_dirs) {
+                const float4 l = a.dirs_order[j];
+                idx = __float_as_int(l.w);
                 const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
-                dx = d.x;
-                dy = d.y;
-                dz = d.z;
-            } else {
-                dx = l.x;
-                dy = l.y;
-                dz = l.z;
-                const float q0 = nx * dx, q1 = ny * dy, q2 = nz * dz;
-                const float nd = (q0 + q1) + q2;
-                cast = !(nd < 0.0f);
+                const bool free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, d.x, d.y,
+                                                                      d.z, lds, lane, a.err, J.n_nodes_alloc,
+                                                                      n_tris_alloc, wc);
+                bit = (uint32_t)free_ray << (idx & 31);
             }
-            if (cast)
-                free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, dx, dy, dz, lds, lane,
-                                                            a.err, J.n_nodes_alloc, n_tris_alloc, wc);
+            atomicOr(&row[idx >> 5], bit);
         }
-        mk[r] = __ballot(free_ray);
     }
-    // words of this item: [ch * RPW/32, min(W, (ch + 1) * RPW/32))
-    const int32_t w0 = ch * (RPW / 32);
-    const int32_t nw = a.W - w0 < RPW / 32 ? a.W - w0 : RPW / 32;
-    if (lane < nw) {
-        uint64_t m = mk[0];
-#pragma unroll
-        for (int r = 1; r < RPW / 64; ++r)
-            if ((lane >> 1) == r) m = mk[r];
-        J.bits[s * a.W + w0 + lane] = (lane & 1) ? (uint32_t)(m >> 32) : (uint32_t)m;
+    __syncthreads();
+    for (int32_t w = threadIdx.x; w < a.W; w += 256) J.bits[s * a.W + w] = row[w];
+    if (STATS) {
+        atomicAdd(a.work, (unsigned long long)wc.nodes);
+        atomicAdd(a.work + 1, (unsigned long long)wc.tris);
     }
+}
+
+// Six-axis cast.  One work item = AX_PER_WAVE samples x 6 world axes on the
+// 60 first lanes of a wavefront.  A ray whose axis points into the material
+// (n . D < 0) is not cast.  The ballot follows the traversal directly and
+// the per-sample 6-bit groups are stored after it.
+constexpr int AX_PER_WAVE = 10;
+
+template <int STACK, bool STATS>
+__global__ __launch_bounds__(256) void k_cast_axes(CastArgs a) {
+    __shared__ int stk[4][STACK * 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t item = (int64_t)blockIdx.x * 4 + wv;
+    if (item >= a.n_items) return;
+    const CastJob J = job_of(a, item);
+    const PartMeta &P = *J.meta;
+    const int32_t root = P.root;
+    const bool empty = P.n_valid <= 0;
+    const int32_t n_tris_alloc = P.leaf_lo + P.n_valid;
+    const int64_t s0 = (item - J.item_base) * AX_PER_WAVE;
+    const int q = lane / 6, k = lane - 6 * (lane / 6);
+    const int64_t s = s0 + q;
+    WorkCount wc;
+    bool free_ray = false;
+    if (q < AX_PER_WAVE && s < J.n_samples) {
+        const float ox = J.origin[3 * s], oy = J.origin[3 * s + 1], oz = J.origin[3 * s + 2];
+        const float nx = J.normal[3 * s], ny = J.normal[3 * s + 1], nz = J.normal[3 * s + 2];
+        const float4 l = a.dirs[k];
+        const float q0 = nx * l.x, q1 = ny * l.y, q2 = nz * l.z;
+        const float nd = (q0 + q1) + q2;
+        if (!(nd < 0.0f))
+            free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, l.x, l.y, l.z, stk[wv], lane,
+                                                        a.err, J.n_nodes_alloc, n_tris_alloc, wc);
+    }
+    const uint64_t m = __ballot(free_ray);
+    if (lane < AX_PER_WAVE && s0 + lane < J.n_samples) J.bits[s0 + lane] = (uint32_t)(m >> (6 * lane)) & 63u;
     if (STATS) {
         atomicAdd(a.work, (unsigned long long)wc.nodes);
         atomicAdd(a.work + 1, (unsigned long long)wc.tris);
@@ -267,9 +297,16 @@ __global__ void k_popcount_rows(const uint32_t *bits, int64_t n, int32_t W, uint
 
 template <int RPW, int STACK, bool STATS>
 static hipError_t launch_cast(const CastArgs &args, hipStream_t s) {
-    const int64_t blocks = (args.n_items + 3) / 4;
-    if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-    k_cast<RPW, STACK, STATS><<<(unsigned)blocks, 256, 0, s>>>(args);
+    if (args.kind == 1) {
+        const int64_t blocks = (args.n_items + 3) / 4;   // four items per block
+        if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+        k_cast_axes<STACK, STATS><<<(unsigned)blocks, 256, 0, s>>>(args);
+    } else {
+        const int64_t blocks = args.n_items;             // one sample per block
+        if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+        const size_t lds = sizeof(int) * (4 * STACK * 64 + (size_t)args.W);
+        k_cast_rows<RPW, STACK, STATS><<<(unsigned)blocks, 256, lds, s>>>(args);
+    }
     return hipGetLastError();
 }
 
@@ -289,6 +326,10 @@ hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, bool stats, hi
         case 256: return launch_rpw<256, false>(a, stack, s);
         default: return launch_rpw<64, false>(a, stack, s);
     }
+}
+
+int64_t cast_items(int32_t kind, int64_t n_samples) {
+    return kind == 1 ? (n_samples + AX_PER_WAVE - 1) / AX_PER_WAVE : n_samples;
 }
 
 // The rays as the cast forms them: out[i][j] = (o, d).
@@ -327,8 +368,10 @@ extern "C" hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *c
         return ctx->fail(HRA_ERR_INVALID_ARG, "rays_per_wave must be 64, 128 or 256");
     if (cfg->stack_depth != 16 && cfg->stack_depth != 24 && cfg->stack_depth != 32)
         return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth must be 16, 24 or 32");
+    if (cfg->leaf_size < 0 || cfg->leaf_size > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 0..8");
     ctx->cast_rpw = cfg->rays_per_wave;
     ctx->cast_stack = cfg->stack_depth;
+    if (cfg->leaf_size) ctx->leaf_default = cfg->leaf_size;
     return HRA_OK;
 }
 
@@ -336,6 +379,7 @@ extern "C" hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *c
     if (!ctx || !cfg) return HRA_ERR_INVALID_ARG;
     cfg->rays_per_wave = ctx->cast_rpw;
     cfg->stack_depth = ctx->cast_stack;
+    cfg->leaf_size = ctx->leaf_default;
     return HRA_OK;
 }
 
@@ -372,14 +416,14 @@ static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, co
     a.n_jobs = 1;
     a.job0 = make_cast_job(bvh, part, samples->origin, samples->normal, d_bits, samples->n, 0);
     a.dirs = table;
+    a.dirs_order = dirs.kind == HRA_DIRS_AXES6 ? table : table + dirs.n;
     a.n_dirs = dirs.n;
     a.kind = dirs.kind == HRA_DIRS_AXES6 ? 1 : 0;
     a.W = (dirs.n + 31) / 32;
-    a.chunks = (dirs.n + rpw - 1) / rpw;
-    a.n_items = samples->n * (int64_t)a.chunks;
+    a.n_items = cast_items(a.kind, samples->n);
     a.err = ctx->d_err;
     a.work = work;
-    if ((a.n_items + 3) / 4 >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call");
+    if (a.n_items >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many samples for one call");
     HRA_HIP(launch_cast_any(a, rpw, ctx->cast_stack, work != nullptr, s));
     if (d_counts) {
         k_popcount_rows<<<blocks_for(samples->n, 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);

@@ -101,6 +101,7 @@ struct hra_ctx {
     hipStream_t own = nullptr;        // internal stream for table builds
     int32_t cast_rpw = 64;            // directions per wave work item
     int32_t cast_stack = 24;          // LDS stack entries per lane
+    int32_t leaf_default = 4;         // leaf size of builds whose options give 0
     std::string err;
     std::map<std::pair<int, int>, float4 *> dir_tables;  // (kind, n) -> device float4 [n]
     std::mutex mu;
@@ -181,12 +182,12 @@ struct CastArgs {
     const CastJob *jobs;       // device table, or null: job0 only
     int32_t n_jobs;
     CastJob job0;
-    const float4 *dirs;
+    const float4 *dirs;        // canonical order
+    const float4 *dirs_order;  // hemisphere: traversal order, w = canonical index (int bits)
     int32_t n_dirs;
     int32_t kind;              // 0: rotate hemisphere onto the normal, 1: world axes (cull n.D < 0)
     int32_t W;                 // words per row
-    int32_t chunks;            // work items per sample
-    int64_t n_items;
+    int64_t n_items;           // cast_items(kind, samples)
     uint32_t *err;
     unsigned long long *work;  // instrumented variant: {node fetches, triangle tests}
 };
@@ -198,6 +199,21 @@ hipError_t launch_sample(const SampleJob *d_jobs, int32_t n_jobs, const SampleJo
 CastJob make_cast_job(const hra_bvh *bvh, int32_t part, const float *origin, const float *normal, uint32_t *bits,
                       int64_t n_samples, int64_t item_base);
 hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, bool stats, hipStream_t s);
+// Work items of a cast over n samples: one per sample (hemisphere), one per
+// ten samples (six axes).
+int64_t cast_items(int32_t kind, int64_t n_samples);
+
+// ---------------------------------------------------------------- builds
+// A build in three steps, so that it can run in memory set aside earlier
+// (batch plans, graphs, the server): check and lay out the meshes, allocate
+// the hierarchy's arrays, then enqueue kernels only, reading the mesh table
+// from the workspace (build_ws_mesh_table) that the caller has filled.
+hra_status check_meshes(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, int32_t leaf,
+                        std::vector<MeshIn> *hm, int64_t *T_out);
+hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out);
+size_t build_ws_bytes(int64_t T, int n_parts);
+MeshIn *build_ws_mesh_table(void *ws, int64_t T, int n_parts);
+hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws, hipStream_t s);
 
 // ---------------------------------------------------------------- helpers
 hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out);

@@ -1,6 +1,7 @@
 // Context, error word, direction tables.
 #include "common.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -40,6 +41,56 @@ __global__ void k_axes6(float4 *out) {
     out[j] = make_float4(ax == 0 ? s : 0.0f, ax == 1 ? s : 0.0f, ax == 2 ? s : 0.0f, 0.0f);
 }
 
+// Index of cell (x, y) along the Hilbert curve over a 2^16 x 2^16 grid
+// (the usual quadrant-rotation construction).
+static uint64_t hilbert_index(uint32_t x, uint32_t y) {
+    uint64_t d = 0;
+    for (uint32_t half = 1u << 15; half > 0; half >>= 1) {
+        const uint32_t rx = (x & half) ? 1u : 0u, ry = (y & half) ? 1u : 0u;
+        d += (uint64_t)half * half * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = (half - 1) - (x & (half - 1));
+                y = (half - 1) - (y & (half - 1));
+            }
+            const uint32_t tmp = x;
+            x = y;
+            y = tmp;
+        }
+        x &= half - 1;
+        y &= half - 1;
+    }
+    return d;
+}
+
+// Traversal order of a hemisphere table: directions sorted along a Hilbert
+// curve over their equal-area (Lambert azimuthal) projection, so runs of 64
+// consecutive entries are compact patches of the hemisphere.  w holds the
+// canonical index.  Only the order of work depends on it, never a result.
+static std::vector<float4> traversal_order(const std::vector<float4> &dirs) {
+    const size_t n = dirs.size();
+    std::vector<std::pair<uint64_t, int32_t>> key(n);
+    for (size_t j = 0; j < n; ++j) {
+        const double x = dirs[j].x, y = dirs[j].y, z = dirs[j].z;
+        const double k = std::sqrt(2.0 / (1.0 + (z > 0.0 ? z : 0.0)));
+        const double u = (k * x / std::sqrt(2.0) + 1.0) * 0.5, v = (k * y / std::sqrt(2.0) + 1.0) * 0.5;
+        auto q = [](double t) {
+            const double c = std::floor(t * 65535.0 + 0.5);
+            return (uint32_t)(c < 0.0 ? 0.0 : (c > 65535.0 ? 65535.0 : c));
+        };
+        key[j] = {hilbert_index(q(u), q(v)), (int32_t)j};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<float4> out(n);
+    for (size_t i = 0; i < n; ++i) {
+        float4 d = dirs[key[i].second];
+        int32_t j = key[i].second;
+        std::memcpy(&d.w, &j, sizeof(j));
+        out[i] = d;
+    }
+    return out;
+}
+
 hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out) {
     if (dirs.kind == HRA_DIRS_AXES6) {
         if (dirs.n != 6) return ctx->fail(HRA_ERR_INVALID_ARG, "AXES6 needs n = 6");
@@ -55,9 +106,12 @@ hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out) {
         *out = it->second;
         return HRA_OK;
     }
+    // hemisphere tables hold the canonical order in [0, n) and the traversal
+    // order in [n, 2n)
     float4 *p = nullptr;
-    HRA_HIP(hipMalloc(&p, sizeof(float4) * dirs.n));
-    if (dirs.kind == HRA_DIRS_AXES6)
+    const bool hemi = dirs.kind == HRA_DIRS_HEMI_FIBONACCI;
+    HRA_HIP(hipMalloc(&p, sizeof(float4) * dirs.n * (hemi ? 2 : 1)));
+    if (!hemi)
         k_axes6<<<1, 64, 0, ctx->own>>>(p);
     else
         k_fibonacci<<<blocks_for(dirs.n, 256), 256, 0, ctx->own>>>(dirs.n, p);
@@ -65,6 +119,12 @@ hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out) {
     // tables are built once per context on its own stream; later work on any
     // stream may read them, so wait here
     HRA_HIP(hipStreamSynchronize(ctx->own));
+    if (hemi) {
+        std::vector<float4> h(dirs.n);
+        HRA_HIP(hipMemcpy(h.data(), p, sizeof(float4) * dirs.n, hipMemcpyDeviceToHost));
+        const std::vector<float4> o = traversal_order(h);
+        HRA_HIP(hipMemcpy(p + dirs.n, o.data(), sizeof(float4) * dirs.n, hipMemcpyHostToDevice));
+    }
     ctx->dir_tables[key] = p;
     *out = p;
     return HRA_OK;

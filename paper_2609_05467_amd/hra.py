@@ -48,7 +48,7 @@ class Dirs(C.Structure):
 
 
 class CastConfig(C.Structure):
-    _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32)]
+    _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32), ("leaf_size", C.c_int32)]
 
 
 class DirStats(C.Structure):
@@ -85,8 +85,17 @@ class PartRequest(C.Structure):
 
 
 class BatchOpts(C.Structure):
-    _fields_ = [("n_dirs", C.c_int32), ("leaf_size", C.c_int32), ("offset_frac", C.c_float),
-                ("thresholds", C.POINTER(Thresholds))]
+    _fields_ = [("n_dirs", C.c_int32), ("leaf_size", C.c_int32), ("rays_per_wave", C.c_int32),
+                ("stack_depth", C.c_int32), ("offset_frac", C.c_float), ("thresholds", C.POINTER(Thresholds))]
+
+
+class TunePoint(C.Structure):
+    _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32), ("leaf_size", C.c_int32),
+                ("ms", C.c_float)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("n_points", C.c_int32), ("best", C.c_int32), ("points", TunePoint * 27)]
 
 
 class PartResult(C.Structure):
@@ -135,6 +144,14 @@ def lib():
                                     C.c_int),
             "hra_batch_run": ([P, C.POINTER(PartRequest), i32, C.POINTER(BatchOpts), C.POINTER(PartResult), P, P],
                               C.c_int),
+            "hra_plan_create": ([P, C.POINTER(PartRequest), i32, C.POINTER(BatchOpts), C.POINTER(P)], C.c_int),
+            "hra_plan_run": ([P, i32, C.POINTER(PartResult), P, P], C.c_int),
+            "hra_plan_stage_ms": ([P, C.POINTER(C.c_float)], C.c_int),
+            "hra_plan_bytes": ([P], i64),
+            "hra_plan_bits": ([P], P),
+            "hra_plan_destroy": ([P], None),
+            "hra_autotune": ([P, C.POINTER(PartRequest), i32, C.POINTER(BatchOpts), i32, C.POINTER(TuneReport), P],
+                             C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -149,7 +166,8 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_set_cast_config", "hra_get_cast_config", "hra_cast_work", "hra_debug_rays", "hra_dirstats_bytes",
            "hra_dominant_axes", "hra_classify", "hra_min_setups", "hra_histogram_peaks", "hra_build_bvh_batch",
            "hra_bvh_parts", "hra_bvh_part_info", "hra_sample_part", "hra_cast_part", "hra_min_setups_part",
-           "hra_batch_run"]
+           "hra_batch_run", "hra_plan_create", "hra_plan_run", "hra_plan_stage_ms", "hra_plan_bytes", "hra_plan_bits",
+           "hra_plan_destroy", "hra_autotune"]
 
 
 def _ptr(t):
@@ -219,10 +237,7 @@ class Context:
                                               _stream(stream), C.byref(out)))
         return Bvh(self, out, keep, stream)
 
-    def batch_run(self, parts, n_dirs, leaf_size=0, offset_frac=0.0, thresholds=None, bits=None, stream=None):
-        """The whole path for many parts: `parts` is a list of dicts with
-        verts, tris (device or host), n_samples, seed, tool_length.  Returns
-        one result dict per part (classification and setups)."""
+    def _requests(self, parts):
         n = len(parts)
         reqs = (PartRequest * n)()
         keep = []
@@ -232,11 +247,44 @@ class Context:
             keep += [v, t]
             reqs[i] = PartRequest(Mesh(_ptr(v), v.shape[0], _ptr(t), t.shape[0]), int(q["n_samples"]),
                                   int(q["seed"]), float(q["tool_length"]))
+        return reqs, keep
+
+    @staticmethod
+    def _batch_opts(n_dirs, leaf_size=0, rays_per_wave=0, stack_depth=0, offset_frac=0.0, thresholds=None):
         th = Thresholds(*thresholds) if thresholds is not None else None
-        opts = BatchOpts(n_dirs, leaf_size, offset_frac, C.pointer(th) if th is not None else None)
-        res = (PartResult * n)()
-        self._check(lib().hra_batch_run(self.ptr, reqs, n, C.byref(opts), res, _ptr(bits), _stream(stream)))
-        return [{"class": _class_dict(r.cls), "setups": _setup_dict(r.setups)} for r in res]
+        o = BatchOpts(n_dirs, leaf_size, rays_per_wave, stack_depth, offset_frac,
+                      C.pointer(th) if th is not None else None)
+        return o, th
+
+    def batch_run(self, parts, n_dirs, leaf_size=0, offset_frac=0.0, thresholds=None, bits=None, stream=None):
+        """The whole path for many parts: `parts` is a list of dicts with
+        verts, tris (device or host), n_samples, seed, tool_length.  Returns
+        one result dict per part (classification and setups)."""
+        reqs, keep = self._requests(parts)
+        opts, th = self._batch_opts(n_dirs, leaf_size, 0, 0, offset_frac, thresholds)
+        res = (PartResult * len(parts))()
+        self._check(lib().hra_batch_run(self.ptr, reqs, len(parts), C.byref(opts), res, _ptr(bits), _stream(stream)))
+        return [_result_dict(r) for r in res]
+
+    def plan(self, parts, n_dirs, leaf_size=0, rays_per_wave=0, stack_depth=0, offset_frac=0.0, thresholds=None):
+        """A batch plan (all buffers allocated once; runs may replay a graph)."""
+        reqs, keep = self._requests(parts)
+        opts, th = self._batch_opts(n_dirs, leaf_size, rays_per_wave, stack_depth, offset_frac, thresholds)
+        out = C.c_void_p()
+        self._check(lib().hra_plan_create(self.ptr, reqs, len(parts), C.byref(opts), C.byref(out)))
+        return Plan(self, out, len(parts), sum(int(q["n_samples"]) for q in parts), n_dirs, keep)
+
+    def autotune(self, parts, n_dirs, reps=2, offset_frac=0.0, stream=None):
+        """Sweep (rays per wave, stack depth, leaf size) on this batch; the
+        fastest point becomes the context's cast configuration."""
+        reqs, keep = self._requests(parts)
+        opts, th = self._batch_opts(n_dirs, 0, 0, 0, offset_frac, None)
+        rep = TuneReport()
+        self._check(lib().hra_autotune(self.ptr, reqs, len(parts), C.byref(opts), reps, C.byref(rep),
+                                       _stream(stream)))
+        pts = [{"rays_per_wave": p.rays_per_wave, "stack_depth": p.stack_depth, "leaf_size": p.leaf_size,
+                "ms": p.ms} for p in rep.points[:rep.n_points]]
+        return {"points": pts, "best": pts[rep.best]}
 
     def dirs_table(self, n, kind=DIRS_HEMI):
         import numpy as np
@@ -244,13 +292,13 @@ class Context:
         self._check(lib().hra_dirs_table(self.ptr, Dirs(kind, n), out.ctypes.data_as(C.c_void_p)))
         return out
 
-    def set_cast_config(self, rays_per_wave=64, stack_depth=24):
-        self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth))))
+    def set_cast_config(self, rays_per_wave=64, stack_depth=24, leaf_size=0):
+        self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth, leaf_size))))
 
     def cast_config(self):
         c = CastConfig()
         self._check(lib().hra_get_cast_config(self.ptr, C.byref(c)))
-        return c.rays_per_wave, c.stack_depth
+        return c.rays_per_wave, c.stack_depth, c.leaf_size
 
     # ---------------------------------------------------------------- samples
     def alloc_samples(self, n):
@@ -350,6 +398,43 @@ def _class_dict(rep):
     return {"access": rep.access, "shares": list(rep.share), "conc": rep.mean_conc, "n_blind": rep.n_blind,
             "n_unobstructed": rep.n_unobstructed, "multi_axis": bool(rep.multi_axis), "tripped": rep.tripped,
             "near_tie": bool(rep.near_tie)}
+
+
+def _result_dict(r):
+    return {"class": _class_dict(r.cls), "setups": _setup_dict(r.setups)}
+
+
+class Plan:
+    """A batch plan: run() returns one result dict per part."""
+
+    def __init__(self, ctx, ptr, n_parts, n_samples, n_dirs, keep):
+        self.ctx, self.ptr, self.n_parts, self.n_samples, self.n_dirs = ctx, ptr, n_parts, n_samples, n_dirs
+        self._keep = keep
+
+    def run(self, graph=False, bits=None, stream=None):
+        res = (PartResult * self.n_parts)()
+        self.ctx._check(lib().hra_plan_run(self.ptr, 1 if graph else 0, res, _ptr(bits), _stream(stream)))
+        return [_result_dict(r) for r in res]
+
+    def stage_ms(self):
+        ms = (C.c_float * 6)()
+        self.ctx._check(lib().hra_plan_stage_ms(self.ptr, ms))
+        return dict(zip(("build", "sample", "cast", "stats", "axes", "setups"), list(ms)))
+
+    @property
+    def bytes(self):
+        return int(lib().hra_plan_bytes(self.ptr))
+
+    def destroy(self):
+        if self.ptr:
+            lib().hra_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def _setup_dict(rep):

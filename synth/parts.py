@@ -1014,17 +1014,39 @@ def batch_sizes(n=64, lo=2_000, hi=500_000, seed=400):
     return [int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))))) for _ in range(n)]
 
 
-def batch_parts(n=64, lo=2_000, hi=500_000, seed0=400):
-    sizes = batch_sizes(n, lo, hi, seed0)
-    out = []
-    for i, tt in enumerate(sizes):
-        fam = "pockets" if i % 3 else "multiaxis"
-        dims = None
-        if tt < 20_000:
-            dims = (100.0, 80.0, 50.0)
-        out.append(procedural_part(seed0 + i, tt, fam, dims=dims,
-                                   n_features=(6, 10) if tt < 20_000 else None))
-    return out
+def batch_part(i, n=64, lo=2_000, hi=500_000, seed0=400):
+    """Part i of the batch: seed seed0 + i, triangle target log-uniform in
+    [lo, hi]; every third part is of the multi-axis family."""
+    tt = batch_sizes(n, lo, hi, seed0)[i]
+    fam = "pockets" if i % 3 else "multiaxis"
+    dims = (100.0, 80.0, 50.0) if tt < 20_000 else None
+    return procedural_part(seed0 + i, tt, fam, dims=dims, n_features=(6, 10) if tt < 20_000 else None)
+
+
+def batch_parts(n=64, lo=2_000, hi=500_000, seed0=400, workers=1):
+    """The batch of uneven parts (optionally generated by `workers`
+    processes; the parts do not depend on it)."""
+    if workers <= 1:
+        return [batch_part(i, n, lo, hi, seed0) for i in range(n)]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    from functools import partial
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        return list(ex.map(partial(batch_part, n=n, lo=lo, hi=hi, seed0=seed0), range(n)))
+
+
+def surface_area(mesh):
+    v = mesh.verts.astype(np.float64)
+    t = mesh.tris
+    c = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+    return 0.5 * float(np.linalg.norm(c, axis=1).sum())
+
+
+def batch_samples(meshes, smin=1_000, smax=50_000):
+    """Samples per part proportional to surface area, the largest part
+    getting smax, clamped to [smin, smax]."""
+    a = np.array([surface_area(m) for m in meshes])
+    return [int(min(smax, max(smin, round(smax * x / a.max())))) for x in a]
 
 
 def planar_overlap(mesh: Mesh, res=0.25, min_group=1):

@@ -161,3 +161,78 @@ def test_batch_run_single_part_and_limits(ctx, meshes):
         ctx.batch_run([{"verts": m.verts, "tris": m.tris, "n_samples": 0, "seed": 4, "tool_length": 50.0}], 128)
     with pytest.raises(hra.HraError):
         ctx.batch_run([], 128)
+
+
+def _reqs(ms, base_n=400):
+    return [{"verts": m.verts, "tris": m.tris, "n_samples": base_n + 137 * p, "seed": 50 + p,
+             "tool_length": 25.0 + 3 * p} for p, m in enumerate(ms)]
+
+
+@pytest.mark.parametrize("rpw,stack,leaf", [(64, 24, 4), (128, 16, 2), (256, 32, 8)])
+def test_plan_eager_matches_batch_run(ctx, meshes, rpw, stack, leaf):
+    import torch
+    reqs = _reqs(meshes)
+    N = 777
+    W = (N + 31) // 32
+    S = sum(r["n_samples"] for r in reqs)
+    _say("plan eager", rpw, stack, leaf)
+    b0 = torch.empty((S, W), dtype=torch.int32, device=ctx.device)
+    b1 = torch.empty_like(b0)
+    want = ctx.batch_run(reqs, N, leaf_size=4, bits=b0)
+    pl = ctx.plan(reqs, N, leaf_size=leaf, rays_per_wave=rpw, stack_depth=stack)
+    got = pl.run(graph=False, bits=b1)
+    assert got == want
+    assert torch.equal(b0, b1)
+    ms = pl.stage_ms()
+    assert all(v >= 0 for v in ms.values()) and ms["cast"] > 0
+    assert pl.bytes > 0
+    pl.destroy()
+
+
+def test_plan_graph_replays_match_eager(ctx, meshes):
+    """Capture once, replay several times with other eager work and
+    synchronisations between the replays; every replay equals the eager run."""
+    import torch
+    reqs = _reqs(meshes, 300)
+    N = 512
+    S = sum(r["n_samples"] for r in reqs)
+    pl = ctx.plan(reqs, N)
+    be = torch.empty((S, N // 32), dtype=torch.int32, device=ctx.device)
+    want = pl.run(graph=False, bits=be)
+    m = meshes[0]
+    b = ctx.build_bvh(m.verts, m.tris)
+    for k in range(4):
+        _say("graph replay", k)
+        bg = torch.full((S, N // 32), -1, dtype=torch.int32, device=ctx.device)
+        got = pl.run(graph=True, bits=bg)
+        torch.cuda.synchronize()
+        assert got == want, k
+        assert torch.equal(bg, be), k
+        # eager work between replays
+        s = ctx.sample_surface(b, 200, 7 + k)
+        ctx.cast(b, s, 256)
+        torch.cuda.synchronize()
+    b.release()
+    pl.destroy()
+
+
+def test_autotune_picks_a_point_and_keeps_results(ctx, meshes):
+    reqs = _reqs(meshes[:3], 300)
+    old = ctx.cast_config()
+    _say("autotune")
+    rep = ctx.autotune(reqs, 256, reps=1)
+    assert len(rep["points"]) == 27
+    best = rep["best"]
+    assert best["ms"] == min(p["ms"] for p in rep["points"])
+    assert ctx.cast_config() == (best["rays_per_wave"], best["stack_depth"], best["leaf_size"])
+    # results of a single-part cast do not depend on the tuned shape
+    m = meshes[0]
+    b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.sample_surface(b, 300, 3)
+    x1, _ = ctx.cast(b, s, 256)
+    ctx.set_cast_config(*old)
+    b2 = ctx.build_bvh(m.verts, m.tris)
+    x2, _ = ctx.cast(b2, s, 256)
+    assert np.array_equal(_u32(x1), _u32(x2))
+    b.release()
+    b2.release()
