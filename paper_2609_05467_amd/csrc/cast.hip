@@ -86,10 +86,14 @@ __device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy,
     return hs == s;
 }
 
-// Slab test, conservative: exact-ray intersections are never rejected.  A
-// zero direction component is replaced by +-1e30 in the inverse so no NaN
-// arises; the far distance is widened by 4e-7 relative (more than the
-// rounding of (bound - o) * inv, cf. Ize 2013, "Robust BVH Ray Traversal").
+// Slab test, conservative: exact-ray intersections are never rejected.  The
+// inverse direction comes from the hardware reciprocal (at most 1 ulp off);
+// a component below 1e-30 in magnitude is replaced by +-1e30 in the inverse,
+// so no NaN or infinity arises.  Each distance (bound - o) * inv then carries
+// at most 4 units of 2^-24 relative error (subtraction, reciprocal,
+// product), so tmin and tmax together 8, and the product with the widening
+// factor one more: the far distance is widened by 6e-7 > 9 * 2^-24 (cf. Ize
+// 2013, "Robust BVH Ray Traversal").
 __device__ inline bool slab(float lx, float ly, float lz, float hx, float hy, float hz, float ox, float oy, float oz,
                             float ix, float iy, float iz, float &tn) {
     const float tx0 = (lx - ox) * ix, tx1 = (hx - ox) * ix;
@@ -98,7 +102,25 @@ __device__ inline bool slab(float lx, float ly, float lz, float hx, float hy, fl
     const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
     tn = tmin;
-    return tmin <= tmax * 1.0000004f;
+    return tmin <= tmax * 1.0000006f;
+}
+
+// 1/x for the slab test (see above).
+__device__ inline float safe_rcp(float x) {
+    return fabsf(x) > 1e-30f ? __builtin_amdgcn_rcpf(x) : copysignf(1e30f, x);
+}
+
+// The hierarchy lives in global memory: 16-byte loads through a global
+// address-space pointer (global loads rather than flat ones).
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+__device__ inline float4 gload_f4(const void *p) {
+    const v4f v = *(const __attribute__((address_space(1))) v4f *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline int4 gload_i4(const void *p) {
+    const v4i v = *(const __attribute__((address_space(1))) v4i *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
 }
 
 struct WorkCount {
@@ -117,7 +139,7 @@ __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, f
     for (int k = 0; k < cnt; ++k) {
         const float4 *t = tris + 3 * (int64_t)(first + k);
         if (STATS) ++wc.tris;
-        if (tri_hit(ox, oy, oz, dx, dy, dz, t[0], t[1], t[2])) return true;
+        if (tri_hit(ox, oy, oz, dx, dy, dz, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2))) return true;
     }
     return false;
 }
@@ -131,9 +153,7 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
                                 float oy, float oz, float dx, float dy, float dz, int *lds, int lane, uint32_t *err,
                                 int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
     if (is_leaf(root)) return leaf_hit<STATS>(tris, root, ox, oy, oz, dx, dy, dz, n_tris_alloc, err, wc);
-    const float ix = dx != 0.0f ? 1.0f / dx : copysignf(1e30f, dx);
-    const float iy = dy != 0.0f ? 1.0f / dy : copysignf(1e30f, dy);
-    const float iz = dz != 0.0f ? 1.0f / dz : copysignf(1e30f, dz);
+    const float ix = safe_rcp(dx), iy = safe_rcp(dy), iz = safe_rcp(dz);
     int spill[SPILL];
     int sp = 0;
     int32_t node = root;
@@ -145,8 +165,8 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
         }
         const Node *nd = nodes + node;
         if (STATS) ++wc.nodes;
-        const float4 A = nd->a, B = nd->b, C = nd->c;
-        const int4 D = nd->d;
+        const float4 A = gload_f4(&nd->a), B = gload_f4(&nd->b), C = gload_f4(&nd->c);
+        const int4 D = gload_i4(&nd->d);
         float t0, t1;
         const bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, ox, oy, oz, ix, iy, iz, t0);
         const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, ox, oy, oz, ix, iy, iz, t1);
@@ -198,9 +218,11 @@ __device__ inline CastJob job_of(const CastArgs &a, int64_t item) {
 // at the direction's canonical index; the finished row is stored with
 // coalesced writes.  The item index is the block index, uniform over the
 // workgroup, so both barriers are reached by every thread, and the kernel
-// has no cross-lane operation.
+// has no cross-lane operation.  Six waves per SIMD (at most 80 VGPRs, a few
+// spilled) measured fastest: the traversal is latency-bound, so occupancy
+// beats registers.
 template <int RPW, int STACK, bool STATS>
-__global__ __launch_bounds__(256) void k_cast_rows(CastArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cast_rows(CastArgs a) {
     extern __shared__ int dyn_lds[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t item = blockIdx.x;
