@@ -31,6 +31,8 @@ WORKLOADS = {
     "multiaxis_1m": ("multiaxis_1m", 250_000, 2048),
     # 64 uneven parts (2k-500k triangles), samples by area in [1k, 50k]
     "batch64": ("batch64", None, 1024),
+    # Poisson arrivals of analyses of parts drawn from the batch64 pool
+    "serve": ("batch64", None, 1024),
 }
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 NODE_BYTES, TRI_BYTES = 64, 48  # one interior-node record, one leaf triangle
@@ -93,6 +95,9 @@ def main():
     ap.add_argument("--stack", type=int, default=24)
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--autotune", action="store_true", help="batch64: sweep the launch shape first")
+    ap.add_argument("--rates", default="20,100,200", help="serve: arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=600, help="serve: requests per rate and mode")
+    ap.add_argument("--budget-gib", type=float, default=200.0, help="serve: device memory budget")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes generating the batch parts (before any GPU work)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -106,6 +111,8 @@ def main():
 
     if args.workload == "batch64":
         return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     import numpy as np
     import torch
@@ -346,6 +353,90 @@ def run_batch(args):
         out["autotune"] = tune
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def serve_run(hra, pool, counts, schedule, N, mode, budget, tool):
+    """Submit `schedule` [(t_arrival_s, part index, seed)] at its arrival
+    times; returns per-request records and the server statistics."""
+    sv = hra.Server(0, n_dirs=N, mode=mode, budget_bytes=budget)
+    tickets = []
+    t0 = time.perf_counter()
+    for (ta, k, seed) in schedule:
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        v, t = pool[k]
+        tickets.append(sv.submit(k, v, t, counts[k], seed, tool))
+    recs = [sv.wait(tk, 600_000) for tk in tickets]
+    st = sv.stats()
+    sv.close()
+    return recs, st
+
+
+def serve_summary(recs, N, counts, schedule):
+    import numpy as np
+    ok = [r for r in recs if r and r["status"] == 0]
+    lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in ok])
+    t_first = min(r["t_submit_ns"] for r in ok)
+    t_last = max(r["t_done_ns"] for r in ok)
+    span = (t_last - t_first) * 1e-9
+    rays = sum(counts[k] for (_, k, _) in schedule) * N
+    return {"requests": len(recs), "ok": len(ok), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "parts_per_s": len(ok) / span, "rays_per_s": rays / span, "span_s": span,
+            "resident_hit_frac": float(np.mean([r["resident_hit"] for r in ok])),
+            "mean_batch": float(np.mean([r["batch_size"] for r in ok]))}
+
+
+def run_serve(args):
+    """Poisson arrivals of part analyses (Zipf(1.1) popularity over the
+    64-part pool, samples by area) served with continuous batching and
+    resident hierarchies, against the plain mode (one request at a time,
+    rebuilt every time), on the same arrival schedule per rate."""
+    import numpy as np
+    from synth import parts
+    N = WORKLOADS["serve"][2]
+    log(f"[bench] generating the 64-part pool with {args.workers} processes")
+    meshes = parts.batch_parts(workers=args.workers)
+    counts = parts.batch_samples(meshes)
+    import torch
+    from paper_2609_05467_amd import hra
+    # meshes in pinned host memory, as a client would hand them over
+    pool = [(torch.from_numpy(m.verts).pin_memory(), torch.from_numpy(m.tris).pin_memory()) for m in meshes]
+    rng = np.random.default_rng(5)
+    zipf = 1.0 / np.arange(1, len(meshes) + 1) ** 1.1
+    zipf /= zipf.sum()
+    order = rng.permutation(len(meshes))          # popularity rank -> part
+    budget = int(args.budget_gib * 2 ** 30)
+    rates = [float(x) for x in args.rates.split(",")]
+    out_rates = []
+    for lam in rates:
+        gaps = rng.exponential(1.0 / lam, args.requests)
+        ta = np.cumsum(gaps) - gaps[0]
+        ks = order[rng.choice(len(meshes), args.requests, p=zipf)]
+        schedule = [(float(t), int(k), 9000 + i) for i, (t, k) in enumerate(zip(ta, ks))]
+        row = {"rate": lam}
+        for name, mode in (("served", hra.SERVE_CONTINUOUS), ("plain", hra.SERVE_PLAIN)):
+            log(f"[bench] rate {lam}/s, {args.requests} requests, {name}")
+            recs, st = serve_run(hra, pool, counts, schedule, N, mode, budget, args.tool_length)
+            row[name] = serve_summary(recs, N, counts, schedule)
+            row[name]["builds"] = st["builds"]
+            row[name]["evictions"] = st["evictions"]
+            log(f"[bench]   p50 {row[name]['p50_ms']:.2f} ms p99 {row[name]['p99_ms']:.2f} ms "
+                f"{row[name]['parts_per_s']:.1f} parts/s")
+        out_rates.append(row)
+    top = out_rates[-1]
+    out = {
+        "metric": "p99 per-part latency, served",
+        "value": top["served"]["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "ms_per_step": top["served"]["mean_ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serve", "pool_parts": len(meshes), "directions": N, "popularity": "zipf 1.1",
+                   "rates_per_s": rates, "requests_per_rate": args.requests, "budget_gib": args.budget_gib,
+                   "samples_min_max": [min(counts), max(counts)]},
+        "rates": out_rates,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

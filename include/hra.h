@@ -398,6 +398,86 @@ typedef struct {
 hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, int32_t n_parts, const hra_batch_opts *opts,
                         int32_t reps, hra_tune_report *out, void *stream);
 
+/* -------------------------------------------------------------- server */
+
+/* Serving part analyses as they arrive (the method's use case is interactive
+ * feedback while a part is designed, Section 1).  A server owns a context
+ * and a worker thread on one device.  Continuous mode: requests are
+ * admitted in arrival order while the device memory they need (a resident
+ * hierarchy, build scratch, samples, bitmasks, statistics) fits the budget,
+ * evicting resident hierarchies that no request uses, least recently used
+ * first; hierarchies of new parts are built on a stream of their own while
+ * earlier batches run; all admitted requests ready at a launch go into one
+ * batch (one launch per stage, as hra_batch_run), with up to max_inflight
+ * batches on the device.  Plain mode: one request at a time in arrival
+ * order, built, cast and finished before the next starts, nothing kept
+ * resident.  Each result equals that of the single-part calls on the same
+ * inputs. */
+typedef struct hra_server hra_server;
+
+enum { HRA_SERVE_CONTINUOUS = 0, HRA_SERVE_PLAIN = 1 };
+
+typedef struct {
+    int64_t budget_bytes;    /* device memory for hierarchies and admitted work; 0 = 200 GiB */
+    int32_t mode;            /* HRA_SERVE_CONTINUOUS or HRA_SERVE_PLAIN */
+    int32_t max_batch;       /* requests per launch batch, 1..255; 0 = 64 */
+    int32_t max_inflight;    /* batches on the device at once, 1..4; 0 = 2 */
+    int32_t keep_resident;   /* continuous mode: keep hierarchies after their requests (LRU) */
+    int32_t n_dirs;          /* hemisphere directions of every analysis */
+    int32_t leaf_size;       /* 0 = the context default (4) */
+    float offset_frac;       /* 0 = 1e-4 */
+    const hra_thresholds *thresholds;   /* NULL = defaults; copied */
+} hra_server_opts;
+
+typedef struct {
+    uint64_t part_key;       /* equal keys name the same mesh: its hierarchy is reused while resident */
+    const float *h_verts;    /* host float [n_verts][3] (pinned memory uploads fastest) */
+    int64_t n_verts;
+    const int32_t *h_tris;   /* host int32 [n_tris][3] */
+    int64_t n_tris;
+    int64_t n_samples;       /* area-weighted samples (>= 1) */
+    uint64_t seed;
+    double tool_length;      /* mm */
+} hra_request;
+
+typedef struct {
+    hra_status status;       /* HRA_OK, HRA_ERR_BAD_MESH (index out of range or no nonzero-area
+                                triangle), HRA_ERR_OVER_BUDGET (cannot fit even alone),
+                                HRA_ERR_DEVICE */
+    int32_t resident_hit;    /* its hierarchy was resident and built when it was admitted */
+    int32_t batch_size;      /* requests in its launch batch */
+    int32_t pad;
+    int64_t batch_id;
+    int64_t t_submit_ns, t_admit_ns, t_launch_ns, t_done_ns;   /* hra_now_ns clock */
+    hra_part_result result;
+} hra_request_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, batches, builds, evictions, resident_hits;
+    int64_t resident_bytes, used_bytes, peak_used_bytes;
+    int32_t resident_parts, pending, inflight, pad;
+} hra_server_stats;
+
+/* Monotonic clock of the server's time stamps, in nanoseconds. */
+int64_t hra_now_ns(void);
+hra_status hra_server_create(int32_t device, const hra_server_opts *opts, hra_server **out);
+/* Queue one analysis; returns at once with a ticket.  The host mesh arrays
+ * must stay valid until the request has ended (poll or wait returns it).
+ * Argument errors are returned here; mesh errors come with the result. */
+hra_status hra_server_submit(hra_server *sv, const hra_request *req, uint64_t *ticket);
+/* HRA_ERR_NOT_READY until the request has ended; then HRA_OK with its
+ * result (taken: a ticket is returned once).  HRA_ERR_INVALID_ARG for an
+ * unknown ticket. */
+hra_status hra_server_poll(hra_server *sv, uint64_t ticket, hra_request_result *out);
+/* As poll, waiting up to timeout_ms (< 0: no limit). */
+hra_status hra_server_wait(hra_server *sv, uint64_t ticket, int64_t timeout_ms, hra_request_result *out);
+/* Wait until every submitted request has ended (HRA_ERR_NOT_READY on time-out). */
+hra_status hra_server_drain(hra_server *sv, int64_t timeout_ms);
+hra_status hra_server_get_stats(hra_server *sv, hra_server_stats *out);
+/* Stops the worker after the batches on the device have finished; requests
+ * not yet launched are dropped. */
+void hra_server_destroy(hra_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

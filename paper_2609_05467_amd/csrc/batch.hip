@@ -7,57 +7,14 @@
 // buffers, job tables, pinned result slots), so running it allocates
 // nothing and enqueues kernels plus three small copies into pinned memory.
 // That sequence can be captured once in a HIP graph and replayed.
-#include "common.hpp"
+#include "stages.hpp"
 
 #include <cstring>
 #include <vector>
 
 namespace hra {
-struct DirTotals;
-hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const float4 *table, int32_t N,
-                           const uint32_t *bits, const hra_dirstats &out, double *c64, uint32_t *cnt, bool hist,
-                           hipStream_t s);
-void classify_from_device_totals(const void *host_totals, int64_t n, int32_t n_dirs, const hra_thresholds *th,
-                                 hra_class_report *out);
-hipError_t launch_part_totals_raw(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,
-                                  const int64_t *d_count, int n_parts, void *tot, hipStream_t s);
-size_t dir_totals_size();
-hipError_t launch_setups_raw(const void *d_jobs, int n_jobs, int64_t n_total, const float *point, const int32_t *tri,
-                             const uint32_t *axes_bits, unsigned long long *cc, uint32_t *hist, uint32_t *err,
-                             hipStream_t s);
-size_t setup_job_size();
-void fill_setup_job(void *dst, const hra_bvh *bvh, int32_t part, int64_t sample_base, int64_t n, double tool);
-void solve_setups(const uint32_t *hist, int32_t *min_count, int32_t *min_mask, int32_t *g_count, int32_t *g_mask);
 
-// Device buffers of one batch of jobs, carved from one allocation.
-struct StageBufs {
-    float *pt, *nr, *org;
-    int32_t *tri;
-    uint32_t *bits, *abits;
-    float *mean, *absm, *conc;
-    int8_t *axis;
-    double *c64;
-    uint32_t *cnt;
-    void *tot;
-    unsigned long long *cc;
-    uint32_t *chist;
-    int64_t *dbase, *dcount;
-    SampleJob *dsj;
-    CastJob *dcj, *daj;
-    void *dsetj;
-};
-
-// Shape of one batch: jobs, samples, work items and launch shape.
-struct StageShape {
-    int32_t n_jobs;
-    int64_t S, items, aitems;
-    int32_t N, W, rpw, stack;
-    const float4 *t_hemi, *t_ax;
-    SampleJob sj0;
-    CastJob cj0, aj0;
-};
-
-static size_t carve_stage(char *base, int64_t S, int32_t W, int32_t n_jobs, StageBufs *out) {
+size_t carve_stage(char *base, int64_t S, int32_t W, int32_t n_jobs, StageBufs *out) {
     size_t off = 0;
     auto take = [&](void **p, size_t bytes) {
         off = (off + 255) & ~(size_t)255;
@@ -90,16 +47,7 @@ static size_t carve_stage(char *base, int64_t S, int32_t W, int32_t n_jobs, Stag
     return (off + 255) & ~(size_t)255;
 }
 
-// Host job tables of a batch: job j is part `part[j]` of hierarchy
-// `bvh[j]`, with its samples at rows [base[j], base[j] + count[j]).
-struct HostJobs {
-    std::vector<int64_t> base, count;
-    std::vector<SampleJob> sj;
-    std::vector<CastJob> cj, aj;
-    std::vector<char> setj;
-};
-
-static void fill_jobs(const StageBufs &B, const std::vector<const hra_bvh *> &bvh, const std::vector<int32_t> &part,
+void fill_jobs(const StageBufs &B, const std::vector<const hra_bvh *> &bvh, const std::vector<int32_t> &part,
                       const std::vector<int64_t> &count, const std::vector<uint64_t> &seed,
                       const std::vector<double> &tool, float frac, StageShape *sh, HostJobs *H) {
     const int n = (int)bvh.size();
@@ -143,11 +91,46 @@ static hipError_t upload_jobs(const StageBufs &B, const HostJobs &H, hipStream_t
     return e;
 }
 
+size_t job_table_bytes(int32_t n) {
+    return sizeof(int64_t) * 2 * n + sizeof(SampleJob) * n + sizeof(CastJob) * 2 * n + setup_job_size() * n;
+}
+
+void pack_jobs(const HostJobs &H, char *dst) {
+    const size_t n = H.base.size();
+    std::memcpy(dst, H.base.data(), sizeof(int64_t) * n);
+    dst += sizeof(int64_t) * n;
+    std::memcpy(dst, H.count.data(), sizeof(int64_t) * n);
+    dst += sizeof(int64_t) * n;
+    std::memcpy(dst, H.sj.data(), sizeof(SampleJob) * n);
+    dst += sizeof(SampleJob) * n;
+    std::memcpy(dst, H.cj.data(), sizeof(CastJob) * n);
+    dst += sizeof(CastJob) * n;
+    std::memcpy(dst, H.aj.data(), sizeof(CastJob) * n);
+    dst += sizeof(CastJob) * n;
+    std::memcpy(dst, H.setj.data(), H.setj.size());
+}
+
+hipError_t upload_packed_jobs(const StageBufs &B, const char *src, int32_t n, hipStream_t s) {
+    // the device tables are separate pieces of the stage block; one copy each
+    hipError_t e = hipMemcpyAsync(B.dbase, src, sizeof(int64_t) * n, hipMemcpyHostToDevice, s);
+    src += sizeof(int64_t) * n;
+    if (e == hipSuccess) e = hipMemcpyAsync(B.dcount, src, sizeof(int64_t) * n, hipMemcpyHostToDevice, s);
+    src += sizeof(int64_t) * n;
+    if (e == hipSuccess) e = hipMemcpyAsync(B.dsj, src, sizeof(SampleJob) * n, hipMemcpyHostToDevice, s);
+    src += sizeof(SampleJob) * n;
+    if (e == hipSuccess) e = hipMemcpyAsync(B.dcj, src, sizeof(CastJob) * n, hipMemcpyHostToDevice, s);
+    src += sizeof(CastJob) * n;
+    if (e == hipSuccess) e = hipMemcpyAsync(B.daj, src, sizeof(CastJob) * n, hipMemcpyHostToDevice, s);
+    src += sizeof(CastJob) * n;
+    if (e == hipSuccess) e = hipMemcpyAsync(B.dsetj, src, setup_job_size() * n, hipMemcpyHostToDevice, s);
+    return e;
+}
+
 // The stage sequence after the build: kernels, then three copies of the
 // per-job results into pinned host slots.  ev (optional, eager runs only)
 // receives an event before each stage and one at the end.
-static hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B, void *h_tot,
-                                 unsigned long long *h_cc, uint32_t *h_ch, hipStream_t s, hipEvent_t *ev) {
+hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B, void *h_tot,
+                          unsigned long long *h_cc, uint32_t *h_ch, hipStream_t s, hipEvent_t *ev, uint32_t *err) {
     hipError_t e = hipSuccess;
     if (ev) e = hipEventRecord(ev[0], s);
     if (e == hipSuccess) e = launch_sample(B.dsj, sh.n_jobs, sh.sj0, sh.S, B.pt, B.nr, B.org, B.tri, s);
@@ -163,7 +146,7 @@ static hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const Stage
         a.kind = 0;
         a.W = sh.W;
         a.n_items = sh.items;
-        a.err = ctx->d_err;
+        a.err = err;
         a.work = nullptr;
         e = launch_cast_any(a, sh.rpw, sh.stack, false, s);
     }
@@ -183,13 +166,12 @@ static hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const Stage
         a.kind = 1;
         a.W = 1;
         a.n_items = sh.aitems;
-        a.err = ctx->d_err;
+        a.err = err;
         a.work = nullptr;
         e = launch_cast_any(a, 64, sh.stack, false, s);
     }
     if (ev && e == hipSuccess) e = hipEventRecord(ev[4], s);
-    if (e == hipSuccess) e = launch_setups_raw(B.dsetj, sh.n_jobs, sh.S, B.pt, B.tri, B.abits, B.cc, B.chist,
-                                               ctx->d_err, s);
+    if (e == hipSuccess) e = launch_setups_raw(B.dsetj, sh.n_jobs, sh.S, B.pt, B.tri, B.abits, B.cc, B.chist, err, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h_tot, B.tot, dir_totals_size() * sh.n_jobs, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
@@ -200,7 +182,7 @@ static hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const Stage
     return e;
 }
 
-static void decode_results(const StageShape &sh, const std::vector<int64_t> &count, const void *h_tot,
+void decode_results(const StageShape &sh, const std::vector<int64_t> &count, const void *h_tot,
                            const unsigned long long *h_cc, const uint32_t *h_ch, const hra_thresholds *th,
                            hra_part_result *results) {
     for (int p = 0; p < sh.n_jobs; ++p) {
@@ -361,8 +343,9 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
 static hipError_t plan_enqueue(hra_plan *P, hipStream_t s, bool timed) {
     hipError_t e = hipSuccess;
     if (timed) e = hipEventRecord(P->ev[6], s);
-    if (e == hipSuccess) e = enqueue_build(P->ctx, P->bvh, P->ws, s);
-    if (e == hipSuccess) e = enqueue_stages(P->ctx, P->sh, P->B, P->h_tot, P->h_cc, P->h_ch, s, timed ? P->ev : nullptr);
+    if (e == hipSuccess) e = enqueue_build(P->ctx, P->bvh, P->ws, s, P->ctx->d_err);
+    if (e == hipSuccess)
+        e = enqueue_stages(P->ctx, P->sh, P->B, P->h_tot, P->h_cc, P->h_ch, s, timed ? P->ev : nullptr, P->ctx->d_err);
     return e;
 }
 

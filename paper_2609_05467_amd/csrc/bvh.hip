@@ -663,7 +663,23 @@ hra_status check_meshes(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, i
 }
 
 // The hierarchy's own arrays (no kernel work).
-hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out) {
+int64_t bvh_bytes(int64_t T, int n_parts) {
+    const int64_t nn = T > 1 ? T - 1 : 1;
+    return (int64_t)(sizeof(Node) * nn + sizeof(float4) * 3 * T + sizeof(int32_t) * 2 * T + sizeof(uint64_t) * T +
+                     sizeof(PartMeta) * n_parts);
+}
+
+__global__ void k_put_mesh(MeshIn *dst, MeshIn m) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = m;
+}
+
+hipError_t put_mesh_table(MeshIn *dst, const MeshIn &m, hipStream_t s) {
+    k_put_mesh<<<1, 64, 0, s>>>(dst, m);
+    return hipGetLastError();
+}
+
+hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out,
+                     hipStream_t alloc_stream) {
     const int n_parts = (int)hm.size();
     hra_bvh *b = new hra_bvh();
     b->ctx = ctx;
@@ -676,9 +692,10 @@ hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int
     }
     const int64_t nn = T > 1 ? T - 1 : 1;
     size_t bytes = 0;
+    b->alloc_stream = alloc_stream;
     auto alloc = [&](void **p, size_t n) -> bool {
         bytes += n;
-        return hipMalloc(p, n) == hipSuccess;
+        return (alloc_stream ? hipMallocAsync(p, n, alloc_stream) : hipMalloc(p, n)) == hipSuccess;
     };
     if (!alloc((void **)&b->nodes, sizeof(Node) * nn) || !alloc((void **)&b->tris, sizeof(float4) * 3 * T) ||
         !alloc((void **)&b->leaf_pos, sizeof(int32_t) * T) || !alloc((void **)&b->valid_rank, sizeof(int32_t) * T) ||
@@ -693,7 +710,7 @@ hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int
 
 // Enqueue the whole build on `s`: kernels only (no allocation, copy or
 // memset), reading the mesh table already in the workspace.
-hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s) {
+hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s, uint32_t *err) {
     const int64_t T = b->n_tris;
     const int n_parts = b->n_parts;
     const int leaf = b->leaf_size;
@@ -705,13 +722,13 @@ hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s)
     k_fill_sentinel_nodes<<<gN, TB, 0, s>>>(b->nodes, nn);
     k_fill_u32<<<gN, TB, 0, s>>>(W.flags, nn, 0u);
     k_fill_i32<<<gN, TB, 0, s>>>(W.PI, nn, -1);
-    k_tri_prep<<<gT, TB, 0, s>>>(W.mesh, n_parts, T, W.area, W.valid, W.tv, W.tpart, ctx->d_err);
+    k_tri_prep<<<gT, TB, 0, s>>>(W.mesh, n_parts, T, W.area, W.valid, W.tv, W.tpart, err);
     k_part_facts<<<n_parts, 256, 0, s>>>(W.mesh, W.area, b->parts);
     k_weights<<<gT, TB, 0, s>>>(W.area, W.tpart, T, b->parts, W.w);
     hipError_t e = scan<uint64_t>(W.w, b->prefix, T, true, W.scan64_ws, s);
     if (e == hipSuccess) e = scan<uint32_t>(W.valid, W.excl, T, false, W.scan32_ws, s);
     if (e != hipSuccess) return e;
-    k_part_counts<<<1, 64, 0, s>>>(b->prefix, W.excl, W.valid, n_parts, T, b->parts, W.nvt, ctx->d_err);
+    k_part_counts<<<1, 64, 0, s>>>(b->prefix, W.excl, W.valid, n_parts, T, b->parts, W.nvt, err);
     k_ranks<<<gT, TB, 0, s>>>(W.valid, W.excl, W.tpart, T, b->parts, b->valid_rank);
     k_keys<<<gT, TB, 0, s>>>(W.tv, W.tpart, W.valid, T, b->parts, W.keys0, W.vals0);
     bool in1 = false;
@@ -747,7 +764,7 @@ static hra_status build_parts(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_pa
     if (e == hipSuccess)
         e = hipMemcpyAsync(build_ws_mesh_table(ws, T, n_parts), hm.data(), sizeof(MeshIn) * n_parts,
                            hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = enqueue_build(ctx, b, ws, s);
+    if (e == hipSuccess) e = enqueue_build(ctx, b, ws, s, ctx->d_err);
     if (ws) hipFreeAsync(ws, s);
     if (e != hipSuccess) {
         hipStreamSynchronize(s);
@@ -814,11 +831,11 @@ extern "C" hra_status hra_bvh_export(hra_bvh *b, void *stream, void *host_nodes,
 extern "C" void hra_bvh_release(hra_bvh *b) {
     if (!b) return;
     if (b->ctx) hipSetDevice(b->ctx->device);
-    hipFree(b->nodes);
-    hipFree(b->tris);
-    hipFree(b->leaf_pos);
-    hipFree(b->valid_rank);
-    hipFree(b->prefix);
-    hipFree(b->parts);
+    for (void *p : {(void *)b->nodes, (void *)b->tris, (void *)b->leaf_pos, (void *)b->valid_rank, (void *)b->prefix,
+                    (void *)b->parts}) {
+        if (!p) continue;
+        if (b->alloc_stream) hipFreeAsync(p, b->alloc_stream);
+        else hipFree(p);
+    }
     delete b;
 }

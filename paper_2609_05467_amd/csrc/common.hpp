@@ -131,6 +131,7 @@ struct hra_bvh {
     std::vector<int64_t> part_tris;  // host: triangles per part
     std::vector<int64_t> part_start; // host: first triangle per part
     int64_t bytes = 0;
+    hipStream_t alloc_stream = nullptr;  // arrays from the stream-ordered allocator on this stream (else hipMalloc)
 };
 
 namespace hra {
@@ -210,10 +211,20 @@ int64_t cast_items(int32_t kind, int64_t n_samples);
 // from the workspace (build_ws_mesh_table) that the caller has filled.
 hra_status check_meshes(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, int32_t leaf,
                         std::vector<MeshIn> *hm, int64_t *T_out);
-hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out);
+// alloc_stream != NULL: allocate from the stream-ordered allocator on that
+// stream (released the same way).
+hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out,
+                     hipStream_t alloc_stream = nullptr);
 size_t build_ws_bytes(int64_t T, int n_parts);
 MeshIn *build_ws_mesh_table(void *ws, int64_t T, int n_parts);
-hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws, hipStream_t s);
+// Device bytes a hierarchy over T triangles in n_parts parts holds.
+int64_t bvh_bytes(int64_t T, int n_parts);
+// err: device error word the build reports to (index out of range, no
+// nonzero-area triangle).
+hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws, hipStream_t s, uint32_t *err);
+// Write one mesh table entry into device memory with a kernel (no host
+// buffer to keep alive; can be captured).
+hipError_t put_mesh_table(MeshIn *dst, const MeshIn &m, hipStream_t s);
 
 // ---------------------------------------------------------------- helpers
 hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out);

@@ -62,7 +62,13 @@ __global__ void k_sample(SampleArgs a) {
     const double e = (double)J.offset_frac * P.diag;
     const float eps = (float)e;
     if (J.mode == HRA_SAMPLE_AREA) {
-        if (P.total_w == 0 || li >= J.n_out) return;  // empty part: reported by the build
+        if (li >= J.n_out) return;
+        if (P.total_w == 0) {
+            // a part without nonzero-area faces (the build reports it): a
+            // defined null sample, face -1
+            write_sample(a, J.out_base + li, make_float3(0.0f, 0.0f, 0.0f), make_float3(0.0f, 0.0f, 0.0f), 0.0f, -1);
+            return;
+        }
         const uint64_t x0 = splitmix64_at(J.seed, 3ull * (uint64_t)li);
         const uint64_t x1 = splitmix64_at(J.seed, 3ull * (uint64_t)li + 1);
         const uint64_t x2 = splitmix64_at(J.seed, 3ull * (uint64_t)li + 2);

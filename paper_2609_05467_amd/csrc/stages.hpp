@@ -1,0 +1,80 @@
+// Stage machinery shared by batch plans and the server: device buffers of
+// one batch of jobs, the job tables, the enqueue of the stage sequence and
+// the decoding of per-job results.
+#pragma once
+
+#include "common.hpp"
+
+#include <vector>
+
+namespace hra {
+struct DirTotals;
+hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const float4 *table, int32_t N,
+                           const uint32_t *bits, const hra_dirstats &out, double *c64, uint32_t *cnt, bool hist,
+                           hipStream_t s);
+void classify_from_device_totals(const void *host_totals, int64_t n, int32_t n_dirs, const hra_thresholds *th,
+                                 hra_class_report *out);
+hipError_t launch_part_totals_raw(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,
+                                  const int64_t *d_count, int n_parts, void *tot, hipStream_t s);
+size_t dir_totals_size();
+hipError_t launch_setups_raw(const void *d_jobs, int n_jobs, int64_t n_total, const float *point, const int32_t *tri,
+                             const uint32_t *axes_bits, unsigned long long *cc, uint32_t *hist, uint32_t *err,
+                             hipStream_t s);
+size_t setup_job_size();
+void fill_setup_job(void *dst, const hra_bvh *bvh, int32_t part, int64_t sample_base, int64_t n, double tool);
+void solve_setups(const uint32_t *hist, int32_t *min_count, int32_t *min_mask, int32_t *g_count, int32_t *g_mask);
+
+// Device buffers of one batch of jobs, carved from one allocation.
+struct StageBufs {
+    float *pt, *nr, *org;
+    int32_t *tri;
+    uint32_t *bits, *abits;
+    float *mean, *absm, *conc;
+    int8_t *axis;
+    double *c64;
+    uint32_t *cnt;
+    void *tot;
+    unsigned long long *cc;
+    uint32_t *chist;
+    int64_t *dbase, *dcount;
+    SampleJob *dsj;
+    CastJob *dcj, *daj;
+    void *dsetj;
+};
+
+// Shape of one batch: jobs, samples, work items and launch shape.
+struct StageShape {
+    int32_t n_jobs;
+    int64_t S, items, aitems;
+    int32_t N, W, rpw, stack;
+    const float4 *t_hemi, *t_ax;
+    SampleJob sj0;
+    CastJob cj0, aj0;
+};
+
+// Host job tables of a batch: job j is part `part[j]` of hierarchy
+// `bvh[j]`, with its samples at rows [base[j], base[j] + count[j]).
+struct HostJobs {
+    std::vector<int64_t> base, count;
+    std::vector<SampleJob> sj;
+    std::vector<CastJob> cj, aj;
+    std::vector<char> setj;
+};
+
+size_t carve_stage(char *base, int64_t S, int32_t W, int32_t n_jobs, StageBufs *out);
+void fill_jobs(const StageBufs &B, const std::vector<const hra_bvh *> &bvh, const std::vector<int32_t> &part,
+               const std::vector<int64_t> &count, const std::vector<uint64_t> &seed, const std::vector<double> &tool,
+               float frac, StageShape *sh, HostJobs *H);
+// Bytes of the job tables of n jobs, and their packing into one host block
+// laid out like the device tables (dbase, dcount, dsj, dcj, daj, dsetj).
+size_t job_table_bytes(int32_t n_jobs);
+void pack_jobs(const HostJobs &H, char *dst);
+// Copies of a packed job block to the device tables.
+hipError_t upload_packed_jobs(const StageBufs &B, const char *src, int32_t n_jobs, hipStream_t s);
+hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B, void *h_tot,
+                          unsigned long long *h_cc, uint32_t *h_ch, hipStream_t s, hipEvent_t *ev, uint32_t *err);
+void decode_results(const StageShape &sh, const std::vector<int64_t> &count, const void *h_tot,
+                    const unsigned long long *h_cc, const uint32_t *h_ch, const hra_thresholds *th,
+                    hra_part_result *results);
+
+}  // namespace hra

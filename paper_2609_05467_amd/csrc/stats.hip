@@ -210,7 +210,10 @@ __global__ void k_setups(SetupArgs a) {
         int32_t p = -1;
         if (f >= 0 && f < P.n_tris) p = J.leaf_pos[P.tri_start + f];
         if (p < 0) {
-            atomicOr(a.err, ERR_BAD_SAMPLE_TRI);
+            // the null samples of a part without nonzero-area faces are no
+            // error here (the build has reported the part); others are
+            if (!(f == -1 && P.n_valid == 0)) atomicOr(a.err, ERR_BAD_SAMPLE_TRI);
+            if (a.cls_out) a.cls_out[i] = HRA_CLASS_INACCESSIBLE;
         } else {
             double lo[3], hi[3];
             for (int c = 0; c < 3; ++c) {

@@ -19,6 +19,7 @@ HRA_OK = 0
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "BAD_MESH", -5: "OVER_BUDGET",
           -6: "NOT_READY"}
 SAMPLE_AREA, SAMPLE_CENTROID = 0, 1
+SERVE_CONTINUOUS, SERVE_PLAIN = 0, 1
 DIRS_HEMI, DIRS_AXES6 = 0, 1
 CLASS_VIABLE, CLASS_OVER, CLASS_INACCESSIBLE, CLASS_FIXTURE = 0, 1, 2, 3
 
@@ -102,6 +103,29 @@ class PartResult(C.Structure):
     _fields_ = [("cls", ClassReport), ("setups", SetupReport)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("mode", C.c_int32), ("max_batch", C.c_int32),
+                ("max_inflight", C.c_int32), ("keep_resident", C.c_int32), ("n_dirs", C.c_int32),
+                ("leaf_size", C.c_int32), ("offset_frac", C.c_float), ("thresholds", C.POINTER(Thresholds))]
+
+
+class Request(C.Structure):
+    _fields_ = [("part_key", C.c_uint64), ("h_verts", C.c_void_p), ("n_verts", C.c_int64), ("h_tris", C.c_void_p),
+                ("n_tris", C.c_int64), ("n_samples", C.c_int64), ("seed", C.c_uint64), ("tool_length", C.c_double)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("resident_hit", C.c_int32), ("batch_size", C.c_int32), ("pad", C.c_int32),
+                ("batch_id", C.c_int64), ("t_submit_ns", C.c_int64), ("t_admit_ns", C.c_int64),
+                ("t_launch_ns", C.c_int64), ("t_done_ns", C.c_int64), ("result", PartResult)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "batches", "builds", "evictions",
+                                         "resident_hits", "resident_bytes", "used_bytes", "peak_used_bytes")] + \
+               [(n, C.c_int32) for n in ("resident_parts", "pending", "inflight", "pad")]
+
+
 _lib = None
 
 
@@ -152,6 +176,14 @@ def lib():
             "hra_plan_destroy": ([P], None),
             "hra_autotune": ([P, C.POINTER(PartRequest), i32, C.POINTER(BatchOpts), i32, C.POINTER(TuneReport), P],
                              C.c_int),
+            "hra_now_ns": ([], i64),
+            "hra_server_create": ([i32, C.POINTER(ServerOpts), C.POINTER(P)], C.c_int),
+            "hra_server_submit": ([P, C.POINTER(Request), C.POINTER(u64)], C.c_int),
+            "hra_server_poll": ([P, u64, C.POINTER(RequestResult)], C.c_int),
+            "hra_server_wait": ([P, u64, i64, C.POINTER(RequestResult)], C.c_int),
+            "hra_server_drain": ([P, i64], C.c_int),
+            "hra_server_get_stats": ([P, C.POINTER(ServerStats)], C.c_int),
+            "hra_server_destroy": ([P], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -167,7 +199,8 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_dominant_axes", "hra_classify", "hra_min_setups", "hra_histogram_peaks", "hra_build_bvh_batch",
            "hra_bvh_parts", "hra_bvh_part_info", "hra_sample_part", "hra_cast_part", "hra_min_setups_part",
            "hra_batch_run", "hra_plan_create", "hra_plan_run", "hra_plan_stage_ms", "hra_plan_bytes", "hra_plan_bits",
-           "hra_plan_destroy", "hra_autotune"]
+           "hra_plan_destroy", "hra_autotune", "hra_now_ns", "hra_server_create", "hra_server_submit",
+           "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy"]
 
 
 def _ptr(t):
@@ -499,5 +532,97 @@ class Bvh:
             if self._keep is not None:
                 torch.cuda.synchronize(self.ctx.device)
             self.release()
+        except Exception:
+            pass
+
+
+def now_ns():
+    """The server's monotonic clock (nanoseconds)."""
+    return int(lib().hra_now_ns())
+
+
+class Server:
+    """Analysis server on one device (its own context and worker thread).
+    submit() takes host meshes (numpy or pinned torch tensors), kept alive
+    here until their result has been taken."""
+
+    def __init__(self, device=0, n_dirs=1024, mode=SERVE_CONTINUOUS, budget_bytes=0, max_batch=0, max_inflight=0,
+                 keep_resident=True, leaf_size=0, offset_frac=0.0, thresholds=None):
+        self._th = Thresholds(*thresholds) if thresholds is not None else None
+        o = ServerOpts(int(budget_bytes), mode, max_batch, max_inflight, int(keep_resident), n_dirs, leaf_size,
+                       offset_frac, C.pointer(self._th) if self._th is not None else None)
+        p = C.c_void_p()
+        st = lib().hra_server_create(device, C.byref(o), C.byref(p))
+        if st != HRA_OK:
+            raise HraError(st, "server creation failed")
+        self.ptr = p
+        self._keep = {}
+
+    @staticmethod
+    def _host(x, dtype):
+        if isinstance(x, torch.Tensor):
+            assert x.device.type == "cpu" and x.is_contiguous() and x.dtype == dtype
+            return x, x.data_ptr()
+        import numpy as np
+        a = np.ascontiguousarray(x, dtype={torch.float32: np.float32, torch.int32: np.int32}[dtype])
+        return a, a.ctypes.data
+
+    def submit(self, part_key, verts, tris, n_samples, seed, tool_length):
+        v, vp = self._host(verts, torch.float32)
+        t, tp = self._host(tris, torch.int32)
+        r = Request(int(part_key), vp, v.shape[0], tp, t.shape[0], int(n_samples), int(seed), float(tool_length))
+        tk = C.c_uint64()
+        st = lib().hra_server_submit(self.ptr, C.byref(r), C.byref(tk))
+        if st != HRA_OK:
+            raise HraError(st, "submit rejected")
+        self._keep[tk.value] = (v, t)
+        return tk.value
+
+    def _out(self, tk, r):
+        self._keep.pop(tk, None)
+        d = {"status": r.status, "resident_hit": bool(r.resident_hit), "batch_size": r.batch_size,
+             "batch_id": r.batch_id, "t_submit_ns": r.t_submit_ns, "t_admit_ns": r.t_admit_ns,
+             "t_launch_ns": r.t_launch_ns, "t_done_ns": r.t_done_ns}
+        if r.status == HRA_OK:
+            d.update(_result_dict(r.result))
+        return d
+
+    def poll(self, ticket):
+        r = RequestResult()
+        st = lib().hra_server_poll(self.ptr, ticket, C.byref(r))
+        if st == -6:
+            return None
+        if st != HRA_OK:
+            raise HraError(st, f"poll of ticket {ticket}")
+        return self._out(ticket, r)
+
+    def wait(self, ticket, timeout_ms=-1):
+        r = RequestResult()
+        st = lib().hra_server_wait(self.ptr, ticket, int(timeout_ms), C.byref(r))
+        if st == -6:
+            return None
+        if st != HRA_OK:
+            raise HraError(st, f"wait for ticket {ticket}")
+        return self._out(ticket, r)
+
+    def drain(self, timeout_ms=-1):
+        st = lib().hra_server_drain(self.ptr, int(timeout_ms))
+        if st != HRA_OK:
+            raise HraError(st, "drain timed out")
+
+    def stats(self):
+        s = ServerStats()
+        lib().hra_server_get_stats(self.ptr, C.byref(s))
+        return {n: getattr(s, n) for n, _ in ServerStats._fields_ if n != "pad"}
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().hra_server_destroy(self.ptr)
+            self.ptr = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -1,0 +1,180 @@
+"""The analysis server on the GPU: every result equals the single-part path
+on the same inputs whether the request ran alone or in a mix (continuous
+batching, resident hierarchies, evictions), plain mode, budget rejection,
+mesh errors isolated to their request, and consistent time stamps."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from synth import parts as P
+
+pytestmark = pytest.mark.gpu
+
+N_DIRS = 512
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2609_05467_amd import hra
+    assert torch.cuda.is_available()
+    c = hra.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def pool():
+    ms = [P.config1_part(), P.box_part(), P.blind_hole_part(), P.pocket_part(),
+          P._procedural(21, 1.0, "multiaxis", (100.0, 80.0, 50.0), (4, 8)),
+          P._procedural(22, 1.0, "pockets", (120.0, 90.0, 60.0), (6, 10))]
+    return ms
+
+
+def _single(ctx, m, n, seed, tool):
+    from paper_2609_05467_amd import hra
+    b = ctx.build_bvh(m.verts, m.tris, leaf_size=4)
+    s = ctx.sample_surface(b, n, seed)
+    bits, _ = ctx.cast(b, s, N_DIRS, counts=False)
+    rep = ctx.classify(ctx.dominant_axes(s, N_DIRS, bits), n, N_DIRS)
+    b6, _ = ctx.cast(b, s, 6, kind=hra.DIRS_AXES6, counts=False)
+    su = ctx.min_setups(b, s, b6, tool, want_class=False)
+    b.release()
+    su.pop("class")
+    return {"class": rep, "setups": su}
+
+
+def _mix(pool, n_req, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_req):
+        k = int(rng.integers(0, len(pool)))
+        out.append((k, int(rng.integers(200, 1500)), 1000 + i, float(rng.choice([10.0, 30.0, 60.0]))))
+    return out
+
+
+def _check(ctx, pool, reqs, results, cache):
+    for (k, n, seed, tool), r in zip(reqs, results):
+        assert r["status"] == 0, r
+        key = (k, n, seed, tool)
+        if key not in cache:
+            cache[key] = _single(ctx, pool[k], n, seed, tool)
+        want = cache[key]
+        assert r["class"] == want["class"], key
+        assert r["setups"] == want["setups"], key
+        assert r["t_submit_ns"] <= r["t_admit_ns"] <= r["t_launch_ns"] <= r["t_done_ns"]
+
+
+@pytest.mark.parametrize("mode", ["continuous", "plain"])
+def test_server_mix_matches_single_part_path(ctx, pool, mode):
+    from paper_2609_05467_amd import hra
+    sv = hra.Server(0, n_dirs=N_DIRS, mode=hra.SERVE_PLAIN if mode == "plain" else hra.SERVE_CONTINUOUS,
+                    max_batch=8)
+    reqs = _mix(pool, 24, seed=1)
+    _say("server", mode, len(reqs))
+    tickets = []
+    for i, (k, n, seed, tool) in enumerate(reqs):
+        tickets.append(sv.submit(k, pool[k].verts, pool[k].tris, n, seed, tool))
+        if i % 5 == 4:
+            time.sleep(0.002)            # arrivals while batches run
+    results = [sv.wait(t, 60_000) for t in tickets]
+    st = sv.stats()
+    sv.close()
+    assert all(r is not None for r in results)
+    _check(ctx, pool, reqs, results, {})
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    if mode == "plain":
+        assert st["builds"] == len(reqs) and st["resident_hits"] == 0
+        assert all(r["batch_size"] == 1 for r in results)
+    else:
+        assert st["builds"] <= len(pool)          # each part built once, then resident
+        assert st["batches"] < len(reqs)          # requests shared launches
+
+
+def test_server_results_alone_equal_results_in_mix(ctx, pool):
+    from paper_2609_05467_amd import hra
+    reqs = _mix(pool, 10, seed=2)
+    sv = hra.Server(0, n_dirs=N_DIRS, max_batch=16)
+    alone = []
+    for (k, n, seed, tool) in reqs:
+        alone.append(sv.wait(sv.submit(k, pool[k].verts, pool[k].tris, n, seed, tool), 60_000))
+    tickets = [sv.submit(k, pool[k].verts, pool[k].tris, n, seed, tool) for (k, n, seed, tool) in reqs]
+    mixed = [sv.wait(t, 60_000) for t in tickets]
+    sv.close()
+    assert max(r["batch_size"] for r in mixed) > 1
+    for a, b in zip(alone, mixed):
+        assert a["status"] == b["status"] == 0
+        assert a["class"] == b["class"] and a["setups"] == b["setups"]
+
+
+def test_server_evicts_under_small_budget(ctx, pool):
+    from paper_2609_05467_amd import hra
+    big = [pool[5], pool[4], pool[0], pool[3]]
+    reqs = [(i % 4, 300, 7 + i, 30.0) for i in range(12)]
+    # measure the largest request's footprint and allow exactly that: every
+    # request fits alone, but no second hierarchy stays beside the largest,
+    # so cycling through four parts must evict
+    probe = hra.Server(0, n_dirs=N_DIRS)
+    probe.wait(probe.submit(0, big[0].verts, big[0].tris, 300, 1, 30.0), 60_000)
+    ps = probe.stats()
+    probe.close()
+    budget = int(ps["peak_used_bytes"])
+    sv = hra.Server(0, n_dirs=N_DIRS, budget_bytes=budget, max_batch=4)
+    _say("evictions, budget", budget)
+    results = []
+    for (k, n, seed, tool) in reqs:
+        results.append(sv.wait(sv.submit(k, big[k].verts, big[k].tris, n, seed, tool), 60_000))
+    st = sv.stats()
+    sv.close()
+    assert st["evictions"] > 0 and st["peak_used_bytes"] <= budget
+    _check(ctx, big, reqs, results, {})
+
+
+def test_server_rejects_what_cannot_fit_and_isolates_bad_meshes(ctx, pool):
+    from paper_2609_05467_amd import hra
+    m = pool[0]
+    sv = hra.Server(0, n_dirs=N_DIRS, budget_bytes=64 * 2 ** 20, max_batch=8)
+    bad_tris = m.tris.copy()
+    bad_tris[5, 1] = len(m.verts) + 3             # index out of range
+    flat = np.zeros((3, 3), np.float32)           # one zero-area triangle
+    t_ok1 = sv.submit(0, m.verts, m.tris, 300, 1, 30.0)
+    t_bad = sv.submit(99, m.verts, bad_tris, 300, 1, 30.0)
+    t_flat = sv.submit(98, flat, np.array([[0, 1, 2]], np.int32), 10, 1, 30.0)
+    t_huge = sv.submit(0, m.verts, m.tris, 20_000_000, 1, 30.0)   # bitmasks alone exceed the budget
+    t_ok2 = sv.submit(0, m.verts, m.tris, 300, 2, 30.0)
+    r = {k: sv.wait(t, 60_000) for k, t in
+         (("ok1", t_ok1), ("bad", t_bad), ("flat", t_flat), ("huge", t_huge), ("ok2", t_ok2))}
+    sv.close()
+    assert r["ok1"]["status"] == 0 and r["ok2"]["status"] == 0
+    assert r["bad"]["status"] == -4 and r["flat"]["status"] == -4   # HRA_ERR_BAD_MESH
+    assert r["huge"]["status"] == -5                                   # HRA_ERR_OVER_BUDGET
+    _check(ctx, pool, [(0, 300, 1, 30.0), (0, 300, 2, 30.0)], [r["ok1"], r["ok2"]], {})
+    with pytest.raises(hra.HraError):
+        hra.Server(0, n_dirs=N_DIRS, max_batch=1000)
+
+
+def test_server_poll_and_tickets(ctx, pool):
+    from paper_2609_05467_amd import hra
+    m = pool[1]
+    sv = hra.Server(0, n_dirs=N_DIRS)
+    t = sv.submit(5, m.verts, m.tris, 200, 3, 30.0)
+    deadline = time.time() + 60
+    r = None
+    while r is None and time.time() < deadline:
+        r = sv.poll(t)
+        time.sleep(0.001)
+    assert r is not None and r["status"] == 0
+    with pytest.raises(hra.HraError):
+        sv.poll(t)                                # taken already
+    with pytest.raises(hra.HraError):
+        sv.submit(5, m.verts, m.tris, 0, 3, 30.0)  # no samples
+    sv.drain(10_000)
+    sv.close()
