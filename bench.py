@@ -36,6 +36,31 @@ WORKLOADS = {
 }
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 NODE_BYTES, TRI_BYTES = 64, 48  # one interior-node record, one leaf triangle
+# FP32 vector operations the cast performs: two slab tests per node visit
+# (25 each), one triangle test (93: translation, three edge functions and
+# the plane side, each with its error bound), ray set-up (rotation and three
+# reciprocals, 18).
+NODE_OPS, TRI_OPS, RAY_OPS = 50, 93, 18
+# VALU lane operations per second: 256 CUs x 64 lanes x 2.4 GHz, one
+# operation per lane per clock without packed FP32 (the published 157.3
+# TFLOP/s counts an FMA as two and packed FP32 twice again).
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
+    """ALU roofline of the cast kernel (the bound: its node and triangle data
+    live in L2 and the MALL, so HBM is not), with the HBM view beside it."""
+    ops_per_ray = (nodes * NODE_OPS + tests * TRI_OPS) / rays + RAY_OPS
+    bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
+    t = cast_ms * 1e-3
+    achieved = ops_per_ray * rays / t / 1e12
+    gbs = bytes_per_ray * rays / t / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
+            "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic, "kernel": "k_cast_rows",
+            "avg_launch_ms": cast_ms, "algorithmic_ops": ops_per_ray * rays, "ops_per_ray": ops_per_ray,
+            "hbm_view": {"algorithmic_bytes": bytes_per_ray * rays, "bytes_per_ray": bytes_per_ray,
+                         "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+                         "measured_traffic_bytes": traffic, "l2_hit_rate": l2_hit}}
 
 
 def log(*a):
@@ -44,7 +69,8 @@ def log(*a):
 
 def cpu_baseline(mesh, samples_np, n_dirs, budget_s=15.0):
     """The oracle (brute force, FP64 decisions) on a bounded sample of the
-    same workload: the first rows of the same samples, all directions."""
+    same workload: the first rows of the same samples, all directions, grown
+    until the run takes about budget_s of wall time."""
     from oracle import oracle as orc
     threads = orc.max_threads()
     dirs = orc.fibonacci_dirs(n_dirs)
@@ -53,9 +79,8 @@ def cpu_baseline(mesh, samples_np, n_dirs, budget_s=15.0):
     t0 = time.perf_counter()
     orc.cast(mesh.verts, mesh.tris, sub, dirs, threads=threads)
     dt = time.perf_counter() - t0
-    # grow the sample to fill about budget_s of CPU time
-    if dt < budget_s / 4:
-        rows = int(min(len(samples_np["origin"]), max(rows, rows * budget_s / max(dt, 1e-3) / 2)))
+    if dt < 0.6 * budget_s:
+        rows = int(min(len(samples_np["origin"]), rows * budget_s / max(dt, 1e-3)))
         rows = max(threads, (rows // threads) * threads)
         sub = {k: v[:rows] for k, v in samples_np.items()}
         t0 = time.perf_counter()
@@ -67,9 +92,10 @@ def cpu_baseline(mesh, samples_np, n_dirs, budget_s=15.0):
 
 
 def measured_traffic(workload):
-    """HBM bytes per launch of the cast kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source has changed
-    since those counters were taken (or none were taken for this workload)."""
+    """HBM bytes per launch of the hemisphere cast kernel and its L2 hit rate
+    from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when
+    the kernel source has changed since those counters were taken (or none
+    were taken for this workload)."""
     import hashlib
     f = os.path.join(ROOT, "profiles", f"k_cast_{workload}_traffic.txt")
     if not os.path.exists(f):
@@ -187,7 +213,6 @@ def main():
     same = bool(torch.equal(wbits, bits))
     bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
     cast_ms = float(np.mean(ev["cast"]))
-    achieved = bytes_per_ray * rays / (cast_ms * 1e-3) / 1e9
     samples_np = {k: v.cpu().numpy() for k, v in samples.items()}
     bvh.release()
     traffic, l2_hit = measured_traffic(args.workload)
@@ -216,10 +241,7 @@ def main():
                          "instrumented_bits_identical": same},
         "result": {"access": rep["access"], "multi_axis": rep["multi_axis"], "shares": rep["shares"],
                    "mean_conc": rep["conc"], "min_setups": su["min_count"], "greedy_setups": su["greedy_count"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_cast", "avg_launch_ms": cast_ms, "algorithmic_bytes": bytes_per_ray * rays,
-                     "l2_hit_rate": l2_hit},
+        "roofline": roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit),
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -325,7 +347,6 @@ def run_batch(args):
         b.release()
     bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
     cast_ms = float(np.mean(stage["cast"]))
-    achieved = bytes_per_ray * rays / (cast_ms * 1e-3) / 1e9
     out = {
         "metric": "any-hit hemisphere rays/s",
         "value": rays / graph_s,
@@ -345,9 +366,7 @@ def run_batch(args):
         "results_identical": {"batch_vs_plain": bool(same_plain), "graph_vs_eager": bool(same_graph)},
         "stage_ms": {k: round(float(np.mean(v)), 3) for k, v in stage.items()},
         "work_per_ray": {"node_fetches": nodes / rays, "tri_tests": tests / rays, "bytes": bytes_per_ray},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("batch64")[0],
-                     "kernel": "k_cast", "avg_launch_ms": cast_ms, "algorithmic_bytes": bytes_per_ray * rays},
+        "roofline": roofline(nodes, tests, rays, W, N, cast_ms, *measured_traffic("batch64")),
     }
     if tune is not None:
         out["autotune"] = tune

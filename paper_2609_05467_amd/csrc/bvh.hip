@@ -12,7 +12,8 @@
 // Stages (one stream, no host round trip):
 //   1. per-triangle prep: part lookup, index check, FP64 doubled area
 //      squared, area, nonzero-area flag, a copy of the three vertices;
-//   2. per-part vertex bbox, diagonal, largest area, weight scale;
+//   2. per-part vertex bbox and largest area (a 2D grid of blocks per part,
+//      exact atomic min/max), then diagonal and weight scale;
 //   3. integer area weights, their global inclusive prefix (the sampler
 //      searches a part's range), ranks of nonzero-area faces;
 //   4. keys (part, Morton of the centroid); zero-area faces get the
@@ -21,10 +22,13 @@
 //      LDS-ranked scatter;
 //   6. binary radix tree over the sorted keys (Karras, "Maximizing
 //      Parallelism in the Construction of BVHs, Octrees, and k-d Trees", HPG
-//      2012), ties between equal keys broken by position; part roots;
-//   7. bottom-up box refit: the second thread to reach a node merges it;
+//      2012), ties between equal keys broken by position within the part;
+//      part roots;
+//   7. bottom-up box refit: the second thread to reach a node merges it and
+//      records its height;
 //   8. leaf collapse (subtrees of one part with <= leaf_size triangles become
-//      one leaf over a contiguous run) and emission of 64-byte nodes.
+//      one leaf over a contiguous run) and emission of 64-byte nodes; node
+//      counts per part and each part's depth (its root's height).
 #include "common.hpp"
 
 #include <algorithm>
@@ -169,49 +173,95 @@ __global__ void k_tri_prep(const MeshIn *mesh, int n_parts, int64_t T, double *a
     valid[g] = ok ? 1u : 0u;
 }
 
-// One block per part: vertex bbox, diagonal, largest area, weight scale
+// Per-part facts from many blocks at once: blocks (b, p) of a 2D grid take
+// slices of part p's vertices and triangles and fold their bounding box and
+// largest area into per-part accumulators with atomics (exact: min, max).
+// Floats are folded as order-preserving unsigned keys.
+struct PartAcc {
+    uint32_t lo[3], hi[3];   // ordered keys of the vertex bbox
+    unsigned long long amax; // bits of the largest area (non-negative double)
+    int32_t pad[2];
+};
+constexpr int FACT_BLOCKS = 64;
+
+__device__ inline uint32_t fkey(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float fkey_inv(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+__global__ void k_acc_init(PartAcc *acc, int n_parts) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_parts) return;
+    for (int c = 0; c < 3; ++c) {
+        acc[p].lo[c] = 0xffffffffu;
+        acc[p].hi[c] = 0u;
+    }
+    acc[p].amax = 0ull;
+}
+
+__global__ void k_part_facts(const MeshIn *mesh, const double *area, PartAcc *acc) {
+    __shared__ uint32_t slo[3], shi[3];
+    __shared__ unsigned long long samax;
+    const int p = blockIdx.y, t = threadIdx.x;
+    const MeshIn m = mesh[p];
+    if (t < 3) {
+        slo[t] = 0xffffffffu;
+        shi[t] = 0u;
+    }
+    if (t == 0) samax = 0ull;
+    __syncthreads();
+    const int64_t vchunk = (m.nv + FACT_BLOCKS - 1) / FACT_BLOCKS, tchunk = (m.nt + FACT_BLOCKS - 1) / FACT_BLOCKS;
+    const int64_t v0 = blockIdx.x * vchunk, v1 = v0 + vchunk < m.nv ? v0 + vchunk : m.nv;
+    const int64_t t0 = blockIdx.x * tchunk, t1 = t0 + tchunk < m.nt ? t0 + tchunk : m.nt;
+    uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0u, 0u, 0u};
+    for (int64_t i = v0 + t; i < v1; i += blockDim.x)
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t k = fkey(m.v[3 * i + c]);
+            lo[c] = k < lo[c] ? k : lo[c];
+            hi[c] = k > hi[c] ? k : hi[c];
+        }
+    unsigned long long am = 0ull;
+    for (int64_t i = t0 + t; i < t1; i += blockDim.x) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(area[m.tri_start + i]);
+        am = b > am ? b : am;
+    }
+    for (int c = 0; c < 3; ++c) {
+        atomicMin(&slo[c], lo[c]);
+        atomicMax(&shi[c], hi[c]);
+    }
+    atomicMax(&samax, am);
+    __syncthreads();
+    if (t < 3) {
+        atomicMin(&acc[p].lo[t], slo[t]);
+        atomicMax(&acc[p].hi[t], shi[t]);
+    }
+    if (t == 0) atomicMax(&acc[p].amax, samax);
+}
+
+// One thread per part: bbox, diagonal, largest area and the weight scale
 // k = 54 - (ilogb(amax) + 1) - bitlen(n_tris), which keeps each part's weight
 // sum below 2^54 and the sum over up to 1024 parts below 2^64.
-__global__ void k_part_facts(const MeshIn *mesh, const double *area, PartMeta *meta) {
-    __shared__ double s[7][256];
-    const int p = blockIdx.x, t = threadIdx.x;
+__global__ void k_part_finalize(const MeshIn *mesh, const PartAcc *acc, int n_parts, PartMeta *meta) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_parts) return;
     const MeshIn m = mesh[p];
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double amax = 0.0;
-    for (int64_t i = t; i < m.nv; i += blockDim.x)
-        for (int c = 0; c < 3; ++c) {
-            const float x = m.v[3 * i + c];
-            lo[c] = fminf(lo[c], x);
-            hi[c] = fmaxf(hi[c], x);
-        }
-    for (int64_t i = t; i < m.nt; i += blockDim.x) amax = fmax(amax, area[m.tri_start + i]);
-    for (int c = 0; c < 3; ++c) {
-        s[c][t] = lo[c];
-        s[3 + c][t] = hi[c];
-    }
-    s[6][t] = amax;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
-            for (int c = 0; c < 3; ++c) {
-                s[c][t] = fmin(s[c][t], s[c][t + off]);
-                s[3 + c][t] = fmax(s[3 + c][t], s[3 + c][t + off]);
-            }
-            s[6][t] = fmax(s[6][t], s[6][t + off]);
-        }
-        __syncthreads();
-    }
-    if (t != 0) return;
+    const PartAcc &A = acc[p];
     PartMeta &P = meta[p];
+    double lo[3], hi[3];
     for (int c = 0; c < 3; ++c) {
-        P.bbox[c] = (float)s[c][0];
-        P.bbox[3 + c] = (float)s[3 + c][0];
+        lo[c] = fkey_inv(A.lo[c]);
+        hi[c] = fkey_inv(A.hi[c]);
+        P.bbox[c] = (float)lo[c];
+        P.bbox[3 + c] = (float)hi[c];
     }
-    const double dx = s[3][0] - s[0][0], dy = s[4][0] - s[1][0], dz = s[5][0] - s[2][0];
+    const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
     const double sx = dx * dx, sy = dy * dy, sz = dz * dz;
     const double sxy = sx + sy;
     P.diag = sqrt(sxy + sz);
-    P.amax = s[6][0];
+    P.amax = __longlong_as_double((long long)A.amax);
     int tb = 0;
     while (tb < 63 && ((int64_t)1 << tb) <= m.nt) ++tb;
     P.k_scale = P.amax > 0.0 ? 54 - (ilogb(P.amax) + 1) - tb : 0;
@@ -490,27 +540,40 @@ __device__ inline void child_box(const float4 *tri4, const float *box_int, int32
         load_box(box_int, c, bx);
 }
 
+// Bottom-up box refit: each leaf's thread walks towards the root; at every
+// node the first arrival stops and the second (which then sees both
+// children done) merges the boxes and goes on.  The same walk records each
+// node's height in emitted interior nodes (a node whose subtree holds at
+// most leaf_size triangles becomes a leaf: height 0).  The counter's
+// acquire-release ordering makes the sibling's box and height visible.
 __global__ void k_refit(const float4 *tri4, const int32_t *parent_leaf, const int32_t *parent_int, const int32_t *left,
-                        const int32_t *right, float *box_int, uint32_t *flags, const int32_t *n_valid_total) {
+                        const int32_t *right, const int32_t *first, const int32_t *last, int leaf_size,
+                        float *box_int, int32_t *height, uint32_t *flags, const int32_t *n_valid_total) {
     const int n = *n_valid_total;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n || n < 2) return;
     int node = parent_leaf[p];
     int steps = 0;
     while (node >= 0 && node < n - 1 && ++steps <= n) {
-        __threadfence();
-        const uint32_t old = atomicAdd(&flags[node], 1u);
+        const uint32_t old = __hip_atomic_fetch_add(&flags[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0) return;  // the sibling subtree is not done yet
-        __threadfence();
         float a[6], b[6];
-        child_box(tri4, box_int, left[node], a);
-        child_box(tri4, box_int, right[node], b);
+        const int32_t l = left[node], r = right[node];
+        child_box(tri4, box_int, l, a);
+        child_box(tri4, box_int, r, b);
         uint32_t *dst = reinterpret_cast<uint32_t *>(box_int) + 6 * (int64_t)node;
         for (int k = 0; k < 3; ++k) {
             __hip_atomic_store(dst + k, __float_as_uint(fminf(a[k], b[k])), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(dst + 3 + k, __float_as_uint(fmaxf(a[3 + k], b[3 + k])), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
+        int h = 0;
+        if (last[node] - first[node] + 1 > leaf_size) {
+            const int hl = ((uint32_t)l & KLEAF) ? 0 : __hip_atomic_load(height + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int hr = ((uint32_t)r & KLEAF) ? 0 : __hip_atomic_load(height + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            h = 1 + (hl > hr ? hl : hr);
+        }
+        __hip_atomic_store(height + node, h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         node = parent_int[node];
     }
 }
@@ -542,11 +605,12 @@ __global__ void k_small_roots(PartMeta *meta, int n_parts, int leaf_size) {
 }
 
 __global__ void k_emit(const float4 *tri4, const uint64_t *keys, const int32_t *left, const int32_t *right,
-                       const int32_t *first, const int32_t *last, const int32_t *parent_int, const float *box_int,
-                       int leaf_size, const int32_t *n_valid_total, Node *nodes, PartMeta *meta) {
+                       const int32_t *first, const int32_t *last, const float *box_int, int leaf_size,
+                       const int32_t *n_valid_total, Node *nodes, uint8_t *emitted) {
     const int n = *n_valid_total;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
+    emitted[i] = 0;
     if (last[i] - first[i] + 1 <= leaf_size) return;
     const int p = (int)(keys[first[i]] >> 56);
     if ((int)(keys[last[i]] >> 56) != p) return;   // spans two parts: never traversed
@@ -571,12 +635,34 @@ __global__ void k_emit(const float4 *tri4, const uint64_t *keys, const int32_t *
     nd.c = make_float4(bx[1][2], bx[1][3], bx[1][4], bx[1][5]);
     nd.d = make_int4(code[0], code[1], 0, 0);
     nodes[i] = nd;
-    atomicAdd(&meta[p].n_nodes, 1);
-    // depth within the part: emitted ancestors up to the part root
-    int depth = 1;
-    const int32_t root = meta[p].root;
-    for (int a = i; a != root && a >= 0 && a < n - 1 && depth <= n; a = parent_int[a]) ++depth;
-    atomicMax(&meta[p].depth, depth);
+    emitted[i] = 1;
+}
+
+// Interior nodes and depth of every part.  In the radix tree each internal
+// node's index is an end of its key range, so part p's interior nodes have
+// indices in [leaf_lo, leaf_lo + n_valid - 1]; the other indices there
+// belong to nodes spanning two parts, which are never emitted.  Blocks (b,
+// p) count slices of that range; the depth is the root's height.
+__global__ void k_part_nodes(const uint8_t *emitted, const int32_t *height, const int32_t *n_valid_total,
+                             PartMeta *meta) {
+    __shared__ int cnt;
+    const int p = blockIdx.y, t = threadIdx.x;
+    const int n = *n_valid_total;
+    PartMeta &P = meta[p];
+    if (t == 0) cnt = 0;
+    __syncthreads();
+    const int64_t a = P.leaf_lo;
+    int64_t b = (int64_t)P.leaf_lo + P.n_valid;   // exclusive
+    if (b > n - 1) b = n - 1;
+    const int64_t len = b > a ? b - a : 0;
+    const int64_t chunk = (len + FACT_BLOCKS - 1) / FACT_BLOCKS;
+    const int64_t c0 = a + blockIdx.x * chunk, c1 = c0 + chunk < b ? c0 + chunk : b;
+    int c = 0;
+    for (int64_t i = c0 + t; i < c1; i += blockDim.x) c += emitted[i];
+    if (c) atomicAdd(&cnt, c);
+    __syncthreads();
+    if (t == 0 && cnt) atomicAdd(&P.n_nodes, cnt);
+    if (t == 0 && blockIdx.x == 0) P.depth = is_leaf(P.root) || P.n_valid < 2 ? 0 : height[P.root];
 }
 
 }  // namespace hra
@@ -593,9 +679,10 @@ struct BuildWs {
     uint32_t *valid, *excl, *vals0, *vals1, *flags, *rs_ws;
     uint64_t *w, *keys0, *keys1, *scan64_ws;
     uint32_t *scan32_ws;
-    int32_t *L, *R, *F, *La, *PI, *PL, *nvt;
+    int32_t *L, *R, *F, *La, *PI, *PL, *nvt, *height;
     float *box, *tv;
-    uint8_t *tpart;
+    uint8_t *tpart, *emitted;
+    PartAcc *acc;
 };
 
 static size_t carve(char *base, int64_t T, int n_parts, BuildWs *w) {
@@ -626,6 +713,9 @@ static size_t carve(char *base, int64_t T, int n_parts, BuildWs *w) {
     take((void **)&d.PL, sizeof(int32_t) * T);
     take((void **)&d.flags, sizeof(uint32_t) * nn);
     take((void **)&d.box, sizeof(float) * 6 * nn);
+    take((void **)&d.height, sizeof(int32_t) * nn);
+    take((void **)&d.emitted, sizeof(uint8_t) * nn);
+    take((void **)&d.acc, sizeof(PartAcc) * n_parts);
     take((void **)&d.nvt, sizeof(int32_t));
     take((void **)&d.scan64_ws, sizeof(uint64_t) * (scan_ws_elems(T) + 1));
     take((void **)&d.scan32_ws, sizeof(uint32_t) * (scan_ws_elems(T) + 1));
@@ -647,15 +737,16 @@ hra_status check_meshes(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, i
                         std::vector<MeshIn> *hm, int64_t *T_out) {
     if (n_parts < 1 || n_parts > MAX_PARTS) return ctx->fail(HRA_ERR_INVALID_ARG, "1..255 parts per hierarchy");
     if (leaf < 1 || leaf > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 1..8");
-    int64_t T = 0;
+    int64_t T = 0, V = 0;
     hm->resize(n_parts);
     for (int p = 0; p < n_parts; ++p) {
         const hra_mesh &m = meshes[p];
         if (!m.d_verts || !m.d_tris || m.n_verts < 3 || m.n_tris < 1)
             return ctx->fail(HRA_ERR_INVALID_ARG, "each mesh needs at least 3 vertices and 1 triangle");
         if (m.n_verts >= (int64_t)1 << 31) return ctx->fail(HRA_ERR_INVALID_ARG, "too many vertices in a mesh");
-        (*hm)[p] = MeshIn{m.d_verts, m.d_tris, m.n_verts, m.n_tris, T};
+        (*hm)[p] = MeshIn{m.d_verts, m.d_tris, m.n_verts, m.n_tris, T, V};
         T += m.n_tris;
+        V += m.n_verts;
     }
     if (T >= (int64_t)1 << 27) return ctx->fail(HRA_ERR_INVALID_ARG, "too many triangles (max 2^27 per hierarchy)");
     *T_out = T;
@@ -723,7 +814,9 @@ hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s,
     k_fill_u32<<<gN, TB, 0, s>>>(W.flags, nn, 0u);
     k_fill_i32<<<gN, TB, 0, s>>>(W.PI, nn, -1);
     k_tri_prep<<<gT, TB, 0, s>>>(W.mesh, n_parts, T, W.area, W.valid, W.tv, W.tpart, err);
-    k_part_facts<<<n_parts, 256, 0, s>>>(W.mesh, W.area, b->parts);
+    k_acc_init<<<blocks_for(n_parts, 64), 64, 0, s>>>(W.acc, n_parts);
+    k_part_facts<<<dim3(FACT_BLOCKS, n_parts), 256, 0, s>>>(W.mesh, W.area, W.acc);
+    k_part_finalize<<<blocks_for(n_parts, 64), 64, 0, s>>>(W.mesh, W.acc, n_parts, b->parts);
     k_weights<<<gT, TB, 0, s>>>(W.area, W.tpart, T, b->parts, W.w);
     hipError_t e = scan<uint64_t>(W.w, b->prefix, T, true, W.scan64_ws, s);
     if (e == hipSuccess) e = scan<uint32_t>(W.valid, W.excl, T, false, W.scan32_ws, s);
@@ -739,8 +832,9 @@ hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s,
     k_gather<<<gT, TB, 0, s>>>(W.tv, vs, W.tpart, b->parts, W.nvt, b->tris, b->leaf_pos);
     k_karras<<<gN, TB, 0, s>>>(ks, W.nvt, W.L, W.R, W.F, W.La, W.PI, W.PL, b->parts);
     k_small_roots<<<blocks_for(n_parts, 64), 64, 0, s>>>(b->parts, n_parts, leaf);
-    k_refit<<<gT, TB, 0, s>>>(b->tris, W.PL, W.PI, W.L, W.R, W.box, W.flags, W.nvt);
-    k_emit<<<gN, TB, 0, s>>>(b->tris, ks, W.L, W.R, W.F, W.La, W.PI, W.box, leaf, W.nvt, b->nodes, b->parts);
+    k_refit<<<gT, TB, 0, s>>>(b->tris, W.PL, W.PI, W.L, W.R, W.F, W.La, leaf, W.box, W.height, W.flags, W.nvt);
+    k_emit<<<gN, TB, 0, s>>>(b->tris, ks, W.L, W.R, W.F, W.La, W.box, leaf, W.nvt, b->nodes, W.emitted);
+    k_part_nodes<<<dim3(FACT_BLOCKS, n_parts), 256, 0, s>>>(W.emitted, W.height, W.nvt, b->parts);
     return hipGetLastError();
 }
 

@@ -83,7 +83,8 @@ struct MeshIn {
     const int32_t *t;
     int64_t nv;
     int64_t nt;
-    int64_t tri_start;
+    int64_t tri_start;    // first triangle of the part in the concatenation
+    int64_t vert_start;   // first vertex of the part in the concatenation
 };
 
 // Largest number of parts in one hierarchy (the part index takes the top
