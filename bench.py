@@ -97,7 +97,7 @@ def measured_traffic(workload):
     the kernel source has changed since those counters were taken (or none
     were taken for this workload)."""
     import hashlib
-    f = os.path.join(ROOT, "profiles", f"k_cast_{workload}_traffic.txt")
+    f = os.path.join(ROOT, "profiles", f"k_cast_rows_{workload}_traffic.txt")
     if not os.path.exists(f):
         return None, None
     kv = dict(l.strip().split("=", 1) for l in open(f) if "=" in l and not l.startswith("#"))

@@ -157,7 +157,7 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
     int spill[SPILL];
     int sp = 0;
     int32_t node = root;
-    int64_t budget = 2 * (int64_t)n_nodes_alloc + 64;
+    int32_t budget = 2 * n_nodes_alloc + 64;
     while (true) {
         if ((uint32_t)node >= (uint32_t)n_nodes_alloc || --budget < 0) {
             atomicOr(err, ERR_STACK);
@@ -195,6 +195,9 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
         }
     }
 }
+
+// A value that is the same in every lane, moved to a scalar register.
+__device__ inline float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
 
 // Job of a wave-uniform work item: the last job whose item_base <= item.
 __device__ inline CastJob job_of(const CastArgs &a, int64_t item) {
@@ -236,10 +239,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     const bool empty = n_valid <= 0;
     const int32_t n_tris_alloc = P.leaf_lo + n_valid;   // end of this part's leaf run
     const int64_t s = item - J.item_base;
-    const float ox = J.origin[3 * s], oy = J.origin[3 * s + 1], oz = J.origin[3 * s + 2];
-    const float nx = J.normal[3 * s], ny = J.normal[3 * s + 1], nz = J.normal[3 * s + 2];
-    float3 t, b;
-    onb_frame(nx, ny, nz, t, b);
+    // the sample, its normal and frame are the same for the whole
+    // workgroup: keep them in scalar registers
+    const float ox = uni(J.origin[3 * s]), oy = uni(J.origin[3 * s + 1]), oz = uni(J.origin[3 * s + 2]);
+    const float nx = uni(J.normal[3 * s]), ny = uni(J.normal[3 * s + 1]), nz = uni(J.normal[3 * s + 2]);
+    float3 t0, b0;
+    onb_frame(nx, ny, nz, t0, b0);
+    const float3 t = make_float3(uni(t0.x), uni(t0.y), uni(t0.z)), b = make_float3(uni(b0.x), uni(b0.y), uni(b0.z));
     for (int32_t w = threadIdx.x; w < a.W; w += 256) row[w] = 0u;
     __syncthreads();
     WorkCount wc;
