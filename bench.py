@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=200.0, help="serve: device memory budget")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes generating the batch parts (before any GPU work)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="single-part workloads: skip the 64-part batch and serving comparisons")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -139,6 +141,9 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    extras = None
+    if not args.no_extras and args.workload == "interactive_200k":
+        extras = gen_batch(args)   # before any GPU work (the generator forks)
 
     import numpy as np
     import torch
@@ -246,8 +251,32 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, samples_np, N)
-    print(json.dumps(out), flush=True)
     ctx.close()
+    if extras is not None:
+        meshes, counts = extras
+        log("[bench] 64-part batch against the plain per-part path")
+        b = batch_compare(args, meshes, counts, 2)
+        out["batch64"] = {k: b[k] for k in ("config", "batched_graph", "batched_eager", "plain", "speedup_vs_plain",
+                                            "results_identical", "stage_ms")}
+        log("[bench] serving at 100 requests/s, served against plain")
+        sv = serve_compare(args, meshes, counts, [100.0], 300)[0]
+        out["serve"] = {"rate_per_s": sv["rate"], "requests": 300, "popularity": "zipf 1.1 over the 64-part pool",
+                        "served": sv["served"], "plain": sv["plain"],
+                        "p99_ratio_plain_over_served": sv["plain"]["p99_ms"] / sv["served"]["p99_ms"]}
+    print(json.dumps(out), flush=True)
+
+
+def gen_batch(args):
+    """The 64-part pool and its sample counts (host only; call before any GPU
+    work, the generator forks worker processes)."""
+    from synth import parts
+    log(f"[bench] generating 64 parts with {args.workers} processes")
+    t0 = time.perf_counter()
+    meshes = parts.batch_parts(workers=args.workers)
+    counts = parts.batch_samples(meshes)
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s: {sum(m.n_tris for m in meshes)} triangles, "
+        f"{sum(counts)} samples")
+    return meshes, counts
 
 
 def run_batch(args):
@@ -255,15 +284,14 @@ def run_batch(args):
     its own launches, synchronising per part) against the batch plan (one
     hierarchy, one launch per stage for all parts) eager and as a replayed
     HIP graph.  value = hemisphere rays/s of the graph runs."""
+    meshes, counts = gen_batch(args)
+    out = batch_compare(args, meshes, counts, args.steps, work=True)
+    print(json.dumps(out), flush=True)
+
+
+def batch_compare(args, meshes, counts, steps, work=False):
     import numpy as np
-    from synth import parts
     N = WORKLOADS["batch64"][2]
-    log(f"[bench] generating 64 parts with {args.workers} processes")
-    t0 = time.perf_counter()
-    meshes = parts.batch_parts(workers=args.workers)   # before any GPU work (fork)
-    counts = parts.batch_samples(meshes)
-    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s: {sum(m.n_tris for m in meshes)} triangles, "
-        f"{sum(counts)} samples")
     import torch
     from paper_2609_05467_amd import hra
     ctx = hra.Context(0)
@@ -304,12 +332,12 @@ def run_batch(args):
     log("[bench] plain warmup")
     plain_res = plain_pass()
     torch.cuda.synchronize()
-    log(f"[bench] plain timing {args.steps} passes")
+    log(f"[bench] plain timing {steps} passes")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plain_pass()
     torch.cuda.synchronize()
-    plain_s = (time.perf_counter() - t0) / args.steps
+    plain_s = (time.perf_counter() - t0) / steps
 
     pl = ctx.plan(reqs, N)
     log(f"[bench] plan holds {pl.bytes / 2**30:.2f} GiB; eager warmup")
@@ -319,39 +347,40 @@ def run_batch(args):
                      for r, p in zip(res, plain_res))
     stage = {k: [] for k in ("build", "sample", "cast", "stats", "axes", "setups")}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         pl.run(graph=False)
         for k, v in pl.stage_ms().items():
             stage[k].append(v)
-    eager_s = (time.perf_counter() - t0) / args.steps
+    eager_s = (time.perf_counter() - t0) / steps
     log("[bench] graph capture + replays")
     res_g = pl.run(graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         res_g = pl.run(graph=True)
     torch.cuda.synchronize()
-    graph_s = (time.perf_counter() - t0) / args.steps
+    graph_s = (time.perf_counter() - t0) / steps
     same_graph = res_g == res
     pl.destroy()
 
     # traversal work per ray (instrumented single-part casts, outside the timed region)
+    W = (N + 31) // 32
     nodes = tests = 0
-    for i, ((v, t), c) in enumerate(zip(dm, counts)):
-        smp = bufs[i][0]
-        b = ctx.build_bvh(v, t, leaf_size=leaf)
-        ctx.sample_surface(b, c, 400 + i, out=smp)
-        _, nf, nt = ctx.cast_work(b, smp, N)
-        nodes += nf
-        tests += nt
-        b.release()
-    bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
+    if work:
+        for i, ((v, t), c) in enumerate(zip(dm, counts)):
+            smp = bufs[i][0]
+            b = ctx.build_bvh(v, t, leaf_size=leaf)
+            ctx.sample_surface(b, c, 400 + i, out=smp)
+            _, nf, nt = ctx.cast_work(b, smp, N)
+            nodes += nf
+            tests += nt
+            b.release()
     cast_ms = float(np.mean(stage["cast"]))
     out = {
         "metric": "any-hit hemisphere rays/s",
         "value": rays / graph_s,
         "unit": "rays/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": graph_s * 1e3,
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": graph_s * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch64", "parts": len(meshes), "triangles": int(sum(m.n_tris for m in meshes)),
                    "triangles_min_max": [int(min(m.n_tris for m in meshes)), int(max(m.n_tris for m in meshes))],
@@ -365,13 +394,14 @@ def run_batch(args):
         "speedup_vs_plain": plain_s / graph_s,
         "results_identical": {"batch_vs_plain": bool(same_plain), "graph_vs_eager": bool(same_graph)},
         "stage_ms": {k: round(float(np.mean(v)), 3) for k, v in stage.items()},
-        "work_per_ray": {"node_fetches": nodes / rays, "tri_tests": tests / rays, "bytes": bytes_per_ray},
-        "roofline": roofline(nodes, tests, rays, W, N, cast_ms, *measured_traffic("batch64")),
     }
+    if work:
+        out["work_per_ray"] = {"node_fetches": nodes / rays, "tri_tests": tests / rays}
+        out["roofline"] = roofline(nodes, tests, rays, W, N, cast_ms, *measured_traffic("batch64"))
     if tune is not None:
         out["autotune"] = tune
-    print(json.dumps(out), flush=True)
     ctx.close()
+    return out
 
 
 def serve_run(hra, pool, counts, schedule, N, mode, budget, tool):
@@ -412,14 +442,28 @@ def run_serve(args):
     64-part pool, samples by area) served with continuous batching and
     resident hierarchies, against the plain mode (one request at a time,
     rebuilt every time), on the same arrival schedule per rate."""
+    meshes, counts = gen_batch(args)
+    rates = [float(x) for x in args.rates.split(",")]
+    out_rates = serve_compare(args, meshes, counts, rates, args.requests)
+    top = out_rates[-1]
+    out = {
+        "metric": "p99 per-part latency, served",
+        "value": top["served"]["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "ms_per_step": top["served"]["mean_ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serve", "pool_parts": len(meshes), "directions": WORKLOADS["serve"][2],
+                   "popularity": "zipf 1.1", "rates_per_s": rates, "requests_per_rate": args.requests,
+                   "budget_gib": args.budget_gib, "samples_min_max": [min(counts), max(counts)]},
+        "rates": out_rates,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_compare(args, meshes, counts, rates, n_requests):
     import numpy as np
-    from synth import parts
-    N = WORKLOADS["serve"][2]
-    log(f"[bench] generating the 64-part pool with {args.workers} processes")
-    meshes = parts.batch_parts(workers=args.workers)
-    counts = parts.batch_samples(meshes)
     import torch
     from paper_2609_05467_amd import hra
+    N = WORKLOADS["serve"][2]
     # meshes in pinned host memory, as a client would hand them over
     pool = [(torch.from_numpy(m.verts).pin_memory(), torch.from_numpy(m.tris).pin_memory()) for m in meshes]
     rng = np.random.default_rng(5)
@@ -427,16 +471,15 @@ def run_serve(args):
     zipf /= zipf.sum()
     order = rng.permutation(len(meshes))          # popularity rank -> part
     budget = int(args.budget_gib * 2 ** 30)
-    rates = [float(x) for x in args.rates.split(",")]
     out_rates = []
     for lam in rates:
-        gaps = rng.exponential(1.0 / lam, args.requests)
+        gaps = rng.exponential(1.0 / lam, n_requests)
         ta = np.cumsum(gaps) - gaps[0]
-        ks = order[rng.choice(len(meshes), args.requests, p=zipf)]
+        ks = order[rng.choice(len(meshes), n_requests, p=zipf)]
         schedule = [(float(t), int(k), 9000 + i) for i, (t, k) in enumerate(zip(ta, ks))]
         row = {"rate": lam}
         for name, mode in (("served", hra.SERVE_CONTINUOUS), ("plain", hra.SERVE_PLAIN)):
-            log(f"[bench] rate {lam}/s, {args.requests} requests, {name}")
+            log(f"[bench] rate {lam}/s, {n_requests} requests, {name}")
             recs, st = serve_run(hra, pool, counts, schedule, N, mode, budget, args.tool_length)
             row[name] = serve_summary(recs, N, counts, schedule)
             row[name]["builds"] = st["builds"]
@@ -444,18 +487,7 @@ def run_serve(args):
             log(f"[bench]   p50 {row[name]['p50_ms']:.2f} ms p99 {row[name]['p99_ms']:.2f} ms "
                 f"{row[name]['parts_per_s']:.1f} parts/s")
         out_rates.append(row)
-    top = out_rates[-1]
-    out = {
-        "metric": "p99 per-part latency, served",
-        "value": top["served"]["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": 0,
-        "ms_per_step": top["served"]["mean_ms"], "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "serve", "pool_parts": len(meshes), "directions": N, "popularity": "zipf 1.1",
-                   "rates_per_s": rates, "requests_per_rate": args.requests, "budget_gib": args.budget_gib,
-                   "samples_min_max": [min(counts), max(counts)]},
-        "rates": out_rates,
-    }
-    print(json.dumps(out), flush=True)
+    return out_rates
 
 
 if __name__ == "__main__":

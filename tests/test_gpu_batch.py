@@ -236,3 +236,51 @@ def test_autotune_picks_a_point_and_keeps_results(ctx, meshes):
     assert np.array_equal(_u32(x1), _u32(x2))
     b.release()
     b2.release()
+
+
+def test_batch64_full_size_matches_single_parts(ctx, orc, tmp_path):
+    """The 64-part workload at full size (2.9k-412k triangles, 1.5M samples
+    x 1,024 directions) in one plan run replayed as a graph: every part's
+    bits, class and setups equal its single-part run, and sampled rows of
+    the smaller parts agree with the oracle (grazing rays excluded)."""
+    import subprocess
+    import torch
+    from paper_2609_05467_amd import hra
+    # generate in a child process (the generator forks workers; this process
+    # has the GPU open)
+    f = tmp_path / "parts.npz"
+    code = ("import sys, numpy as np; sys.path.insert(0, %r); from synth import parts; "
+            "ms = parts.batch_parts(workers=16); "
+            "np.savez(%r, **{f'v{i}': m.verts for i, m in enumerate(ms)}, **{f't{i}': m.tris for i, m in enumerate(ms)})"
+            % (str(P.__file__).rsplit("/synth/", 1)[0], str(f)))
+    _say("generating the 64 parts")
+    subprocess.run([sys.executable, "-c", code], check=True, timeout=600)
+    z = np.load(f)
+    meshes = [P.Mesh(z[f"v{i}"], z[f"t{i}"]) for i in range(64)]
+    counts = P.batch_samples(meshes)
+    N, tool = 1024, 50.0
+    reqs = [{"verts": m.verts, "tris": m.tris, "n_samples": c, "seed": 400 + i, "tool_length": tool}
+            for i, (m, c) in enumerate(zip(meshes, counts))]
+    S = sum(counts)
+    bits = torch.empty((S, N // 32), dtype=torch.int32, device=ctx.device)
+    _say("plan", S, "samples")
+    pl = ctx.plan(reqs, N)
+    pl.run(graph=True)
+    res = pl.run(graph=True, bits=bits)
+    pl.destroy()
+    got = _u32(bits)
+    dirs = orc.fibonacci_dirs(N)
+    off = 0
+    for p, (m, c) in enumerate(zip(meshes, counts)):
+        _say("part", p, m.n_tris, c)
+        s, b1, rep, su = _single(ctx, m, c, 400 + p, N, tool)
+        assert np.array_equal(got[off:off + c], _u32(b1)), p
+        assert res[p]["class"] == rep, p
+        for k in ("min_count", "min_mask", "greedy_count", "greedy_mask", "n_class", "code_hist"):
+            assert res[p]["setups"][k] == su[k], (p, k)
+        if m.n_tris < 20_000:
+            rows = np.array([0, c // 2, c - 1])
+            sn = {k: v.cpu().numpy()[rows] for k, v in s.items()}
+            ob, og, _ = orc.cast(m.verts, m.tris, sn, dirs)
+            assert not ((got[off + rows] ^ ob) & ~og).any(), p
+        off += c
