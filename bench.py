@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--tool-length", type=float, default=50.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rays-per-wave", type=int, default=64)
-    ap.add_argument("--stack", type=int, default=24)
+    ap.add_argument("--stack", type=int, default=20)
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--autotune", action="store_true", help="batch64: sweep the launch shape first")
     ap.add_argument("--rates", default="20,100,200", help="serve: arrival rates (requests/s)")

@@ -188,8 +188,8 @@ hra_status hra_cast_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const h
 
 typedef struct {
     int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
-    int32_t stack_depth;   /* traversal stack entries per lane held in LDS: 16, 24 or 32
-                              (deeper paths overflow into private memory) */
+    int32_t stack_depth;   /* traversal stack entries per lane held in LDS: 16, 20, 24 or
+                              32, default 20 (deeper paths overflow into private memory) */
     int32_t leaf_size;     /* triangles per leaf of builds whose options give 0: 1..8
                               (0 in hra_set_cast_config: keep the current value) */
 } hra_cast_config;
@@ -390,7 +390,7 @@ typedef struct {
 } hra_tune_report;
 
 /* Autotuner for a batch: sweeps rays per wave {64, 128, 256} x stack depth
- * {16, 24, 32} x leaf size {2, 4, 8}, times `reps` runs of a plan for each
+ * {16, 20, 24} x leaf size {2, 4, 8}, times `reps` runs of a plan for each
  * point after one warm-up run, checks that every point gives the same
  * results, and stores the fastest point in the context's cast
  * configuration (hra_get_cast_config).  opts: as for hra_plan_create (its

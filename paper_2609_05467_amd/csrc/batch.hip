@@ -249,7 +249,8 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
     const int rpw = opts->rays_per_wave ? opts->rays_per_wave : ctx->cast_rpw;
     const int stack = opts->stack_depth ? opts->stack_depth : ctx->cast_stack;
     if (rpw != 64 && rpw != 128 && rpw != 256) return ctx->fail(HRA_ERR_INVALID_ARG, "rays_per_wave: 64, 128 or 256");
-    if (stack != 16 && stack != 24 && stack != 32) return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth: 16, 24 or 32");
+    if (stack != 16 && stack != 20 && stack != 24 && stack != 32)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth: 16, 20, 24 or 32");
     const float frac = opts->offset_frac > 0.0f ? opts->offset_frac : 1e-4f;
     if (!(frac <= 0.01f)) return ctx->fail(HRA_ERR_INVALID_ARG, "offset_frac must be in (0, 0.01]");
     hra_dirs hemi = {HRA_DIRS_HEMI_FIBONACCI, N}, ax6 = {HRA_DIRS_AXES6, 6};
@@ -430,7 +431,7 @@ extern "C" hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, 
                                    const hra_batch_opts *opts, int32_t reps, hra_tune_report *out, void *stream) {
     if (!ctx || !parts || !opts || !out) return HRA_ERR_INVALID_ARG;
     if (reps < 1 || reps > 100) return ctx->fail(HRA_ERR_INVALID_ARG, "reps must be in 1..100");
-    static const int RPW[3] = {64, 128, 256}, STK[3] = {16, 24, 32}, LEAF[3] = {2, 4, 8};
+    static const int RPW[3] = {64, 128, 256}, STK[3] = {16, 20, 24}, LEAF[3] = {2, 4, 8};
     std::vector<hra_part_result> ref(n_parts > 0 ? n_parts : 1), got(n_parts > 0 ? n_parts : 1);
     out->n_points = 0;
     out->best = -1;

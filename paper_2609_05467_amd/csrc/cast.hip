@@ -1,24 +1,33 @@
 // Any-hit accessibility cast: BVH traversal with a short per-lane stack in
-// LDS, robust slab tests, FP32 edge functions with an error bound and an FP64
+// LDS, robust slab tests, an FP32 triangle test with error bounds and an FP64
 // fallback, and wave-ballot packing of direction bits.
 //
 // Decision per (ray, triangle), origin o, direction d, a,b,c = v - o:
 //   e0 = d.(b x c), e1 = d.(c x a), e2 = d.(a x b)   (side of each edge)
 //   h  = a.(b x c)                                  (side of the plane)
 // The ray meets the triangle at t > 0 iff all e_i share a sign s (edges
-// inclusive) and h has the sign s.  Each FP32 value is trusted only when its
-// magnitude exceeds K times the sum of the magnitudes of its terms (K covers
-// the rounding of the translated vertices, products and sums); otherwise it is
+// inclusive) and h has the sign s.  In FP32 the same four numbers come, up to
+// sign, from the translated-origin form T = o - A, E1 = B - A, E2 = C - A,
+// P = d x E2, Q = T x E1:
+//   U = T.P = -e1,  V = d.Q = -e2,  det - U - V = -e0 (det = E1.P),  E2.Q = -h
+// (scalar triple products; the identities are exact in real arithmetic).
+// Each FP32 value is trusted only when its magnitude exceeds a bound on its
+// rounding error, written from the largest component M of T, E1, E2 and the
+// largest direction component; otherwise the edge or plane function is
 // recomputed in FP64 from the FP32 inputs.  A sign trusted this way is the
 // exact sign, so a ray whose verdict is not on a knife edge gets the exact
-// answer.  The trust test and the FP64 value are antisymmetric in the two
-// vertices of an edge, so two triangles sharing an edge see it on opposite
-// sides and no ray slips between them.
+// answer, and two triangles sharing an edge see it on opposite sides (exact
+// signs are antisymmetric, and so is the FP64 value), so no ray slips
+// between them.
 #include "common.hpp"
 
 namespace hra {
 
-constexpr float EDGE_K = 1.0e-6f;   // ~16.8 units of FP32 roundoff
+// 16 units of 2^-24 per bounded product term: U, V, det and E2.Q carry at
+// most 7 to 8 roundings each (the translated inputs, the cross product, the
+// dot product), and the recombined third edge function (det - U - V) about 26
+// of the 64 units it is given.
+constexpr float TRI_K = 16.0f * 5.9604645e-8f;
 constexpr int SPILL = 64;           // private overflow entries per lane beyond the LDS stack
 
 __device__ __noinline__ int edge_sign64(float ox, float oy, float oz, float dx, float dy, float dz, float4 P, float4 Q) {
@@ -40,31 +49,33 @@ __device__ __noinline__ int plane_sign64(float ox, float oy, float oz, float4 A,
     return (h > 0.0) - (h < 0.0);
 }
 
-// FP32 edge function of edge (P, Q) with its trust bound.  Returns +1/-1 when
-// the sign is certain, 2 when it is not.
-__device__ inline int edge_sign32(float dx, float dy, float dz, float px, float py, float pz, float qx, float qy,
-                                  float qz) {
-    const float p1 = py * qz, p2 = pz * qy, p3 = pz * qx, p4 = px * qz, p5 = px * qy, p6 = py * qx;
-    const float X = p1 - p2, Y = p3 - p4, Z = p5 - p6;
-    const float e = fmaf(dz, Z, fmaf(dy, Y, dx * X));
-    const float m = fmaf(fabsf(dz), fabsf(p5) + fabsf(p6),
-                         fmaf(fabsf(dy), fabsf(p3) + fabsf(p4), fabsf(dx) * (fabsf(p1) + fabsf(p2))));
-    const float bound = EDGE_K * m;
-    if (e > bound) return 1;
-    if (e < -bound) return -1;
-    return 2;
-}
-
-__device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy, float dz, float4 A, float4 B, float4 C) {
-    const float ax = A.x - ox, ay = A.y - oy, az = A.z - oz;
-    const float bx = B.x - ox, by = B.y - oy, bz = B.z - oz;
-    const float cx = C.x - ox, cy = C.y - oy, cz = C.z - oz;
-    int s0 = edge_sign32(dx, dy, dz, bx, by, bz, cx, cy, cz);
-    int s1 = edge_sign32(dx, dy, dz, cx, cy, cz, ax, ay, az);
+// kd = 6 * TRI_K * max|d_i|, a per-ray constant.  Every product term of U,
+// V and det is at most max|d_i| * M^2 and there are six of them; those of
+// E2.Q at most M^3.  M has a floor so that a bound never underflows below the
+// absolute error of subnormal results.
+__device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy, float dz, float kd, float4 A, float4 B,
+                               float4 C) {
+    const float tx = ox - A.x, ty = oy - A.y, tz = oz - A.z;
+    const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z;
+    const float e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
+    const float M = fmaxf(fmaxf(fmaxf(fmaxf(fabsf(tx), fabsf(ty)), fmaxf(fabsf(tz), 1e-12f)),
+                                fmaxf(fmaxf(fabsf(e1x), fabsf(e1y)), fabsf(e1z))),
+                          fmaxf(fmaxf(fabsf(e2x), fabsf(e2y)), fabsf(e2z)));
+    const float MM = M * M;
+    const float bd = kd * MM;
+    const float px = fmaf(dy, e2z, -(dz * e2y)), py = fmaf(dz, e2x, -(dx * e2z)), pz = fmaf(dx, e2y, -(dy * e2x));
+    const float U = fmaf(tz, pz, fmaf(ty, py, tx * px));
+    const float qx = fmaf(ty, e1z, -(tz * e1y)), qy = fmaf(tz, e1x, -(tx * e1z)), qz = fmaf(tx, e1y, -(ty * e1x));
+    const float V = fmaf(dz, qz, fmaf(dy, qy, dx * qx));
+    int s1 = U > bd ? -1 : (U < -bd ? 1 : 2);
+    int s2 = V > bd ? -1 : (V < -bd ? 1 : 2);
     // certain opposite signs: the line misses the triangle
-    if ((s0 == 1 && s1 == -1) || (s0 == -1 && s1 == 1)) return false;
-    int s2 = edge_sign32(dx, dy, dz, ax, ay, az, bx, by, bz);
-    if ((s2 == 1 && (s0 == -1 || s1 == -1)) || (s2 == -1 && (s0 == 1 || s1 == 1))) return false;
+    if ((s1 == 1 && s2 == -1) || (s1 == -1 && s2 == 1)) return false;
+    const float det = fmaf(e1z, pz, fmaf(e1y, py, e1x * px));
+    const float W = (det - U) - V;
+    const float bw = 4.0f * bd;
+    int s0 = W > bw ? -1 : (W < -bw ? 1 : 2);
+    if ((s0 == 1 && (s1 == -1 || s2 == -1)) || (s0 == -1 && (s1 == 1 || s2 == 1))) return false;
     if (s0 == 2) s0 = edge_sign64(ox, oy, oz, dx, dy, dz, B, C);
     if (s1 == 2) s1 = edge_sign64(ox, oy, oz, dx, dy, dz, C, A);
     if (s2 == 2) s2 = edge_sign64(ox, oy, oz, dx, dy, dz, A, B);
@@ -72,16 +83,11 @@ __device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy,
     if (s0 >= 0 && s1 >= 0 && s2 >= 0 && (s0 | s1 | s2)) s = 1;
     else if (s0 <= 0 && s1 <= 0 && s2 <= 0 && (s0 | s1 | s2)) s = -1;
     else return false;
-    // plane side: h = a.(b x c)
-    const float p1 = by * cz, p2 = bz * cy, p3 = bz * cx, p4 = bx * cz, p5 = bx * cy, p6 = by * cx;
-    const float X = p1 - p2, Y = p3 - p4, Z = p5 - p6;
-    const float h = fmaf(az, Z, fmaf(ay, Y, ax * X));
-    const float m = fmaf(fabsf(az), fabsf(p5) + fabsf(p6),
-                         fmaf(fabsf(ay), fabsf(p3) + fabsf(p4), fabsf(ax) * (fabsf(p1) + fabsf(p2))));
-    const float bound = EDGE_K * m;
+    const float Tn = fmaf(e2z, qz, fmaf(e2y, qy, e2x * qx));
+    const float bt = (6.0f * TRI_K) * MM * M;
     int hs;
-    if (h > bound) hs = 1;
-    else if (h < -bound) hs = -1;
+    if (Tn > bt) hs = -1;
+    else if (Tn < -bt) hs = 1;
     else hs = plane_sign64(ox, oy, oz, A, B, C);
     return hs == s;
 }
@@ -130,7 +136,7 @@ struct WorkCount {
 
 template <bool STATS>
 __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, float ox, float oy, float oz, float dx,
-                                float dy, float dz, int32_t n_tris_alloc, uint32_t *err, WorkCount &wc) {
+                                float dy, float dz, float kd, int32_t n_tris_alloc, uint32_t *err, WorkCount &wc) {
     const int first = leaf_first(code), cnt = leaf_count(code);
     if (first + cnt > n_tris_alloc) {
         atomicOr(err, ERR_STACK);
@@ -139,10 +145,15 @@ __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, f
     for (int k = 0; k < cnt; ++k) {
         const float4 *t = tris + 3 * (int64_t)(first + k);
         if (STATS) ++wc.tris;
-        if (tri_hit(ox, oy, oz, dx, dy, dz, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2))) return true;
+        if (tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2))) return true;
     }
     return false;
 }
+
+// The per-lane stack is addressed through an LDS-typed pointer: a pop then
+// stays an LDS read with a 32-bit address, and cannot be merged with the
+// private overflow read into one generic (flat) access.
+typedef __attribute__((address_space(3))) int lds_int;
 
 // true if some triangle blocks the ray
 // Guards: a node index outside the array, a leaf run outside the triangle
@@ -150,9 +161,10 @@ __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, f
 // and end the ray, so a malformed hierarchy cannot fault or spin.
 template <int STACK, bool STATS>
 __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
-                                float oy, float oz, float dx, float dy, float dz, int *lds, int lane, uint32_t *err,
+                                float oy, float oz, float dx, float dy, float dz, lds_int *lds, int lane, uint32_t *err,
                                 int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
-    if (is_leaf(root)) return leaf_hit<STATS>(tris, root, ox, oy, oz, dx, dy, dz, n_tris_alloc, err, wc);
+    const float kd = (6.0f * TRI_K) * fmaxf(fmaxf(fabsf(dx), fabsf(dy)), fabsf(dz));
+    if (is_leaf(root)) return leaf_hit<STATS>(tris, root, ox, oy, oz, dx, dy, dz, kd, n_tris_alloc, err, wc);
     const float ix = safe_rcp(dx), iy = safe_rcp(dy), iz = safe_rcp(dz);
     int spill[SPILL];
     int sp = 0;
@@ -171,8 +183,20 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
         const bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, ox, oy, oz, ix, iy, iz, t0);
         const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, ox, oy, oz, ix, iy, iz, t1);
         const int32_t c0 = D.x, c1 = D.y;
-        if (h0 && is_leaf(c0) && leaf_hit<STATS>(tris, c0, ox, oy, oz, dx, dy, dz, n_tris_alloc, err, wc)) return true;
-        if (h1 && is_leaf(c1) && leaf_hit<STATS>(tris, c1, ox, oy, oz, dx, dy, dz, n_tris_alloc, err, wc)) return true;
+        // the triangles of both hit leaf children in one loop, [f0, f0 + n0)
+        // then [f1, f1 + n1): lanes with a leaf on either side test together
+        const int32_t n0 = h0 && is_leaf(c0) ? leaf_count(c0) : 0;
+        const int32_t n1 = h1 && is_leaf(c1) ? leaf_count(c1) : 0;
+        const int32_t f0 = leaf_first(c0), f1 = leaf_first(c1);
+        if ((n0 && f0 + n0 > n_tris_alloc) || (n1 && f1 + n1 > n_tris_alloc)) {
+            atomicOr(err, ERR_STACK);
+            return true;
+        }
+        for (int32_t k = 0; k < n0 + n1; ++k) {
+            const float4 *t = tris + 3 * (int64_t)(k < n0 ? f0 + k : f1 + (k - n0));
+            if (STATS) ++wc.tris;
+            if (tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2))) return true;
+        }
         const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
         if (g0 && g1) {
             const int32_t nearc = t0 <= t1 ? c0 : c1, farc = t0 <= t1 ? c1 : c0;
@@ -191,13 +215,40 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
         } else {
             if (sp == 0) return false;
             --sp;
-            node = sp < STACK ? lds[sp * 64 + lane] : spill[sp - STACK];
+            if (sp < STACK) node = lds[sp * 64 + lane];
+            else node = spill[sp - STACK];
         }
     }
 }
 
 // A value that is the same in every lane, moved to a scalar register.
 __device__ inline float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+
+__device__ inline int32_t uni_i(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline int64_t uni_l(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T> __device__ inline T *uni_p(T *p) { return (T *)uni_l((int64_t)p); }
+
+// A job's fields are wave-uniform; the compiler cannot prove it for values
+// loaded from the job table, so they are moved to scalar registers here (the
+// hierarchy pointers, sizes and root then cost no vector registers).
+__device__ inline CastJob uni_job(const CastJob &j) {
+    CastJob u;
+    u.nodes = uni_p(j.nodes);
+    u.tris = uni_p(j.tris);
+    u.meta = uni_p(j.meta);
+    u.origin = uni_p(j.origin);
+    u.normal = uni_p(j.normal);
+    u.bits = uni_p(j.bits);
+    u.n_samples = uni_l(j.n_samples);
+    u.item_base = uni_l(j.item_base);
+    u.n_nodes_alloc = uni_i(j.n_nodes_alloc);
+    u.pad = 0;
+    return u;
+}
 
 // Job of a wave-uniform work item: the last job whose item_base <= item.
 __device__ inline CastJob job_of(const CastArgs &a, int64_t item) {
@@ -221,23 +272,23 @@ __device__ inline CastJob job_of(const CastArgs &a, int64_t item) {
 // at the direction's canonical index; the finished row is stored with
 // coalesced writes.  The item index is the block index, uniform over the
 // workgroup, so both barriers are reached by every thread, and the kernel
-// has no cross-lane operation.  Six waves per SIMD (at most 80 VGPRs, a few
-// spilled) measured fastest: the traversal is latency-bound, so occupancy
-// beats registers.
+// has no cross-lane operation.  Seven waves per SIMD (at most 72 VGPRs, none
+// spilled) measured fastest; with a 20-entry stack seven workgroups also fit
+// in LDS (20.7 KB each).  Eight waves spill and are slower.
 template <int RPW, int STACK, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cast_rows(CastArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_cast_rows(CastArgs a) {
     extern __shared__ int dyn_lds[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t item = blockIdx.x;
     if (item >= a.n_items) return;  // the whole workgroup leaves together
-    int *lds = dyn_lds + wv * (STACK * 64);
+    lds_int *lds = (lds_int *)(dyn_lds + wv * (STACK * 64));
     uint32_t *row = (uint32_t *)(dyn_lds + 4 * STACK * 64);
-    const CastJob J = job_of(a, item);
+    const CastJob J = uni_job(job_of(a, item));
     const PartMeta &P = *J.meta;
-    const int32_t root = P.root;
-    const int32_t n_valid = P.n_valid;
+    const int32_t root = uni_i(P.root);
+    const int32_t n_valid = uni_i(P.n_valid);
     const bool empty = n_valid <= 0;
-    const int32_t n_tris_alloc = P.leaf_lo + n_valid;   // end of this part's leaf run
+    const int32_t n_tris_alloc = uni_i(P.leaf_lo) + n_valid;   // end of this part's leaf run
     const int64_t s = item - J.item_base;
     // the sample, its normal and frame are the same for the whole
     // workgroup: keep them in scalar registers
@@ -284,14 +335,15 @@ constexpr int AX_PER_WAVE = 10;
 template <int STACK, bool STATS>
 __global__ __launch_bounds__(256) void k_cast_axes(CastArgs a) {
     __shared__ int stk[4][STACK * 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = uni_i(threadIdx.x >> 6);
     const int64_t item = (int64_t)blockIdx.x * 4 + wv;
     if (item >= a.n_items) return;
-    const CastJob J = job_of(a, item);
+    const CastJob J = uni_job(job_of(a, item));
     const PartMeta &P = *J.meta;
-    const int32_t root = P.root;
-    const bool empty = P.n_valid <= 0;
-    const int32_t n_tris_alloc = P.leaf_lo + P.n_valid;
+    const int32_t root = uni_i(P.root);
+    const int32_t n_valid = uni_i(P.n_valid);
+    const bool empty = n_valid <= 0;
+    const int32_t n_tris_alloc = uni_i(P.leaf_lo) + n_valid;
     const int64_t s0 = (item - J.item_base) * AX_PER_WAVE;
     const int q = lane / 6, k = lane - 6 * (lane / 6);
     const int64_t s = s0 + q;
@@ -304,7 +356,7 @@ __global__ __launch_bounds__(256) void k_cast_axes(CastArgs a) {
         const float q0 = nx * l.x, q1 = ny * l.y, q2 = nz * l.z;
         const float nd = (q0 + q1) + q2;
         if (!(nd < 0.0f))
-            free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, l.x, l.y, l.z, stk[wv], lane,
+            free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, l.x, l.y, l.z, (lds_int *)stk[wv], lane,
                                                         a.err, J.n_nodes_alloc, n_tris_alloc, wc);
     }
     const uint64_t m = __ballot(free_ray);
@@ -342,6 +394,7 @@ template <int RPW, bool STATS>
 static hipError_t launch_rpw(const CastArgs &a, int stack, hipStream_t s) {
     switch (stack) {
         case 16: return launch_cast<RPW, 16, STATS>(a, s);
+        case 20: return launch_cast<RPW, 20, STATS>(a, s);
         case 32: return launch_cast<RPW, 32, STATS>(a, s);
         default: return launch_cast<RPW, 24, STATS>(a, s);
     }
@@ -394,8 +447,8 @@ extern "C" hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *c
     if (!ctx || !cfg) return HRA_ERR_INVALID_ARG;
     if (cfg->rays_per_wave != 64 && cfg->rays_per_wave != 128 && cfg->rays_per_wave != 256)
         return ctx->fail(HRA_ERR_INVALID_ARG, "rays_per_wave must be 64, 128 or 256");
-    if (cfg->stack_depth != 16 && cfg->stack_depth != 24 && cfg->stack_depth != 32)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth must be 16, 24 or 32");
+    if (cfg->stack_depth != 16 && cfg->stack_depth != 20 && cfg->stack_depth != 24 && cfg->stack_depth != 32)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth must be 16, 20, 24 or 32");
     if (cfg->leaf_size < 0 || cfg->leaf_size > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 0..8");
     ctx->cast_rpw = cfg->rays_per_wave;
     ctx->cast_stack = cfg->stack_depth;

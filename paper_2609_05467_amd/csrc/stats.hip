@@ -18,6 +18,29 @@ struct DirTotals {
 };
 
 constexpr int HIST_BINS = 8192;
+constexpr float HIST_EDGE = 4e-3f;   // bins: distance from an edge below which FP64 decides
+
+// atan(r) on [0, 1] as r * P(r^2): least-squares fit on Chebyshev-spaced
+// nodes, reweighted towards the largest errors; the largest error of the
+// FP32 evaluation is 3.3e-7 rad.
+constexpr float ATAN_C[7] = {0.9999961256980896f, -0.3331736922264099f, 0.19807815551757812f, -0.1323334127664566f,
+                             0.07962365448474884f, -0.033604204654693604f, 0.006811786908656359f};
+
+// (atan2(y, x) + pi) * 64 / pi, the azimuth in histogram-sector units, from
+// the octant and the polynomial above.  x = y = 0 gives NaN, which the
+// caller's edge test sends to the FP64 path.
+__device__ inline float azimuth_bins(float x, float y) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float r = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
+    const float r2 = r * r;
+    float p = ATAN_C[6];
+    for (int k = 5; k >= 0; --k) p = fmaf(p, r2, ATAN_C[k]);
+    float a = r * p;
+    a = ay > ax ? 1.57079637f - a : a;
+    a = x < 0.0f ? 3.14159274f - a : a;
+    a = y < 0.0f ? -a : a;
+    return (a + 3.14159274f) * 20.3718327f;
+}
 
 // One wavefront per sample: lanes stride over the directions, FP64 sums,
 // wave butterfly reduction.  The histogram (when asked for) is privatised in
@@ -54,11 +77,22 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
             sa2 += fabs(dz);
             ++cnt;
             if (hist_part) {
-                const double len = sqrt(dx * dx + dy * dy + dz * dz);
-                const double zh = dz / len;
-                int zb = (int)floor((zh + 1.0) * 32.0);
+                // Bin coordinates in FP32 first; the bin is taken from them
+                // unless they lie within HIST_EDGE of a bin edge, where the
+                // FP64 coordinates decide.  The FP32 coordinates are within
+                // 5e-5 bin of the FP64 ones (hardware reciprocal square root
+                // and reciprocal, 1 ulp; arctangent polynomial, 3.3e-7 rad),
+                // so both give the same bin.
+                const float len2 = fmaf(d.x, d.x, fmaf(d.y, d.y, d.z * d.z));
+                const float xz = fmaf(d.z * __builtin_amdgcn_rsqf(len2), 32.0f, 32.0f);
+                const float xa = azimuth_bins(d.x, d.y);
+                const float fz = xz - floorf(xz), fa = xa - floorf(xa);
+                int zb, az;
+                if (fz > HIST_EDGE && fz < 1.0f - HIST_EDGE) zb = (int)floorf(xz);
+                else zb = (int)floor((dz / sqrt(dx * dx + dy * dy + dz * dz) + 1.0) * 32.0);
+                if (fa > HIST_EDGE && fa < 1.0f - HIST_EDGE) az = (int)floorf(xa);
+                else az = (int)floor((atan2(dy, dx) + pi) * 128.0 / (2.0 * pi));
                 zb = zb > 63 ? 63 : (zb < 0 ? 0 : zb);
-                int az = (int)floor((atan2(dy, dx) + pi) * 128.0 / (2.0 * pi));
                 az = az > 127 ? 127 : (az < 0 ? 0 : az);
                 atomicAdd(&h[zb * 128 + az], 1u);
             }

@@ -325,7 +325,7 @@ class Context:
         self._check(lib().hra_dirs_table(self.ptr, Dirs(kind, n), out.ctypes.data_as(C.c_void_p)))
         return out
 
-    def set_cast_config(self, rays_per_wave=64, stack_depth=24, leaf_size=0):
+    def set_cast_config(self, rays_per_wave=64, stack_depth=20, leaf_size=0):
         self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth, leaf_size))))
 
     def cast_config(self):
