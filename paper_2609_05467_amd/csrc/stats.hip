@@ -18,7 +18,7 @@ struct DirTotals {
 };
 
 constexpr int HIST_BINS = 8192;
-constexpr float HIST_EDGE = 4e-3f;   // bins: distance from an edge below which FP64 decides
+constexpr float HIST_EDGE = 5e-4f;   // bins: distance from an edge below which FP64 decides
 
 // atan(r) on [0, 1] as r * P(r^2): least-squares fit on Chebyshev-spaced
 // nodes, reweighted towards the largest errors; the largest error of the
@@ -45,8 +45,8 @@ __device__ inline float azimuth_bins(float x, float y) {
 // One wavefront per sample: lanes stride over the directions, FP64 sums,
 // wave butterfly reduction.  The histogram (when asked for) is privatised in
 // LDS per block and written out without atomics to a per-block slice;
-// k_hist_reduce sums the slices in a fixed order.  Part totals are formed
-// afterwards from the per-sample outputs by k_part_totals.
+// k_hist_reduce sums the slices (integer sums: the same in any order).  Part
+// totals are formed afterwards from the per-sample outputs by k_part_totals.
 __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n, const float4 *dirs, int32_t N,
                                                   int32_t W, const uint32_t *bits, hra_dirstats out, double *conc64,
                                                   uint32_t *cnt_out, uint32_t *hist_part) {
@@ -135,18 +135,19 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
 
 // Part totals, one block per part over its sample range [base, base + n)
 // (base == NULL: one part, range [0, n_one)): integer counts, and the FP64
-// sum of concentrations in a fixed order (thread t sums a contiguous chunk
-// in order, then a fixed tree).
-__global__ void k_part_totals(const int8_t *axis, const uint32_t *cnt, const double *conc64, const int64_t *base,
-                              const int64_t *count, int64_t n_one, DirTotals *tot) {
-    __shared__ double sc[256];
-    __shared__ unsigned long long si[5][256];
+// sum of concentrations in a fixed order (thread t sums samples t, t + 1024,
+// ... in order, then a fixed tree), so the result does not depend on timing.
+constexpr int PT_THREADS = 1024;
+__global__ __launch_bounds__(PT_THREADS) void k_part_totals(const int8_t *axis, const uint32_t *cnt,
+                                                            const double *conc64, const int64_t *base,
+                                                            const int64_t *count, int64_t n_one, DirTotals *tot) {
+    __shared__ double sc[PT_THREADS];
+    __shared__ unsigned long long si[5][PT_THREADS];
     const int p = blockIdx.x, t = threadIdx.x;
     const int64_t b0 = base ? base[p] : 0, n = base ? count[p] : n_one;
-    const int64_t chunk = (n + 255) / 256;
     double acc = 0.0;
     unsigned long long a0 = 0, a1 = 0, a2 = 0, bl = 0, un = 0;
-    for (int64_t i = b0 + t * chunk; i < b0 + n && i < b0 + (t + 1) * chunk; ++i) {
+    for (int64_t i = b0 + t; i < b0 + n; i += PT_THREADS) {
         acc += conc64[i];
         const int k = axis[i];
         a0 += k == 0;
@@ -162,7 +163,7 @@ __global__ void k_part_totals(const int8_t *axis, const uint32_t *cnt, const dou
     si[3][t] = bl;
     si[4][t] = un;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = PT_THREADS / 2; off > 0; off >>= 1) {
         if (t < off) {
             sc[t] += sc[t + off];
             for (int q = 0; q < 5; ++q) si[q][t] += si[q][t + off];
@@ -180,13 +181,16 @@ __global__ void k_part_totals(const int8_t *axis, const uint32_t *cnt, const dou
     }
 }
 
-// hist[b] = sum over blocks of hist_part[block][b], in block order.
+// hist[b] += sum over a range of blocks of hist_part[block][b]: blockIdx.y
+// takes blocks y, y + HR_CHUNKS, ...; the sums are integers, so the atomic
+// additions give the same histogram in any order.  hist starts at zero.
+constexpr int HR_CHUNKS = 32;
 __global__ void k_hist_reduce(const uint32_t *hist_part, int nblocks, uint32_t *hist) {
     const int bin = blockIdx.x * blockDim.x + threadIdx.x;
     if (bin >= HIST_BINS) return;
     uint32_t acc = 0;
-    for (int b = 0; b < nblocks; ++b) acc += hist_part[(int64_t)b * HIST_BINS + bin];
-    hist[bin] = acc;
+    for (int b = blockIdx.y; b < nblocks; b += HR_CHUNKS) acc += hist_part[(int64_t)b * HIST_BINS + bin];
+    if (acc) atomicAdd(&hist[bin], acc);
 }
 
 // Reach, fixture faces, classes and the histogram of reachable-direction
@@ -382,7 +386,8 @@ hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const f
     }
     k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(normal, n, table, N, (N + 31) / 32, bits, out, c64, cnt, part);
     if (hist) {
-        k_hist_reduce<<<HIST_BINS / 256, 256, 0, s>>>(part, (int)blocks, out.hist);
+        k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out.hist, HIST_BINS);
+        k_hist_reduce<<<dim3(HIST_BINS / 256, HR_CHUNKS), 256, 0, s>>>(part, (int)blocks, out.hist);
         hipFreeAsync(part, s);
     }
     return hipGetLastError();
@@ -390,7 +395,7 @@ hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const f
 
 hipError_t launch_part_totals(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,
                               const int64_t *d_count, int n_parts, DirTotals *tot, hipStream_t s) {
-    k_part_totals<<<n_parts, 256, 0, s>>>(axis, cnt, c64, d_base, d_count, 0, tot);
+    k_part_totals<<<n_parts, PT_THREADS, 0, s>>>(axis, cnt, c64, d_base, d_count, 0, tot);
     return hipGetLastError();
 }
 
@@ -497,12 +502,12 @@ extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples
         // no samples: an empty histogram and zero totals (fill kernels, so
         // the call can be captured in a graph)
         k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out->hist, HIST_BINS);
-        k_part_totals<<<1, 256, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nullptr, 0, tot);
+        k_part_totals<<<1, PT_THREADS, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nullptr, 0, tot);
         HRA_HIP(hipGetLastError());
         return HRA_OK;
     }
     HRA_HIP(launch_dirstats(ctx, samples->normal, n, table, dirs.n, d_bits, *out, c64, cnt, true, s));
-    k_part_totals<<<1, 256, 0, s>>>(out->axis, cnt, c64, nullptr, nullptr, n, tot);
+    k_part_totals<<<1, PT_THREADS, 0, s>>>(out->axis, cnt, c64, nullptr, nullptr, n, tot);
     HRA_HIP(hipGetLastError());
     return HRA_OK;
 }
