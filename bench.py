@@ -36,11 +36,14 @@ WORKLOADS = {
 }
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 NODE_BYTES, TRI_BYTES = 64, 48  # one interior-node record, one leaf triangle
-# FP32 vector operations the cast performs: two slab tests per node visit
-# (25 each), one triangle test (93: translation, three edge functions and
-# the plane side, each with its error bound), ray set-up (rotation and three
-# reciprocals, 18).
-NODE_OPS, TRI_OPS, RAY_OPS = 50, 93, 18
+# FP32 vector operations the cast performs: per node visit two slab tests
+# (22 each: 6 differences, 6 products, 9 min/max, the widening product and the
+# compare) and the leaf decoding (6); per triangle test 54 (the translated
+# vertex and two edges, 9; the largest component, 5; the two bounds, 4; the
+# cross products P and Q, 12; U, V, det and Tn, 12; the third edge, 2; the
+# compares, 10); per ray 20 (rotation 9, three guarded reciprocals 9, the
+# bound factor 2).
+NODE_OPS, TRI_OPS, RAY_OPS = 50, 54, 20
 # VALU lane operations per second: 256 CUs x 64 lanes x 2.4 GHz, one
 # operation per lane per clock without packed FP32 (the published 157.3
 # TFLOP/s counts an FMA as two and packed FP32 twice again).
