@@ -48,6 +48,12 @@ NODE_OPS, TRI_OPS, RAY_OPS = 50, 54, 20
 # operation per lane per clock without packed FP32 (the published 157.3
 # TFLOP/s counts an FMA as two and packed FP32 twice again).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+TRAVERSAL = {"step": 1, "leaf_loop": 2}     # hra.h HRA_TRAVERSAL_*
+# the traversal loop measured faster on each workload's part (the 1M-triangle
+# part tests 3.8 triangles per ray, and there lanes kept in step on the tree
+# win; elsewhere one unit of work per iteration does)
+DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "multiaxis_1m": "leaf_loop",
+                     "batch64": "step", "serve": "step"}
 
 
 def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
@@ -123,6 +129,9 @@ def main():
     ap.add_argument("--rays-per-wave", type=int, default=64)
     ap.add_argument("--stack", type=int, default=20)
     ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--traversal", choices=("step", "leaf_loop"), default=None,
+                    help="traversal loop of the casts (same results; see hra.h); default: the one measured "
+                         "faster for the workload's part")
     ap.add_argument("--autotune", action="store_true", help="batch64: sweep the launch shape first")
     ap.add_argument("--rates", default="20,100,200", help="serve: arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=600, help="serve: requests per rate and mode")
@@ -135,6 +144,8 @@ def main():
                     help="before timing, copy this many MiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.traversal is None:
+        args.traversal = DEFAULT_TRAVERSAL[args.workload]
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by part and "
               "by samples with no exchange, see the design notes)", file=sys.stderr)
@@ -157,7 +168,7 @@ def main():
     log(f"[bench] generating {part_name}")
     mesh = parts.workload_parts(part_name)[0]
     ctx = hra.Context(0)
-    ctx.set_cast_config(args.rays_per_wave, args.stack)
+    ctx.set_cast_config(args.rays_per_wave, args.stack, 0, TRAVERSAL[args.traversal])
     dev = ctx.device
     verts = torch.tensor(mesh.verts, device=dev)
     tris = torch.tensor(mesh.tris, device=dev)
@@ -240,7 +251,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "triangles": mesh.n_tris, "samples": S, "directions": N,
                    "rays_per_step": rays, "leaf_size": args.leaf, "rays_per_wave": args.rays_per_wave,
-                   "stack_depth": args.stack, "tool_length_mm": args.tool_length},
+                   "stack_depth": args.stack, "traversal": args.traversal, "tool_length_mm": args.tool_length},
         "parts_per_s": args.steps / dt,
         "stage_ms": {k: round(float(np.mean(v)), 3) for k, v in ev.items()},
         "cast_rays_per_s": rays / (cast_ms * 1e-3),
@@ -299,7 +310,7 @@ def batch_compare(args, meshes, counts, steps, work=False):
     from paper_2609_05467_amd import hra
     ctx = hra.Context(0)
     dev = ctx.device
-    ctx.set_cast_config(args.rays_per_wave, args.stack, args.leaf)
+    ctx.set_cast_config(args.rays_per_wave, args.stack, args.leaf, TRAVERSAL[args.traversal])
     dm = [(torch.tensor(m.verts, device=dev), torch.tensor(m.tris, device=dev)) for m in meshes]
     reqs = [{"verts": v, "tris": t, "n_samples": c, "seed": 400 + i, "tool_length": args.tool_length}
             for i, ((v, t), c) in enumerate(zip(dm, counts))]
@@ -307,10 +318,10 @@ def batch_compare(args, meshes, counts, steps, work=False):
     rays = S * N
     tune = None
     if args.autotune:
-        log("[bench] autotune sweep (27 points)")
+        log("[bench] autotune sweep (18 points)")
         tune = ctx.autotune(reqs, N, reps=1)
         log(f"[bench] best {tune['best']}")
-    rpw, stack, leaf = ctx.cast_config()
+    rpw, stack, leaf, trav = ctx.cast_config()
 
     # plain: one part after another
     W = (N + 31) // 32
@@ -389,7 +400,7 @@ def batch_compare(args, meshes, counts, steps, work=False):
                    "triangles_min_max": [int(min(m.n_tris for m in meshes)), int(max(m.n_tris for m in meshes))],
                    "samples": S, "samples_min_max": [min(counts), max(counts)], "directions": N,
                    "rays_per_step": rays, "leaf_size": leaf, "rays_per_wave": rpw, "stack_depth": stack,
-                   "tool_length_mm": args.tool_length},
+                   "traversal": {v: k for k, v in TRAVERSAL.items()}[trav], "tool_length_mm": args.tool_length},
         "parts_per_s": len(meshes) / graph_s,
         "batched_graph": {"ms": graph_s * 1e3, "parts_per_s": len(meshes) / graph_s, "rays_per_s": rays / graph_s},
         "batched_eager": {"ms": eager_s * 1e3, "parts_per_s": len(meshes) / eager_s, "rays_per_s": rays / eager_s},

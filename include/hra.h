@@ -186,16 +186,29 @@ hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_sampl
 hra_status hra_cast_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples, hra_dirs dirs,
                          uint32_t *d_bits, uint32_t *d_counts, void *stream);
 
+/* Traversal loops of the casts.  Both visit the same nodes and test the same
+ * triangles in the same order, so results are identical; which is faster
+ * depends on the part (the autotuner measures it).
+ *   HRA_TRAVERSAL_STEP: one unit of work per lane and loop iteration, a
+ *     triangle test or a stack pop and node visit (lanes at a leaf and lanes
+ *     inside the tree advance together);
+ *   HRA_TRAVERSAL_LEAF_LOOP: one node visit per iteration, then the
+ *     triangles of its hit leaf children (lanes stay in step on the tree). */
+#define HRA_TRAVERSAL_STEP 1
+#define HRA_TRAVERSAL_LEAF_LOOP 2
+
 typedef struct {
     int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
     int32_t stack_depth;   /* traversal stack entries per lane held in LDS: 16, 20, 24 or
                               32, default 20 (deeper paths overflow into private memory) */
     int32_t leaf_size;     /* triangles per leaf of builds whose options give 0: 1..8
                               (0 in hra_set_cast_config: keep the current value) */
+    int32_t traversal;     /* HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP
+                              (0 in hra_set_cast_config: keep the current value) */
 } hra_cast_config;
 
 /* Launch shape of hra_cast_hemisphere and default leaf size for this
- * context (defaults 64 / 24 / 4).  Results do not depend on it; only speed
+ * context (defaults 64 / 20 / 4 / HRA_TRAVERSAL_STEP).  Results do not depend on it; only speed
  * does. */
 hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *cfg);
 hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
@@ -327,6 +340,7 @@ typedef struct {
     int32_t leaf_size;                  /* 0 = default (4) */
     int32_t rays_per_wave;              /* 0 = the context's cast configuration */
     int32_t stack_depth;                /* 0 = the context's cast configuration */
+    int32_t traversal;                  /* 0 = the context's cast configuration */
     float offset_frac;                  /* 0 = 1e-4 */
     const hra_thresholds *thresholds;   /* NULL = defaults */
 } hra_batch_opts;
@@ -354,7 +368,7 @@ hra_status hra_batch_run(hra_ctx *ctx, const hra_part_request *parts, int32_t n_
  * slots for its results, allocated once.  The part meshes are read at each
  * run, so they must stay allocated (their contents may change, their sizes
  * may not) until the plan is destroyed.  The launch shape (rays per wave,
- * stack depth, leaf size) is fixed at creation. */
+ * stack depth, leaf size, traversal) is fixed at creation. */
 typedef struct hra_plan hra_plan;
 hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *parts, int32_t n_parts, const hra_batch_opts *opts,
                            hra_plan **out);
@@ -380,18 +394,20 @@ typedef struct {
     int32_t rays_per_wave;
     int32_t stack_depth;
     int32_t leaf_size;
+    int32_t traversal;
     float ms;              /* mean time of one whole run of the batch (build to setups) */
 } hra_tune_point;
 
 typedef struct {
     int32_t n_points;
     int32_t best;          /* index of the fastest point */
-    hra_tune_point points[27];
+    hra_tune_point points[27];   /* the first n_points are used */
 } hra_tune_report;
 
-/* Autotuner for a batch: sweeps rays per wave {64, 128, 256} x stack depth
- * {16, 20, 24} x leaf size {2, 4, 8}, times `reps` runs of a plan for each
- * point after one warm-up run, checks that every point gives the same
+/* Autotuner for a batch: sweeps rays per wave {64, 128, 256} x traversal
+ * {STEP, LEAF_LOOP} x leaf size {2, 4, 8} (18 points; the stack depth is
+ * opts->stack_depth, 0 = the context's), times `reps` runs of a plan for
+ * each point after one warm-up run, checks that every point gives the same
  * results, and stores the fastest point in the context's cast
  * configuration (hra_get_cast_config).  opts: as for hra_plan_create (its
  * launch-shape fields are overridden).  Synchronises `stream`. */

@@ -148,7 +148,7 @@ hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B
         a.n_items = sh.items;
         a.err = err;
         a.work = nullptr;
-        e = launch_cast_any(a, sh.rpw, sh.stack, false, s);
+        e = launch_cast_any(a, sh.rpw, sh.stack, sh.trav, false, s);
     }
     if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
     hra_dirstats ds = {B.mean, B.absm, B.axis, B.conc, nullptr, nullptr};
@@ -168,7 +168,7 @@ hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B
         a.n_items = sh.aitems;
         a.err = err;
         a.work = nullptr;
-        e = launch_cast_any(a, 64, sh.stack, false, s);
+        e = launch_cast_any(a, 64, sh.stack, sh.trav, false, s);
     }
     if (ev && e == hipSuccess) e = hipEventRecord(ev[4], s);
     if (e == hipSuccess) e = launch_setups_raw(B.dsetj, sh.n_jobs, sh.S, B.pt, B.tri, B.abits, B.cc, B.chist, err, s);
@@ -251,6 +251,9 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
     if (rpw != 64 && rpw != 128 && rpw != 256) return ctx->fail(HRA_ERR_INVALID_ARG, "rays_per_wave: 64, 128 or 256");
     if (stack != 16 && stack != 20 && stack != 24 && stack != 32)
         return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth: 16, 20, 24 or 32");
+    const int trav = opts->traversal ? opts->traversal : ctx->cast_traversal;
+    if (trav != HRA_TRAVERSAL_STEP && trav != HRA_TRAVERSAL_LEAF_LOOP)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "traversal: 0, HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP");
     const float frac = opts->offset_frac > 0.0f ? opts->offset_frac : 1e-4f;
     if (!(frac <= 0.01f)) return ctx->fail(HRA_ERR_INVALID_ARG, "offset_frac must be in (0, 0.01]");
     hra_dirs hemi = {HRA_DIRS_HEMI_FIBONACCI, N}, ax6 = {HRA_DIRS_AXES6, 6};
@@ -318,6 +321,7 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
     sh.W = W;
     sh.rpw = rpw;
     sh.stack = stack;
+    sh.trav = trav;
     sh.t_hemi = t_hemi;
     sh.t_ax = t_ax;
     HostJobs H;
@@ -431,18 +435,20 @@ extern "C" hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, 
                                    const hra_batch_opts *opts, int32_t reps, hra_tune_report *out, void *stream) {
     if (!ctx || !parts || !opts || !out) return HRA_ERR_INVALID_ARG;
     if (reps < 1 || reps > 100) return ctx->fail(HRA_ERR_INVALID_ARG, "reps must be in 1..100");
-    static const int RPW[3] = {64, 128, 256}, STK[3] = {16, 20, 24}, LEAF[3] = {2, 4, 8};
+    static const int RPW[3] = {64, 128, 256}, TRAV[2] = {HRA_TRAVERSAL_STEP, HRA_TRAVERSAL_LEAF_LOOP}, LEAF[3] = {2, 4, 8};
+    const int stack = opts->stack_depth ? opts->stack_depth : ctx->cast_stack;
     std::vector<hra_part_result> ref(n_parts > 0 ? n_parts : 1), got(n_parts > 0 ? n_parts : 1);
     out->n_points = 0;
     out->best = -1;
     float best_ms = 0.0f;
     for (int li = 0; li < 3; ++li)
         for (int ri = 0; ri < 3; ++ri)
-            for (int si = 0; si < 3; ++si) {
+            for (int ti = 0; ti < 2; ++ti) {
                 hra_batch_opts o = *opts;
                 o.leaf_size = LEAF[li];
                 o.rays_per_wave = RPW[ri];
-                o.stack_depth = STK[si];
+                o.stack_depth = stack;
+                o.traversal = TRAV[ti];
                 hra_plan *P = nullptr;
                 hra_status st = hra_plan_create(ctx, parts, n_parts, &o, &P);
                 if (st != HRA_OK) return st;
@@ -462,8 +468,9 @@ extern "C" hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, 
                     return ctx->fail(HRA_ERR_DEVICE, "autotuner: results differ between launch shapes");
                 hra_tune_point &pt = out->points[out->n_points];
                 pt.rays_per_wave = RPW[ri];
-                pt.stack_depth = STK[si];
+                pt.stack_depth = stack;
                 pt.leaf_size = LEAF[li];
+                pt.traversal = TRAV[ti];
                 pt.ms = (float)(sum / reps);
                 if (out->best < 0 || pt.ms < best_ms) {
                     out->best = out->n_points;
@@ -475,5 +482,6 @@ extern "C" hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, 
     ctx->cast_rpw = b.rays_per_wave;
     ctx->cast_stack = b.stack_depth;
     ctx->leaf_default = b.leaf_size;
+    ctx->cast_traversal = b.traversal;
     return HRA_OK;
 }

@@ -155,12 +155,107 @@ __device__ inline bool leaf_hit(const float4 *__restrict__ tris, int32_t code, f
 // private overflow read into one generic (flat) access.
 typedef __attribute__((address_space(3))) int lds_int;
 
-// true if some triangle blocks the ray
 // Guards: a node index outside the array, a leaf run outside the triangle
 // array, or more node visits than twice the node count set the error word
 // and end the ray, so a malformed hierarchy cannot fault or spin.
 template <int STACK, bool STATS>
-__device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
+__device__ inline bool occluded_step(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
+                                float oy, float oz, float dx, float dy, float dz, lds_int *lds, int lane, uint32_t *err,
+                                int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
+    const float kd = (6.0f * TRI_K) * fmaxf(fmaxf(fabsf(dx), fabsf(dy)), fabsf(dz));
+    if (is_leaf(root)) return leaf_hit<STATS>(tris, root, ox, oy, oz, dx, dy, dz, kd, n_tris_alloc, err, wc);
+    const float ix = safe_rcp(dx), iy = safe_rcp(dy), iz = safe_rcp(dz);
+    int spill[SPILL];
+    int sp = 0;
+    int32_t node = root;      // next interior node to visit, or -1: take the stack
+    int32_t ti = 0, tn = 0;   // the leaf under test: triangles [ti, ti + tn)
+    int32_t budget = 2 * n_nodes_alloc + 64;
+    // One unit of work per iteration: a triangle test while the lane holds a
+    // leaf, otherwise a stack pop and/or a node visit.  Lanes at a leaf and
+    // lanes inside the tree thus advance in the same iteration instead of the
+    // tree lanes idling through a leaf loop.  The loop has a single back edge
+    // (no continue), so the compiler keeps it one loop rather than nesting a
+    // triangle loop inside it (see also the asm below).  The visit order is that of a plain recursive
+    // traversal: hit leaf children first (child 0 before child 1; a second
+    // leaf waits on top of the stack), then the nearer interior child, the
+    // farther one pushed.
+    while (true) {
+        // the empty asm hides tn's value from the optimiser, which would
+        // otherwise thread "tn still > 0" back into an inner triangle loop
+        asm volatile("" : "+v"(tn));
+        if (tn > 0) {
+            const float4 *t = tris + 3 * (int64_t)ti;
+            if (STATS) ++wc.tris;
+            if (tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2))) return true;
+            ++ti;
+            --tn;
+        } else {
+            bool visit = true;
+            if (node < 0) {
+                if (sp == 0) return false;
+                --sp;
+                int32_t item;
+                if (sp < STACK) item = lds[sp * 64 + lane];
+                else item = spill[sp - STACK];
+                if (is_leaf(item)) {
+                    ti = leaf_first(item);
+                    tn = leaf_count(item);
+                    if (ti + tn > n_tris_alloc) {
+                        atomicOr(err, ERR_STACK);
+                        return true;
+                    }
+                    visit = false;
+                } else {
+                    node = item;
+                }
+            }
+            if (visit) {
+                if ((uint32_t)node >= (uint32_t)n_nodes_alloc || --budget < 0) {
+                    atomicOr(err, ERR_STACK);
+                    return true;
+                }
+                const Node *nd = nodes + node;
+                if (STATS) ++wc.nodes;
+                const float4 A = gload_f4(&nd->a), B = gload_f4(&nd->b), C = gload_f4(&nd->c);
+                const int4 D = gload_i4(&nd->d);
+                float t0, t1;
+                const bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, ox, oy, oz, ix, iy, iz, t0);
+                const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, ox, oy, oz, ix, iy, iz, t1);
+                const int32_t c0 = D.x, c1 = D.y;
+                const bool l0 = h0 && is_leaf(c0), l1 = h1 && is_leaf(c1);
+                const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
+                if (l0 || l1) {
+                    const int32_t lc = l0 ? c0 : c1;
+                    ti = leaf_first(lc);
+                    tn = leaf_count(lc);
+                    if (ti + tn > n_tris_alloc || (l0 && l1 && leaf_first(c1) + leaf_count(c1) > n_tris_alloc)) {
+                        atomicOr(err, ERR_STACK);
+                        return true;
+                    }
+                }
+                // at most one push per visit: the second leaf, or the farther
+                // of two interior children (a node with two leaf children has
+                // no interior one)
+                const bool push = (l0 && l1) || (g0 && g1);
+                const int32_t pv = (l0 && l1) ? c1 : (t0 <= t1 ? c1 : c0);
+                node = (g0 && g1) ? (t0 <= t1 ? c0 : c1) : (g0 ? c0 : (g1 ? c1 : -1));
+                if (push) {
+                    if (sp < STACK) lds[sp * 64 + lane] = pv;
+                    else if (sp < STACK + SPILL) spill[sp - STACK] = pv;
+                    else {
+                        atomicOr(err, ERR_STACK);
+                        return true;
+                    }
+                    ++sp;
+                }
+            }
+        }
+    }
+}
+
+// One node visit per iteration, then the triangles of its hit leaf children.
+template <int STACK, bool STATS>
+__device__ inline bool occluded_leafloop(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
                                 float oy, float oz, float dx, float dy, float dz, lds_int *lds, int lane, uint32_t *err,
                                 int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
     const float kd = (6.0f * TRI_K) * fmaxf(fmaxf(fabsf(dx), fabsf(dy)), fabsf(dz));
@@ -221,6 +316,23 @@ __device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__
     }
 }
 
+// true if some triangle blocks the ray.  Two traversal loops give the same
+// visits in the same order and the same results; they differ in how a wave's
+// lanes share iterations (HRA_TRAVERSAL_STEP: one unit of work per lane and
+// iteration; HRA_TRAVERSAL_LEAF_LOOP: a node visit per iteration followed by
+// the hit leaves' triangles).  Which is faster depends on the part.
+template <int STACK, bool STATS, bool STEP>
+__device__ inline bool occluded(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
+                                float oy, float oz, float dx, float dy, float dz, lds_int *lds, int lane, uint32_t *err,
+                                int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
+    if constexpr (STEP)
+        return occluded_step<STACK, STATS>(nodes, tris, root, ox, oy, oz, dx, dy, dz, lds, lane, err, n_nodes_alloc,
+                                           n_tris_alloc, wc);
+    else
+        return occluded_leafloop<STACK, STATS>(nodes, tris, root, ox, oy, oz, dx, dy, dz, lds, lane, err,
+                                               n_nodes_alloc, n_tris_alloc, wc);
+}
+
 // A value that is the same in every lane, moved to a scalar register.
 __device__ inline float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
 
@@ -275,7 +387,7 @@ __device__ inline CastJob job_of(const CastArgs &a, int64_t item) {
 // has no cross-lane operation.  Seven waves per SIMD (at most 72 VGPRs, none
 // spilled) measured fastest; with a 20-entry stack seven workgroups also fit
 // in LDS (20.7 KB each).  Eight waves spill and are slower.
-template <int RPW, int STACK, bool STATS>
+template <int RPW, int STACK, bool STATS, bool STEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_cast_rows(CastArgs a) {
     extern __shared__ int dyn_lds[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -310,7 +422,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
                 const float4 l = a.dirs_order[j];
                 idx = __float_as_int(l.w);
                 const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
-                const bool free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, d.x, d.y,
+                const bool free_ray = empty || !occluded<STACK, STATS, STEP>(J.nodes, J.tris, root, ox, oy, oz, d.x, d.y,
                                                                       d.z, lds, lane, a.err, J.n_nodes_alloc,
                                                                       n_tris_alloc, wc);
                 bit = (uint32_t)free_ray << (idx & 31);
@@ -332,7 +444,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
 // the per-sample 6-bit groups are stored after it.
 constexpr int AX_PER_WAVE = 10;
 
-template <int STACK, bool STATS>
+template <int STACK, bool STATS, bool STEP>
 __global__ __launch_bounds__(256) void k_cast_axes(CastArgs a) {
     __shared__ int stk[4][STACK * 64];
     const int lane = threadIdx.x & 63, wv = uni_i(threadIdx.x >> 6);
@@ -356,7 +468,7 @@ __global__ __launch_bounds__(256) void k_cast_axes(CastArgs a) {
         const float q0 = nx * l.x, q1 = ny * l.y, q2 = nz * l.z;
         const float nd = (q0 + q1) + q2;
         if (!(nd < 0.0f))
-            free_ray = empty || !occluded<STACK, STATS>(J.nodes, J.tris, root, ox, oy, oz, l.x, l.y, l.z, (lds_int *)stk[wv], lane,
+            free_ray = empty || !occluded<STACK, STATS, STEP>(J.nodes, J.tris, root, ox, oy, oz, l.x, l.y, l.z, (lds_int *)stk[wv], lane,
                                                         a.err, J.n_nodes_alloc, n_tris_alloc, wc);
     }
     const uint64_t m = __ballot(free_ray);
@@ -375,38 +487,44 @@ __global__ void k_popcount_rows(const uint32_t *bits, int64_t n, int32_t W, uint
     counts[s] = c;
 }
 
-template <int RPW, int STACK, bool STATS>
+template <int RPW, int STACK, bool STATS, bool STEP>
 static hipError_t launch_cast(const CastArgs &args, hipStream_t s) {
     if (args.kind == 1) {
         const int64_t blocks = (args.n_items + 3) / 4;   // four items per block
         if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-        k_cast_axes<STACK, STATS><<<(unsigned)blocks, 256, 0, s>>>(args);
+        k_cast_axes<STACK, STATS, STEP><<<(unsigned)blocks, 256, 0, s>>>(args);
     } else {
         const int64_t blocks = args.n_items;             // one sample per block
         if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
         const size_t lds = sizeof(int) * (4 * STACK * 64 + (size_t)args.W);
-        k_cast_rows<RPW, STACK, STATS><<<(unsigned)blocks, 256, lds, s>>>(args);
+        k_cast_rows<RPW, STACK, STATS, STEP><<<(unsigned)blocks, 256, lds, s>>>(args);
     }
     return hipGetLastError();
 }
 
-template <int RPW, bool STATS>
+template <int RPW, bool STATS, bool STEP>
 static hipError_t launch_rpw(const CastArgs &a, int stack, hipStream_t s) {
     switch (stack) {
-        case 16: return launch_cast<RPW, 16, STATS>(a, s);
-        case 20: return launch_cast<RPW, 20, STATS>(a, s);
-        case 32: return launch_cast<RPW, 32, STATS>(a, s);
-        default: return launch_cast<RPW, 24, STATS>(a, s);
+        case 16: return launch_cast<RPW, 16, STATS, STEP>(a, s);
+        case 20: return launch_cast<RPW, 20, STATS, STEP>(a, s);
+        case 32: return launch_cast<RPW, 32, STATS, STEP>(a, s);
+        default: return launch_cast<RPW, 24, STATS, STEP>(a, s);
     }
 }
 
-hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, bool stats, hipStream_t s) {
-    if (stats) return launch_rpw<64, true>(a, stack, s);
+template <bool STEP>
+static hipError_t launch_mode(const CastArgs &a, int rpw, int stack, bool stats, hipStream_t s) {
+    if (stats) return launch_rpw<64, true, STEP>(a, stack, s);
     switch (rpw) {
-        case 128: return launch_rpw<128, false>(a, stack, s);
-        case 256: return launch_rpw<256, false>(a, stack, s);
-        default: return launch_rpw<64, false>(a, stack, s);
+        case 128: return launch_rpw<128, false, STEP>(a, stack, s);
+        case 256: return launch_rpw<256, false, STEP>(a, stack, s);
+        default: return launch_rpw<64, false, STEP>(a, stack, s);
     }
+}
+
+hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, int traversal, bool stats, hipStream_t s) {
+    return traversal == HRA_TRAVERSAL_LEAF_LOOP ? launch_mode<false>(a, rpw, stack, stats, s)
+                                                : launch_mode<true>(a, rpw, stack, stats, s);
 }
 
 int64_t cast_items(int32_t kind, int64_t n_samples) {
@@ -450,9 +568,12 @@ extern "C" hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *c
     if (cfg->stack_depth != 16 && cfg->stack_depth != 20 && cfg->stack_depth != 24 && cfg->stack_depth != 32)
         return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth must be 16, 20, 24 or 32");
     if (cfg->leaf_size < 0 || cfg->leaf_size > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 0..8");
+    if (cfg->traversal != 0 && cfg->traversal != HRA_TRAVERSAL_STEP && cfg->traversal != HRA_TRAVERSAL_LEAF_LOOP)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "traversal must be 0, HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP");
     ctx->cast_rpw = cfg->rays_per_wave;
     ctx->cast_stack = cfg->stack_depth;
     if (cfg->leaf_size) ctx->leaf_default = cfg->leaf_size;
+    if (cfg->traversal) ctx->cast_traversal = cfg->traversal;
     return HRA_OK;
 }
 
@@ -461,6 +582,7 @@ extern "C" hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *c
     cfg->rays_per_wave = ctx->cast_rpw;
     cfg->stack_depth = ctx->cast_stack;
     cfg->leaf_size = ctx->leaf_default;
+    cfg->traversal = ctx->cast_traversal;
     return HRA_OK;
 }
 
@@ -505,7 +627,7 @@ static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, co
     a.err = ctx->d_err;
     a.work = work;
     if (a.n_items >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many samples for one call");
-    HRA_HIP(launch_cast_any(a, rpw, ctx->cast_stack, work != nullptr, s));
+    HRA_HIP(launch_cast_any(a, rpw, ctx->cast_stack, ctx->cast_traversal, work != nullptr, s));
     if (d_counts) {
         k_popcount_rows<<<blocks_for(samples->n, 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);
         HRA_HIP(hipGetLastError());

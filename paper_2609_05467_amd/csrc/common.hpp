@@ -102,6 +102,7 @@ struct hra_ctx {
     hipStream_t own = nullptr;        // internal stream for table builds
     int32_t cast_rpw = 64;            // directions per wave work item
     int32_t cast_stack = 20;          // LDS stack entries per lane
+    int32_t cast_traversal = HRA_TRAVERSAL_STEP;   // traversal loop (hra.h)
     int32_t leaf_default = 4;         // leaf size of builds whose options give 0
     std::string err;
     std::map<std::pair<int, int>, float4 *> dir_tables;  // (kind, n) -> device float4 [n]
@@ -200,7 +201,7 @@ hipError_t launch_sample(const SampleJob *d_jobs, int32_t n_jobs, const SampleJo
                          float *point, float *normal, float *origin, int32_t *tri, hipStream_t s);
 CastJob make_cast_job(const hra_bvh *bvh, int32_t part, const float *origin, const float *normal, uint32_t *bits,
                       int64_t n_samples, int64_t item_base);
-hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, bool stats, hipStream_t s);
+hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, int traversal, bool stats, hipStream_t s);
 // Work items of a cast over n samples: one per sample (hemisphere), one per
 // ten samples (six axes).
 int64_t cast_items(int32_t kind, int64_t n_samples);

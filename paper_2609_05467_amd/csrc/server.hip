@@ -254,6 +254,7 @@ void launch_batch(hra_server *sv, const std::vector<uint64_t> &tickets) {
     sh.W = (sh.N + 31) / 32;
     sh.rpw = sv->ctx->cast_rpw;
     sh.stack = sv->ctx->cast_stack;
+    sh.trav = sv->ctx->cast_traversal;
     sh.t_hemi = sv->t_hemi;
     sh.t_ax = sv->t_ax;
     int64_t S = 0;

@@ -21,6 +21,7 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "BA
 SAMPLE_AREA, SAMPLE_CENTROID = 0, 1
 SERVE_CONTINUOUS, SERVE_PLAIN = 0, 1
 DIRS_HEMI, DIRS_AXES6 = 0, 1
+TRAVERSAL_STEP, TRAVERSAL_LEAF_LOOP = 1, 2
 CLASS_VIABLE, CLASS_OVER, CLASS_INACCESSIBLE, CLASS_FIXTURE = 0, 1, 2, 3
 
 
@@ -49,7 +50,8 @@ class Dirs(C.Structure):
 
 
 class CastConfig(C.Structure):
-    _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32), ("leaf_size", C.c_int32)]
+    _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32), ("leaf_size", C.c_int32),
+                ("traversal", C.c_int32)]
 
 
 class DirStats(C.Structure):
@@ -87,12 +89,13 @@ class PartRequest(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("n_dirs", C.c_int32), ("leaf_size", C.c_int32), ("rays_per_wave", C.c_int32),
-                ("stack_depth", C.c_int32), ("offset_frac", C.c_float), ("thresholds", C.POINTER(Thresholds))]
+                ("stack_depth", C.c_int32), ("traversal", C.c_int32), ("offset_frac", C.c_float),
+                ("thresholds", C.POINTER(Thresholds))]
 
 
 class TunePoint(C.Structure):
     _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32), ("leaf_size", C.c_int32),
-                ("ms", C.c_float)]
+                ("traversal", C.c_int32), ("ms", C.c_float)]
 
 
 class TuneReport(C.Structure):
@@ -283,9 +286,10 @@ class Context:
         return reqs, keep
 
     @staticmethod
-    def _batch_opts(n_dirs, leaf_size=0, rays_per_wave=0, stack_depth=0, offset_frac=0.0, thresholds=None):
+    def _batch_opts(n_dirs, leaf_size=0, rays_per_wave=0, stack_depth=0, offset_frac=0.0, thresholds=None,
+                    traversal=0):
         th = Thresholds(*thresholds) if thresholds is not None else None
-        o = BatchOpts(n_dirs, leaf_size, rays_per_wave, stack_depth, offset_frac,
+        o = BatchOpts(n_dirs, leaf_size, rays_per_wave, stack_depth, traversal, offset_frac,
                       C.pointer(th) if th is not None else None)
         return o, th
 
@@ -299,16 +303,18 @@ class Context:
         self._check(lib().hra_batch_run(self.ptr, reqs, len(parts), C.byref(opts), res, _ptr(bits), _stream(stream)))
         return [_result_dict(r) for r in res]
 
-    def plan(self, parts, n_dirs, leaf_size=0, rays_per_wave=0, stack_depth=0, offset_frac=0.0, thresholds=None):
+    def plan(self, parts, n_dirs, leaf_size=0, rays_per_wave=0, stack_depth=0, offset_frac=0.0, thresholds=None,
+             traversal=0):
         """A batch plan (all buffers allocated once; runs may replay a graph)."""
         reqs, keep = self._requests(parts)
-        opts, th = self._batch_opts(n_dirs, leaf_size, rays_per_wave, stack_depth, offset_frac, thresholds)
+        opts, th = self._batch_opts(n_dirs, leaf_size, rays_per_wave, stack_depth, offset_frac, thresholds,
+                                    traversal)
         out = C.c_void_p()
         self._check(lib().hra_plan_create(self.ptr, reqs, len(parts), C.byref(opts), C.byref(out)))
         return Plan(self, out, len(parts), sum(int(q["n_samples"]) for q in parts), n_dirs, keep)
 
     def autotune(self, parts, n_dirs, reps=2, offset_frac=0.0, stream=None):
-        """Sweep (rays per wave, stack depth, leaf size) on this batch; the
+        """Sweep (rays per wave, traversal, leaf size) on this batch; the
         fastest point becomes the context's cast configuration."""
         reqs, keep = self._requests(parts)
         opts, th = self._batch_opts(n_dirs, 0, 0, 0, offset_frac, None)
@@ -316,7 +322,7 @@ class Context:
         self._check(lib().hra_autotune(self.ptr, reqs, len(parts), C.byref(opts), reps, C.byref(rep),
                                        _stream(stream)))
         pts = [{"rays_per_wave": p.rays_per_wave, "stack_depth": p.stack_depth, "leaf_size": p.leaf_size,
-                "ms": p.ms} for p in rep.points[:rep.n_points]]
+                "traversal": p.traversal, "ms": p.ms} for p in rep.points[:rep.n_points]]
         return {"points": pts, "best": pts[rep.best]}
 
     def dirs_table(self, n, kind=DIRS_HEMI):
@@ -325,13 +331,15 @@ class Context:
         self._check(lib().hra_dirs_table(self.ptr, Dirs(kind, n), out.ctypes.data_as(C.c_void_p)))
         return out
 
-    def set_cast_config(self, rays_per_wave=64, stack_depth=20, leaf_size=0):
-        self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth, leaf_size))))
+    def set_cast_config(self, rays_per_wave=64, stack_depth=20, leaf_size=0, traversal=0):
+        """Launch shape of the casts (0 for leaf_size or traversal keeps the current value)."""
+        self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth, leaf_size,
+                                                                            traversal))))
 
     def cast_config(self):
         c = CastConfig()
         self._check(lib().hra_get_cast_config(self.ptr, C.byref(c)))
-        return c.rays_per_wave, c.stack_depth, c.leaf_size
+        return c.rays_per_wave, c.stack_depth, c.leaf_size, c.traversal
 
     # ---------------------------------------------------------------- samples
     def alloc_samples(self, n):

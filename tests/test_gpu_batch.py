@@ -168,18 +168,18 @@ def _reqs(ms, base_n=400):
              "tool_length": 25.0 + 3 * p} for p, m in enumerate(ms)]
 
 
-@pytest.mark.parametrize("rpw,stack,leaf", [(64, 24, 4), (128, 16, 2), (256, 32, 8)])
-def test_plan_eager_matches_batch_run(ctx, meshes, rpw, stack, leaf):
+@pytest.mark.parametrize("rpw,stack,leaf,trav", [(64, 24, 4, 1), (128, 16, 2, 2), (256, 32, 8, 1), (64, 20, 4, 2)])
+def test_plan_eager_matches_batch_run(ctx, meshes, rpw, stack, leaf, trav):
     import torch
     reqs = _reqs(meshes)
     N = 777
     W = (N + 31) // 32
     S = sum(r["n_samples"] for r in reqs)
-    _say("plan eager", rpw, stack, leaf)
+    _say("plan eager", rpw, stack, leaf, trav)
     b0 = torch.empty((S, W), dtype=torch.int32, device=ctx.device)
     b1 = torch.empty_like(b0)
     want = ctx.batch_run(reqs, N, leaf_size=4, bits=b0)
-    pl = ctx.plan(reqs, N, leaf_size=leaf, rays_per_wave=rpw, stack_depth=stack)
+    pl = ctx.plan(reqs, N, leaf_size=leaf, rays_per_wave=rpw, stack_depth=stack, traversal=trav)
     got = pl.run(graph=False, bits=b1)
     assert got == want
     assert torch.equal(b0, b1)
@@ -217,14 +217,16 @@ def test_plan_graph_replays_match_eager(ctx, meshes):
 
 
 def test_autotune_picks_a_point_and_keeps_results(ctx, meshes):
+    from paper_2609_05467_amd import hra
     reqs = _reqs(meshes[:3], 300)
     old = ctx.cast_config()
     _say("autotune")
     rep = ctx.autotune(reqs, 256, reps=1)
-    assert len(rep["points"]) == 27
+    assert len(rep["points"]) == 18
+    assert {p["traversal"] for p in rep["points"]} == {hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP}
     best = rep["best"]
     assert best["ms"] == min(p["ms"] for p in rep["points"])
-    assert ctx.cast_config() == (best["rays_per_wave"], best["stack_depth"], best["leaf_size"])
+    assert ctx.cast_config() == (best["rays_per_wave"], best["stack_depth"], best["leaf_size"], best["traversal"])
     # results of a single-part cast do not depend on the tuned shape
     m = meshes[0]
     b = ctx.build_bvh(m.verts, m.tris)

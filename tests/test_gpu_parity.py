@@ -163,19 +163,32 @@ def test_cast_multiaxis_part(ctx, orc):
 
 
 def test_cast_configs_identical(ctx, orc, cfg1):
+    """Every launch shape and both traversal loops give the same bits, for
+    the hemisphere and the six-axis casts, and the same work counts."""
+    from paper_2609_05467_amd import hra
     m, b = cfg1
     s = ctx.sample_surface(b, 300, 8)
-    ref = None
-    for rpw in (64, 128, 256):
-        for st in (16, 24, 32):
-            _say("config", rpw, st)
-            ctx.set_cast_config(rpw, st)
-            bits, _ = ctx.cast(b, s, 1000)
-            g = _u32(bits)
-            if ref is None:
-                ref = g
-            assert np.array_equal(g, ref), (rpw, st)
-    ctx.set_cast_config(64, 24)
+    ref = ref6 = None
+    for trav in (hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP):
+        for rpw in (64, 128, 256):
+            for st in (16, 20, 24, 32):
+                _say("config", trav, rpw, st)
+                ctx.set_cast_config(rpw, st, 0, trav)
+                bits, _ = ctx.cast(b, s, 1000)
+                b6, _ = ctx.cast(b, s, 6, kind=hra.DIRS_AXES6)
+                g, g6 = _u32(bits), _u32(b6)
+                if ref is None:
+                    ref, ref6 = g, g6
+                assert np.array_equal(g, ref), (trav, rpw, st)
+                assert np.array_equal(g6, ref6), (trav, rpw, st)
+    works = []
+    for trav in (hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP):
+        ctx.set_cast_config(64, 20, 0, trav)
+        wb, nf, nt = ctx.cast_work(b, s, 1000)
+        assert np.array_equal(_u32(wb), ref)
+        works.append((nf, nt))
+    assert works[0] == works[1] and works[0][0] > 0
+    ctx.set_cast_config(64, 20, 0, hra.TRAVERSAL_STEP)
 
 
 def test_convex_box_all_free(ctx):
