@@ -127,7 +127,8 @@ def main():
     ap.add_argument("--tool-length", type=float, default=50.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rays-per-wave", type=int, default=64)
-    ap.add_argument("--stack", type=int, default=20)
+    ap.add_argument("--stack", type=int, default=None,
+                    help="LDS stack entries per lane (default 16: nine workgroups fit in LDS)")
     ap.add_argument("--leaf", type=int, default=4)
     ap.add_argument("--traversal", choices=("step", "leaf_loop"), default=None,
                     help="traversal loop of the casts (same results; see hra.h); default: the one measured "
@@ -146,6 +147,8 @@ def main():
     args = ap.parse_args()
     if args.traversal is None:
         args.traversal = DEFAULT_TRAVERSAL[args.workload]
+    if args.stack is None:
+        args.stack = 16
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by part and "
               "by samples with no exchange, see the design notes)", file=sys.stderr)

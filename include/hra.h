@@ -200,7 +200,7 @@ hra_status hra_cast_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const h
 typedef struct {
     int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
     int32_t stack_depth;   /* traversal stack entries per lane held in LDS: 16, 20, 24 or
-                              32, default 20 (deeper paths overflow into private memory) */
+                              32, default 16 (deeper paths overflow into private memory) */
     int32_t leaf_size;     /* triangles per leaf of builds whose options give 0: 1..8
                               (0 in hra_set_cast_config: keep the current value) */
     int32_t traversal;     /* HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP
@@ -208,7 +208,7 @@ typedef struct {
 } hra_cast_config;
 
 /* Launch shape of hra_cast_hemisphere and default leaf size for this
- * context (defaults 64 / 20 / 4 / HRA_TRAVERSAL_STEP).  Results do not depend on it; only speed
+ * context (defaults 64 / 16 / 4 / HRA_TRAVERSAL_STEP).  Results do not depend on it; only speed
  * does. */
 hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *cfg);
 hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);

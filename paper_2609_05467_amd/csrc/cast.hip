@@ -384,11 +384,12 @@ __device__ inline CastJob job_of(const CastArgs &a, int64_t item) {
 // at the direction's canonical index; the finished row is stored with
 // coalesced writes.  The item index is the block index, uniform over the
 // workgroup, so both barriers are reached by every thread, and the kernel
-// has no cross-lane operation.  Seven waves per SIMD (at most 72 VGPRs, none
-// spilled) measured fastest; with a 20-entry stack seven workgroups also fit
-// in LDS (20.7 KB each).  Eight waves spill and are slower.
+// has no cross-lane operation.  The step loop runs at eight waves per SIMD
+// (64 VGPRs, none spilled; with the default 16-entry stack nine workgroups
+// fit in LDS, 16.6 KB each), the leaf loop at seven (72 VGPRs; at eight it
+// spills and is slower).
 template <int RPW, int STACK, bool STATS, bool STEP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_cast_rows(CastArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP ? 8 : 7))) void k_cast_rows(CastArgs a) {
     extern __shared__ int dyn_lds[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t item = blockIdx.x;
@@ -660,7 +661,8 @@ extern "C" hra_status hra_cast_work(hra_ctx *ctx, const hra_bvh *bvh, const hra_
     hra_status st = cast_common(ctx, bvh, 0, samples, dirs, d_bits, nullptr, w, 64, s);
     unsigned long long h[2] = {0, 0};
     hipError_t e = hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, s);
-    hipFreeAsync(w, s);
+    const hipError_t ef = hipFreeAsync(w, s);
+    if (e == hipSuccess) e = ef;
     if (st != HRA_OK) return st;
     if (e != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, "work counter copy failed", hipGetErrorString(e));
     st = check_error_word(ctx, s);

@@ -101,7 +101,7 @@ struct hra_ctx {
     uint32_t *d_counter = nullptr;    // work counters for persistent kernels (64 words)
     hipStream_t own = nullptr;        // internal stream for table builds
     int32_t cast_rpw = 64;            // directions per wave work item
-    int32_t cast_stack = 20;          // LDS stack entries per lane
+    int32_t cast_stack = 16;          // LDS stack entries per lane
     int32_t cast_traversal = HRA_TRAVERSAL_STEP;   // traversal loop (hra.h)
     int32_t leaf_default = 4;         // leaf size of builds whose options give 0
     std::string err;

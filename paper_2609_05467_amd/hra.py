@@ -331,7 +331,7 @@ class Context:
         self._check(lib().hra_dirs_table(self.ptr, Dirs(kind, n), out.ctypes.data_as(C.c_void_p)))
         return out
 
-    def set_cast_config(self, rays_per_wave=64, stack_depth=20, leaf_size=0, traversal=0):
+    def set_cast_config(self, rays_per_wave=64, stack_depth=16, leaf_size=0, traversal=0):
         """Launch shape of the casts (0 for leaf_size or traversal keeps the current value)."""
         self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth, leaf_size,
                                                                             traversal))))

@@ -188,7 +188,7 @@ def test_cast_configs_identical(ctx, orc, cfg1):
         assert np.array_equal(_u32(wb), ref)
         works.append((nf, nt))
     assert works[0] == works[1] and works[0][0] > 0
-    ctx.set_cast_config(64, 20, 0, hra.TRAVERSAL_STEP)
+    ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP)
 
 
 def test_convex_box_all_free(ctx):
