@@ -544,8 +544,22 @@ __device__ inline void child_box(const float4 *tri4, const float *box_int, int32
 // node the first arrival stops and the second (which then sees both
 // children done) merges the boxes and goes on.  The same walk records each
 // node's height in emitted interior nodes (a node whose subtree holds at
-// most leaf_size triangles becomes a leaf: height 0).  The counter's
-// acquire-release ordering makes the sibling's box and height visible.
+// most leaf_size triangles becomes a leaf: height 0).
+//
+// Publication between the two children's threads, which may run on
+// different compute dies with separate L2 caches: every box and height
+// this kernel shares is written and read with agent-scope atomic stores and
+// loads, which the compiler issues as device-coherent accesses (they do not
+// hit a die's own L2 copy).  A thread waits until all its earlier memory
+// operations have completed (s_waitcnt 0) before it increments the node's
+// counter, so the box and height it wrote are visible device-wide before
+// its sibling can see the increment; the sibling's loads come after the
+// increment's returned value (control dependence, in-order issue).  An
+// acquire-release increment would order the same accesses, but it also
+// writes back and invalidates the whole L2 at every step (about six times
+// slower for the whole build); nothing here needs that, since no plain
+// (L2-cached) store is shared.  The compiler fences keep the shared
+// accesses on their side of the increment.
 __global__ void k_refit(const float4 *tri4, const int32_t *parent_leaf, const int32_t *parent_int, const int32_t *left,
                         const int32_t *right, const int32_t *first, const int32_t *last, int leaf_size,
                         float *box_int, int32_t *height, uint32_t *flags, const int32_t *n_valid_total) {
@@ -555,7 +569,10 @@ __global__ void k_refit(const float4 *tri4, const int32_t *parent_leaf, const in
     int node = parent_leaf[p];
     int steps = 0;
     while (node >= 0 && node < n - 1 && ++steps <= n) {
-        const uint32_t old = __hip_atomic_fetch_add(&flags[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        const uint32_t old = __hip_atomic_fetch_add(&flags[node], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (old == 0) return;  // the sibling subtree is not done yet
         float a[6], b[6];
         const int32_t l = left[node], r = right[node];

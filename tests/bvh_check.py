@@ -12,11 +12,13 @@ def decode(c):
     return "node", c, 0
 
 
-def check_bvh(nodes, tris, root, n_valid, verts=None, faces=None):
+def check_bvh(nodes, tris, root, n_valid, verts=None, faces=None, tight=False):
     """Returns dict(depth, n_internal, leaf_sizes) or raises AssertionError.
     Checks: tree (no node reached twice), no sentinel reached, leaf runs
     partition [0, n_valid), child boxes contain everything below them,
-    leaf triangles are the mesh's faces."""
+    leaf triangles are the mesh's faces.  tight: every child box equals the
+    union of the triangle boxes below it (min/max are exact, so a correct
+    refit reproduces it bit for bit)."""
     ch = nodes[:, 12:14].view(np.int32)
     box = nodes[:, :12]
     seen = np.zeros(len(nodes), bool)
@@ -52,12 +54,16 @@ def check_bvh(nodes, tris, root, n_valid, verts=None, faces=None):
                 leaf_sizes.append(cnt)
                 tl, th = tri_box(idx, cnt)
                 assert np.all(lo <= tl) and np.all(hi >= th), f"leaf box of node {i} child {k}"
+                if tight:
+                    assert np.array_equal(lo, tl) and np.array_equal(hi, th), f"leaf box of node {i} child {k}"
             else:
                 assert 0 <= idx < len(nodes)
                 cb = box[idx]
                 sub_lo = np.minimum(cb[0:3], cb[6:9])
                 sub_hi = np.maximum(cb[3:6], cb[9:12])
                 assert np.all(lo <= sub_lo) and np.all(hi >= sub_hi), f"box of node {i} child {k}"
+                if tight:
+                    assert np.array_equal(lo, sub_lo) and np.array_equal(hi, sub_hi), f"box of node {i} child {k}"
                 stack.append((idx, d + 1))
     assert np.all(covered == 1), f"{int((covered != 1).sum())} triangles not in exactly one leaf"
     if verts is not None:

@@ -1,0 +1,70 @@
+"""The hierarchy the GPU builds: a tree over every nonzero-area face, every
+child box exactly the union of the triangle boxes below it, and the same
+bytes on every rebuild.  The refit publishes boxes between threads of
+different compute dies; a box read before its writer finished would show up
+here as a box that is not the exact union, or as a difference between
+builds."""
+import sys
+
+import numpy as np
+import pytest
+
+from synth import parts as P
+from bvh_check import check_bvh
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2609_05467_amd import hra
+    assert torch.cuda.is_available()
+    c = hra.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+MESHES = {
+    "config1": lambda: P.config1_part(),
+    "icosphere": lambda: P.icosphere(subdiv=4),
+    "multiaxis-small": lambda: P._procedural(21, 1.0, "multiaxis", (100.0, 80.0, 50.0), (4, 8)),
+    "pockets-small": lambda: P._procedural(22, 1.0, "pockets", (120.0, 90.0, 60.0), (6, 10)),
+}
+
+
+def _export(ctx, m, leaf):
+    b = ctx.build_bvh(m.verts, m.tris, leaf_size=leaf)
+    out = b.export()
+    b.release()
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+@pytest.mark.parametrize("leaf", [1, 4, 8])
+def test_bvh_tight_and_identical_across_builds(ctx, name, leaf):
+    m = MESHES[name]()
+    _say("bvh", name, leaf, m.n_tris)
+    nodes, tris, root, nv = _export(ctx, m, leaf)
+    check_bvh(nodes, tris, root, nv, m.verts, m.tris, tight=True)
+    for k in range(6):
+        n2, t2, r2, nv2 = _export(ctx, m, leaf)
+        assert (r2, nv2) == (root, nv), k
+        assert np.array_equal(t2.view(np.uint32), tris.view(np.uint32)), k
+        assert np.array_equal(n2.view(np.uint32), nodes.view(np.uint32)), k
+
+
+def test_bvh_interactive_size_tight(ctx):
+    m = P.workload_parts("interactive_200k")[0]
+    _say("bvh interactive", m.n_tris)
+    nodes, tris, root, nv = _export(ctx, m, 4)
+    check_bvh(nodes, tris, root, nv, tight=True)
+    for k in range(3):
+        n2, t2, r2, _ = _export(ctx, m, 4)
+        assert r2 == root and np.array_equal(n2.view(np.uint32), nodes.view(np.uint32)), k
