@@ -49,10 +49,9 @@ NODE_OPS, TRI_OPS, RAY_OPS = 50, 54, 20
 # TFLOP/s counts an FMA as two and packed FP32 twice again).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 TRAVERSAL = {"step": 1, "leaf_loop": 2}     # hra.h HRA_TRAVERSAL_*
-# the traversal loop measured faster on each workload's part (the 1M-triangle
-# part tests 3.8 triangles per ray, and there lanes kept in step on the tree
-# win; elsewhere one unit of work per iteration does)
-DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "multiaxis_1m": "leaf_loop",
+# the traversal loop measured faster on each workload's part (the step loop
+# on all of them)
+DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "multiaxis_1m": "step",
                      "batch64": "step", "serve": "step"}
 
 

@@ -159,26 +159,33 @@ typedef __attribute__((address_space(3))) int lds_int;
 // array, or more node visits than twice the node count set the error word
 // and end the ray, so a malformed hierarchy cannot fault or spin.
 template <int STACK, bool STATS>
-__device__ inline bool occluded_step(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root, float ox,
-                                float oy, float oz, float dx, float dy, float dz, lds_int *lds, int lane, uint32_t *err,
-                                int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
+__device__ inline bool occluded_step(const Node *__restrict__ nodes, const float4 *__restrict__ tris, int32_t root,
+                                     float ox, float oy, float oz, float dx, float dy, float dz, lds_int *lds, int lane,
+                                     uint32_t *err, int32_t n_nodes_alloc, int32_t n_tris_alloc, WorkCount &wc) {
     const float kd = (6.0f * TRI_K) * fmaxf(fmaxf(fabsf(dx), fabsf(dy)), fabsf(dz));
     if (is_leaf(root)) return leaf_hit<STATS>(tris, root, ox, oy, oz, dx, dy, dz, kd, n_tris_alloc, err, wc);
+    if (n_nodes_alloc <= 0) {
+        atomicOr(err, ERR_STACK);
+        return true;
+    }
     const float ix = safe_rcp(dx), iy = safe_rcp(dy), iz = safe_rcp(dz);
     int spill[SPILL];
     int sp = 0;
     int32_t node = root;      // next interior node to visit, or -1: take the stack
     int32_t ti = 0, tn = 0;   // the leaf under test: triangles [ti, ti + tn)
     int32_t budget = 2 * n_nodes_alloc + 64;
+    bool hit = false, done = false, bad = false;
     // One unit of work per iteration: a triangle test while the lane holds a
     // leaf, otherwise a stack pop and/or a node visit.  Lanes at a leaf and
     // lanes inside the tree thus advance in the same iteration instead of the
     // tree lanes idling through a leaf loop.  The loop has a single back edge
-    // (no continue), so the compiler keeps it one loop rather than nesting a
-    // triangle loop inside it (see also the asm below).  The visit order is that of a plain recursive
-    // traversal: hit leaf children first (child 0 before child 1; a second
-    // leaf waits on top of the stack), then the nearer interior child, the
-    // farther one pushed.
+    // and a single exit (hit, finished or a guard tripped), so the compiler
+    // keeps it one loop; the guards (node index, visit budget, leaf run,
+    // stack) only set a flag, and an out-of-range node index reads node 0
+    // instead, whose contents the exit then discards.  The visit order is that
+    // of a plain recursive traversal: hit leaf children first (child 0 before
+    // child 1; a second leaf waits on top of the stack), then the nearer
+    // interior child, the farther one pushed.
     while (true) {
         // the empty asm hides tn's value from the optimiser, which would
         // otherwise thread "tn still > 0" back into an inner triangle loop
@@ -186,35 +193,32 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
         if (tn > 0) {
             const float4 *t = tris + 3 * (int64_t)ti;
             if (STATS) ++wc.tris;
-            if (tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2))) return true;
+            hit = tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2));
             ++ti;
             --tn;
         } else {
             bool visit = true;
             if (node < 0) {
-                if (sp == 0) return false;
-                --sp;
-                int32_t item;
-                if (sp < STACK) item = lds[sp * 64 + lane];
-                else item = spill[sp - STACK];
-                if (is_leaf(item)) {
-                    ti = leaf_first(item);
-                    tn = leaf_count(item);
-                    if (ti + tn > n_tris_alloc) {
-                        atomicOr(err, ERR_STACK);
-                        return true;
-                    }
+                if (sp == 0) {
+                    done = true;
                     visit = false;
                 } else {
-                    node = item;
+                    --sp;
+                    int32_t item;
+                    if (sp < STACK) item = lds[sp * 64 + lane];
+                    else item = spill[sp - STACK];
+                    if (is_leaf(item)) {
+                        ti = leaf_first(item);
+                        tn = leaf_count(item);
+                        visit = false;
+                    } else {
+                        node = item;
+                    }
                 }
             }
             if (visit) {
-                if ((uint32_t)node >= (uint32_t)n_nodes_alloc || --budget < 0) {
-                    atomicOr(err, ERR_STACK);
-                    return true;
-                }
-                const Node *nd = nodes + node;
+                bad = (uint32_t)node >= (uint32_t)n_nodes_alloc || --budget < 0;
+                const Node *nd = nodes + (bad ? 0 : node);
                 if (STATS) ++wc.nodes;
                 const float4 A = gload_f4(&nd->a), B = gload_f4(&nd->b), C = gload_f4(&nd->c);
                 const int4 D = gload_i4(&nd->d);
@@ -228,10 +232,6 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
                     const int32_t lc = l0 ? c0 : c1;
                     ti = leaf_first(lc);
                     tn = leaf_count(lc);
-                    if (ti + tn > n_tris_alloc || (l0 && l1 && leaf_first(c1) + leaf_count(c1) > n_tris_alloc)) {
-                        atomicOr(err, ERR_STACK);
-                        return true;
-                    }
                 }
                 // at most one push per visit: the second leaf, or the farther
                 // of two interior children (a node with two leaf children has
@@ -242,15 +242,18 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
                 if (push) {
                     if (sp < STACK) lds[sp * 64 + lane] = pv;
                     else if (sp < STACK + SPILL) spill[sp - STACK] = pv;
-                    else {
-                        atomicOr(err, ERR_STACK);
-                        return true;
-                    }
+                    else bad = true;
                     ++sp;
                 }
             }
+            // a leaf run outside the triangle array (checked before its first
+            // triangle is read: the exit below comes first)
+            bad = bad || (tn > 0 && ti + tn > n_tris_alloc);
         }
+        if (hit || done || bad) break;
     }
+    if (bad) atomicOr(err, ERR_STACK);
+    return hit || bad;
 }
 
 // One node visit per iteration, then the triangles of its hit leaf children.
