@@ -53,6 +53,23 @@ __device__ __noinline__ int plane_sign64(float ox, float oy, float oz, float4 A,
 // V and det is at most max|d_i| * M^2 and there are six of them; those of
 // E2.Q at most M^3.  M has a floor so that a bound never underflows below the
 // absolute error of subnormal results.
+// The decision when some FP32 sign is uncertain (value 2): the uncertain
+// edge functions, and the plane side if the edges agree, in FP64; the rule
+// is the one tri_hit applies to trusted signs.  Out of line: rare, and its
+// FP64 registers stay out of the traversal loop.
+__device__ __noinline__ bool tri_hit_fp64(float ox, float oy, float oz, float dx, float dy, float dz, float4 A, float4 B,
+                                          float4 C, int s0, int s1, int s2, int hs) {
+    if (s0 == 2) s0 = edge_sign64(ox, oy, oz, dx, dy, dz, B, C);
+    if (s1 == 2) s1 = edge_sign64(ox, oy, oz, dx, dy, dz, C, A);
+    if (s2 == 2) s2 = edge_sign64(ox, oy, oz, dx, dy, dz, A, B);
+    int s;
+    if (s0 >= 0 && s1 >= 0 && s2 >= 0 && (s0 | s1 | s2)) s = 1;
+    else if (s0 <= 0 && s1 <= 0 && s2 <= 0 && (s0 | s1 | s2)) s = -1;
+    else return false;
+    if (hs == 2) hs = plane_sign64(ox, oy, oz, A, B, C);
+    return hs == s;
+}
+
 __device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy, float dz, float kd, float4 A, float4 B,
                                float4 C) {
     const float tx = ox - A.x, ty = oy - A.y, tz = oz - A.z;
@@ -67,29 +84,22 @@ __device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy,
     const float U = fmaf(tz, pz, fmaf(ty, py, tx * px));
     const float qx = fmaf(ty, e1z, -(tz * e1y)), qy = fmaf(tz, e1x, -(tx * e1z)), qz = fmaf(tx, e1y, -(ty * e1x));
     const float V = fmaf(dz, qz, fmaf(dy, qy, dx * qx));
-    int s1 = U > bd ? -1 : (U < -bd ? 1 : 2);
-    int s2 = V > bd ? -1 : (V < -bd ? 1 : 2);
-    // certain opposite signs: the line misses the triangle
-    if ((s1 == 1 && s2 == -1) || (s1 == -1 && s2 == 1)) return false;
     const float det = fmaf(e1z, pz, fmaf(e1y, py, e1x * px));
     const float W = (det - U) - V;
     const float bw = 4.0f * bd;
-    int s0 = W > bw ? -1 : (W < -bw ? 1 : 2);
-    if ((s0 == 1 && (s1 == -1 || s2 == -1)) || (s0 == -1 && (s1 == 1 || s2 == 1))) return false;
-    if (s0 == 2) s0 = edge_sign64(ox, oy, oz, dx, dy, dz, B, C);
-    if (s1 == 2) s1 = edge_sign64(ox, oy, oz, dx, dy, dz, C, A);
-    if (s2 == 2) s2 = edge_sign64(ox, oy, oz, dx, dy, dz, A, B);
-    int s;
-    if (s0 >= 0 && s1 >= 0 && s2 >= 0 && (s0 | s1 | s2)) s = 1;
-    else if (s0 <= 0 && s1 <= 0 && s2 <= 0 && (s0 | s1 | s2)) s = -1;
-    else return false;
     const float Tn = fmaf(e2z, qz, fmaf(e2y, qy, e2x * qx));
     const float bt = (6.0f * TRI_K) * MM * M;
-    int hs;
-    if (Tn > bt) hs = -1;
-    else if (Tn < -bt) hs = 1;
-    else hs = plane_sign64(ox, oy, oz, A, B, C);
-    return hs == s;
+    const int s1 = U > bd ? -1 : (U < -bd ? 1 : 2);
+    const int s2 = V > bd ? -1 : (V < -bd ? 1 : 2);
+    const int s0 = W > bw ? -1 : (W < -bw ? 1 : 2);
+    const int hs = Tn > bt ? -1 : (Tn < -bt ? 1 : 2);
+    // two certain, opposite edge signs: the line misses the triangle
+    const bool miss = (s0 == 1 || s1 == 1 || s2 == 1) && (s0 == -1 || s1 == -1 || s2 == -1);
+    const bool unsure = s0 == 2 || s1 == 2 || s2 == 2 || hs == 2;
+    // no miss and nothing uncertain: the three edges share the certain sign s0
+    bool hit = !miss && !unsure && hs == s0;
+    if (!miss && unsure) hit = tri_hit_fp64(ox, oy, oz, dx, dy, dz, A, B, C, s0, s1, s2, hs);
+    return hit;
 }
 
 // Slab test, conservative: exact-ray intersections are never rejected.  The
