@@ -1,0 +1,225 @@
+"""Pins of the canonical-frame oracle (oracle/frame.py) against closed forms
+and invariants that do not come from the oracle itself: axis-aligned parts
+give the identity exactly, known rotations are recovered, symmetric facets
+average onto the axis between them, weighted means match their closed form,
+the frame is right-handed and orthonormal, ties resolve by the stated rules,
+and a sphere has low confidence."""
+import numpy as np
+import pytest
+
+from oracle import frame as F
+from oracle.oracle import histogram_bin
+from synth import parts as P
+
+
+def _quad(p0, u, v):
+    """Two triangles of the parallelogram p0, p0+u, p0+u+v, p0+v (normal u x v)."""
+    p0, u, v = (np.asarray(x, np.float64) for x in (p0, u, v))
+    pts = np.array([p0, p0 + u, p0 + u + v, p0 + v])
+    return pts, np.array([[0, 1, 2], [0, 2, 3]])
+
+
+def _soup(quads):
+    vs, ts, off = [], [], 0
+    for p0, u, v in quads:
+        pts, t = _quad(p0, u, v)
+        vs.append(pts)
+        ts.append(t + off)
+        off += 4
+    return np.concatenate(vs).astype(np.float32), np.concatenate(ts).astype(np.int32)
+
+
+def _rot(axis, deg):
+    a = np.asarray(axis, np.float64)
+    a = a / np.linalg.norm(a)
+    t = np.radians(deg)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + np.sin(t) * K + (1 - np.cos(t)) * (K @ K)
+
+
+def _random_rotation(seed):
+    q = np.random.default_rng(seed).normal(size=4)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _valid(fr):
+    A = fr["axes"]
+    assert np.allclose(A @ A.T, np.eye(3), atol=1e-12)
+    assert abs(np.linalg.det(A) - 1.0) < 1e-12
+    for row in (A[0], A[2]):  # X and Z: largest component positive
+        k = int(np.argmax(np.abs(row)))
+        assert row[k] > 0
+
+
+AXIS_ALIGNED = {
+    "box": lambda: P.box_part(),
+    "config1": lambda: P.config1_part(),
+    "l_bracket": lambda: P.l_bracket(),
+    "pocket": lambda: P.pocket_part(),
+    "pockets-small": lambda: P._procedural(22, 1.0, "pockets", (120.0, 90.0, 60.0), (6, 10)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(AXIS_ALIGNED))
+def test_axis_aligned_parts_give_the_identity(name):
+    m = AXIS_ALIGNED[name]()
+    fr = F.estimate(m.verts, m.tris)
+    _valid(fr)
+    # faces exactly normal to the world axes average to exactly those axes
+    assert np.array_equal(np.abs(fr["axes"]), np.eye(3)), fr["axes"]
+
+
+def test_box_labels_follow_area_and_extent():
+    # 100 x 60 x 40: the largest faces are normal to z, x is the longest remaining side
+    m = P.box_part(W=100.0, D=60.0, H=40.0)
+    fr = F.estimate(m.verts, m.tris)
+    assert np.array_equal(fr["axes"], np.eye(3))
+    assert fr["confidence"] == 1.0
+    assert np.allclose(fr["aligned"], [2 * 60 * 40, 2 * 100 * 40, 2 * 100 * 60], rtol=1e-12)
+    assert np.allclose(fr["extent"], [100, 60, 40], rtol=1e-12)
+    # the same box standing on its side: z is now the longest edge
+    m2 = P.box_part(W=40.0, D=60.0, H=100.0)
+    fr2 = F.estimate(m2.verts, m2.tris)
+    assert np.array_equal(np.abs(fr2["axes"]), np.eye(3)[[2, 1, 0]])   # X = world z, Z = world x
+    _valid(fr2)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+@pytest.mark.parametrize("name", ["config1", "pockets-small"])
+def test_known_rotation_is_recovered(name, seed):
+    m = AXIS_ALIGNED[name]()
+    R = _random_rotation(seed)
+    v = (np.asarray(m.verts, np.float64) @ R.T).astype(np.float32)
+    fr = F.estimate(v, m.tris)
+    _valid(fr)
+    # rows of the frame are the rotated world axes, up to the sign rule
+    M = fr["axes"] @ R
+    assert np.allclose(np.abs(M), np.eye(3), atol=2e-6), M
+    back = F.apply(fr["axes"], v)
+    assert np.allclose(back, np.asarray(m.verts) * np.sign(np.diag(M)), atol=2e-4)
+
+
+def test_peak_bin_of_axis_directions():
+    # +x: zenith band 32, azimuth sector 64 -> bin 4160; +z: band 63, sector 64 -> 8128
+    assert histogram_bin([1.0, 0.0, 0.0]) == 32 * 128 + 64
+    assert histogram_bin([0.0, 0.0, 1.0]) == 63 * 128 + 64
+    # a plate whose largest faces face x: both of them fold into the +x bin
+    v, t = _soup([((0, 0, 0), (0, 0, 50), (0, 80, 0)), ((10, 0, 0), (0, 80, 0), (0, 0, 50)),
+                  ((0, 0, 0), (10, 0, 0), (0, 0, 50))])
+    fr = F.estimate(v, t)
+    assert fr["peak_bins"][0] == 4160
+    H = fr["hist"]
+    yb = histogram_bin([0.0, 1.0, 0.0])
+    assert H[4160] == H.max() and int(H.sum()) == int(H[4160]) + int(H[yb])
+    assert fr["peak_bins"][1] == yb
+
+
+def test_weights_are_scaled_below_2_31():
+    m = P.config1_part()
+    n, area, ok = F.faces(m.verts, m.tris)
+    w, s = F.weights(area, ok)
+    assert int(w.max()) < 2 ** 31 and int(w.max()) >= 2 ** 30
+    assert int(F.histogram(F.face_bins(n, ok), w, ok).sum()) == int(w.sum())
+
+
+def test_symmetric_facets_average_onto_the_axis():
+    # a dominant "roof" of two facets tilted +-1 deg about x, equal areas, plus
+    # a smaller vertical face: the first axis is exactly z, although neither
+    # facet is; without the sign alignment the equator pair would cancel
+    t = np.radians(1.0)
+    L = 30.0 / np.cos(t)
+    u = (100.0, 0.0, 0.0)
+    v, tri = _soup([((0, 0, 0), u, (0, 30.0, 30.0 * np.tan(t))),
+                    ((0, 30.0, 30.0 * np.tan(t)), u, (0, 30.0, -30.0 * np.tan(t))),
+                    ((0, 0, 0), (0, 0, 20.0), u)])
+    fr = F.estimate(v, tri)
+    assert abs(fr["a"][0] @ np.array([0, 0, 1.0]) - 1) < 1e-12
+    assert fr["aligned"][2] > 2 * 100 * L * 0.999
+    # facets tilted +-1 deg about z around the x axis (the equator): folding
+    # puts them on opposite sides, the signed mean is x
+    v, tri = _soup([((0, 0, 0), (0, 100.0, 0), (30.0 * np.sin(t), 0, 30.0 * np.cos(t))),
+                    ((0, 0, 0), (0, 100.0, 0), (-30.0 * np.sin(t), 0, 30.0 * np.cos(t))),
+                    ((0, 0, 0), (0, 0, 20.0), (0, 5.0, 0))])
+    n, area, ok = F.faces(v, tri)
+    assert n[0][0] < 0 < n[2][0]          # folded onto opposite sides of the equator
+    fr = F.estimate(v, tri)
+    a1 = fr["a"][0]
+    assert abs(abs(a1[0]) - 1) < 1e-12, a1
+
+
+def _tilted_pair(tilt_deg, big=100.0, small=50.0):
+    """A square of area `big` facing z and one of area `small` tilted by
+    tilt_deg about x, plus a small vertical face for the second axis."""
+    t = np.radians(tilt_deg)
+    sb, ss = np.sqrt(big), np.sqrt(small)
+    return _soup([((0, 0, 0), (sb, 0, 0), (0, sb, 0)),
+                  ((0, 50, 0), (ss, 0, 0), (0, ss * np.cos(t), ss * np.sin(t))),
+                  ((0, 0, 0), (0, 0, 1.0), (1.0, 0, 0))])
+
+
+def test_refinement_closed_forms():
+    # tilt 4 deg: the 5-degree mean leans 1.33 deg, the facet is then 2.67
+    # deg away and the 2-degree refinement returns exactly z
+    v, t = _tilted_pair(4.0)
+    fr = F.estimate(v, t)
+    assert abs(fr["a"][0][2] - 1.0) < 1e-15
+    # tilt 2.5 deg: the facet stays inside both cones; a1 is the area-weighted mean
+    v, t = _tilted_pair(2.5)
+    fr = F.estimate(v, t)
+    n, area, ok = F.faces(v, t)
+    A_big, A_small = 100.0, 50.0
+    th = np.radians(2.5)
+    expect = np.array([0.0, -A_small * np.sin(th), A_big + A_small * np.cos(th)])
+    expect /= np.linalg.norm(expect)
+    assert np.allclose(fr["a"][0], expect, atol=1e-6), (fr["a"][0], expect)
+    assert abs(np.degrees(np.arccos(fr["a"][0][2])) - np.degrees(np.arctan2(A_small * np.sin(th), A_big + A_small * np.cos(th)))) < 1e-4
+
+
+def test_single_plane_has_no_second_peak():
+    v, t = _soup([((0, 0, 0), (10.0, 0, 0), (0, 20.0, 0))])
+    fr = F.estimate(v, t)
+    assert fr["peak_bins"][1] == -1
+    _valid(fr)
+    # a1 = z; a2 = the least-aligned world axis (x, the first of x and y); Z = z
+    # (all area aligned with it); X = the longer extent of x (10) and y (20)
+    assert np.allclose(fr["axes"], [[0, 1, 0], [-1, 0, 0], [0, 0, 1]], atol=1e-15)
+    assert fr["confidence"] == 1.0
+
+
+def test_cube_ties_resolve_to_a_valid_frame():
+    m = P.box_part(W=50.0, D=50.0, H=50.0, cs=10.0)
+    fr = F.estimate(m.verts, m.tris)
+    _valid(fr)
+    assert np.array_equal(np.abs(fr["axes"]) @ np.ones(3), np.ones(3))
+    # the tie goes to the first axis (the heaviest bin, lowest index)
+    assert fr["order"][2] == 0
+
+
+def test_sphere_has_low_confidence():
+    m = P.icosphere(subdiv=3)
+    fr = F.estimate(m.verts, m.tris)
+    _valid(fr)
+    assert fr["confidence"] < 0.05
+
+
+def test_degenerate_mesh_is_an_error():
+    v = np.zeros((3, 3), np.float32)
+    with pytest.raises(ValueError):
+        F.estimate(v, np.array([[0, 1, 2]], np.int32))
+
+
+def test_apply_exact_cases():
+    rng = np.random.default_rng(5)
+    v = rng.uniform(-100, 100, (1000, 3)).astype(np.float32)
+    assert np.array_equal(F.apply(np.eye(3), v), v)
+    Pm = np.eye(3)[[2, 0, 1]] * np.array([[1], [-1], [1]])
+    assert np.array_equal(F.apply(Pm, v), (v[:, [2, 0, 1]] * np.array([1, -1, 1], np.float32)))
+    R = _random_rotation(9)
+    out = F.apply(R, v).astype(np.float64)
+    exact = v.astype(np.float64) @ R.astype(np.float32).astype(np.float64).T
+    # three products and two sums, each rounded once
+    bound = 4 * 2.0 ** -24 * (np.abs(v.astype(np.float64)) @ np.abs(R).T)
+    assert np.all(np.abs(out - exact) <= bound)
