@@ -326,6 +326,61 @@ hra_status hra_min_setups_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, c
                                const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
                                hra_setup_report *out, void *stream);
 
+/* ------------------------------------------------------------ machining frame */
+
+#define HRA_FRAME_BAD_INDEX 1u  /* a triangle index outside [0, n_verts) */
+#define HRA_FRAME_EMPTY 2u      /* no triangle with nonzero area */
+
+typedef struct {
+    double axes[3][3];     /* rows X, Y, Z: unit vectors in world coordinates, right-handed */
+    double confidence;     /* share of the surface area on faces within 5 degrees of an axis */
+    double aligned[3];     /* that area per axis X, Y, Z (mm^2) */
+    double extent[3];      /* vertex extent along X, Y, Z (mm) */
+    double total_area;     /* area of the nonzero-area faces (mm^2) */
+    int32_t peak_bin[2];   /* histogram bins the first and second axes came from (-1: none) */
+    int32_t shift;         /* histogram weights are floor(area * 2^shift) */
+    uint32_t error;        /* 0, or HRA_FRAME_BAD_INDEX | HRA_FRAME_EMPTY (axes are then the identity) */
+} hra_frame;
+
+/* Canonical machining frame of a part (Section 3.2: parts are reoriented
+ * into a canonical machining frame before the orthogonal casts; the paper
+ * gives no method, this is the library's).  Per face, the FP64 unit normal
+ * of the FP32 vertices, folded so that opposite faces agree, and the area.
+ * Integer area weights floor(area * 2^shift), shift = 31 - e for the largest
+ * area m 2^e (m in [0.5, 1)), go into the 8192 bins of the direction
+ * histogram (64 z bands x 128 azimuth sectors, as hra_dominant_axes).  The
+ * heaviest bin (lowest index on ties) seeds the first axis: the
+ * area-weighted mean normal of the bin, then of the faces within 5 degrees,
+ * then within 2 degrees (each normal signed to agree with the axis).  The
+ * heaviest bin whose centre lies within 15 degrees of perpendicular seeds
+ * the second axis the same way, made orthogonal to the first after each
+ * step; without one, the world axis least aligned with the first is used.
+ * The third is their cross product.  Z is the axis with the most area on
+ * faces within 5 degrees of it, X the remaining one of larger vertex
+ * extent, Y = Z x X; Z and X have their largest component positive.
+ * Values within a relative 1e-9 count as tied; the earlier axis wins.
+ *
+ * mesh: device arrays as for hra_build_bvh (n_tris in [1, 2^31 - 256]).
+ * d_frame: device hra_frame, written when the stream reaches it.  d_hist:
+ * device uint64 [8192] that receives the weighted histogram, or NULL.  Index
+ * errors and meshes without a nonzero-area face set d_frame->error and the
+ * context's error word (HRA_ERR_BAD_MESH at the next synchronising call).
+ * Enqueues on `stream`; the workspace (hra_frame_ws_bytes) is taken from and
+ * returned to the stream-ordered allocator.  The result is the same on every
+ * run (fixed reduction order). */
+hra_status hra_frame_estimate(hra_ctx *ctx, const hra_mesh *mesh, uint64_t *d_hist, hra_frame *d_frame,
+                              void *stream);
+/* Device workspace hra_frame_estimate takes for n_tris triangles. */
+int64_t hra_frame_ws_bytes(int64_t n_tris);
+
+/* Vertices in the frame: out_k = (f_k0 x + f_k1 y) + f_k2 z in FP32, f =
+ * d_frame->axes rounded to FP32 (so a part reoriented with it can go through
+ * every other call unchanged).  d_in and d_out: float [n_verts][3], may be
+ * the same array.  A frame with an error copies the vertices unchanged.
+ * Enqueues on `stream`. */
+hra_status hra_frame_apply(hra_ctx *ctx, const hra_frame *d_frame, const float *d_in, float *d_out, int64_t n_verts,
+                           void *stream);
+
 /* ------------------------------------------------------------- batches */
 
 typedef struct {

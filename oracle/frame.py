@@ -11,7 +11,9 @@ reading written out here (plain numpy, FP64, one step after another) is:
    vertices, |N| = sqrt((Nx^2 + Ny^2) + Nz^2), area |N| / 2.  A face with
    |N| = 0 takes no part.  The unit normal n = N / |N| is folded onto the
    upper hemisphere (a face and its opposite face give the same machining
-   axis): n -> -n when nz < 0, or nz = 0 and ny < 0, or nz = ny = 0 and nx < 0.
+   axis): n -> -n when nz < 0, or nz = 0 and ny < 0, or nz = ny = 0 and nx < 0;
+   zero components are then made +0, so that the bin of a direction such as
+   (0, 0, 1) does not depend on the sign of a zero (atan2 tells -0 from +0).
 2. Histogram.  Integer area weights w = floor(area * 2^s), s = 31 - e where
    the largest area is m * 2^e with m in [0.5, 1), summed into the 8192 bins
    of the direction histogram (`oracle.histogram_bin`).  Integer sums make the
@@ -89,6 +91,7 @@ def faces(verts, tris):
     n[ok] = N[ok] / L[ok, None]
     flip = (n[:, 2] < 0) | ((n[:, 2] == 0) & ((n[:, 1] < 0) | ((n[:, 1] == 0) & (n[:, 0] < 0))))
     n[flip] = -n[flip]
+    n = n + 0.0   # -0 -> +0: the azimuth of (0, 0, 1) must not depend on the sign of a zero
     return n, 0.5 * L, ok
 
 

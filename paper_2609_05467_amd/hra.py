@@ -83,6 +83,12 @@ class Mesh(C.Structure):
     _fields_ = [("d_verts", C.c_void_p), ("n_verts", C.c_int64), ("d_tris", C.c_void_p), ("n_tris", C.c_int64)]
 
 
+class Frame(C.Structure):
+    _fields_ = [("axes", (C.c_double * 3) * 3), ("confidence", C.c_double), ("aligned", C.c_double * 3),
+                ("extent", C.c_double * 3), ("total_area", C.c_double), ("peak_bin", C.c_int32 * 2),
+                ("shift", C.c_int32), ("error", C.c_uint32)]
+
+
 class PartRequest(C.Structure):
     _fields_ = [("mesh", Mesh), ("n_samples", C.c_int64), ("seed", C.c_uint64), ("tool_length", C.c_double)]
 
@@ -187,6 +193,9 @@ def lib():
             "hra_server_drain": ([P, i64], C.c_int),
             "hra_server_get_stats": ([P, C.POINTER(ServerStats)], C.c_int),
             "hra_server_destroy": ([P], None),
+            "hra_frame_estimate": ([P, C.POINTER(Mesh), P, P, P], C.c_int),
+            "hra_frame_ws_bytes": ([i64], i64),
+            "hra_frame_apply": ([P, P, P, P, i64, P], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -203,7 +212,9 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_bvh_parts", "hra_bvh_part_info", "hra_sample_part", "hra_cast_part", "hra_min_setups_part",
            "hra_batch_run", "hra_plan_create", "hra_plan_run", "hra_plan_stage_ms", "hra_plan_bytes", "hra_plan_bits",
            "hra_plan_destroy", "hra_autotune", "hra_now_ns", "hra_server_create", "hra_server_submit",
-           "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy"]
+           "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy",
+           "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply"]
+FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
 def _ptr(t):
@@ -396,6 +407,41 @@ class Context:
         st = self._samples_struct(samples)
         self._check(lib().hra_debug_rays(self.ptr, C.byref(st), Dirs(kind, n_dirs), _ptr(idx), idx.shape[0], _ptr(out),
                                          _stream(stream)))
+        return out
+
+    # ---------------------------------------------------------------- frame
+    def estimate_frame(self, verts, tris, want_hist=False, stream=None):
+        """Canonical machining frame (hra_frame_estimate), enqueued on the
+        stream.  Returns the device record (a uint8 tensor holding one
+        hra_frame; read it with read_frame) and the uint64 [8192] weighted
+        histogram, or None."""
+        v = _dev_tensor(verts, torch.float32, self.device)
+        t = _dev_tensor(tris, torch.int32, self.device)
+        fr = torch.empty((C.sizeof(Frame),), dtype=torch.uint8, device=self.device)
+        hist = torch.empty((8192,), dtype=torch.int64, device=self.device) if want_hist else None
+        m = Mesh(_ptr(v), v.shape[0], _ptr(t), t.shape[0])
+        self._check(lib().hra_frame_estimate(self.ptr, C.byref(m), _ptr(hist), _ptr(fr), _stream(stream)))
+        if stream is not None:   # copies made here are freed only after that stream passes the call
+            v.record_stream(stream)
+            t.record_stream(stream)
+        return fr, hist
+
+    @staticmethod
+    def read_frame(fr):
+        """The hra_frame in a device record as a dict (waits for the record)."""
+        import numpy as np
+        r = Frame.from_buffer_copy(bytes(fr.cpu().numpy().tobytes()))
+        return {"axes": np.array([list(row) for row in r.axes]), "confidence": r.confidence,
+                "aligned": np.array(list(r.aligned)), "extent": np.array(list(r.extent)),
+                "total_area": r.total_area, "peak_bins": (r.peak_bin[0], r.peak_bin[1]), "shift": r.shift,
+                "error": r.error}
+
+    def apply_frame(self, fr, verts, out=None, stream=None):
+        """Vertices in the frame (hra_frame_apply): float32 [n][3] on the device."""
+        v = _dev_tensor(verts, torch.float32, self.device)
+        if out is None:
+            out = torch.empty_like(v)
+        self._check(lib().hra_frame_apply(self.ptr, _ptr(fr), _ptr(v), _ptr(out), v.shape[0], _stream(stream)))
         return out
 
     # ---------------------------------------------------------------- stats

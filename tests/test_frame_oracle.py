@@ -223,3 +223,14 @@ def test_apply_exact_cases():
     # three products and two sums, each rounded once
     bound = 4 * 2.0 ** -24 * (np.abs(v.astype(np.float64)) @ np.abs(R).T)
     assert np.all(np.abs(out - exact) <= bound)
+
+
+def test_opposite_faces_share_a_bin():
+    # the bottom of a box (normal -z) folds onto +z, and its zero components
+    # carry no sign: every horizontal face lands in the +z bin 8128
+    m = P.box_part()
+    n, area, ok = F.faces(m.verts, m.tris)
+    b = F.face_bins(n, ok)
+    horiz = np.abs(n[:, 2]) == 1.0
+    assert horiz.sum() > 0 and set(b[horiz].tolist()) == {63 * 128 + 64}
+    assert not np.any(np.signbit(n) & (n == 0))
