@@ -11,7 +11,9 @@ samples, 4096 Fibonacci-hemisphere directions (4.1e8 rays per step).
 
 Prints one JSON line.  Extra keys: parts/s, per-stage milliseconds, BVH
 facts, the traversal work per ray, the roofline of the cast kernel (HIP
-events over the timed region) and the CPU oracle timed on a bounded sample.
+events over the timed region), the CPU oracle timed on a bounded sample, and
+the canonical machining frame of the part (estimate and reorientation, timed
+apart from the step: the workload parts are generated in that frame).
 """
 from __future__ import annotations
 
@@ -69,6 +71,59 @@ def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
             "hbm_view": {"algorithmic_bytes": bytes_per_ray * rays, "bytes_per_ray": bytes_per_ray,
                          "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
                          "measured_traffic_bytes": traffic, "l2_hit_rate": l2_hit}}
+
+
+# Canonical frame (hra_frame_estimate), algorithmic HBM bytes: per face the
+# indices (12), the record and bin written (36), the histogram pass (bin and
+# area, 12), two bin-mean passes (bins, 8), four cone passes (records, 128)
+# and the aligned-area pass (32); per vertex the vertices read twice (24).
+FRAME_FACE_BYTES, FRAME_VERT_BYTES = 228, 24
+
+
+def frame_extra(ctx, verts, tris, mesh, reps=20, oracle=True):
+    """Canonical machining frame of the workload's part: the estimate and the
+    reorientation timed with HIP events on the stream they run on, their HBM
+    rooflines, and the oracle's time for the same estimate."""
+    import numpy as np
+    import torch
+    fr, _ = ctx.estimate_frame(verts, tris)
+    out = torch.empty_like(verts)
+    ctx.apply_frame(fr, verts, out=out)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        fr, _ = ctx.estimate_frame(verts, tris)
+    e[1].record()
+    for _ in range(reps):
+        ctx.apply_frame(fr, verts, out=out)
+    e[2].record()
+    torch.cuda.synchronize()
+    est_ms = e[0].elapsed_time(e[1]) / reps
+    app_ms = e[1].elapsed_time(e[2]) / reps
+    g = ctx.read_frame(fr)
+    nt, nv = mesh.n_tris, len(mesh.verts)
+    eb = FRAME_FACE_BYTES * nt + FRAME_VERT_BYTES * nv
+    ab = 24 * nv
+    res = {"triangles": nt, "vertices": nv, "estimate_ms": est_ms, "apply_ms": app_ms,
+           "axes": np.round(g["axes"], 12).tolist(), "confidence": g["confidence"], "peak_bins": g["peak_bins"],
+           "reoriented_identical": bool(torch.equal(out, verts)),
+           "roofline_estimate": {"bound": "hbm", "achieved": eb / (est_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": eb / (est_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "algorithmic_bytes": eb, "launches": 10},
+           "roofline_apply": {"bound": "hbm", "achieved": ab / (app_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": ab / (app_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "algorithmic_bytes": ab}}
+    if oracle:
+        from oracle import frame as F
+        t0 = time.perf_counter()
+        o = F.estimate(mesh.verts, mesh.tris)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": nt / dt, "unit": "faces/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole part ({nt} triangles), numpy FP64", "seconds": round(dt, 3)}
+        res["matches_oracle"] = bool(np.allclose(g["axes"], o["axes"], rtol=0, atol=1e-9)
+                                     and g["peak_bins"] == o["peak_bins"])
+    return res
 
 
 def log(*a):
@@ -140,6 +195,8 @@ def main():
                     help="processes generating the batch parts (before any GPU work)")
     ap.add_argument("--no-extras", action="store_true",
                     help="single-part workloads: skip the 64-part batch and serving comparisons")
+    ap.add_argument("--no-frame", action="store_true",
+                    help="single-part workloads: skip the canonical-frame measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -267,6 +324,9 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, samples_np, N)
+    if not args.no_frame:
+        log("[bench] canonical frame of the part")
+        out["frame"] = frame_extra(ctx, verts, tris, mesh, oracle=not args.no_cpu_baseline)
     ctx.close()
     if extras is not None:
         meshes, counts = extras

@@ -18,13 +18,17 @@
 //            X = the remaining axis of largest vertex extent, Y = Z x X; Z
 //            and X have their largest component positive.
 //
-// Data flow, all on the caller's stream: per-face records (normal, area) and
-// bins are written once; each later pass streams them and leaves one FP64
-// partial per workgroup.  The fixed grid of FR_GRID workgroups and the fixed
-// reduction order make every sum independent of scheduling, so the result is
-// the same on every run.  A pass that needs the previous pass's result
-// reduces that pass's partials itself (every workgroup computes the same
-// value), which keeps each step one launch.
+// Data flow, all on the caller's stream, ten launches: per-face records
+// (normal, area) and bins are written once; each later pass streams them and
+// leaves one partial per workgroup.  The fixed grid of FR_GRID workgroups and
+// the fixed reduction order make every sum independent of scheduling, so the
+// result is the same on every run.  A pass that needs the previous pass's
+// result (an axis, a peak bin) derives it itself from that pass's partials or
+// from the histogram: every workgroup computes the same value, so each step
+// is one launch with no grid-wide synchronisation.  The histogram is built
+// in LDS per workgroup and merged with one global atomic per nonzero bin:
+// the faces of a CAD part crowd into a few bins, and per-face global atomics
+// on those bins serialise.
 #include "common.hpp"
 
 namespace hra {
@@ -42,10 +46,16 @@ enum : uint32_t { FR_BAD_INDEX = 1u, FR_EMPTY = 2u };
 struct FrameState {
     double ax[6][3];              // ax[k]: the axis refinement step k used (k = 1, 2, 4, 5)
     double a[3][3];               // a1, a2, a3
-    unsigned long long amax;      // bits of the largest area (positive doubles order as integers)
+    double amax;                  // largest face area
     int32_t b1, b2;
     int32_t shift;
     uint32_t err;
+};
+
+struct FacePart {                 // per workgroup of the face pass
+    double amax;
+    uint32_t err;
+    uint32_t pad;
 };
 
 struct FinalPart {
@@ -55,9 +65,10 @@ struct FinalPart {
 
 struct FrameWs {
     double4 *rec;                 // [nt] folded unit normal and area (all zero for a face of zero area)
-    int32_t *bin;                 // [nt]
+    int32_t *bin;                 // [nt], -1 for a face of zero area
     unsigned long long *hist;     // [FR_BINS]
     FrameState *st;
+    FacePart *fpart;              // [FR_GRID]
     double4 *part;                // [6][FR_GRID]
     FinalPart *fin;               // [FR_GRID]
 };
@@ -98,17 +109,6 @@ __device__ inline int32_t dir_bin64(double x, double y, double z) {
     return (int32_t)fz * 128 + (int32_t)fa;
 }
 
-__device__ inline void bin_centre64(int32_t b, double *c) {
-    const int32_t zb = b / 128, az = b % 128;
-    const double z = (zb + 0.5) / 32.0 - 1.0;
-    const double phi = (az + 0.5) * (2.0 * M_PI / 128.0) - M_PI;
-    const double r2 = 1.0 - z * z;
-    const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
-    c[0] = r * cos(phi);
-    c[1] = r * sin(phi);
-    c[2] = z;
-}
-
 // Sum of a double4 across the workgroup in a fixed order (every thread's
 // value enters the same tree position on every run); the result is returned
 // to every thread.
@@ -132,136 +132,19 @@ __device__ double4 block_sum4(double4 v, double4 *lds) {
 __device__ double4 reduce_parts(const double4 *p, double4 *lds) {
     return block_sum4(p[threadIdx.x], lds);   // FR_GRID == FR_THREADS
 }
-static_assert(FR_GRID == FR_THREADS, "one partial per thread in reduce_parts");
+static_assert(FR_GRID == FR_THREADS, "one partial per thread in the reductions");
+static_assert(FR_BINS % FR_GRID == 0, "histogram zeroing by slices");
 
-__global__ __launch_bounds__(FR_THREADS) void k_fr_init(FrameWs w) {
-    const int i = blockIdx.x * FR_THREADS + threadIdx.x;
-    if (i < FR_BINS) w.hist[i] = 0ull;
-    if (i == 0) {
-        FrameState z = {};
-        z.b1 = -1;
-        z.b2 = -1;
-        *w.st = z;
-    }
-}
-
-// Per face: bounds check, FP64 normal and area, fold, bin.
-__global__ __launch_bounds__(FR_THREADS) void k_fr_faces(const float *v, int64_t nv, const int32_t *t, int64_t nt,
-                                                          FrameWs w) {
-    const int64_t i = (int64_t)blockIdx.x * FR_THREADS + threadIdx.x;
-    if (i >= nt) return;
-    const int32_t i0 = t[3 * i], i1 = t[3 * i + 1], i2 = t[3 * i + 2];
-    double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
-    int32_t bin = -1;
-    if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
-        atomicOr(&w.st->err, FR_BAD_INDEX);
-    } else {
-        const double ax = v[3 * (int64_t)i0], ay = v[3 * (int64_t)i0 + 1], az = v[3 * (int64_t)i0 + 2];
-        const double e1x = v[3 * (int64_t)i1] - ax, e1y = v[3 * (int64_t)i1 + 1] - ay, e1z = v[3 * (int64_t)i1 + 2] - az;
-        const double e2x = v[3 * (int64_t)i2] - ax, e2y = v[3 * (int64_t)i2 + 1] - ay, e2z = v[3 * (int64_t)i2 + 2] - az;
-        const double Nx = e1y * e2z - e1z * e2y;
-        const double Ny = e1z * e2x - e1x * e2z;
-        const double Nz = e1x * e2y - e1y * e2x;
-        const double L = sqrt((Nx * Nx + Ny * Ny) + Nz * Nz);
-        if (L > 0.0) {
-            double nx = Nx / L, ny = Ny / L, nz = Nz / L;
-            // Fold by a select, not a branch: the short-circuit form of this
-            // test, with the negation under it, was compiled for gfx950 so
-            // that lanes with nz == 0 kept the unfolded normal.
-            const bool flip = (nz < 0.0) | ((nz == 0.0) & ((ny < 0.0) | ((ny == 0.0) & (nx < 0.0))));
-            const double sg = flip ? -1.0 : 1.0;
-            // times -1 is exact; + 0 turns -0 into +0 (not an identity under
-            // IEEE rules, so it stays): the azimuth of (0, 0, 1) must not
-            // depend on a zero's sign
-            nx = nx * sg + 0.0;
-            ny = ny * sg + 0.0;
-            nz = nz * sg + 0.0;
-            const double area = 0.5 * L;
-            r = make_double4(nx, ny, nz, area);
-            bin = dir_bin64(nx, ny, nz);
-            atomicMax(&w.st->amax, (unsigned long long)__double_as_longlong(area));
-        }
-    }
-    w.rec[i] = r;
-    w.bin[i] = bin;
-}
-
-__global__ __launch_bounds__(FR_THREADS) void k_fr_hist(int64_t nt, FrameWs w) {
-    const int64_t i = (int64_t)blockIdx.x * FR_THREADS + threadIdx.x;
-    const double amax = __longlong_as_double((long long)w.st->amax);
-    int e = 0;
-    frexp(amax, &e);                      // amax = m 2^e, m in [0.5, 1)
-    const int s = 31 - e;
-    if (i == 0) w.st->shift = s;
-    if (i >= nt) return;
-    const int32_t b = w.bin[i];
-    if (b < 0) return;
-    const unsigned long long wt = (unsigned long long)floor(ldexp(w.rec[i].w, s));
-    if (wt) atomicAdd(&w.hist[b], wt);
-}
-
-// Heaviest bin (lowest index on ties) in one workgroup of 1024 threads.
-// mode 0: all bins, writes b1.  mode 1: first finishes a1 from the last
-// refinement, then takes the bins whose centre is within 15 degrees of
-// perpendicular to it, writes b2 (-1 if none).
-constexpr int PK_THREADS = 1024;
-
-__global__ __launch_bounds__(PK_THREADS) void k_fr_peak(FrameWs w, int mode, const double4 *prev, double perp_cos) {
-    __shared__ unsigned long long sv[PK_THREADS];
-    __shared__ int32_t sb[PK_THREADS];
-    __shared__ double4 lds4[FR_THREADS];
-    __shared__ double a1[3];
+// Heaviest histogram bin among those `take` accepts (lowest index on ties),
+// -1 if none holds weight; the same answer in every workgroup.
+template <class Take>
+__device__ int32_t heaviest_bin(const unsigned long long *hist, Take take, unsigned long long *sv, int32_t *sb) {
     const int t = threadIdx.x;
-    if (mode == 1 && w.st->b1 < 0) {   // no face with nonzero area: the error is set
-        if (t == 0) w.st->b2 = -1;
-        return;
-    }
-    if (mode == 1) {
-        double4 S = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (t < FR_THREADS) {
-            // block_sum4 on the first 256 threads; the rest wait at the barriers
-            lds4[t] = prev[t];
-        }
-        __syncthreads();
-        for (int o = FR_THREADS / 2; o > 0; o >>= 1) {
-            if (t < o) {
-                double4 a = lds4[t], b = lds4[t + o];
-                lds4[t] = make_double4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
-            }
-            __syncthreads();
-        }
-        S = lds4[0];
-        if (t == 0) {
-            double x[3];
-            if (S.w > 0.0) {
-                x[0] = S.x;
-                x[1] = S.y;
-                x[2] = S.z;
-                normalise(x);
-            } else {   // empty cone: the axis of the last step stands
-                x[0] = w.st->ax[2][0];
-                x[1] = w.st->ax[2][1];
-                x[2] = w.st->ax[2][2];
-            }
-            for (int k = 0; k < 3; ++k) {
-                a1[k] = x[k];
-                w.st->a[0][k] = x[k];
-            }
-        }
-        __syncthreads();
-    }
     unsigned long long best = 0ull;
     int32_t bb = -1;
-    for (int b = t; b < FR_BINS; b += PK_THREADS) {
-        const unsigned long long h = w.hist[b];
-        if (h == 0ull) continue;
-        if (mode == 1) {
-            double c[3];
-            bin_centre64(b, c);
-            const double d = dot3(c, a1);
-            if (fabs(d) > perp_cos) continue;
-        }
-        if (h > best) {   // b rises within a thread: the first maximum is kept
+    for (int b = t; b < FR_BINS; b += FR_THREADS) {   // b rises: the first maximum of the thread stays
+        const unsigned long long h = hist[b];
+        if (h > best && take(b)) {
             best = h;
             bb = b;
         }
@@ -269,7 +152,7 @@ __global__ __launch_bounds__(PK_THREADS) void k_fr_peak(FrameWs w, int mode, con
     sv[t] = best;
     sb[t] = bb;
     __syncthreads();
-    for (int o = PK_THREADS / 2; o > 0; o >>= 1) {
+    for (int o = FR_THREADS / 2; o > 0; o >>= 1) {
         if (t < o) {
             const unsigned long long v2 = sv[t + o];
             const int32_t b2 = sb[t + o];
@@ -280,30 +163,10 @@ __global__ __launch_bounds__(PK_THREADS) void k_fr_peak(FrameWs w, int mode, con
         }
         __syncthreads();
     }
-    if (t == 0) {
-        if (mode == 0) {
-            w.st->b1 = sb[0];
-            if (sb[0] < 0) atomicOr(&w.st->err, FR_EMPTY);
-        } else {
-            w.st->b2 = sb[0];
-        }
-    }
+    const int32_t r = sb[0];
+    __syncthreads();
+    return r;
 }
-
-// One refinement pass.  Steps:
-//   0  mean of bin b1                      (no axis needed)
-//   1  cone 5 deg about a1 from step 0
-//   2  cone 2 deg about a1 from step 1
-//   3  mean of bin b2                      (a1 finished by k_fr_peak)
-//   4  cone 5 deg about a2 from step 3
-//   5  cone 2 deg about a2 from step 4
-// Partial: sum of area * sign * n over the selected faces, w = their area.
-struct PassArgs {
-    int step;
-    double cos_cone;
-    const double4 *prev;   // partials of the previous step (steps 1, 2, 4, 5)
-    double4 *out;
-};
 
 // The normalised sum S, or `keep` when no face was selected (empty cone).
 __device__ inline void axis_from(const double4 &S, const double *keep, double *x) {
@@ -319,37 +182,204 @@ __device__ inline void axis_from(const double4 &S, const double *keep, double *x
     }
 }
 
+// Per face: bounds check, FP64 normal and area, fold, bin; per workgroup the
+// largest area and the error bits.  Also clears the global histogram.
+__global__ __launch_bounds__(FR_THREADS) void k_fr_faces(const float *v, int64_t nv, const int32_t *t, int64_t nt,
+                                                          FrameWs w) {
+    __shared__ double smax[FR_THREADS];
+    __shared__ uint32_t serr[FR_THREADS];
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x * (FR_BINS / FR_GRID) + tid; b < (blockIdx.x + 1) * (FR_BINS / FR_GRID); b += FR_THREADS)
+        w.hist[b] = 0ull;
+    double amax = 0.0;
+    uint32_t err = 0;
+    for (int64_t i = (int64_t)blockIdx.x * FR_THREADS + tid; i < nt; i += (int64_t)FR_GRID * FR_THREADS) {
+        const int32_t i0 = t[3 * i], i1 = t[3 * i + 1], i2 = t[3 * i + 2];
+        double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+        int32_t bin = -1;
+        if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= nv || i1 >= nv || i2 >= nv) {
+            err |= FR_BAD_INDEX;
+        } else {
+            const double ax = v[3 * (int64_t)i0], ay = v[3 * (int64_t)i0 + 1], az = v[3 * (int64_t)i0 + 2];
+            const double e1x = v[3 * (int64_t)i1] - ax, e1y = v[3 * (int64_t)i1 + 1] - ay,
+                         e1z = v[3 * (int64_t)i1 + 2] - az;
+            const double e2x = v[3 * (int64_t)i2] - ax, e2y = v[3 * (int64_t)i2 + 1] - ay,
+                         e2z = v[3 * (int64_t)i2 + 2] - az;
+            const double Nx = e1y * e2z - e1z * e2y;
+            const double Ny = e1z * e2x - e1x * e2z;
+            const double Nz = e1x * e2y - e1y * e2x;
+            const double L = sqrt((Nx * Nx + Ny * Ny) + Nz * Nz);
+            if (L > 0.0) {
+                double nx = Nx / L, ny = Ny / L, nz = Nz / L;
+                // Fold by a select, not a branch: the short-circuit form of
+                // this test, with the negation under it, was compiled for
+                // gfx950 so that lanes with nz == 0 kept the unfolded normal.
+                const bool flip = (nz < 0.0) | ((nz == 0.0) & ((ny < 0.0) | ((ny == 0.0) & (nx < 0.0))));
+                const double sg = flip ? -1.0 : 1.0;
+                // times -1 is exact; + 0 turns -0 into +0 (not an identity
+                // under IEEE rules, so it stays): the azimuth of (0, 0, 1)
+                // must not depend on a zero's sign
+                nx = nx * sg + 0.0;
+                ny = ny * sg + 0.0;
+                nz = nz * sg + 0.0;
+                const double area = 0.5 * L;
+                r = make_double4(nx, ny, nz, area);
+                bin = dir_bin64(nx, ny, nz);
+                amax = fmax(amax, area);
+            }
+        }
+        w.rec[i] = r;
+        w.bin[i] = bin;
+    }
+    smax[tid] = amax;
+    serr[tid] = err;
+    __syncthreads();
+    for (int o = FR_THREADS / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            smax[tid] = fmax(smax[tid], smax[tid + o]);
+            serr[tid] |= serr[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        FacePart f;
+        f.amax = smax[0];
+        f.err = serr[0];
+        f.pad = 0;
+        w.fpart[blockIdx.x] = f;
+    }
+}
+
+// Integer weights into a workgroup histogram in LDS, then one global atomic
+// per nonzero bin.  Every workgroup first reduces the face pass's partials
+// (largest area, error bits); workgroup 0 also resets the state.
+__global__ __launch_bounds__(FR_THREADS) void k_fr_hist(int64_t nt, FrameWs w) {
+    __shared__ unsigned long long h[FR_BINS];
+    __shared__ double smax[FR_THREADS];
+    __shared__ uint32_t serr[FR_THREADS];
+    const int tid = threadIdx.x;
+    const FacePart f = w.fpart[tid];
+    smax[tid] = f.amax;
+    serr[tid] = f.err;
+    for (int b = tid; b < FR_BINS; b += FR_THREADS) h[b] = 0ull;
+    __syncthreads();
+    for (int o = FR_THREADS / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            smax[tid] = fmax(smax[tid], smax[tid + o]);
+            serr[tid] |= serr[tid + o];
+        }
+        __syncthreads();
+    }
+    const double amax = smax[0];
+    int e = 0;
+    frexp(amax, &e);                      // amax = m 2^e, m in [0.5, 1)
+    const int s = 31 - e;
+    if (blockIdx.x == 0 && tid == 0) {
+        FrameState z = {};
+        z.amax = amax;
+        z.b1 = -1;
+        z.b2 = -1;
+        z.shift = s;
+        z.err = serr[0];
+        *w.st = z;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * FR_THREADS + tid; i < nt; i += (int64_t)FR_GRID * FR_THREADS) {
+        const int32_t b = w.bin[i];
+        if (b < 0) continue;
+        const unsigned long long wt = (unsigned long long)floor(ldexp(w.rec[i].w, s));
+        if (wt) atomicAdd(&h[b], wt);
+    }
+    __syncthreads();
+    for (int b = tid; b < FR_BINS; b += FR_THREADS)
+        if (h[b]) atomicAdd(&w.hist[b], h[b]);
+}
+
+// One refinement pass.  Steps:
+//   0  peak b1 from the histogram, mean of bin b1
+//   1  cone 5 deg about a1 from step 0
+//   2  cone 2 deg about a1 from step 1
+//   3  a1 from step 2, peak b2 among the bins within 15 degrees of
+//      perpendicular to it, mean of bin b2
+//   4  cone 5 deg about a2 from step 3
+//   5  cone 2 deg about a2 from step 4
+// Partial: sum of area * sign * n over the selected faces, w = their area.
+struct PassArgs {
+    int step;
+    double cos_cone;       // steps 1, 2, 4, 5
+    double perp_cos;       // step 3
+    const double4 *prev;   // partials of the previous step (steps 1 to 5)
+    double4 *out;
+};
+
 __global__ __launch_bounds__(FR_THREADS) void k_fr_pass(int64_t nt, FrameWs w, PassArgs p) {
     __shared__ double4 lds[FR_THREADS];
+    __shared__ unsigned long long sv[FR_THREADS];
+    __shared__ int32_t sb[FR_THREADS];
+    __shared__ double sec_c[128], sec_s[128], band_z[64], band_r[64];
     FrameState *st = w.st;
-    const int second = p.step >= 3;
-    if (st->b1 < 0) return;              // no face with nonzero area: the error is set
-    if (second && st->b2 < 0) return;    // no second peak: a2 is taken from the world axes
+    const int tid = threadIdx.x;
+    const bool lead = blockIdx.x == 0 && tid == 0;
     double c[3] = {0.0, 0.0, 0.0};
-    const int kind = p.step % 3;         // 0 bin mean, 1 and 2 cone
-    if (kind != 0) {
+    int32_t bsel = -1;
+    if (p.step == 0) {
+        bsel = heaviest_bin(w.hist, [](int) { return true; }, sv, sb);
+        if (lead) {
+            st->b1 = bsel;
+            if (bsel < 0) st->err |= FR_EMPTY;
+        }
+        if (bsel < 0) return;            // no face with nonzero area
+    } else if (p.step == 3) {
+        if (st->b1 < 0) return;
+        double a1[3];
+        const double4 S = reduce_parts(p.prev, lds);
+        axis_from(S, st->ax[2], a1);
+        if (tid < 128) {
+            const double phi = (tid + 0.5) * (2.0 * M_PI / 128.0) - M_PI;
+            sec_c[tid] = cos(phi);
+            sec_s[tid] = sin(phi);
+        } else if (tid < 192) {
+            const double z = ((tid - 128) + 0.5) / 32.0 - 1.0;
+            const double r2 = 1.0 - z * z;
+            band_z[tid - 128] = z;
+            band_r[tid - 128] = sqrt(r2 > 0.0 ? r2 : 0.0);
+        }
+        __syncthreads();
+        // candidates: bin centres (r cos phi, r sin phi, z) with |centre . a1| <= cos 75 deg
+        bsel = heaviest_bin(
+            w.hist,
+            [&](int b) {
+                const double r = band_r[b >> 7], ctr[3] = {r * sec_c[b & 127], r * sec_s[b & 127], band_z[b >> 7]};
+                return !(fabs(dot3(ctr, a1)) > p.perp_cos);
+            },
+            sv, sb);
+        if (lead) {
+            for (int k = 0; k < 3; ++k) st->a[0][k] = a1[k];
+            st->b2 = bsel;
+        }
+        if (bsel < 0) return;            // no second peak: a2 is taken from the world axes
+    } else {
+        const int second = p.step > 3;
+        if (st->b1 < 0 || (second && st->b2 < 0)) return;
         // every workgroup derives the same axis; the fallback for an empty
         // cone is the previous step's axis, written by an earlier launch
         const double4 S = reduce_parts(p.prev, lds);
         axis_from(S, st->ax[p.step - 1], c);
         if (second) orth(c, st->a[0]);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->ax[p.step][0] = c[0];
-            st->ax[p.step][1] = c[1];
-            st->ax[p.step][2] = c[2];
-        }
+        if (lead)
+            for (int k = 0; k < 3; ++k) st->ax[p.step][k] = c[k];
     }
-    const int32_t bsel = second ? st->b2 : st->b1;
     double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
-    for (int64_t i = (int64_t)blockIdx.x * FR_THREADS + threadIdx.x; i < nt; i += (int64_t)FR_GRID * FR_THREADS) {
-        if (kind == 0) {
+    if (bsel >= 0) {                     // mean of one bin
+        for (int64_t i = (int64_t)blockIdx.x * FR_THREADS + tid; i < nt; i += (int64_t)FR_GRID * FR_THREADS) {
             if (w.bin[i] != bsel) continue;
             const double4 r = w.rec[i];
             acc.x += r.w * r.x;
             acc.y += r.w * r.y;
             acc.z += r.w * r.z;
             acc.w += r.w;
-        } else {
+        }
+    } else {                             // cone about c
+        for (int64_t i = (int64_t)blockIdx.x * FR_THREADS + tid; i < nt; i += (int64_t)FR_GRID * FR_THREADS) {
             const double4 r = w.rec[i];
             if (r.w == 0.0) continue;
             const double n[3] = {r.x, r.y, r.z};
@@ -363,7 +393,7 @@ __global__ __launch_bounds__(FR_THREADS) void k_fr_pass(int64_t nt, FrameWs w, P
         }
     }
     const double4 S = block_sum4(acc, lds);
-    if (threadIdx.x == 0) p.out[blockIdx.x] = S;
+    if (tid == 0) p.out[blockIdx.x] = S;
 }
 
 // Index of the largest of three values; values within a relative FR_TIE_REL
@@ -564,7 +594,8 @@ int64_t blocks_for(int64_t n) { return (n + FR_THREADS - 1) / FR_THREADS; }
 size_t frame_ws_bytes(int64_t nt) {
     auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     return up(sizeof(double4) * nt) + up(sizeof(int32_t) * nt) + up(sizeof(unsigned long long) * FR_BINS) +
-           up(sizeof(FrameState)) + up(sizeof(double4) * 6 * FR_GRID) + up(sizeof(FinalPart) * FR_GRID);
+           up(sizeof(FrameState)) + up(sizeof(FacePart) * FR_GRID) + up(sizeof(double4) * 6 * FR_GRID) +
+           up(sizeof(FinalPart) * FR_GRID);
 }
 
 hipError_t enqueue_frame(const float *v, int64_t nv, const int32_t *t, int64_t nt, void *ws, unsigned long long *hist,
@@ -581,6 +612,8 @@ hipError_t enqueue_frame(const float *v, int64_t nv, const int32_t *t, int64_t n
     if (hist) w.hist = hist;
     w.st = (FrameState *)p;
     p += up(sizeof(FrameState));
+    w.fpart = (FacePart *)p;
+    p += up(sizeof(FacePart) * FR_GRID);
     w.part = (double4 *)p;
     p += up(sizeof(double4) * 6 * FR_GRID);
     w.fin = (FinalPart *)p;
@@ -588,18 +621,15 @@ hipError_t enqueue_frame(const float *v, int64_t nv, const int32_t *t, int64_t n
     const double cos_wide = cos(5.0 * (M_PI / 180.0));
     const double cos_fine = cos(2.0 * (M_PI / 180.0));
     const double perp_cos = cos(75.0 * (M_PI / 180.0));
-    const unsigned gf = (unsigned)blocks_for(nt);
 
-    k_fr_init<<<FR_BINS / FR_THREADS, FR_THREADS, 0, s>>>(w);
-    k_fr_faces<<<gf, FR_THREADS, 0, s>>>(v, nv, t, nt, w);
-    k_fr_hist<<<gf, FR_THREADS, 0, s>>>(nt, w);
-    k_fr_peak<<<1, PK_THREADS, 0, s>>>(w, 0, nullptr, perp_cos);
+    k_fr_faces<<<FR_GRID, FR_THREADS, 0, s>>>(v, nv, t, nt, w);
+    k_fr_hist<<<FR_GRID, FR_THREADS, 0, s>>>(nt, w);
     for (int step = 0; step < 6; ++step) {
-        if (step == 3) k_fr_peak<<<1, PK_THREADS, 0, s>>>(w, 1, w.part + 2 * FR_GRID, perp_cos);
         PassArgs a;
         a.step = step;
         a.cos_cone = step % 3 == 2 ? cos_fine : cos_wide;
-        a.prev = step % 3 == 0 ? nullptr : w.part + (step - 1) * FR_GRID;
+        a.perp_cos = perp_cos;
+        a.prev = step == 0 ? nullptr : w.part + (step - 1) * FR_GRID;
         a.out = w.part + step * FR_GRID;
         k_fr_pass<<<FR_GRID, FR_THREADS, 0, s>>>(nt, w, a);
     }
