@@ -35,7 +35,15 @@ WORKLOADS = {
     "batch64": ("batch64", None, 1024),
     # Poisson arrivals of analyses of parts drawn from the batch64 pool
     "serve": ("batch64", None, 1024),
+    # the shape of the paper's case studies (Table 3): one ray origin per
+    # face (offset centroid), 150 directions, on a housing-like 22.5k-face
+    # part and an impeller-like 124k-face part, one after the other
+    "paper_shape": (("paper_housing_22k", "paper_impeller_124k"), "centroid", 150),
 }
+# the paper's own times for its two cases (Table 3; GTX 1650, PyTorch + Warp):
+# context for paper_shape, never a target
+PAPER_TABLE3 = {"paper_housing_22k": {"faces": 22_530, "seconds": 0.18},
+                "paper_impeller_124k": {"faces": 123_958, "seconds": 4.50}}
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 NODE_BYTES, TRI_BYTES = 64, 48  # one interior-node record, one leaf triangle
 # FP32 vector operations the cast performs: per node visit two slab tests
@@ -54,7 +62,7 @@ TRAVERSAL = {"step": 1, "leaf_loop": 2}     # hra.h HRA_TRAVERSAL_*
 # the traversal loop measured faster on each workload's part (the step loop
 # on all of them)
 DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "multiaxis_1m": "step",
-                     "batch64": "step", "serve": "step"}
+                     "batch64": "step", "serve": "step", "paper_shape": "step"}
 
 
 def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
@@ -212,6 +220,8 @@ def main():
 
     if args.workload == "batch64":
         return run_batch(args)
+    if args.workload == "paper_shape":
+        return run_paper_shape(args)
     if args.workload == "serve":
         return run_serve(args)
     extras = None
@@ -339,6 +349,99 @@ def main():
         out["serve"] = {"rate_per_s": sv["rate"], "requests": 300, "popularity": "zipf 1.1 over the 64-part pool",
                         "served": sv["served"], "plain": sv["plain"],
                         "p99_ratio_plain_over_served": sv["plain"]["p99_ms"] / sv["served"]["p99_ms"]}
+    print(json.dumps(out), flush=True)
+
+
+def run_paper_shape(args):
+    """The paper's workload shape: per part, build, one offset-centroid
+    sample per face, 150 hemisphere directions, statistics and class, the
+    six-axis casts and the setup search; the two parts one after the other
+    make one step.  value = hemisphere rays per second over both."""
+    import numpy as np
+    import torch
+    from paper_2609_05467_amd import hra
+    from synth import parts
+
+    names, _, N = WORKLOADS["paper_shape"]
+    meshes = [parts.workload_parts(n)[0] for n in names]
+    ctx = hra.Context(0)
+    ctx.set_cast_config(args.rays_per_wave, args.stack, 0, TRAVERSAL[args.traversal])
+    dev = ctx.device
+    W = (N + 31) // 32
+    per = []
+    for m in meshes:
+        v = torch.tensor(m.verts, device=dev)
+        t = torch.tensor(m.tris, device=dev)
+        b = ctx.build_bvh(v, t, leaf_size=args.leaf)
+        S = m.n_tris - b.info().n_degenerate
+        b.release()
+        per.append({"mesh": m, "v": v, "t": t, "S": S, "samples": ctx.alloc_samples(S),
+                    "bits": torch.empty((S, W), dtype=torch.int32, device=dev),
+                    "bits6": torch.empty((S, 1), dtype=torch.int32, device=dev), "ms": []})
+
+    def one(p, record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        bvh = ctx.build_bvh(p["v"], p["t"], leaf_size=args.leaf)
+        ctx.sample_surface(bvh, p["S"], 0, mode=hra.SAMPLE_CENTROID, out=p["samples"])
+        ctx.cast(bvh, p["samples"], N, counts=False, bits=p["bits"])
+        ds = ctx.dominant_axes(p["samples"], N, p["bits"])
+        rep = ctx.classify(ds, p["S"], N)
+        ctx.cast(bvh, p["samples"], 6, kind=hra.DIRS_AXES6, counts=False, bits=p["bits6"])
+        su = ctx.min_setups(bvh, p["samples"], p["bits6"], args.tool_length, want_class=False)
+        e[1].record()
+        if record:
+            torch.cuda.synchronize()
+            p["ms"].append(e[0].elapsed_time(e[1]))
+        bvh.release()
+        p["rep"], p["su"] = rep, su
+
+    log(f"[bench] paper_shape: {[p['mesh'].n_tris for p in per]} faces, {N} directions; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        for p in per:
+            one(p, False)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for p in per:
+            one(p, True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rays = sum(p["S"] for p in per) * N
+    out = {
+        "metric": "any-hit hemisphere rays/s",
+        "value": rays * args.steps / dt,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper_shape", "parts": list(names), "samples": "offset centroid of every face",
+                   "directions": N, "rays_per_step": rays, "leaf_size": args.leaf,
+                   "rays_per_wave": args.rays_per_wave, "stack_depth": args.stack, "traversal": args.traversal,
+                   "tool_length_mm": args.tool_length},
+        "parts": {},
+    }
+    for n, p in zip(names, per):
+        ms = float(np.mean(p["ms"]))
+        out["parts"][n] = {
+            "faces": p["mesh"].n_tris, "samples": p["S"], "ms": ms, "rays_per_s": p["S"] * N / (ms * 1e-3),
+            "result": {"access": p["rep"]["access"], "multi_axis": p["rep"]["multi_axis"],
+                       "shares": p["rep"]["shares"], "mean_conc": p["rep"]["conc"],
+                       "min_setups": p["su"]["min_count"], "greedy_setups": p["su"]["greedy_count"]},
+            "paper_table3_context": dict(PAPER_TABLE3[n], hardware="GeForce GTX 1650 (another machine, another part)"),
+        }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (housing part)")
+        p = per[0]
+        out["cpu_baseline"] = cpu_baseline(p["mesh"], {k: x.cpu().numpy() for k, x in p["samples"].items()}, N)
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

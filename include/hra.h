@@ -205,6 +205,12 @@ typedef struct {
                               (0 in hra_set_cast_config: keep the current value) */
     int32_t traversal;     /* HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP
                               (0 in hra_set_cast_config: keep the current value) */
+    int32_t samples_per_group; /* samples per workgroup of the hemisphere cast,
+                              1..16; 0 (default) = chosen from the direction count:
+                              1 from 256 directions on, else the count that leaves
+                              the fewest of the workgroup's 256 lanes idle (5 for
+                              150 directions).  Plans and servers take the value in
+                              force when they are created. */
 } hra_cast_config;
 
 /* Launch shape of hra_cast_hemisphere and default leaf size for this
@@ -325,6 +331,31 @@ hra_status hra_min_setups(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *s
 hra_status hra_min_setups_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
                                const uint32_t *d_axes_bits, double tool_length, uint8_t *d_class,
                                hra_setup_report *out, void *stream);
+
+/* ------------------------------------------------------------------- files */
+
+typedef struct hra_stl hra_stl;
+
+/* Read an STL file into host memory (the paper analyses parts given as
+ * STEP/STL geometry, Sections 1 and 3.1).  Binary when the file size is
+ * exactly 84 + 50 x (the uint32 at byte 80), otherwise ASCII ("solid",
+ * facets of "facet [normal ...] outer loop", three "vertex x y z",
+ * "endloop endfacet", then "endsolid"; numbers parsed to the nearest FP64
+ * value, then rounded to FP32).  Vertices are welded: equal FP32
+ * coordinates (-0 taken as +0) share an index, numbered by first
+ * appearance; facets keep file order and vertex order, and stored facet
+ * normals are ignored.  Host only: no device, no context.  *out holds the
+ * mesh until hra_stl_free; *n_verts and *n_tris give the array sizes for
+ * hra_stl_copy.  HRA_ERR_INVALID_ARG for an unreadable, malformed or empty
+ * file or a non-finite coordinate; hra_stl_error() has the text (per host
+ * thread). */
+hra_status hra_stl_read(const char *path, hra_stl **out, int64_t *n_verts, int64_t *n_tris);
+/* Copy the welded mesh to host_verts float [n_verts][3] and host_tris int32
+ * [n_tris][3], ready for hra_build_bvh once on the device. */
+hra_status hra_stl_copy(const hra_stl *m, float *host_verts, int32_t *host_tris);
+void hra_stl_free(hra_stl *m);
+/* Text of the last hra_stl_read error on this host thread. */
+const char *hra_stl_error(void);
 
 /* ------------------------------------------------------------ machining frame */
 

@@ -51,7 +51,7 @@ class Dirs(C.Structure):
 
 class CastConfig(C.Structure):
     _fields_ = [("rays_per_wave", C.c_int32), ("stack_depth", C.c_int32), ("leaf_size", C.c_int32),
-                ("traversal", C.c_int32)]
+                ("traversal", C.c_int32), ("samples_per_group", C.c_int32)]
 
 
 class DirStats(C.Structure):
@@ -196,6 +196,10 @@ def lib():
             "hra_frame_estimate": ([P, C.POINTER(Mesh), P, P, P], C.c_int),
             "hra_frame_ws_bytes": ([i64], i64),
             "hra_frame_apply": ([P, P, P, P, i64, P], C.c_int),
+            "hra_stl_read": ([C.c_char_p, C.POINTER(P), C.POINTER(i64), C.POINTER(i64)], C.c_int),
+            "hra_stl_copy": ([P, P, P], C.c_int),
+            "hra_stl_free": ([P], None),
+            "hra_stl_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -213,7 +217,8 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_batch_run", "hra_plan_create", "hra_plan_run", "hra_plan_stage_ms", "hra_plan_bytes", "hra_plan_bits",
            "hra_plan_destroy", "hra_autotune", "hra_now_ns", "hra_server_create", "hra_server_submit",
            "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy",
-           "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply"]
+           "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply", "hra_stl_read", "hra_stl_copy",
+           "hra_stl_free", "hra_stl_error"]
 FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
@@ -342,15 +347,17 @@ class Context:
         self._check(lib().hra_dirs_table(self.ptr, Dirs(kind, n), out.ctypes.data_as(C.c_void_p)))
         return out
 
-    def set_cast_config(self, rays_per_wave=64, stack_depth=16, leaf_size=0, traversal=0):
-        """Launch shape of the casts (0 for leaf_size or traversal keeps the current value)."""
+    def set_cast_config(self, rays_per_wave=64, stack_depth=16, leaf_size=0, traversal=0, samples_per_group=0):
+        """Launch shape of the casts (0 for leaf_size or traversal keeps the current value;
+        samples_per_group 0 chooses it from the direction count)."""
         self._check(lib().hra_set_cast_config(self.ptr, C.byref(CastConfig(rays_per_wave, stack_depth, leaf_size,
-                                                                            traversal))))
+                                                                            traversal, samples_per_group))))
 
     def cast_config(self):
+        """(rays_per_wave, stack_depth, leaf_size, traversal, samples_per_group)."""
         c = CastConfig()
         self._check(lib().hra_get_cast_config(self.ptr, C.byref(c)))
-        return c.rays_per_wave, c.stack_depth, c.leaf_size, c.traversal
+        return c.rays_per_wave, c.stack_depth, c.leaf_size, c.traversal, c.samples_per_group
 
     # ---------------------------------------------------------------- samples
     def alloc_samples(self, n):
@@ -588,6 +595,26 @@ class Bvh:
             self.release()
         except Exception:
             pass
+
+
+def read_stl(path):
+    """Read a binary or ASCII STL file (hra_stl_read, host only): welded
+    float32 vertices [n][3] and int32 triangles [m][3] as numpy arrays."""
+    import numpy as np
+    m = C.c_void_p()
+    nv, nt = C.c_int64(), C.c_int64()
+    st = lib().hra_stl_read(os.fsencode(path), C.byref(m), C.byref(nv), C.byref(nt))
+    if st != HRA_OK:
+        raise HraError(st, (lib().hra_stl_error() or b"").decode())
+    try:
+        v = np.empty((nv.value, 3), np.float32)
+        t = np.empty((nt.value, 3), np.int32)
+        st = lib().hra_stl_copy(m, v.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p))
+        if st != HRA_OK:
+            raise HraError(st, "hra_stl_copy")
+    finally:
+        lib().hra_stl_free(m)
+    return v, t
 
 
 def now_ns():

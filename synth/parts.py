@@ -994,6 +994,110 @@ def is_watertight(mesh: Mesh) -> bool:
 
 
 # ----------------------------------------------------------------------------
+# impeller-like part (multi-axis: curved blades crowding a hub)
+# ----------------------------------------------------------------------------
+def _closed_shell(mb, v, t):
+    """Add a closed shell, flipping its winding if its signed volume is negative."""
+    v = np.asarray(v, np.float64)
+    t = np.asarray(t, np.int64)
+    a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    vol = np.einsum("ij,ij->i", a, np.cross(b, c)).sum() / 6.0
+    if vol < 0:
+        t = t[:, [0, 2, 1]]
+    idx = mb.add_verts(v)
+    mb.add_tris(idx[t])
+
+
+def _ring_grid(n_i, n_j):
+    """Quads of an n_i x n_j grid periodic in both directions, as triangles."""
+    i, j = np.meshgrid(np.arange(n_i), np.arange(n_j), indexing="ij")
+    a = i * n_j + j
+    b = ((i + 1) % n_i) * n_j + j
+    c = ((i + 1) % n_i) * n_j + (j + 1) % n_j
+    d = i * n_j + (j + 1) % n_j
+    return np.concatenate([np.stack([a, b, c], -1).reshape(-1, 3), np.stack([a, c, d], -1).reshape(-1, 3)])
+
+
+def _impeller(density, n_blades=12, R_hub=60.0, r_bore=10.0, H_hub=20.0, r_in=16.0, r_out=58.0,
+              h_in=35.0, h_out=12.0, sweep_deg=60.0, thick=2.0):
+    mb = MeshBuilder()
+    k = max(24, int(round(192 * density)))
+    n_r = max(2, int(round(8 * density)))
+    n_z = max(2, int(round(4 * density)))
+    # hub: an annular solid of revolution; the profile loop runs along the
+    # bottom, up the outer side, back along the top and down the bore
+    prof = [(r_bore + (R_hub - r_bore) * q / n_r, 0.0) for q in range(n_r)]
+    prof += [(R_hub, H_hub * q / n_z) for q in range(n_z)]
+    prof += [(R_hub - (R_hub - r_bore) * q / n_r, H_hub) for q in range(n_r)]
+    prof += [(r_bore, H_hub - H_hub * q / n_z) for q in range(n_z)]
+    phi = 2 * np.pi * np.arange(k) / k
+    pr = np.array(prof)
+    v = np.stack([pr[:, None, 0] * np.cos(phi)[None], pr[:, None, 0] * np.sin(phi)[None],
+                  np.broadcast_to(pr[:, None, 1], (len(pr), k))], -1).reshape(-1, 3)
+    _closed_shell(mb, v, _ring_grid(len(pr), k))
+    # blades: thin walls on the hub top along a swept spiral, taller near the bore
+    n_s = max(4, int(round(64 * density)))
+    n_v = max(2, int(round(24 * density)))
+    s = np.linspace(0.0, 1.0, n_s + 1)
+    beta = np.radians(sweep_deg)
+    for bl in range(n_blades):
+        th0 = 2 * np.pi * bl / n_blades
+        r = r_in + (r_out - r_in) * s
+        th = th0 + beta * s ** 1.5
+        P = np.stack([r * np.cos(th), r * np.sin(th)], -1)
+        dr = r_out - r_in
+        dth = 1.5 * beta * np.sqrt(s)
+        T = np.stack([dr * np.cos(th) - r * np.sin(th) * dth, dr * np.sin(th) + r * np.cos(th) * dth], -1)
+        T /= np.linalg.norm(T, axis=1, keepdims=True)
+        N = np.stack([-T[:, 1], T[:, 0]], -1)
+        h = h_in + (h_out - h_in) * s
+        vk = np.arange(n_v + 1) / n_v
+        # cross-section loop: (-,0), (+,v_0..v_n), (-,v_n..v_1)
+        side = np.array([-1.0] + [1.0] * (n_v + 1) + [-1.0] * n_v)
+        frac = np.concatenate([[0.0], vk, vk[::-1][:-1]])
+        L = len(side)
+        xy = P[:, None, :] + (0.5 * thick) * side[None, :, None] * N[:, None, :]
+        z = H_hub + frac[None, :] * h[:, None]
+        vb = np.concatenate([xy, z[..., None]], -1).reshape(-1, 3)
+        i, j = np.meshgrid(np.arange(n_s), np.arange(L), indexing="ij")
+        a = i * L + j
+        b = (i + 1) * L + j
+        c = (i + 1) * L + (j + 1) % L
+        d = i * L + (j + 1) % L
+        tri = [np.stack([a, b, c], -1).reshape(-1, 3), np.stack([a, c, d], -1).reshape(-1, 3)]
+        pk = 1 + np.arange(n_v + 1)
+        mk = np.array([0] + [2 * n_v + 2 - q for q in range(1, n_v + 1)])
+        for base, flip in ((0, False), (n_s * L, True)):
+            cap = np.concatenate([np.stack([mk[:-1], pk[:-1], pk[1:]], -1), np.stack([mk[:-1], pk[1:], mk[1:]], -1)])
+            tri.append(base + (cap[:, [0, 2, 1]] if flip else cap))
+        _closed_shell(mb, vb, np.concatenate(tri))
+    v, t = mb.arrays()
+    return Mesh(v, t, "impeller", {"blades": n_blades})
+
+
+def impeller_part(target_tris=124_000, n_blades=12):
+    """Impeller-like part: an annular hub with `n_blades` thin curved blades
+    (a 60-degree swept spiral, 35 mm tall at the bore side, 12 mm at the rim).
+    Closed shells: the hub and each blade (the blades stand on the hub top).
+    Tessellation density is bisected so the triangle count lands near
+    `target_tris`."""
+    lo, hi = 0.05, 16.0
+    best = _impeller(1.0, n_blades)
+    for _ in range(30):
+        mid = math.sqrt(lo * hi)
+        m = _impeller(mid, n_blades)
+        if abs(m.n_tris - target_tris) < abs(best.n_tris - target_tris):
+            best = m
+        if m.n_tris < target_tris:
+            lo = mid
+        else:
+            hi = mid
+        if abs(m.n_tris - target_tris) <= 0.01 * target_tris:
+            break
+    return best
+
+
+# ----------------------------------------------------------------------------
 # the workloads (names follow the configurations they stand for)
 # ----------------------------------------------------------------------------
 def workload_parts(name: str):
@@ -1004,6 +1108,13 @@ def workload_parts(name: str):
         return [procedural_part(2, 200_000, "pockets")]
     if name == "multiaxis_1m":
         return [procedural_part(3, 1_000_000, "multiaxis")]
+    # stand-ins of the shape of the paper's two case studies (Table 3): a
+    # housing-like block with a few top and side features (22,512 faces) and
+    # an impeller-like part (about 124k faces)
+    if name == "paper_housing_22k":
+        return [procedural_part(13, 22_530, "pockets", dims=(150.0, 100.0, 50.0), n_features=(5, 10))]
+    if name == "paper_impeller_124k":
+        return [impeller_part(123_958)]
     if name.startswith("batch64"):
         return batch_parts()
     raise KeyError(name)

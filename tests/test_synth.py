@@ -53,3 +53,25 @@ def test_generator_deterministic():
     a = P._procedural(11, 1.5, "multiaxis", None, None)
     b = P._procedural(11, 1.5, "multiaxis", None, None)
     assert np.array_equal(a.verts, b.verts) and np.array_equal(a.tris, b.tris)
+
+
+def test_paper_shape_parts():
+    """Stand-ins for the paper's two case-study shapes (Table 3 face counts)."""
+    h = P.workload_parts("paper_housing_22k")[0]
+    assert P.is_watertight(h) and abs(h.n_tris - 22_530) < 0.03 * 22_530
+    m = P.workload_parts("paper_impeller_124k")[0]
+    r = P.check_watertight(m)   # every shell closed: the hub and each blade
+    assert r["dup_directed_edges"] == 0 and r["unmatched_edges"] == 0 and r["zero_area"] == 0, r
+    assert abs(m.n_tris - 123_958) < 0.01 * 123_958
+    # volume: the hub's k-gon annulus plus 12 blades of rectangular section
+    # t x h(s) swept along the spiral centreline
+    k = int(round(len(np.unique(np.round(np.arctan2(m.verts[:, 1], m.verts[:, 0])[m.verts[:, 2] == 0], 9)))))
+    hub = 0.5 * k * (60.0 ** 2 - 10.0 ** 2) * np.sin(2 * np.pi / k) * 20.0
+    s = np.linspace(0, 1, 20001)
+    r_, th = 16.0 + 42.0 * s, np.radians(60.0) * s ** 1.5
+    ds = np.hypot(np.gradient(r_ * np.cos(th), s), np.gradient(r_ * np.sin(th), s))
+    blade = np.trapezoid(2.0 * (35.0 - 23.0 * s) * ds, s)
+    want = hub + 12 * blade
+    assert abs(P.signed_volume(m.verts, m.tris) - want) < 5e-3 * want, (P.signed_volume(m.verts, m.tris), want)
+    lo, hi = m.bbox()
+    assert np.allclose(lo[2], 0.0) and np.isclose(hi[2], 55.0)
