@@ -66,8 +66,8 @@ void fill_jobs(const StageBufs &B, const std::vector<const hra_bvh *> &bvh, cons
         H->aj[j] = make_cast_job(bvh[j], part[j], B.org + 3 * S, B.nr + 3 * S, B.abits + S, count[j], aitems);
         fill_setup_job(H->setj.data() + setup_job_size() * j, bvh[j], part[j], S, count[j], tool[j]);
         S += count[j];
-        items += cast_items(0, count[j]);
-        aitems += cast_items(1, count[j]);
+        items += cast_items(0, count[j], sh->group);
+        aitems += cast_items(1, count[j], 1);
     }
     sh->n_jobs = n;
     sh->S = S;
@@ -146,6 +146,7 @@ hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B
         a.kind = 0;
         a.W = sh.W;
         a.n_items = sh.items;
+        a.group = sh.group;
         a.err = err;
         a.work = nullptr;
         e = launch_cast_any(a, sh.rpw, sh.stack, sh.trav, false, s);
@@ -166,6 +167,7 @@ hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B
         a.kind = 1;
         a.W = 1;
         a.n_items = sh.aitems;
+        a.group = 1;
         a.err = err;
         a.work = nullptr;
         e = launch_cast_any(a, 64, sh.stack, sh.trav, false, s);
@@ -322,6 +324,7 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
     sh.rpw = rpw;
     sh.stack = stack;
     sh.trav = trav;
+    sh.group = cast_group(N, ctx->cast_group);
     sh.t_hemi = t_hemi;
     sh.t_ax = t_ax;
     HostJobs H;

@@ -452,11 +452,75 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP ? 8 : 
     }
 }
 
+// Hemisphere cast with several samples per workgroup, for direction counts
+// that would leave lanes of a one-sample workgroup idle (150 directions fill
+// 150 of 256 lanes; five samples fill 750 of 768).  Work item = `group`
+// consecutive samples of one job; lane k of the workgroup takes rays k,
+// k + 256, ... of the flattened (sample, direction) list, so a wave's lanes
+// hold consecutive directions of one sample, or of two at a boundary.  The
+// origin is per lane here, not per workgroup; the rays, the test and the
+// bits are those of k_cast_rows.
+template <int STACK, bool STATS, bool STEP>
+// Seven waves per SIMD: the per-lane origin takes three more registers than
+// k_cast_rows, which at eight waves (64 registers) would spill.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_cast_rows_grouped(CastArgs a) {
+    extern __shared__ int dyn_lds[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t item = blockIdx.x;
+    if (item >= a.n_items) return;  // the whole workgroup leaves together
+    lds_int *lds = (lds_int *)(dyn_lds + wv * (STACK * 64));
+    uint32_t *row = (uint32_t *)(dyn_lds + 4 * STACK * 64);
+    const CastJob J = uni_job(job_of(a, item));
+    const PartMeta &P = *J.meta;
+    const int32_t root = uni_i(P.root);
+    const int32_t n_valid = uni_i(P.n_valid);
+    const bool empty = n_valid <= 0;
+    const int32_t n_tris_alloc = uni_i(P.leaf_lo) + n_valid;
+    const int32_t G = uni_i(a.group), N = uni_i(a.n_dirs), W = uni_i(a.W);
+    const int64_t s0 = (item - J.item_base) * G;
+    const int64_t left = J.n_samples - s0;
+    const int32_t g_n = uni_i((int32_t)(left < G ? left : G));   // samples of this item
+    const int32_t total = g_n * N;
+    for (int32_t w = threadIdx.x; w < g_n * W; w += 256) row[w] = 0u;
+    __syncthreads();
+    WorkCount wc;
+    for (int32_t c = 0; c < total; c += 256) {
+        const int32_t jf = c + wv * 64 + lane;
+        uint32_t bit = 0u;
+        int32_t pos = 0;   // bit position in the workgroup's rows: word pos >> 5, bit pos & 31
+        if (jf < total) {
+            const int32_t g = jf / N;
+            const int32_t j = jf - g * N;
+            const int64_t s = s0 + g;
+            const float ox = J.origin[3 * s], oy = J.origin[3 * s + 1], oz = J.origin[3 * s + 2];
+            const float nx = J.normal[3 * s], ny = J.normal[3 * s + 1], nz = J.normal[3 * s + 2];
+            float3 t, b;
+            onb_frame(nx, ny, nz, t, b);
+            const float4 l = a.dirs_order[j];
+            pos = g * W * 32 + __float_as_int(l.w);
+            const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+            const bool free_ray = empty || !occluded<STACK, STATS, STEP>(J.nodes, J.tris, root, ox, oy, oz, d.x, d.y,
+                                                                  d.z, lds, lane, a.err, J.n_nodes_alloc,
+                                                                  n_tris_alloc, wc);
+            bit = (uint32_t)free_ray << (pos & 31);
+        }
+        atomicOr(&row[pos >> 5], bit);
+    }
+    __syncthreads();
+    for (int32_t w = threadIdx.x; w < g_n * W; w += 256) J.bits[s0 * W + w] = row[w];
+    if (STATS) {
+        atomicAdd(a.work, (unsigned long long)wc.nodes);
+        atomicAdd(a.work + 1, (unsigned long long)wc.tris);
+    }
+}
+
 // Six-axis cast.  One work item = AX_PER_WAVE samples x 6 world axes on the
 // 60 first lanes of a wavefront.  A ray whose axis points into the material
 // (n . D < 0) is not cast.  The ballot follows the traversal directly and
 // the per-sample 6-bit groups are stored after it.
 constexpr int AX_PER_WAVE = 10;
+// Most samples in one work item of the grouped hemisphere cast.
+constexpr int MAX_GROUP = 16;
 
 template <int STACK, bool STATS, bool STEP>
 __global__ __launch_bounds__(256) void k_cast_axes(CastArgs a) {
@@ -507,6 +571,11 @@ static hipError_t launch_cast(const CastArgs &args, hipStream_t s) {
         const int64_t blocks = (args.n_items + 3) / 4;   // four items per block
         if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
         k_cast_axes<STACK, STATS, STEP><<<(unsigned)blocks, 256, 0, s>>>(args);
+    } else if (args.group > 1) {
+        const int64_t blocks = args.n_items;             // `group` samples per block
+        if (blocks >= ((int64_t)1 << 31) || args.group > MAX_GROUP) return hipErrorInvalidValue;
+        const size_t lds = sizeof(int) * (4 * STACK * 64 + (size_t)args.W * args.group);
+        k_cast_rows_grouped<STACK, STATS, STEP><<<(unsigned)blocks, 256, lds, s>>>(args);
     } else {
         const int64_t blocks = args.n_items;             // one sample per block
         if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
@@ -541,8 +610,25 @@ hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, int traversal,
                                                 : launch_mode<true>(a, rpw, stack, stats, s);
 }
 
-int64_t cast_items(int32_t kind, int64_t n_samples) {
-    return kind == 1 ? (n_samples + AX_PER_WAVE - 1) / AX_PER_WAVE : n_samples;
+int32_t cast_group(int32_t n_dirs, int32_t setting) {
+    if (setting > 0) return setting;
+    if (n_dirs <= 0 || n_dirs >= 256) return 1;
+    int32_t best = 1;
+    double best_fill = 0.0;
+    for (int32_t g = 1; g <= MAX_GROUP; ++g) {
+        const int64_t rays = (int64_t)g * n_dirs, slots = (rays + 255) / 256 * 256;
+        const double fill = (double)rays / (double)slots;
+        if (fill > best_fill + 1e-12) {
+            best_fill = fill;
+            best = g;
+        }
+    }
+    return best;
+}
+
+int64_t cast_items(int32_t kind, int64_t n_samples, int32_t group) {
+    if (kind == 1) return (n_samples + AX_PER_WAVE - 1) / AX_PER_WAVE;
+    return group > 1 ? (n_samples + group - 1) / group : n_samples;
 }
 
 // The rays as the cast forms them: out[i][j] = (o, d).
@@ -584,7 +670,10 @@ extern "C" hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *c
     if (cfg->leaf_size < 0 || cfg->leaf_size > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 0..8");
     if (cfg->traversal != 0 && cfg->traversal != HRA_TRAVERSAL_STEP && cfg->traversal != HRA_TRAVERSAL_LEAF_LOOP)
         return ctx->fail(HRA_ERR_INVALID_ARG, "traversal must be 0, HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP");
+    if (cfg->samples_per_group < 0 || cfg->samples_per_group > MAX_GROUP)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "samples_per_group must be in 0..16");
     ctx->cast_rpw = cfg->rays_per_wave;
+    ctx->cast_group = cfg->samples_per_group;
     ctx->cast_stack = cfg->stack_depth;
     if (cfg->leaf_size) ctx->leaf_default = cfg->leaf_size;
     if (cfg->traversal) ctx->cast_traversal = cfg->traversal;
@@ -597,6 +686,7 @@ extern "C" hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *c
     cfg->stack_depth = ctx->cast_stack;
     cfg->leaf_size = ctx->leaf_default;
     cfg->traversal = ctx->cast_traversal;
+    cfg->samples_per_group = ctx->cast_group;
     return HRA_OK;
 }
 
@@ -637,7 +727,8 @@ static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, co
     a.n_dirs = dirs.n;
     a.kind = dirs.kind == HRA_DIRS_AXES6 ? 1 : 0;
     a.W = (dirs.n + 31) / 32;
-    a.n_items = cast_items(a.kind, samples->n);
+    a.group = a.kind == 0 ? cast_group(dirs.n, ctx->cast_group) : 1;
+    a.n_items = cast_items(a.kind, samples->n, a.group);
     a.err = ctx->d_err;
     a.work = work;
     if (a.n_items >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many samples for one call");

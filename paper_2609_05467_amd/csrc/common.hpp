@@ -103,6 +103,7 @@ struct hra_ctx {
     int32_t cast_rpw = 64;            // directions per wave work item
     int32_t cast_stack = 16;          // LDS stack entries per lane
     int32_t cast_traversal = HRA_TRAVERSAL_STEP;   // traversal loop (hra.h)
+    int32_t cast_group = 0;           // samples per hemisphere work item (0: chosen from the direction count)
     int32_t leaf_default = 4;         // leaf size of builds whose options give 0
     std::string err;
     std::map<std::pair<int, int>, float4 *> dir_tables;  // (kind, n) -> device float4 [n]
@@ -190,7 +191,8 @@ struct CastArgs {
     int32_t n_dirs;
     int32_t kind;              // 0: rotate hemisphere onto the normal, 1: world axes (cull n.D < 0)
     int32_t W;                 // words per row
-    int64_t n_items;           // cast_items(kind, samples)
+    int64_t n_items;           // cast_items(kind, samples, group)
+    int32_t group;             // hemisphere cast: samples per work item (cast_group)
     uint32_t *err;
     unsigned long long *work;  // instrumented variant: {node fetches, triangle tests}
 };
@@ -204,7 +206,13 @@ CastJob make_cast_job(const hra_bvh *bvh, int32_t part, const float *origin, con
 hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, int traversal, bool stats, hipStream_t s);
 // Work items of a cast over n samples: one per sample (hemisphere), one per
 // ten samples (six axes).
-int64_t cast_items(int32_t kind, int64_t n_samples);
+// Work items of a cast: hemisphere, ceil(n_samples / group); six-axis,
+// ceil(n_samples / AX_PER_WAVE).
+int64_t cast_items(int32_t kind, int64_t n_samples, int32_t group);
+// Samples per hemisphere work item for n_dirs directions: `setting` if
+// nonzero, else the count in 1..16 that leaves the fewest of a workgroup's
+// 256 lanes idle (1 from 256 directions on).
+int32_t cast_group(int32_t n_dirs, int32_t setting);
 
 // ---------------------------------------------------------------- builds
 // A build in three steps, so that it can run in memory set aside earlier

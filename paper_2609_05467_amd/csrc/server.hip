@@ -255,6 +255,7 @@ void launch_batch(hra_server *sv, const std::vector<uint64_t> &tickets) {
     sh.rpw = sv->ctx->cast_rpw;
     sh.stack = sv->ctx->cast_stack;
     sh.trav = sv->ctx->cast_traversal;
+    sh.group = cast_group(sh.N, sv->ctx->cast_group);
     sh.t_hemi = sv->t_hemi;
     sh.t_ax = sv->t_ax;
     int64_t S = 0;

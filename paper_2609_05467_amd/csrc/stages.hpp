@@ -46,7 +46,7 @@ struct StageBufs {
 struct StageShape {
     int32_t n_jobs;
     int64_t S, items, aitems;
-    int32_t N, W, rpw, stack, trav;
+    int32_t N, W, rpw, stack, trav, group;
     const float4 *t_hemi, *t_ax;
     SampleJob sj0;
     CastJob cj0, aj0;

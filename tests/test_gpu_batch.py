@@ -109,7 +109,7 @@ def _single(ctx, m, n, seed, N, tool, leaf=4):
     return s, bits, rep, su
 
 
-@pytest.mark.parametrize("N", [256, 1000])
+@pytest.mark.parametrize("N", [150, 256, 1000])
 def test_batch_run_matches_single_calls(ctx, meshes, N):
     import torch
     reqs = [{"verts": m.verts, "tris": m.tris, "n_samples": 500 + 311 * p, "seed": 100 + p,
@@ -226,7 +226,7 @@ def test_autotune_picks_a_point_and_keeps_results(ctx, meshes):
     assert {p["traversal"] for p in rep["points"]} == {hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP}
     best = rep["best"]
     assert best["ms"] == min(p["ms"] for p in rep["points"])
-    assert ctx.cast_config() == (best["rays_per_wave"], best["stack_depth"], best["leaf_size"], best["traversal"])
+    assert ctx.cast_config()[:4] == (best["rays_per_wave"], best["stack_depth"], best["leaf_size"], best["traversal"])
     # results of a single-part cast do not depend on the tuned shape
     m = meshes[0]
     b = ctx.build_bvh(m.verts, m.tris)

@@ -191,6 +191,29 @@ def test_cast_configs_identical(ctx, orc, cfg1):
     ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP)
 
 
+@pytest.mark.parametrize("N", [1, 7, 33, 100, 150, 255, 256])
+def test_cast_grouped_matches_one_sample_per_workgroup(ctx, orc, cfg1, N):
+    """Several samples per workgroup (chosen or forced) give the bits of one
+    sample per workgroup, on a sample count no group size divides, and the
+    same work counts."""
+    from paper_2609_05467_amd import hra
+    m, b = cfg1
+    _say("grouped", N)
+    s = ctx.sample_surface(b, 211, 12)
+    ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP, 1)
+    ref, _ = ctx.cast(b, s, N)
+    ref = _u32(ref)
+    _, nf1, nt1 = ctx.cast_work(b, s, N)
+    for g in (0, 2, 3, 5, 16):
+        ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP, g)
+        got, cnt = ctx.cast(b, s, N)
+        assert np.array_equal(_u32(got), ref), g
+        wb, nf, nt = ctx.cast_work(b, s, N)
+        assert np.array_equal(_u32(wb), ref) and (nf, nt) == (nf1, nt1), g
+    ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP, 0)
+    _cast_parity(ctx, orc, m, b, 211, N, 12, s=s)
+
+
 def test_convex_box_all_free(ctx):
     m = P.box_part()
     b = ctx.build_bvh(m.verts, m.tris)
