@@ -560,9 +560,30 @@ __device__ inline void child_box(const float4 *tri4, const float *box_int, int32
 // slower for the whole build); nothing here needs that, since no plain
 // (L2-cached) store is shared.  The compiler fences keep the shared
 // accesses on their side of the increment.
-__global__ void k_refit(const float4 *tri4, const int32_t *parent_leaf, const int32_t *parent_int, const int32_t *left,
-                        const int32_t *right, const int32_t *first, const int32_t *last, int leaf_size,
-                        float *box_int, int32_t *height, uint32_t *flags, const int32_t *n_valid_total) {
+// Relative costs of the traversal's two units of work for the collapse
+// decision: one interior-node visit (both child boxes) and one ray-triangle
+// test, in VALU operations.
+constexpr float SAH_NODE = 50.0f, SAH_TRI = 54.0f;
+
+__device__ inline float half_area(const float *bx) {
+    const float dx = bx[3] - bx[0], dy = bx[4] - bx[1], dz = bx[5] - bx[2];
+    return (dx * dy + dy * dz) + dz * dx;
+}
+
+__device__ inline float child_cost(const float4 *tri4, const float *cost, int32_t c) {
+    if ((uint32_t)c & KLEAF) {
+        float bx[6];
+        tri_box(tri4, (int)((uint32_t)c & ~KLEAF), bx);
+        return SAH_TRI * half_area(bx);
+    }
+    return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t *>(cost) + c, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__global__ void k_refit(const float4 *tri4, const uint64_t *keys, const int32_t *parent_leaf, const int32_t *parent_int,
+                        const int32_t *left, const int32_t *right, const int32_t *first, const int32_t *last,
+                        int leaf_size, float *box_int, float *cost, int32_t *leafy, int32_t *height, uint32_t *flags,
+                        const int32_t *n_valid_total) {
     const int n = *n_valid_total;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n || n < 2) return;
@@ -574,18 +595,31 @@ __global__ void k_refit(const float4 *tri4, const int32_t *parent_leaf, const in
         const uint32_t old = __hip_atomic_fetch_add(&flags[node], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (old == 0) return;  // the sibling subtree is not done yet
-        float a[6], b[6];
+        float a[6], b[6], u[6];
         const int32_t l = left[node], r = right[node];
         child_box(tri4, box_int, l, a);
         child_box(tri4, box_int, r, b);
         uint32_t *dst = reinterpret_cast<uint32_t *>(box_int) + 6 * (int64_t)node;
         for (int k = 0; k < 3; ++k) {
-            __hip_atomic_store(dst + k, __float_as_uint(fminf(a[k], b[k])), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(dst + 3 + k, __float_as_uint(fmaxf(a[3 + k], b[3 + k])), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            u[k] = fminf(a[k], b[k]);
+            u[3 + k] = fmaxf(a[3 + k], b[3 + k]);
+            __hip_atomic_store(dst + k, __float_as_uint(u[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(dst + 3 + k, __float_as_uint(u[3 + k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        // Surface-area cost: a subtree of at most leaf_size triangles (all of
+        // one part) becomes a single leaf when testing its triangles costs
+        // less than traversing it.
+        const int cnt = last[node] - first[node] + 1;
+        const float A = half_area(u);
+        const float keep = (SAH_NODE * A + child_cost(tri4, cost, l)) + child_cost(tri4, cost, r);
+        const float as_leaf = (SAH_TRI * (float)cnt) * A;
+        const bool one_part = (keys[first[node]] >> 56) == (keys[last[node]] >> 56);
+        const bool col = cnt <= leaf_size && one_part && as_leaf <= keep;
+        __hip_atomic_store(reinterpret_cast<uint32_t *>(cost) + node, __float_as_uint(col ? as_leaf : keep),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(leafy + node, col ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int h = 0;
-        if (last[node] - first[node] + 1 > leaf_size) {
+        if (!col) {
             const int hl = ((uint32_t)l & KLEAF) ? 0 : __hip_atomic_load(height + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int hr = ((uint32_t)r & KLEAF) ? 0 : __hip_atomic_load(height + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             h = 1 + (hl > hr ? hl : hr);
@@ -622,13 +656,22 @@ __global__ void k_small_roots(PartMeta *meta, int n_parts, int leaf_size) {
 }
 
 __global__ void k_emit(const float4 *tri4, const uint64_t *keys, const int32_t *left, const int32_t *right,
-                       const int32_t *first, const int32_t *last, const float *box_int, int leaf_size,
-                       const int32_t *n_valid_total, Node *nodes, uint8_t *emitted) {
+                       const int32_t *first, const int32_t *last, const int32_t *parent_int, const int32_t *leafy,
+                       const float *box_int, int leaf_size, const int32_t *n_valid_total, Node *nodes,
+                       uint8_t *emitted) {
     const int n = *n_valid_total;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
     emitted[i] = 0;
-    if (last[i] - first[i] + 1 <= leaf_size) return;
+    if (last[i] - first[i] + 1 <= leaf_size) {
+        // inside a collapsed subtree (this node, or an ancestor of at most
+        // leaf_size triangles that became the leaf) it is not a node at all
+        if (leafy[i]) return;
+        for (int p = parent_int[i], g = 0; p >= 0 && g < 16; p = parent_int[p], ++g) {
+            if (last[p] - first[p] + 1 > leaf_size) break;
+            if (leafy[p]) return;
+        }
+    }
     const int p = (int)(keys[first[i]] >> 56);
     if ((int)(keys[last[i]] >> 56) != p) return;   // spans two parts: never traversed
     float bx[2][6];
@@ -642,8 +685,7 @@ __global__ void k_emit(const float4 *tri4, const uint64_t *keys, const int32_t *
             code[k] = leaf_code(q, 1);
         } else {
             load_box(box_int, c, bx[k]);
-            const int cnt = last[c] - first[c] + 1;
-            code[k] = cnt <= leaf_size ? leaf_code(first[c], cnt) : c;
+            code[k] = leafy[c] ? leaf_code(first[c], last[c] - first[c] + 1) : c;
         }
     }
     Node nd;
@@ -696,8 +738,8 @@ struct BuildWs {
     uint32_t *valid, *excl, *vals0, *vals1, *flags, *rs_ws;
     uint64_t *w, *keys0, *keys1, *scan64_ws;
     uint32_t *scan32_ws;
-    int32_t *L, *R, *F, *La, *PI, *PL, *nvt, *height;
-    float *box, *tv;
+    int32_t *L, *R, *F, *La, *PI, *PL, *nvt, *height, *leafy;
+    float *box, *tv, *cost;
     uint8_t *tpart, *emitted;
     PartAcc *acc;
 };
@@ -731,6 +773,8 @@ static size_t carve(char *base, int64_t T, int n_parts, BuildWs *w) {
     take((void **)&d.flags, sizeof(uint32_t) * nn);
     take((void **)&d.box, sizeof(float) * 6 * nn);
     take((void **)&d.height, sizeof(int32_t) * nn);
+    take((void **)&d.leafy, sizeof(int32_t) * nn);
+    take((void **)&d.cost, sizeof(float) * nn);
     take((void **)&d.emitted, sizeof(uint8_t) * nn);
     take((void **)&d.acc, sizeof(PartAcc) * n_parts);
     take((void **)&d.nvt, sizeof(int32_t));
@@ -849,8 +893,10 @@ hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s,
     k_gather<<<gT, TB, 0, s>>>(W.tv, vs, W.tpart, b->parts, W.nvt, b->tris, b->leaf_pos);
     k_karras<<<gN, TB, 0, s>>>(ks, W.nvt, W.L, W.R, W.F, W.La, W.PI, W.PL, b->parts);
     k_small_roots<<<blocks_for(n_parts, 64), 64, 0, s>>>(b->parts, n_parts, leaf);
-    k_refit<<<gT, TB, 0, s>>>(b->tris, W.PL, W.PI, W.L, W.R, W.F, W.La, leaf, W.box, W.height, W.flags, W.nvt);
-    k_emit<<<gN, TB, 0, s>>>(b->tris, ks, W.L, W.R, W.F, W.La, W.box, leaf, W.nvt, b->nodes, W.emitted);
+    k_refit<<<gT, TB, 0, s>>>(b->tris, ks, W.PL, W.PI, W.L, W.R, W.F, W.La, leaf, W.box, W.cost, W.leafy, W.height,
+                              W.flags, W.nvt);
+    k_emit<<<gN, TB, 0, s>>>(b->tris, ks, W.L, W.R, W.F, W.La, W.PI, W.leafy, W.box, leaf, W.nvt, b->nodes,
+                             W.emitted);
     k_part_nodes<<<dim3(FACT_BLOCKS, n_parts), 256, 0, s>>>(W.emitted, W.height, W.nvt, b->parts);
     return hipGetLastError();
 }
