@@ -494,6 +494,154 @@ int orc_cast_rays(const float *V, const int32_t *T, int64_t nt, const float *O, 
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Tool-aware accessibility (the tool-geometry row next to Section 3.3's
+ * reach test; the paper's rays are infinitely thin).  A ball-end tool of
+ * radius r touches the surface point p from outside: its tip centre is
+ * c = p + r n (FP64 from the FP32 p and n), and the tool, shank included,
+ * fills every point within r of the half-line L = {c + t u, t >= 0}, u the
+ * direction normalised in FP64.  The direction is free iff no triangle comes
+ * closer to L than thr = r - tol.  Distance between L and a triangle, the
+ * plain definition: 0 if L meets the triangle, else the least of the
+ * distance from c to the triangle and the distances from L to its three
+ * edges (for convex sets the nearest pair has an end point of one set, or
+ * lies in both interiors, which for a line and a triangle means L meets it
+ * or runs parallel to it and the edge distances attain it). */
+static double seg_point(const double *x, const double *a, const double *b) {
+    /* distance from x to the segment [a, b] */
+    double e[3], w[3], q[3];
+    for (int k = 0; k < 3; ++k) { e[k] = b[k] - a[k]; w[k] = x[k] - a[k]; }
+    double ee = dot3(e, e), s = ee > 0 ? dot3(w, e) / ee : 0.0;
+    if (s < 0) s = 0;
+    if (s > 1) s = 1;
+    for (int k = 0; k < 3; ++k) q[k] = w[k] - s * e[k];
+    return norm3(q);
+}
+
+static double ray_point(const double *c, const double *u, const double *x) {
+    /* distance from x to the half-line c + t u, t >= 0 (u unit) */
+    double w[3], q[3];
+    for (int k = 0; k < 3; ++k) w[k] = x[k] - c[k];
+    double t = dot3(w, u);
+    if (t < 0) t = 0;
+    for (int k = 0; k < 3; ++k) q[k] = w[k] - t * u[k];
+    return norm3(q);
+}
+
+static double ray_segment(const double *c, const double *u, const double *a, const double *b) {
+    double best = ray_point(c, u, a);
+    double d2 = ray_point(c, u, b);
+    if (d2 < best) best = d2;
+    d2 = seg_point(c, a, b);
+    if (d2 < best) best = d2;
+    /* both interiors: the common perpendicular of the two lines */
+    double e[3], w[3];
+    for (int k = 0; k < 3; ++k) { e[k] = b[k] - a[k]; w[k] = c[k] - a[k]; }
+    double B = dot3(u, e), Cc = dot3(e, e), D = dot3(u, w), E = dot3(e, w);
+    double den = Cc - B * B;   /* |u| = 1 */
+    if (den > 1e-300 * (Cc > 1 ? Cc : 1)) {
+        double t = (B * E - Cc * D) / den, sp = (E - B * D) / den;
+        if (t > 0 && sp > 0 && sp < 1) {
+            double q[3];
+            for (int k = 0; k < 3; ++k) q[k] = w[k] + t * u[k] - sp * e[k];
+            d2 = norm3(q);
+            if (d2 < best) best = d2;
+        }
+    }
+    return best;
+}
+
+static double tri_point(const double *x, const double v[3][3]) {
+    /* distance from x to the triangle: the plane when x projects inside it,
+     * else the nearest edge */
+    double e1[3], e2[3], w[3], nrm[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = v[1][k] - v[0][k]; e2[k] = v[2][k] - v[0][k]; w[k] = x[k] - v[0][k]; }
+    cross3(e1, e2, nrm);
+    double nn = dot3(nrm, nrm);
+    if (nn > 0) {
+        /* barycentric coordinates of the projection */
+        double d11 = dot3(e1, e1), d12 = dot3(e1, e2), d22 = dot3(e2, e2), dw1 = dot3(w, e1), dw2 = dot3(w, e2);
+        double den = d11 * d22 - d12 * d12;
+        double b1 = (d22 * dw1 - d12 * dw2) / den, b2 = (d11 * dw2 - d12 * dw1) / den;
+        if (b1 >= 0 && b2 >= 0 && b1 + b2 <= 1) return fabs(dot3(w, nrm)) / sqrt(nn);
+    }
+    double best = seg_point(x, v[0], v[1]), d;
+    if ((d = seg_point(x, v[1], v[2])) < best) best = d;
+    if ((d = seg_point(x, v[2], v[0])) < best) best = d;
+    return best;
+}
+
+static int ray_meets(const double *c, const double *u, const double v[3][3]) {
+    /* the half-line meets the (closed) triangle: signed volumes */
+    double a[3], b[3], cc[3], X[3];
+    for (int k = 0; k < 3; ++k) { a[k] = v[0][k] - c[k]; b[k] = v[1][k] - c[k]; cc[k] = v[2][k] - c[k]; }
+    cross3(b, cc, X);
+    double e0 = dot3(u, X);
+    cross3(cc, a, X);
+    double e1 = dot3(u, X);
+    cross3(a, b, X);
+    double e2 = dot3(u, X);
+    if (!((e0 >= 0 && e1 >= 0 && e2 >= 0) || (e0 <= 0 && e1 <= 0 && e2 <= 0))) return 0;
+    double ba[3], ca[3], P[3];
+    for (int k = 0; k < 3; ++k) { ba[k] = b[k] - a[k]; ca[k] = cc[k] - a[k]; }
+    cross3(ba, ca, P);
+    double h = dot3(a, P), q = dot3(u, P);
+    return (h >= 0 && q > 0) || (h <= 0 && q < 0);
+}
+
+double orc_tool_distance(const double *v9, const double *c, const double *u) {
+    double v[3][3];
+    memcpy(v, v9, sizeof(v));
+    if (ray_meets(c, u, v)) return 0.0;
+    double best = tri_point(c, v), d;
+    for (int k = 0; k < 3; ++k)
+        if ((d = ray_segment(c, u, v[k], v[(k + 1) % 3])) < best) best = d;
+    return best;
+}
+
+/* bits: 1 = free; amb: 1 = some triangle within +-band of thr and none below
+ * thr - band (excluded from comparisons).  kind as in orc_cast. */
+int orc_cast_tool(const float *V, const int32_t *T, int64_t nt, const float *Pt, const float *Nrm, int64_t s0,
+                  int64_t s1, const float *dirs, int32_t N, int32_t kind, double r, double tol, double band,
+                  uint32_t *bits, uint32_t *amb, int32_t nthreads) {
+    const int32_t W = (N + 31) / 32;
+    const double thr = r - tol;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = s0; s < s1; ++s) {
+        const float *n = Nrm + 3 * s, *p = Pt + 3 * s;
+        float t3[3], b3[3];
+        orc_frame(n, t3, b3);
+        double c[3];
+        for (int k = 0; k < 3; ++k) c[k] = (double)p[k] + r * (double)n[k];
+        uint32_t *rb = bits + (s - s0) * W, *ra = amb + (s - s0) * W;
+        for (int32_t w = 0; w < W; ++w) rb[w] = ra[w] = 0;
+        for (int32_t j = 0; j < N; ++j) {
+            float d[3];
+            if (kind == 0) world_dir(t3, b3, n, dirs + 3 * j, d);
+            else { d[0] = dirs[3 * j]; d[1] = dirs[3 * j + 1]; d[2] = dirs[3 * j + 2]; }
+            if (kind == 1 && n[0] * d[0] + n[1] * d[1] + n[2] * d[2] < 0.0f) continue;   /* culled */
+            double dd[3] = {d[0], d[1], d[2]};
+            double L = sqrt((dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2]);
+            double u[3] = {dd[0] / L, dd[1] / L, dd[2] / L};
+            int blocked = 0, near = 0;
+            for (int64_t f = 0; f < nt && !blocked; ++f) {
+                double v[3][3];
+                tri_verts(V, T, f, v);
+                double dist = orc_tool_distance(&v[0][0], c, u);
+                if (dist < thr - band) blocked = 1;
+                else if (dist <= thr + band) near = 1;
+            }
+            uint32_t m = 1u << (j & 31);
+            if (!blocked && !near) rb[j >> 5] |= m;
+            if (!blocked && near) ra[j >> 5] |= m;
+        }
+    }
+    return 0;
+}
+
 /* Decision of one (ray, triangle) pair, for tests: returns DEC_* and the
  * informational exact-sign verdict. */
 int orc_decide_one(const double *v9, const double *o, const double *d, int32_t *info) {

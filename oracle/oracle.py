@@ -42,6 +42,11 @@ def lib():
         P = C.c_void_p
         i64, i32, u64, f32 = C.c_int64, C.c_int32, C.c_uint64, C.c_float
         L.orc_splitmix64.argtypes = [u64, u64, i64, P]
+        L.orc_cast_tool.argtypes = [P, P, i64, P, P, i64, i64, P, i32, i32, C.c_double, C.c_double, C.c_double,
+                                    P, P, i32]
+        L.orc_cast_tool.restype = C.c_int
+        L.orc_tool_distance.argtypes = [P, P, P]
+        L.orc_tool_distance.restype = C.c_double
         L.orc_fibonacci_dirs.argtypes = [i32, P]
         L.orc_axes6.argtypes = [P]
         L.orc_frame.argtypes = [P, P, P]
@@ -191,6 +196,34 @@ def cast_rays(verts, tris, origins, dirs, threads=0):
     out = np.empty(len(O), np.uint8)
     lib().orc_cast_rays(_p(v), _p(t), len(t), _p(O), _p(D), len(O), _p(out), threads)
     return out
+
+
+TOOL_TOL_FRAC = 1e-4    # tool clearance tolerance: 1e-4 x bbox diagonal
+TOOL_BAND_FRAC = 1e-9   # decisions this close to the threshold (x diagonal) are ambiguous
+
+
+def cast_tool(verts, tris, samples, dirs, radius, kind=0, s0=0, s1=None, threads=0):
+    """Brute-force tool cast (ball-end tool of `radius` touching each sample
+    point from outside).  Returns (bits, ambiguous), uint32 [S][W]."""
+    v, t = _f32(verts), _i32(tris)
+    Pt, Nn, d = _f32(samples["point"]), _f32(samples["normal"]), _f32(dirs)
+    s1 = len(Pt) if s1 is None else s1
+    N = len(d)
+    W = (N + 31) // 32
+    S = s1 - s0
+    _, diag, _ = mesh_info(verts)
+    bits = np.empty((S, W), np.uint32)
+    amb = np.empty((S, W), np.uint32)
+    lib().orc_cast_tool(_p(v), _p(t), len(t), _p(Pt), _p(Nn), s0, s1, _p(d), N, kind, float(radius),
+                        TOOL_TOL_FRAC * diag, TOOL_BAND_FRAC * diag, _p(bits), _p(amb), threads)
+    return bits, amb
+
+
+def tool_distance(tri9, c, u):
+    """FP64 distance between the half-line c + t u (t >= 0, u unit) and a triangle (9 coordinates)."""
+    a = np.ascontiguousarray(tri9, np.float64).reshape(9)
+    return lib().orc_tool_distance(_p(a), _p(np.ascontiguousarray(c, np.float64)),
+                                   _p(np.ascontiguousarray(u, np.float64)))
 
 
 def decide_one(tri9, o, d):
