@@ -81,6 +81,40 @@ def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
                          "measured_traffic_bytes": traffic, "l2_hit_rate": l2_hit}}
 
 
+# Tool-aware cast (hra_cast_tool): FP32 operations per node visit (two slab
+# tests against grown boxes: 28 each) and FP64 operations per triangle
+# distance test (the half-line meeting test 76, the point-triangle distance
+# 60, three edge distances 110 each, no early exit).  FP64 vector arithmetic
+# runs at one operation per lane and clock on this chip, like FP32 without
+# packing, so both count against the same peak.
+TOOL_NODE_OPS, TOOL_TRI_OPS = 56, 470
+TOOL_RADIUS_MM = 3.0
+
+
+def tool_extra(ctx, bvh, samples, N, reps=3):
+    """Tool-aware cast (ball-end tool of TOOL_RADIUS_MM) over the same samples
+    and directions: time by HIP events, work per direction, ALU roofline."""
+    import torch
+    S = samples["origin"].shape[0]
+    bits, cnt = ctx.cast_tool(bvh, samples, N, TOOL_RADIUS_MM)
+    free = int(cnt.to(torch.int64).sum())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.cast_tool(bvh, samples, N, TOOL_RADIUS_MM, counts=False, bits=bits)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    wb, nv, nt = ctx.cast_tool_work(bvh, samples, N, TOOL_RADIUS_MM)
+    rays = S * N
+    ops = nv * TOOL_NODE_OPS + nt * TOOL_TRI_OPS
+    return {"radius_mm": TOOL_RADIUS_MM, "ms": ms, "dirs_per_s": rays / (ms * 1e-3),
+            "node_visits_per_dir": nv / rays, "distance_tests_per_dir": nt / rays,
+            "instrumented_bits_identical": bool(torch.equal(wb, bits)), "free_fraction": free / rays,
+            "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
+                         "frac": ops / (ms * 1e-3) / 1e12 / ALU_PEAK_TOPS, "ops_per_dir": ops / rays}}
+
+
 # Canonical frame (hra_frame_estimate), algorithmic HBM bytes: per face the
 # indices (12), the record and bin written (36), the histogram pass (bin and
 # area, 12), two bin-mean passes (bins, 8), four cone passes (records, 128)
@@ -430,12 +464,18 @@ def run_paper_shape(args):
     }
     for n, p in zip(names, per):
         ms = float(np.mean(p["ms"]))
+        b = ctx.build_bvh(p["v"], p["t"], leaf_size=args.leaf)
+        ctx.sample_surface(b, p["S"], 0, mode=hra.SAMPLE_CENTROID, out=p["samples"])
+        log(f"[bench] tool cast on {n}")
+        tool = tool_extra(ctx, b, p["samples"], N)
+        b.release()
         out["parts"][n] = {
             "faces": p["mesh"].n_tris, "samples": p["S"], "ms": ms, "rays_per_s": p["S"] * N / (ms * 1e-3),
             "result": {"access": p["rep"]["access"], "multi_axis": p["rep"]["multi_axis"],
                        "shares": p["rep"]["shares"], "mean_conc": p["rep"]["conc"],
                        "min_setups": p["su"]["min_count"], "greedy_setups": p["su"]["greedy_count"]},
             "paper_table3_context": dict(PAPER_TABLE3[n], hardware="GeForce GTX 1650 (another machine, another part)"),
+            "tool": tool,
         }
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (housing part)")

@@ -219,6 +219,30 @@ typedef struct {
 hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *cfg);
 hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
 
+/* Tool-aware accessibility (the paper's rays are infinitely thin; its
+ * Section 3.3 reach test and its limitations concern the real tool).  A
+ * ball-end tool of radius tool_radius (mm) touches each sample point p from
+ * outside: tip centre c = p + r n (FP64 from the FP32 point and normal),
+ * and the tool, shank included, fills every point within r of the
+ * half-line from c along the approach direction (the direction normalised
+ * in FP64).  Direction j is free (bit 1) iff no triangle of the part comes
+ * closer to that half-line than r - tol, tol = 1e-4 x the part's
+ * bounding-box diagonal.  Directions as in hra_cast_part: the Fibonacci
+ * hemisphere rotated onto each normal, or HRA_DIRS_AXES6 (an axis with
+ * n . D < 0 is not cast: bit 0).  Uses samples->point and ->normal; the
+ * origin is not used.  d_bits: uint32 [n][ceil(N/32)], d_counts: uint32
+ * [n] or NULL.  A radius of at most 2 tol sets the error word
+ * (HRA_ERR_INVALID_ARG at the next synchronising call); a non-positive or
+ * non-finite one fails at once.  Enqueues on `stream`. */
+hra_status hra_cast_tool(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples, hra_dirs dirs,
+                         double tool_radius, uint32_t *d_bits, uint32_t *d_counts, void *stream);
+/* The same tool cast (identical bits) in an instrumented build that also
+ * counts, over all directions, the interior nodes visited and the
+ * triangle-distance tests made.  Synchronises `stream`. */
+hra_status hra_cast_tool_work(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                              hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint64_t *node_visits,
+                              uint64_t *tri_tests, void *stream);
+
 /* The same cast as hra_cast_hemisphere (identical bits) in an instrumented
  * build of the traversal that also counts, over all rays, the interior
  * nodes fetched and the ray-triangle tests made.  These counts give the

@@ -24,7 +24,8 @@ enum : uint32_t {
     ERR_BAD_INDEX = 1u << 0,     // a triangle index outside [0, n_verts)
     ERR_EMPTY_MESH = 1u << 1,    // no triangle with nonzero area
     ERR_STACK = 1u << 2,         // traversal stack exhausted
-    ERR_BAD_SAMPLE_TRI = 1u << 3 // a sample names a face that is not in the mesh
+    ERR_BAD_SAMPLE_TRI = 1u << 3, // a sample names a face that is not in the mesh
+    ERR_TOOL_RADIUS = 1u << 4     // a tool radius below twice the clearance tolerance
 };
 
 #define HRA_HIP(call)                                                                      \

@@ -139,6 +139,8 @@ hra_status check_error_word(hra_ctx *ctx, hipStream_t s) {
     if (w & ERR_BAD_INDEX) return ctx->fail(HRA_ERR_BAD_MESH, "triangle index out of range");
     if (w & ERR_EMPTY_MESH) return ctx->fail(HRA_ERR_BAD_MESH, "mesh has no triangle with nonzero area");
     if (w & ERR_BAD_SAMPLE_TRI) return ctx->fail(HRA_ERR_INVALID_ARG, "a sample names a face outside the mesh");
+    if (w & ERR_TOOL_RADIUS)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "tool radius below 2e-4 x the part's bounding-box diagonal");
     if (w & ERR_STACK) return ctx->fail(HRA_ERR_DEVICE, "traversal stack exhausted");
     return ctx->fail(HRA_ERR_DEVICE, "device error word set");
 }

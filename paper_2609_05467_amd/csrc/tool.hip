@@ -1,0 +1,366 @@
+// Tool-aware accessibility.  The paper's rays are infinitely thin; a real
+// cutter is not (Section 3.3 checks tool reach along the six axes; tool
+// geometry is listed as a limitation).  Here a ball-end tool of radius r
+// touches each sample point p from outside: its tip centre is c = p + r n
+// and the tool, shank included, fills every point within r of the half-line
+// L = {c + t u, t >= 0}, u the approach direction.  A direction is free iff
+// no triangle of the part comes closer to L than r - tol, tol = 1e-4 x the
+// part's bounding-box diagonal (the tool touches its own face at exactly r).
+//
+// One lane per (sample, direction), the directions of a sample on
+// consecutive lanes in traversal order (neighbouring rays, shared nodes).
+// The hierarchy is walked with FP32 slab tests against boxes grown by r and
+// a margin (conservative: the capsule inside a grown box's sweep), and each
+// candidate triangle's distance to L is computed in FP64: the plain
+// definition (0 if L meets the triangle, else the least of the distance
+// from c to the triangle and the three edge-to-L distances).
+#include <cmath>
+
+#include "common.hpp"
+
+namespace hra {
+namespace {
+
+constexpr int TOOL_THREADS = 256;
+constexpr int TOOL_STACK = 32;    // LDS entries per lane
+constexpr int TOOL_SPILL = 64;    // private overflow
+
+struct ToolArgs {
+    const Node *nodes;
+    const float4 *tris;
+    const PartMeta *meta;
+    const float *point, *normal;
+    const float4 *dirs;           // hemisphere: traversal order, w = canonical index bits; axes: the six axes
+    int32_t n_dirs, kind, W, n_nodes_alloc;
+    int64_t n_samples, n_rays;
+    double radius;
+    uint32_t *bits;               // [n_samples][W], cleared first
+    uint32_t *err;
+    unsigned long long *work;     // instrumented launch: {node visits, triangle distance tests}
+};
+
+struct D3 {
+    double x, y, z;
+};
+__device__ inline D3 mk(double x, double y, double z) { return D3{x, y, z}; }
+__device__ inline D3 operator-(D3 a, D3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ inline D3 operator+(D3 a, D3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ inline D3 operator*(double s, D3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+__device__ inline double dot(D3 a, D3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ inline D3 cross(D3 a, D3 b) { return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+__device__ inline double norm(D3 a) { return sqrt(dot(a, a)); }
+__device__ inline D3 f4d(float4 v) { return mk(v.x, v.y, v.z); }
+
+// distance from x to the segment [a, b]
+__device__ inline double seg_dist(D3 x, D3 a, D3 b) {
+    const D3 e = b - a, w = x - a;
+    const double ee = dot(e, e);
+    double s = ee > 0.0 ? dot(w, e) / ee : 0.0;
+    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+    return norm(w - s * e);
+}
+
+// distance from x to the half-line c + t u (u unit)
+__device__ inline double ray_dist(D3 c, D3 u, D3 x) {
+    const D3 w = x - c;
+    double t = dot(w, u);
+    t = t < 0.0 ? 0.0 : t;
+    return norm(w - t * u);
+}
+
+// distance between the half-line and the segment: an end point of one of
+// them, or the common perpendicular when it falls inside both
+__device__ inline double ray_seg_dist(D3 c, D3 u, D3 a, D3 b) {
+    double best = fmin(fmin(ray_dist(c, u, a), ray_dist(c, u, b)), seg_dist(c, a, b));
+    const D3 e = b - a, w = c - a;
+    const double B = dot(u, e), C = dot(e, e), D = dot(u, w), E = dot(e, w);
+    const double den = C - B * B;
+    if (den > 1e-300 * (C > 1.0 ? C : 1.0)) {
+        const double t = (B * E - C * D) / den, s = (E - B * D) / den;
+        if (t > 0.0 && s > 0.0 && s < 1.0) best = fmin(best, norm((w + t * u) - s * e));
+    }
+    return best;
+}
+
+// distance from x to the triangle: to its plane when x projects inside it,
+// else to the nearest edge
+__device__ inline double tri_dist(D3 x, D3 a, D3 b, D3 c) {
+    const D3 e1 = b - a, e2 = c - a, w = x - a;
+    const D3 nrm = cross(e1, e2);
+    const double nn = dot(nrm, nrm);
+    if (nn > 0.0) {
+        const double d11 = dot(e1, e1), d12 = dot(e1, e2), d22 = dot(e2, e2), w1 = dot(w, e1), w2 = dot(w, e2);
+        const double den = d11 * d22 - d12 * d12;
+        const double b1 = (d22 * w1 - d12 * w2) / den, b2 = (d11 * w2 - d12 * w1) / den;
+        if (b1 >= 0.0 && b2 >= 0.0 && b1 + b2 <= 1.0) return fabs(dot(w, nrm)) / sqrt(nn);
+    }
+    return fmin(fmin(seg_dist(x, a, b), seg_dist(x, b, c)), seg_dist(x, c, a));
+}
+
+// the half-line meets the closed triangle (signed volumes about c)
+__device__ inline bool ray_meets(D3 c, D3 u, D3 A, D3 B, D3 C) {
+    const D3 a = A - c, b = B - c, cc = C - c;
+    const double e0 = dot(u, cross(b, cc)), e1 = dot(u, cross(cc, a)), e2 = dot(u, cross(a, b));
+    const bool inside = (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) || (e0 <= 0.0 && e1 <= 0.0 && e2 <= 0.0);
+    const D3 P = cross(b - a, cc - a);
+    const double h = dot(a, P), q = dot(u, P);
+    return inside && ((h >= 0.0 && q > 0.0) || (h <= 0.0 && q < 0.0));
+}
+
+// Cheap FP32 screen: the triangle lies inside the sphere about its centroid
+// m of radius rho (its farthest vertex), so it is at least
+// |axis to m| - rho from the axis.  When that exceeds thr by the margin
+// (far above the FP32 rounding of these few operations), it cannot block.
+__device__ inline bool far_from_axis(float cx, float cy, float cz, float ux, float uy, float uz, float4 A, float4 B,
+                                     float4 C, float thr_hi) {
+    const float mx = ((A.x + B.x) + C.x) * (1.0f / 3.0f), my = ((A.y + B.y) + C.y) * (1.0f / 3.0f),
+                mz = ((A.z + B.z) + C.z) * (1.0f / 3.0f);
+    const float ax = A.x - mx, ay = A.y - my, az = A.z - mz, bx = B.x - mx, by = B.y - my, bz = B.z - mz;
+    const float qx = C.x - mx, qy = C.y - my, qz = C.z - mz;
+    const float rho2 = fmaxf(fmaxf((ax * ax + ay * ay) + az * az, (bx * bx + by * by) + bz * bz),
+                             (qx * qx + qy * qy) + qz * qz);
+    const float wx = mx - cx, wy = my - cy, wz = mz - cz;
+    const float t = fmaxf((wx * ux + wy * uy) + wz * uz, 0.0f);
+    const float px = wx - t * ux, py = wy - t * uy, pz = wz - t * uz;
+    const float d = sqrtf((px * px + py * py) + pz * pz);
+    return d - sqrtf(rho2) > thr_hi;
+}
+
+// true when the triangle comes closer than thr to the tool axis
+__device__ inline bool tool_blocked(D3 c, D3 u, float4 A4, float4 B4, float4 C4, double thr) {
+    const D3 A = f4d(A4), B = f4d(B4), C = f4d(C4);
+    if (ray_meets(c, u, A, B, C)) return true;
+    if (tri_dist(c, A, B, C) < thr) return true;
+    return fmin(fmin(ray_seg_dist(c, u, A, B), ray_seg_dist(c, u, B, C)), ray_seg_dist(c, u, C, A)) < thr;
+}
+
+// FP32 slab test against a box grown by pad on every side
+__device__ inline bool grown_slab(float lx, float ly, float lz, float hx, float hy, float hz, float pad, float ox,
+                                  float oy, float oz, float ix, float iy, float iz, float &tn) {
+    const float tx0 = ((lx - pad) - ox) * ix, tx1 = ((hx + pad) - ox) * ix;
+    const float ty0 = ((ly - pad) - oy) * iy, ty1 = ((hy + pad) - oy) * iy;
+    const float tz0 = ((lz - pad) - oz) * iz, tz1 = ((hz + pad) - oz) * iz;
+    const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+    tn = tmin;
+    return tmin <= tmax * 1.0000006f;
+}
+
+__device__ inline float rcp_guarded(float x) { return fabsf(x) > 1e-30f ? 1.0f / x : copysignf(1e30f, x); }
+
+template <bool STATS>
+__global__ __launch_bounds__(TOOL_THREADS) void k_cast_tool(ToolArgs a) {
+    __shared__ int stk[TOOL_STACK * TOOL_THREADS];
+    const int64_t g = (int64_t)blockIdx.x * TOOL_THREADS + threadIdx.x;
+    if (g >= a.n_rays) return;
+    const int lane = threadIdx.x;
+    const int64_t s = g / a.n_dirs;
+    const int32_t j = (int32_t)(g - s * a.n_dirs);
+    const PartMeta &P = *a.meta;
+    const float px = a.point[3 * s], py = a.point[3 * s + 1], pz = a.point[3 * s + 2];
+    const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
+    const float4 l = a.dirs[j];
+    int32_t idx;
+    float3 d;
+    if (a.kind == 0) {
+        float3 t, b;
+        onb_frame(nx, ny, nz, t, b);
+        d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+        idx = __float_as_int(l.w);
+    } else {
+        d = make_float3(l.x, l.y, l.z);
+        idx = j;
+        if ((nx * d.x + ny * d.y) + nz * d.z < 0.0f) return;   // into the material: not cast, bit 0
+    }
+    const double r = a.radius, tol = 1e-4 * P.diag, thr = r - tol;
+    if (!(thr > tol)) {   // a tool thinner than twice the tolerance is not meaningful
+        atomicOr(a.err, ERR_TOOL_RADIUS);
+        return;
+    }
+    const D3 c = mk((double)px + r * (double)nx, (double)py + r * (double)ny, (double)pz + r * (double)nz);
+    const double dl = sqrt(((double)d.x * d.x + (double)d.y * d.y) + (double)d.z * d.z);
+    const D3 u = mk(d.x / dl, d.y / dl, d.z / dl);
+    const int32_t root = P.root, n_valid = P.n_valid, n_tris_alloc = P.leaf_lo + P.n_valid;
+    bool blocked = false;
+    uint32_t n_nodes = 0, n_tests = 0;
+    if (n_valid > 0) {
+        // FP32 box tests from the rounded tip centre; the margin covers the
+        // rounding of the centre and of the grown box faces
+        const float cx = (float)c.x, cy = (float)c.y, cz = (float)c.z;
+        const float pad = (float)(r * 1.0001) + (float)(1e-5 * P.diag);
+        const float ix = rcp_guarded(d.x), iy = rcp_guarded(d.y), iz = rcp_guarded(d.z);
+        // unit direction and threshold for the FP32 screen; the margin
+        // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a
+        // part far from the origin) is far above the screen's rounding
+        const float ux = (float)u.x, uy = (float)u.y, uz = (float)u.z;
+        const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
+        const float thr_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax);
+        int spill[TOOL_SPILL];
+        int sp = 0;
+        int32_t node = root;
+        int32_t budget = 2 * a.n_nodes_alloc + 64;
+        bool bad = false;
+        if (is_leaf(root)) {
+            const int32_t f = leaf_first(root), n = leaf_count(root);
+            if (f + n > n_tris_alloc) bad = true;
+            for (int32_t k = 0; k < n && !bad && !blocked; ++k) {
+                const float4 *t = a.tris + 3 * (int64_t)(f + k);
+                const float4 A4 = t[0], B4 = t[1], C4 = t[2];
+                if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
+                if (STATS) ++n_tests;
+                blocked = tool_blocked(c, u, A4, B4, C4, thr);
+            }
+            node = -1;
+        }
+        while (node >= 0 && !blocked && !bad) {
+            if ((uint32_t)node >= (uint32_t)a.n_nodes_alloc || --budget < 0) {
+                bad = true;
+                break;
+            }
+            const Node nd = a.nodes[node];
+            if (STATS) ++n_nodes;
+            float t0, t1;
+            const bool h0 = grown_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, pad, cx, cy, cz, ix, iy, iz, t0);
+            const bool h1 = grown_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, pad, cx, cy, cz, ix, iy, iz, t1);
+            const int32_t ch[2] = {nd.d.x, nd.d.y};
+            const bool hit[2] = {h0, h1};
+            for (int k = 0; k < 2 && !blocked && !bad; ++k) {
+                if (!hit[k] || !is_leaf(ch[k])) continue;
+                const int32_t f = leaf_first(ch[k]), n = leaf_count(ch[k]);
+                if (f + n > n_tris_alloc) {
+                    bad = true;
+                    break;
+                }
+                for (int32_t q = 0; q < n && !blocked; ++q) {
+                    const float4 *t = a.tris + 3 * (int64_t)(f + q);
+                    const float4 A4 = t[0], B4 = t[1], C4 = t[2];
+                    if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
+                    if (STATS) ++n_tests;
+                    blocked = tool_blocked(c, u, A4, B4, C4, thr);
+                }
+            }
+            if (blocked || bad) break;
+            const bool g0 = h0 && !is_leaf(ch[0]), g1 = h1 && !is_leaf(ch[1]);
+            if (g0 && g1) {
+                const int32_t nearc = t0 <= t1 ? ch[0] : ch[1], farc = t0 <= t1 ? ch[1] : ch[0];
+                if (sp < TOOL_STACK) stk[sp * TOOL_THREADS + lane] = farc;
+                else if (sp < TOOL_STACK + TOOL_SPILL) spill[sp - TOOL_STACK] = farc;
+                else {
+                    bad = true;
+                    break;
+                }
+                ++sp;
+                node = nearc;
+            } else if (g0) {
+                node = ch[0];
+            } else if (g1) {
+                node = ch[1];
+            } else if (sp == 0) {
+                node = -1;
+            } else {
+                --sp;
+                node = sp < TOOL_STACK ? stk[sp * TOOL_THREADS + lane] : spill[sp - TOOL_STACK];
+            }
+        }
+        if (bad) {
+            atomicOr(a.err, ERR_STACK);
+            return;
+        }
+    }
+    if (!blocked) atomicOr(&a.bits[s * a.W + (idx >> 5)], 1u << (idx & 31));
+    if (STATS) {
+        atomicAdd(a.work, (unsigned long long)n_nodes);
+        atomicAdd(a.work + 1, (unsigned long long)n_tests);
+    }
+}
+
+__global__ void k_tool_zero(uint32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void k_tool_popcount(const uint32_t *bits, int64_t n, int32_t W, uint32_t *counts) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    uint32_t c = 0;
+    for (int32_t w = 0; w < W; ++w) c += __popc(bits[s * W + w]);
+    counts[s] = c;
+}
+
+}  // namespace
+}  // namespace hra
+
+using namespace hra;
+
+static hra_status tool_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                               hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint32_t *d_counts,
+                               unsigned long long *work, hipStream_t s) {
+    if (!ctx || !bvh || !samples) return HRA_ERR_INVALID_ARG;
+    if (part < 0 || part >= bvh->n_parts) return ctx->fail(HRA_ERR_INVALID_ARG, "part index out of range");
+    if (samples->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
+    if (!(tool_radius > 0.0) || !std::isfinite(tool_radius))
+        return ctx->fail(HRA_ERR_INVALID_ARG, "tool radius must be positive and finite");
+    const float4 *table = nullptr;
+    hra_status st = dir_table(ctx, dirs, &table);
+    if (st != HRA_OK) return st;
+    if (samples->n == 0) return HRA_OK;
+    if (!d_bits || !samples->point || !samples->normal)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "bits, points and normals must be non-null");
+    HRA_HIP(hipSetDevice(ctx->device));
+    ToolArgs a;
+    a.nodes = bvh->nodes;
+    a.tris = bvh->tris;
+    a.meta = bvh->parts + part;
+    a.point = samples->point;
+    a.normal = samples->normal;
+    a.kind = dirs.kind == HRA_DIRS_AXES6 ? 1 : 0;
+    a.dirs = a.kind == 1 ? table : table + dirs.n;
+    a.n_dirs = dirs.n;
+    a.W = (dirs.n + 31) / 32;
+    a.n_nodes_alloc = (int32_t)(bvh->n_tris > 1 ? bvh->n_tris - 1 : 1);
+    a.n_samples = samples->n;
+    a.n_rays = samples->n * (int64_t)dirs.n;
+    a.radius = tool_radius;
+    a.bits = d_bits;
+    a.err = ctx->d_err;
+    a.work = work;
+    const int64_t words = samples->n * (int64_t)a.W;
+    const int64_t blocks = (a.n_rays + TOOL_THREADS - 1) / TOOL_THREADS;
+    if (blocks >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call");
+    k_tool_zero<<<(unsigned)((words + 255) / 256), 256, 0, s>>>(d_bits, words);
+    if (work) k_cast_tool<true><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
+    else k_cast_tool<false><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
+    if (d_counts) k_tool_popcount<<<(unsigned)((samples->n + 255) / 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);
+    HRA_HIP(hipGetLastError());
+    return HRA_OK;
+}
+
+extern "C" hra_status hra_cast_tool(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                                    hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint32_t *d_counts,
+                                    void *stream) {
+    return tool_common(ctx, bvh, part, samples, dirs, tool_radius, d_bits, d_counts, nullptr, (hipStream_t)stream);
+}
+
+extern "C" hra_status hra_cast_tool_work(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                                         hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint64_t *node_visits,
+                                         uint64_t *tri_tests, void *stream) {
+    if (!ctx) return HRA_ERR_INVALID_ARG;
+    if (!node_visits || !tri_tests) return ctx->fail(HRA_ERR_INVALID_ARG, "counter outputs must be non-null");
+    *node_visits = *tri_tests = 0;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *w = nullptr;
+    HRA_HIP(hipMallocAsync((void **)&w, 2 * sizeof(unsigned long long), s));
+    k_tool_zero<<<1, 256, 0, s>>>(reinterpret_cast<uint32_t *>(w), 4);
+    hra_status st = tool_common(ctx, bvh, part, samples, dirs, tool_radius, d_bits, nullptr, w, s);
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipSuccess;
+    if (st == HRA_OK) e = hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, s);
+    const hipError_t e2 = hipFreeAsync(w, s);
+    const hipError_t e3 = hipStreamSynchronize(s);
+    if (st != HRA_OK) return st;
+    if (e != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return ctx->fail(HRA_ERR_DEVICE, "tool work counters", hipGetErrorString(e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3)));
+    *node_visits = h[0];
+    *tri_tests = h[1];
+    return check_error_word(ctx, s);
+}

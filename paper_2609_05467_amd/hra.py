@@ -200,6 +200,9 @@ def lib():
             "hra_stl_copy": ([P, P, P], C.c_int),
             "hra_stl_free": ([P], None),
             "hra_stl_error": ([], C.c_char_p),
+            "hra_cast_tool": ([P, P, i32, C.POINTER(Samples), Dirs, f64, P, P, P], C.c_int),
+            "hra_cast_tool_work": ([P, P, i32, C.POINTER(Samples), Dirs, f64, P, C.POINTER(u64), C.POINTER(u64),
+                                    P], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -218,7 +221,7 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_plan_destroy", "hra_autotune", "hra_now_ns", "hra_server_create", "hra_server_submit",
            "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy",
            "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply", "hra_stl_read", "hra_stl_copy",
-           "hra_stl_free", "hra_stl_error"]
+           "hra_stl_free", "hra_stl_error", "hra_cast_tool", "hra_cast_tool_work"]
 FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
@@ -397,6 +400,28 @@ class Context:
         self._check(lib().hra_cast_part(self.ptr, bvh.ptr, part, C.byref(st), Dirs(kind, n_dirs), _ptr(bits),
                                         _ptr(cnt), _stream(stream)))
         return bits, cnt
+
+    def cast_tool(self, bvh, samples, n_dirs, radius, kind=DIRS_HEMI, counts=True, stream=None, bits=None, part=0):
+        """Tool-aware cast (hra_cast_tool): ball-end tool of `radius` mm."""
+        n = samples["origin"].shape[0]
+        W = (n_dirs + 31) // 32
+        if bits is None:
+            bits = torch.empty((n, W), dtype=torch.int32, device=self.device)
+        cnt = torch.empty((n,), dtype=torch.int32, device=self.device) if counts else None
+        st = self._samples_struct(samples)
+        self._check(lib().hra_cast_tool(self.ptr, bvh.ptr, part, C.byref(st), Dirs(kind, n_dirs), float(radius),
+                                        _ptr(bits), _ptr(cnt), _stream(stream)))
+        return bits, cnt
+
+    def cast_tool_work(self, bvh, samples, n_dirs, radius, kind=DIRS_HEMI, stream=None, part=0):
+        """Instrumented tool cast: (bits, node visits, triangle-distance tests)."""
+        n = samples["origin"].shape[0]
+        bits = torch.empty((n, (n_dirs + 31) // 32), dtype=torch.int32, device=self.device)
+        nv, nt = C.c_uint64(), C.c_uint64()
+        st = self._samples_struct(samples)
+        self._check(lib().hra_cast_tool_work(self.ptr, bvh.ptr, part, C.byref(st), Dirs(kind, n_dirs), float(radius),
+                                             _ptr(bits), C.byref(nv), C.byref(nt), _stream(stream)))
+        return bits, nv.value, nt.value
 
     def cast_work(self, bvh, samples, n_dirs, kind=DIRS_HEMI, stream=None):
         """Instrumented cast: (bits, node fetches, triangle tests) over all rays."""

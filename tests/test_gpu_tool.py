@@ -1,0 +1,144 @@
+"""GPU parity of the tool-aware cast (hra_cast_tool) against the CPU oracle
+(oracle.cast_tool): bits equal on every direction the oracle decides (an
+ambiguous direction has a triangle within 1e-9 x diagonal of the clearance
+threshold), counts equal to the bits' popcounts, the blind-hole clearance
+angle, monotonicity in the radius, and the errors."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import parts as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2609_05467_amd import hra
+    assert torch.cuda.is_available()
+    c = hra.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _np(s):
+    return {k: v.cpu().numpy() for k, v in s.items()}
+
+
+def _parity(ctx, orc, m, b, s, N, radius, kind=0):
+    from paper_2609_05467_amd import hra
+    sn = _np(s)
+    dirs = orc.fibonacci_dirs(N) if kind == 0 else orc.axes6()
+    bits, cnt = ctx.cast_tool(b, s, N, radius, kind=hra.DIRS_HEMI if kind == 0 else hra.DIRS_AXES6)
+    got = _u32(bits)
+    ob, oa = orc.cast_tool(m.verts, m.tris, sn, dirs, radius, kind=kind)
+    bad = (got ^ ob) & ~oa
+    assert not bad.any(), f"{int(np.unpackbits(bad.view(np.uint8)).sum())} decided directions differ"
+    popc = np.array([int(np.unpackbits(r.view(np.uint8)).sum()) for r in got])
+    assert np.array_equal(_u32(cnt), popc.astype(np.uint32))
+    W = (N + 31) // 32
+    if N % 32:
+        assert np.all(got[:, W - 1] >> (N % 32) == 0)
+    return got, ob, oa
+
+
+@pytest.mark.parametrize("radius", [0.5, 2.0, 5.0])
+def test_tool_config1(ctx, orc, radius):
+    m = P.config1_part()
+    b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.sample_surface(b, 300, 4)
+    _say("tool config1", radius)
+    got, ob, oa = _parity(ctx, orc, m, b, s, 150, radius)
+    assert int(np.unpackbits(oa.view(np.uint8)).sum()) <= 1e-3 * 300 * 150
+    _parity(ctx, orc, m, b, s, 6, radius, kind=1)
+    # the instrumented build gives the same bits
+    wb, nv, nt = ctx.cast_tool_work(b, s, 150, radius)
+    assert np.array_equal(_u32(wb), got) and nv > 0 and nt > 0
+
+
+@pytest.mark.parametrize("name,N", [("pockets-small", 64), ("multiaxis-small", 100), ("l_bracket", 33),
+                                    ("icosphere", 256)])
+def test_tool_parts(ctx, orc, name, N):
+    m = {"pockets-small": lambda: P._procedural(22, 1.0, "pockets", (120.0, 90.0, 60.0), (6, 10)),
+         "multiaxis-small": lambda: P._procedural(21, 1.0, "multiaxis", (100.0, 80.0, 50.0), (4, 8)),
+         "l_bracket": P.l_bracket, "icosphere": lambda: P.icosphere(subdiv=3)}[name]()
+    b = ctx.build_bvh(m.verts, m.tris, leaf_size=4)
+    s = ctx.sample_surface(b, 120, 7)
+    _say("tool", name, m.n_tris, N)
+    _parity(ctx, orc, m, b, s, N, 1.5)
+
+
+def test_tool_blind_hole_clearance(ctx, orc):
+    import torch
+    R, D, k, rt = 4.0, 12.0, 160, 2.0
+    m = P.blind_hole_part(R, D, k)
+    b = ctx.build_bvh(m.verts, m.tris)
+    cu, cv, top = m.meta["centre"]
+    dev = ctx.device
+    s = {"point": torch.tensor([[cu, cv, top - D]], dtype=torch.float32, device=dev),
+         "normal": torch.tensor([[0, 0, 1.0]], device=dev),
+         "origin": torch.tensor([[cu, cv, top - D]], dtype=torch.float32, device=dev),
+         "tri": torch.zeros(1, dtype=torch.int32, device=dev)}
+    N = 2048
+    got, ob, oa = _parity(ctx, orc, m, b, s, N, rt)
+    _, diag, _ = orc.mesh_info(m.verts)
+    thr = rt - 1e-4 * diag
+    dirs = orc.fibonacci_dirs(N)
+    th = np.arccos(np.clip(dirs[:, 2].astype(np.float64), -1, 1))
+    free = (got[0][np.arange(N) >> 5] >> (np.arange(N) & 31)) & 1
+    sure_free = R * math.cos(math.pi / k) * np.cos(th) - (D - rt) * np.sin(th) > thr + 1e-6
+    sure_blocked = R * np.cos(th) - (D - rt) * np.sin(th) < thr - 1e-6
+    assert np.all(free[sure_free] == 1) and np.all(free[sure_blocked] == 0)
+
+
+def test_tool_monotone_and_full_size_rows(ctx, orc):
+    m = P.workload_parts("interactive_200k")[0]
+    b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.sample_surface(b, 2000, 11)
+    _say("tool interactive", m.n_tris)
+    prev = None
+    for r in (0.5, 2.0, 6.0):
+        bits, _ = ctx.cast_tool(b, s, 150, r)
+        g = _u32(bits)
+        if prev is not None:
+            # a larger tool reaches a subset (up to decisions at the threshold)
+            extra = int(np.unpackbits((g & ~prev).view(np.uint8)).sum())
+            assert extra <= 1e-4 * g.size * 32, extra
+        prev = g
+    # sampled rows against the oracle at full size
+    sn = _np(s)
+    idx = np.arange(0, 2000, 500)
+    ob, oa = orc.cast_tool(m.verts, m.tris, {k: v[idx] for k, v in sn.items()}, orc.fibonacci_dirs(150), 6.0)
+    assert not ((prev[idx] ^ ob) & ~oa).any()
+
+
+def test_tool_errors(ctx):
+    from paper_2609_05467_amd import hra
+    m = P.box_part()
+    b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.sample_surface(b, 50, 1)
+    for r in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(hra.HraError):
+            ctx.cast_tool(b, s, 64, r)
+    # thinner than twice the tolerance (2e-4 x diagonal): reported once at the next synchronising call
+    ctx.cast_tool(b, s, 64, 1e-5)
+    with pytest.raises(hra.HraError) as e:
+        b.info()
+    assert e.value.status == -1
+    b.info()
+    # no samples: nothing to do
+    bits, _ = ctx.cast_tool(b, ctx.alloc_samples(0), 64, 1.0)
+    assert bits.shape == (0, 2)
