@@ -526,7 +526,7 @@ def batch_compare(args, meshes, counts, steps, work=False):
         log("[bench] autotune sweep (18 points)")
         tune = ctx.autotune(reqs, N, reps=1)
         log(f"[bench] best {tune['best']}")
-    rpw, stack, leaf, trav = ctx.cast_config()
+    rpw, stack, leaf, trav, _ = ctx.cast_config()
 
     # plain: one part after another
     W = (N + 31) // 32
