@@ -99,10 +99,14 @@ def test_server_mix_matches_single_part_path(ctx, pool, mode):
         assert st["batches"] < len(reqs)          # requests shared launches
 
 
-def test_server_results_alone_equal_results_in_mix(ctx, pool):
+@pytest.mark.parametrize("n_dirs", [N_DIRS, 150])
+def test_server_results_alone_equal_results_in_mix(ctx, pool, n_dirs):
+    """Also at 150 directions, where the hemisphere cast takes five samples
+    per workgroup and each request's last group is partly filled."""
     from paper_2609_05467_amd import hra
     reqs = _mix(pool, 10, seed=2)
-    sv = hra.Server(0, n_dirs=N_DIRS, max_batch=16)
+    _say("server alone vs mix", n_dirs)
+    sv = hra.Server(0, n_dirs=n_dirs, max_batch=16)
     alone = []
     for (k, n, seed, tool) in reqs:
         alone.append(sv.wait(sv.submit(k, pool[k].verts, pool[k].tris, n, seed, tool), 60_000))
