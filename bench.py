@@ -82,12 +82,15 @@ def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
 
 
 # Tool-aware cast (hra_cast_tool): FP32 operations per node visit (two slab
-# tests against grown boxes: 28 each) and FP64 operations per triangle
-# distance test (the half-line meeting test 76, the point-triangle distance
-# 60, three edge distances 110 each, no early exit).  FP64 vector arithmetic
-# runs at one operation per lane and clock on this chip, like FP32 without
-# packing, so both count against the same peak.
-TOOL_NODE_OPS, TOOL_TRI_OPS = 56, 470
+# tests against grown boxes: 28 each), per screened triangle (the FP32
+# bounding-sphere screen every candidate takes: centroid 9, farthest-vertex
+# radius 26, distance from the axis 22) and FP64 operations per distance test (the half-line
+# meeting test 76, the point-triangle distance 60, three edge distances 110
+# each, no early exit).  FP64 vector arithmetic runs at one operation per
+# lane and clock on this chip, like FP32 without packing, so all count
+# against the same peak.  The plane screen some candidates also take is not
+# counted.
+TOOL_NODE_OPS, TOOL_SCREEN_OPS, TOOL_TRI_OPS = 56, 57, 470
 TOOL_RADIUS_MM = 3.0
 
 
@@ -105,11 +108,11 @@ def tool_extra(ctx, bvh, samples, N, reps=3):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    wb, nv, nt = ctx.cast_tool_work(bvh, samples, N, TOOL_RADIUS_MM)
+    wb, nv, nt, ns = ctx.cast_tool_work(bvh, samples, N, TOOL_RADIUS_MM)
     rays = S * N
-    ops = nv * TOOL_NODE_OPS + nt * TOOL_TRI_OPS
+    ops = nv * TOOL_NODE_OPS + ns * TOOL_SCREEN_OPS + nt * TOOL_TRI_OPS
     return {"radius_mm": TOOL_RADIUS_MM, "ms": ms, "dirs_per_s": rays / (ms * 1e-3),
-            "node_visits_per_dir": nv / rays, "distance_tests_per_dir": nt / rays,
+            "node_visits_per_dir": nv / rays, "screened_tris_per_dir": ns / rays, "distance_tests_per_dir": nt / rays,
             "instrumented_bits_identical": bool(torch.equal(wb, bits)), "free_fraction": free / rays,
             "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
                          "frac": ops / (ms * 1e-3) / 1e12 / ALU_PEAK_TOPS, "ops_per_dir": ops / rays}}

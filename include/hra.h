@@ -237,11 +237,12 @@ hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
 hra_status hra_cast_tool(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples, hra_dirs dirs,
                          double tool_radius, uint32_t *d_bits, uint32_t *d_counts, void *stream);
 /* The same tool cast (identical bits) in an instrumented build that also
- * counts, over all directions, the interior nodes visited and the
- * triangle-distance tests made.  Synchronises `stream`. */
+ * counts, over all directions, the interior nodes visited, the FP64
+ * triangle-distance tests made and the triangles that reached the FP32
+ * screens ahead of them.  Synchronises `stream`. */
 hra_status hra_cast_tool_work(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
                               hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint64_t *node_visits,
-                              uint64_t *tri_tests, void *stream);
+                              uint64_t *tri_tests, uint64_t *tri_screened, void *stream);
 
 /* The same cast as hra_cast_hemisphere (identical bits) in an instrumented
  * build of the traversal that also counts, over all rays, the interior

@@ -36,7 +36,7 @@ struct ToolArgs {
     double radius;
     uint32_t *bits;               // [n_samples][W], cleared first
     uint32_t *err;
-    unsigned long long *work;     // instrumented launch: {node visits, triangle distance tests}
+    unsigned long long *work;     // instrumented launch: {node visits, FP64 distance tests, screened triangles}
 };
 
 struct D3 {
@@ -123,7 +123,24 @@ __device__ inline bool far_from_axis(float cx, float cy, float cz, float ux, flo
     const float t = fmaxf((wx * ux + wy * uy) + wz * uz, 0.0f);
     const float px = wx - t * ux, py = wy - t * uy, pz = wz - t * uz;
     const float d = sqrtf((px * px + py * py) + pz * pz);
-    return d - sqrtf(rho2) > thr_hi;
+    if (d - sqrtf(rho2) > thr_hi) return true;
+    // Second screen, for the faces around the sample: when the axis does not
+    // approach the triangle's plane (it moves away or runs parallel), every
+    // point of the axis is at least as far from the plane as the tip centre,
+    // so a plane distance above thr_hi rules the triangle out.  Only for
+    // triangles whose smallest-angle bound |N| > 0.05 |e1||e2| holds (about 3
+    // degrees): their FP32 unit normal is good to a few 1e-6 rad, so the plane
+    // distance is good to a few 1e-6 x diagonal, inside the margin of thr_hi;
+    // a tiny approach rate (1e-6) costs at most 2e-6 x diagonal over the part.
+    const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z, e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
+    const float Nx = e1y * e2z - e1z * e2y, Ny = e1z * e2x - e1x * e2z, Nz = e1x * e2y - e1y * e2x;
+    const float nn = sqrtf((Nx * Nx + Ny * Ny) + Nz * Nz);
+    const float l1 = sqrtf((e1x * e1x + e1y * e1y) + e1z * e1z), l2 = sqrtf((e2x * e2x + e2y * e2y) + e2z * e2z);
+    if (!(nn > 0.05f * (l1 * l2))) return false;
+    const float s0 = ((cx - A.x) * Nx + (cy - A.y) * Ny) + (cz - A.z) * Nz;
+    const float s1 = (ux * Nx + uy * Ny) + uz * Nz;
+    const float away = s0 >= 0.0f ? s1 : -s1;
+    return away >= -1e-6f * nn && fabsf(s0) > thr_hi * nn;
 }
 
 // true when the triangle comes closer than thr to the tool axis
@@ -182,7 +199,7 @@ __global__ __launch_bounds__(TOOL_THREADS) void k_cast_tool(ToolArgs a) {
     const D3 u = mk(d.x / dl, d.y / dl, d.z / dl);
     const int32_t root = P.root, n_valid = P.n_valid, n_tris_alloc = P.leaf_lo + P.n_valid;
     bool blocked = false;
-    uint32_t n_nodes = 0, n_tests = 0;
+    uint32_t n_nodes = 0, n_tests = 0, n_cands = 0;
     if (n_valid > 0) {
         // FP32 box tests from the rounded tip centre; the margin covers the
         // rounding of the centre and of the grown box faces
@@ -206,6 +223,7 @@ __global__ __launch_bounds__(TOOL_THREADS) void k_cast_tool(ToolArgs a) {
             for (int32_t k = 0; k < n && !bad && !blocked; ++k) {
                 const float4 *t = a.tris + 3 * (int64_t)(f + k);
                 const float4 A4 = t[0], B4 = t[1], C4 = t[2];
+                if (STATS) ++n_cands;
                 if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
                 if (STATS) ++n_tests;
                 blocked = tool_blocked(c, u, A4, B4, C4, thr);
@@ -234,6 +252,7 @@ __global__ __launch_bounds__(TOOL_THREADS) void k_cast_tool(ToolArgs a) {
                 for (int32_t q = 0; q < n && !blocked; ++q) {
                     const float4 *t = a.tris + 3 * (int64_t)(f + q);
                     const float4 A4 = t[0], B4 = t[1], C4 = t[2];
+                    if (STATS) ++n_cands;
                     if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
                     if (STATS) ++n_tests;
                     blocked = tool_blocked(c, u, A4, B4, C4, thr);
@@ -271,6 +290,7 @@ __global__ __launch_bounds__(TOOL_THREADS) void k_cast_tool(ToolArgs a) {
     if (STATS) {
         atomicAdd(a.work, (unsigned long long)n_nodes);
         atomicAdd(a.work + 1, (unsigned long long)n_tests);
+        atomicAdd(a.work + 2, (unsigned long long)n_cands);
     }
 }
 
@@ -343,16 +363,17 @@ extern "C" hra_status hra_cast_tool(hra_ctx *ctx, const hra_bvh *bvh, int32_t pa
 
 extern "C" hra_status hra_cast_tool_work(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
                                          hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint64_t *node_visits,
-                                         uint64_t *tri_tests, void *stream) {
+                                         uint64_t *tri_tests, uint64_t *tri_screened, void *stream) {
     if (!ctx) return HRA_ERR_INVALID_ARG;
-    if (!node_visits || !tri_tests) return ctx->fail(HRA_ERR_INVALID_ARG, "counter outputs must be non-null");
-    *node_visits = *tri_tests = 0;
+    if (!node_visits || !tri_tests || !tri_screened)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "counter outputs must be non-null");
+    *node_visits = *tri_tests = *tri_screened = 0;
     hipStream_t s = (hipStream_t)stream;
     unsigned long long *w = nullptr;
-    HRA_HIP(hipMallocAsync((void **)&w, 2 * sizeof(unsigned long long), s));
-    k_tool_zero<<<1, 256, 0, s>>>(reinterpret_cast<uint32_t *>(w), 4);
+    HRA_HIP(hipMallocAsync((void **)&w, 3 * sizeof(unsigned long long), s));
+    k_tool_zero<<<1, 256, 0, s>>>(reinterpret_cast<uint32_t *>(w), 6);
     hra_status st = tool_common(ctx, bvh, part, samples, dirs, tool_radius, d_bits, nullptr, w, s);
-    unsigned long long h[2] = {0, 0};
+    unsigned long long h[3] = {0, 0, 0};
     hipError_t e = hipSuccess;
     if (st == HRA_OK) e = hipMemcpyAsync(h, w, sizeof(h), hipMemcpyDeviceToHost, s);
     const hipError_t e2 = hipFreeAsync(w, s);
@@ -362,5 +383,6 @@ extern "C" hra_status hra_cast_tool_work(hra_ctx *ctx, const hra_bvh *bvh, int32
         return ctx->fail(HRA_ERR_DEVICE, "tool work counters", hipGetErrorString(e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3)));
     *node_visits = h[0];
     *tri_tests = h[1];
+    *tri_screened = h[2];
     return check_error_word(ctx, s);
 }

@@ -202,7 +202,7 @@ def lib():
             "hra_stl_error": ([], C.c_char_p),
             "hra_cast_tool": ([P, P, i32, C.POINTER(Samples), Dirs, f64, P, P, P], C.c_int),
             "hra_cast_tool_work": ([P, P, i32, C.POINTER(Samples), Dirs, f64, P, C.POINTER(u64), C.POINTER(u64),
-                                    P], C.c_int),
+                                    C.POINTER(u64), P], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -414,14 +414,14 @@ class Context:
         return bits, cnt
 
     def cast_tool_work(self, bvh, samples, n_dirs, radius, kind=DIRS_HEMI, stream=None, part=0):
-        """Instrumented tool cast: (bits, node visits, triangle-distance tests)."""
+        """Instrumented tool cast: (bits, node visits, FP64 distance tests, screened triangles)."""
         n = samples["origin"].shape[0]
         bits = torch.empty((n, (n_dirs + 31) // 32), dtype=torch.int32, device=self.device)
-        nv, nt = C.c_uint64(), C.c_uint64()
+        nv, nt, ns = C.c_uint64(), C.c_uint64(), C.c_uint64()
         st = self._samples_struct(samples)
         self._check(lib().hra_cast_tool_work(self.ptr, bvh.ptr, part, C.byref(st), Dirs(kind, n_dirs), float(radius),
-                                             _ptr(bits), C.byref(nv), C.byref(nt), _stream(stream)))
-        return bits, nv.value, nt.value
+                                             _ptr(bits), C.byref(nv), C.byref(nt), C.byref(ns), _stream(stream)))
+        return bits, nv.value, nt.value, ns.value
 
     def cast_work(self, bvh, samples, n_dirs, kind=DIRS_HEMI, stream=None):
         """Instrumented cast: (bits, node fetches, triangle tests) over all rays."""
