@@ -526,7 +526,7 @@ def batch_compare(args, meshes, counts, steps, work=False):
     rays = S * N
     tune = None
     if args.autotune:
-        log("[bench] autotune sweep (18 points)")
+        log("[bench] autotune sweep (27 points)")
         tune = ctx.autotune(reqs, N, reps=1)
         log(f"[bench] best {tune['best']}")
     rpw, stack, leaf, trav, _ = ctx.cast_config()

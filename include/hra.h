@@ -515,9 +515,9 @@ typedef struct {
     hra_tune_point points[27];   /* the first n_points are used */
 } hra_tune_report;
 
-/* Autotuner for a batch: sweeps rays per wave {64, 128, 256} x traversal
- * {STEP, LEAF_LOOP} x leaf size {2, 4, 8} (18 points; the stack depth is
- * opts->stack_depth, 0 = the context's), times `reps` runs of a plan for
+/* Autotuner for a batch: sweeps rays per wave {64, 128, 256} x LDS stack
+ * depth {16, 24, 32} x leaf size {2, 4, 8} (27 points; the traversal loop
+ * is opts->traversal, 0 = the context's), times `reps` runs of a plan for
  * each point after one warm-up run, checks that every point gives the same
  * results, and stores the fastest point in the context's cast
  * configuration (hra_get_cast_config).  opts: as for hra_plan_create (its

@@ -438,20 +438,22 @@ extern "C" hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, 
                                    const hra_batch_opts *opts, int32_t reps, hra_tune_report *out, void *stream) {
     if (!ctx || !parts || !opts || !out) return HRA_ERR_INVALID_ARG;
     if (reps < 1 || reps > 100) return ctx->fail(HRA_ERR_INVALID_ARG, "reps must be in 1..100");
-    static const int RPW[3] = {64, 128, 256}, TRAV[2] = {HRA_TRAVERSAL_STEP, HRA_TRAVERSAL_LEAF_LOOP}, LEAF[3] = {2, 4, 8};
-    const int stack = opts->stack_depth ? opts->stack_depth : ctx->cast_stack;
+    static const int RPW[3] = {64, 128, 256}, STACK[3] = {16, 24, 32}, LEAF[3] = {2, 4, 8};
+    const int trav = opts->traversal ? opts->traversal : ctx->cast_traversal;
+    if (trav != HRA_TRAVERSAL_STEP && trav != HRA_TRAVERSAL_LEAF_LOOP)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "traversal must be 0, HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP");
     std::vector<hra_part_result> ref(n_parts > 0 ? n_parts : 1), got(n_parts > 0 ? n_parts : 1);
     out->n_points = 0;
     out->best = -1;
     float best_ms = 0.0f;
     for (int li = 0; li < 3; ++li)
         for (int ri = 0; ri < 3; ++ri)
-            for (int ti = 0; ti < 2; ++ti) {
+            for (int si = 0; si < 3; ++si) {
                 hra_batch_opts o = *opts;
                 o.leaf_size = LEAF[li];
                 o.rays_per_wave = RPW[ri];
-                o.stack_depth = stack;
-                o.traversal = TRAV[ti];
+                o.stack_depth = STACK[si];
+                o.traversal = trav;
                 hra_plan *P = nullptr;
                 hra_status st = hra_plan_create(ctx, parts, n_parts, &o, &P);
                 if (st != HRA_OK) return st;
@@ -471,9 +473,9 @@ extern "C" hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, 
                     return ctx->fail(HRA_ERR_DEVICE, "autotuner: results differ between launch shapes");
                 hra_tune_point &pt = out->points[out->n_points];
                 pt.rays_per_wave = RPW[ri];
-                pt.stack_depth = stack;
+                pt.stack_depth = STACK[si];
                 pt.leaf_size = LEAF[li];
-                pt.traversal = TRAV[ti];
+                pt.traversal = trav;
                 pt.ms = (float)(sum / reps);
                 if (out->best < 0 || pt.ms < best_ms) {
                     out->best = out->n_points;

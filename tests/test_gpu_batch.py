@@ -222,8 +222,10 @@ def test_autotune_picks_a_point_and_keeps_results(ctx, meshes):
     old = ctx.cast_config()
     _say("autotune")
     rep = ctx.autotune(reqs, 256, reps=1)
-    assert len(rep["points"]) == 18
-    assert {p["traversal"] for p in rep["points"]} == {hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP}
+    assert len(rep["points"]) == 27
+    assert {(p["rays_per_wave"], p["stack_depth"], p["leaf_size"]) for p in rep["points"]} == {
+        (r, st, lf) for r in (64, 128, 256) for st in (16, 24, 32) for lf in (2, 4, 8)}
+    assert {p["traversal"] for p in rep["points"]} == {old[3]}
     best = rep["best"]
     assert best["ms"] == min(p["ms"] for p in rep["points"])
     assert ctx.cast_config()[:4] == (best["rays_per_wave"], best["stack_depth"], best["leaf_size"], best["traversal"])
