@@ -89,16 +89,21 @@ __device__ inline bool tri_hit(float ox, float oy, float oz, float dx, float dy,
     const float bw = 4.0f * bd;
     const float Tn = fmaf(e2z, qz, fmaf(e2y, qy, e2x * qx));
     const float bt = (6.0f * TRI_K) * MM * M;
-    const int s1 = U > bd ? -1 : (U < -bd ? 1 : 2);
-    const int s2 = V > bd ? -1 : (V < -bd ? 1 : 2);
-    const int s0 = W > bw ? -1 : (W < -bw ? 1 : 2);
-    const int hs = Tn > bt ? -1 : (Tn < -bt ? 1 : 2);
+    // certain signs as lane masks: P = certainly positive (sign code -1),
+    // N = certainly negative (code 1), neither = uncertain (code 2, NaN too)
+    const bool uP = U > bd, uN = U < -bd, vP = V > bd, vN = V < -bd;
+    const bool wP = W > bw, wN = W < -bw, tP = Tn > bt, tN = Tn < -bt;
     // two certain, opposite edge signs: the line misses the triangle
-    const bool miss = (s0 == 1 || s1 == 1 || s2 == 1) && (s0 == -1 || s1 == -1 || s2 == -1);
-    const bool unsure = s0 == 2 || s1 == 2 || s2 == 2 || hs == 2;
-    // no miss and nothing uncertain: the three edges share the certain sign s0
-    bool hit = !miss && !unsure && hs == s0;
-    if (!miss && unsure) hit = tri_hit_fp64(ox, oy, oz, dx, dy, dz, A, B, C, s0, s1, s2, hs);
+    const bool miss = (uN || vN || wN) && (uP || vP || wP);
+    const bool sure = (uP || uN) && (vP || vN) && (wP || wN) && (tP || tN);
+    // no miss and nothing uncertain: the three edges share W's certain sign,
+    // and the plane side must equal it
+    bool hit = !miss && sure && tP == wP;
+    if (!miss && !sure) {
+        const int s1 = uP ? -1 : (uN ? 1 : 2), s2 = vP ? -1 : (vN ? 1 : 2);
+        const int s0 = wP ? -1 : (wN ? 1 : 2), hs = tP ? -1 : (tN ? 1 : 2);
+        hit = tri_hit_fp64(ox, oy, oz, dx, dy, dz, A, B, C, s0, s1, s2, hs);
+    }
     return hit;
 }
 
@@ -183,7 +188,15 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
     int sp = 0;
     int32_t node = root;      // next interior node to visit, or -1: take the stack
     int32_t ti = 0, tn = 0;   // the leaf under test: triangles [ti, ti + tn)
-    int32_t budget = 2 * n_nodes_alloc + 64;
+    // A valid hierarchy takes at most one iteration per node visit, stack
+    // pop and triangle test, plus the last: fewer than 2 x nodes + triangles
+    // + 1.  The count is the wave's (every lane still in the loop has taken
+    // each iteration), so it lives in a scalar register; reaching the cap
+    // means a cycle or a corrupt index.
+    const int64_t cap = 2 * (int64_t)n_nodes_alloc + (int64_t)n_tris_alloc + 64;
+    const uint32_t iter_cap = cap < 0xffffffffll ? (uint32_t)cap : 0xffffffffu;
+    uint32_t iter = 0;
+    const uint32_t last_node = (uint32_t)n_nodes_alloc - 1u, last_tri = (uint32_t)max(n_tris_alloc, 1) - 1u;
     bool hit = false, done = false, bad = false;
     // One unit of work per iteration: a triangle test while the lane holds a
     // leaf, otherwise a stack pop and/or a node visit.  Lanes at a leaf and
@@ -201,7 +214,10 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
         // otherwise thread "tn still > 0" back into an inner triangle loop
         asm volatile("" : "+v"(tn));
         if (tn > 0) {
-            const float4 *t = tris + 3 * (int64_t)ti;
+            // a leaf run outside the triangle array: a clamped (in-range)
+            // read, whose verdict the exit below discards
+            bad = (uint32_t)ti > last_tri;
+            const float4 *t = tris + 3 * (uint64_t)min((uint32_t)ti, last_tri);
             if (STATS) ++wc.tris;
             hit = tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2));
             ++ti;
@@ -227,8 +243,8 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
                 }
             }
             if (visit) {
-                bad = (uint32_t)node >= (uint32_t)n_nodes_alloc || --budget < 0;
-                const Node *nd = nodes + (bad ? 0 : node);
+                bad = (uint32_t)node > last_node;
+                const Node *nd = nodes + min((uint32_t)node, last_node);
                 if (STATS) ++wc.nodes;
                 const float4 A = gload_f4(&nd->a), B = gload_f4(&nd->b), C = gload_f4(&nd->c);
                 const int4 D = gload_i4(&nd->d);
@@ -256,10 +272,10 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
                     ++sp;
                 }
             }
-            // a leaf run outside the triangle array (checked before its first
-            // triangle is read: the exit below comes first)
-            bad = bad || (tn > 0 && ti + tn > n_tris_alloc);
         }
+        ++iter;
+        const bool over = iter > iter_cap;
+        bad = bad || over;
         if (hit || done || bad) break;
     }
     if (bad) atomicOr(err, ERR_STACK);
