@@ -63,6 +63,11 @@ TRAVERSAL = {"step": 1, "leaf_loop": 2}     # hra.h HRA_TRAVERSAL_*
 # on all of them)
 DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "multiaxis_1m": "step",
                      "batch64": "step", "serve": "step", "paper_shape": "step"}
+# (rays per wave, leaf size) measured faster per workload; (64, 4) elsewhere.
+# On the 1M-triangle part 256 rays per wave and leaves of up to 8 triangles
+# cast in 29.4 ms against 32.7; on the interactive part the two are within
+# run-to-run noise (11.80-11.88 against 11.84-11.86 ms).
+DEFAULT_SHAPE = {"multiaxis_1m": (256, 8)}
 
 
 def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
@@ -225,10 +230,10 @@ def main():
     ap.add_argument("--workload", default="interactive_200k", choices=sorted(WORKLOADS))
     ap.add_argument("--tool-length", type=float, default=50.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--rays-per-wave", type=int, default=64)
+    ap.add_argument("--rays-per-wave", type=int, default=None, help="default: the workload's measured best")
     ap.add_argument("--stack", type=int, default=None,
                     help="LDS stack entries per lane (default 16: nine workgroups fit in LDS)")
-    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--leaf", type=int, default=None, help="default: the workload's measured best")
     ap.add_argument("--traversal", choices=("step", "leaf_loop"), default=None,
                     help="traversal loop of the casts (same results; see hra.h); default: the one measured "
                          "faster for the workload's part")
@@ -250,6 +255,11 @@ def main():
         args.traversal = DEFAULT_TRAVERSAL[args.workload]
     if args.stack is None:
         args.stack = 16
+    rpw0, leaf0 = DEFAULT_SHAPE.get(args.workload, (64, 4))
+    if args.rays_per_wave is None:
+        args.rays_per_wave = rpw0
+    if args.leaf is None:
+        args.leaf = leaf0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by part and "
               "by samples with no exchange, see the design notes)", file=sys.stderr)
