@@ -177,7 +177,10 @@ hra_status hra_dirs_table(hra_ctx *ctx, hra_dirs dirs, float *host_out);
  * l is rotated onto the sample normal with the orthonormal basis of Duff et
  * al. (2017); for AXES6 the world direction is used and a direction with
  * normal . D < 0 is not cast (bit 0).  Triangles block from both sides; rays
- * extend over t in (0, inf).
+ * extend over t in (0, inf).  Only the samples' origin and normal are read
+ * (not their triangle index), so samples drawn on one mesh may be cast
+ * against a hierarchy of that mesh together with other geometry (fixtures,
+ * clamps, a machine envelope): the obstacles then block rays as well.
  * d_bits: uint32 [samples->n][W] (written in full); d_counts: uint32
  * [samples->n] popcount of each row, or NULL. */
 hra_status hra_cast_hemisphere(hra_ctx *ctx, const hra_bvh *bvh, const hra_samples *samples, hra_dirs dirs,
@@ -230,7 +233,9 @@ hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
  * bounding-box diagonal.  Directions as in hra_cast_part: the Fibonacci
  * hemisphere rotated onto each normal, or HRA_DIRS_AXES6 (an axis with
  * n . D < 0 is not cast: bit 0).  Uses samples->point and ->normal; the
- * origin is not used.  d_bits: uint32 [n][ceil(N/32)], d_counts: uint32
+ * origin and triangle index are not used (obstacles as for
+ * hra_cast_hemisphere: cast against a hierarchy that includes them; tol
+ * then follows that hierarchy's diagonal).  d_bits: uint32 [n][ceil(N/32)], d_counts: uint32
  * [n] or NULL.  A radius of at most 2 tol sets the error word
  * (HRA_ERR_INVALID_ARG at the next synchronising call); a non-positive or
  * non-finite one fails at once.  Enqueues on `stream`. */
