@@ -599,13 +599,60 @@ double orc_tool_distance(const double *v9, const double *c, const double *u) {
     return best;
 }
 
+/* distance between the segments [p, q] and [a, b]: an end point of one to
+ * the other segment, or their common perpendicular when its feet fall inside
+ * both */
+static double segment_segment(const double *p, const double *q, const double *a, const double *b) {
+    double best = seg_point(p, a, b), d;
+    if ((d = seg_point(q, a, b)) < best) best = d;
+    if ((d = seg_point(a, p, q)) < best) best = d;
+    if ((d = seg_point(b, p, q)) < best) best = d;
+    double f[3], e[3], w[3];
+    for (int k = 0; k < 3; ++k) { f[k] = q[k] - p[k]; e[k] = b[k] - a[k]; w[k] = p[k] - a[k]; }
+    const double ff = dot3(f, f), fe = dot3(f, e), ee = dot3(e, e), fw = dot3(f, w), ew = dot3(e, w);
+    const double den = ff * ee - fe * fe;
+    if (den > 1e-300 * (ff * ee > 1.0 ? ff * ee : 1.0)) {
+        const double s = (fe * ew - ee * fw) / den, t = (ff * ew - fe * fw) / den;
+        if (s > 0.0 && s < 1.0 && t > 0.0 && t < 1.0) {
+            double x[3];
+            for (int k = 0; k < 3; ++k) x[k] = (p[k] + s * f[k]) - (a[k] + t * e[k]);
+            d = sqrt(dot3(x, x));
+            if (d < best) best = d;
+        }
+    }
+    return best;
+}
+
+/* Distances of a ball-end tool with a holder (Section 3.3 names tool reach;
+ * the holder envelope is this library's extension): the cutter is the
+ * segment c + t u, 0 <= t <= len; the holder the half-line from h = c + len u
+ * along u.  out[0] = distance from the cutter segment to the triangle (0 when
+ * the segment crosses it: the half-lines from c along u and from h along -u
+ * both meet it), out[1] = distance from the holder half-line. */
+void orc_tool_holder_distances(const double *v9, const double *c, const double *u, double len, double *out) {
+    double v[3][3], h[3], mu[3];
+    memcpy(v, v9, sizeof(v));
+    for (int k = 0; k < 3; ++k) { h[k] = c[k] + len * u[k]; mu[k] = -u[k]; }
+    double dc = 0.0;
+    if (!(ray_meets(c, u, v) && ray_meets(h, mu, v))) {
+        dc = tri_point(c, v);
+        double d = tri_point(h, v);
+        if (d < dc) dc = d;
+        for (int k = 0; k < 3; ++k)
+            if ((d = segment_segment(c, h, v[k], v[(k + 1) % 3])) < dc) dc = d;
+    }
+    out[0] = dc;
+    out[1] = orc_tool_distance(v9, h, u);
+}
+
 /* bits: 1 = free; amb: 1 = some triangle within +-band of thr and none below
  * thr - band (excluded from comparisons).  kind as in orc_cast. */
-int orc_cast_tool(const float *V, const int32_t *T, int64_t nt, const float *Pt, const float *Nrm, int64_t s0,
-                  int64_t s1, const float *dirs, int32_t N, int32_t kind, double r, double tol, double band,
-                  uint32_t *bits, uint32_t *amb, int32_t nthreads) {
+int orc_cast_tool_holder(const float *V, const int32_t *T, int64_t nt, const float *Pt, const float *Nrm,
+                         int64_t s0, int64_t s1, const float *dirs, int32_t N, int32_t kind, double r, double len,
+                         double R, double tol, double band, uint32_t *bits, uint32_t *amb, int32_t nthreads) {
     const int32_t W = (N + 31) / 32;
-    const double thr = r - tol;
+    const double thr = r - tol, thr_h = R - tol;
+    const int holder = len > 0.0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -630,9 +677,16 @@ int orc_cast_tool(const float *V, const int32_t *T, int64_t nt, const float *Pt,
             for (int64_t f = 0; f < nt && !blocked; ++f) {
                 double v[3][3];
                 tri_verts(V, T, f, v);
-                double dist = orc_tool_distance(&v[0][0], c, u);
-                if (dist < thr - band) blocked = 1;
-                else if (dist <= thr + band) near = 1;
+                if (!holder) {
+                    double dist = orc_tool_distance(&v[0][0], c, u);
+                    if (dist < thr - band) blocked = 1;
+                    else if (dist <= thr + band) near = 1;
+                } else {
+                    double dd2[2];
+                    orc_tool_holder_distances(&v[0][0], c, u, len, dd2);
+                    if (dd2[0] < thr - band || dd2[1] < thr_h - band) blocked = 1;
+                    else if (dd2[0] <= thr + band || dd2[1] <= thr_h + band) near = 1;
+                }
             }
             uint32_t m = 1u << (j & 31);
             if (!blocked && !near) rb[j >> 5] |= m;
@@ -640,6 +694,12 @@ int orc_cast_tool(const float *V, const int32_t *T, int64_t nt, const float *Pt,
         }
     }
     return 0;
+}
+
+int orc_cast_tool(const float *V, const int32_t *T, int64_t nt, const float *Pt, const float *Nrm, int64_t s0,
+                  int64_t s1, const float *dirs, int32_t N, int32_t kind, double r, double tol, double band,
+                  uint32_t *bits, uint32_t *amb, int32_t nthreads) {
+    return orc_cast_tool_holder(V, T, nt, Pt, Nrm, s0, s1, dirs, N, kind, r, 0.0, r, tol, band, bits, amb, nthreads);
 }
 
 /* Decision of one (ray, triangle) pair, for tests: returns DEC_* and the

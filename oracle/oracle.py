@@ -47,6 +47,11 @@ def lib():
         L.orc_cast_tool.restype = C.c_int
         L.orc_tool_distance.argtypes = [P, P, P]
         L.orc_tool_distance.restype = C.c_double
+        d = C.c_double
+        L.orc_cast_tool_holder.argtypes = [P, P, i64, P, P, i64, i64, P, i32, i32, d, d, d, d, d, P, P, i32]
+        L.orc_cast_tool_holder.restype = C.c_int
+        L.orc_tool_holder_distances.argtypes = [P, P, P, d, P]
+        L.orc_tool_holder_distances.restype = None
         L.orc_fibonacci_dirs.argtypes = [i32, P]
         L.orc_axes6.argtypes = [P]
         L.orc_frame.argtypes = [P, P, P]
@@ -217,6 +222,35 @@ def cast_tool(verts, tris, samples, dirs, radius, kind=0, s0=0, s1=None, threads
     lib().orc_cast_tool(_p(v), _p(t), len(t), _p(Pt), _p(Nn), s0, s1, _p(d), N, kind, float(radius),
                         TOOL_TOL_FRAC * diag, TOOL_BAND_FRAC * diag, _p(bits), _p(amb), threads)
     return bits, amb
+
+
+def cast_tool_holder(verts, tris, samples, dirs, radius, cut_length, holder_radius, kind=0, threads=0):
+    """Brute-force tool cast with a holder: the ball-end cutter of `radius`
+    swept over `cut_length` from the tip centre, then a holder of
+    `holder_radius` along the rest of the approach half-line.  Blocked when a
+    triangle comes within radius - tol of the cutter segment or within
+    holder_radius - tol of the holder half-line.  Returns (bits, ambiguous)."""
+    v, t = _f32(verts), _i32(tris)
+    Pt, Nn, d = _f32(samples["point"]), _f32(samples["normal"]), _f32(dirs)
+    S, N = len(Pt), len(d)
+    W = (N + 31) // 32
+    _, diag, _ = mesh_info(verts)
+    bits = np.empty((S, W), np.uint32)
+    amb = np.empty((S, W), np.uint32)
+    lib().orc_cast_tool_holder(_p(v), _p(t), len(t), _p(Pt), _p(Nn), 0, S, _p(d), N, kind, float(radius),
+                               float(cut_length), float(holder_radius), TOOL_TOL_FRAC * diag, TOOL_BAND_FRAC * diag,
+                               _p(bits), _p(amb), threads)
+    return bits, amb
+
+
+def tool_holder_distances(tri9, c, u, cut_length):
+    """FP64 (distance from the cutter segment c + t u, 0 <= t <= cut_length,
+    distance from the holder half-line from c + cut_length u) to a triangle."""
+    a = np.ascontiguousarray(tri9, np.float64).reshape(9)
+    out = np.zeros(2, np.float64)
+    lib().orc_tool_holder_distances(_p(a), _p(np.ascontiguousarray(c, np.float64)),
+                                    _p(np.ascontiguousarray(u, np.float64)), float(cut_length), _p(out))
+    return float(out[0]), float(out[1])
 
 
 def tool_distance(tri9, c, u):
