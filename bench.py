@@ -97,6 +97,7 @@ def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
 # counted.
 TOOL_NODE_OPS, TOOL_SCREEN_OPS, TOOL_TRI_OPS = 56, 57, 470
 TOOL_RADIUS_MM = 3.0
+CUT_LENGTH_MM, HOLDER_RADIUS_MM = 20.0, 8.0   # a 6 mm ball-end cutter, 20 mm of flute, a 16 mm holder
 
 
 def tool_extra(ctx, bvh, samples, N, reps=3):
@@ -115,10 +116,19 @@ def tool_extra(ctx, bvh, samples, N, reps=3):
     ms = e0.elapsed_time(e1) / reps
     wb, nv, nt, ns = ctx.cast_tool_work(bvh, samples, N, TOOL_RADIUS_MM)
     rays = S * N
+    # the same ball with a holder: HOLDER_RADIUS_MM from CUT_LENGTH_MM above the tip centre
+    _, hc = ctx.cast_tool_holder(bvh, samples, N, TOOL_RADIUS_MM, CUT_LENGTH_MM, HOLDER_RADIUS_MM)
+    e0.record()
+    ctx.cast_tool_holder(bvh, samples, N, TOOL_RADIUS_MM, CUT_LENGTH_MM, HOLDER_RADIUS_MM, counts=False)
+    e1.record()
+    torch.cuda.synchronize()
+    hms = e0.elapsed_time(e1)
+    holder = {"cut_length_mm": CUT_LENGTH_MM, "holder_radius_mm": HOLDER_RADIUS_MM, "ms": hms,
+              "dirs_per_s": rays / (hms * 1e-3), "free_fraction": int(hc.to(torch.int64).sum()) / rays}
     ops = nv * TOOL_NODE_OPS + ns * TOOL_SCREEN_OPS + nt * TOOL_TRI_OPS
     return {"radius_mm": TOOL_RADIUS_MM, "ms": ms, "dirs_per_s": rays / (ms * 1e-3),
             "node_visits_per_dir": nv / rays, "screened_tris_per_dir": ns / rays, "distance_tests_per_dir": nt / rays,
-            "instrumented_bits_identical": bool(torch.equal(wb, bits)), "free_fraction": free / rays,
+            "instrumented_bits_identical": bool(torch.equal(wb, bits)), "free_fraction": free / rays, "holder": holder,
             "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
                          "frac": ops / (ms * 1e-3) / 1e12 / ALU_PEAK_TOPS, "ops_per_dir": ops / rays}}
 

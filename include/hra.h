@@ -241,6 +241,21 @@ hra_status hra_get_cast_config(const hra_ctx *ctx, hra_cast_config *cfg);
  * non-finite one fails at once.  Enqueues on `stream`. */
 hra_status hra_cast_tool(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples, hra_dirs dirs,
                          double tool_radius, uint32_t *d_bits, uint32_t *d_counts, void *stream);
+/* The tool cast with a holder (an extension of the same reading: Section
+ * 3.3 names tool reach, and a real cutter sits in a wider holder).  The
+ * cutter is the ball of tool_radius swept from the tip centre c over
+ * cut_length mm along the approach direction u (the segment c .. c +
+ * cut_length u); the holder is every point within holder_radius of the rest
+ * of the half-line, from h = c + cut_length u on.  Direction free iff no
+ * triangle comes closer than tool_radius - tol to the segment nor closer
+ * than holder_radius - tol to the holder half-line (tol and the ambiguity
+ * band as for hra_cast_tool).  cut_length must be positive and finite and
+ * holder_radius finite and >= tool_radius (HRA_ERR_INVALID_ARG otherwise);
+ * holder_radius == tool_radius gives hra_cast_tool's tool.  Outputs,
+ * directions and stream as for hra_cast_tool. */
+hra_status hra_cast_tool_holder(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                                hra_dirs dirs, double tool_radius, double cut_length, double holder_radius,
+                                uint32_t *d_bits, uint32_t *d_counts, void *stream);
 /* The same tool cast (identical bits) in an instrumented build that also
  * counts, over all directions, the interior nodes visited, the FP64
  * triangle-distance tests made and the triangles that reached the FP32

@@ -34,6 +34,7 @@ struct ToolArgs {
     int32_t n_dirs, kind, W, n_nodes_alloc;
     int64_t n_samples, n_rays;
     double radius;
+    double hlen, hrad;            // holder: cutter length from the tip centre and holder radius (HOLDER only)
     uint32_t *bits;               // [n_samples][W], cleared first
     uint32_t *err;
     unsigned long long *work;     // instrumented launch: {node visits, FP64 distance tests, screened triangles}
@@ -151,6 +152,35 @@ __device__ inline bool tool_blocked(D3 c, D3 u, float4 A4, float4 B4, float4 C4,
     return fmin(fmin(ray_seg_dist(c, u, A, B), ray_seg_dist(c, u, B, C)), ray_seg_dist(c, u, C, A)) < thr;
 }
 
+// distance between the segments [p, q] and [a, b]: an end point of one to
+// the other, or the common perpendicular when its feet fall inside both
+__device__ inline double seg_seg_dist(D3 p, D3 q, D3 a, D3 b) {
+    double best = fmin(fmin(seg_dist(p, a, b), seg_dist(q, a, b)), fmin(seg_dist(a, p, q), seg_dist(b, p, q)));
+    const D3 f = q - p, e = b - a, w = p - a;
+    const double ff = dot(f, f), fe = dot(f, e), ee = dot(e, e), fw = dot(f, w), ew = dot(e, w);
+    const double den = ff * ee - fe * fe;
+    if (den > 1e-300 * (ff * ee > 1.0 ? ff * ee : 1.0)) {
+        const double sp = (fe * ew - ee * fw) / den, tp = (ff * ew - fe * fw) / den;
+        if (sp > 0.0 && sp < 1.0 && tp > 0.0 && tp < 1.0) best = fmin(best, norm((w + sp * f) - tp * e));
+    }
+    return best;
+}
+
+// Tool with a holder: the cutter (radius r) is the segment from c to
+// h = c + len u, the holder (radius R) the half-line from h along u.  True
+// when the triangle comes closer than thr = r - tol to the cutter or closer
+// than thr_h = R - tol to the holder.  The segment crosses the triangle when
+// the half-lines from c along u and from h along -u both meet it.
+__device__ inline bool tool_blocked_holder(D3 c, D3 u, double len, float4 A4, float4 B4, float4 C4, double thr,
+                                           double thr_h) {
+    const D3 A = f4d(A4), B = f4d(B4), C = f4d(C4);
+    const D3 h = c + len * u, mu = mk(-u.x, -u.y, -u.z);
+    if (ray_meets(c, u, A, B, C) && ray_meets(h, mu, A, B, C)) return true;
+    if (fmin(tri_dist(c, A, B, C), tri_dist(h, A, B, C)) < thr) return true;
+    if (fmin(fmin(seg_seg_dist(c, h, A, B), seg_seg_dist(c, h, B, C)), seg_seg_dist(c, h, C, A)) < thr) return true;
+    return tool_blocked(h, u, A4, B4, C4, thr_h);
+}
+
 // FP32 slab test against a box grown by pad on every side
 __device__ inline bool grown_slab(float lx, float ly, float lz, float hx, float hy, float hz, float pad, float ox,
                                   float oy, float oz, float ix, float iy, float iz, float &tn) {
@@ -168,7 +198,10 @@ __device__ inline float rcp_guarded(float x) { return fabsf(x) > 1e-30f ? 1.0f /
 // Four waves per SIMD: the compiler's own choice (142 VGPRs) allows three;
 // capped at 128 it spills 15 registers on the FP64 path and the cast runs 9 %
 // faster (the FP64 test out of line at the same cap: 5 %).
-template <bool STATS>
+// HOLDER: the cutter and holder of tool_blocked_holder; the box growth and
+// both FP32 screens then use the larger radius, which covers the whole
+// half-line from c (the cutter segment and the holder both lie on it).
+template <bool STATS, bool HOLDER>
 __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_cast_tool(ToolArgs a) {
     __shared__ int stk[TOOL_STACK * TOOL_THREADS];
     const int64_t g = (int64_t)blockIdx.x * TOOL_THREADS + threadIdx.x;
@@ -193,6 +226,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
         if ((nx * d.x + ny * d.y) + nz * d.z < 0.0f) return;   // into the material: not cast, bit 0
     }
     const double r = a.radius, tol = 1e-4 * P.diag, thr = r - tol;
+    const double rr = HOLDER ? fmax(r, a.hrad) : r, thr_h = HOLDER ? a.hrad - tol : thr;
     if (!(thr > tol)) {   // a tool thinner than twice the tolerance is not meaningful
         atomicOr(a.err, ERR_TOOL_RADIUS);
         return;
@@ -207,14 +241,14 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
         // FP32 box tests from the rounded tip centre; the margin covers the
         // rounding of the centre and of the grown box faces
         const float cx = (float)c.x, cy = (float)c.y, cz = (float)c.z;
-        const float pad = (float)(r * 1.0001) + (float)(1e-5 * P.diag);
+        const float pad = (float)(rr * 1.0001) + (float)(1e-5 * P.diag);
         const float ix = rcp_guarded(d.x), iy = rcp_guarded(d.y), iz = rcp_guarded(d.z);
         // unit direction and threshold for the FP32 screen; the margin
         // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a
         // part far from the origin) is far above the screen's rounding
         const float ux = (float)u.x, uy = (float)u.y, uz = (float)u.z;
         const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
-        const float thr_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax);
+        const float thr_hi = (float)(fmax(thr, thr_h) + 1e-5 * P.diag + 1e-6 * cmax);
         int spill[TOOL_SPILL];
         int sp = 0;
         int32_t node = root;
@@ -229,7 +263,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                 if (STATS) ++n_cands;
                 if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
                 if (STATS) ++n_tests;
-                blocked = tool_blocked(c, u, A4, B4, C4, thr);
+                blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
             }
             node = -1;
         }
@@ -258,7 +292,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                     if (STATS) ++n_cands;
                     if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
                     if (STATS) ++n_tests;
-                    blocked = tool_blocked(c, u, A4, B4, C4, thr);
+                    blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
                 }
             }
             if (blocked || bad) break;
@@ -317,12 +351,18 @@ using namespace hra;
 
 static hra_status tool_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
                                hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint32_t *d_counts,
-                               unsigned long long *work, hipStream_t s) {
+                               unsigned long long *work, hipStream_t s, double cut_length = 0.0,
+                               double holder_radius = 0.0) {
+    const bool holder = cut_length != 0.0;
     if (!ctx || !bvh || !samples) return HRA_ERR_INVALID_ARG;
     if (part < 0 || part >= bvh->n_parts) return ctx->fail(HRA_ERR_INVALID_ARG, "part index out of range");
     if (samples->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
     if (!(tool_radius > 0.0) || !std::isfinite(tool_radius))
         return ctx->fail(HRA_ERR_INVALID_ARG, "tool radius must be positive and finite");
+    if (holder && (!(cut_length > 0.0) || !std::isfinite(cut_length)))
+        return ctx->fail(HRA_ERR_INVALID_ARG, "cutting length must be positive and finite");
+    if (holder && (!(holder_radius >= tool_radius) || !std::isfinite(holder_radius)))
+        return ctx->fail(HRA_ERR_INVALID_ARG, "holder radius must be finite and at least the tool radius");
     const float4 *table = nullptr;
     hra_status st = dir_table(ctx, dirs, &table);
     if (st != HRA_OK) return st;
@@ -344,6 +384,8 @@ static hra_status tool_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, co
     a.n_samples = samples->n;
     a.n_rays = samples->n * (int64_t)dirs.n;
     a.radius = tool_radius;
+    a.hlen = cut_length;
+    a.hrad = holder ? holder_radius : tool_radius;
     a.bits = d_bits;
     a.err = ctx->d_err;
     a.work = work;
@@ -351,8 +393,13 @@ static hra_status tool_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, co
     const int64_t blocks = (a.n_rays + TOOL_THREADS - 1) / TOOL_THREADS;
     if (blocks >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call");
     k_tool_zero<<<(unsigned)((words + 255) / 256), 256, 0, s>>>(d_bits, words);
-    if (work) k_cast_tool<true><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
-    else k_cast_tool<false><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
+    if (holder) {
+        if (work) k_cast_tool<true, true><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
+        else k_cast_tool<false, true><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
+    } else {
+        if (work) k_cast_tool<true, false><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
+        else k_cast_tool<false, false><<<(unsigned)blocks, TOOL_THREADS, 0, s>>>(a);
+    }
     if (d_counts) k_tool_popcount<<<(unsigned)((samples->n + 255) / 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);
     HRA_HIP(hipGetLastError());
     return HRA_OK;
@@ -362,6 +409,17 @@ extern "C" hra_status hra_cast_tool(hra_ctx *ctx, const hra_bvh *bvh, int32_t pa
                                     hra_dirs dirs, double tool_radius, uint32_t *d_bits, uint32_t *d_counts,
                                     void *stream) {
     return tool_common(ctx, bvh, part, samples, dirs, tool_radius, d_bits, d_counts, nullptr, (hipStream_t)stream);
+}
+
+extern "C" hra_status hra_cast_tool_holder(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
+                                           hra_dirs dirs, double tool_radius, double cut_length,
+                                           double holder_radius, uint32_t *d_bits, uint32_t *d_counts, void *stream) {
+    if (!(cut_length != 0.0)) {
+        if (!ctx) return HRA_ERR_INVALID_ARG;
+        return ctx->fail(HRA_ERR_INVALID_ARG, "cutting length must be positive and finite");
+    }
+    return tool_common(ctx, bvh, part, samples, dirs, tool_radius, d_bits, d_counts, nullptr, (hipStream_t)stream,
+                       cut_length, holder_radius);
 }
 
 extern "C" hra_status hra_cast_tool_work(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,

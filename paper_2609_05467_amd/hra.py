@@ -201,6 +201,7 @@ def lib():
             "hra_stl_free": ([P], None),
             "hra_stl_error": ([], C.c_char_p),
             "hra_cast_tool": ([P, P, i32, C.POINTER(Samples), Dirs, f64, P, P, P], C.c_int),
+            "hra_cast_tool_holder": ([P, P, i32, C.POINTER(Samples), Dirs, f64, f64, f64, P, P, P], C.c_int),
             "hra_cast_tool_work": ([P, P, i32, C.POINTER(Samples), Dirs, f64, P, C.POINTER(u64), C.POINTER(u64),
                                     C.POINTER(u64), P], C.c_int),
         }
@@ -221,7 +222,8 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_plan_destroy", "hra_autotune", "hra_now_ns", "hra_server_create", "hra_server_submit",
            "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy",
            "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply", "hra_stl_read", "hra_stl_copy",
-           "hra_stl_free", "hra_stl_error", "hra_cast_tool", "hra_cast_tool_work"]
+           "hra_stl_free", "hra_stl_error", "hra_cast_tool", "hra_cast_tool_work",
+           "hra_cast_tool_holder"]
 FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
@@ -411,6 +413,19 @@ class Context:
         st = self._samples_struct(samples)
         self._check(lib().hra_cast_tool(self.ptr, bvh.ptr, part, C.byref(st), Dirs(kind, n_dirs), float(radius),
                                         _ptr(bits), _ptr(cnt), _stream(stream)))
+        return bits, cnt
+
+    def cast_tool_holder(self, bvh, samples, n_dirs, radius, cut_length, holder_radius, kind=DIRS_HEMI, counts=True,
+                         stream=None, part=0):
+        """Tool cast with a holder (hra_cast_tool_holder): cutter of `radius` over
+        `cut_length` mm from the tip centre, holder of `holder_radius` beyond."""
+        n = samples["origin"].shape[0]
+        bits = torch.empty((n, (n_dirs + 31) // 32), dtype=torch.int32, device=self.device)
+        cnt = torch.empty((n,), dtype=torch.int32, device=self.device) if counts else None
+        st = self._samples_struct(samples)
+        self._check(lib().hra_cast_tool_holder(self.ptr, bvh.ptr, part, C.byref(st), Dirs(kind, n_dirs),
+                                               float(radius), float(cut_length), float(holder_radius), _ptr(bits),
+                                               _ptr(cnt), _stream(stream)))
         return bits, cnt
 
     def cast_tool_work(self, bvh, samples, n_dirs, radius, kind=DIRS_HEMI, stream=None, part=0):

@@ -142,3 +142,33 @@ def test_tool_errors(ctx):
     # no samples: nothing to do
     bits, _ = ctx.cast_tool(b, ctx.alloc_samples(0), 64, 1.0)
     assert bits.shape == (0, 2)
+
+
+@pytest.mark.parametrize("R", [1.5, 4.0, 12.0])
+def test_tool_holder_parity(ctx, orc, R):
+    m = P.config1_part()
+    b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.sample_surface(b, 300, 6)
+    sn = _np(s)
+    r, L, N = 1.5, 8.0, 150
+    _say("tool holder", r, L, R)
+    bits, cnt = ctx.cast_tool_holder(b, s, N, r, L, R)
+    got = _u32(bits)
+    ob, oa = orc.cast_tool_holder(m.verts, m.tris, sn, orc.fibonacci_dirs(N), r, L, R)
+    assert not ((got ^ ob) & ~oa).any()
+    popc = np.array([int(np.unpackbits(w.view(np.uint8)).sum()) for w in got])
+    assert np.array_equal(_u32(cnt), popc.astype(np.uint32))
+    if R == r:
+        plain, _ = ctx.cast_tool(b, s, N, r)
+        pb, pa = orc.cast_tool(m.verts, m.tris, sn, orc.fibonacci_dirs(N), r)
+        assert not ((_u32(plain) ^ got) & ~(oa | pa)).any()
+
+
+def test_tool_holder_errors(ctx):
+    from paper_2609_05467_amd import hra
+    m = P.box_part()
+    b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.sample_surface(b, 20, 1)
+    for L, R in ((0.0, 2.0), (-1.0, 2.0), (float("nan"), 2.0), (float("inf"), 2.0), (5.0, 0.5), (5.0, float("nan"))):
+        with pytest.raises(hra.HraError):
+            ctx.cast_tool_holder(b, s, 64, 1.0, L, R)
