@@ -144,6 +144,26 @@ __device__ inline bool far_from_axis(float cx, float cy, float cz, float ux, flo
     return away >= -1e-6f * nn && fabsf(s0) > thr_hi * nn;
 }
 
+// The sphere screen of far_from_axis for a tool with a holder: the
+// triangle's bounding sphere (centroid m, radius rho) against the cutter
+// segment c .. c + len u with thr_hi and against the holder half-line from
+// c + len u with thr_h_hi; ruled out only when it clears both.
+__device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float ux, float uy, float uz, float len,
+                                            float4 A, float4 B, float4 C, float thr_hi, float thr_h_hi) {
+    const float mx = ((A.x + B.x) + C.x) * (1.0f / 3.0f), my = ((A.y + B.y) + C.y) * (1.0f / 3.0f),
+                mz = ((A.z + B.z) + C.z) * (1.0f / 3.0f);
+    const float ax = A.x - mx, ay = A.y - my, az = A.z - mz, bx = B.x - mx, by = B.y - my, bz = B.z - mz;
+    const float qx = C.x - mx, qy = C.y - my, qz = C.z - mz;
+    const float rho = sqrtf(fmaxf(fmaxf((ax * ax + ay * ay) + az * az, (bx * bx + by * by) + bz * bz),
+                                  (qx * qx + qy * qy) + qz * qz));
+    const float wx = mx - cx, wy = my - cy, wz = mz - cz;
+    const float t = (wx * ux + wy * uy) + wz * uz;
+    const float ts = fminf(fmaxf(t, 0.0f), len), th = fmaxf(t, len);
+    const float sx = wx - ts * ux, sy = wy - ts * uy, sz = wz - ts * uz;
+    const float hx = wx - th * ux, hy = wy - th * uy, hz = wz - th * uz;
+    return sqrtf((sx * sx + sy * sy) + sz * sz) - rho > thr_hi && sqrtf((hx * hx + hy * hy) + hz * hz) - rho > thr_h_hi;
+}
+
 // true when the triangle comes closer than thr to the tool axis
 __device__ inline bool tool_blocked(D3 c, D3 u, float4 A4, float4 B4, float4 C4, double thr) {
     const D3 A = f4d(A4), B = f4d(B4), C = f4d(C4);
@@ -191,6 +211,25 @@ __device__ inline bool grown_slab(float lx, float ly, float lz, float hx, float 
     const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
     tn = tmin;
     return tmin <= tmax * 1.0000006f;
+}
+
+// Box test of a tool with a holder: the box grown by the cutter's pad must
+// meet the ray before the cutting length ends (t <= len_hi), or the box grown
+// by the holder's pad after it starts (t >= len_lo); len_hi and len_lo carry
+// a wide slack, so a doubt means a visit.  tn orders the children.
+__device__ inline bool holder_slab(float lx, float ly, float lz, float hx, float hy, float hz, float pad_c, float pad_h,
+                                   float len_lo, float len_hi, float ox, float oy, float oz, float ix, float iy,
+                                   float iz, float &tn) {
+    float tc, th;
+    const bool hc = grown_slab(lx, ly, lz, hx, hy, hz, pad_c, ox, oy, oz, ix, iy, iz, tc) && tc <= len_hi;
+    const float tx0 = ((lx - pad_h) - ox) * ix, tx1 = ((hx + pad_h) - ox) * ix;
+    const float ty0 = ((ly - pad_h) - oy) * iy, ty1 = ((hy + pad_h) - oy) * iy;
+    const float tz0 = ((lz - pad_h) - oz) * iz, tz1 = ((hz + pad_h) - oz) * iz;
+    th = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * 1.0000006f;
+    const bool hh = th <= tmax && tmax >= len_lo;
+    tn = hc ? tc : th;
+    return hc || hh;
 }
 
 __device__ inline float rcp_guarded(float x) { return fabsf(x) > 1e-30f ? 1.0f / x : copysignf(1e30f, x); }
@@ -242,6 +281,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
         // rounding of the centre and of the grown box faces
         const float cx = (float)c.x, cy = (float)c.y, cz = (float)c.z;
         const float pad = (float)(rr * 1.0001) + (float)(1e-5 * P.diag);
+        const float pad_c = (float)(r * 1.0001) + (float)(1e-5 * P.diag);   // the cutter's (HOLDER)
         const float ix = rcp_guarded(d.x), iy = rcp_guarded(d.y), iz = rcp_guarded(d.z);
         // unit direction and threshold for the FP32 screen; the margin
         // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a
@@ -249,6 +289,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
         const float ux = (float)u.x, uy = (float)u.y, uz = (float)u.z;
         const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
         const float thr_hi = (float)(fmax(thr, thr_h) + 1e-5 * P.diag + 1e-6 * cmax);
+        const float thr_c_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax), hl = (float)a.hlen;
         int spill[TOOL_SPILL];
         int sp = 0;
         int32_t node = root;
@@ -261,6 +302,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                 const float4 *t = a.tris + 3 * (int64_t)(f + k);
                 const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                 if (STATS) ++n_cands;
+                if (HOLDER && far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)) continue;
                 if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
                 if (STATS) ++n_tests;
                 blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
@@ -275,8 +317,16 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
             const Node nd = a.nodes[node];
             if (STATS) ++n_nodes;
             float t0, t1;
-            const bool h0 = grown_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, pad, cx, cy, cz, ix, iy, iz, t0);
-            const bool h1 = grown_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, pad, cx, cy, cz, ix, iy, iz, t1);
+            bool h0, h1;
+            if (HOLDER) {
+                h0 = holder_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, pad_c, pad, hl * 0.99f, hl * 1.01f, cx, cy,
+                                 cz, ix, iy, iz, t0);
+                h1 = holder_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, pad_c, pad, hl * 0.99f, hl * 1.01f, cx, cy,
+                                 cz, ix, iy, iz, t1);
+            } else {
+                h0 = grown_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, pad, cx, cy, cz, ix, iy, iz, t0);
+                h1 = grown_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, pad, cx, cy, cz, ix, iy, iz, t1);
+            }
             const int32_t ch[2] = {nd.d.x, nd.d.y};
             const bool hit[2] = {h0, h1};
             for (int k = 0; k < 2 && !blocked && !bad; ++k) {
@@ -290,6 +340,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                     const float4 *t = a.tris + 3 * (int64_t)(f + q);
                     const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                     if (STATS) ++n_cands;
+                    if (HOLDER && far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)) continue;
                     if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
                     if (STATS) ++n_tests;
                     blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
