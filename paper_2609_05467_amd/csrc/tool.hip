@@ -144,10 +144,10 @@ __device__ inline bool far_from_axis(float cx, float cy, float cz, float ux, flo
     return away >= -1e-6f * nn && fabsf(s0) > thr_hi * nn;
 }
 
-// The sphere screen of far_from_axis for a tool with a holder: the
-// triangle's bounding sphere (centroid m, radius rho) against the cutter
-// segment c .. c + len u with thr_hi and against the holder half-line from
-// c + len u with thr_h_hi; ruled out only when it clears both.
+// The screens of far_from_axis for a tool with a holder.  The triangle's
+// bounding sphere (centroid m, radius rho) against the cutter segment
+// c .. c + len u with thr_hi and against the holder half-line from c + len u
+// with thr_h_hi: ruled out when it clears both.
 __device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float ux, float uy, float uz, float len,
                                             float4 A, float4 B, float4 C, float thr_hi, float thr_h_hi) {
     const float mx = ((A.x + B.x) + C.x) * (1.0f / 3.0f), my = ((A.y + B.y) + C.y) * (1.0f / 3.0f),
@@ -161,7 +161,21 @@ __device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float 
     const float ts = fminf(fmaxf(t, 0.0f), len), th = fmaxf(t, len);
     const float sx = wx - ts * ux, sy = wy - ts * uy, sz = wz - ts * uz;
     const float hx = wx - th * ux, hy = wy - th * uy, hz = wz - th * uz;
-    return sqrtf((sx * sx + sy * sy) + sz * sz) - rho > thr_hi && sqrtf((hx * hx + hy * hy) + hz * hz) - rho > thr_h_hi;
+    if (sqrtf((sx * sx + sy * sy) + sz * sz) - rho > thr_hi && sqrtf((hx * hx + hy * hy) + hz * hz) - rho > thr_h_hi)
+        return true;
+    // The plane screen split the same way: when the axis does not approach
+    // the plane, cutter points are at least as far from it as c and holder
+    // points at least as far as h = c + len u (conditions and margins as in
+    // far_from_axis).
+    const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z, e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
+    const float Nx = e1y * e2z - e1z * e2y, Ny = e1z * e2x - e1x * e2z, Nz = e1x * e2y - e1y * e2x;
+    const float nn = sqrtf((Nx * Nx + Ny * Ny) + Nz * Nz);
+    const float l1 = sqrtf((e1x * e1x + e1y * e1y) + e1z * e1z), l2 = sqrtf((e2x * e2x + e2y * e2y) + e2z * e2z);
+    if (!(nn > 0.05f * (l1 * l2))) return false;
+    const float s0 = ((cx - A.x) * Nx + (cy - A.y) * Ny) + (cz - A.z) * Nz;
+    const float s1 = (ux * Nx + uy * Ny) + uz * Nz;
+    const float away = s0 >= 0.0f ? s1 : -s1;
+    return away >= -1e-6f * nn && fabsf(s0) > thr_hi * nn && fabsf(s0 + len * s1) > thr_h_hi * nn;
 }
 
 // true when the triangle comes closer than thr to the tool axis
@@ -302,8 +316,9 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                 const float4 *t = a.tris + 3 * (int64_t)(f + k);
                 const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                 if (STATS) ++n_cands;
-                if (HOLDER && far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)) continue;
-                if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
+                if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)
+                           : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi))
+                    continue;
                 if (STATS) ++n_tests;
                 blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
             }
@@ -340,8 +355,9 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                     const float4 *t = a.tris + 3 * (int64_t)(f + q);
                     const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                     if (STATS) ++n_cands;
-                    if (HOLDER && far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)) continue;
-                    if (far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi)) continue;
+                    if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)
+                               : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi))
+                        continue;
                     if (STATS) ++n_tests;
                     blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
                 }
