@@ -70,6 +70,14 @@ def lib():
         L.orc_decide_one.restype = C.c_int
         L.orc_dirstats.argtypes = [P, i64, P, i32, P, P, P, P, P, P, P]
         L.orc_max_threads.restype = C.c_int32
+        L.orc_bvh_build.argtypes = [P, i64, P, i64, C.c_double]
+        L.orc_bvh_build.restype = C.c_void_p
+        L.orc_bvh_free.argtypes = [P]
+        L.orc_bvh_free.restype = None
+        L.orc_bvh_shape.argtypes = [P, P]
+        L.orc_bvh_shape.restype = None
+        L.orc_bvh_cast.argtypes = [P, P, P, i64, i64, P, i32, i32, P, P, P, P, i32]
+        L.orc_bvh_cast.restype = C.c_int
         _lib = L
     return _lib
 
@@ -201,6 +209,65 @@ def cast_rays(verts, tris, origins, dirs, threads=0):
     out = np.empty(len(O), np.uint8)
     lib().orc_cast_rays(_p(v), _p(t), len(t), _p(O), _p(D), len(O), _p(out), threads)
     return out
+
+
+BVH_PAD_FRAC = 1e-4     # outward growth of the oracle hierarchy's boxes: 1e-4 x bbox diagonal
+
+
+class BVHCast:
+    """The brute-force cast through a padded median-split hierarchy
+    (hra_oracle.c, orc_bvh_cast): the same bits wherever brute force decides
+    a ray, and a subset of its grazing flags (equal on every mesh the tests
+    compare).  Holds its own copies of the mesh arrays."""
+
+    def __init__(self, verts, tris, pad_frac=BVH_PAD_FRAC):
+        self.v, self.t = _f32(verts).copy(), _i32(tris).copy()
+        _, diag, _ = mesh_info(self.v)
+        self.pad = float(pad_frac) * diag
+        self.h = lib().orc_bvh_build(_p(self.v), len(self.v), _p(self.t), len(self.t), self.pad)
+        if not self.h:
+            raise MemoryError("oracle hierarchy build failed")
+        sh = np.zeros(2, np.int64)
+        lib().orc_bvh_shape(self.h, _p(sh))
+        self.n_nodes, self.depth = int(sh[0]), int(sh[1])
+        self.work = np.zeros(2, np.uint64)
+
+    def cast(self, samples, dirs, kind=0, s0=0, s1=None, threads=0):
+        """(bits, grazing, info), uint32 [s1 - s0][W], as oracle.cast."""
+        O, Nn, d = _f32(samples["origin"]), _f32(samples["normal"]), _f32(dirs)
+        s1 = len(O) if s1 is None else s1
+        N = len(d)
+        W = (N + 31) // 32
+        S = s1 - s0
+        bits = np.empty((S, W), np.uint32)
+        gr = np.empty((S, W), np.uint32)
+        inf = np.empty((S, W), np.uint32)
+        if S > 0:
+            rc = lib().orc_bvh_cast(self.h, _p(O), _p(Nn), s0, s1, _p(d), N, kind, _p(bits), _p(gr), _p(inf),
+                                    _p(self.work), threads)
+            if rc != 0:
+                raise MemoryError("oracle hierarchy cast failed")
+        return bits, gr, inf
+
+    def close(self):
+        if self.h:
+            lib().orc_bvh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cast_bvh(verts, tris, samples, dirs, kind=0, s0=0, s1=None, threads=0):
+    """oracle.cast through the padded hierarchy (one-off build)."""
+    b = BVHCast(verts, tris)
+    try:
+        return b.cast(samples, dirs, kind, s0, s1, threads)
+    finally:
+        b.close()
 
 
 TOOL_TOL_FRAC = 1e-4    # tool clearance tolerance: 1e-4 x bbox diagonal

@@ -61,6 +61,39 @@ def test_fibonacci_hemisphere_properties(orc, n):
     assert abs((d[:, 2] ** 2).mean() - 1.0 / 3.0) < 1e-3
 
 
+GOLDEN_ANGLE = math.pi * (3.0 - math.sqrt(5.0))   # 137.5078 degrees
+
+
+def _azimuth_walk_ok(d, n):
+    """Point 0 lies at azimuth 0 (on the +x side of the x-z plane), point j
+    at height 1 - (2j+1)/(2n), and each point lies one golden angle
+    counter-clockwise from the one before (Section 3.1's uniform hemisphere
+    read as the spherical Fibonacci lattice).  A mirrored set turns
+    clockwise; a shifted index moves point 0 off azimuth 0 and every height."""
+    d = np.asarray(d, np.float64)
+    j = np.arange(n)
+    if not np.all(np.abs(d[:, 2] - (1.0 - (2.0 * j + 1.0) / (2.0 * n))) <= 1.2e-7):
+        return False
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    if not (abs(phi[0]) < 1e-6 and d[0, 0] > 0):
+        return False
+    step = np.mod(np.diff(phi) - GOLDEN_ANGLE + math.pi, 2 * math.pi) - math.pi
+    r = np.hypot(d[:, 0], d[:, 1])
+    tol = 4e-7 / np.minimum(r[1:], r[:-1]) + 1e-6
+    return bool(np.all(np.abs(step) <= tol))
+
+
+@pytest.mark.parametrize("n", [1, 2, 150, 512, 4096, 8192])
+def test_fibonacci_azimuth_walk(orc, n):
+    d = orc.fibonacci_dirs(n)
+    assert _azimuth_walk_ok(d, n)
+    if n >= 2:
+        # the check itself catches a mirror (phi -> -phi) and a shifted index
+        mirrored = d * np.array([1, -1, 1], np.float32)
+        assert not _azimuth_walk_ok(mirrored, n)
+        assert not _azimuth_walk_ok(np.roll(d, 1, axis=0), n)
+
+
 def test_axes6(orc):
     a = orc.axes6()
     assert np.array_equal(a, np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float32))
