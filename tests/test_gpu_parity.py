@@ -314,7 +314,12 @@ def _stats_parity(ctx, orc, m, b, S, N, seed):
     rep = ctx.classify(st, S, N)
     ind = orc.indicators(orc.counts(got, N), N, o["axis"], o["conc"])
     assert abs(rep["access"] - ind["access"]) < 1e-12
-    assert np.allclose(rep["shares"], ind["shares"], atol=0, rtol=0) or not sel.all()
+    # the GPU and the oracle read the same bits, so a sample's axis can differ
+    # only where the oracle flags a tie: each share moves by at most
+    # ties / included samples (0 without ties: then equal exactly)
+    n_tie = int((~sel & (o["axis"] >= 0)).sum())
+    bound = n_tie / max(1, ind["n_included"])
+    assert max(abs(a - b) for a, b in zip(rep["shares"], ind["shares"])) <= bound + 1e-15
     assert abs(rep["conc"] - ind["conc"]) < 1e-4
     if not rep["near_tie"]:
         assert rep["multi_axis"] == orc.classify(ind)[0]
@@ -367,34 +372,8 @@ def test_setups_config1(ctx, orc, cfg1, L):
         assert (rep["min_count"], rep["min_mask"]) == (2, 0b010001)
 
 
-# ---------------------------------------------------------------- full size (interactive part)
-@pytest.fixture(scope="module")
-def interactive(ctx):
-    m = P.workload_parts("interactive_200k")[0]
-    b = ctx.build_bvh(m.verts, m.tris)
-    return m, b
-
-
-def test_interactive_full_size_sampled_rows(ctx, orc, interactive):
-    """Full 100k x 4096 cast in the benchmark's launch shape; rows of a
-    seeded subset are checked one by one against brute force."""
-    m, b = interactive
-    S, N = 100_000, 4096
-    _say("interactive full", m.n_tris, S, N)
-    s = ctx.sample_surface(b, S, 2)
-    bits, cnt = ctx.cast(b, s, N)
-    got = _u32(bits)
-    rng = np.random.default_rng(2)
-    rows = np.sort(rng.choice(S, 6, replace=False))
-    sn = _np_samples(s)
-    sub = {k: v[rows] for k, v in sn.items()}
-    ob, og, _ = orc.cast(m.verts, m.tris, sub, orc.fibonacci_dirs(N))
-    assert not ((got[rows] ^ ob) & ~og).any()
-    # samples of the whole set match the oracle's sampler
-    o = orc.sample_area(m.verts, m.tris, S, 2)
-    assert np.array_equal(sn["origin"], o["origin"]) and np.array_equal(sn["tri"], o["tri"])
-    c = _u32(cnt)
-    assert np.all(c <= N) and c.sum() > 0
+# Full-size workloads: every row is compared with the oracle in
+# test_gpu_full_size.py.
 
 
 def test_cast_work_counts(ctx, cfg1):
@@ -408,8 +387,9 @@ def test_cast_work_counts(ctx, cfg1):
 
 # ---------------------------------------------------------------- full size (multi-axis stress part)
 def test_multiaxis_full_size(ctx, orc):
-    """1M-triangle part, 250k samples x 2048 directions in one cast: sampled
-    rows against brute force; the histogram of each inclined bore's floor
+    """1M-triangle part, 250k samples x 2048 directions in one cast (every
+    row is compared with the oracle in test_gpu_full_size.py): the histogram
+    of each inclined bore's floor
     samples has the same peak as the oracle's on the same bits, and
     the rays from each bore's floor centre escape exactly when they cross
     the face plane inside the rim polygon (convex cavity closed form)."""
@@ -425,9 +405,6 @@ def test_multiaxis_full_size(ctx, orc):
     bits, cnt = ctx.cast(b, s, N)
     got = _u32(bits)
     sn = _np_samples(s)
-    rows = np.sort(np.random.default_rng(3).choice(S, 8, replace=False))
-    ob, og, _ = orc.cast(m.verts, m.tris, {k: v[rows] for k, v in sn.items()}, orc.fibonacci_dirs(N))
-    assert not ((got[rows] ^ ob) & ~og).any()
     st = ctx.dominant_axes(s, N, bits)
     h = st["hist"].cpu().numpy().view(np.uint32)
     assert int(h.astype(np.int64).sum()) == int(_u32(cnt).astype(np.int64).sum())
