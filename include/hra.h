@@ -305,6 +305,19 @@ int64_t hra_dirstats_bytes(int64_t n);
 hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
                              const hra_dirstats *out, void *stream);
 
+/* hra_dominant_axes for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same outputs, bit for bit, with no allocation.  What
+ * hra_dominant_axes allocates (its cached direction table and per-block
+ * histogram slices) sits instead in a device array of the library, 32 MiB +
+ * 128 KiB per device, held from the first context on that device until the
+ * process ends.  dirs.n must be 1..8192 (HRA_ERR_INVALID_ARG beyond).  Every
+ * call on one device shares that array: calls that overlap on a device (two
+ * streams, two threads) race and must be ordered by the caller.  Arguments,
+ * outputs and stream as for hra_dominant_axes. */
+hra_status hra_dominant_axes_noalloc(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
+                                     const hra_dirstats *out, void *stream);
+
 typedef struct {
     double min_access; /* multi-axis if overall accessibility < this (default 0.60) */
     double min_share;  /* multi-axis if the largest dominant-axis share < this (default 0.45) */

@@ -239,6 +239,12 @@ hipError_t put_mesh_table(MeshIn *dst, const MeshIn &m, hipStream_t s);
 
 // ---------------------------------------------------------------- helpers
 hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out);
+// The canonical Fibonacci hemisphere table of n directions (the values
+// dir_table caches) written to out[0, n) on stream s.
+hipError_t launch_fibonacci(int32_t n, float4 *out, hipStream_t s);
+// Look up, once per device, the address of the statistics' allocation-free
+// scratch array; called by hra_ctx_create with `device` current.
+hipError_t noalloc_setup(int device);
 hra_status check_error_word(hra_ctx *ctx, hipStream_t s);
 int blocks_for(int64_t n, int threads);
 

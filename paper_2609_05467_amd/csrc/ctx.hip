@@ -130,6 +130,11 @@ hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out) {
     return HRA_OK;
 }
 
+hipError_t launch_fibonacci(int32_t n, float4 *out, hipStream_t s) {
+    k_fibonacci<<<blocks_for(n, 256), 256, 0, s>>>(n, out);
+    return hipGetLastError();
+}
+
 hra_status check_error_word(hra_ctx *ctx, hipStream_t s) {
     HRA_HIP(hipStreamSynchronize(s));
     uint32_t w = 0;
@@ -167,6 +172,10 @@ hra_status hra_ctx_create(int32_t device, hra_ctx **out) {
         return HRA_ERR_DEVICE;
     }
     ctx->n_cu = prop.multiProcessorCount;
+    if (noalloc_setup(device) != hipSuccess) {
+        delete ctx;
+        return HRA_ERR_DEVICE;
+    }
     if (hipMalloc(&ctx->d_err, sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&ctx->d_counter, 64 * sizeof(uint32_t)) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) {

@@ -9,9 +9,13 @@
 
 namespace hra {
 struct DirTotals;
+// Directional statistics of n samples (k_dirstats); with `hist`, the
+// direction histogram too, formed from per-block slices in `slices`
+// (HIST_BINS words per block; NULL: stream-ordered allocation for the
+// launch); at most max_blocks blocks.
 hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const float4 *table, int32_t N,
                            const uint32_t *bits, const hra_dirstats &out, double *c64, uint32_t *cnt, bool hist,
-                           hipStream_t s);
+                           hipStream_t s, uint32_t *slices = nullptr, int64_t max_blocks = INT64_MAX);
 void classify_from_device_totals(const void *host_totals, int64_t n, int32_t n_dirs, const hra_thresholds *th,
                                  hra_class_report *out);
 hipError_t launch_part_totals_raw(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,

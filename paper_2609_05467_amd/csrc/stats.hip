@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstring>
 #include <vector>
+#include <map>
+#include <mutex>
 
 namespace hra {
 
@@ -371,24 +373,36 @@ extern "C" int64_t hra_dirstats_bytes(int64_t n) {
 
 namespace hra {
 
-hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const float4 *table, int32_t N,
-                           const uint32_t *bits, const hra_dirstats &out, double *c64, uint32_t *cnt, bool hist,
-                           hipStream_t s) {
-    if (n <= 0) return hipSuccess;
+// Blocks of a k_dirstats launch over n samples: four samples per block at
+// first, at most four blocks per compute unit, and at most max_blocks.
+static int64_t dirstats_blocks(const hra_ctx *ctx, int64_t n, int64_t max_blocks) {
     int64_t blocks = (n + 3) / 4;
     const int64_t cap = (int64_t)ctx->n_cu * 4;
     if (blocks > cap) blocks = cap;
-    uint32_t *part = nullptr;
+    if (blocks > max_blocks) blocks = max_blocks;
+    return blocks < 1 ? 1 : blocks;
+}
+
+// hist: also form the direction histogram, from per-block slices in
+// `slices` (HIST_BINS words per block; NULL: taken from the stream-ordered
+// allocator for the launch and returned after it).
+hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const float4 *table, int32_t N,
+                           const uint32_t *bits, const hra_dirstats &out, double *c64, uint32_t *cnt, bool hist,
+                           hipStream_t s, uint32_t *slices, int64_t max_blocks) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = dirstats_blocks(ctx, n, max_blocks);
+    uint32_t *part = slices;
     hipError_t e = hipSuccess;
-    if (hist) {
+    if (hist && !slices) {
         e = hipMallocAsync((void **)&part, sizeof(uint32_t) * HIST_BINS * (size_t)blocks, s);
         if (e != hipSuccess) return e;
     }
-    k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(normal, n, table, N, (N + 31) / 32, bits, out, c64, cnt, part);
+    k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(normal, n, table, N, (N + 31) / 32, bits, out, c64, cnt,
+                                                hist ? part : nullptr);
     if (hist) {
         k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out.hist, HIST_BINS);
         k_hist_reduce<<<dim3(HIST_BINS / 256, HR_CHUNKS), 256, 0, s>>>(part, (int)blocks, out.hist);
-        hipFreeAsync(part, s);
+        if (!slices) hipFreeAsync(part, s);
     }
     return hipGetLastError();
 }
@@ -506,7 +520,86 @@ extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples
         HRA_HIP(hipGetLastError());
         return HRA_OK;
     }
-    HRA_HIP(launch_dirstats(ctx, samples->normal, n, table, dirs.n, d_bits, *out, c64, cnt, true, s));
+    HRA_HIP(launch_dirstats(ctx, samples->normal, n, table, dirs.n, d_bits, *out, c64, cnt, true, s, nullptr,
+                            INT64_MAX));
+    k_part_totals<<<1, PT_THREADS, 0, s>>>(out->axis, cnt, c64, nullptr, nullptr, n, tot);
+    HRA_HIP(hipGetLastError());
+    return HRA_OK;
+}
+
+// ------------------------------------------------------ allocation-free form
+namespace hra {
+// hra_dominant_axes_noalloc keeps what hra_dominant_axes allocates (the
+// canonical direction table, cached per context, and the per-block
+// histogram slices, taken from the stream-ordered allocator) in this array
+// instead: NA_MAX_DIRS float4 table entries, then NA_SLICES slices of
+// HIST_BINS words (NA_SLICES = four blocks on each of MI355X's 256 compute
+// units, the cap of the allocating launch, so both launch the same grid
+// there).  The module holds one copy per device until the process ends.
+// Host code never names the array: it uses the address that
+// hipGetSymbolAddress returned for the current device (noalloc_setup).
+constexpr int32_t NA_MAX_DIRS = 8192;
+constexpr int64_t NA_SLICES = 1024;
+constexpr size_t NA_TABLE_BYTES = sizeof(float4) * NA_MAX_DIRS;
+constexpr size_t NA_SCRATCH_BYTES = NA_TABLE_BYTES + sizeof(uint32_t) * HIST_BINS * NA_SLICES;
+static __device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];
+
+static std::mutex na_mu;
+static std::map<int, unsigned char *> na_ptr;   // device -> address of `scratch` there
+
+// Called by hra_ctx_create with `device` current: look up the array's
+// address on this device once.
+hipError_t noalloc_setup(int device) {
+    std::lock_guard<std::mutex> lk(na_mu);
+    if (na_ptr.count(device)) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    na_ptr[device] = (unsigned char *)p;
+    return hipSuccess;
+}
+
+static unsigned char *noalloc_ptr(int device) {
+    std::lock_guard<std::mutex> lk(na_mu);
+    auto it = na_ptr.find(device);
+    return it == na_ptr.end() ? nullptr : it->second;
+}
+
+}  // namespace hra
+
+extern "C" hra_status hra_dominant_axes_noalloc(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs,
+                                                const uint32_t *d_bits, const hra_dirstats *out, void *stream) {
+    using namespace hra;
+    if (!ctx || !samples || !out) return HRA_ERR_INVALID_ARG;
+    if (!out->hist || !out->totals) return ctx->fail(HRA_ERR_INVALID_ARG, "histogram and totals must be non-null");
+    if (samples->n < 0) return ctx->fail(HRA_ERR_INVALID_ARG, "negative sample count");
+    if (samples->n > 0 && (!d_bits || !out->mean || !out->absmean || !out->axis || !out->conc || !samples->normal))
+        return ctx->fail(HRA_ERR_INVALID_ARG, "all hra_dirstats arrays must be non-null");
+    if (dirs.kind != HRA_DIRS_HEMI_FIBONACCI)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "directional statistics need the hemisphere set");
+    if (dirs.n < 1 || dirs.n > NA_MAX_DIRS)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "hra_dominant_axes_noalloc takes 1 to 8192 directions");
+    unsigned char *base = noalloc_ptr(ctx->device);
+    if (!base) return ctx->fail(HRA_ERR_DEVICE, "scratch address not set up for this device");
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(hipSetDevice(ctx->device));
+    float4 *table = (float4 *)base;
+    uint32_t *slices = (uint32_t *)(base + NA_TABLE_BYTES);
+    const int64_t n = samples->n;
+    DirTotals *tot = (DirTotals *)out->totals;
+    double *c64 = (double *)((char *)out->totals + sizeof(DirTotals));
+    uint32_t *cnt = (uint32_t *)(c64 + (n > 0 ? n : 0));
+    if (n == 0) {
+        k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out->hist, HIST_BINS);
+        k_part_totals<<<1, PT_THREADS, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nullptr, 0, tot);
+        HRA_HIP(hipGetLastError());
+        return HRA_OK;
+    }
+    // the table the cached one holds (same kernel), written on this stream
+    // ahead of its readers
+    HRA_HIP(launch_fibonacci(dirs.n, table, s));
+    HRA_HIP(launch_dirstats(ctx, samples->normal, n, table, dirs.n, d_bits, *out, c64, cnt, true, s, slices,
+                            NA_SLICES));
     k_part_totals<<<1, PT_THREADS, 0, s>>>(out->axis, cnt, c64, nullptr, nullptr, n, tot);
     HRA_HIP(hipGetLastError());
     return HRA_OK;

@@ -164,6 +164,7 @@ def lib():
             "hra_debug_rays": ([P, C.POINTER(Samples), Dirs, P, i64, P, P], C.c_int),
             "hra_dirstats_bytes": ([i64], i64),
             "hra_dominant_axes": ([P, C.POINTER(Samples), Dirs, P, C.POINTER(DirStats), P], C.c_int),
+            "hra_dominant_axes_noalloc": ([P, C.POINTER(Samples), Dirs, P, C.POINTER(DirStats), P], C.c_int),
             "hra_classify": ([P, C.POINTER(DirStats), i64, i32, C.POINTER(Thresholds), C.POINTER(ClassReport), P],
                              C.c_int),
             "hra_min_setups": ([P, P, C.POINTER(Samples), P, f64, P, C.POINTER(SetupReport), P], C.c_int),
@@ -223,7 +224,7 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy",
            "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply", "hra_stl_read", "hra_stl_copy",
            "hra_stl_free", "hra_stl_error", "hra_cast_tool", "hra_cast_tool_work",
-           "hra_cast_tool_holder"]
+           "hra_cast_tool_holder", "hra_dominant_axes_noalloc"]
 FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
@@ -492,7 +493,9 @@ class Context:
         return out
 
     # ---------------------------------------------------------------- stats
-    def dominant_axes(self, samples, n_dirs, bits, stream=None):
+    def dominant_axes(self, samples, n_dirs, bits, stream=None, noalloc=False):
+        """hra_dominant_axes, or with noalloc=True hra_dominant_axes_noalloc
+        (same outputs; the library allocates nothing for the call)."""
         n = samples["origin"].shape[0]
         d = self.device
         out = {"mean": torch.empty((n, 3), dtype=torch.float32, device=d),
@@ -503,8 +506,8 @@ class Context:
                "totals": torch.empty((int(lib().hra_dirstats_bytes(n)),), dtype=torch.uint8, device=d)}
         ds = DirStats(*[_ptr(out[k]) for k in ("mean", "absmean", "axis", "conc", "hist", "totals")])
         st = self._samples_struct(samples)
-        self._check(lib().hra_dominant_axes(self.ptr, C.byref(st), Dirs(DIRS_HEMI, n_dirs), _ptr(bits), C.byref(ds),
-                                            _stream(stream)))
+        fn = lib().hra_dominant_axes_noalloc if noalloc else lib().hra_dominant_axes
+        self._check(fn(self.ptr, C.byref(st), Dirs(DIRS_HEMI, n_dirs), _ptr(bits), C.byref(ds), _stream(stream)))
         out["_struct"] = ds
         return out
 
