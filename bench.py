@@ -58,11 +58,12 @@ NODE_OPS, TRI_OPS, RAY_OPS = 50, 54, 20
 # operation per lane per clock without packed FP32 (the published 157.3
 # TFLOP/s counts an FMA as two and packed FP32 twice again).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-TRAVERSAL = {"step": 1, "leaf_loop": 2}     # hra.h HRA_TRAVERSAL_*
-# the traversal loop measured faster on each workload's part (the step loop
-# on all of them)
+TRAVERSAL = {"step": 1, "leaf_loop": 2, "refill": 3}     # hra.h HRA_TRAVERSAL_*
+# the traversal loop measured faster on each workload's part: the step loop,
+# except for the paper-shape parts (150 directions), whose hemisphere cast
+# runs faster with refilled lanes (impeller 6.45 -> 5.6 ms per cast)
 DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "multiaxis_1m": "step",
-                     "batch64": "step", "serve": "step", "paper_shape": "step"}
+                     "batch64": "step", "serve": "step", "paper_shape": "refill"}
 # (rays per wave, leaf size) measured faster per workload; (64, 4) elsewhere.
 # On the 1M-triangle part 256 rays per wave and leaves of up to 8 triangles
 # cast in 29.4 ms against 32.7; on the interactive part the two are within
@@ -244,7 +245,7 @@ def main():
     ap.add_argument("--stack", type=int, default=None,
                     help="LDS stack entries per lane (default 16: nine workgroups fit in LDS)")
     ap.add_argument("--leaf", type=int, default=None, help="default: the workload's measured best")
-    ap.add_argument("--traversal", choices=("step", "leaf_loop"), default=None,
+    ap.add_argument("--traversal", choices=("step", "leaf_loop", "refill"), default=None,
                     help="traversal loop of the casts (same results; see hra.h); default: the one measured "
                          "faster for the workload's part")
     ap.add_argument("--autotune", action="store_true", help="batch64: sweep the launch shape first")

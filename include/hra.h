@@ -124,6 +124,10 @@ hra_status hra_bvh_part_info(hra_bvh *bvh, int32_t part, void *stream, hra_bvh_i
  * hierarchy; its other parts follow in the same arrays).  Synchronises. */
 hra_status hra_bvh_export(hra_bvh *bvh, void *stream, void *host_nodes, void *host_tris, int32_t *root,
                           int32_t *n_valid);
+/* Free a hierarchy (waits for nothing: the caller ends the work that reads
+ * it first).  Allowed after its context has been destroyed, so that
+ * garbage-collected handles may go in any order; every other call on a
+ * hierarchy needs its context alive. */
 void hra_bvh_release(hra_bvh *bvh);
 
 /* ----------------------------------------------------------------- samples */
@@ -199,6 +203,10 @@ hra_status hra_cast_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const h
  *     triangles of its hit leaf children (lanes stay in step on the tree). */
 #define HRA_TRAVERSAL_STEP 1
 #define HRA_TRAVERSAL_LEAF_LOOP 2
+/*   HRA_TRAVERSAL_REFILL: the step loop, with lanes whose ray has ended
+ *     taking the next rays of their work item's list (hemisphere casts; the
+ *     six-axis cast uses the step loop). */
+#define HRA_TRAVERSAL_REFILL 3
 
 typedef struct {
     int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
@@ -532,6 +540,7 @@ hra_status hra_plan_stage_ms(const hra_plan *plan, float *ms6);
 int64_t hra_plan_bytes(const hra_plan *plan);
 /* The plan's own bitmask array (valid until the next run or destroy). */
 const uint32_t *hra_plan_bits(const hra_plan *plan);
+/* Free a plan; allowed after its context has been destroyed. */
 void hra_plan_destroy(hra_plan *plan);
 
 typedef struct {

@@ -201,7 +201,8 @@ void decode_results(const StageShape &sh, const std::vector<int64_t> &count, con
 using namespace hra;
 
 struct hra_plan {
-    hra_ctx *ctx = nullptr;
+    hra_ctx *ctx = nullptr;    // valid while the context lives (destroy does not use it)
+    int32_t device = 0;        // the context's device
     hra_bvh *bvh = nullptr;
     void *ws = nullptr;        // build scratch
     void *stage = nullptr;     // stage buffers
@@ -224,7 +225,7 @@ struct hra_plan {
 
 extern "C" void hra_plan_destroy(hra_plan *P) {
     if (!P) return;
-    hipSetDevice(P->ctx->device);
+    hipSetDevice(P->device);
     if (P->own) hipStreamSynchronize(P->own);
     if (P->exec) hipGraphExecDestroy(P->exec);
     if (P->graph) hipGraphDestroy(P->graph);
@@ -254,8 +255,8 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
     if (stack != 16 && stack != 20 && stack != 24 && stack != 32)
         return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth: 16, 20, 24 or 32");
     const int trav = opts->traversal ? opts->traversal : ctx->cast_traversal;
-    if (trav != HRA_TRAVERSAL_STEP && trav != HRA_TRAVERSAL_LEAF_LOOP)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "traversal: 0, HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP");
+    if (trav != HRA_TRAVERSAL_STEP && trav != HRA_TRAVERSAL_LEAF_LOOP && trav != HRA_TRAVERSAL_REFILL)
+        return ctx->fail(HRA_ERR_INVALID_ARG, "traversal: 0, HRA_TRAVERSAL_STEP, _LEAF_LOOP or _REFILL");
     const float frac = opts->offset_frac > 0.0f ? opts->offset_frac : 1e-4f;
     if (!(frac <= 0.01f)) return ctx->fail(HRA_ERR_INVALID_ARG, "offset_frac must be in (0, 0.01]");
     hra_dirs hemi = {HRA_DIRS_HEMI_FIBONACCI, N}, ax6 = {HRA_DIRS_AXES6, 6};
@@ -289,6 +290,7 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
 
     hra_plan *P = new hra_plan();
     P->ctx = ctx;
+    P->device = ctx->device;
     P->count = count;
     if (opts->thresholds) {
         P->th = *opts->thresholds;
@@ -440,8 +442,9 @@ extern "C" hra_status hra_autotune(hra_ctx *ctx, const hra_part_request *parts, 
     if (reps < 1 || reps > 100) return ctx->fail(HRA_ERR_INVALID_ARG, "reps must be in 1..100");
     static const int RPW[3] = {64, 128, 256}, STACK[3] = {16, 24, 32}, LEAF[3] = {2, 4, 8};
     const int trav = opts->traversal ? opts->traversal : ctx->cast_traversal;
-    if (trav != HRA_TRAVERSAL_STEP && trav != HRA_TRAVERSAL_LEAF_LOOP)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "traversal must be 0, HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP");
+    if (trav != HRA_TRAVERSAL_STEP && trav != HRA_TRAVERSAL_LEAF_LOOP && trav != HRA_TRAVERSAL_REFILL)
+        return ctx->fail(HRA_ERR_INVALID_ARG,
+                         "traversal must be 0, HRA_TRAVERSAL_STEP, HRA_TRAVERSAL_LEAF_LOOP or HRA_TRAVERSAL_REFILL");
     std::vector<hra_part_result> ref(n_parts > 0 ? n_parts : 1), got(n_parts > 0 ? n_parts : 1);
     out->n_points = 0;
     out->best = -1;

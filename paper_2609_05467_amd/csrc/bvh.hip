@@ -835,6 +835,7 @@ hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int
     const int n_parts = (int)hm.size();
     hra_bvh *b = new hra_bvh();
     b->ctx = ctx;
+    b->device = ctx->device;
     b->n_parts = n_parts;
     b->n_tris = T;
     b->leaf_size = leaf;
@@ -987,7 +988,7 @@ extern "C" hra_status hra_bvh_export(hra_bvh *b, void *stream, void *host_nodes,
 
 extern "C" void hra_bvh_release(hra_bvh *b) {
     if (!b) return;
-    if (b->ctx) hipSetDevice(b->ctx->device);
+    hipSetDevice(b->device);
     for (void *p : {(void *)b->nodes, (void *)b->tris, (void *)b->leaf_pos, (void *)b->valid_rank, (void *)b->prefix,
                     (void *)b->parts}) {
         if (!p) continue;

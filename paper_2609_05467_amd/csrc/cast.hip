@@ -530,6 +530,219 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
     }
 }
 
+// Hemisphere cast with refilled lanes.  The work item's rays (one sample's
+// directions in traversal order, or `group` samples' in a row) form a list
+// behind a workgroup counter in LDS.  A lane runs the step loop above on one
+// ray at a time; when its ray ends it records the bit and goes idle, and the
+// idle lanes of a wave take the next rays of the list together once at
+// least REFILL_K of them wait (or the whole wave does).  A wave thus stops
+// waiting for its slowest ray before the next 64 start, while rays that
+// start together stay neighbours on the hemisphere.  Lanes coordinate only
+// through LDS words (the list counter and one idle count per wave, read by
+// the whole wave at the top of each iteration), never through cross-lane
+// instructions.  Each ray keeps the step loop's visit order, work counts and
+// guards (its own iteration cap), so bits and counts equal those of
+// k_cast_rows and k_cast_rows_grouped.
+constexpr int REFILL_K = 8;
+
+__device__ inline int lds_peek(int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+template <int STACK, bool STATS, bool GROUPED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GROUPED ? 7 : 8))) void k_cast_refill(CastArgs a) {
+    extern __shared__ int dyn_lds[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t item = blockIdx.x;
+    if (item >= a.n_items) return;  // the whole workgroup leaves together
+    lds_int *lds = (lds_int *)(dyn_lds + wv * (STACK * 64));
+    const CastJob J = uni_job(job_of(a, item));
+    const PartMeta &P = *J.meta;
+    const int32_t root = uni_i(P.root);
+    const int32_t n_valid = uni_i(P.n_valid);
+    const bool empty = n_valid <= 0;
+    const int32_t n_tris_alloc = uni_i(P.leaf_lo) + n_valid;
+    const int32_t N = uni_i(a.n_dirs), W = uni_i(a.W);
+    const int32_t G = GROUPED ? uni_i(a.group) : 1;
+    const int64_t s0 = (item - J.item_base) * G;
+    int32_t g_n = 1;
+    if (GROUPED) {
+        const int64_t left = J.n_samples - s0;
+        g_n = uni_i((int32_t)(left < G ? left : G));
+    }
+    const int32_t total = g_n * N;
+    uint32_t *row = (uint32_t *)(dyn_lds + 4 * STACK * 64);
+    int *ctr = dyn_lds + 4 * STACK * 64 + g_n * W;   // [0] next ray, [1 + w] idle lanes of wave w
+    for (int32_t w = threadIdx.x; w < g_n * W; w += 256) row[w] = 0u;
+    if (threadIdx.x == 0) ctr[0] = 0;
+    if (threadIdx.x < 4) ctr[1 + threadIdx.x] = 64;
+    // one sample per item: origin and frame are the workgroup's, in scalar
+    // registers
+    float uox = 0.f, uoy = 0.f, uoz = 0.f, unx = 0.f, uny = 0.f, unz = 1.f;
+    float3 ut = make_float3(1.f, 0.f, 0.f), ub = make_float3(0.f, 1.f, 0.f);
+    if (!GROUPED) {
+        uox = uni(J.origin[3 * s0]);
+        uoy = uni(J.origin[3 * s0 + 1]);
+        uoz = uni(J.origin[3 * s0 + 2]);
+        unx = uni(J.normal[3 * s0]);
+        uny = uni(J.normal[3 * s0 + 1]);
+        unz = uni(J.normal[3 * s0 + 2]);
+        float3 t0, b0;
+        onb_frame(unx, uny, unz, t0, b0);
+        ut = make_float3(uni(t0.x), uni(t0.y), uni(t0.z));
+        ub = make_float3(uni(b0.x), uni(b0.y), uni(b0.z));
+    }
+    // reciprocal of N for splitting a list position into (sample, direction)
+    const float rN = 1.0f / (float)N;
+    __syncthreads();
+    WorkCount wc;
+    if (empty) {
+        // no triangle: every ray is free
+        for (int32_t q = threadIdx.x; q < total; q += 256) {
+            int32_t g = GROUPED ? (int32_t)((float)q * rN) : 0;
+            g -= (g * N > q);
+            g += ((g + 1) * N <= q);
+            const int32_t j = q - g * N;
+            const int32_t pos = g * W * 32 + __float_as_int(a.dirs_order[j].w);
+            atomicOr(&row[pos >> 5], 1u << (pos & 31));
+        }
+    } else {
+        const float ZERO = 0.0f;
+        const int64_t cap = 2 * (int64_t)J.n_nodes_alloc + (int64_t)n_tris_alloc + 64;
+        const uint32_t iter_cap = cap < 0xffffffffll ? (uint32_t)cap : 0xffffffffu;
+        const uint32_t last_node = (uint32_t)J.n_nodes_alloc - 1u, last_tri = (uint32_t)max(n_tris_alloc, 1) - 1u;
+        const bool root_leaf = is_leaf(root);
+        bool active = false;
+        float ox = uox, oy = uoy, oz = uoz, dx = ZERO, dy = ZERO, dz = ZERO, ix = ZERO, iy = ZERO, iz = ZERO, kd = ZERO;
+        int32_t node = -1, sp = 0, ti = 0, tn = 0, pos = 0;
+        uint32_t iter = 0;
+        int spill[SPILL];
+        while (true) {
+            const int n_idle = lds_peek(ctr + 1 + wv);
+            const int nxt = lds_peek(ctr);
+            if (nxt >= total && n_idle == 64) break;
+            if (n_idle >= REFILL_K && nxt < total && !active) {
+                const int32_t q = atomicAdd(ctr, 1);
+                if (q < total) {
+                    int32_t g = 0;
+                    float px = uox, py = uoy, pz = uoz, nx = unx, ny = uny, nz = unz;
+                    float3 t = ut, b = ub;
+                    if (GROUPED) {
+                        g = (int32_t)((float)q * rN);
+                        g -= (g * N > q);
+                        g += ((g + 1) * N <= q);
+                        const int64_t smp = s0 + g;
+                        px = J.origin[3 * smp];
+                        py = J.origin[3 * smp + 1];
+                        pz = J.origin[3 * smp + 2];
+                        nx = J.normal[3 * smp];
+                        ny = J.normal[3 * smp + 1];
+                        nz = J.normal[3 * smp + 2];
+                        onb_frame(nx, ny, nz, t, b);
+                    }
+                    const int32_t j = q - g * N;
+                    const float4 l = a.dirs_order[j];
+                    pos = g * W * 32 + __float_as_int(l.w);
+                    const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+                    if (GROUPED) {
+                        ox = px;
+                        oy = py;
+                        oz = pz;
+                    }
+                    dx = d.x;
+                    dy = d.y;
+                    dz = d.z;
+                    kd = (6.0f * TRI_K) * fmaxf(fmaxf(fabsf(dx), fabsf(dy)), fabsf(dz));
+                    ix = safe_rcp(dx);
+                    iy = safe_rcp(dy);
+                    iz = safe_rcp(dz);
+                    // a root that is a leaf: its triangles first, no node
+                    node = root_leaf ? -1 : root;
+                    ti = root_leaf ? leaf_first(root) : 0;
+                    tn = root_leaf ? leaf_count(root) : 0;
+                    sp = 0;
+                    iter = 0;
+                    active = true;
+                    atomicSub(ctr + 1 + wv, 1);
+                }
+            }
+            if (active) {
+                // one sample per item: the origin stays in scalar registers
+                const float rox = GROUPED ? ox : uox, roy = GROUPED ? oy : uoy, roz = GROUPED ? oz : uoz;
+                bool hit = false, done = false, bad = false;
+                asm volatile("" : "+v"(tn));
+                if (tn > 0) {
+                    bad = (uint32_t)ti > last_tri;
+                    const float4 *tp = J.tris + 3 * (uint64_t)min((uint32_t)ti, last_tri);
+                    if (STATS) ++wc.tris;
+                    hit = tri_hit(rox, roy, roz, dx, dy, dz, kd, gload_f4(tp), gload_f4(tp + 1), gload_f4(tp + 2));
+                    ++ti;
+                    --tn;
+                } else {
+                    bool visit = true;
+                    if (node < 0) {
+                        if (sp == 0) {
+                            done = true;
+                            visit = false;
+                        } else {
+                            --sp;
+                            int32_t itm;
+                            if (sp < STACK) itm = lds[sp * 64 + lane];
+                            else itm = spill[sp - STACK];
+                            if (is_leaf(itm)) {
+                                ti = leaf_first(itm);
+                                tn = leaf_count(itm);
+                                visit = false;
+                            } else {
+                                node = itm;
+                            }
+                        }
+                    }
+                    if (visit) {
+                        bad = (uint32_t)node > last_node;
+                        const Node *nd = J.nodes + min((uint32_t)node, last_node);
+                        if (STATS) ++wc.nodes;
+                        const float4 A = gload_f4(&nd->a), B = gload_f4(&nd->b), C = gload_f4(&nd->c);
+                        const int4 D = gload_i4(&nd->d);
+                        float t0, t1;
+                        const bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, rox, roy, roz, ix, iy, iz, t0);
+                        const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, rox, roy, roz, ix, iy, iz, t1);
+                        const int32_t c0 = D.x, c1 = D.y;
+                        const bool l0 = h0 && is_leaf(c0), l1 = h1 && is_leaf(c1);
+                        const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
+                        if (l0 || l1) {
+                            const int32_t lc = l0 ? c0 : c1;
+                            ti = leaf_first(lc);
+                            tn = leaf_count(lc);
+                        }
+                        const bool push = (l0 && l1) || (g0 && g1);
+                        const int32_t pv = (l0 && l1) ? c1 : (t0 <= t1 ? c1 : c0);
+                        node = (g0 && g1) ? (t0 <= t1 ? c0 : c1) : (g0 ? c0 : (g1 ? c1 : -1));
+                        if (push) {
+                            if (sp < STACK) lds[sp * 64 + lane] = pv;
+                            else if (sp < STACK + SPILL) spill[sp - STACK] = pv;
+                            else bad = true;
+                            ++sp;
+                        }
+                    }
+                }
+                ++iter;
+                bad = bad || iter > iter_cap;
+                if (hit || done || bad) {
+                    if (!(hit || bad)) atomicOr(&row[pos >> 5], 1u << (pos & 31));
+                    if (bad) atomicOr(a.err, ERR_STACK);
+                    active = false;
+                    atomicAdd(ctr + 1 + wv, 1);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int32_t w = threadIdx.x; w < g_n * W; w += 256) J.bits[s0 * W + w] = row[w];
+    if (STATS) {
+        atomicAdd(a.work, (unsigned long long)wc.nodes);
+        atomicAdd(a.work + 1, (unsigned long long)wc.tris);
+    }
+}
+
 // Six-axis cast.  One work item = AX_PER_WAVE samples x 6 world axes on the
 // 60 first lanes of a wavefront.  A ray whose axis points into the material
 // (n . D < 0) is not cast.  The ballot follows the traversal directly and
@@ -581,6 +794,16 @@ __global__ void k_popcount_rows(const uint32_t *bits, int64_t n, int32_t W, uint
     counts[s] = c;
 }
 
+template <int STACK, bool STATS>
+static hipError_t launch_refill(const CastArgs &args, hipStream_t s) {
+    const int64_t blocks = args.n_items;
+    if (blocks >= ((int64_t)1 << 31) || args.group > MAX_GROUP) return hipErrorInvalidValue;
+    const size_t lds = sizeof(int) * (4 * STACK * 64 + (size_t)args.W * (args.group > 1 ? args.group : 1) + 8);
+    if (args.group > 1) k_cast_refill<STACK, STATS, true><<<(unsigned)blocks, 256, lds, s>>>(args);
+    else k_cast_refill<STACK, STATS, false><<<(unsigned)blocks, 256, lds, s>>>(args);
+    return hipGetLastError();
+}
+
 template <int RPW, int STACK, bool STATS, bool STEP>
 static hipError_t launch_cast(const CastArgs &args, hipStream_t s) {
     if (args.kind == 1) {
@@ -622,6 +845,16 @@ static hipError_t launch_mode(const CastArgs &a, int rpw, int stack, bool stats,
 }
 
 hipError_t launch_cast_any(const CastArgs &a, int rpw, int stack, int traversal, bool stats, hipStream_t s) {
+    if (traversal == HRA_TRAVERSAL_REFILL && a.kind == 0) {
+        // the hemisphere cast with refilled lanes (the six-axis cast keeps
+        // the step loop: ten samples per wave, no list to refill from)
+        switch (stack) {
+            case 16: return stats ? launch_refill<16, true>(a, s) : launch_refill<16, false>(a, s);
+            case 20: return stats ? launch_refill<20, true>(a, s) : launch_refill<20, false>(a, s);
+            case 32: return stats ? launch_refill<32, true>(a, s) : launch_refill<32, false>(a, s);
+            default: return stats ? launch_refill<24, true>(a, s) : launch_refill<24, false>(a, s);
+        }
+    }
     return traversal == HRA_TRAVERSAL_LEAF_LOOP ? launch_mode<false>(a, rpw, stack, stats, s)
                                                 : launch_mode<true>(a, rpw, stack, stats, s);
 }
@@ -684,8 +917,10 @@ extern "C" hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *c
     if (cfg->stack_depth != 16 && cfg->stack_depth != 20 && cfg->stack_depth != 24 && cfg->stack_depth != 32)
         return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth must be 16, 20, 24 or 32");
     if (cfg->leaf_size < 0 || cfg->leaf_size > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 0..8");
-    if (cfg->traversal != 0 && cfg->traversal != HRA_TRAVERSAL_STEP && cfg->traversal != HRA_TRAVERSAL_LEAF_LOOP)
-        return ctx->fail(HRA_ERR_INVALID_ARG, "traversal must be 0, HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP");
+    if (cfg->traversal != 0 && cfg->traversal != HRA_TRAVERSAL_STEP && cfg->traversal != HRA_TRAVERSAL_LEAF_LOOP &&
+        cfg->traversal != HRA_TRAVERSAL_REFILL)
+        return ctx->fail(HRA_ERR_INVALID_ARG,
+                         "traversal must be 0, HRA_TRAVERSAL_STEP, HRA_TRAVERSAL_LEAF_LOOP or HRA_TRAVERSAL_REFILL");
     if (cfg->samples_per_group < 0 || cfg->samples_per_group > MAX_GROUP)
         return ctx->fail(HRA_ERR_INVALID_ARG, "samples_per_group must be in 0..16");
     ctx->cast_rpw = cfg->rays_per_wave;

@@ -122,7 +122,8 @@ struct hra_ctx {
 };
 
 struct hra_bvh {
-    hra_ctx *ctx = nullptr;
+    hra_ctx *ctx = nullptr;          // valid while the context lives (release does not use it)
+    int32_t device = 0;              // the context's device, for release after the context has gone
     int32_t n_parts = 0;
     int64_t n_tris = 0;              // all parts
     int32_t leaf_size = 4;

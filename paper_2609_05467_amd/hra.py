@@ -21,7 +21,7 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "BA
 SAMPLE_AREA, SAMPLE_CENTROID = 0, 1
 SERVE_CONTINUOUS, SERVE_PLAIN = 0, 1
 DIRS_HEMI, DIRS_AXES6 = 0, 1
-TRAVERSAL_STEP, TRAVERSAL_LEAF_LOOP = 1, 2
+TRAVERSAL_STEP, TRAVERSAL_LEAF_LOOP, TRAVERSAL_REFILL = 1, 2, 3
 CLASS_VIABLE, CLASS_OVER, CLASS_INACCESSIBLE, CLASS_FIXTURE = 0, 1, 2, 3
 
 

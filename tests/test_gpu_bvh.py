@@ -68,3 +68,24 @@ def test_bvh_interactive_size_tight(ctx):
     for k in range(3):
         n2, t2, r2, _ = _export(ctx, m, 4)
         assert r2 == root and np.array_equal(n2.view(np.uint32), nodes.view(np.uint32)), k
+
+
+def test_release_after_context_destroyed():
+    """Handles may be freed after their context (Python collects them in any
+    order): releasing a hierarchy and a plan then must leave no error behind
+    for the next context's calls."""
+    from paper_2609_05467_amd import hra
+    m = P.config1_part()
+    c1 = hra.Context(0)
+    b = c1.build_bvh(m.verts, m.tris)
+    b.info()
+    pl = c1.plan([{"verts": m.verts, "tris": m.tris, "n_samples": 100, "seed": 1, "tool_length": 50.0}], 256)
+    pl.run()
+    c1.close()
+    b.release()
+    pl.destroy()
+    c2 = hra.Context(0)
+    b2 = c2.build_bvh(m.verts, m.tris)
+    assert b2.info().n_tris == m.n_tris
+    b2.release()
+    c2.close()

@@ -21,9 +21,9 @@ from synth import parts as P
 
 pytestmark = pytest.mark.gpu
 
-# benchmark launch shapes (rays per wave, leaf size) per workload
-SHAPE = {"interactive_200k": (64, 4), "multiaxis_1m": (256, 8), "batch64": (64, 4),
-         "paper_housing_22k": (64, 4), "paper_impeller_124k": (64, 4)}
+# benchmark launch shapes (rays per wave, leaf size, traversal loop) per workload
+SHAPE = {"interactive_200k": (64, 4, "step"), "multiaxis_1m": (256, 8, "step"), "batch64": (64, 4, "step"),
+         "paper_housing_22k": (64, 4, "refill"), "paper_impeller_124k": (64, 4, "refill")}
 
 
 def _say(*a):
@@ -133,8 +133,8 @@ def _single_part(ctx, orc, name, rec_all):
     N = rec_all["n_dirs"]
     m = P.workload_parts(name)[0]
     assert FS.array_sha256(m.verts, m.tris) == rec["mesh_sha256"], "part generator changed since the records"
-    rpw, leaf = SHAPE[name]
-    ctx.set_cast_config(rpw, 16, 0, hra.TRAVERSAL_STEP)
+    rpw, leaf, trav = SHAPE[name]
+    ctx.set_cast_config(rpw, 16, 0, {"step": hra.TRAVERSAL_STEP, "refill": hra.TRAVERSAL_REFILL}[trav])
     b = ctx.build_bvh(m.verts, m.tris, leaf_size=leaf)
     smp = rec["samples"]
     if smp["mode"] == "area":

@@ -169,7 +169,7 @@ def test_cast_configs_identical(ctx, orc, cfg1):
     m, b = cfg1
     s = ctx.sample_surface(b, 300, 8)
     ref = ref6 = None
-    for trav in (hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP):
+    for trav in (hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP, hra.TRAVERSAL_REFILL):
         for rpw in (64, 128, 256):
             for st in (16, 20, 24, 32):
                 _say("config", trav, rpw, st)
@@ -182,12 +182,12 @@ def test_cast_configs_identical(ctx, orc, cfg1):
                 assert np.array_equal(g, ref), (trav, rpw, st)
                 assert np.array_equal(g6, ref6), (trav, rpw, st)
     works = []
-    for trav in (hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP):
+    for trav in (hra.TRAVERSAL_STEP, hra.TRAVERSAL_LEAF_LOOP, hra.TRAVERSAL_REFILL):
         ctx.set_cast_config(64, 20, 0, trav)
         wb, nf, nt = ctx.cast_work(b, s, 1000)
         assert np.array_equal(_u32(wb), ref)
         works.append((nf, nt))
-    assert works[0] == works[1] and works[0][0] > 0
+    assert works[0] == works[1] == works[2] and works[0][0] > 0
     ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP)
 
 
@@ -204,12 +204,13 @@ def test_cast_grouped_matches_one_sample_per_workgroup(ctx, orc, cfg1, N):
     ref, _ = ctx.cast(b, s, N)
     ref = _u32(ref)
     _, nf1, nt1 = ctx.cast_work(b, s, N)
-    for g in (0, 2, 3, 5, 16):
-        ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP, g)
-        got, cnt = ctx.cast(b, s, N)
-        assert np.array_equal(_u32(got), ref), g
-        wb, nf, nt = ctx.cast_work(b, s, N)
-        assert np.array_equal(_u32(wb), ref) and (nf, nt) == (nf1, nt1), g
+    for trav in (hra.TRAVERSAL_STEP, hra.TRAVERSAL_REFILL):
+        for g in (0, 1, 2, 3, 5, 16):
+            ctx.set_cast_config(64, 16, 0, trav, g)
+            got, cnt = ctx.cast(b, s, N)
+            assert np.array_equal(_u32(got), ref), (trav, g)
+            wb, nf, nt = ctx.cast_work(b, s, N)
+            assert np.array_equal(_u32(wb), ref) and (nf, nt) == (nf1, nt1), (trav, g)
     ctx.set_cast_config(64, 16, 0, hra.TRAVERSAL_STEP, 0)
     _cast_parity(ctx, orc, m, b, 211, N, 12, s=s)
 
