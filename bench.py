@@ -54,9 +54,24 @@ NODE_BYTES, TRI_BYTES = 64, 48  # one interior-node record, one leaf triangle
 # compares, 10); per ray 20 (rotation 9, three guarded reciprocals 9, the
 # bound factor 2).
 NODE_OPS, TRI_OPS, RAY_OPS = 50, 54, 20
+# Floating-point operations of the hemisphere cast, counted from its source
+# with a fused multiply-add as two and a min, max, compare or reciprocal as
+# one (sign flips, absolute values and selects not counted): per node visit
+# two slab tests of 25 (six differences, six products, eleven min/max, the
+# widening product, the compare) and the near-far compare; per triangle test
+# 71 (translated vertex and edges 9, largest component 9, the squared and
+# bound products 2, cross products P and Q 18, U, V, det and Tn 20, the
+# third edge 2, its bound 1, the plane bound 2, compares 8); per ray 24
+# (rotation 15, three guarded reciprocals 6, the bound factor 3).
+NODE_FLOPS, TRI_FLOPS, RAY_FLOPS = 51, 71, 24
+# MI355X published vector FP32 peak (counts an FMA as two flops and packed
+# FP32 as two lanes; this build issues no packed FP32, so 78.6 TFLOP/s is
+# the most it can reach with FMAs only, and 39.3 T/s with single operations)
+FP32_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_FMA_TFLOPS = 78.6
 # VALU lane operations per second: 256 CUs x 64 lanes x 2.4 GHz, one
-# operation per lane per clock without packed FP32 (the published 157.3
-# TFLOP/s counts an FMA as two and packed FP32 twice again).
+# operation per lane per clock without packed FP32 (the issue limit of the
+# instructions this build emits).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 TRAVERSAL = {"step": 1, "leaf_loop": 2, "refill": 3}     # hra.h HRA_TRAVERSAL_*
 # the traversal loop measured faster on each workload's part: the step loop,
@@ -71,20 +86,33 @@ DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "mu
 DEFAULT_SHAPE = {"multiaxis_1m": (256, 8)}
 
 
-def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit):
-    """ALU roofline of the cast kernel (the bound: its node and triangle data
-    live in L2 and the MALL, so HBM is not), with the HBM view beside it."""
+def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit, kernel="k_cast_rows"):
+    """Roofline of the hemisphere cast kernel against the published FP32
+    peak (the kernel is bound by vector-ALU issue: its node and triangle data
+    live in L2 and the MALL), with the issue-rate and cache-served byte views
+    beside it.  nodes, tests: node visits and triangle tests over `rays`
+    (the instrumented build of the same kernel)."""
+    flops_per_ray = (nodes * NODE_FLOPS + tests * TRI_FLOPS) / rays + RAY_FLOPS
     ops_per_ray = (nodes * NODE_OPS + tests * TRI_OPS) / rays + RAY_OPS
     bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
     t = cast_ms * 1e-3
-    achieved = ops_per_ray * rays / t / 1e12
+    achieved = flops_per_ray * rays / t / 1e12
+    ops = ops_per_ray * rays / t / 1e12
     gbs = bytes_per_ray * rays / t / 1e9
-    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
-            "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic, "kernel": "k_cast_rows",
-            "avg_launch_ms": cast_ms, "algorithmic_ops": ops_per_ray * rays, "ops_per_ray": ops_per_ray,
-            "hbm_view": {"algorithmic_bytes": bytes_per_ray * rays, "bytes_per_ray": bytes_per_ray,
-                         "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
-                         "measured_traffic_bytes": traffic, "l2_hit_rate": l2_hit}}
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel,
+            "avg_launch_ms": cast_ms, "flops_per_launch": flops_per_ray * rays, "flops_per_ray": flops_per_ray,
+            "frac_of_unpacked_fma_peak": achieved / FP32_UNPACKED_FMA_TFLOPS,
+            "issue_view": {"ops_per_ray": ops_per_ray, "achieved_tops": ops, "peak_tops": ALU_PEAK_TOPS,
+                           "frac": ops / ALU_PEAK_TOPS,
+                           "note": "FP32 operations as issued (no packed FP32, FMA as one) against "
+                                   "256 CUs x 64 lanes x 2.4 GHz"},
+            "cache_served_bytes_view": {"algorithmic_bytes": bytes_per_ray * rays, "bytes_per_ray": bytes_per_ray,
+                                        "achieved_gbs": gbs, "hbm_peak_gbs": HBM_PEAK_GBS,
+                                        "ratio_to_hbm_peak": gbs / HBM_PEAK_GBS,
+                                        "measured_hbm_traffic_bytes": traffic, "l2_hit_rate": l2_hit,
+                                        "note": "node and triangle bytes per ray x rays / time; above the HBM "
+                                                "peak because L2 and the MALL serve them"}}
 
 
 # Tool-aware cast (hra_cast_tool): FP32 operations per node visit (two slab
@@ -191,28 +219,66 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(mesh, samples_np, n_dirs, budget_s=15.0):
-    """The oracle (brute force, FP64 decisions) on a bounded sample of the
-    same workload: the first rows of the same samples, all directions, grown
-    until the run takes about budget_s of wall time."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _popcount(a):
+    import numpy as np
+    return int(np.unpackbits(np.ascontiguousarray(a).view(np.uint8)).sum())
+
+
+def cpu_baseline(mesh, samples_np, n_dirs, gpu_bits, budget_s=40.0, brute=False):
+    """The CPU oracle on the same samples and directions, timed on the host
+    cores: its padded-hierarchy cast (bit-identical to brute force wherever
+    brute force decides a ray), or brute force itself with brute=True.  All
+    rows when the whole run fits budget_s (estimated from a first slice),
+    else the leading rows that do.  Every GPU row it covers is compared
+    with it: the rays that differ outside the oracle's grazing set (must be
+    0) and the grazing share."""
+    import numpy as np
     from oracle import oracle as orc
     threads = orc.max_threads()
     dirs = orc.fibonacci_dirs(n_dirs)
-    rows = max(1, threads)
-    sub = {k: v[:rows] for k, v in samples_np.items()}
-    t0 = time.perf_counter()
-    orc.cast(mesh.verts, mesh.tris, sub, dirs, threads=threads)
-    dt = time.perf_counter() - t0
-    if dt < 0.6 * budget_s:
-        rows = int(min(len(samples_np["origin"]), rows * budget_s / max(dt, 1e-3)))
-        rows = max(threads, (rows // threads) * threads)
-        sub = {k: v[:rows] for k, v in samples_np.items()}
+    S = len(samples_np["origin"])
+    if brute:
+        def cast(r0, r1):
+            return orc.cast(mesh.verts, mesh.tris, samples_np, dirs, s0=r0, s1=r1, threads=threads)
+        t_build = 0.0
+    else:
         t0 = time.perf_counter()
-        orc.cast(mesh.verts, mesh.tris, sub, dirs, threads=threads)
-        dt = time.perf_counter() - t0
-    return {"value": rows * n_dirs / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows} samples x {n_dirs} directions of the same part ({mesh.n_tris} triangles), brute force",
-            "seconds": round(dt, 3)}
+        h = orc.BVHCast(mesh.verts, mesh.tris)
+        t_build = time.perf_counter() - t0
+
+        def cast(r0, r1):
+            return h.cast(samples_np, dirs, s0=r0, s1=r1, threads=threads)
+    probe = min(S, max(4 * threads, S // 100))
+    t0 = time.perf_counter()
+    cast(0, probe)
+    tp = time.perf_counter() - t0
+    rows = S if tp * S / probe <= budget_s else max(probe, int(probe * budget_s / max(tp, 1e-6)))
+    t0 = time.perf_counter()
+    bits, gr, _ = cast(0, rows)
+    dt = time.perf_counter() - t0
+    n_diff = _popcount((np.asarray(gpu_bits[:rows]) ^ bits) & ~gr)
+    n_gr = _popcount(gr)
+    rays = rows * n_dirs
+    kind = "brute force (every ray against every triangle)" if brute else \
+        "padded median-split hierarchy (FP64 decisions, bit-identical to brute force where it decides)"
+    base = {"value": rays / dt, "unit": "rays/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{'all ' if rows == S else 'the first '}{rows} of {S} samples x {n_dirs} directions "
+                      f"({rays} rays) of the same part ({mesh.n_tris} triangles); {kind}",
+            "seconds": round(dt, 3), "hierarchy_build_s": round(t_build, 3)}
+    parity = {"rows_compared": rows, "rays_compared": rays, "rays_differing_outside_grazing": n_diff,
+              "grazing_rays": n_gr, "grazing_fraction": n_gr / rays if rays else 0.0,
+              "status": "equal" if n_diff == 0 else "DIFFERENT", "oracle": "brute force" if brute else "padded hierarchy"}
+    return base, parity
 
 
 def measured_traffic(workload):
@@ -249,8 +315,8 @@ def main():
                     help="traversal loop of the casts (same results; see hra.h); default: the one measured "
                          "faster for the workload's part")
     ap.add_argument("--autotune", action="store_true", help="batch64: sweep the launch shape first")
-    ap.add_argument("--rates", default="20,100,200", help="serve: arrival rates (requests/s)")
-    ap.add_argument("--requests", type=int, default=600, help="serve: requests per rate and mode")
+    ap.add_argument("--rates", default="100,500,1000", help="serve: arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate and mode")
     ap.add_argument("--budget-gib", type=float, default=200.0, help="serve: device memory budget")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes generating the batch parts (before any GPU work)")
@@ -272,8 +338,8 @@ def main():
     if args.leaf is None:
         args.leaf = leaf0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards by part and "
-              "by samples with no exchange, see the design notes)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path would shard by part "
+              "and by samples, with no bulk exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch64":
@@ -285,13 +351,51 @@ def main():
     extras = None
     if not args.no_extras and args.workload == "interactive_200k":
         extras = gen_batch(args)   # before any GPU work (the generator forks)
+    out = run_single(args, args.workload, cpu_budget_s=40.0, frame=not args.no_frame,
+                     brute=args.workload == "single_block_1k5")
+    if extras is not None:
+        out["workloads"] = {}
+        for name in ("single_block_1k5", "multiaxis_1m"):
+            log(f"[bench] extra workload {name}")
+            w = run_single(workload_args(args, name), name, cpu_budget_s=12.0, frame=False,
+                           brute=name == "single_block_1k5")
+            out["workloads"][name] = {k: w[k] for k in ("value", "unit", "ms_per_step", "steps", "warmup", "config",
+                                                        "parts_per_s", "stage_ms", "cast_rays_per_s", "bvh",
+                                                        "work_per_ray", "result", "roofline", "cpu_baseline",
+                                                        "parity") if k in w}
+        meshes, counts = extras
+        log("[bench] 64-part batch against the plain per-part path")
+        b = batch_compare(args, meshes, counts, 2)
+        out["batch64"] = {k: b[k] for k in ("config", "batched_graph", "batched_eager", "plain", "speedup_vs_plain",
+                                            "results_identical", "stage_ms")}
+        log("[bench] serving: served against plain at 100, 500 and 1000 requests/s, and an eviction run")
+        out["serve"] = serve_extra(args, meshes, counts)
+    print(json.dumps(out), flush=True)
 
+
+def workload_args(args, name):
+    """Launch shape of a workload: its measured-best rays per wave, leaf size
+    and traversal loop unless given on the command line for the main one."""
+    import copy
+    a = copy.copy(args)
+    a.workload = name
+    a.rays_per_wave, a.leaf = DEFAULT_SHAPE.get(name, (64, 4))
+    a.traversal = DEFAULT_TRAVERSAL[name]
+    a.stack = 16
+    return a
+
+
+def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
+    """One part per step (build, sample, hemisphere cast, statistics and
+    class, six-axis cast, setups), timed over args.steps steps with the mesh
+    resident; then the work counts, the roofline, and the CPU oracle over the
+    same samples with parity of every row it covers."""
     import numpy as np
     import torch
     from paper_2609_05467_amd import hra
     from synth import parts
 
-    part_name, S, N = WORKLOADS[args.workload]
+    part_name, S, N = WORKLOADS[workload]
     log(f"[bench] generating {part_name}")
     mesh = parts.workload_parts(part_name)[0]
     ctx = hra.Context(0)
@@ -304,7 +408,6 @@ def main():
     bits = torch.empty((S, W), dtype=torch.int32, device=dev)
     bits6 = torch.empty((S, 1), dtype=torch.int32, device=dev)
     samples = ctx.alloc_samples(S)
-    stream = torch.cuda.current_stream()
 
     ev = {k: [] for k in ("build", "sample", "cast", "stats", "axes", "setups")}
 
@@ -337,7 +440,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log(f"[bench] {mesh.n_tris} triangles, {S} samples x {N} directions; warmup {args.warmup}")
+    log(f"[bench] {workload}: {mesh.n_tris} triangles, {S} samples x {N} directions; warmup {args.warmup}")
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -350,6 +453,7 @@ def main():
     ms = dt / args.steps * 1e3
     rays = S * N
     value = rays * args.steps / dt
+    gpu_bits = bits.cpu().numpy().view(np.uint32)
 
     # traversal work per ray (instrumented build of the same kernel, outside the timed region)
     bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
@@ -361,7 +465,7 @@ def main():
     cast_ms = float(np.mean(ev["cast"]))
     samples_np = {k: v.cpu().numpy() for k, v in samples.items()}
     bvh.release()
-    traffic, l2_hit = measured_traffic(args.workload)
+    traffic, l2_hit = measured_traffic(workload)
 
     out = {
         "metric": "any-hit hemisphere rays/s",
@@ -376,7 +480,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "triangles": mesh.n_tris, "samples": S, "directions": N,
+        "config": {"workload": workload, "triangles": mesh.n_tris, "samples": S, "directions": N,
                    "rays_per_step": rays, "leaf_size": args.leaf, "rays_per_wave": args.rays_per_wave,
                    "stack_depth": args.stack, "traversal": args.traversal, "tool_length_mm": args.tool_length},
         "parts_per_s": args.steps / dt,
@@ -390,24 +494,15 @@ def main():
         "roofline": roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit),
     }
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(mesh, samples_np, N)
-    if not args.no_frame:
+        log(f"[bench] CPU oracle on the same samples ({'brute force' if brute else 'padded hierarchy'})")
+        out["cpu_baseline"], out["parity"] = cpu_baseline(mesh, samples_np, N, gpu_bits, cpu_budget_s, brute)
+        log(f"[bench]   {out['parity']['rows_compared']} rows: {out['parity']['status']}, grazing "
+            f"{out['parity']['grazing_rays']} ({out['parity']['grazing_fraction']:.2e})")
+    if frame:
         log("[bench] canonical frame of the part")
         out["frame"] = frame_extra(ctx, verts, tris, mesh, oracle=not args.no_cpu_baseline)
     ctx.close()
-    if extras is not None:
-        meshes, counts = extras
-        log("[bench] 64-part batch against the plain per-part path")
-        b = batch_compare(args, meshes, counts, 2)
-        out["batch64"] = {k: b[k] for k in ("config", "batched_graph", "batched_eager", "plain", "speedup_vs_plain",
-                                            "results_identical", "stage_ms")}
-        log("[bench] serving at 100 requests/s, served against plain")
-        sv = serve_compare(args, meshes, counts, [100.0], 300)[0]
-        out["serve"] = {"rate_per_s": sv["rate"], "requests": 300, "popularity": "zipf 1.1 over the 64-part pool",
-                        "served": sv["served"], "plain": sv["plain"],
-                        "p99_ratio_plain_over_served": sv["plain"]["p99_ms"] / sv["served"]["p99_ms"]}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_paper_shape(args):
@@ -502,9 +597,12 @@ def run_paper_shape(args):
             "tool": tool,
         }
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline (housing part)")
+        import numpy as np
+        log("[bench] CPU oracle on the housing part's samples")
         p = per[0]
-        out["cpu_baseline"] = cpu_baseline(p["mesh"], {k: x.cpu().numpy() for k, x in p["samples"].items()}, N)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(
+            p["mesh"], {k: x.cpu().numpy() for k, x in p["samples"].items()}, N,
+            p["bits"].cpu().numpy().view(np.uint32), 30.0)
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -700,6 +798,43 @@ def run_serve(args):
         "rates": out_rates,
     }
     print(json.dumps(out), flush=True)
+
+
+SERVE_RATES = (100.0, 500.0, 1000.0)   # requests/s; plain mode keeps up with about 270 parts/s
+SERVE_REQUESTS = 2000
+EVICT_BUDGET_GIB = 0.25   # below the pool's ~0.7 GB of hierarchies, above its largest request
+
+
+def serve_extra(args, meshes, counts):
+    """Served against plain at three arrival rates, the upper two past plain
+    mode's capacity, 2000 requests each; then the served mode under a small
+    budget (256 MiB, below the ~0.7 GB the pool's hierarchies take), which
+    forces hierarchies out of residency (LRU)."""
+    import numpy as np
+    rates = serve_compare(args, meshes, counts, list(SERVE_RATES), SERVE_REQUESTS)
+    from paper_2609_05467_amd import hra
+    N = WORKLOADS["serve"][2]
+    import torch
+    pool = [(torch.from_numpy(m.verts).pin_memory(), torch.from_numpy(m.tris).pin_memory()) for m in meshes]
+    rng = np.random.default_rng(55)
+    zipf = 1.0 / np.arange(1, len(meshes) + 1) ** 1.1
+    zipf /= zipf.sum()
+    order = rng.permutation(len(meshes))
+    lam = 500.0
+    gaps = rng.exponential(1.0 / lam, SERVE_REQUESTS)
+    ta = np.cumsum(gaps) - gaps[0]
+    ks = order[rng.choice(len(meshes), SERVE_REQUESTS, p=zipf)]
+    schedule = [(float(t), int(k), 9000 + i) for i, (t, k) in enumerate(zip(ta, ks))]
+    log(f"[bench] eviction run: {lam}/s, {SERVE_REQUESTS} requests, {EVICT_BUDGET_GIB} GiB budget")
+    recs, st = serve_run(hra, pool, counts, schedule, N, hra.SERVE_CONTINUOUS, int(EVICT_BUDGET_GIB * 2 ** 30),
+                         args.tool_length)
+    ev = serve_summary(recs, N, counts, schedule)
+    ev.update({"rate": lam, "budget_gib": EVICT_BUDGET_GIB, "builds": st["builds"], "evictions": st["evictions"],
+               "peak_used_bytes": st["peak_used_bytes"]})
+    log(f"[bench]   p50 {ev['p50_ms']:.2f} ms p99 {ev['p99_ms']:.2f} ms {ev['parts_per_s']:.1f} parts/s, "
+        f"{st['evictions']} evictions")
+    return {"popularity": "zipf 1.1 over the 64-part pool", "requests_per_rate": SERVE_REQUESTS,
+            "budget_gib": args.budget_gib, "rates": rates, "eviction_run": ev}
 
 
 def serve_compare(args, meshes, counts, rates, n_requests):
