@@ -884,50 +884,21 @@ double orc_tool_distance(const double *v9, const double *c, const double *u) {
     return best;
 }
 
-/* distance between the segments [p, q] and [a, b]: an end point of one to
- * the other segment, or their common perpendicular when its feet fall inside
- * both */
-static double segment_segment(const double *p, const double *q, const double *a, const double *b) {
-    double best = seg_point(p, a, b), d;
-    if ((d = seg_point(q, a, b)) < best) best = d;
-    if ((d = seg_point(a, p, q)) < best) best = d;
-    if ((d = seg_point(b, p, q)) < best) best = d;
-    double f[3], e[3], w[3];
-    for (int k = 0; k < 3; ++k) { f[k] = q[k] - p[k]; e[k] = b[k] - a[k]; w[k] = p[k] - a[k]; }
-    const double ff = dot3(f, f), fe = dot3(f, e), ee = dot3(e, e), fw = dot3(f, w), ew = dot3(e, w);
-    const double den = ff * ee - fe * fe;
-    if (den > 1e-300 * (ff * ee > 1.0 ? ff * ee : 1.0)) {
-        const double s = (fe * ew - ee * fw) / den, t = (ff * ew - fe * fw) / den;
-        if (s > 0.0 && s < 1.0 && t > 0.0 && t < 1.0) {
-            double x[3];
-            for (int k = 0; k < 3; ++k) x[k] = (p[k] + s * f[k]) - (a[k] + t * e[k]);
-            d = sqrt(dot3(x, x));
-            if (d < best) best = d;
-        }
-    }
-    return best;
-}
-
 /* Distances of a ball-end tool with a holder (Section 3.3 names tool reach;
- * the holder envelope is this library's extension): the cutter is the
- * segment c + t u, 0 <= t <= len; the holder the half-line from h = c + len u
- * along u.  out[0] = distance from the cutter segment to the triangle (0 when
- * the segment crosses it: the half-lines from c along u and from h along -u
- * both meet it), out[1] = distance from the holder half-line. */
-void orc_tool_holder_distances(const double *v9, const double *c, const double *u, double len, double *out) {
-    double v[3][3], h[3], mu[3];
-    memcpy(v, v9, sizeof(v));
-    for (int k = 0; k < 3; ++k) { h[k] = c[k] + len * u[k]; mu[k] = -u[k]; }
-    double dc = 0.0;
-    if (!(ray_meets(c, u, v) && ray_meets(h, mu, v))) {
-        dc = tri_point(c, v);
-        double d = tri_point(h, v);
-        if (d < dc) dc = d;
-        for (int k = 0; k < 3; ++k)
-            if ((d = segment_segment(c, h, v[k], v[(k + 1) % 3])) < dc) dc = d;
-    }
-    out[0] = dc;
-    out[1] = orc_tool_distance(v9, h, u);
+ * the holder is this library's extension).  The cutter and its shank are the
+ * plain tool, every point within r of the half-line from the tip centre c
+ * along u; the holder is every point within R of the half-line from
+ * g = c + (len + R) u: a cylinder of radius R whose rounded nose reaches down
+ * exactly to c + len u, the end of the cutting length, and never below it.
+ * out[0] = distance from the tool's half-line to the triangle, out[1] =
+ * distance from the holder's half-line.  With R = r the holder lies inside
+ * the tool, so the pair decides as the plain tool does. */
+void orc_tool_holder_distances(const double *v9, const double *c, const double *u, double len, double R,
+                               double *out) {
+    double g[3];
+    for (int k = 0; k < 3; ++k) g[k] = c[k] + (len + R) * u[k];
+    out[0] = orc_tool_distance(v9, c, u);
+    out[1] = orc_tool_distance(v9, g, u);
 }
 
 /* bits: 1 = free; amb: 1 = some triangle within +-band of thr and none below
@@ -968,7 +939,7 @@ int orc_cast_tool_holder(const float *V, const int32_t *T, int64_t nt, const flo
                     else if (dist <= thr + band) near = 1;
                 } else {
                     double dd2[2];
-                    orc_tool_holder_distances(&v[0][0], c, u, len, dd2);
+                    orc_tool_holder_distances(&v[0][0], c, u, len, R, dd2);
                     if (dd2[0] < thr - band || dd2[1] < thr_h - band) blocked = 1;
                     else if (dd2[0] <= thr + band || dd2[1] <= thr_h + band) near = 1;
                 }

@@ -50,7 +50,7 @@ def lib():
         d = C.c_double
         L.orc_cast_tool_holder.argtypes = [P, P, i64, P, P, i64, i64, P, i32, i32, d, d, d, d, d, P, P, i32]
         L.orc_cast_tool_holder.restype = C.c_int
-        L.orc_tool_holder_distances.argtypes = [P, P, P, d, P]
+        L.orc_tool_holder_distances.argtypes = [P, P, P, d, d, P]
         L.orc_tool_holder_distances.restype = None
         L.orc_fibonacci_dirs.argtypes = [i32, P]
         L.orc_axes6.argtypes = [P]
@@ -292,11 +292,13 @@ def cast_tool(verts, tris, samples, dirs, radius, kind=0, s0=0, s1=None, threads
 
 
 def cast_tool_holder(verts, tris, samples, dirs, radius, cut_length, holder_radius, kind=0, threads=0):
-    """Brute-force tool cast with a holder: the ball-end cutter of `radius`
-    swept over `cut_length` from the tip centre, then a holder of
-    `holder_radius` along the rest of the approach half-line.  Blocked when a
-    triangle comes within radius - tol of the cutter segment or within
-    holder_radius - tol of the holder half-line.  Returns (bits, ambiguous)."""
+    """Brute-force tool cast with a holder: the ball-end tool of `radius`
+    (every point within radius of the approach half-line from the tip
+    centre), and a holder of `holder_radius` about the half-line that starts
+    cut_length + holder_radius above the tip centre, so that its rounded nose
+    reaches down to the end of the cutting length.  Blocked when a triangle
+    comes within radius - tol of the tool's half-line or within
+    holder_radius - tol of the holder's.  Returns (bits, ambiguous)."""
     v, t = _f32(verts), _i32(tris)
     Pt, Nn, d = _f32(samples["point"]), _f32(samples["normal"]), _f32(dirs)
     S, N = len(Pt), len(d)
@@ -310,13 +312,15 @@ def cast_tool_holder(verts, tris, samples, dirs, radius, cut_length, holder_radi
     return bits, amb
 
 
-def tool_holder_distances(tri9, c, u, cut_length):
-    """FP64 (distance from the cutter segment c + t u, 0 <= t <= cut_length,
-    distance from the holder half-line from c + cut_length u) to a triangle."""
+def tool_holder_distances(tri9, c, u, cut_length, holder_radius):
+    """FP64 (distance from the tool's half-line c + t u, t >= 0, distance
+    from the holder's half-line from c + (cut_length + holder_radius) u) to
+    a triangle."""
     a = np.ascontiguousarray(tri9, np.float64).reshape(9)
     out = np.zeros(2, np.float64)
     lib().orc_tool_holder_distances(_p(a), _p(np.ascontiguousarray(c, np.float64)),
-                                    _p(np.ascontiguousarray(u, np.float64)), float(cut_length), _p(out))
+                                    _p(np.ascontiguousarray(u, np.float64)), float(cut_length),
+                                    float(holder_radius), _p(out))
     return float(out[0]), float(out[1])
 
 
