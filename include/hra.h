@@ -251,15 +251,16 @@ hra_status hra_cast_tool(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const h
                          double tool_radius, uint32_t *d_bits, uint32_t *d_counts, void *stream);
 /* The tool cast with a holder (an extension of the same reading: Section
  * 3.3 names tool reach, and a real cutter sits in a wider holder).  The
- * cutter is the ball of tool_radius swept from the tip centre c over
- * cut_length mm along the approach direction u (the segment c .. c +
- * cut_length u); the holder is every point within holder_radius of the rest
- * of the half-line, from h = c + cut_length u on.  Direction free iff no
- * triangle comes closer than tool_radius - tol to the segment nor closer
- * than holder_radius - tol to the holder half-line (tol and the ambiguity
+ * tool, as in hra_cast_tool, is every point within tool_radius of the
+ * approach half-line from the tip centre c; the holder is every point within
+ * holder_radius of the half-line from c + (cut_length + holder_radius) u, a
+ * cylinder whose rounded nose reaches down exactly to c + cut_length u (the
+ * end of the cutting length) and never below it.  Direction free iff no
+ * triangle comes closer than tool_radius - tol to the tool's half-line nor
+ * closer than holder_radius - tol to the holder's (tol and the ambiguity
  * band as for hra_cast_tool).  cut_length must be positive and finite and
  * holder_radius finite and >= tool_radius (HRA_ERR_INVALID_ARG otherwise);
- * holder_radius == tool_radius gives hra_cast_tool's tool.  Outputs,
+ * holder_radius == tool_radius gives hra_cast_tool's bits.  Outputs,
  * directions and stream as for hra_cast_tool. */
 hra_status hra_cast_tool_holder(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples,
                                 hra_dirs dirs, double tool_radius, double cut_length, double holder_radius,

@@ -52,50 +52,71 @@ __device__ inline D3 cross(D3 a, D3 b) { return mk(a.y * b.z - a.z * b.y, a.z * 
 __device__ inline double norm(D3 a) { return sqrt(dot(a, a)); }
 __device__ inline D3 f4d(float4 v) { return mk(v.x, v.y, v.z); }
 
-// distance from x to the segment [a, b]
-__device__ inline double seg_dist(D3 x, D3 a, D3 b) {
+// Squared distances: every test compares a distance with a threshold, so
+// the comparisons take squares and no square root is computed.  The
+// decision changes only for distances within a few units of 2^-53 of the
+// threshold, far inside the band (1e-9 x diagonal) where the oracle calls a
+// direction ambiguous.
+
+// squared distance from x to the segment [a, b]
+__device__ inline double seg_dist2(D3 x, D3 a, D3 b) {
     const D3 e = b - a, w = x - a;
-    const double ee = dot(e, e);
-    double s = ee > 0.0 ? dot(w, e) / ee : 0.0;
-    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
-    return norm(w - s * e);
+    const double ee = dot(e, e), we = dot(w, e);
+    if (!(we > 0.0) || !(ee > 0.0)) return dot(w, w);     // nearest: a
+    if (we >= ee) {                                        // nearest: b
+        const D3 q = x - b;
+        return dot(q, q);
+    }
+    const D3 q = w - (we / ee) * e;
+    return dot(q, q);
 }
 
-// distance from x to the half-line c + t u (u unit)
-__device__ inline double ray_dist(D3 c, D3 u, D3 x) {
+// squared distance from x to the half-line c + t u (u unit)
+__device__ inline double ray_dist2(D3 c, D3 u, D3 x) {
     const D3 w = x - c;
     double t = dot(w, u);
     t = t < 0.0 ? 0.0 : t;
-    return norm(w - t * u);
+    const D3 q = w - t * u;
+    return dot(q, q);
 }
 
-// distance between the half-line and the segment: an end point of one of
-// them, or the common perpendicular when it falls inside both
-__device__ inline double ray_seg_dist(D3 c, D3 u, D3 a, D3 b) {
-    double best = fmin(fmin(ray_dist(c, u, a), ray_dist(c, u, b)), seg_dist(c, a, b));
+// squared distance between the half-line and the segment: an end point of
+// one of them, or the common perpendicular when it falls inside both
+__device__ inline double ray_seg_dist2(D3 c, D3 u, D3 a, D3 b) {
+    double best = fmin(fmin(ray_dist2(c, u, a), ray_dist2(c, u, b)), seg_dist2(c, a, b));
     const D3 e = b - a, w = c - a;
     const double B = dot(u, e), C = dot(e, e), D = dot(u, w), E = dot(e, w);
     const double den = C - B * B;
     if (den > 1e-300 * (C > 1.0 ? C : 1.0)) {
-        const double t = (B * E - C * D) / den, s = (E - B * D) / den;
-        if (t > 0.0 && s > 0.0 && s < 1.0) best = fmin(best, norm((w + t * u) - s * e));
+        // the feet t = tn / den on the half-line and s = sn / den on the
+        // segment lie inside both when tn > 0 and 0 < sn < den (den > 0)
+        const double tn = B * E - C * D, sn = E - B * D;
+        if (tn > 0.0 && sn > 0.0 && sn < den) {
+            const D3 q = (w + (tn / den) * u) - (sn / den) * e;
+            best = fmin(best, dot(q, q));
+        }
     }
     return best;
 }
 
-// distance from x to the triangle: to its plane when x projects inside it,
-// else to the nearest edge
-__device__ inline double tri_dist(D3 x, D3 a, D3 b, D3 c) {
+// squared distance from x to the triangle: to its plane when x projects
+// inside it, else to the nearest edge
+__device__ inline double tri_dist2(D3 x, D3 a, D3 b, D3 c) {
     const D3 e1 = b - a, e2 = c - a, w = x - a;
     const D3 nrm = cross(e1, e2);
     const double nn = dot(nrm, nrm);
     if (nn > 0.0) {
         const double d11 = dot(e1, e1), d12 = dot(e1, e2), d22 = dot(e2, e2), w1 = dot(w, e1), w2 = dot(w, e2);
+        // barycentric numerators over the Gram determinant den > 0: inside
+        // iff both are >= 0 and their sum is <= den
         const double den = d11 * d22 - d12 * d12;
-        const double b1 = (d22 * w1 - d12 * w2) / den, b2 = (d11 * w2 - d12 * w1) / den;
-        if (b1 >= 0.0 && b2 >= 0.0 && b1 + b2 <= 1.0) return fabs(dot(w, nrm)) / sqrt(nn);
+        const double n1 = d22 * w1 - d12 * w2, n2 = d11 * w2 - d12 * w1;
+        if (den > 0.0 && n1 >= 0.0 && n2 >= 0.0 && n1 + n2 <= den) {
+            const double h = dot(w, nrm);
+            return h * h / nn;
+        }
     }
-    return fmin(fmin(seg_dist(x, a, b), seg_dist(x, b, c)), seg_dist(x, c, a));
+    return fmin(fmin(seg_dist2(x, a, b), seg_dist2(x, b, c)), seg_dist2(x, c, a));
 }
 
 // the half-line meets the closed triangle (signed volumes about c)
@@ -144,11 +165,13 @@ __device__ inline bool far_from_axis(float cx, float cy, float cz, float ux, flo
     return away >= -1e-6f * nn && fabsf(s0) > thr_hi * nn;
 }
 
-// The screens of far_from_axis for a tool with a holder.  The triangle's
-// bounding sphere (centroid m, radius rho) against the cutter segment
-// c .. c + len u with thr_hi and against the holder half-line from c + len u
-// with thr_h_hi: ruled out when it clears both.
-__device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float ux, float uy, float uz, float len,
+// The screens of far_from_axis for a tool with a holder: the tool's
+// half-line from c with thr_hi and the holder's half-line from
+// g = c + glen u (glen = cutting length + holder radius) with thr_h_hi.  The
+// bounding sphere (centroid m, radius rho) must clear both, or, for the faces
+// around the sample, the axis must not approach the plane and both c and g
+// clear it (conditions and margins as in far_from_axis).
+__device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float ux, float uy, float uz, float glen,
                                             float4 A, float4 B, float4 C, float thr_hi, float thr_h_hi) {
     const float mx = ((A.x + B.x) + C.x) * (1.0f / 3.0f), my = ((A.y + B.y) + C.y) * (1.0f / 3.0f),
                 mz = ((A.z + B.z) + C.z) * (1.0f / 3.0f);
@@ -158,15 +181,11 @@ __device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float 
                                   (qx * qx + qy * qy) + qz * qz));
     const float wx = mx - cx, wy = my - cy, wz = mz - cz;
     const float t = (wx * ux + wy * uy) + wz * uz;
-    const float ts = fminf(fmaxf(t, 0.0f), len), th = fmaxf(t, len);
+    const float ts = fmaxf(t, 0.0f), th = fmaxf(t, glen);
     const float sx = wx - ts * ux, sy = wy - ts * uy, sz = wz - ts * uz;
     const float hx = wx - th * ux, hy = wy - th * uy, hz = wz - th * uz;
     if (sqrtf((sx * sx + sy * sy) + sz * sz) - rho > thr_hi && sqrtf((hx * hx + hy * hy) + hz * hz) - rho > thr_h_hi)
         return true;
-    // The plane screen split the same way: when the axis does not approach
-    // the plane, cutter points are at least as far from it as c and holder
-    // points at least as far as h = c + len u (conditions and margins as in
-    // far_from_axis).
     const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z, e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
     const float Nx = e1y * e2z - e1z * e2y, Ny = e1z * e2x - e1x * e2z, Nz = e1x * e2y - e1y * e2x;
     const float nn = sqrtf((Nx * Nx + Ny * Ny) + Nz * Nz);
@@ -175,73 +194,66 @@ __device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float 
     const float s0 = ((cx - A.x) * Nx + (cy - A.y) * Ny) + (cz - A.z) * Nz;
     const float s1 = (ux * Nx + uy * Ny) + uz * Nz;
     const float away = s0 >= 0.0f ? s1 : -s1;
-    return away >= -1e-6f * nn && fabsf(s0) > thr_hi * nn && fabsf(s0 + len * s1) > thr_h_hi * nn;
+    return away >= -1e-6f * nn && fabsf(s0) > thr_hi * nn && fabsf(s0 + glen * s1) > thr_h_hi * nn;
 }
 
-// true when the triangle comes closer than thr to the tool axis
-__device__ inline bool tool_blocked(D3 c, D3 u, float4 A4, float4 B4, float4 C4, double thr) {
+// true when the triangle comes closer than sqrt(thr2) to the half-line
+// c + t u: it meets the half-line, or c lies that near it, or one of its
+// edges does (each evaluated in turn, the first near one decides)
+__device__ inline bool tool_blocked(D3 c, D3 u, float4 A4, float4 B4, float4 C4, double thr2) {
     const D3 A = f4d(A4), B = f4d(B4), C = f4d(C4);
     if (ray_meets(c, u, A, B, C)) return true;
-    if (tri_dist(c, A, B, C) < thr) return true;
-    return fmin(fmin(ray_seg_dist(c, u, A, B), ray_seg_dist(c, u, B, C)), ray_seg_dist(c, u, C, A)) < thr;
+    if (tri_dist2(c, A, B, C) < thr2) return true;
+    if (ray_seg_dist2(c, u, A, B) < thr2) return true;
+    if (ray_seg_dist2(c, u, B, C) < thr2) return true;
+    return ray_seg_dist2(c, u, C, A) < thr2;
 }
 
-// distance between the segments [p, q] and [a, b]: an end point of one to
-// the other, or the common perpendicular when its feet fall inside both
-__device__ inline double seg_seg_dist(D3 p, D3 q, D3 a, D3 b) {
-    double best = fmin(fmin(seg_dist(p, a, b), seg_dist(q, a, b)), fmin(seg_dist(a, p, q), seg_dist(b, p, q)));
-    const D3 f = q - p, e = b - a, w = p - a;
-    const double ff = dot(f, f), fe = dot(f, e), ee = dot(e, e), fw = dot(f, w), ew = dot(e, w);
-    const double den = ff * ee - fe * fe;
-    if (den > 1e-300 * (ff * ee > 1.0 ? ff * ee : 1.0)) {
-        const double sp = (fe * ew - ee * fw) / den, tp = (ff * ew - fe * fw) / den;
-        if (sp > 0.0 && sp < 1.0 && tp > 0.0 && tp < 1.0) best = fmin(best, norm((w + sp * f) - tp * e));
-    }
-    return best;
+// Tool with a holder: the tool is the half-line from c (squared threshold
+// thr2), the holder the half-line from g = c + (cutting length + holder
+// radius) u (thr_h2): its rounded nose reaches down to the end of the
+// cutting length.
+__device__ inline bool tool_blocked_holder(D3 c, D3 g, D3 u, float4 A4, float4 B4, float4 C4, double thr2,
+                                           double thr_h2) {
+    return tool_blocked(c, u, A4, B4, C4, thr2) || tool_blocked(g, u, A4, B4, C4, thr_h2);
 }
 
-// Tool with a holder: the cutter (radius r) is the segment from c to
-// h = c + len u, the holder (radius R) the half-line from h along u.  True
-// when the triangle comes closer than thr = r - tol to the cutter or closer
-// than thr_h = R - tol to the holder.  The segment crosses the triangle when
-// the half-lines from c along u and from h along -u both meet it.
-__device__ inline bool tool_blocked_holder(D3 c, D3 u, double len, float4 A4, float4 B4, float4 C4, double thr,
-                                           double thr_h) {
-    const D3 A = f4d(A4), B = f4d(B4), C = f4d(C4);
-    const D3 h = c + len * u, mu = mk(-u.x, -u.y, -u.z);
-    if (ray_meets(c, u, A, B, C) && ray_meets(h, mu, A, B, C)) return true;
-    if (fmin(tri_dist(c, A, B, C), tri_dist(h, A, B, C)) < thr) return true;
-    if (fmin(fmin(seg_seg_dist(c, h, A, B), seg_seg_dist(c, h, B, C)), seg_seg_dist(c, h, C, A)) < thr) return true;
-    return tool_blocked(h, u, A4, B4, C4, thr_h);
+// FP32 slab test against a box grown by pad on every side.  The growth is
+// carried by the origin, shifted per ray: lo - pad - o = lo - (o + pad) and
+// hi + pad - o = hi - (o - pad), with (o + pad) and (o - pad) formed once
+// (their rounding, a few units of 2^-24 of the coordinates, lies far inside
+// the margin the pad carries beyond the radius).
+struct Shifted {
+    float lx, ly, lz, hx, hy, hz;   // o + pad (for low faces), o - pad (for high faces)
+};
+__device__ inline Shifted shift(float ox, float oy, float oz, float pad) {
+    return Shifted{ox + pad, oy + pad, oz + pad, ox - pad, oy - pad, oz - pad};
 }
-
-// FP32 slab test against a box grown by pad on every side
-__device__ inline bool grown_slab(float lx, float ly, float lz, float hx, float hy, float hz, float pad, float ox,
-                                  float oy, float oz, float ix, float iy, float iz, float &tn) {
-    const float tx0 = ((lx - pad) - ox) * ix, tx1 = ((hx + pad) - ox) * ix;
-    const float ty0 = ((ly - pad) - oy) * iy, ty1 = ((hy + pad) - oy) * iy;
-    const float tz0 = ((lz - pad) - oz) * iz, tz1 = ((hz + pad) - oz) * iz;
+__device__ inline bool grown_slab(float lx, float ly, float lz, float hx, float hy, float hz, const Shifted &o, float ix,
+                                  float iy, float iz, float &tn) {
+    const float tx0 = (lx - o.lx) * ix, tx1 = (hx - o.hx) * ix;
+    const float ty0 = (ly - o.ly) * iy, ty1 = (hy - o.hy) * iy;
+    const float tz0 = (lz - o.lz) * iz, tz1 = (hz - o.hz) * iz;
     const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
     tn = tmin;
     return tmin <= tmax * 1.0000006f;
 }
 
-// Box test of a tool with a holder: the box grown by the cutter's pad must
-// meet the ray before the cutting length ends (t <= len_hi), or the box grown
-// by the holder's pad after it starts (t >= len_lo); len_hi and len_lo carry
-// a wide slack, so a doubt means a visit.  tn orders the children.
-__device__ inline bool holder_slab(float lx, float ly, float lz, float hx, float hy, float hz, float pad_c, float pad_h,
-                                   float len_lo, float len_hi, float ox, float oy, float oz, float ix, float iy,
-                                   float iz, float &tn) {
+// Box test of a tool with a holder: the box grown by the tool's pad meets
+// the ray anywhere on it, or the box grown by the holder's pad meets it at
+// some t >= g_lo (a little below the holder's start, so a doubt means a
+// visit).  tn orders the children.
+__device__ inline bool holder_slab(float lx, float ly, float lz, float hx, float hy, float hz, const Shifted &oc,
+                                   const Shifted &oh, float g_lo, float ix, float iy, float iz, float &tn) {
     float tc, th;
-    const bool hc = grown_slab(lx, ly, lz, hx, hy, hz, pad_c, ox, oy, oz, ix, iy, iz, tc) && tc <= len_hi;
-    const float tx0 = ((lx - pad_h) - ox) * ix, tx1 = ((hx + pad_h) - ox) * ix;
-    const float ty0 = ((ly - pad_h) - oy) * iy, ty1 = ((hy + pad_h) - oy) * iy;
-    const float tz0 = ((lz - pad_h) - oz) * iz, tz1 = ((hz + pad_h) - oz) * iz;
+    const bool hc = grown_slab(lx, ly, lz, hx, hy, hz, oc, ix, iy, iz, tc);
+    const float tx0 = (lx - oh.lx) * ix, tx1 = (hx - oh.hx) * ix;
+    const float ty0 = (ly - oh.ly) * iy, ty1 = (hy - oh.hy) * iy;
+    const float tz0 = (lz - oh.lz) * iz, tz1 = (hz - oh.hz) * iz;
     th = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * 1.0000006f;
-    const bool hh = th <= tmax && tmax >= len_lo;
+    const bool hh = th <= tmax && tmax >= g_lo;
     tn = hc ? tc : th;
     return hc || hh;
 }
@@ -251,9 +263,8 @@ __device__ inline float rcp_guarded(float x) { return fabsf(x) > 1e-30f ? 1.0f /
 // Four waves per SIMD: the compiler's own choice (142 VGPRs) allows three;
 // capped at 128 it spills 15 registers on the FP64 path and the cast runs 9 %
 // faster (the FP64 test out of line at the same cap: 5 %).
-// HOLDER: the cutter and holder of tool_blocked_holder; the box growth and
-// both FP32 screens then use the larger radius, which covers the whole
-// half-line from c (the cutter segment and the holder both lie on it).
+// HOLDER: the tool and the holder of tool_blocked_holder; boxes, screens
+// and tests take each with its own radius and half-line.
 template <bool STATS, bool HOLDER>
 __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_cast_tool(ToolArgs a) {
     __shared__ int stk[TOOL_STACK * TOOL_THREADS];
@@ -287,6 +298,9 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
     const D3 c = mk((double)px + r * (double)nx, (double)py + r * (double)ny, (double)pz + r * (double)nz);
     const double dl = sqrt(((double)d.x * d.x + (double)d.y * d.y) + (double)d.z * d.z);
     const D3 u = mk(d.x / dl, d.y / dl, d.z / dl);
+    const double glen = a.hlen + a.hrad;          // HOLDER: the holder's half-line starts at c + glen u
+    const D3 hg = c + glen * u;
+    const double thr2 = thr * thr, thr_h2 = thr_h * thr_h;
     const int32_t root = P.root, n_valid = P.n_valid, n_tris_alloc = P.leaf_lo + P.n_valid;
     bool blocked = false;
     uint32_t n_nodes = 0, n_tests = 0, n_cands = 0;
@@ -297,13 +311,14 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
         const float pad = (float)(rr * 1.0001) + (float)(1e-5 * P.diag);
         const float pad_c = (float)(r * 1.0001) + (float)(1e-5 * P.diag);   // the cutter's (HOLDER)
         const float ix = rcp_guarded(d.x), iy = rcp_guarded(d.y), iz = rcp_guarded(d.z);
+        const Shifted so = shift(cx, cy, cz, pad), so_c = shift(cx, cy, cz, pad_c);
         // unit direction and threshold for the FP32 screen; the margin
         // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a
         // part far from the origin) is far above the screen's rounding
         const float ux = (float)u.x, uy = (float)u.y, uz = (float)u.z;
         const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
         const float thr_hi = (float)(fmax(thr, thr_h) + 1e-5 * P.diag + 1e-6 * cmax);
-        const float thr_c_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax), hl = (float)a.hlen;
+        const float thr_c_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax), gl = (float)glen;
         int spill[TOOL_SPILL];
         int sp = 0;
         int32_t node = root;
@@ -316,11 +331,11 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                 const float4 *t = a.tris + 3 * (int64_t)(f + k);
                 const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                 if (STATS) ++n_cands;
-                if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)
+                if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, gl, A4, B4, C4, thr_c_hi, thr_hi)
                            : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi))
                     continue;
                 if (STATS) ++n_tests;
-                blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
+                blocked = HOLDER ? tool_blocked_holder(c, hg, u, A4, B4, C4, thr2, thr_h2) : tool_blocked(c, u, A4, B4, C4, thr2);
             }
             node = -1;
         }
@@ -334,13 +349,11 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
             float t0, t1;
             bool h0, h1;
             if (HOLDER) {
-                h0 = holder_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, pad_c, pad, hl * 0.99f, hl * 1.01f, cx, cy,
-                                 cz, ix, iy, iz, t0);
-                h1 = holder_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, pad_c, pad, hl * 0.99f, hl * 1.01f, cx, cy,
-                                 cz, ix, iy, iz, t1);
+                h0 = holder_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, so_c, so, gl * 0.99f, ix, iy, iz, t0);
+                h1 = holder_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, so_c, so, gl * 0.99f, ix, iy, iz, t1);
             } else {
-                h0 = grown_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, pad, cx, cy, cz, ix, iy, iz, t0);
-                h1 = grown_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, pad, cx, cy, cz, ix, iy, iz, t1);
+                h0 = grown_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, so, ix, iy, iz, t0);
+                h1 = grown_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, so, ix, iy, iz, t1);
             }
             const int32_t ch[2] = {nd.d.x, nd.d.y};
             const bool hit[2] = {h0, h1};
@@ -355,11 +368,11 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                     const float4 *t = a.tris + 3 * (int64_t)(f + q);
                     const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                     if (STATS) ++n_cands;
-                    if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, hl, A4, B4, C4, thr_c_hi, thr_hi)
+                    if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, gl, A4, B4, C4, thr_c_hi, thr_hi)
                                : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi))
                         continue;
                     if (STATS) ++n_tests;
-                    blocked = HOLDER ? tool_blocked_holder(c, u, a.hlen, A4, B4, C4, thr, thr_h) : tool_blocked(c, u, A4, B4, C4, thr);
+                    blocked = HOLDER ? tool_blocked_holder(c, hg, u, A4, B4, C4, thr2, thr_h2) : tool_blocked(c, u, A4, B4, C4, thr2);
                 }
             }
             if (blocked || bad) break;

@@ -144,24 +144,50 @@ def test_tool_errors(ctx):
     assert bits.shape == (0, 2)
 
 
-@pytest.mark.parametrize("R", [1.5, 4.0, 12.0])
-def test_tool_holder_parity(ctx, orc, R):
+def test_tool_holder_parity(ctx, orc):
+    """Holders of 1.5 (= the tool), 2.5, 4 and 6 mm at a cutting length of
+    8 mm on config 1: every non-ambiguous direction equals the oracle's, the
+    R = r holder equals the plain tool, and free directions are nonzero and
+    strictly fewer as the holder widens."""
     m = P.config1_part()
     b = ctx.build_bvh(m.verts, m.tris)
     s = ctx.sample_surface(b, 300, 6)
     sn = _np(s)
     r, L, N = 1.5, 8.0, 150
-    _say("tool holder", r, L, R)
-    bits, cnt = ctx.cast_tool_holder(b, s, N, r, L, R)
+    frees = []
+    for R in (1.5, 2.5, 4.0, 6.0):
+        _say("tool holder", r, L, R)
+        bits, cnt = ctx.cast_tool_holder(b, s, N, r, L, R)
+        got = _u32(bits)
+        ob, oa = orc.cast_tool_holder(m.verts, m.tris, sn, orc.fibonacci_dirs(N), r, L, R)
+        assert not ((got ^ ob) & ~oa).any(), R
+        popc = np.array([int(np.unpackbits(w.view(np.uint8)).sum()) for w in got])
+        assert np.array_equal(_u32(cnt), popc.astype(np.uint32))
+        frees.append(int(popc.sum()))
+        if R == r:
+            plain, _ = ctx.cast_tool(b, s, N, r)
+            assert np.array_equal(_u32(plain), got)
+    assert frees[-1] > 0 and all(a > c for a, c in zip(frees, frees[1:])), frees
+
+
+def test_tool_holder_housing_rows(ctx, orc):
+    """The benchmark's holder (r = 3, L = 20, R = 8 mm) on the housing-like
+    part (22.5k faces, one offset centroid per face, 150 directions):
+    seeded rows against the oracle."""
+    from paper_2609_05467_amd import hra
+    m = P.workload_parts("paper_housing_22k")[0]
+    b = ctx.build_bvh(m.verts, m.tris)
+    S = m.n_tris
+    s = ctx.sample_surface(b, S, 0, mode=hra.SAMPLE_CENTROID)
+    N = 150
+    _say("tool holder housing", S)
+    bits, _ = ctx.cast_tool_holder(b, s, N, 3.0, 20.0, 8.0)
     got = _u32(bits)
-    ob, oa = orc.cast_tool_holder(m.verts, m.tris, sn, orc.fibonacci_dirs(N), r, L, R)
-    assert not ((got ^ ob) & ~oa).any()
-    popc = np.array([int(np.unpackbits(w.view(np.uint8)).sum()) for w in got])
-    assert np.array_equal(_u32(cnt), popc.astype(np.uint32))
-    if R == r:
-        plain, _ = ctx.cast_tool(b, s, N, r)
-        pb, pa = orc.cast_tool(m.verts, m.tris, sn, orc.fibonacci_dirs(N), r)
-        assert not ((_u32(plain) ^ got) & ~(oa | pa)).any()
+    rows = np.sort(np.random.default_rng(13).choice(S, 120, replace=False))
+    sn = {k: v.cpu().numpy()[rows] for k, v in s.items()}
+    ob, oa = orc.cast_tool_holder(m.verts, m.tris, sn, orc.fibonacci_dirs(N), 3.0, 20.0, 8.0)
+    assert not ((got[rows] ^ ob) & ~oa).any()
+    assert int(np.unpackbits(ob.view(np.uint8)).sum()) > 0
 
 
 def test_tool_holder_errors(ctx):
