@@ -143,15 +143,24 @@ public:
     // A build finished: its scratch is released.  With `ok` false the part
     // is marked broken: the server fails its requests instead of launching
     // them, and the part is released once its last request has ended.
-    void build_done(uint64_t key, bool ok) {
+    // Returns the part keys to release now: the part itself when no request
+    // holds it any more (all of them cancelled while it was being built) and
+    // it is not to stay resident.
+    std::vector<uint64_t> build_done(uint64_t key, bool ok) {
+        std::vector<uint64_t> release;
         auto it = parts_.find(key);
-        if (it == parts_.end() || it->second.state != PartState::Building) return;
+        if (it == parts_.end() || it->second.state != PartState::Building) return release;
         Part &p = it->second;
         used_ -= p.build_bytes;
         p.build_bytes = 0;
         --building_;
         p.state = PartState::Ready;
         if (!ok) broken_.insert_or_assign(key, true);   // released when its pins drop
+        if (p.pins == 0 && (!cfg_.keep_resident || broken(key))) {
+            release.push_back(key);
+            remove_part(it);
+        }
+        return release;
     }
 
     bool broken(uint64_t key) const { return broken_.count(key) != 0; }
@@ -170,29 +179,37 @@ public:
     }
 
     // A batch returned by next_batch finished (or was failed without a
-    // launch): its working sets are released and its parts unpinned.
-    // Returns the part keys that must be released now (parts not kept
-    // resident, broken parts).
-    std::vector<uint64_t> batch_done(const std::vector<uint64_t> &tickets) {
+    // launch): its working sets are released and its parts unpinned.  With
+    // `failed` (the batch's device error word was set) the parts it read are
+    // marked broken, so they are dropped once unpinned and rebuilt on their
+    // next use rather than trusted again.  Returns the part keys that must be
+    // released now (parts not kept resident, broken parts).
+    std::vector<uint64_t> batch_done(const std::vector<uint64_t> &tickets, bool failed = false) {
         std::vector<uint64_t> release;
         --inflight_;
-        for (uint64_t t : tickets) {
-            auto sit = stage_.find(t);
-            if (sit == stage_.end()) continue;
-            const Req r = sit->second;
-            stage_.erase(sit);
-            used_ -= r.stage_bytes;
-            auto pit = parts_.find(r.part_key);
-            if (pit == parts_.end()) continue;
-            Part &p = pit->second;
-            --p.pins;
-            touch(p);
-            if (p.pins == 0 && (!cfg_.keep_resident || broken(p.key))) {
-                release.push_back(p.key);
-                remove_part(pit);
-            }
-        }
+        for (uint64_t t : tickets) end_request(t, failed, &release);
         return release;
+    }
+
+    // Cancel a request that has not been launched.  A pending one leaves the
+    // queue; an admitted one gives back its working set and its pin (part
+    // keys to release are appended to *release, as batch_done returns them;
+    // a part still being built is released by build_done instead).  Returns
+    // false, changing nothing, for a ticket that is unknown or already in a
+    // launched batch.
+    bool cancel(uint64_t ticket, std::vector<uint64_t> *release) {
+        for (auto it = pending_.begin(); it != pending_.end(); ++it)
+            if (it->ticket == ticket) {
+                pending_.erase(it);
+                return true;
+            }
+        for (auto it = waiting_.begin(); it != waiting_.end(); ++it)
+            if (*it == ticket) {
+                waiting_.erase(it);
+                end_request(ticket, false, release);
+                return true;
+            }
+        return false;
     }
 
     // Part key of an admitted ticket.
@@ -203,6 +220,26 @@ public:
 
 private:
     void touch(Part &p) { lru_.splice(lru_.end(), lru_, p.lru); }
+
+    // An admitted request ended (its batch finished or failed, or it was
+    // cancelled before launch): release its working set and its pin.
+    void end_request(uint64_t t, bool failed, std::vector<uint64_t> *release) {
+        auto sit = stage_.find(t);
+        if (sit == stage_.end()) return;
+        const Req r = sit->second;
+        stage_.erase(sit);
+        used_ -= r.stage_bytes;
+        auto pit = parts_.find(r.part_key);
+        if (pit == parts_.end()) return;
+        Part &p = pit->second;
+        if (failed) broken_.insert_or_assign(p.key, true);
+        --p.pins;
+        touch(p);
+        if (p.pins == 0 && p.state == PartState::Ready && (!cfg_.keep_resident || broken(p.key))) {
+            release->push_back(p.key);
+            remove_part(pit);
+        }
+    }
 
     void remove_part(std::unordered_map<uint64_t, Part>::iterator it) {
         used_ -= it->second.bytes;

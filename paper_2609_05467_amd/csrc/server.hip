@@ -202,6 +202,8 @@ void start_build(hra_server *sv, uint64_t key, const hra_request &r) {
         hipStreamSynchronize(s);
         p.failed_launch = true;
         p.known_done = true;
+        // its requests still pin it (they fail when their batch forms), so
+        // nothing is released here
         sv->S->build_done(key, false);
     }
 }
@@ -332,7 +334,9 @@ void complete_batch(hra_server *sv, SrvBatch &b) {
     }
     sv->pinned_pool.push_back({b.pinned, b.pinned_cap});
     sv->event_pool.push_back(b.done);
-    for (uint64_t k : sv->S->batch_done(b.tickets)) release_part(sv, k);
+    // a batch whose device error word is set: the hierarchies it read are
+    // not trusted again (dropped when unpinned, rebuilt on next use)
+    for (uint64_t k : sv->S->batch_done(b.tickets, h_err != 0u)) release_part(sv, k);
 }
 
 void worker_loop(hra_server *sv) {
@@ -358,16 +362,19 @@ void worker_loop(hra_server *sv) {
             sv->S->submit(q);
             progress = true;
         }
-        // finished builds
+        // finished builds (a part no request holds any more is released
+        // after the loop)
+        std::vector<uint64_t> unheld;
         for (auto &kv : sv->parts) {
             SrvPart &p = kv.second;
             if (p.known_done || !p.built) continue;
             if (hipEventQuery(p.built) == hipSuccess) {
                 p.known_done = true;
-                sv->S->build_done(kv.first, *p.h_err == 0u);
+                for (uint64_t k : sv->S->build_done(kv.first, *p.h_err == 0u)) unheld.push_back(k);
                 progress = true;
             }
         }
+        for (uint64_t k : unheld) release_part(sv, k);
         // finished batches
         for (size_t i = 0; i < sv->inflight.size();) {
             if (hipEventQuery(sv->inflight[i]->done) == hipSuccess) {

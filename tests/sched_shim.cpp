@@ -49,7 +49,9 @@ void shim_admit(void *s, unsigned long long *evict, unsigned long long *build, u
     counts[4] = put(a.rejected, rejected, cap);
 }
 
-void shim_build_done(void *s, unsigned long long key, int ok) { ((Scheduler *)s)->build_done(key, ok != 0); }
+int shim_build_done(void *s, unsigned long long key, int ok, unsigned long long *released, int cap) {
+    return put(((Scheduler *)s)->build_done(key, ok != 0), released, cap);
+}
 
 int shim_next_batch(void *s, unsigned long long *out, int cap) { return put(((Scheduler *)s)->next_batch(), out, cap); }
 
@@ -57,6 +59,22 @@ int shim_batch_done(void *s, const unsigned long long *tickets, int n, unsigned 
     std::vector<uint64_t> t(tickets, tickets + n);
     return put(((Scheduler *)s)->batch_done(t), released, cap);
 }
+
+// a batch whose device error word was set
+int shim_batch_failed(void *s, const unsigned long long *tickets, int n, unsigned long long *released, int cap) {
+    std::vector<uint64_t> t(tickets, tickets + n);
+    return put(((Scheduler *)s)->batch_done(t, true), released, cap);
+}
+
+// 1 if cancelled (pending or admitted, not launched), 0 otherwise
+int shim_cancel(void *s, unsigned long long ticket, unsigned long long *released, int cap, int *n_released) {
+    std::vector<uint64_t> rel;
+    const bool ok = ((Scheduler *)s)->cancel(ticket, &rel);
+    *n_released = put(rel, released, cap);
+    return ok ? 1 : 0;
+}
+
+int shim_broken(void *s, unsigned long long key) { return ((Scheduler *)s)->broken(key) ? 1 : 0; }
 
 long long shim_used(void *s) { return ((Scheduler *)s)->used(); }
 long long shim_resident(void *s) { return ((Scheduler *)s)->resident_bytes(); }

@@ -30,7 +30,10 @@ def shim(tmp_path_factory):
     L.shim_destroy.argtypes = [C.c_void_p]
     L.shim_submit.argtypes = [C.c_void_p, U64, U64, C.c_longlong, C.c_longlong, C.c_longlong]
     L.shim_admit.argtypes = [C.c_void_p] + [C.POINTER(U64)] * 5 + [C.c_int, C.POINTER(C.c_int)]
-    L.shim_build_done.argtypes = [C.c_void_p, U64, C.c_int]
+    L.shim_build_done.argtypes = [C.c_void_p, U64, C.c_int, C.POINTER(U64), C.c_int]
+    L.shim_batch_failed.argtypes = [C.c_void_p, C.POINTER(U64), C.c_int, C.POINTER(U64), C.c_int]
+    L.shim_cancel.argtypes = [C.c_void_p, U64, C.POINTER(U64), C.c_int, C.POINTER(C.c_int)]
+    L.shim_broken.argtypes = [C.c_void_p, U64]
     L.shim_next_batch.argtypes = [C.c_void_p, C.POINTER(U64), C.c_int]
     L.shim_batch_done.argtypes = [C.c_void_p, C.POINTER(U64), C.c_int, C.POINTER(U64), C.c_int]
     return L
@@ -54,7 +57,21 @@ class Sched:
         return {n: list(a[:c]) for n, a, c in zip(names, arrs, cnt)}
 
     def build_done(self, key, ok=True):
-        self.L.shim_build_done(self.p, key, int(ok))
+        r = (U64 * self.CAP)()
+        n = self.L.shim_build_done(self.p, key, int(ok), r, self.CAP)
+        return list(r[:n])
+
+    def batch_failed(self, tickets):
+        t = (U64 * len(tickets))(*tickets)
+        r = (U64 * self.CAP)()
+        n = self.L.shim_batch_failed(self.p, t, len(tickets), r, self.CAP)
+        return list(r[:n])
+
+    def cancel(self, ticket):
+        r = (U64 * self.CAP)()
+        n = C.c_int()
+        ok = self.L.shim_cancel(self.p, ticket, r, self.CAP, C.byref(n))
+        return bool(ok), list(r[:n.value])
 
     def next_batch(self):
         a = (U64 * self.CAP)()
@@ -263,4 +280,125 @@ def test_random_run_invariants(shim):
     assert admitted_order == submitted                 # arrival order
     assert ended | rejected == set(submitted) and not (ended & rejected)
     assert s.used() == s.resident()                    # only resident hierarchies remain
+    s.close()
+
+
+# ---------------------------------------------------------------- faults and cancellation
+def test_cancel_pending_admitted_and_launched(shim):
+    s = Sched(shim, 10_000)
+    for t in (1, 2, 3):
+        s.submit(t, 40 + t, 300, 100, 50)
+    s.submit(4, 41, 300, 100, 50)                  # a second request on part 41
+    a = s.admit()
+    assert a["admitted"] == [1, 2, 3, 4]
+    s.submit(5, 45, 300, 100, 50)                  # still pending (not admitted yet)
+    ok, rel = s.cancel(5)
+    assert ok and rel == [] and s.pending() == 0
+    for k in (41, 42, 43):
+        s.build_done(k)
+    used = s.used()
+    ok, rel = s.cancel(2)                          # admitted, not launched: working set and pin back
+    assert ok and rel == [] and s.used() == used - 50 and s.pins(42) == 0
+    b = s.next_batch()
+    assert b == [1, 3, 4]
+    ok, _ = s.cancel(3)                            # launched: not cancellable
+    assert not ok and s.pins(43) == 1
+    assert s.cancel(99) == (False, [])             # unknown ticket
+    s.batch_done(b)
+    assert s.idle() and s.used() == 3 * 300        # three parts resident
+    s.close()
+
+
+def test_cancel_while_building_releases_at_build_done(shim):
+    s = Sched(shim, 10_000, keep=False)
+    s.submit(1, 51, 400, 200, 30)
+    assert s.admit()["build"] == [51]
+    ok, rel = s.cancel(1)
+    assert ok and rel == []                        # the build still runs: nothing freed yet
+    assert s.has_part(51) and not s.idle()
+    assert s.build_done(51) == [51]                # released when the build ends
+    assert not s.has_part(51) and s.used() == 0 and s.idle()
+    s.close()
+
+
+def test_device_error_on_batch_k(shim):
+    """Batches 0..5 over three parts; the device error word of batch 3 is
+    set: its requests fail, its parts are dropped once unpinned and rebuilt
+    on their next use; everything else is unaffected and the accounting
+    returns to the resident parts alone."""
+    s = Sched(shim, 100_000, max_batch=2)
+    t = 0
+    rebuilt = []
+    for k in range(6):
+        keys = [60 + (k % 3), 60 + ((k + 1) % 3)]
+        for key in keys:
+            t += 1
+            s.submit(t, key, 1000, 300, 40)
+        a = s.admit()
+        for key in a["build"]:
+            rebuilt.append((k, key))
+            assert s.build_done(key) == []
+        b = s.next_batch()
+        assert len(b) == 2
+        if k == 3:
+            rel = s.batch_failed(b)
+            assert sorted(rel) == sorted(keys)     # both parts it read are dropped
+            assert not any(s.has_part(x) for x in keys)
+        else:
+            assert s.batch_done(b) == []
+        assert s.used() == s.resident()
+    # batch 3 read parts 60 and 61: batch 4 (61, 62) rebuilds 61 and batch 5
+    # (62, 60) rebuilds 60; nothing else was built after the first round
+    assert [(k, key) for k, key in rebuilt if k >= 1] == [(1, 62), (4, 61), (5, 60)]
+    assert s.idle() and s.resident() == 3 * 1000
+    s.close()
+
+
+def test_random_run_with_faults_keeps_invariants(shim):
+    """A seeded run with cancellations, failed builds and failed batches:
+    bytes in use never exceed the budget, equal the resident parts plus the
+    admitted working sets, and return to the resident parts at the end."""
+    rng = random.Random(11)
+    budget = 5000
+    s = Sched(shim, budget, max_batch=4, max_inflight=2)
+    parts = {k: rng.randint(200, 1500) for k in range(70, 82)}
+    stage = {}
+    building = set()
+    inflight = []
+    t = 0
+    for step in range(600):
+        r = rng.random()
+        if r < 0.35:
+            t += 1
+            k = rng.choice(list(parts))
+            st = rng.randint(10, 200)
+            stage[t] = st
+            s.submit(t, k, parts[k], rng.randint(0, 300), st)
+        elif r < 0.45 and stage:
+            s.cancel(rng.choice(list(stage)))
+        a = s.admit()
+        building.update(a["build"])
+        if building and rng.random() < 0.5:
+            k = rng.choice(sorted(building))
+            building.discard(k)
+            s.build_done(k, rng.random() > 0.1)
+        b = s.next_batch()
+        if b:
+            inflight.append(b)
+        if inflight and rng.random() < 0.5:
+            b = inflight.pop(0)
+            (s.batch_failed if rng.random() < 0.1 else s.batch_done)(b)
+        assert 0 <= s.used() <= budget
+        assert s.used() >= s.resident()
+    for k in sorted(building):
+        s.build_done(k)
+    while True:
+        while inflight:
+            s.batch_done(inflight.pop(0))
+        s.admit()
+        b = s.next_batch()
+        if not b:
+            break
+        inflight.append(b)
+    assert s.used() == s.resident() and s.inflight() == 0
     s.close()
