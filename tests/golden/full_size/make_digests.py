@@ -29,6 +29,7 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 import numpy as np  # noqa: E402
 
 import full_size as FS  # noqa: E402
+import oracle_records as OR  # noqa: E402
 from oracle import oracle as orc  # noqa: E402
 from synth import parts as P  # noqa: E402
 
@@ -73,28 +74,11 @@ def part_record(m, mode, seed, S, N, keep_hist=True):
     rec["hemi"], bits = cast_record(bvh, s, dirs, 0)
     rec["hemi"]["oracle_work_per_ray"] = (bvh.work / float(S * N)).tolist()
     t1 = time.perf_counter()
-    st = orc.dirstats(s, dirs, bits)
-    cnt = orc.counts(bits, N)
-    ind = orc.indicators(cnt, N, st["axis"], st["conc"])
-    multi, tripped = orc.classify(ind)
-    g_rows = np.unique(np.asarray(rec["hemi"]["grazing_rows"], np.int64))
-    hist = st["hist"].astype(np.int64)
-    rec["stats"] = {"access": ind["access"], "shares": ind["shares"], "conc": ind["conc"],
-                    "n_included": ind["n_included"], "n_blind": ind["n_blind"],
-                    "n_ties": int(st["tie"].sum()), "rows_with_grazing": int(len(g_rows)),
-                    "multi_axis": bool(multi), "tripped": int(tripped),
-                    # the batch results carry no histogram: kept for single parts
-                    "hist": FS.pack_hist(hist) if keep_hist else None}
+    rec["stats"], hist = OR.stats_record(orc, s, dirs, bits, rec["hemi"]["grazing_rows"], hist=keep_hist)
+    # the batch results carry no histogram: kept for single parts
+    rec["stats"]["hist"] = FS.pack_hist(hist) if keep_hist else None
     rec["axes"], a6 = cast_record(bvh, s, orc.axes6(), 1)
-    bbox, diag, _ = orc.mesh_info(m.verts)
-    cls, code = orc.reach_classes(s["point"], s["tri"], a6[:, 0], bbox,
-                                  orc.bbox_face_tris(m.verts, m.tris, bbox, diag), TOOL_LENGTH)
-    h = orc.code_histogram(cls, code)
-    mn = orc.min_setups_exact(h)
-    gr = orc.min_setups_greedy(h) if h.sum() else (0, 0)
-    rec["setups"] = {"tool_length": TOOL_LENGTH, "min_count": mn[0], "min_mask": mn[1], "greedy_count": gr[0],
-                     "greedy_mask": gr[1], "n_class": [int((cls == k).sum()) for k in range(4)],
-                     "code_hist": [int(x) for x in h]}
+    rec["setups"] = OR.setups_record(orc, m, s, a6, TOOL_LENGTH)
     bvh.close()
     log(f"  {m.n_tris} triangles, {S} samples x {N}: cast {t1 - t0:.1f} s, stats {time.perf_counter() - t1:.1f} s, "
         f"grazing {rec['hemi']['n_grazing']} + {rec['axes']['n_grazing']} (axes)")

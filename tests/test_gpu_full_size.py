@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import full_size as FS
+import oracle_records as OR
 from synth import parts as P
 
 pytestmark = pytest.mark.gpu
@@ -78,52 +79,12 @@ def _check_cast(orc, m, sn, bits, rec, kind, what):
 
 
 def _check_stats(rep, hist, cnt, rec, S, N):
-    """GPU class report and histogram against the oracle's on its own bits.
-    Outside grazing rows the bits are equal, so only G rows with a grazing
-    ray (their free count and axis may differ) and T flagged ties (axis may
-    differ) move the indicators: access by at most the grazing rays over S N;
-    a share by (T + 2G) over the included samples; the mean concentration by
-    1e-4 (FP32 sums) plus (T + 2G) over them; the histogram by 2e-4 of its
-    mass (bin edges) plus the grazing rays."""
-    o, h = rec["stats"], rec["hemi"]
-    G, T = o["rows_with_grazing"], o["n_ties"]
-    n_inc = max(1, o["n_included"] - G)
-    assert abs(rep["access"] - o["access"]) <= h["n_grazing"] / (S * N) + 1e-12
-    assert abs(rep["access"] - o["access"]) <= 1e-4
-    tol_share = (T + 2 * G) / n_inc
-    for k in range(3):
-        assert abs(rep["shares"][k] - o["shares"][k]) <= tol_share + 1e-12, (k, rep["shares"], o["shares"], T, G)
-    assert abs(rep["conc"] - o["conc"]) <= 1e-4 + (T + 2 * G) / n_inc
-    assert abs(rep["n_blind"] - o["n_blind"]) <= G
-    if not rep["near_tie"] and T + 2 * G == 0:
-        assert rep["multi_axis"] == o["multi_axis"]
-    elif not rep["near_tie"]:
-        # the class is unique when no allowance reaches a threshold
-        th = {"access": 0.60, "share": 0.45, "conc": 0.40}
-        margin = min(abs(o["access"] - th["access"]), abs(max(o["shares"]) - th["share"]),
-                     abs(o["conc"] - th["conc"]))
-        if margin > 1e-4 + tol_share:
-            assert rep["multi_axis"] == o["multi_axis"]
-    oh = FS.unpack_hist(o["hist"])
-    gh = hist.astype(np.int64)
-    assert gh.sum() == int(cnt.astype(np.int64).sum())
-    assert np.abs(gh - oh).sum() <= 2e-4 * oh.sum() + h["n_grazing"]
+    OR.check_class(rep, rec["stats"], rec["hemi"]["n_grazing"], S, N)
+    OR.check_hist(hist, FS.unpack_hist(rec["stats"]["hist"]), int(cnt.astype(np.int64).sum()), rec["hemi"]["n_grazing"])
 
 
 def _check_setups(orc, su, rec):
-    o = rec["setups"]
-    got = {k: su[k] for k in ("min_count", "min_mask", "greedy_count", "greedy_mask")}
-    got["n_class"], got["code_hist"] = list(su["n_class"]), list(su["code_hist"])
-    if rec["axes"]["n_grazing"] == 0:
-        for k in ("min_count", "min_mask", "greedy_count", "greedy_mask", "n_class", "code_hist"):
-            assert got[k] == o[k], (k, got[k], o[k])
-    else:
-        # rows with a grazing axis ray may change class; the rest is unique,
-        # and the reported minimum must be exact on the GPU's own histogram
-        g = len(set(rec["axes"]["grazing_rows"]))
-        assert np.abs(np.array(got["code_hist"]) - np.array(o["code_hist"])).sum() <= 2 * g
-        assert np.abs(np.array(got["n_class"]) - np.array(o["n_class"])).sum() <= 2 * g
-        assert (got["min_count"], got["min_mask"]) == orc.min_setups_exact(np.array(got["code_hist"]))
+    OR.check_setups(orc, su, rec["setups"], rec["axes"]["grazing_rows"])
 
 
 def _single_part(ctx, orc, name, rec_all):
@@ -213,14 +174,7 @@ def test_batch64_every_row_matches_oracle(ctx, orc, tmp_path):
             raise AssertionError(f"part {p}: blocks {bad[:8]} differ: "
                                  f"{_diagnose(orc, m, sn, rec['hemi'], part_bits, bad, 0)}")
         r = res[p]
-        o = rec["stats"]
-        G, T = o["rows_with_grazing"], o["n_ties"]
-        assert abs(r["class"]["access"] - o["access"]) <= rec["hemi"]["n_grazing"] / (c * N) + 1e-12, p
-        tol = (T + 2 * G) / max(1, o["n_included"] - G)
-        assert max(abs(a - b) for a, b in zip(r["class"]["shares"], o["shares"])) <= tol + 1e-12, p
-        assert abs(r["class"]["conc"] - o["conc"]) <= 1e-4 + tol, p
-        if T + 2 * G == 0 and not r["class"]["near_tie"]:
-            assert r["class"]["multi_axis"] == o["multi_axis"], p
+        OR.check_class(r["class"], rec["stats"], rec["hemi"]["n_grazing"], c, N)
         _check_setups(orc, r["setups"], rec)
         n_graze += rec["hemi"]["n_grazing"]
         off += c

@@ -182,3 +182,43 @@ def test_server_poll_and_tickets(ctx, pool):
         sv.submit(5, m.verts, m.tris, 0, 3, 30.0)  # no samples
     sv.drain(10_000)
     sv.close()
+
+
+def test_served_results_match_oracle(pool):
+    """Continuous serving of a mix (several requests per batch, hierarchies
+    resident between them): each served class and setup report against the
+    CPU oracle's own result for that request (its samples, its
+    padded-hierarchy cast of the hemisphere and the six axes, its statistics,
+    class and setups), with the allowances grazing rays and flagged ties
+    leave (tests/oracle_records.py)."""
+    from paper_2609_05467_amd import hra
+    from oracle import oracle as orc
+    import full_size as FS
+    import oracle_records as OR
+    sv = hra.Server(0, n_dirs=N_DIRS, mode=hra.SERVE_CONTINUOUS, max_batch=8)
+    reqs = _mix(pool, 16, seed=7)
+    _say("served vs oracle", len(reqs))
+    tickets = []
+    for i, (k, n, seed, tool) in enumerate(reqs):
+        tickets.append(sv.submit(k, pool[k].verts, pool[k].tris, n, seed, tool))
+        if i % 4 == 3:
+            time.sleep(0.002)
+    results = [sv.wait(t, 60_000) for t in tickets]
+    st = sv.stats()
+    sv.close()
+    assert st["batches"] < len(reqs)
+    dirs = orc.fibonacci_dirs(N_DIRS)
+    hier = {}
+    for (k, n, seed, tool), r in zip(reqs, results):
+        assert r is not None and r["status"] == 0, r
+        m = pool[k]
+        if k not in hier:
+            hier[k] = orc.BVHCast(m.verts, m.tris)
+        s = orc.sample_area(m.verts, m.tris, n, seed)
+        bits, gr, _ = hier[k].cast(s, dirs)
+        rows, _ = FS.flagged(gr)
+        ost, _ = OR.stats_record(orc, s, dirs, bits, rows, hist=False)
+        OR.check_class(r["class"], ost, len(rows), n, N_DIRS)
+        a6, g6, _ = hier[k].cast(s, orc.axes6(), kind=1)
+        rows6, _ = FS.flagged(g6)
+        OR.check_setups(orc, r["setups"], OR.setups_record(orc, m, s, a6, tool), rows6)
