@@ -115,16 +115,16 @@ def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit, kernel="k_cast_
                                                 "peak because L2 and the MALL serve them"}}
 
 
-# Tool-aware cast (hra_cast_tool): FP32 operations per node visit (two slab
-# tests against grown boxes: 28 each), per screened triangle (the FP32
-# bounding-sphere screen every candidate takes: centroid 9, farthest-vertex
-# radius 26, distance from the axis 22) and FP64 operations per distance test (the half-line
-# meeting test 76, the point-triangle distance 60, three edge distances 110
-# each, no early exit).  FP64 vector arithmetic runs at one operation per
-# lane and clock on this chip, like FP32 without packing, so all count
-# against the same peak.  The plane screen some candidates also take is not
-# counted.
-TOOL_NODE_OPS, TOOL_SCREEN_OPS, TOOL_TRI_OPS = 56, 57, 470
+# Tool-aware cast (hra_cast_tool), flops counted from its source as for the
+# hemisphere cast: FP32 per node visit 51 (two slab tests against boxes
+# grown through shifted origins, 25 each, and the near-far compare), per
+# screened triangle 57 (the bounding-sphere screen every candidate takes:
+# centroid 8, farthest-vertex radius 18, distance from the axis 28, the
+# compare 3; the plane screen some also take is not counted); FP64 per
+# distance test 352 (the half-line meeting test 64, the squared point-triangle
+# distance 70, three squared edge distances 72 each, without early exits).
+TOOL_NODE_FLOPS, TOOL_SCREEN_FLOPS, TOOL_TEST_FLOPS = 51, 57, 352
+FP64_PEAK_TFLOPS = 78.6
 TOOL_RADIUS_MM = 3.0
 CUT_LENGTH_MM, HOLDER_RADIUS_MM = 20.0, 8.0   # a 6 mm ball-end cutter, 20 mm of flute, a 16 mm holder
 
@@ -154,12 +154,17 @@ def tool_extra(ctx, bvh, samples, N, reps=3):
     hms = e0.elapsed_time(e1)
     holder = {"cut_length_mm": CUT_LENGTH_MM, "holder_radius_mm": HOLDER_RADIUS_MM, "ms": hms,
               "dirs_per_s": rays / (hms * 1e-3), "free_fraction": int(hc.to(torch.int64).sum()) / rays}
-    ops = nv * TOOL_NODE_OPS + ns * TOOL_SCREEN_OPS + nt * TOOL_TRI_OPS
-    return {"radius_mm": TOOL_RADIUS_MM, "ms": ms, "dirs_per_s": rays / (ms * 1e-3),
+    f32 = nv * TOOL_NODE_FLOPS + ns * TOOL_SCREEN_FLOPS
+    f64 = nt * TOOL_TEST_FLOPS
+    t = ms * 1e-3
+    return {"radius_mm": TOOL_RADIUS_MM, "ms": ms, "dirs_per_s": rays / t,
             "node_visits_per_dir": nv / rays, "screened_tris_per_dir": ns / rays, "distance_tests_per_dir": nt / rays,
             "instrumented_bits_identical": bool(torch.equal(wb, bits)), "free_fraction": free / rays, "holder": holder,
-            "roofline": {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": ALU_PEAK_TOPS, "unit": "Top/s",
-                         "frac": ops / (ms * 1e-3) / 1e12 / ALU_PEAK_TOPS, "ops_per_dir": ops / rays}}
+            "roofline": {"bound": "alu", "achieved": (f32 + f64) / t / 1e12, "unit": "TFLOP/s",
+                         "peak": FP32_PEAK_TFLOPS, "fp32_tflops": f32 / t / 1e12, "fp64_tflops": f64 / t / 1e12,
+                         "frac": f32 / t / 1e12 / FP32_PEAK_TFLOPS + f64 / t / 1e12 / FP64_PEAK_TFLOPS,
+                         "note": "frac = FP32 flops / 157.3 TFLOP/s + FP64 flops / 78.6 TFLOP/s over the launch",
+                         "fp32_flops_per_dir": f32 / rays, "fp64_flops_per_dir": f64 / rays}}
 
 
 # Canonical frame (hra_frame_estimate), algorithmic HBM bytes: per face the
