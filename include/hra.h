@@ -298,6 +298,16 @@ typedef struct {
     void *totals;     /* device scratch of hra_dirstats_bytes() bytes: part totals */
 } hra_dirstats;
 
+/* The azimuth boundary table hra_dominant_axes bins with, for checking
+ * (host only, no device or context): 4 quadrants (index 2 * (x < 0) +
+ * (y < 0), sign bits) x 129 cells over the pseudo-angle p = |y| / (|x| +
+ * |y|) in [0, 1] (cell floor(128 p)), each 4 floats: the last sector
+ * boundary in p at or below the cell's start, the next boundary, and the
+ * sectors (bit patterns of uint32 byte offsets, 4 x sector) below and at or
+ * above that next boundary.  Returns the float count (2064); writes `out`
+ * only when capacity is at least that. */
+int32_t hra_debug_azimuth_table(float *out, int32_t capacity);
+
 /* Bytes needed for hra_dirstats.totals for n samples. */
 int64_t hra_dirstats_bytes(int64_t n);
 
@@ -306,9 +316,13 @@ int64_t hra_dirstats_bytes(int64_t n);
  * Per sample with set U of unobstructed directions d_j (world frame, as
  * cast): mean m = sum d_j / |U|, absmean A_k = sum |d_jk| / |U|; dominant
  * axis = smallest k with |m_k| >= (1 - 1e-5) max |m|; concentration
- * A_axis / (A_x + A_y + A_z).  Sums in FP64.  Histogram bin =
- * zb * 128 + az with zb = min(63, floor((d_z/|d| + 1) 32)) and
- * az = min(127, floor((atan2(d_y, d_x) + pi) 128 / (2 pi))), FP64.
+ * A_axis / (A_x + A_y + A_z).  m is the frame applied in FP64 to the FP64
+ * sum of the local-frame directions; A is summed in FP32 over at most 64
+ * terms per lane and 4096-direction chunk, then in FP64 (relative error
+ * below 4e-6).  Histogram bin = zb * 128 + az with zb = min(63,
+ * floor((d_z/|d| + 1) 32)) and az = min(127, floor((atan2(d_y, d_x) + pi)
+ * 128 / (2 pi))) as in FP64: taken in FP32 where the coordinates lie clear
+ * of a bin edge, else by that FP64 formula.
  * Part totals (counts per axis, blind samples, total unobstructed rays, sum
  * of concentrations in a fixed order) go to out->totals for hra_classify. */
 hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,

@@ -246,6 +246,9 @@ hipError_t launch_fibonacci(int32_t n, float4 *out, hipStream_t s);
 // Look up, once per device, the address of the statistics' allocation-free
 // scratch array; called by hra_ctx_create with `device` current.
 hipError_t noalloc_setup(int device);
+// Upload, once per device, the statistics' azimuth boundary table to its
+// device array; called by hra_ctx_create with `device` current.
+hipError_t stats_setup(int device);
 hra_status check_error_word(hra_ctx *ctx, hipStream_t s);
 int blocks_for(int64_t n, int threads);
 

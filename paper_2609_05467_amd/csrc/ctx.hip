@@ -172,7 +172,7 @@ hra_status hra_ctx_create(int32_t device, hra_ctx **out) {
         return HRA_ERR_DEVICE;
     }
     ctx->n_cu = prop.multiProcessorCount;
-    if (noalloc_setup(device) != hipSuccess) {
+    if (noalloc_setup(device) != hipSuccess || stats_setup(device) != hipSuccess) {
         delete ctx;
         return HRA_ERR_DEVICE;
     }

@@ -20,89 +20,164 @@ struct DirTotals {
 };
 
 constexpr int HIST_BINS = 8192;
-constexpr float HIST_EDGE = 5e-4f;   // bins: distance from an edge below which FP64 decides
+constexpr float HIST_EDGE = 5e-4f;   // zenith bins: distance from an edge below which FP64 decides
 
-// atan(r) on [0, 1] as r * P(r^2): least-squares fit on Chebyshev-spaced
-// nodes, reweighted towards the largest errors; the largest error of the
-// FP32 evaluation is 3.3e-7 rad.
-constexpr float ATAN_C[7] = {0.9999961256980896f, -0.3331736922264099f, 0.19807815551757812f, -0.1323334127664566f,
-                             0.07962365448474884f, -0.033604204654693604f, 0.006811786908656359f};
+// Azimuth sectors.  Within a quadrant the pseudo-angle p = |y| / (|x| + |y|)
+// rises strictly with a = atan2(|y|, |x|) in [0, pi/2], so the sector
+// boundaries a_k = k pi / 64 (k = 0..32) are boundaries p_k of p.  A table
+// of AZ_CELLS + 1 cells per quadrant over p in [0, 1] holds, for each cell,
+// the last boundary at or below the cell's start, the next boundary, and the
+// sector (as a byte offset into a histogram row) on either side of that next
+// boundary.  Boundaries lie at least 0.5 pi/64 = 0.0245 apart in p (dp/da
+// is 1 / (cos a + sin a)^2 >= 1/2), more than a cell's width, so a cell holds
+// at most one.  The FP32 p (one add, the hardware reciprocal, one multiply)
+// is within 2e-7 of the exact value and the table's FP32 boundaries within
+// 6e-8, so wherever p lies at least AZ_EPS from both boundaries the FP32
+// comparison gives the sector of the exact angle.
+constexpr int AZ_CELLS = 128;
+constexpr int AZ_TAB = 4 * (AZ_CELLS + 1);
+constexpr float AZ_EPS = 4e-6f;
+static __device__ float4 az_table[AZ_TAB];
 
-// (atan2(y, x) + pi) * 64 / pi, the azimuth in histogram-sector units, from
-// the octant and the polynomial above.  x = y = 0 gives NaN, which the
-// caller's edge test sends to the FP64 path.
-__device__ inline float azimuth_bins(float x, float y) {
-    const float ax = fabsf(x), ay = fabsf(y);
-    const float r = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(ax, ay));
-    const float r2 = r * r;
-    float p = ATAN_C[6];
-    for (int k = 5; k >= 0; --k) p = fmaf(p, r2, ATAN_C[k]);
-    float a = r * p;
-    a = ay > ax ? 1.57079637f - a : a;
-    a = x < 0.0f ? 3.14159274f - a : a;
-    a = y < 0.0f ? -a : a;
-    return (a + 3.14159274f) * 20.3718327f;
+// Directions per wave whose bin is taken in FP64 after the sample (beyond
+// this many, in place).
+constexpr int EDGE_Q = 64;
+constexpr int DS_WAVES = 8;           // waves per k_dirstats block
+constexpr int DS_BLOCKS_PER_CU = 3;   // LDS: 3 x 46.3 KiB of the 160 KiB
+
+__device__ inline bool near_zenith_edge(float xz) {
+    const float f = __builtin_amdgcn_fractf(xz);
+    return !(fabsf(f - 0.5f) < 0.5f - HIST_EDGE);
 }
 
-// One wavefront per sample: lanes stride over the directions, FP64 sums,
-// wave butterfly reduction.  The histogram (when asked for) is privatised in
-// LDS per block and written out without atomics to a per-block slice;
-// k_hist_reduce sums the slices (integer sums: the same in any order).  Part
-// totals are formed afterwards from the per-sample outputs by k_part_totals.
-__global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n, const float4 *dirs, int32_t N,
-                                                  int32_t W, const uint32_t *bits, hra_dirstats out, double *conc64,
-                                                  uint32_t *cnt_out, uint32_t *hist_part) {
+// Histogram bin of direction d by the definition, in FP64.
+__device__ __noinline__ int hist_bin_fp64(float fx, float fy, float fz) {
+    const double pi = 3.14159265358979323846264338327950288;
+    const double dx = fx, dy = fy, dz = fz;
+    int zb = (int)floor((dz / sqrt(dx * dx + dy * dy + dz * dz) + 1.0) * 32.0);
+    int az = (int)floor((atan2(dy, dx) + pi) * 128.0 / (2.0 * pi));
+    zb = zb > 63 ? 63 : (zb < 0 ? 0 : zb);
+    az = az > 127 ? 127 : (az < 0 ? 0 : az);
+    return zb * 128 + az;
+}
+
+// One wavefront per sample, DS_WAVES per block.  Per 4096-direction chunk the
+// wave stages the row's bit words in LDS (zero past the last direction) and
+// each lane takes directions lane, lane + 64, ...; for a free direction l
+// (local frame) it adds l to FP64 sums, rotates it to d = R l and adds
+// |d| to FP32 sums (at most 64 terms per lane per chunk, folded into FP64 at
+// the chunk's end: relative error below 4e-6), and bins d.  The world mean
+// is R applied once, in FP64, to the local sum: the same quantity as the sum
+// of the rotated directions, without their per-term rounding.
+//
+// Zenith: (d_z + 1) 32 in FP32 without renormalising d.  |d| is 1 within
+// 6e-7 for a unit normal (|n|^2 within 1e-6 of 1, as sampled) and a table of
+// unit directions, so the FP32 coordinate is within 3e-5 bins of the FP64
+// one (d_z / |d| + 1) 32; outside HIST_EDGE of an edge both give one bin.
+// Azimuth: the pseudo-angle table above.  A direction near an edge, or of a
+// sample whose normal is not unit, goes to a per-wave LDS queue and is binned
+// by the FP64 definition after the sample's loop, with all lanes.
+//
+// The histogram is privatised in LDS per block and written out without
+// atomics to a per-block slice; k_hist_reduce sums the slices (integer sums:
+// the same in any order).  Part totals are formed afterwards from the
+// per-sample outputs by k_part_totals.
+__global__ __launch_bounds__(64 * DS_WAVES) __attribute__((amdgpu_waves_per_eu(6))) void k_dirstats(const float *normal, int64_t n, const float4 *dirs,
+                                                            int32_t N, int32_t W, const uint32_t *bits,
+                                                            hra_dirstats out, double *conc64, uint32_t *cnt_out,
+                                                            uint32_t *hist_part, const float4 *az_tab_g) {
     __shared__ uint32_t h[HIST_BINS];
-    if (hist_part) {
+    __shared__ float4 az_tab[AZ_TAB];
+    __shared__ uint32_t rowbuf[DS_WAVES][128];
+    __shared__ int32_t edgeq[DS_WAVES][EDGE_Q];
+    __shared__ int32_t edgen[DS_WAVES];
+    const bool want_hist = hist_part != nullptr;
+    if (want_hist) {
         for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) h[k] = 0;
+        for (int k = threadIdx.x; k < AZ_TAB; k += blockDim.x) az_tab[k] = az_tab_g[k];
         __syncthreads();
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    const double pi = 3.14159265358979323846264338327950288;
-    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < n; s += nwaves) {
+    const int64_t nwaves = (int64_t)gridDim.x * DS_WAVES;
+    for (int64_t s = (int64_t)blockIdx.x * DS_WAVES + wv; s < n; s += nwaves) {
         const float nx = normal[3 * s], ny = normal[3 * s + 1], nz = normal[3 * s + 2];
         float3 t, b;
         onb_frame(nx, ny, nz, t, b);
-        double sm0 = 0, sm1 = 0, sm2 = 0, sa0 = 0, sa1 = 0, sa2 = 0;
+        const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+        const bool unit = fabsf(nn - 1.0f) <= 1e-6f;
+        double sl0 = 0, sl1 = 0, sl2 = 0, sa0 = 0, sa1 = 0, sa2 = 0;
         uint32_t cnt = 0;
-        for (int32_t j = lane; j < N; j += 64) {
-            if (!((bits[s * W + (j >> 5)] >> (j & 31)) & 1u)) continue;
-            const float4 l = dirs[j];
-            const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
-            const double dx = d.x, dy = d.y, dz = d.z;
-            sm0 += dx;
-            sm1 += dy;
-            sm2 += dz;
-            sa0 += fabs(dx);
-            sa1 += fabs(dy);
-            sa2 += fabs(dz);
-            ++cnt;
-            if (hist_part) {
-                // Bin coordinates in FP32 first; the bin is taken from them
-                // unless they lie within HIST_EDGE of a bin edge, where the
-                // FP64 coordinates decide.  The FP32 coordinates are within
-                // 5e-5 bin of the FP64 ones (hardware reciprocal square root
-                // and reciprocal, 1 ulp; arctangent polynomial, 3.3e-7 rad),
-                // so both give the same bin.
-                const float len2 = fmaf(d.x, d.x, fmaf(d.y, d.y, d.z * d.z));
-                const float xz = fmaf(d.z * __builtin_amdgcn_rsqf(len2), 32.0f, 32.0f);
-                const float xa = azimuth_bins(d.x, d.y);
-                const float fz = xz - floorf(xz), fa = xa - floorf(xa);
-                int zb, az;
-                if (fz > HIST_EDGE && fz < 1.0f - HIST_EDGE) zb = (int)floorf(xz);
-                else zb = (int)floor((dz / sqrt(dx * dx + dy * dy + dz * dz) + 1.0) * 32.0);
-                if (fa > HIST_EDGE && fa < 1.0f - HIST_EDGE) az = (int)floorf(xa);
-                else az = (int)floor((atan2(dy, dx) + pi) * 128.0 / (2.0 * pi));
-                zb = zb > 63 ? 63 : (zb < 0 ? 0 : zb);
-                az = az > 127 ? 127 : (az < 0 ? 0 : az);
-                atomicAdd(&h[zb * 128 + az], 1u);
+        edgen[wv] = 0;
+        for (int32_t c = 0; c < W; c += 128) {
+            const int32_t cw = W - c < 128 ? W - c : 128;
+            // an odd word count leaves the upper half-wave of the chunk's
+            // last step one word past the row: that word is staged as zero
+            const int32_t cwp = (cw + 1) & ~1;
+            __builtin_amdgcn_wave_barrier();
+            for (int32_t k = lane; k < cwp; k += 64) {
+                uint32_t wd = k < cw ? bits[s * W + c + k] : 0u;
+                if (c + k == W - 1 && (N & 31)) wd &= (1u << (N & 31)) - 1u;
+                rowbuf[wv][k] = wd;
+                cnt += __popc(wd);
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int32_t j0 = 32 * c;
+            const int32_t nj = N - j0 < 4096 ? N - j0 : 4096;
+            const int32_t last = N - 1;
+            float fa0 = 0.f, fa1 = 0.f, fa2 = 0.f;
+            float4 lnext = dirs[min(j0 + lane, last)];
+            for (int32_t i = 0; i < nj; i += 64) {
+                const int32_t j = j0 + i + lane;
+                const float4 l = lnext;
+                lnext = dirs[min(j + 64, last)];
+                const uint32_t wd = rowbuf[wv][(i >> 5) + (lane >> 5)];
+                if ((wd >> (lane & 31)) & 1u) {
+                    sl0 += (double)l.x;
+                    sl1 += (double)l.y;
+                    sl2 += (double)l.z;
+                    const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+                    fa0 += fabsf(d.x);
+                    fa1 += fabsf(d.y);
+                    fa2 += fabsf(d.z);
+                    if (want_hist) {
+                        const float xz = fmaf(d.z, 32.0f, 32.0f);
+                        const float p = fabsf(d.y) * __builtin_amdgcn_rcpf(fabsf(d.x) + fabsf(d.y));
+                        const uint32_t cell = (uint32_t)(p * (float)AZ_CELLS);
+                        const uint32_t q = ((__float_as_uint(d.x) >> 31) << 1) | (__float_as_uint(d.y) >> 31);
+                        const float4 e = az_tab[q * (AZ_CELLS + 1) + (cell < AZ_CELLS ? cell : AZ_CELLS)];
+                        // NaN p (x = y = 0) fails the comparison: FP64 path
+                        const bool clear = fminf(p - e.x, fabsf(e.y - p)) >= AZ_EPS;
+                        if (unit && clear && !near_zenith_edge(xz)) {
+                            const uint32_t zb = min((uint32_t)xz, 63u);
+                            const uint32_t az4 = __float_as_uint(p >= e.y ? e.w : e.z);
+                            atomicAdd((uint32_t *)((char *)h + (zb << 9) + az4), 1u);
+                        } else {
+                            const int slot = atomicAdd(&edgen[wv], 1);
+                            if (slot < EDGE_Q) edgeq[wv][slot] = j;
+                            else atomicAdd(&h[hist_bin_fp64(d.x, d.y, d.z)], 1u);
+                        }
+                    }
+                }
+            }
+            sa0 += (double)fa0;
+            sa1 += (double)fa1;
+            sa2 += (double)fa2;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (want_hist) {
+            const int32_t qn = edgen[wv];
+            const int32_t ne = qn < EDGE_Q ? qn : EDGE_Q;
+            for (int32_t k = lane; k < ne; k += 64) {
+                const int32_t j = edgeq[wv][k];
+                const float4 l = dirs[j];
+                const float3 d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+                atomicAdd(&h[hist_bin_fp64(d.x, d.y, d.z)], 1u);
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
-            sm0 += __shfl_xor(sm0, off);
-            sm1 += __shfl_xor(sm1, off);
-            sm2 += __shfl_xor(sm2, off);
+            sl0 += __shfl_xor(sl0, off);
+            sl1 += __shfl_xor(sl1, off);
+            sl2 += __shfl_xor(sl2, off);
             sa0 += __shfl_xor(sa0, off);
             sa1 += __shfl_xor(sa1, off);
             sa2 += __shfl_xor(sa2, off);
@@ -111,28 +186,68 @@ __global__ __launch_bounds__(256) void k_dirstats(const float *normal, int64_t n
         // every lane holds the totals after the butterfly; all lanes store the
         // same values, with no lane-dependent branch ahead of the next
         // iteration's shuffles
+        const double tx = t.x, ty = t.y, tz = t.z, bx = b.x, by = b.y, bz = b.z;
+        const double sm0 = tx * sl0 + bx * sl1 + (double)nx * sl2;
+        const double sm1 = ty * sl0 + by * sl1 + (double)ny * sl2;
+        const double sm2 = tz * sl0 + bz * sl1 + (double)nz * sl2;
         const bool blind = cnt == 0;
-        const double c = blind ? 1.0 : (double)cnt;
-        const double m[3] = {sm0 / c, sm1 / c, sm2 / c}, A[3] = {sa0 / c, sa1 / c, sa2 / c};
+        const double cd = blind ? 1.0 : (double)cnt;
+        const double m[3] = {sm0 / cd, sm1 / cd, sm2 / cd}, A[3] = {sa0 / cd, sa1 / cd, sa2 / cd};
         const double am[3] = {fabs(m[0]), fabs(m[1]), fabs(m[2])};
         const double mx = fmax(am[0], fmax(am[1], am[2]));
         int k = 0;
         while (k < 2 && !(am[k] >= (1.0 - 1e-5) * mx)) ++k;
         const double den = A[0] + A[1] + A[2];
         const double cc = blind ? 0.0 : A[k] / den;
-        const int q = lane % 3;
-        out.mean[3 * s + q] = blind ? 0.0f : (float)m[q];
-        out.absmean[3 * s + q] = blind ? 0.0f : (float)A[q];
+        const int qq = lane % 3;
+        out.mean[3 * s + qq] = blind ? 0.0f : (float)m[qq];
+        out.absmean[3 * s + qq] = blind ? 0.0f : (float)A[qq];
         out.axis[s] = blind ? (int8_t)-1 : (int8_t)k;
         out.conc[s] = (float)cc;
         conc64[s] = cc;
         cnt_out[s] = cnt;
     }
-    if (hist_part) {
+    if (want_hist) {
         __syncthreads();
         uint32_t *dst = hist_part + (int64_t)blockIdx.x * HIST_BINS;
         for (int k = threadIdx.x; k < HIST_BINS; k += blockDim.x) dst[k] = h[k];
     }
+}
+
+// The azimuth table, in FP64 on the host: boundary p_k = sin a_k / (sin a_k
+// + cos a_k), and for quadrant (sign of x, sign of y) the sector of a
+// quadrant angle in [a_k, a_k+1): a = phi (x, y >= 0), pi - phi (x < 0 <= y),
+// phi + pi (x, y < 0), -phi (y < 0 <= x), with phi = atan2(y, x) and sector
+// floor((phi + pi) 64 / pi).
+static std::vector<float4> make_az_table() {
+    const double pi = 3.14159265358979323846264338327950288;
+    double pk[33];
+    for (int k = 0; k <= 32; ++k) {
+        const double a = k * pi / 64.0;
+        pk[k] = k == 32 ? 1.0 : std::sin(a) / (std::sin(a) + std::cos(a));
+    }
+    auto as_float = [](uint32_t u) {
+        float f;
+        std::memcpy(&f, &u, sizeof f);
+        return f;
+    };
+    std::vector<float4> tab(AZ_TAB);
+    for (int q = 0; q < 4; ++q) {
+        const int sx = q >> 1, sy = q & 1;
+        auto sector4 = [&](int k) {
+            k = k > 31 ? 31 : k;
+            return 4u * (uint32_t)((sy ? 0 : 64) + ((sx ^ sy) ? 63 - k : k));
+        };
+        for (int c = 0; c <= AZ_CELLS; ++c) {
+            const double lo = (double)c / AZ_CELLS;
+            int kb = 0;
+            for (int k = 1; k <= 31; ++k)
+                if (pk[k] <= lo) kb = k;
+            tab[q * (AZ_CELLS + 1) + c] = make_float4((float)pk[kb], (float)pk[kb + 1], as_float(sector4(kb)),
+                                                      as_float(sector4(kb + 1)));
+        }
+    }
+    return tab;
 }
 
 // Part totals, one block per part over its sample range [base, base + n)
@@ -373,14 +488,39 @@ extern "C" int64_t hra_dirstats_bytes(int64_t n) {
 
 namespace hra {
 
-// Blocks of a k_dirstats launch over n samples: four samples per block at
-// first, at most four blocks per compute unit, and at most max_blocks.
+// Blocks of a k_dirstats launch over n samples: DS_WAVES samples per block at
+// first, at most DS_BLOCKS_PER_CU blocks per compute unit (one wave of
+// blocks), and at most max_blocks.
 static int64_t dirstats_blocks(const hra_ctx *ctx, int64_t n, int64_t max_blocks) {
-    int64_t blocks = (n + 3) / 4;
-    const int64_t cap = (int64_t)ctx->n_cu * 4;
+    int64_t blocks = (n + DS_WAVES - 1) / DS_WAVES;
+    const int64_t cap = (int64_t)ctx->n_cu * DS_BLOCKS_PER_CU;
     if (blocks > cap) blocks = cap;
     if (blocks > max_blocks) blocks = max_blocks;
     return blocks < 1 ? 1 : blocks;
+}
+
+// Per device, once: the azimuth table uploaded to `az_table` there, and the
+// array's address on that device.
+static std::mutex az_mu;
+static std::map<int, const float4 *> az_ptr;
+
+hipError_t stats_setup(int device) {
+    std::lock_guard<std::mutex> lk(az_mu);
+    if (az_ptr.count(device)) return hipSuccess;
+    const std::vector<float4> tab = make_az_table();
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(az_table), tab.data(), sizeof(float4) * tab.size());
+    if (e != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(az_table));
+    if (e != hipSuccess) return e;
+    az_ptr[device] = (const float4 *)p;
+    return hipSuccess;
+}
+
+static const float4 *az_table_ptr(int device) {
+    std::lock_guard<std::mutex> lk(az_mu);
+    auto it = az_ptr.find(device);
+    return it == az_ptr.end() ? nullptr : it->second;
 }
 
 // hist: also form the direction histogram, from per-block slices in
@@ -390,6 +530,8 @@ hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const f
                            const uint32_t *bits, const hra_dirstats &out, double *c64, uint32_t *cnt, bool hist,
                            hipStream_t s, uint32_t *slices, int64_t max_blocks) {
     if (n <= 0) return hipSuccess;
+    const float4 *az = az_table_ptr(ctx->device);
+    if (hist && !az) return hipErrorNotInitialized;
     const int64_t blocks = dirstats_blocks(ctx, n, max_blocks);
     uint32_t *part = slices;
     hipError_t e = hipSuccess;
@@ -397,8 +539,8 @@ hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const f
         e = hipMallocAsync((void **)&part, sizeof(uint32_t) * HIST_BINS * (size_t)blocks, s);
         if (e != hipSuccess) return e;
     }
-    k_dirstats<<<(unsigned)blocks, 256, 0, s>>>(normal, n, table, N, (N + 31) / 32, bits, out, c64, cnt,
-                                                hist ? part : nullptr);
+    k_dirstats<<<(unsigned)blocks, 64 * DS_WAVES, 0, s>>>(normal, n, table, N, (N + 31) / 32, bits, out, c64, cnt,
+                                                         hist ? part : nullptr, az);
     if (hist) {
         k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out.hist, HIST_BINS);
         k_hist_reduce<<<dim3(HIST_BINS / 256, HR_CHUNKS), 256, 0, s>>>(part, (int)blocks, out.hist);
@@ -495,6 +637,13 @@ void classify_from_device_totals(const void *host_totals, int64_t n, int32_t n_d
 }
 }  // namespace hra
 
+extern "C" int32_t hra_debug_azimuth_table(float *out, int32_t capacity) {
+    const std::vector<float4> tab = hra::make_az_table();
+    const int32_t nf = (int32_t)(4 * tab.size());
+    if (out && capacity >= nf) std::memcpy(out, tab.data(), sizeof(float) * nf);
+    return nf;
+}
+
 extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
                                         const hra_dirstats *out, void *stream) {
     if (!ctx || !samples || !out) return HRA_ERR_INVALID_ARG;
@@ -533,13 +682,14 @@ namespace hra {
 // canonical direction table, cached per context, and the per-block
 // histogram slices, taken from the stream-ordered allocator) in this array
 // instead: NA_MAX_DIRS float4 table entries, then NA_SLICES slices of
-// HIST_BINS words (NA_SLICES = four blocks on each of MI355X's 256 compute
-// units, the cap of the allocating launch, so both launch the same grid
-// there).  The module holds one copy per device until the process ends.
+// HIST_BINS words (NA_SLICES is at least DS_BLOCKS_PER_CU blocks on each of
+// MI355X's 256 compute units, the cap of the allocating launch, so both
+// launch the same grid there).  The module holds one copy per device until the process ends.
 // Host code never names the array: it uses the address that
 // hipGetSymbolAddress returned for the current device (noalloc_setup).
 constexpr int32_t NA_MAX_DIRS = 8192;
 constexpr int64_t NA_SLICES = 1024;
+static_assert(NA_SLICES >= 256 * DS_BLOCKS_PER_CU, "slices for one block wave on 256 compute units");
 constexpr size_t NA_TABLE_BYTES = sizeof(float4) * NA_MAX_DIRS;
 constexpr size_t NA_SCRATCH_BYTES = NA_TABLE_BYTES + sizeof(uint32_t) * HIST_BINS * NA_SLICES;
 static __device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];

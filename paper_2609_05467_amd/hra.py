@@ -163,6 +163,7 @@ def lib():
             "hra_get_cast_config": ([P, C.POINTER(CastConfig)], C.c_int),
             "hra_debug_rays": ([P, C.POINTER(Samples), Dirs, P, i64, P, P], C.c_int),
             "hra_dirstats_bytes": ([i64], i64),
+            "hra_debug_azimuth_table": ([P, i32], i32),
             "hra_dominant_axes": ([P, C.POINTER(Samples), Dirs, P, C.POINTER(DirStats), P], C.c_int),
             "hra_dominant_axes_noalloc": ([P, C.POINTER(Samples), Dirs, P, C.POINTER(DirStats), P], C.c_int),
             "hra_classify": ([P, C.POINTER(DirStats), i64, i32, C.POINTER(Thresholds), C.POINTER(ClassReport), P],
@@ -224,7 +225,7 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy",
            "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply", "hra_stl_read", "hra_stl_copy",
            "hra_stl_free", "hra_stl_error", "hra_cast_tool", "hra_cast_tool_work",
-           "hra_cast_tool_holder", "hra_dominant_axes_noalloc"]
+           "hra_cast_tool_holder", "hra_dominant_axes_noalloc", "hra_debug_azimuth_table"]
 FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
