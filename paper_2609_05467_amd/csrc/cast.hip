@@ -530,6 +530,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k
     }
 }
 
+// One unit of the step loop for a lane's current ray in the refilled casts:
+// a triangle test while the lane holds a leaf, else a stack pop and/or a node
+// visit, in the visit order of occluded_step.  `win` bounds the near
+// distance of a box that is entered (WINDOW; otherwise unbounded), in units
+// of the ray's direction; triangles take the exact half-line test.  Sets
+// hit, done (stack empty) or bad (a guard tripped).
+template <int STACK, bool STATS, bool WINDOW>
+__device__ __forceinline__ void step_unit(const CastJob &J, float ox, float oy, float oz, float dx, float dy, float dz,
+                                          float ix, float iy, float iz, float kd, float win, lds_int *lds, int lane,
+                                          int *spill, uint32_t last_node, uint32_t last_tri, int32_t &node, int32_t &sp,
+                                          int32_t &ti, int32_t &tn, WorkCount &wc, bool &hit, bool &done, bool &bad) {
+    asm volatile("" : "+v"(tn));
+    if (tn > 0) {
+        bad = (uint32_t)ti > last_tri;
+        const float4 *tp = J.tris + 3 * (uint64_t)min((uint32_t)ti, last_tri);
+        if (STATS) ++wc.tris;
+        hit = tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(tp), gload_f4(tp + 1), gload_f4(tp + 2));
+        ++ti;
+        --tn;
+        return;
+    }
+    bool visit = true;
+    if (node < 0) {
+        if (sp == 0) {
+            done = true;
+            visit = false;
+        } else {
+            --sp;
+            int32_t itm;
+            if (sp < STACK) itm = lds[sp * 64 + lane];
+            else itm = spill[sp - STACK];
+            if (is_leaf(itm)) {
+                ti = leaf_first(itm);
+                tn = leaf_count(itm);
+                visit = false;
+            } else {
+                node = itm;
+            }
+        }
+    }
+    if (visit) {
+        bad = (uint32_t)node > last_node;
+        const Node *nd = J.nodes + min((uint32_t)node, last_node);
+        if (STATS) ++wc.nodes;
+        const float4 A = gload_f4(&nd->a), B = gload_f4(&nd->b), C = gload_f4(&nd->c);
+        const int4 D = gload_i4(&nd->d);
+        float t0, t1;
+        bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, ox, oy, oz, ix, iy, iz, t0);
+        bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, ox, oy, oz, ix, iy, iz, t1);
+        if (WINDOW) {
+            h0 = h0 && t0 <= win;
+            h1 = h1 && t1 <= win;
+        }
+        const int32_t c0 = D.x, c1 = D.y;
+        const bool l0 = h0 && is_leaf(c0), l1 = h1 && is_leaf(c1);
+        const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
+        if (l0 || l1) {
+            const int32_t lc = l0 ? c0 : c1;
+            ti = leaf_first(lc);
+            tn = leaf_count(lc);
+        }
+        const bool push = (l0 && l1) || (g0 && g1);
+        const int32_t pv = (l0 && l1) ? c1 : (t0 <= t1 ? c1 : c0);
+        node = (g0 && g1) ? (t0 <= t1 ? c0 : c1) : (g0 ? c0 : (g1 ? c1 : -1));
+        if (push) {
+            if (sp < STACK) lds[sp * 64 + lane] = pv;
+            else if (sp < STACK + SPILL) spill[sp - STACK] = pv;
+            else bad = true;
+            ++sp;
+        }
+    }
+}
+
 // Hemisphere cast with refilled lanes.  The work item's rays (one sample's
 // directions in traversal order, or `group` samples' in a row) form a list
 // behind a workgroup counter in LDS.  A lane runs the step loop above on one
@@ -668,62 +741,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GROUPED ? 7
                 // one sample per item: the origin stays in scalar registers
                 const float rox = GROUPED ? ox : uox, roy = GROUPED ? oy : uoy, roz = GROUPED ? oz : uoz;
                 bool hit = false, done = false, bad = false;
-                asm volatile("" : "+v"(tn));
-                if (tn > 0) {
-                    bad = (uint32_t)ti > last_tri;
-                    const float4 *tp = J.tris + 3 * (uint64_t)min((uint32_t)ti, last_tri);
-                    if (STATS) ++wc.tris;
-                    hit = tri_hit(rox, roy, roz, dx, dy, dz, kd, gload_f4(tp), gload_f4(tp + 1), gload_f4(tp + 2));
-                    ++ti;
-                    --tn;
-                } else {
-                    bool visit = true;
-                    if (node < 0) {
-                        if (sp == 0) {
-                            done = true;
-                            visit = false;
-                        } else {
-                            --sp;
-                            int32_t itm;
-                            if (sp < STACK) itm = lds[sp * 64 + lane];
-                            else itm = spill[sp - STACK];
-                            if (is_leaf(itm)) {
-                                ti = leaf_first(itm);
-                                tn = leaf_count(itm);
-                                visit = false;
-                            } else {
-                                node = itm;
-                            }
-                        }
-                    }
-                    if (visit) {
-                        bad = (uint32_t)node > last_node;
-                        const Node *nd = J.nodes + min((uint32_t)node, last_node);
-                        if (STATS) ++wc.nodes;
-                        const float4 A = gload_f4(&nd->a), B = gload_f4(&nd->b), C = gload_f4(&nd->c);
-                        const int4 D = gload_i4(&nd->d);
-                        float t0, t1;
-                        const bool h0 = slab(A.x, A.y, A.z, A.w, B.x, B.y, rox, roy, roz, ix, iy, iz, t0);
-                        const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, rox, roy, roz, ix, iy, iz, t1);
-                        const int32_t c0 = D.x, c1 = D.y;
-                        const bool l0 = h0 && is_leaf(c0), l1 = h1 && is_leaf(c1);
-                        const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
-                        if (l0 || l1) {
-                            const int32_t lc = l0 ? c0 : c1;
-                            ti = leaf_first(lc);
-                            tn = leaf_count(lc);
-                        }
-                        const bool push = (l0 && l1) || (g0 && g1);
-                        const int32_t pv = (l0 && l1) ? c1 : (t0 <= t1 ? c1 : c0);
-                        node = (g0 && g1) ? (t0 <= t1 ? c0 : c1) : (g0 ? c0 : (g1 ? c1 : -1));
-                        if (push) {
-                            if (sp < STACK) lds[sp * 64 + lane] = pv;
-                            else if (sp < STACK + SPILL) spill[sp - STACK] = pv;
-                            else bad = true;
-                            ++sp;
-                        }
-                    }
-                }
+                step_unit<STACK, STATS, false>(J, rox, roy, roz, dx, dy, dz, ix, iy, iz, kd, 0.0f, lds, lane, spill,
+                                               last_node, last_tri, node, sp, ti, tn, wc, hit, done, bad);
                 ++iter;
                 bad = bad || iter > iter_cap;
                 if (hit || done || bad) {
@@ -743,43 +762,185 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GROUPED ? 7
     }
 }
 
-// Six-axis cast.  One work item = AX_PER_WAVE samples x 6 world axes on the
-// 60 first lanes of a wavefront.  A ray whose axis points into the material
-// (n . D < 0) is not cast.  The ballot follows the traversal directly and
-// the per-sample 6-bit groups are stored after it.
-constexpr int AX_PER_WAVE = 10;
+// Six-axis cast.  Axis rays are few (six per sample) but some are long: a
+// ray that runs along a wall, tangent to it, passes one box after another for
+// hundreds of node visits, while the median ray takes one step.  Cast one
+// ray per lane, a wavefront would iterate until its slowest lane ended, with
+// a few lanes busy: the kernel would be bound by issue slots spent on idle
+// lanes and then by a handful of dependent chains.  Here a workgroup takes
+// AX_GROUP samples and runs two phases, each over a list in LDS from which
+// every lane takes the next entry when its own ends (as in k_cast_refill):
+//   1. every cast ray (n . D >= 0; a ray pointing into the material is not
+//      cast), whole, for at most AX_BUDGET iterations of the step loop; a ray
+//      still undecided then is marked open;
+//   2. every open ray, cut into AX_SEGS pieces.
+// Each sample's six verdicts sit in an LDS word (bit k set while ray k is
+// free, bit 8 + k while it is open).
+//
+// Piece s of the ray o + t e (e = +-e_c) starts at o_s, equal to o but for
+// its c coordinate o_c + sign * t_exit s / AX_SEGS in FP32 (t_exit the
+// distance from o to the part's box face along e), so o_s lies on the ray at
+// or beyond o; it is the half-line from o_s whose boxes are entered within
+// win_s = |o_{s+1,c} - o_{s,c}| (1 + 1e-6) (the last piece: unbounded).
+// Consecutive pieces meet exactly (the same FP32 expression) and win_s
+// exceeds the slab test's relative error, so the windows cover the ray.  A
+// triangle a piece reports is hit by the half-line from o_s, hence by the
+// ray.  A triangle the ray hits at t is reported by the piece whose window
+// holds t: an axis ray's edge functions do not involve o_c (the c column of
+// the direction's cross products is zero), so they equal the unsplit ray's,
+// and only the plane side depends on the origin, which decides as for the
+// unsplit ray when o_s lies before the hit (a hit exactly at o_s is reported
+// by the piece before).  So the bits equal those of one unsplit cast.
+constexpr int AX_GROUP = 128;
+constexpr uint32_t AX_BUDGET = 48;
+constexpr int AX_SEGS = 16;
 // Most samples in one work item of the grouped hemisphere cast.
 constexpr int MAX_GROUP = 16;
 
-template <int STACK, bool STATS, bool STEP>
-__global__ __launch_bounds__(256) void k_cast_axes(CastArgs a) {
-    __shared__ int stk[4][STACK * 64];
-    const int lane = threadIdx.x & 63, wv = uni_i(threadIdx.x >> 6);
-    const int64_t item = (int64_t)blockIdx.x * 4 + wv;
-    if (item >= a.n_items) return;
+// One phase of k_cast_axes: the `total` entries of the phase's list, taken
+// by refilled lanes.  SPLIT: entry = (open ray, piece), else a whole ray.
+template <int STACK, bool STATS, bool SPLIT>
+__device__ __forceinline__ void axes_phase(const CastArgs &a, const CastJob &J, const PartMeta &P, int64_t s0,
+                                           const int32_t *list, int32_t total, uint32_t *word, int *ctr, lds_int *lds,
+                                           int lane, int wv, int32_t root, uint32_t iter_cap, uint32_t last_node,
+                                           uint32_t last_tri, WorkCount &wc) {
+    const bool root_leaf = is_leaf(root);
+    const float inv_segs = 1.0f / (float)AX_SEGS;
+    const float ZERO = 0.0f;
+    bool active = false;
+    float ox = ZERO, oy = ZERO, oz = ZERO, dx = ZERO, dy = ZERO, dz = ZERO, ix = ZERO, iy = ZERO, iz = ZERO;
+    float kd = ZERO, win = ZERO;
+    int32_t node = -1, sp = 0, ti = 0, tn = 0, g = 0, k = 0;
+    uint32_t iter = 0;
+    int spill[SPILL];
+    while (true) {
+        const int n_idle = lds_peek(ctr + 2 + wv);
+        const int nxt = lds_peek(ctr + 1);
+        if (nxt >= total && n_idle == 64) break;
+        if (!active && nxt < total) {
+            const int32_t q = atomicAdd(ctr + 1, 1);
+            if (q < total) {
+                const int32_t e = SPLIT ? q / AX_SEGS : q, seg = SPLIT ? q - e * AX_SEGS : 0;
+                const int32_t code = list[e];
+                g = code >> 3;
+                k = code & 7;
+                const int64_t smp = s0 + g;
+                const float4 l = a.dirs[k];
+                const float px = J.origin[3 * smp], py = J.origin[3 * smp + 1], pz = J.origin[3 * smp + 2];
+                bool run = true;
+                ox = px;
+                oy = py;
+                oz = pz;
+                win = 1e30f;
+                if (SPLIT) {
+                    run = ((uint32_t)__hip_atomic_load(word + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >> k) & 1u;
+                    const int c = l.x != 0.0f ? 0 : (l.y != 0.0f ? 1 : 2);
+                    const float sg = c == 0 ? l.x : (c == 1 ? l.y : l.z);
+                    const float oc = c == 0 ? px : (c == 1 ? py : pz);
+                    const float t_exit = sg > 0.0f ? P.bbox[3 + c] - oc : oc - P.bbox[c];
+                    if (!(t_exit > 0.0f)) {
+                        // the origin is on or past the box face: one unbounded piece
+                        run = run && seg == 0;
+                    } else {
+                        const float oa = oc + sg * (t_exit * ((float)seg * inv_segs));
+                        const float ob = oc + sg * (t_exit * ((float)(seg + 1) * inv_segs));
+                        if (seg != AX_SEGS - 1) win = fabsf(ob - oa) * 1.000001f;
+                        ox = c == 0 ? oa : px;
+                        oy = c == 1 ? oa : py;
+                        oz = c == 2 ? oa : pz;
+                    }
+                }
+                if (run) {
+                    dx = l.x;
+                    dy = l.y;
+                    dz = l.z;
+                    kd = (6.0f * TRI_K) * fmaxf(fmaxf(fabsf(dx), fabsf(dy)), fabsf(dz));
+                    ix = safe_rcp(dx);
+                    iy = safe_rcp(dy);
+                    iz = safe_rcp(dz);
+                    node = root_leaf ? -1 : root;
+                    ti = root_leaf ? leaf_first(root) : 0;
+                    tn = root_leaf ? leaf_count(root) : 0;
+                    sp = 0;
+                    iter = 0;
+                    active = true;
+                    atomicSub(ctr + 2 + wv, 1);
+                }
+            }
+        }
+        if (active) {
+            bool hit = false, done = false, bad = false;
+            step_unit<STACK, STATS, SPLIT>(J, ox, oy, oz, dx, dy, dz, ix, iy, iz, kd, win, lds, lane, spill, last_node,
+                                           last_tri, node, sp, ti, tn, wc, hit, done, bad);
+            ++iter;
+            bad = bad || iter > iter_cap;
+            const bool open = !SPLIT && !(hit || done || bad) && iter >= AX_BUDGET;
+            if (hit || done || bad || open) {
+                if (hit || bad) atomicAnd(word + g, ~(1u << k));
+                if (open) atomicOr(word + g, 1u << (8 + k));
+                if (bad) atomicOr(a.err, ERR_STACK);
+                active = false;
+                atomicAdd(ctr + 2 + wv, 1);
+            }
+        }
+    }
+}
+
+template <int STACK, bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cast_axes(CastArgs a) {
+    __shared__ int stk[4 * STACK * 64];
+    __shared__ uint32_t word[AX_GROUP];
+    __shared__ int32_t list[6 * AX_GROUP];   // the phase's rays: 8 * sample + axis
+    __shared__ int ctr[6];                   // [0] list length, [1] next entry, [2 + w] idle lanes of wave w
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t item = blockIdx.x;
+    if (item >= a.n_items) return;  // the whole workgroup leaves together
+    lds_int *lds = (lds_int *)(stk + wv * (STACK * 64));
     const CastJob J = uni_job(job_of(a, item));
     const PartMeta &P = *J.meta;
     const int32_t root = uni_i(P.root);
     const int32_t n_valid = uni_i(P.n_valid);
     const bool empty = n_valid <= 0;
     const int32_t n_tris_alloc = uni_i(P.leaf_lo) + n_valid;
-    const int64_t s0 = (item - J.item_base) * AX_PER_WAVE;
-    const int q = lane / 6, k = lane - 6 * (lane / 6);
-    const int64_t s = s0 + q;
-    WorkCount wc;
-    bool free_ray = false;
-    if (q < AX_PER_WAVE && s < J.n_samples) {
-        const float ox = J.origin[3 * s], oy = J.origin[3 * s + 1], oz = J.origin[3 * s + 2];
-        const float nx = J.normal[3 * s], ny = J.normal[3 * s + 1], nz = J.normal[3 * s + 2];
+    const int64_t s0 = (item - J.item_base) * AX_GROUP;
+    const int64_t left = J.n_samples - s0;
+    const int32_t g_n = uni_i((int32_t)(left < AX_GROUP ? left : AX_GROUP));
+    if (threadIdx.x < AX_GROUP) word[threadIdx.x] = 0u;
+    if (threadIdx.x < 6) ctr[threadIdx.x] = threadIdx.x < 2 ? 0 : 64;
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < 6 * g_n; q += 256) {
+        const int32_t g = q / 6, k = q - 6 * g;
+        const int64_t smp = s0 + g;
         const float4 l = a.dirs[k];
-        const float q0 = nx * l.x, q1 = ny * l.y, q2 = nz * l.z;
-        const float nd = (q0 + q1) + q2;
-        if (!(nd < 0.0f))
-            free_ray = empty || !occluded<STACK, STATS, STEP>(J.nodes, J.tris, root, ox, oy, oz, l.x, l.y, l.z, (lds_int *)stk[wv], lane,
-                                                        a.err, J.n_nodes_alloc, n_tris_alloc, wc);
+        const float q0 = J.normal[3 * smp] * l.x, q1 = J.normal[3 * smp + 1] * l.y, q2 = J.normal[3 * smp + 2] * l.z;
+        if (!(((q0 + q1) + q2) < 0.0f)) {
+            atomicOr(word + g, 1u << k);
+            list[atomicAdd(ctr, 1)] = 8 * g + k;
+        }
     }
-    const uint64_t m = __ballot(free_ray);
-    if (lane < AX_PER_WAVE && s0 + lane < J.n_samples) J.bits[s0 + lane] = (uint32_t)(m >> (6 * lane)) & 63u;
+    __syncthreads();
+    WorkCount wc;
+    if (!empty) {
+        const int64_t cap = 2 * (int64_t)J.n_nodes_alloc + (int64_t)n_tris_alloc + 64;
+        const uint32_t iter_cap = cap < 0xffffffffll ? (uint32_t)cap : 0xffffffffu;
+        const uint32_t last_node = (uint32_t)J.n_nodes_alloc - 1u, last_tri = (uint32_t)max(n_tris_alloc, 1) - 1u;
+        axes_phase<STACK, STATS, false>(a, J, P, s0, list, uni_i(ctr[0]), word, ctr, lds, lane, wv, root, iter_cap,
+                                        last_node, last_tri, wc);
+        __syncthreads();
+        if (threadIdx.x < 6) ctr[threadIdx.x] = threadIdx.x < 2 ? 0 : 64;
+        __syncthreads();
+        for (int32_t q = threadIdx.x; q < 6 * g_n; q += 256) {
+            const int32_t g = q / 6, k = q - 6 * g;
+            if ((word[g] >> (8 + k)) & 1u) list[atomicAdd(ctr, 1)] = 8 * g + k;
+        }
+        __syncthreads();
+        const int32_t n_open = uni_i(ctr[0]);
+        if (n_open > 0)   // uniform: every thread reads the same count after the barrier
+            axes_phase<STACK, STATS, true>(a, J, P, s0, list, n_open * AX_SEGS, word, ctr, lds, lane, wv, root,
+                                           iter_cap, last_node, last_tri, wc);
+    }
+    __syncthreads();
+    for (int32_t w = threadIdx.x; w < g_n; w += 256) J.bits[s0 + w] = word[w] & 63u;
     if (STATS) {
         atomicAdd(a.work, (unsigned long long)wc.nodes);
         atomicAdd(a.work + 1, (unsigned long long)wc.tris);
@@ -807,9 +968,9 @@ static hipError_t launch_refill(const CastArgs &args, hipStream_t s) {
 template <int RPW, int STACK, bool STATS, bool STEP>
 static hipError_t launch_cast(const CastArgs &args, hipStream_t s) {
     if (args.kind == 1) {
-        const int64_t blocks = (args.n_items + 3) / 4;   // four items per block
+        const int64_t blocks = args.n_items;             // AX_GROUP samples per block
         if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-        k_cast_axes<STACK, STATS, STEP><<<(unsigned)blocks, 256, 0, s>>>(args);
+        k_cast_axes<STACK, STATS><<<(unsigned)blocks, 256, 0, s>>>(args);
     } else if (args.group > 1) {
         const int64_t blocks = args.n_items;             // `group` samples per block
         if (blocks >= ((int64_t)1 << 31) || args.group > MAX_GROUP) return hipErrorInvalidValue;
@@ -876,7 +1037,7 @@ int32_t cast_group(int32_t n_dirs, int32_t setting) {
 }
 
 int64_t cast_items(int32_t kind, int64_t n_samples, int32_t group) {
-    if (kind == 1) return (n_samples + AX_PER_WAVE - 1) / AX_PER_WAVE;
+    if (kind == 1) return (n_samples + AX_GROUP - 1) / AX_GROUP;
     return group > 1 ? (n_samples + group - 1) / group : n_samples;
 }
 
