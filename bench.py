@@ -416,26 +416,38 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
 
     ev = {k: [] for k in ("build", "sample", "cast", "stats", "axes", "setups")}
 
+    # the six-axis cast and the setups need only the samples and the
+    # hierarchy: they run on a second stream beside the hemisphere cast and
+    # its statistics (default priority, as every stream here)
+    side = torch.cuda.Stream()
+
     def step(record):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        main = torch.cuda.current_stream()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        f = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record()
         bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
         e[1].record()
         ctx.sample_surface(bvh, S, 2, out=samples)
         e[2].record()
+        side.wait_stream(main)
+        f[0].record(side)
+        ctx.cast(bvh, samples, 6, kind=hra.DIRS_AXES6, counts=False, bits=bits6, stream=side)
+        f[1].record(side)
         ctx.cast(bvh, samples, N, counts=False, bits=bits)
         e[3].record()
         ds = ctx.dominant_axes(samples, N, bits)
         rep = ctx.classify(ds, S, N)
         e[4].record()
-        ctx.cast(bvh, samples, 6, kind=hra.DIRS_AXES6, counts=False, bits=bits6)
-        e[5].record()
-        su = ctx.min_setups(bvh, samples, bits6, args.tool_length, want_class=False)
-        e[6].record()
+        su = ctx.min_setups(bvh, samples, bits6, args.tool_length, want_class=False, stream=side)
+        f[2].record(side)
+        main.wait_stream(side)
         if record:
             torch.cuda.synchronize()
-            for k, (a, b) in zip(ev, zip(e[:-1], e[1:])):
+            for k, (a, b) in zip(("build", "sample", "cast", "stats"), zip(e[:-1], e[1:])):
                 ev[k].append(a.elapsed_time(b))
+            ev["axes"].append(f[0].elapsed_time(f[1]))
+            ev["setups"].append(f[1].elapsed_time(f[2]))
         bvh.release()
         return rep, su
 
@@ -464,6 +476,20 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
     info = bvh.info()
     ctx.sample_surface(bvh, S, 2, out=samples)
+    # the secondary stages alone on the main stream (inside the step they
+    # overlap the hemisphere cast, so their stage times there include waiting)
+    alone = {}
+    for name, fn in (("dominant_axes", lambda: ctx.dominant_axes(samples, N, bits)),
+                     ("six_axis_cast", lambda: ctx.cast(bvh, samples, 6, kind=hra.DIRS_AXES6, counts=False,
+                                                         bits=bits6))):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        alone[name] = a.elapsed_time(b) / 5
     wbits, nodes, tests = ctx.cast_work(bvh, samples, N)
     same = bool(torch.equal(wbits, bits))
     bytes_per_ray = (nodes * NODE_BYTES + tests * TRI_BYTES) / rays + W * 4 / N
@@ -490,6 +516,8 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
                    "stack_depth": args.stack, "traversal": args.traversal, "tool_length_mm": args.tool_length},
         "parts_per_s": args.steps / dt,
         "stage_ms": {k: round(float(np.mean(v)), 3) for k, v in ev.items()},
+        "stage_streams": {"main": ["build", "sample", "cast", "stats"], "side, after sample": ["axes", "setups"]},
+        "secondary_alone_ms": {k: round(v, 4) for k, v in alone.items()},
         "cast_rays_per_s": rays / (cast_ms * 1e-3),
         "bvh": {"depth": info.depth, "nodes": info.n_nodes, "bytes": info.bytes},
         "work_per_ray": {"node_fetches": nodes / rays, "tri_tests": tests / rays, "bytes": bytes_per_ray,
