@@ -22,7 +22,7 @@ namespace hra {
 namespace {
 
 constexpr int TOOL_THREADS = 256;
-constexpr int TOOL_STACK = 32;    // LDS entries per lane
+constexpr int TOOL_STACK = 24;    // LDS entries per lane
 constexpr int TOOL_SPILL = 64;    // private overflow
 
 struct ToolArgs {
@@ -129,6 +129,13 @@ __device__ inline bool ray_meets(D3 c, D3 u, D3 A, D3 B, D3 C) {
     return inside && ((h >= 0.0 && q > 0.0) || (h <= 0.0 && q < 0.0));
 }
 
+// Hardware square root (within 1 ulp, 1.2e-7 relative): the screens below
+// compare distances of at most a few diagonals with margins of 1e-5 x the
+// diagonal beyond the threshold, far above its error, so a correctly rounded
+// root (a dozen instructions more, five times per screened triangle) would
+// change no decision.
+__device__ inline float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Cheap FP32 screen: the triangle lies inside the sphere about its centroid
 // m of radius rho (its farthest vertex), so it is at least
 // |axis to m| - rho from the axis.  When that exceeds thr by the margin
@@ -144,8 +151,8 @@ __device__ inline bool far_from_axis(float cx, float cy, float cz, float ux, flo
     const float wx = mx - cx, wy = my - cy, wz = mz - cz;
     const float t = fmaxf((wx * ux + wy * uy) + wz * uz, 0.0f);
     const float px = wx - t * ux, py = wy - t * uy, pz = wz - t * uz;
-    const float d = sqrtf((px * px + py * py) + pz * pz);
-    if (d - sqrtf(rho2) > thr_hi) return true;
+    const float d = hsqrt((px * px + py * py) + pz * pz);
+    if (d - hsqrt(rho2) > thr_hi) return true;
     // Second screen, for the faces around the sample: when the axis does not
     // approach the triangle's plane (it moves away or runs parallel), every
     // point of the axis is at least as far from the plane as the tip centre,
@@ -156,8 +163,8 @@ __device__ inline bool far_from_axis(float cx, float cy, float cz, float ux, flo
     // a tiny approach rate (1e-6) costs at most 2e-6 x diagonal over the part.
     const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z, e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
     const float Nx = e1y * e2z - e1z * e2y, Ny = e1z * e2x - e1x * e2z, Nz = e1x * e2y - e1y * e2x;
-    const float nn = sqrtf((Nx * Nx + Ny * Ny) + Nz * Nz);
-    const float l1 = sqrtf((e1x * e1x + e1y * e1y) + e1z * e1z), l2 = sqrtf((e2x * e2x + e2y * e2y) + e2z * e2z);
+    const float nn = hsqrt((Nx * Nx + Ny * Ny) + Nz * Nz);
+    const float l1 = hsqrt((e1x * e1x + e1y * e1y) + e1z * e1z), l2 = hsqrt((e2x * e2x + e2y * e2y) + e2z * e2z);
     if (!(nn > 0.05f * (l1 * l2))) return false;
     const float s0 = ((cx - A.x) * Nx + (cy - A.y) * Ny) + (cz - A.z) * Nz;
     const float s1 = (ux * Nx + uy * Ny) + uz * Nz;
@@ -177,19 +184,19 @@ __device__ inline bool far_from_holder_tool(float cx, float cy, float cz, float 
                 mz = ((A.z + B.z) + C.z) * (1.0f / 3.0f);
     const float ax = A.x - mx, ay = A.y - my, az = A.z - mz, bx = B.x - mx, by = B.y - my, bz = B.z - mz;
     const float qx = C.x - mx, qy = C.y - my, qz = C.z - mz;
-    const float rho = sqrtf(fmaxf(fmaxf((ax * ax + ay * ay) + az * az, (bx * bx + by * by) + bz * bz),
+    const float rho = hsqrt(fmaxf(fmaxf((ax * ax + ay * ay) + az * az, (bx * bx + by * by) + bz * bz),
                                   (qx * qx + qy * qy) + qz * qz));
     const float wx = mx - cx, wy = my - cy, wz = mz - cz;
     const float t = (wx * ux + wy * uy) + wz * uz;
     const float ts = fmaxf(t, 0.0f), th = fmaxf(t, glen);
     const float sx = wx - ts * ux, sy = wy - ts * uy, sz = wz - ts * uz;
     const float hx = wx - th * ux, hy = wy - th * uy, hz = wz - th * uz;
-    if (sqrtf((sx * sx + sy * sy) + sz * sz) - rho > thr_hi && sqrtf((hx * hx + hy * hy) + hz * hz) - rho > thr_h_hi)
+    if (hsqrt((sx * sx + sy * sy) + sz * sz) - rho > thr_hi && hsqrt((hx * hx + hy * hy) + hz * hz) - rho > thr_h_hi)
         return true;
     const float e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z, e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
     const float Nx = e1y * e2z - e1z * e2y, Ny = e1z * e2x - e1x * e2z, Nz = e1x * e2y - e1y * e2x;
-    const float nn = sqrtf((Nx * Nx + Ny * Ny) + Nz * Nz);
-    const float l1 = sqrtf((e1x * e1x + e1y * e1y) + e1z * e1z), l2 = sqrtf((e2x * e2x + e2y * e2y) + e2z * e2z);
+    const float nn = hsqrt((Nx * Nx + Ny * Ny) + Nz * Nz);
+    const float l1 = hsqrt((e1x * e1x + e1y * e1y) + e1z * e1z), l2 = hsqrt((e2x * e2x + e2y * e2y) + e2z * e2z);
     if (!(nn > 0.05f * (l1 * l2))) return false;
     const float s0 = ((cx - A.x) * Nx + (cy - A.y) * Ny) + (cz - A.z) * Nz;
     const float s1 = (ux * Nx + uy * Ny) + uz * Nz;
@@ -260,25 +267,48 @@ __device__ inline bool holder_slab(float lx, float ly, float lz, float hx, float
 
 __device__ inline float rcp_guarded(float x) { return fabsf(x) > 1e-30f ? 1.0f / x : copysignf(1e30f, x); }
 
-// Four waves per SIMD: the compiler's own choice (142 VGPRs) allows three;
-// capped at 128 it spills 15 registers on the FP64 path and the cast runs 9 %
-// faster (the FP64 test out of line at the same cap: 5 %).
+// The cast's cost lies in the FP64 distance tests (a few hundred
+// instructions each, about ten per direction on a part with deep pockets):
+// run inside each lane's traversal they execute with one or two lanes of the
+// wave active.  Here a lane only walks the hierarchy and screens candidate
+// triangles in FP32, one unit of work per loop iteration (a node visit or a
+// screen, in the visit order of a plain recursive walk); a triangle that
+// survives its screen goes to the wave's queue in LDS, and whenever 64
+// wait, the whole wave runs 64 FP64 tests at once, each against the tip
+// centre and direction its owner stored in LDS.  A test that finds its
+// owner blocked sets the owner's bit in the wave's blocked mask; the owner
+// then stops walking and the wave skips its queued tests.  A lane whose walk
+// has ended waits for its queued tests; the loop ends when no lane walks
+// and the queue is empty.  Lanes coordinate through LDS words read by the
+// whole wave at the top of each iteration, never through cross-lane
+// instructions, and every lane stays in the loop to its end.
+//
+// Four waves per SIMD (128 VGPRs, the FP64 test inline in the batch).
 // HOLDER: the tool and the holder of tool_blocked_holder; boxes, screens
 // and tests take each with its own radius and half-line.
+constexpr int TOOL_WAVES = TOOL_THREADS / 64;
+constexpr int TOOL_Q = 128;   // queue entries per wave: at most 63 wait after a batch, at most 64 join per iteration
+
 template <bool STATS, bool HOLDER>
 __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_cast_tool(ToolArgs a) {
     __shared__ int stk[TOOL_STACK * TOOL_THREADS];
+    __shared__ int32_t q_tri[TOOL_WAVES][TOOL_Q];
+    __shared__ uint8_t q_own[TOOL_WAVES][TOOL_Q];
+    __shared__ double cu[TOOL_WAVES][64][6];       // per lane: tip centre c, unit direction u
+    __shared__ int ctl[TOOL_WAVES][4];             // per wave: queue head, queue tail, walking lanes
+    __shared__ unsigned long long blk[TOOL_WAVES]; // per wave: lanes whose direction is blocked
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t g = (int64_t)blockIdx.x * TOOL_THREADS + threadIdx.x;
-    if (g >= a.n_rays) return;
-    const int lane = threadIdx.x;
-    const int64_t s = g / a.n_dirs;
-    const int32_t j = (int32_t)(g - s * a.n_dirs);
+    const bool alive = g < a.n_rays;
+    const int64_t s = alive ? g / a.n_dirs : 0;
+    const int32_t j = alive ? (int32_t)(g - s * a.n_dirs) : 0;
     const PartMeta &P = *a.meta;
     const float px = a.point[3 * s], py = a.point[3 * s + 1], pz = a.point[3 * s + 2];
     const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
     const float4 l = a.dirs[j];
     int32_t idx;
     float3 d;
+    bool cast = alive;
     if (a.kind == 0) {
         float3 t, b;
         onb_frame(nx, ny, nz, t, b);
@@ -287,123 +317,176 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
     } else {
         d = make_float3(l.x, l.y, l.z);
         idx = j;
-        if ((nx * d.x + ny * d.y) + nz * d.z < 0.0f) return;   // into the material: not cast, bit 0
+        // into the material: not cast, bit 0
+        cast = cast && !((nx * d.x + ny * d.y) + nz * d.z < 0.0f);
     }
     const double r = a.radius, tol = 1e-4 * P.diag, thr = r - tol;
     const double rr = HOLDER ? fmax(r, a.hrad) : r, thr_h = HOLDER ? a.hrad - tol : thr;
-    if (!(thr > tol)) {   // a tool thinner than twice the tolerance is not meaningful
+    if (cast && !(thr > tol)) {   // a tool thinner than twice the tolerance is not meaningful
         atomicOr(a.err, ERR_TOOL_RADIUS);
-        return;
+        cast = false;
     }
     const D3 c = mk((double)px + r * (double)nx, (double)py + r * (double)ny, (double)pz + r * (double)nz);
     const double dl = sqrt(((double)d.x * d.x + (double)d.y * d.y) + (double)d.z * d.z);
     const D3 u = mk(d.x / dl, d.y / dl, d.z / dl);
     const double glen = a.hlen + a.hrad;          // HOLDER: the holder's half-line starts at c + glen u
-    const D3 hg = c + glen * u;
     const double thr2 = thr * thr, thr_h2 = thr_h * thr_h;
     const int32_t root = P.root, n_valid = P.n_valid, n_tris_alloc = P.leaf_lo + P.n_valid;
-    bool blocked = false;
+    cu[wv][lane][0] = c.x;
+    cu[wv][lane][1] = c.y;
+    cu[wv][lane][2] = c.z;
+    cu[wv][lane][3] = u.x;
+    cu[wv][lane][4] = u.y;
+    cu[wv][lane][5] = u.z;
+    if (lane == 0) {
+        ctl[wv][0] = 0;
+        ctl[wv][1] = 0;
+        ctl[wv][2] = 0;
+        blk[wv] = 0ull;
+    }
+    __syncthreads();
+    bool walking = cast && n_valid > 0;
+    if (walking) atomicAdd(&ctl[wv][2], 1);
+    __syncthreads();
+    // FP32 box tests from the rounded tip centre; the margin covers the
+    // rounding of the centre and of the grown box faces
+    const float cx = (float)c.x, cy = (float)c.y, cz = (float)c.z;
+    const float pad = (float)(rr * 1.0001) + (float)(1e-5 * P.diag);
+    const float pad_c = (float)(r * 1.0001) + (float)(1e-5 * P.diag);   // the cutter's (HOLDER)
+    const float ix = rcp_guarded(d.x), iy = rcp_guarded(d.y), iz = rcp_guarded(d.z);
+    const Shifted so = shift(cx, cy, cz, pad), so_c = shift(cx, cy, cz, pad_c);
+    // unit direction and threshold for the FP32 screen; the margin
+    // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a part
+    // far from the origin) is far above the screen's rounding
+    const float ux = (float)u.x, uy = (float)u.y, uz = (float)u.z;
+    const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
+    const float thr_hi = (float)(fmax(thr, thr_h) + 1e-5 * P.diag + 1e-6 * cmax);
+    const float thr_c_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax), gl = (float)glen;
+    const double gap = glen;   // the holder's start along u, for the batch's tests
+    int spill[TOOL_SPILL];
+    int sp = 0;
+    int32_t node = is_leaf(root) ? -1 : root;
+    int32_t ti = is_leaf(root) ? leaf_first(root) : 0, tn = is_leaf(root) ? leaf_count(root) : 0;
+    int32_t budget = 2 * a.n_nodes_alloc + 64;
+    bool bad = false;
     uint32_t n_nodes = 0, n_tests = 0, n_cands = 0;
-    if (n_valid > 0) {
-        // FP32 box tests from the rounded tip centre; the margin covers the
-        // rounding of the centre and of the grown box faces
-        const float cx = (float)c.x, cy = (float)c.y, cz = (float)c.z;
-        const float pad = (float)(rr * 1.0001) + (float)(1e-5 * P.diag);
-        const float pad_c = (float)(r * 1.0001) + (float)(1e-5 * P.diag);   // the cutter's (HOLDER)
-        const float ix = rcp_guarded(d.x), iy = rcp_guarded(d.y), iz = rcp_guarded(d.z);
-        const Shifted so = shift(cx, cy, cz, pad), so_c = shift(cx, cy, cz, pad_c);
-        // unit direction and threshold for the FP32 screen; the margin
-        // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a
-        // part far from the origin) is far above the screen's rounding
-        const float ux = (float)u.x, uy = (float)u.y, uz = (float)u.z;
-        const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
-        const float thr_hi = (float)(fmax(thr, thr_h) + 1e-5 * P.diag + 1e-6 * cmax);
-        const float thr_c_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax), gl = (float)glen;
-        int spill[TOOL_SPILL];
-        int sp = 0;
-        int32_t node = root;
-        int32_t budget = 2 * a.n_nodes_alloc + 64;
-        bool bad = false;
-        if (is_leaf(root)) {
-            const int32_t f = leaf_first(root), n = leaf_count(root);
-            if (f + n > n_tris_alloc) bad = true;
-            for (int32_t k = 0; k < n && !bad && !blocked; ++k) {
-                const float4 *t = a.tris + 3 * (int64_t)(f + k);
-                const float4 A4 = t[0], B4 = t[1], C4 = t[2];
-                if (STATS) ++n_cands;
-                if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, gl, A4, B4, C4, thr_c_hi, thr_hi)
-                           : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi))
-                    continue;
-                if (STATS) ++n_tests;
-                blocked = HOLDER ? tool_blocked_holder(c, hg, u, A4, B4, C4, thr2, thr_h2) : tool_blocked(c, u, A4, B4, C4, thr2);
-            }
-            node = -1;
-        }
-        while (node >= 0 && !blocked && !bad) {
-            if ((uint32_t)node >= (uint32_t)a.n_nodes_alloc || --budget < 0) {
-                bad = true;
-                break;
-            }
-            const Node nd = a.nodes[node];
-            if (STATS) ++n_nodes;
-            float t0, t1;
-            bool h0, h1;
-            if (HOLDER) {
-                h0 = holder_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, so_c, so, gl * 0.99f, ix, iy, iz, t0);
-                h1 = holder_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, so_c, so, gl * 0.99f, ix, iy, iz, t1);
-            } else {
-                h0 = grown_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, so, ix, iy, iz, t0);
-                h1 = grown_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, so, ix, iy, iz, t1);
-            }
-            const int32_t ch[2] = {nd.d.x, nd.d.y};
-            const bool hit[2] = {h0, h1};
-            for (int k = 0; k < 2 && !blocked && !bad; ++k) {
-                if (!hit[k] || !is_leaf(ch[k])) continue;
-                const int32_t f = leaf_first(ch[k]), n = leaf_count(ch[k]);
-                if (f + n > n_tris_alloc) {
-                    bad = true;
-                    break;
+    while (true) {
+        const int head = __hip_atomic_load(&ctl[wv][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int tail = __hip_atomic_load(&ctl[wv][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int n_walk = __hip_atomic_load(&ctl[wv][2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int qn = tail - head;
+        if (qn >= 64 || (n_walk == 0 && qn > 0)) {
+            // a batch of FP64 tests, one per lane
+            if (lane < qn) {
+                const int slot = (head + lane) & (TOOL_Q - 1);
+                const int own = q_own[wv][slot];
+                const int32_t f = q_tri[wv][slot];
+                const unsigned long long bm =
+                    __hip_atomic_load(&blk[wv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (!((bm >> own) & 1ull)) {
+                    const D3 oc = mk(cu[wv][own][0], cu[wv][own][1], cu[wv][own][2]);
+                    const D3 ou = mk(cu[wv][own][3], cu[wv][own][4], cu[wv][own][5]);
+                    const float4 *t = a.tris + 3 * (int64_t)f;
+                    const float4 A4 = t[0], B4 = t[1], C4 = t[2];
+                    if (STATS) ++n_tests;
+                    const bool hit = HOLDER ? tool_blocked_holder(oc, oc + gap * ou, ou, A4, B4, C4, thr2, thr_h2)
+                                            : tool_blocked(oc, ou, A4, B4, C4, thr2);
+                    if (hit) atomicOr(&blk[wv], 1ull << own);
                 }
-                for (int32_t q = 0; q < n && !blocked; ++q) {
-                    const float4 *t = a.tris + 3 * (int64_t)(f + q);
+            }
+            // every lane stores the same new head
+            ctl[wv][0] = head + (qn < 64 ? qn : 64);
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
+        if (n_walk == 0) break;
+        if (walking) {
+            const unsigned long long bm = __hip_atomic_load(&blk[wv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            bool end = ((bm >> lane) & 1ull) != 0ull;
+            if (!end && tn > 0) {
+                // screen one triangle of the current leaf
+                if ((uint32_t)ti >= (uint32_t)n_tris_alloc) {
+                    bad = true;
+                } else {
+                    const float4 *t = a.tris + 3 * (int64_t)ti;
                     const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                     if (STATS) ++n_cands;
-                    if (HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, gl, A4, B4, C4, thr_c_hi, thr_hi)
-                               : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi))
-                        continue;
-                    if (STATS) ++n_tests;
-                    blocked = HOLDER ? tool_blocked_holder(c, hg, u, A4, B4, C4, thr2, thr_h2) : tool_blocked(c, u, A4, B4, C4, thr2);
+                    const bool far = HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, gl, A4, B4, C4, thr_c_hi, thr_hi)
+                                            : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi);
+                    if (!far) {
+                        const int slot = atomicAdd(&ctl[wv][1], 1) & (TOOL_Q - 1);
+                        q_tri[wv][slot] = ti;
+                        q_own[wv][slot] = (uint8_t)lane;
+                    }
+                }
+                ++ti;
+                --tn;
+            } else if (!end) {
+                bool visit = true;
+                if (node < 0) {
+                    if (sp == 0) {
+                        end = true;
+                        visit = false;
+                    } else {
+                        --sp;
+                        const int32_t itm = sp < TOOL_STACK ? stk[sp * TOOL_THREADS + threadIdx.x] : spill[sp - TOOL_STACK];
+                        if (is_leaf(itm)) {
+                            ti = leaf_first(itm);
+                            tn = leaf_count(itm);
+                            visit = false;
+                        } else {
+                            node = itm;
+                        }
+                    }
+                }
+                if (visit) {
+                    if ((uint32_t)node >= (uint32_t)a.n_nodes_alloc || --budget < 0) {
+                        bad = true;
+                    } else {
+                        const Node nd = a.nodes[node];
+                        if (STATS) ++n_nodes;
+                        float t0, t1;
+                        bool h0, h1;
+                        if (HOLDER) {
+                            h0 = holder_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, so_c, so, gl * 0.99f, ix, iy,
+                                             iz, t0);
+                            h1 = holder_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, so_c, so, gl * 0.99f, ix, iy,
+                                             iz, t1);
+                        } else {
+                            h0 = grown_slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, so, ix, iy, iz, t0);
+                            h1 = grown_slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, so, ix, iy, iz, t1);
+                        }
+                        const int32_t c0 = nd.d.x, c1 = nd.d.y;
+                        const bool l0 = h0 && is_leaf(c0), l1 = h1 && is_leaf(c1);
+                        const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
+                        if (l0 || l1) {
+                            const int32_t lc = l0 ? c0 : c1;
+                            ti = leaf_first(lc);
+                            tn = leaf_count(lc);
+                        }
+                        // at most one push per visit: the second leaf, or the
+                        // farther of two interior children
+                        const bool push = (l0 && l1) || (g0 && g1);
+                        const int32_t pv = (l0 && l1) ? c1 : (t0 <= t1 ? c1 : c0);
+                        node = (g0 && g1) ? (t0 <= t1 ? c0 : c1) : (g0 ? c0 : (g1 ? c1 : -1));
+                        if (push) {
+                            if (sp < TOOL_STACK) stk[sp * TOOL_THREADS + threadIdx.x] = pv;
+                            else if (sp < TOOL_STACK + TOOL_SPILL) spill[sp - TOOL_STACK] = pv;
+                            else bad = true;
+                            ++sp;
+                        }
+                    }
                 }
             }
-            if (blocked || bad) break;
-            const bool g0 = h0 && !is_leaf(ch[0]), g1 = h1 && !is_leaf(ch[1]);
-            if (g0 && g1) {
-                const int32_t nearc = t0 <= t1 ? ch[0] : ch[1], farc = t0 <= t1 ? ch[1] : ch[0];
-                if (sp < TOOL_STACK) stk[sp * TOOL_THREADS + lane] = farc;
-                else if (sp < TOOL_STACK + TOOL_SPILL) spill[sp - TOOL_STACK] = farc;
-                else {
-                    bad = true;
-                    break;
-                }
-                ++sp;
-                node = nearc;
-            } else if (g0) {
-                node = ch[0];
-            } else if (g1) {
-                node = ch[1];
-            } else if (sp == 0) {
-                node = -1;
-            } else {
-                --sp;
-                node = sp < TOOL_STACK ? stk[sp * TOOL_THREADS + lane] : spill[sp - TOOL_STACK];
+            if (end || bad) {
+                walking = false;
+                atomicSub(&ctl[wv][2], 1);
             }
-        }
-        if (bad) {
-            atomicOr(a.err, ERR_STACK);
-            return;
         }
     }
-    if (!blocked) atomicOr(&a.bits[s * a.W + (idx >> 5)], 1u << (idx & 31));
+    if (bad) atomicOr(a.err, ERR_STACK);
+    const unsigned long long bm = __hip_atomic_load(&blk[wv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cast && !bad && !((bm >> lane) & 1ull)) atomicOr(&a.bits[s * a.W + (idx >> 5)], 1u << (idx & 31));
     if (STATS) {
         atomicAdd(a.work, (unsigned long long)n_nodes);
         atomicAdd(a.work + 1, (unsigned long long)n_tests);
