@@ -220,6 +220,45 @@ def frame_extra(ctx, verts, tris, mesh, reps=20, oracle=True):
     return res
 
 
+DATUM_FACE_BYTES = 60   # per triangle: its three float4 vertices, leaf position and weight prefix, read once
+
+
+def datum_extra(ctx, verts, tris, mesh, reps=20, oracle=True):
+    """Datum planes of the part's six setup orientations: the call timed
+    (it synchronises, so host wall clock per call, and HIP events around
+    the same calls), its HBM roofline, and the oracle's time for the same
+    frames, with their equality."""
+    import torch
+    bvh = ctx.build_bvh(verts, tris)
+    got = ctx.datum_frames(bvh)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    t0 = time.perf_counter()
+    e[0].record()
+    for _ in range(reps):
+        got = ctx.datum_frames(bvh)
+    e[1].record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) / reps * 1e3
+    dev_ms = e[0].elapsed_time(e[1]) / reps
+    bvh.release()
+    nt = mesh.n_tris
+    b = DATUM_FACE_BYTES * nt
+    res = {"triangles": nt, "call_ms": wall_ms, "event_ms": dev_ms,
+           "frame_pz": [(r["dir"], r["offset"]) for r in got[4]],
+           "roofline": {"bound": "hbm", "achieved": b / (dev_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": b / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": b}}
+    if oracle:
+        from oracle import datum as D
+        t0 = time.perf_counter()
+        want = D.datum_frames(mesh.verts, mesh.tris)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": nt / dt, "unit": "faces/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole part ({nt} triangles), numpy FP64", "seconds": round(dt, 3)}
+        res["matches_oracle"] = got == want
+    return res
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -328,7 +367,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="single-part workloads: skip the 64-part batch and serving comparisons")
     ap.add_argument("--no-frame", action="store_true",
-                    help="single-part workloads: skip the canonical-frame measurement")
+                    help="single-part workloads: skip the canonical-frame and datum-plane measurements")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, copy this many MiB device to device (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -534,6 +573,8 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     if frame:
         log("[bench] canonical frame of the part")
         out["frame"] = frame_extra(ctx, verts, tris, mesh, oracle=not args.no_cpu_baseline)
+        log("[bench] datum planes of the part")
+        out["datum"] = datum_extra(ctx, verts, tris, mesh, oracle=not args.no_cpu_baseline)
     ctx.close()
     return out
 

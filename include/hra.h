@@ -493,6 +493,39 @@ int64_t hra_frame_ws_bytes(int64_t n_tris);
 hra_status hra_frame_apply(hra_ctx *ctx, const hra_frame *d_frame, const float *d_in, float *d_out, int64_t n_verts,
                            void *stream);
 
+/* ------------------------------------------------------------- datum planes */
+
+typedef struct {
+    int32_t dir[3];      /* primary, secondary, tertiary: axis direction 0..5 (+X,-X,+Y,-Y,+Z,-Z), -1 empty */
+    int32_t n_tris[3];   /* faces of each plane */
+    double offset[3];    /* the plane's coordinate along its axis: the least face offset (mm) */
+    double area[3];      /* area_w x 2^-k, k the part's weight scale (mm^2) */
+    uint64_t area_w[3];  /* sum of the faces' integer area weights floor(area x 2^k) */
+} hra_datum_frame;
+
+/* Datum planes of each setup orientation (Section 6 names reference frames
+ * for the tolerancing of each setup as future work and gives no method; this
+ * is the library's, the 3-2-1 rule of fixturing on axis-facing planes).
+ * A face faces direction d = 2c + (N_c < 0) when its FP64 normal N = (B - A)
+ * x (C - A) of the FP32 vertices has its dominant component c (lowest on
+ * ties) with N_c^2 >= 0.99999999 |N|^2, i.e. within 1e-4 rad of the axis;
+ * its offset is h = ((A_c + B_c) + C_c) / 3 in FP64.  Faces sorted by (d, h
+ * with the three low bits of its order-preserving 64-bit key dropped, face
+ * index) form planes, linked while consecutive offsets differ by at most
+ * 1e-6 x the bounding-box diagonal.  For approach direction a (out[a], a =
+ * 0..5): primary = the plane of direction a ^ 1 of largest area (the side
+ * the part rests on), secondary = the largest plane whose axis is not a's,
+ * tertiary = the largest plane whose axis is neither a's nor the
+ * secondary's; ties to the lower direction, then the lower offset.  Areas
+ * are the sampler's integer weights, so sums and choices are exact.
+ *
+ * bvh: a hierarchy from hra_build_bvh(_batch); part: its part index.  out:
+ * host hra_datum_frame [6].  A part without axis-facing faces yields empty
+ * roles.  Enqueues on `stream` with a stream-ordered workspace of about
+ * 60 bytes per triangle, then synchronises it.  HRA_ERR_INVALID_ARG for a
+ * null argument or a part index outside [0, parts). */
+hra_status hra_datum_frames(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, hra_datum_frame *out, void *stream);
+
 /* ------------------------------------------------------------- batches */
 
 typedef struct {

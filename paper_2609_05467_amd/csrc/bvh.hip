@@ -30,6 +30,7 @@
 //      one leaf over a contiguous run) and emission of 64-byte nodes; node
 //      counts per part and each part's depth (its root's height).
 #include "common.hpp"
+#include "prims.hpp"
 
 #include <algorithm>
 #include <vector>
@@ -449,6 +450,17 @@ __global__ void k_gather(const float *tv, const uint32_t *sorted_vals, const uin
     const float *v = tv + 9 * (int64_t)g;
     for (int k = 0; k < 3; ++k) tri4[3 * q + k] = make_float4(v[3 * k], v[3 * k + 1], v[3 * k + 2], __int_as_float(f));
     leaf_pos[g] = (int32_t)q;
+}
+
+// The sort and the scan for other translation units (declared in prims.hpp).
+int64_t sort_pairs_ws_elems(int64_t n) { return radix_ws_elems(n); }
+hipError_t sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws, hipStream_t s,
+                      bool *result_in_k1) {
+    return radix_sort(k0, v0, k1, v1, n, ws, s, result_in_k1);
+}
+int64_t scan_u32_ws_elems(int64_t n) { return scan_ws_elems(n); }
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, bool inclusive, uint32_t *ws, hipStream_t s) {
+    return scan<uint32_t>(in, out, n, inclusive, ws, s);
 }
 
 // ---------------------------------------------------------------- Karras

@@ -1,0 +1,17 @@
+// Device-wide primitives of the hierarchy build (bvh.hip) for the other
+// stages: the stable LSD radix sort of (uint64 key, uint32 value) pairs
+// (eight passes of eight bits; the result lands in k1/v1 when
+// *result_in_k1, else in k0/v0) and the prefix sum over uint32, each with
+// its workspace size in uint32 elements.  Both are stream-ordered and
+// allocate nothing.
+#pragma once
+
+#include "common.hpp"
+
+namespace hra {
+int64_t sort_pairs_ws_elems(int64_t n);
+hipError_t sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws, hipStream_t s,
+                      bool *result_in_k1);
+int64_t scan_u32_ws_elems(int64_t n);
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, bool inclusive, uint32_t *ws, hipStream_t s);
+}  // namespace hra

@@ -89,6 +89,11 @@ class Frame(C.Structure):
                 ("shift", C.c_int32), ("error", C.c_uint32)]
 
 
+class DatumFrame(C.Structure):
+    _fields_ = [("dir", C.c_int32 * 3), ("n_tris", C.c_int32 * 3), ("offset", C.c_double * 3),
+                ("area", C.c_double * 3), ("area_w", C.c_uint64 * 3)]
+
+
 class PartRequest(C.Structure):
     _fields_ = [("mesh", Mesh), ("n_samples", C.c_int64), ("seed", C.c_uint64), ("tool_length", C.c_double)]
 
@@ -198,6 +203,7 @@ def lib():
             "hra_frame_estimate": ([P, C.POINTER(Mesh), P, P, P], C.c_int),
             "hra_frame_ws_bytes": ([i64], i64),
             "hra_frame_apply": ([P, P, P, P, i64, P], C.c_int),
+            "hra_datum_frames": ([P, P, i32, C.POINTER(DatumFrame), P], C.c_int),
             "hra_stl_read": ([C.c_char_p, C.POINTER(P), C.POINTER(i64), C.POINTER(i64)], C.c_int),
             "hra_stl_copy": ([P, P, P], C.c_int),
             "hra_stl_free": ([P], None),
@@ -225,7 +231,8 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_server_poll", "hra_server_wait", "hra_server_drain", "hra_server_get_stats", "hra_server_destroy",
            "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply", "hra_stl_read", "hra_stl_copy",
            "hra_stl_free", "hra_stl_error", "hra_cast_tool", "hra_cast_tool_work",
-           "hra_cast_tool_holder", "hra_dominant_axes_noalloc", "hra_debug_azimuth_table"]
+           "hra_cast_tool_holder", "hra_dominant_axes_noalloc", "hra_debug_azimuth_table",
+           "hra_datum_frames"]
 FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
@@ -492,6 +499,15 @@ class Context:
             out = torch.empty_like(v)
         self._check(lib().hra_frame_apply(self.ptr, _ptr(fr), _ptr(v), _ptr(out), v.shape[0], _stream(stream)))
         return out
+
+    def datum_frames(self, bvh, part=0, stream=None):
+        """Datum planes per approach direction (hra_datum_frames): six lists
+        (a = +X, -X, +Y, -Y, +Z, -Z) of three dicts, primary, secondary and
+        tertiary, each {dir, offset, area_w, area, n_tris} (dir -1: empty)."""
+        out = (DatumFrame * 6)()
+        self._check(lib().hra_datum_frames(self.ptr, bvh.ptr, int(part), out, _stream(stream)))
+        return [[{"dir": f.dir[r], "offset": f.offset[r], "area_w": int(f.area_w[r]), "area": f.area[r],
+                  "n_tris": f.n_tris[r]} for r in range(3)] for f in out]
 
     # ---------------------------------------------------------------- stats
     def dominant_axes(self, samples, n_dirs, bits, stream=None, noalloc=False):
