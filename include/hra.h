@@ -522,7 +522,7 @@ typedef struct {
  * bvh: a hierarchy from hra_build_bvh(_batch); part: its part index.  out:
  * host hra_datum_frame [6].  A part without axis-facing faces yields empty
  * roles.  Enqueues on `stream` with a stream-ordered workspace of about
- * 60 bytes per triangle, then synchronises it.  HRA_ERR_INVALID_ARG for a
+ * 76 bytes per triangle, then synchronises it.  HRA_ERR_INVALID_ARG for a
  * null argument or a part index outside [0, parts). */
 hra_status hra_datum_frames(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, hra_datum_frame *out, void *stream);
 

@@ -89,19 +89,24 @@ __device__ inline int face_of(const float4 *tris, const int32_t *leaf_pos, int64
     return face_dir(tris[3 * (int64_t)p], tris[3 * (int64_t)p + 1], tris[3 * (int64_t)p + 2], h);
 }
 
-__global__ void k_datum_keys(const float4 *tris, const int32_t *leaf_pos, int64_t tri_start, int64_t n,
-                             uint64_t *keys, uint32_t *vals) {
+// Per face (index f within the part): its sort key and index, and its
+// offset and integer weight for the later passes.
+__global__ void k_datum_keys(const float4 *tris, const int32_t *leaf_pos, const uint64_t *prefix, int64_t tri_start,
+                             int64_t n, uint64_t *keys, uint32_t *vals, double *hf, uint64_t *wf) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n) return;
+    const int64_t g = tri_start + f;
     double h;
-    const int d = face_of(tris, leaf_pos, tri_start + f, h);
+    const int d = face_of(tris, leaf_pos, g, h);
     keys[f] = d < 0 ? DT_NONE : (((uint64_t)d << 61) | (order_key(h) >> 3));
     vals[f] = (uint32_t)f;
+    hf[f] = h;
+    wf[f] = prefix[g] - (g > 0 ? prefix[g - 1] : 0ull);
 }
 
 // flags[i] = 1 where a plane starts in sorted order
-__global__ void k_datum_starts(const uint64_t *keys, const uint32_t *vals, const float4 *tris, const int32_t *leaf_pos,
-                               int64_t tri_start, int64_t n, const PartMeta *meta, uint32_t *flags) {
+__global__ void k_datum_starts(const uint64_t *keys, const uint32_t *vals, const double *hf, int64_t n,
+                               const PartMeta *meta, uint32_t *flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t k = keys[i];
@@ -110,12 +115,7 @@ __global__ void k_datum_starts(const uint64_t *keys, const uint32_t *vals, const
         return;
     }
     bool start = i == 0 || (keys[i - 1] >> 61) != (k >> 61);
-    if (!start) {
-        double h, hp;
-        face_of(tris, leaf_pos, tri_start + vals[i], h);
-        face_of(tris, leaf_pos, tri_start + vals[i - 1], hp);
-        start = (h - hp) > DT_LINK * meta->diag;
-    }
+    if (!start) start = (hf[vals[i]] - hf[vals[i - 1]]) > DT_LINK * meta->diag;
     flags[i] = start ? 1u : 0u;
 }
 
@@ -128,23 +128,77 @@ __global__ void k_datum_clear(DatumRun *runs, int64_t n) {
     runs[i].dir = -1;
 }
 
-// rid: inclusive scan of the starts (run index + 1)
-__global__ void k_datum_accum(const uint64_t *keys, const uint32_t *vals, const uint32_t *flags, const uint32_t *rid,
-                              const float4 *tris, const int32_t *leaf_pos, const uint64_t *prefix, int64_t tri_start,
-                              int64_t n, DatumRun *runs) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t k = keys[i];
-    if (k == DT_NONE) return;
-    const int64_t g = tri_start + vals[i];
-    double h;
-    face_of(tris, leaf_pos, g, h);
-    const uint64_t w = prefix[g] - (g > 0 ? prefix[g - 1] : 0ull);
-    DatumRun &R = runs[rid[i] - 1u];
-    atomicAdd(&R.area_w, (unsigned long long)w);
-    atomicAdd(&R.count, 1u);
-    atomicMin(&R.h_key, (unsigned long long)order_key(h));
-    if (flags[i]) R.dir = (int32_t)(k >> 61);
+constexpr int DT_ACC_TILES = 16;   // consecutive 64-element tiles per wave in k_datum_accum
+
+__device__ inline void run_flush(DatumRun *runs, int64_t r, unsigned long long w, uint32_t c, unsigned long long hk) {
+    DatumRun &R = runs[r];
+    atomicAdd(&R.area_w, w);
+    atomicAdd(&R.count, c);
+    atomicMin(&R.h_key, hk);
+}
+
+// rid: inclusive scan of the starts (run index + 1).  Runs are contiguous
+// in sorted order.  Each wave walks DT_ACC_TILES consecutive tiles of 64
+// elements; in a tile its lanes fold their values per run (a segmented
+// inclusive scan over shuffles), runs that end inside the tile go to their
+// totals from their last lane, and the run still open at lane 63 is carried
+// to the next tile in registers.  A plane of a million faces then costs one
+// atomic per 1,024 faces, not one per face; all sums are integers and the
+// offset a minimum, so the order of the atomics does not matter.
+__global__ __launch_bounds__(DT_TB) void k_datum_accum(const uint64_t *keys, const uint32_t *vals, const uint32_t *flags,
+                                                       const uint32_t *rid, const double *hf, const uint64_t *wf,
+                                                       int64_t n, DatumRun *runs) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * DT_TB + threadIdx.x) >> 6;
+    const int64_t base = wave * 64 * DT_ACC_TILES;
+    int64_t cr = -1;   // carried run (-1: none) and its partial totals, the same in every lane
+    unsigned long long cw = 0ull, chk = ~0ull;
+    uint32_t cc = 0u;
+    for (int it = 0; it < DT_ACC_TILES; ++it) {
+        const int64_t i = base + 64 * it + lane;
+        int64_t r = -1;   // run index, -1: no run (past the end, or a face that faces no axis)
+        unsigned long long w = 0ull, hk = ~0ull;
+        uint32_t cnt = 0u;
+        if (i < n) {
+            const uint64_t k = keys[i];
+            if (k != DT_NONE) {
+                const uint32_t f = vals[i];
+                w = wf[f];
+                hk = order_key(hf[f]);
+                cnt = 1u;
+                r = (int64_t)rid[i] - 1;
+                if (flags[i]) runs[r].dir = (int32_t)(k >> 61);
+            }
+        }
+        // a carried run that does not continue into this tile is complete
+        const int64_t r0 = __shfl(r, 0, 64);
+        if (cr >= 0 && r0 != cr) {
+            if (lane == 0) run_flush(runs, cr, cw, cc, chk);
+            cr = -1;
+        }
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t r_o = __shfl_up(r, off, 64);
+            const unsigned long long w_o = __shfl_up(w, off, 64), hk_o = __shfl_up(hk, off, 64);
+            const uint32_t c_o = __shfl_up(cnt, off, 64);
+            if (lane >= off && r_o == r) {
+                w += w_o;
+                cnt += c_o;
+                hk = hk_o < hk ? hk_o : hk;
+            }
+        }
+        if (r >= 0 && r == cr) {   // the tile's first run continues the carried one
+            w += cw;
+            cnt += cc;
+            hk = chk < hk ? chk : hk;
+        }
+        const int64_t r_next = __shfl_down(r, 1, 64);
+        if (r >= 0 && lane != 63 && r_next != r) run_flush(runs, r, w, cnt, hk);
+        cr = __shfl(r, 63, 64);
+        cw = __shfl(w, 63, 64);
+        chk = __shfl(hk, 63, 64);
+        cc = __shfl(cnt, 63, 64);
+    }
+    if (cr >= 0 && lane == 0) run_flush(runs, cr, cw, cc, chk);
 }
 
 // (area desc, direction asc, offset asc): true when run x is better than y
@@ -154,41 +208,49 @@ __device__ inline bool better(const DatumRun &x, const DatumRun &y) {
     return x.h_key < y.h_key;
 }
 
-// One block: for each approach direction a and role r, the best run under
-// the role's filter; sel[3 a + r] = run index or -1.
+__device__ inline int32_t pick(const DatumRun *runs, int32_t x, int32_t y) {
+    if (x < 0) return y;
+    if (y < 0) return x;
+    return better(runs[y], runs[x]) ? y : x;
+}
+
+// One block.  Under a total order the best plane of a set of directions is
+// the best of the directions' own bests, so one pass finds the best run of
+// each direction and thread 0 forms the eighteen roles from those six:
+// sel[3 a + r] = run index or -1.
 __global__ __launch_bounds__(DT_TB) void k_datum_select(const DatumRun *runs, const uint32_t *rid_last, int32_t *sel) {
-    __shared__ int32_t best[DT_TB];
-    __shared__ int32_t axis_sec;
+    __shared__ int32_t best[6][DT_TB];
     const int t = threadIdx.x;
     const int64_t nr = *rid_last;
+    int32_t b[6] = {-1, -1, -1, -1, -1, -1};
+    for (int64_t j = t; j < nr; j += DT_TB) {
+        const int d = runs[j].dir;
+        for (int q = 0; q < 6; ++q)
+            if (q == d) b[q] = pick(runs, b[q], (int32_t)j);
+    }
+    for (int q = 0; q < 6; ++q) best[q][t] = b[q];
+    __syncthreads();
+    for (int off = DT_TB / 2; off > 0; off >>= 1) {
+        if (t < off)
+            for (int q = 0; q < 6; ++q) best[q][t] = pick(runs, best[q][t], best[q][t + off]);
+        __syncthreads();
+    }
+    if (t != 0) return;
     for (int a = 0; a < 6; ++a) {
-        for (int r = 0; r < 3; ++r) {
-            const int ax = a >> 1;
-            const int sec_axis = r == 2 ? axis_sec : -1;
-            int32_t b = -1;
-            for (int64_t j = t; j < nr; j += DT_TB) {
-                const DatumRun &R = runs[j];
-                bool ok;
-                if (r == 0) ok = R.dir == (a ^ 1);
-                else if (r == 1) ok = (R.dir >> 1) != ax;
-                else ok = sec_axis >= 0 && (R.dir >> 1) != ax && (R.dir >> 1) != sec_axis;
-                if (ok && (b < 0 || better(R, runs[b]))) b = (int32_t)j;
-            }
-            best[t] = b;
-            __syncthreads();
-            for (int off = DT_TB / 2; off > 0; off >>= 1) {
-                if (t < off) {
-                    const int32_t o = best[t + off], m = best[t];
-                    if (o >= 0 && (m < 0 || better(runs[o], runs[m]))) best[t] = o;
-                }
-                __syncthreads();
-            }
-            if (t == 0) {
-                sel[3 * a + r] = best[0];
-                if (r == 1) axis_sec = best[0] >= 0 ? (runs[best[0]].dir >> 1) : -1;
-            }
-            __syncthreads();
+        const int ax = a >> 1;
+        const int32_t prim = best[a ^ 1][0];
+        int32_t sec = -1;
+        for (int d = 0; d < 6; ++d)
+            if ((d >> 1) != ax) sec = pick(runs, sec, best[d][0]);
+        int32_t ter = -1;
+        if (sec >= 0) {
+            const int sx = runs[sec].dir >> 1;
+            for (int d = 0; d < 6; ++d)
+                if ((d >> 1) != ax && (d >> 1) != sx) ter = pick(runs, ter, best[d][0]);
         }
+        sel[3 * a] = prim;
+        sel[3 * a + 1] = sec;
+        sel[3 * a + 2] = ter;
     }
 }
 
@@ -236,13 +298,13 @@ extern "C" hra_status hra_datum_frames(hra_ctx *ctx, const hra_bvh *bvh, int32_t
     }
     if (n <= 0) return HRA_OK;
     if (n >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "part too large for the datum search");
-    PartMeta P;
-    HRA_HIP(hipMemcpyAsync(&P, bvh->parts + part, sizeof(P), hipMemcpyDeviceToHost, s));
-    // workspace: keys x2, values x2, starts, run ids, runs, sort and scan
-    // space, selection and its gathered runs
+    // workspace: keys x2, values x2, starts, run ids, runs, per-face offsets
+    // and weights, sort and scan space, selection and its gathered runs
     const int64_t sort_ws = sort_pairs_ws_elems(n), scan_ws = scan_u32_ws_elems(n);
-    const size_t bytes = 16 * (size_t)n + 8 * (size_t)n + 8 * (size_t)n + sizeof(DatumRun) * (size_t)n +
-                         4 * (size_t)(sort_ws + scan_ws) + 4 * 18 + sizeof(DatumRun) * 18 + 256;
+    // (thirteen pieces, each padded to a multiple of 16 bytes)
+    const size_t bytes = 16 * (size_t)n + 8 * (size_t)n + 8 * (size_t)n + 16 * (size_t)n +
+                         sizeof(DatumRun) * (size_t)n + 4 * (size_t)(sort_ws + scan_ws) + 4 * 18 +
+                         sizeof(DatumRun) * 18 + 13 * 16;
     char *ws = nullptr;
     HRA_HIP(hipMallocAsync((void **)&ws, bytes, s));
     char *q = ws;
@@ -255,31 +317,40 @@ extern "C" hra_status hra_datum_frames(hra_ctx *ctx, const hra_bvh *bvh, int32_t
     uint32_t *v0 = (uint32_t *)take(4 * n), *v1 = (uint32_t *)take(4 * n);
     uint32_t *flags = (uint32_t *)take(4 * n), *rid = (uint32_t *)take(4 * n);
     DatumRun *runs = (DatumRun *)take(sizeof(DatumRun) * n);
+    double *hf = (double *)take(8 * n);
+    uint64_t *wf = (uint64_t *)take(8 * n);
     uint32_t *sws = (uint32_t *)take(4 * sort_ws), *cws = (uint32_t *)take(4 * scan_ws);
     int32_t *sel = (int32_t *)take(4 * 18);
     DatumRun *picked = (DatumRun *)take(sizeof(DatumRun) * 18);
     const unsigned nb = (unsigned)((n + DT_TB - 1) / DT_TB);
     hipError_t e = hipSuccess;
-    k_datum_keys<<<nb, DT_TB, 0, s>>>(bvh->tris, bvh->leaf_pos, t0, n, k0, v0);
+    k_datum_keys<<<nb, DT_TB, 0, s>>>(bvh->tris, bvh->leaf_pos, bvh->prefix, t0, n, k0, v0, hf, wf);
     bool in_k1 = false;
     e = hipGetLastError();
     if (e == hipSuccess) e = sort_pairs(k0, v0, k1, v1, n, sws, s, &in_k1);
     const uint64_t *ks = in_k1 ? k1 : k0;
     const uint32_t *vs = in_k1 ? v1 : v0;
     if (e == hipSuccess) {
-        k_datum_starts<<<nb, DT_TB, 0, s>>>(ks, vs, bvh->tris, bvh->leaf_pos, t0, n, bvh->parts + part, flags);
+        k_datum_starts<<<nb, DT_TB, 0, s>>>(ks, vs, hf, n, bvh->parts + part, flags);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = scan_u32(flags, rid, n, true, cws, s);
     if (e == hipSuccess) {
         k_datum_clear<<<nb, DT_TB, 0, s>>>(runs, n);
-        k_datum_accum<<<nb, DT_TB, 0, s>>>(ks, vs, flags, rid, bvh->tris, bvh->leaf_pos, bvh->prefix, t0, n, runs);
+        const int64_t acc_waves = (n + 64 * DT_ACC_TILES - 1) / (64 * DT_ACC_TILES);
+        k_datum_accum<<<(unsigned)((acc_waves + DT_TB / 64 - 1) / (DT_TB / 64)), DT_TB, 0, s>>>(ks, vs, flags, rid, hf,
+                                                                                              wf, n, runs);
         k_datum_select<<<1, DT_TB, 0, s>>>(runs, rid + (n - 1), sel);
         k_datum_gather<<<1, 64, 0, s>>>(runs, sel, picked);
         e = hipGetLastError();
     }
     DatumRun h[18];
+    // both copies after every launch: a copy to pageable host memory waits
+    // for the stream, which would leave the device idle while the launches
+    // behind it are enqueued
+    PartMeta P;
     if (e == hipSuccess) e = hipMemcpyAsync(h, picked, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&P, bvh->parts + part, sizeof(P), hipMemcpyDeviceToHost, s);
     const hipError_t ef = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = ef;
     if (e != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, "datum search launch failed", hipGetErrorString(e));
