@@ -323,8 +323,9 @@ int64_t hra_dirstats_bytes(int64_t n);
  * floor((d_z/|d| + 1) 32)) and az = min(127, floor((atan2(d_y, d_x) + pi)
  * 128 / (2 pi))) as in FP64: taken in FP32 where the coordinates lie clear
  * of a bin edge, else by that FP64 formula.
- * Part totals (counts per axis, blind samples, total unobstructed rays, sum
- * of concentrations in a fixed order) go to out->totals for hra_classify. */
+ * Part totals (counts per axis, blind samples, total unobstructed rays, and
+ * the concentrations summed as integers round(c 2^32), so the same on every
+ * run) go to out->totals for hra_classify. */
 hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs dirs, const uint32_t *d_bits,
                              const hra_dirstats *out, void *stream);
 

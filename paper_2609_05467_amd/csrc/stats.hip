@@ -15,7 +15,7 @@ struct DirTotals {
     unsigned long long n_axis[3];
     unsigned long long n_blind;
     unsigned long long n_unob;
-    double conc_sum;
+    unsigned long long conc_fx;   // sum of round(concentration x 2^32): an integer, so any order gives it
     double pad[2];
 };
 
@@ -250,51 +250,42 @@ static std::vector<float4> make_az_table() {
     return tab;
 }
 
-// Part totals, one block per part over its sample range [base, base + n)
-// (base == NULL: one part, range [0, n_one)): integer counts, and the FP64
-// sum of concentrations in a fixed order (thread t sums samples t, t + 1024,
-// ... in order, then a fixed tree), so the result does not depend on timing.
-constexpr int PT_THREADS = 1024;
+// Part totals over each part's sample range [base, base + n) (base ==
+// NULL: one part, range [0, n_one)): counts per axis, blind samples,
+// unobstructed rays, and the concentrations as integers round(c 2^32)
+// (c in [0, 1], so 2^31 samples fit in 64 bits; the mean is then within
+// 2^-33 of the FP64 mean).  Every total is an integer, so PT_CHUNKS blocks
+// per part add their shares with atomics in any order and the result is
+// the same on every run.  `tot` starts at zero (k_zero_u32).
+constexpr int PT_THREADS = 256;
+constexpr int PT_CHUNKS = 32;
 __global__ __launch_bounds__(PT_THREADS) void k_part_totals(const int8_t *axis, const uint32_t *cnt,
                                                             const double *conc64, const int64_t *base,
                                                             const int64_t *count, int64_t n_one, DirTotals *tot) {
-    __shared__ double sc[PT_THREADS];
-    __shared__ unsigned long long si[5][PT_THREADS];
-    const int p = blockIdx.x, t = threadIdx.x;
+    __shared__ unsigned long long si[6][PT_THREADS / 64];
+    const int p = blockIdx.y, t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t b0 = base ? base[p] : 0, n = base ? count[p] : n_one;
-    double acc = 0.0;
-    unsigned long long a0 = 0, a1 = 0, a2 = 0, bl = 0, un = 0;
-    for (int64_t i = b0 + t; i < b0 + n; i += PT_THREADS) {
-        acc += conc64[i];
+    unsigned long long a[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    for (int64_t i = b0 + (int64_t)blockIdx.x * PT_THREADS + t; i < b0 + n; i += (int64_t)PT_CHUNKS * PT_THREADS) {
         const int k = axis[i];
-        a0 += k == 0;
-        a1 += k == 1;
-        a2 += k == 2;
-        bl += k < 0;
-        un += cnt[i];
+        a[0] += k == 0;
+        a[1] += k == 1;
+        a[2] += k == 2;
+        a[3] += k < 0;
+        a[4] += cnt[i];
+        a[5] += __double2ull_rn(conc64[i] * 4294967296.0);
     }
-    sc[t] = acc;
-    si[0][t] = a0;
-    si[1][t] = a1;
-    si[2][t] = a2;
-    si[3][t] = bl;
-    si[4][t] = un;
+    for (int q = 0; q < 6; ++q) {
+        for (int off = 32; off > 0; off >>= 1) a[q] += __shfl_down(a[q], off, 64);
+        if (lane == 0) si[q][wv] = a[q];
+    }
     __syncthreads();
-    for (int off = PT_THREADS / 2; off > 0; off >>= 1) {
-        if (t < off) {
-            sc[t] += sc[t + off];
-            for (int q = 0; q < 5; ++q) si[q][t] += si[q][t + off];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        DirTotals &T = tot[p];
-        T.n_axis[0] = si[0][0];
-        T.n_axis[1] = si[1][0];
-        T.n_axis[2] = si[2][0];
-        T.n_blind = si[3][0];
-        T.n_unob = si[4][0];
-        T.conc_sum = sc[0];
+    if (t < 6) {
+        unsigned long long v = 0ull;
+        for (int w = 0; w < PT_THREADS / 64; ++w) v += si[t][w];
+        unsigned long long *T = reinterpret_cast<unsigned long long *>(tot + p);
+        // field order of DirTotals: n_axis[3], n_blind, n_unob, conc_fx
+        if (v) atomicAdd(T + t, v);
     }
 }
 
@@ -549,10 +540,22 @@ hipError_t launch_dirstats(hra_ctx *ctx, const float *normal, int64_t n, const f
     return hipGetLastError();
 }
 
+static_assert(sizeof(DirTotals) % sizeof(uint32_t) == 0, "totals are cleared as 32-bit words");
+
+// Zeroes n_parts totals, then adds each part's range (base NULL: one part,
+// [0, n_one)).  Kernels only, so the call can be captured in a graph.
+static hipError_t part_totals(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,
+                              const int64_t *d_count, int64_t n_one, int n_parts, DirTotals *tot, hipStream_t s) {
+    const int words = (int)(sizeof(DirTotals) / sizeof(uint32_t)) * n_parts;
+    k_zero_u32<<<(words + 255) / 256, 256, 0, s>>>(reinterpret_cast<uint32_t *>(tot), words);
+    if (d_base || n_one > 0) k_part_totals<<<dim3(PT_CHUNKS, n_parts), PT_THREADS, 0, s>>>(axis, cnt, c64, d_base,
+                                                                                         d_count, n_one, tot);
+    return hipGetLastError();
+}
+
 hipError_t launch_part_totals(const int8_t *axis, const uint32_t *cnt, const double *c64, const int64_t *d_base,
                               const int64_t *d_count, int n_parts, DirTotals *tot, hipStream_t s) {
-    k_part_totals<<<n_parts, PT_THREADS, 0, s>>>(axis, cnt, c64, d_base, d_count, 0, tot);
-    return hipGetLastError();
+    return part_totals(axis, cnt, c64, d_base, d_count, 0, n_parts, tot, s);
 }
 
 void classify_totals(const DirTotals &t, int64_t n, int32_t n_dirs, const hra_thresholds *th, hra_class_report *out) {
@@ -564,7 +567,7 @@ void classify_totals(const DirTotals &t, int64_t n, int32_t n_dirs, const hra_th
     out->n_unobstructed = t.n_unob;
     out->access = n ? (double)t.n_unob / ((double)n * (double)n_dirs) : 0.0;
     for (int k = 0; k < 3; ++k) out->share[k] = inc ? (double)t.n_axis[k] / (double)inc : 0.0;
-    out->mean_conc = inc ? t.conc_sum / (double)inc : 0.0;
+    out->mean_conc = inc ? std::ldexp((double)t.conc_fx, -32) / (double)inc : 0.0;
     const double smax = fmax(out->share[0], fmax(out->share[1], out->share[2]));
     int tr = 0;
     if (out->access < T.min_access) tr |= 1;
@@ -665,14 +668,12 @@ extern "C" hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples
         // no samples: an empty histogram and zero totals (fill kernels, so
         // the call can be captured in a graph)
         k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out->hist, HIST_BINS);
-        k_part_totals<<<1, PT_THREADS, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nullptr, 0, tot);
-        HRA_HIP(hipGetLastError());
+        HRA_HIP(part_totals(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 1, tot, s));
         return HRA_OK;
     }
     HRA_HIP(launch_dirstats(ctx, samples->normal, n, table, dirs.n, d_bits, *out, c64, cnt, true, s, nullptr,
                             INT64_MAX));
-    k_part_totals<<<1, PT_THREADS, 0, s>>>(out->axis, cnt, c64, nullptr, nullptr, n, tot);
-    HRA_HIP(hipGetLastError());
+    HRA_HIP(part_totals(out->axis, cnt, c64, nullptr, nullptr, n, 1, tot, s));
     return HRA_OK;
 }
 
@@ -741,8 +742,7 @@ extern "C" hra_status hra_dominant_axes_noalloc(hra_ctx *ctx, const hra_samples 
     uint32_t *cnt = (uint32_t *)(c64 + (n > 0 ? n : 0));
     if (n == 0) {
         k_zero_u32<<<HIST_BINS / 256, 256, 0, s>>>(out->hist, HIST_BINS);
-        k_part_totals<<<1, PT_THREADS, 0, s>>>(nullptr, nullptr, nullptr, nullptr, nullptr, 0, tot);
-        HRA_HIP(hipGetLastError());
+        HRA_HIP(part_totals(nullptr, nullptr, nullptr, nullptr, nullptr, 0, 1, tot, s));
         return HRA_OK;
     }
     // the table the cached one holds (same kernel), written on this stream
@@ -750,8 +750,7 @@ extern "C" hra_status hra_dominant_axes_noalloc(hra_ctx *ctx, const hra_samples 
     HRA_HIP(launch_fibonacci(dirs.n, table, s));
     HRA_HIP(launch_dirstats(ctx, samples->normal, n, table, dirs.n, d_bits, *out, c64, cnt, true, s, slices,
                             NA_SLICES));
-    k_part_totals<<<1, PT_THREADS, 0, s>>>(out->axis, cnt, c64, nullptr, nullptr, n, tot);
-    HRA_HIP(hipGetLastError());
+    HRA_HIP(part_totals(out->axis, cnt, c64, nullptr, nullptr, n, 1, tot, s));
     return HRA_OK;
 }
 
