@@ -334,7 +334,7 @@ hra_status hra_dominant_axes(hra_ctx *ctx, const hra_samples *samples, hra_dirs 
  * hipMalloc): the same outputs, bit for bit, with no allocation.  What
  * hra_dominant_axes allocates (its cached direction table and per-block
  * histogram slices) sits instead in a device array of the library, 32 MiB +
- * 128 KiB per device, held from the first context on that device until the
+ * 130 KiB per device, held from the first context on that device until the
  * process ends.  dirs.n must be 1..8192 (HRA_ERR_INVALID_ARG beyond).  Every
  * call on one device shares that array: calls that overlap on a device (two
  * streams, two threads) race and must be ordered by the caller.  Arguments,

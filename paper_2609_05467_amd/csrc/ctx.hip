@@ -1,5 +1,6 @@
 // Context, error word, direction tables.
 #include "common.hpp"
+#include "stages.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -107,10 +108,11 @@ hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out) {
         return HRA_OK;
     }
     // hemisphere tables hold the canonical order in [0, n) and the traversal
-    // order in [n, 2n)
+    // order in [n, 2n), then DIR_TABLE_PAD entries that may be read, never used
     float4 *p = nullptr;
     const bool hemi = dirs.kind == HRA_DIRS_HEMI_FIBONACCI;
-    HRA_HIP(hipMalloc(&p, sizeof(float4) * dirs.n * (hemi ? 2 : 1)));
+    const size_t entries = hemi ? 2 * (size_t)dirs.n + DIR_TABLE_PAD : (size_t)dirs.n;
+    HRA_HIP(hipMalloc(&p, sizeof(float4) * entries));
     if (!hemi)
         k_axes6<<<1, 64, 0, ctx->own>>>(p);
     else

@@ -8,6 +8,11 @@
 #include <vector>
 
 namespace hra {
+// Entries past the N directions of a direction table that stay readable
+// (hemisphere tables from dir_table, the allocation-free table):
+// k_dirstats prefetches the next 64 entries without clamping, up to 127
+// entries past N.
+constexpr int DIR_TABLE_PAD = 128;
 struct DirTotals;
 // Directional statistics of n samples (k_dirstats); with `hist`, the
 // direction histogram too, formed from per-block slices in `slices`

@@ -1,6 +1,7 @@
 // Directional statistics, classification, reachability and setups
 // (Section 3.3).
 #include "common.hpp"
+#include "stages.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -123,13 +124,16 @@ __global__ __launch_bounds__(64 * DS_WAVES) __attribute__((amdgpu_waves_per_eu(6
             __builtin_amdgcn_wave_barrier();
             const int32_t j0 = 32 * c;
             const int32_t nj = N - j0 < 4096 ? N - j0 : 4096;
-            const int32_t last = N - 1;
             float fa0 = 0.f, fa1 = 0.f, fa2 = 0.f;
-            float4 lnext = dirs[min(j0 + lane, last)];
+            // the table is readable DIR_TABLE_PAD entries past N, so neither
+            // read is clamped and both address from a uniform base
+            const float4 *dp = dirs + j0;
+            float4 lnext = dp[lane];
+#pragma unroll 2
             for (int32_t i = 0; i < nj; i += 64) {
                 const int32_t j = j0 + i + lane;
                 const float4 l = lnext;
-                lnext = dirs[min(j + 64, last)];
+                lnext = (dp + i + 64)[lane];
                 const uint32_t wd = rowbuf[wv][(i >> 5) + (lane >> 5)];
                 if ((wd >> (lane & 31)) & 1u) {
                     sl0 += (double)l.x;
@@ -682,7 +686,8 @@ namespace hra {
 // hra_dominant_axes_noalloc keeps what hra_dominant_axes allocates (the
 // canonical direction table, cached per context, and the per-block
 // histogram slices, taken from the stream-ordered allocator) in this array
-// instead: NA_MAX_DIRS float4 table entries, then NA_SLICES slices of
+// instead: NA_MAX_DIRS float4 table entries (and DIR_TABLE_PAD more that
+// k_dirstats may read), then NA_SLICES slices of
 // HIST_BINS words (NA_SLICES is at least DS_BLOCKS_PER_CU blocks on each of
 // MI355X's 256 compute units, the cap of the allocating launch, so both
 // launch the same grid there).  The module holds one copy per device until the process ends.
@@ -691,7 +696,7 @@ namespace hra {
 constexpr int32_t NA_MAX_DIRS = 8192;
 constexpr int64_t NA_SLICES = 1024;
 static_assert(NA_SLICES >= 256 * DS_BLOCKS_PER_CU, "slices for one block wave on 256 compute units");
-constexpr size_t NA_TABLE_BYTES = sizeof(float4) * NA_MAX_DIRS;
+constexpr size_t NA_TABLE_BYTES = sizeof(float4) * (NA_MAX_DIRS + DIR_TABLE_PAD);
 constexpr size_t NA_SCRATCH_BYTES = NA_TABLE_BYTES + sizeof(uint32_t) * HIST_BINS * NA_SLICES;
 static __device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];
 
