@@ -7,13 +7,16 @@
 // no triangle of the part comes closer to L than r - tol, tol = 1e-4 x the
 // part's bounding-box diagonal (the tool touches its own face at exactly r).
 //
-// One lane per (sample, direction), the directions of a sample on
-// consecutive lanes in traversal order (neighbouring rays, shared nodes).
+// One lane per (sample, direction) at a time, the directions of a sample
+// on consecutive lanes in traversal order (neighbouring rays, shared
+// nodes), each lane taking the next direction of its wave's range when its
+// own is settled.
 // The hierarchy is walked with FP32 slab tests against boxes grown by r and
 // a margin (conservative: the capsule inside a grown box's sweep), and each
 // candidate triangle's distance to L is computed in FP64: the plain
 // definition (0 if L meets the triangle, else the least of the distance
 // from c to the triangle and the three edge-to-L distances).
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -33,6 +36,8 @@ struct ToolArgs {
     const float4 *dirs;           // hemisphere: traversal order, w = canonical index bits; axes: the six axes
     int32_t n_dirs, kind, W, n_nodes_alloc;
     int64_t n_samples, n_rays;
+    int32_t rays_per_lane;        // a wave's range: 64 x this consecutive directions
+    int32_t pad;
     double radius;
     double hlen, hrad;            // holder: cutter length from the tip centre and holder radius (HOLDER only)
     uint32_t *bits;               // [n_samples][W], cleared first
@@ -220,6 +225,13 @@ __device__ inline bool tool_blocked(D3 c, D3 u, float4 A4, float4 B4, float4 C4,
 // thr2), the holder the half-line from g = c + (cutting length + holder
 // radius) u (thr_h2): its rounded nose reaches down to the end of the
 // cutting length.
+// The plain tool's batch calls the test out of line: inlined, its
+// temporaries pushed the walk's per-direction state (grown-box origins)
+// into scratch, reloaded at every node visit (impeller 92 -> 61 ms).
+__device__ __noinline__ bool tool_blocked_call(D3 c, D3 u, float4 A4, float4 B4, float4 C4, double thr2) {
+    return tool_blocked(c, u, A4, B4, C4, thr2);
+}
+
 __device__ inline bool tool_blocked_holder(D3 c, D3 g, D3 u, float4 A4, float4 B4, float4 C4, double thr2,
                                            double thr_h2) {
     return tool_blocked(c, u, A4, B4, C4, thr2) || tool_blocked(g, u, A4, B4, C4, thr_h2);
@@ -274,20 +286,35 @@ __device__ inline float rcp_guarded(float x) { return fabsf(x) > 1e-30f ? 1.0f /
 // triangles in FP32, one unit of work per loop iteration (a node visit or a
 // screen, in the visit order of a plain recursive walk); a triangle that
 // survives its screen goes to the wave's queue in LDS, and whenever 64
-// wait, the whole wave runs 64 FP64 tests at once, each against the tip
-// centre and direction its owner stored in LDS.  A test that finds its
-// owner blocked sets the owner's bit in the wave's blocked mask; the owner
-// then stops walking and the wave skips its queued tests.  A lane whose walk
-// has ended waits for its queued tests; the loop ends when no lane walks
-// and the queue is empty.  Lanes coordinate through LDS words read by the
-// whole wave at the top of each iteration, never through cross-lane
-// instructions, and every lane stays in the loop to its end.
+// wait, or no lane walks, or enough lanes wait on their queued tests, the
+// whole wave runs up to 64
+// FP64 tests at once, each against the tip centre and direction its owner
+// stored in LDS.  A test that finds its owner blocked sets the owner's bit
+// in the wave's blocked mask; the owner then stops walking and the wave
+// skips its queued tests.
+//
+// Each wave owns a range of 64 x TOOL_RAYS_PER_LANE consecutive directions
+// (a sample's directions in traversal order, then the next sample's).  A
+// lane whose direction is settled (walk ended and every test it queued
+// done, or blocked and its queued entries passed) writes its bit and takes
+// the next direction of the range from a counter in LDS, so the wave runs
+// for about the mean walk of its directions instead of the longest one.  A
+// lane takes a new direction only once the queue head has passed its last
+// entry, so no queued entry ever names a lane's earlier direction.  The
+// loop ends when no lane holds a direction (the range is used up, and
+// every lane settled, so the queue is empty).  Lanes coordinate through
+// LDS words read by the whole wave at the top of each iteration, never
+// through cross-lane instructions, and every lane stays in the loop to its
+// end.
 //
 // Four waves per SIMD (128 VGPRs, the FP64 test inline in the batch).
 // HOLDER: the tool and the holder of tool_blocked_holder; boxes, screens
 // and tests take each with its own radius and half-line.
 constexpr int TOOL_WAVES = TOOL_THREADS / 64;
 constexpr int TOOL_Q = 128;   // queue entries per wave: at most 63 wait after a batch, at most 64 join per iteration
+constexpr int TOOL_RAYS_PER_LANE = 8;   // the most directions per lane (the launch picks fewer for small casts)
+constexpr int TOOL_BATCH_WAIT = 16;   // a batch also runs once this many lanes wait on queued tests
+enum : int { TS_IDLE = 0, TS_WALK = 1, TS_WAIT = 2 };
 
 template <bool STATS, bool HOLDER>
 __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_cast_tool(ToolArgs a) {
@@ -295,87 +322,144 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
     __shared__ int32_t q_tri[TOOL_WAVES][TOOL_Q];
     __shared__ uint8_t q_own[TOOL_WAVES][TOOL_Q];
     __shared__ double cu[TOOL_WAVES][64][6];       // per lane: tip centre c, unit direction u
-    __shared__ int ctl[TOOL_WAVES][4];             // per wave: queue head, queue tail, walking lanes
+    __shared__ int ctl[TOOL_WAVES][6];             // per wave: queue head, queue tail, walking lanes,
+                                                   // lanes holding a direction, next direction of the
+                                                   // range, lanes whose walk ended and that wait
     __shared__ unsigned long long blk[TOOL_WAVES]; // per wave: lanes whose direction is blocked
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t g = (int64_t)blockIdx.x * TOOL_THREADS + threadIdx.x;
-    const bool alive = g < a.n_rays;
-    const int64_t s = alive ? g / a.n_dirs : 0;
-    const int32_t j = alive ? (int32_t)(g - s * a.n_dirs) : 0;
+    const int64_t wave_id = (int64_t)blockIdx.x * TOOL_WAVES + wv;
+    const int64_t range0 = wave_id * (64 * (int64_t)a.rays_per_lane);
+    const int64_t range1 = min(range0 + 64 * (int64_t)a.rays_per_lane, a.n_rays);
     const PartMeta &P = *a.meta;
-    const float px = a.point[3 * s], py = a.point[3 * s + 1], pz = a.point[3 * s + 2];
-    const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
-    const float4 l = a.dirs[j];
-    int32_t idx;
-    float3 d;
-    bool cast = alive;
-    if (a.kind == 0) {
-        float3 t, b;
-        onb_frame(nx, ny, nz, t, b);
-        d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
-        idx = __float_as_int(l.w);
-    } else {
-        d = make_float3(l.x, l.y, l.z);
-        idx = j;
-        // into the material: not cast, bit 0
-        cast = cast && !((nx * d.x + ny * d.y) + nz * d.z < 0.0f);
-    }
     const double r = a.radius, tol = 1e-4 * P.diag, thr = r - tol;
     const double rr = HOLDER ? fmax(r, a.hrad) : r, thr_h = HOLDER ? a.hrad - tol : thr;
-    if (cast && !(thr > tol)) {   // a tool thinner than twice the tolerance is not meaningful
-        atomicOr(a.err, ERR_TOOL_RADIUS);
-        cast = false;
-    }
-    const D3 c = mk((double)px + r * (double)nx, (double)py + r * (double)ny, (double)pz + r * (double)nz);
-    const double dl = sqrt(((double)d.x * d.x + (double)d.y * d.y) + (double)d.z * d.z);
-    const D3 u = mk(d.x / dl, d.y / dl, d.z / dl);
     const double glen = a.hlen + a.hrad;          // HOLDER: the holder's half-line starts at c + glen u
     const double thr2 = thr * thr, thr_h2 = thr_h * thr_h;
     const int32_t root = P.root, n_valid = P.n_valid, n_tris_alloc = P.leaf_lo + P.n_valid;
-    cu[wv][lane][0] = c.x;
-    cu[wv][lane][1] = c.y;
-    cu[wv][lane][2] = c.z;
-    cu[wv][lane][3] = u.x;
-    cu[wv][lane][4] = u.y;
-    cu[wv][lane][5] = u.z;
+    // FP32 box tests from the rounded tip centre; the margin covers the
+    // rounding of the centre and of the grown box faces
+    const float pad = (float)(rr * 1.0001) + (float)(1e-5 * P.diag);
+    const float pad_c = (float)(r * 1.0001) + (float)(1e-5 * P.diag);   // the cutter's (HOLDER)
+    const float gl = (float)glen;
+    const double gap = glen;   // the holder's start along u, for the batch's tests
     if (lane == 0) {
         ctl[wv][0] = 0;
         ctl[wv][1] = 0;
         ctl[wv][2] = 0;
+        ctl[wv][3] = 0;
+        ctl[wv][4] = 64;
+        ctl[wv][5] = 0;
         blk[wv] = 0ull;
     }
     __syncthreads();
-    bool walking = cast && n_valid > 0;
-    if (walking) atomicAdd(&ctl[wv][2], 1);
-    __syncthreads();
-    // FP32 box tests from the rounded tip centre; the margin covers the
-    // rounding of the centre and of the grown box faces
-    const float cx = (float)c.x, cy = (float)c.y, cz = (float)c.z;
-    const float pad = (float)(rr * 1.0001) + (float)(1e-5 * P.diag);
-    const float pad_c = (float)(r * 1.0001) + (float)(1e-5 * P.diag);   // the cutter's (HOLDER)
-    const float ix = rcp_guarded(d.x), iy = rcp_guarded(d.y), iz = rcp_guarded(d.z);
-    const Shifted so = shift(cx, cy, cz, pad), so_c = shift(cx, cy, cz, pad_c);
-    // unit direction and threshold for the FP32 screen; the margin
-    // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a part
-    // far from the origin) is far above the screen's rounding
-    const float ux = (float)u.x, uy = (float)u.y, uz = (float)u.z;
-    const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
-    const float thr_hi = (float)(fmax(thr, thr_h) + 1e-5 * P.diag + 1e-6 * cmax);
-    const float thr_c_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax), gl = (float)glen;
-    const double gap = glen;   // the holder's start along u, for the batch's tests
+
+    // the lane's direction: sample s, bit index idx; tip centre and
+    // direction for the FP32 walk; the traversal state
+    int64_t s = 0;
+    int32_t idx = 0;
+    bool cast = false, bad = false;
+    float cx = 0.f, cy = 0.f, cz = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, ix = 0.f, iy = 0.f, iz = 0.f;
+    float thr_hi = 0.f, thr_c_hi = 0.f;
+    Shifted so{}, so_c{};
     int spill[TOOL_SPILL];
     int sp = 0;
-    int32_t node = is_leaf(root) ? -1 : root;
-    int32_t ti = is_leaf(root) ? leaf_first(root) : 0, tn = is_leaf(root) ? leaf_count(root) : 0;
-    int32_t budget = 2 * a.n_nodes_alloc + 64;
-    bool bad = false;
+    int32_t node = -1, ti = 0, tn = 0, budget = 0;
+    int state = TS_IDLE;
+    int last = 0;   // queue position after this direction's last entry
     uint32_t n_nodes = 0, n_tests = 0, n_cands = 0;
+
+    // Take direction g of the range: set the lane up to walk it (or to
+    // settle at once, when it is not cast).
+    auto begin = [&](int64_t g) {
+        s = g / a.n_dirs;
+        const int32_t j = (int32_t)(g - s * a.n_dirs);
+        const float px = a.point[3 * s], py = a.point[3 * s + 1], pz = a.point[3 * s + 2];
+        const float nx = a.normal[3 * s], ny = a.normal[3 * s + 1], nz = a.normal[3 * s + 2];
+        const float4 l = a.dirs[j];
+        float3 d;
+        cast = true;
+        if (a.kind == 0) {
+            float3 t, b;
+            onb_frame(nx, ny, nz, t, b);
+            d = rotate_dir(t, b, nx, ny, nz, l.x, l.y, l.z);
+            idx = __float_as_int(l.w);
+        } else {
+            d = make_float3(l.x, l.y, l.z);
+            idx = j;
+            // into the material: not cast, bit 0
+            cast = !((nx * d.x + ny * d.y) + nz * d.z < 0.0f);
+        }
+        if (cast && !(thr > tol)) {   // a tool thinner than twice the tolerance is not meaningful
+            atomicOr(a.err, ERR_TOOL_RADIUS);
+            cast = false;
+        }
+        const D3 c = mk((double)px + r * (double)nx, (double)py + r * (double)ny, (double)pz + r * (double)nz);
+        const double dl = sqrt(((double)d.x * d.x + (double)d.y * d.y) + (double)d.z * d.z);
+        const D3 u = mk(d.x / dl, d.y / dl, d.z / dl);
+        cu[wv][lane][0] = c.x;
+        cu[wv][lane][1] = c.y;
+        cu[wv][lane][2] = c.z;
+        cu[wv][lane][3] = u.x;
+        cu[wv][lane][4] = u.y;
+        cu[wv][lane][5] = u.z;
+        cx = (float)c.x;
+        cy = (float)c.y;
+        cz = (float)c.z;
+        ix = rcp_guarded(d.x);
+        iy = rcp_guarded(d.y);
+        iz = rcp_guarded(d.z);
+        so = shift(cx, cy, cz, pad);
+        so_c = shift(cx, cy, cz, pad_c);
+        // unit direction and threshold for the FP32 screen; the margin
+        // (1e-5 x diagonal, plus 1e-6 of the coordinates' magnitude for a
+        // part far from the origin) is far above the screen's rounding
+        ux = (float)u.x;
+        uy = (float)u.y;
+        uz = (float)u.z;
+        const double cmax = fmax(fmax(fabs(c.x), fabs(c.y)), fabs(c.z)) + P.diag;
+        thr_hi = (float)(fmax(thr, thr_h) + 1e-5 * P.diag + 1e-6 * cmax);
+        thr_c_hi = (float)(thr + 1e-5 * P.diag + 1e-6 * cmax);
+        sp = 0;
+        node = is_leaf(root) ? -1 : root;
+        ti = is_leaf(root) ? leaf_first(root) : 0;
+        tn = is_leaf(root) ? leaf_count(root) : 0;
+        budget = 2 * a.n_nodes_alloc + 64;
+        bad = false;
+        last = 0;
+        if (cast && n_valid > 0) {
+            state = TS_WALK;
+            atomicAdd(&ctl[wv][2], 1);
+        } else {
+            state = TS_WAIT;
+        }
+    };
+
+    // A lane's first direction is range0 + lane, later ones come from the
+    // range's counter.  The plain tool starts every lane settled on no
+    // direction (cast false, nothing queued), so the first one comes from
+    // the set-up site in the loop; the holder's sets it up here as well.
+    // Both orders give the same directions; they differ only in how the
+    // compiler allocates registers (measured: plain 61 against 66 ms,
+    // holder 188 against 214 ms on the impeller-like part).
+    bool first = !HOLDER, walked = false;
+    if constexpr (HOLDER) {
+        if (range0 + lane < range1) {
+            atomicAdd(&ctl[wv][3], 1);
+            begin(range0 + lane);
+        }
+    } else {
+        state = TS_WAIT;
+        if (lane == 0) ctl[wv][3] = 64;
+    }
+    __syncthreads();
     while (true) {
         const int head = __hip_atomic_load(&ctl[wv][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         const int tail = __hip_atomic_load(&ctl[wv][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         const int n_walk = __hip_atomic_load(&ctl[wv][2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int n_busy = __hip_atomic_load(&ctl[wv][3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int n_wait = __hip_atomic_load(&ctl[wv][5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         const int qn = tail - head;
-        if (qn >= 64 || (n_walk == 0 && qn > 0)) {
+        if (qn > 0 && (qn >= 64 || n_walk == 0 || n_wait >= TOOL_BATCH_WAIT)) {
             // a batch of FP64 tests, one per lane
             if (lane < qn) {
                 const int slot = (head + lane) & (TOOL_Q - 1);
@@ -390,7 +474,7 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                     const float4 A4 = t[0], B4 = t[1], C4 = t[2];
                     if (STATS) ++n_tests;
                     const bool hit = HOLDER ? tool_blocked_holder(oc, oc + gap * ou, ou, A4, B4, C4, thr2, thr_h2)
-                                            : tool_blocked(oc, ou, A4, B4, C4, thr2);
+                                            : tool_blocked_call(oc, ou, A4, B4, C4, thr2);
                     if (hit) atomicOr(&blk[wv], 1ull << own);
                 }
             }
@@ -399,9 +483,9 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
             __builtin_amdgcn_wave_barrier();
             continue;
         }
-        if (n_walk == 0) break;
-        if (walking) {
-            const unsigned long long bm = __hip_atomic_load(&blk[wv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (n_busy == 0) break;
+        const unsigned long long bm = __hip_atomic_load(&blk[wv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (state == TS_WALK) {
             bool end = ((bm >> lane) & 1ull) != 0ull;
             if (!end && tn > 0) {
                 // screen one triangle of the current leaf
@@ -414,9 +498,11 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                     const bool far = HOLDER ? far_from_holder_tool(cx, cy, cz, ux, uy, uz, gl, A4, B4, C4, thr_c_hi, thr_hi)
                                             : far_from_axis(cx, cy, cz, ux, uy, uz, A4, B4, C4, thr_hi);
                     if (!far) {
-                        const int slot = atomicAdd(&ctl[wv][1], 1) & (TOOL_Q - 1);
+                        const int pos = atomicAdd(&ctl[wv][1], 1);
+                        const int slot = pos & (TOOL_Q - 1);
                         q_tri[wv][slot] = ti;
                         q_own[wv][slot] = (uint8_t)lane;
+                        last = pos + 1;
                     }
                 }
                 ++ti;
@@ -479,14 +565,31 @@ __global__ __launch_bounds__(TOOL_THREADS) __attribute__((amdgpu_waves_per_eu(4)
                 }
             }
             if (end || bad) {
-                walking = false;
+                state = TS_WAIT;
+                walked = true;
                 atomicSub(&ctl[wv][2], 1);
+                atomicAdd(&ctl[wv][5], 1);
+            }
+        } else if (state == TS_WAIT && head >= last) {
+            // settled: every entry this direction queued has been tested or
+            // skipped, so its blocked bit is final
+            const bool blocked = ((bm >> lane) & 1ull) != 0ull;
+            if (bad) atomicOr(a.err, ERR_STACK);
+            if (cast && !bad && !blocked) atomicOr(&a.bits[s * a.W + (idx >> 5)], 1u << (idx & 31));
+            if (blocked) atomicAnd(&blk[wv], ~(1ull << lane));
+            if (walked) atomicSub(&ctl[wv][5], 1);
+            walked = false;
+            const int64_t g = range0 + (first ? lane : atomicAdd(&ctl[wv][4], 1));
+            first = false;
+            if (g < range1) {
+                begin(g);
+            } else {
+                state = TS_IDLE;
+                atomicSub(&ctl[wv][3], 1);
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (bad) atomicOr(a.err, ERR_STACK);
-    const unsigned long long bm = __hip_atomic_load(&blk[wv], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (cast && !bad && !((bm >> lane) & 1ull)) atomicOr(&a.bits[s * a.W + (idx >> 5)], 1u << (idx & 31));
     if (STATS) {
         atomicAdd(a.work, (unsigned long long)n_nodes);
         atomicAdd(a.work + 1, (unsigned long long)n_tests);
@@ -553,7 +656,14 @@ static hra_status tool_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, co
     a.err = ctx->d_err;
     a.work = work;
     const int64_t words = samples->n * (int64_t)a.W;
-    const int64_t blocks = (a.n_rays + TOOL_THREADS - 1) / TOOL_THREADS;
+    // longer ranges balance a wave's lanes better, shorter ones give more
+    // waves: ranges grow only while the grid keeps about 64 waves per
+    // compute unit (four times what fits at once)
+    const int64_t per_range = 64 * (int64_t)std::max(ctx->n_cu, 1) * 64;
+    a.rays_per_lane = (int32_t)std::min<int64_t>(TOOL_RAYS_PER_LANE, std::max<int64_t>(1, a.n_rays / per_range));
+    a.pad = 0;
+    const int64_t rays_per_block = (int64_t)TOOL_THREADS * a.rays_per_lane;
+    const int64_t blocks = (a.n_rays + rays_per_block - 1) / rays_per_block;
     if (blocks >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many rays for one call");
     k_tool_zero<<<(unsigned)((words + 255) / 256), 256, 0, s>>>(d_bits, words);
     if (holder) {
