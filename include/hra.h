@@ -577,13 +577,18 @@ hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *parts, int32_t 
  * statistics, six-axis cast, setups; results as for hra_batch_run.  With
  * use_graph != 0 the first call captures the sequence (kernels and three
  * copies into pinned memory; no allocation, memset or host callback) in a
- * HIP graph on the plan's own stream and every call replays it.  Without a
+ * HIP graph on the plan's own streams (the six-axis cast and the setups on
+ * a second stream beside the cast, forked and joined by events) and every
+ * call replays it.  Without a
  * graph the per-stage times are kept (hra_plan_stage_ms).  Runs of one plan
  * must not overlap: the call synchronises before it returns. */
 hra_status hra_plan_run(hra_plan *plan, int32_t use_graph, hra_part_result *results, uint32_t *d_bits_out,
                         void *stream);
 /* Milliseconds of the last run without a graph: build, sample, cast,
- * statistics and totals, six-axis cast, setups. */
+ * statistics and totals, six-axis cast, setups.  The six-axis cast and the
+ * setups run on a second stream of the plan beside the cast and the
+ * statistics: their times are that stream's intervals from the end of the
+ * sampling, and they share the device with the cast meanwhile. */
 hra_status hra_plan_stage_ms(const hra_plan *plan, float *ms6);
 /* Device bytes the plan holds. */
 int64_t hra_plan_bytes(const hra_plan *plan);

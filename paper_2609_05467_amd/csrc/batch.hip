@@ -128,13 +128,21 @@ hipError_t upload_packed_jobs(const StageBufs &B, const char *src, int32_t n, hi
 
 // The stage sequence after the build: kernels, then three copies of the
 // per-job results into pinned host slots.  ev (optional, eager runs only)
-// receives an event before each stage and one at the end.
+// receives an event before each stage and one at the end: ev[0..3] on s
+// (before the samples, after them, after the cast, after the statistics),
+// ev[4] after the six-axis cast and ev[5] after the setups, on the side
+// stream when there is one.
 hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B, void *h_tot,
-                          unsigned long long *h_cc, uint32_t *h_ch, hipStream_t s, hipEvent_t *ev, uint32_t *err) {
+                          unsigned long long *h_cc, uint32_t *h_ch, hipStream_t s, hipEvent_t *ev, uint32_t *err,
+                          hipStream_t side, hipEvent_t fork, hipEvent_t join) {
     hipError_t e = hipSuccess;
+    const bool forked = side && fork && join;
     if (ev) e = hipEventRecord(ev[0], s);
     if (e == hipSuccess) e = launch_sample(B.dsj, sh.n_jobs, sh.sj0, sh.S, B.pt, B.nr, B.org, B.tri, s);
     if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (forked && e == hipSuccess) e = hipEventRecord(fork, s);
+    if (forked && e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    const hipStream_t sa = forked ? side : s;   // the six-axis cast and the setups
     if (e == hipSuccess) {
         CastArgs a;
         a.jobs = B.dcj;
@@ -170,17 +178,20 @@ hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B
         a.group = 1;
         a.err = err;
         a.work = nullptr;
-        e = launch_cast_any(a, 64, sh.stack, sh.trav, false, s);
+        e = launch_cast_any(a, 64, sh.stack, sh.trav, false, sa);
     }
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[4], s);
-    if (e == hipSuccess) e = launch_setups_raw(B.dsetj, sh.n_jobs, sh.S, B.pt, B.tri, B.abits, B.cc, B.chist, err, s);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[4], sa);
+    if (e == hipSuccess) e = launch_setups_raw(B.dsetj, sh.n_jobs, sh.S, B.pt, B.tri, B.abits, B.cc, B.chist, err, sa);
+    if (ev && forked && e == hipSuccess) e = hipEventRecord(ev[5], sa);
+    if (forked && e == hipSuccess) e = hipEventRecord(join, side);
+    if (forked && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h_tot, B.tot, dir_totals_size() * sh.n_jobs, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h_cc, B.cc, sizeof(unsigned long long) * 4 * sh.n_jobs, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h_ch, B.chist, sizeof(uint32_t) * 64 * sh.n_jobs, hipMemcpyDeviceToHost, s);
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[5], s);
+    if (ev && !forked && e == hipSuccess) e = hipEventRecord(ev[5], s);
     return e;
 }
 
@@ -215,7 +226,9 @@ struct hra_plan {
     unsigned long long *h_cc = nullptr;
     uint32_t *h_ch = nullptr;
     hipStream_t own = nullptr;
+    hipStream_t side = nullptr;   // the six-axis cast and the setups, beside the cast
     hipEvent_t ev[7] = {};
+    hipEvent_t fork = nullptr, join = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -227,12 +240,16 @@ extern "C" void hra_plan_destroy(hra_plan *P) {
     if (!P) return;
     hipSetDevice(P->device);
     if (P->own) hipStreamSynchronize(P->own);
+    if (P->side) hipStreamSynchronize(P->side);
     if (P->exec) hipGraphExecDestroy(P->exec);
     if (P->graph) hipGraphDestroy(P->graph);
     for (hipEvent_t e : P->ev)
         if (e) hipEventDestroy(e);
     if (P->ev_in) hipEventDestroy(P->ev_in);
     if (P->ev_out) hipEventDestroy(P->ev_out);
+    if (P->fork) hipEventDestroy(P->fork);
+    if (P->join) hipEventDestroy(P->join);
+    if (P->side) hipStreamDestroy(P->side);
     if (P->own) hipStreamDestroy(P->own);
     if (P->bvh) hra_bvh_release(P->bvh);
     hipFree(P->ws);
@@ -320,6 +337,9 @@ extern "C" hra_status hra_plan_create(hra_ctx *ctx, const hra_part_request *part
     for (int k = 0; k < 7 && e == hipSuccess; ++k) e = hipEventCreate(&P->ev[k]);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join, hipEventDisableTiming);
     StageShape &sh = P->sh;
     sh.N = N;
     sh.W = W;
@@ -355,7 +375,8 @@ static hipError_t plan_enqueue(hra_plan *P, hipStream_t s, bool timed) {
     if (timed) e = hipEventRecord(P->ev[6], s);
     if (e == hipSuccess) e = enqueue_build(P->ctx, P->bvh, P->ws, s, P->ctx->d_err);
     if (e == hipSuccess)
-        e = enqueue_stages(P->ctx, P->sh, P->B, P->h_tot, P->h_cc, P->h_ch, s, timed ? P->ev : nullptr, P->ctx->d_err);
+        e = enqueue_stages(P->ctx, P->sh, P->B, P->h_tot, P->h_cc, P->h_ch, s, timed ? P->ev : nullptr, P->ctx->d_err,
+                           P->side, P->fork, P->join);
     return e;
 }
 
@@ -398,6 +419,7 @@ extern "C" hra_status hra_plan_run(hra_plan *P, int32_t use_graph, hra_part_resu
     if (e == hipSuccess) e = hipStreamWaitEvent(caller, P->ev_out, 0);
     if (e != hipSuccess) {
         hipStreamSynchronize(s);
+        hipStreamSynchronize(P->side);
         return ctx->fail(HRA_ERR_DEVICE, "batch launch failed", hipGetErrorString(e));
     }
     hra_status st = check_error_word(ctx, s);   // synchronises the plan's stream
@@ -405,7 +427,11 @@ extern "C" hra_status hra_plan_run(hra_plan *P, int32_t use_graph, hra_part_resu
     if (!use_graph) {
         float t[6];
         hipEventElapsedTime(&t[0], P->ev[6], P->ev[0]);   // build
-        for (int k = 0; k < 5; ++k) hipEventElapsedTime(&t[k + 1], P->ev[k], P->ev[k + 1]);
+        for (int k = 0; k < 3; ++k) hipEventElapsedTime(&t[k + 1], P->ev[k], P->ev[k + 1]);
+        // the six-axis cast from the samples' end (it starts there, on the
+        // side stream, beside the cast), then the setups after it
+        hipEventElapsedTime(&t[4], P->ev[1], P->ev[4]);
+        hipEventElapsedTime(&t[5], P->ev[4], P->ev[5]);
         for (int k = 0; k < 6; ++k) P->stage_ms[k] = t[k];
     }
     decode_results(P->sh, P->count, P->h_tot, P->h_cc, P->h_ch, P->has_th ? &P->th : nullptr, results);

@@ -80,8 +80,14 @@ size_t job_table_bytes(int32_t n_jobs);
 void pack_jobs(const HostJobs &H, char *dst);
 // Copies of a packed job block to the device tables.
 hipError_t upload_packed_jobs(const StageBufs &B, const char *src, int32_t n_jobs, hipStream_t s);
+// The stage sequence on s.  With a side stream (and its fork and join
+// events), the six-axis cast and the setups, which need only the samples
+// and the hierarchy, run on it beside the hemisphere cast and the
+// statistics, and s waits for them before the copies; without one they
+// follow the statistics on s.
 hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B, void *h_tot,
-                          unsigned long long *h_cc, uint32_t *h_ch, hipStream_t s, hipEvent_t *ev, uint32_t *err);
+                          unsigned long long *h_cc, uint32_t *h_ch, hipStream_t s, hipEvent_t *ev, uint32_t *err,
+                          hipStream_t side = nullptr, hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 void decode_results(const StageShape &sh, const std::vector<int64_t> &count, const void *h_tot,
                     const unsigned long long *h_cc, const uint32_t *h_ch, const hra_thresholds *th,
                     hra_part_result *results);
