@@ -963,10 +963,12 @@ extern "C" int32_t hra_bvh_parts(const hra_bvh *b) { return b ? b->n_parts : 0; 
 extern "C" hra_status hra_bvh_part_info(hra_bvh *b, int32_t part, void *stream, hra_bvh_info *out) {
     if (!b || !out || part < 0 || part >= b->n_parts) return HRA_ERR_INVALID_ARG;
     hra_ctx *ctx = b->ctx;
-    hra_status st = check_error_word(ctx, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    hra_status st = check_error_word(ctx, s);
     if (st != HRA_OK) return st;
     PartMeta m;
-    HRA_HIP(hipMemcpy(&m, b->parts + part, sizeof(m), hipMemcpyDeviceToHost));
+    HRA_HIP(hipMemcpyAsync(&m, b->parts + part, sizeof(m), hipMemcpyDeviceToHost, s));
+    HRA_HIP(hipStreamSynchronize(s));
     for (int k = 0; k < 6; ++k) out->bbox[k] = m.bbox[k];
     out->diag = m.diag;
     out->n_tris = m.n_tris;
@@ -986,13 +988,15 @@ extern "C" hra_status hra_bvh_export(hra_bvh *b, void *stream, void *host_nodes,
                                      int32_t *n_valid) {
     if (!b || !host_nodes || !host_tris || !root || !n_valid) return HRA_ERR_INVALID_ARG;
     hra_ctx *ctx = b->ctx;
-    hra_status st = check_error_word(ctx, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    hra_status st = check_error_word(ctx, s);
     if (st != HRA_OK) return st;
     PartMeta m;
-    HRA_HIP(hipMemcpy(&m, b->parts, sizeof(m), hipMemcpyDeviceToHost));
     const int64_t nn = b->n_tris > 1 ? b->n_tris - 1 : 1;
-    HRA_HIP(hipMemcpy(host_nodes, b->nodes, sizeof(Node) * nn, hipMemcpyDeviceToHost));
-    HRA_HIP(hipMemcpy(host_tris, b->tris, sizeof(float4) * 3 * b->n_tris, hipMemcpyDeviceToHost));
+    HRA_HIP(hipMemcpyAsync(&m, b->parts, sizeof(m), hipMemcpyDeviceToHost, s));
+    HRA_HIP(hipMemcpyAsync(host_nodes, b->nodes, sizeof(Node) * nn, hipMemcpyDeviceToHost, s));
+    HRA_HIP(hipMemcpyAsync(host_tris, b->tris, sizeof(float4) * 3 * b->n_tris, hipMemcpyDeviceToHost, s));
+    HRA_HIP(hipStreamSynchronize(s));
     *root = m.root;
     *n_valid = m.n_valid;
     return HRA_OK;

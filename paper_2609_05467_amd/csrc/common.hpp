@@ -100,6 +100,10 @@ struct hra_ctx {
     int32_t n_cu = 0;
     uint32_t *d_err = nullptr;        // device error word
     uint32_t *d_counter = nullptr;    // work counters for persistent kernels (64 words)
+    // pinned host staging for small readbacks on the caller's stream (a copy
+    // into pageable memory, or a blocking copy, can wait on other streams):
+    // bytes [0, 64) take the error word, [64, STAGE_BYTES) a call's results
+    void *h_stage = nullptr;
     hipStream_t own = nullptr;        // internal stream for table builds
     int32_t cast_rpw = 64;            // directions per wave work item
     int32_t cast_stack = 16;          // LDS stack entries per lane
@@ -250,6 +254,10 @@ hipError_t noalloc_setup(int device);
 // device array; called by hra_ctx_create with `device` current.
 hipError_t stats_setup(int device);
 hra_status check_error_word(hra_ctx *ctx, hipStream_t s);
+constexpr size_t STAGE_BYTES = 4096, STAGE_USER = 64;
+// ctx->h_stage + STAGE_USER: where a call copies its small results before
+// check_error_word synchronises the stream.
+inline void *stage_user(hra_ctx *ctx) { return (char *)ctx->h_stage + STAGE_USER; }
 int blocks_for(int64_t n, int threads);
 
 // SplitMix64 (Steele, Lea & Flood 2014) as a counter-based stream: output

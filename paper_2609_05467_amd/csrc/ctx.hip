@@ -123,9 +123,11 @@ hra_status dir_table(hra_ctx *ctx, hra_dirs dirs, const float4 **out) {
     HRA_HIP(hipStreamSynchronize(ctx->own));
     if (hemi) {
         std::vector<float4> h(dirs.n);
-        HRA_HIP(hipMemcpy(h.data(), p, sizeof(float4) * dirs.n, hipMemcpyDeviceToHost));
+        HRA_HIP(hipMemcpyAsync(h.data(), p, sizeof(float4) * dirs.n, hipMemcpyDeviceToHost, ctx->own));
+        HRA_HIP(hipStreamSynchronize(ctx->own));
         const std::vector<float4> o = traversal_order(h);
-        HRA_HIP(hipMemcpy(p + dirs.n, o.data(), sizeof(float4) * dirs.n, hipMemcpyHostToDevice));
+        HRA_HIP(hipMemcpyAsync(p + dirs.n, o.data(), sizeof(float4) * dirs.n, hipMemcpyHostToDevice, ctx->own));
+        HRA_HIP(hipStreamSynchronize(ctx->own));
     }
     ctx->dir_tables[key] = p;
     *out = p;
@@ -138,11 +140,15 @@ hipError_t launch_fibonacci(int32_t n, float4 *out, hipStream_t s) {
 }
 
 hra_status check_error_word(hra_ctx *ctx, hipStream_t s) {
+    // the word comes through pinned memory on s itself, so the call waits
+    // for s alone, not for work on other streams
+    uint32_t *hw = (uint32_t *)ctx->h_stage;
+    HRA_HIP(hipMemcpyAsync(hw, ctx->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HRA_HIP(hipStreamSynchronize(s));
-    uint32_t w = 0;
-    HRA_HIP(hipMemcpy(&w, ctx->d_err, sizeof(w), hipMemcpyDeviceToHost));
+    const uint32_t w = *hw;
     if (w == 0) return HRA_OK;
-    HRA_HIP(hipMemset(ctx->d_err, 0, sizeof(uint32_t)));
+    HRA_HIP(hipMemsetAsync(ctx->d_err, 0, sizeof(uint32_t), s));
+    HRA_HIP(hipStreamSynchronize(s));
     if (w & ERR_BAD_INDEX) return ctx->fail(HRA_ERR_BAD_MESH, "triangle index out of range");
     if (w & ERR_EMPTY_MESH) return ctx->fail(HRA_ERR_BAD_MESH, "mesh has no triangle with nonzero area");
     if (w & ERR_BAD_SAMPLE_TRI) return ctx->fail(HRA_ERR_INVALID_ARG, "a sample names a face outside the mesh");
@@ -180,7 +186,8 @@ hra_status hra_ctx_create(int32_t device, hra_ctx **out) {
     }
     if (hipMalloc(&ctx->d_err, sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&ctx->d_counter, 64 * sizeof(uint32_t)) != hipSuccess ||
-        hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc(&ctx->h_stage, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
         hra_ctx_destroy(ctx);
         return HRA_ERR_OUT_OF_MEMORY;
     }
@@ -200,6 +207,7 @@ void hra_ctx_destroy(hra_ctx *ctx) {
     for (auto &kv : ctx->dir_tables) hipFree(kv.second);
     if (ctx->d_err) hipFree(ctx->d_err);
     if (ctx->d_counter) hipFree(ctx->d_counter);
+    if (ctx->h_stage) hipHostFree(ctx->h_stage);
     if (ctx->own) hipStreamDestroy(ctx->own);
     delete ctx;
 }
@@ -212,7 +220,8 @@ hra_status hra_dirs_table(hra_ctx *ctx, hra_dirs dirs, float *host_out) {
     hra_status st = dir_table(ctx, dirs, &d);
     if (st != HRA_OK) return st;
     std::vector<float4> h(dirs.n);
-    HRA_HIP(hipMemcpy(h.data(), d, sizeof(float4) * dirs.n, hipMemcpyDeviceToHost));
+    HRA_HIP(hipMemcpyAsync(h.data(), d, sizeof(float4) * dirs.n, hipMemcpyDeviceToHost, ctx->own));
+    HRA_HIP(hipStreamSynchronize(ctx->own));
     for (int32_t j = 0; j < dirs.n; ++j) {
         host_out[3 * j + 0] = h[j].x;
         host_out[3 * j + 1] = h[j].y;

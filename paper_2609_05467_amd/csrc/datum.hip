@@ -344,19 +344,18 @@ extern "C" hra_status hra_datum_frames(hra_ctx *ctx, const hra_bvh *bvh, int32_t
         k_datum_gather<<<1, 64, 0, s>>>(runs, sel, picked);
         e = hipGetLastError();
     }
-    DatumRun h[18];
-    // both copies after every launch: a copy to pageable host memory waits
-    // for the stream, which would leave the device idle while the launches
-    // behind it are enqueued
-    PartMeta P;
-    if (e == hipSuccess) e = hipMemcpyAsync(h, picked, sizeof(h), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&P, bvh->parts + part, sizeof(P), hipMemcpyDeviceToHost, s);
+    // both results through the context's pinned staging, after every launch
+    static_assert(sizeof(DatumRun) * 18 + 16 + sizeof(PartMeta) <= STAGE_BYTES - STAGE_USER, "staging too small");
+    DatumRun *h = (DatumRun *)stage_user(ctx);
+    PartMeta *hp = (PartMeta *)((char *)h + ((sizeof(DatumRun) * 18 + 15) & ~(size_t)15));
+    if (e == hipSuccess) e = hipMemcpyAsync(h, picked, sizeof(DatumRun) * 18, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hp, bvh->parts + part, sizeof(PartMeta), hipMemcpyDeviceToHost, s);
     const hipError_t ef = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = ef;
     if (e != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, "datum search launch failed", hipGetErrorString(e));
     hra_status st = check_error_word(ctx, s);   // synchronises the stream
     if (st != HRA_OK) return st;
-    const double scale = std::ldexp(1.0, -P.k_scale);
+    const double scale = std::ldexp(1.0, -hp->k_scale);
     for (int a = 0; a < 6; ++a) {
         for (int r = 0; r < 3; ++r) {
             const DatumRun &R = h[3 * a + r];

@@ -762,10 +762,14 @@ extern "C" hra_status hra_dominant_axes_noalloc(hra_ctx *ctx, const hra_samples 
 extern "C" hra_status hra_classify(hra_ctx *ctx, const hra_dirstats *stats, int64_t n, int32_t n_dirs,
                                    const hra_thresholds *th, hra_class_report *out, void *stream) {
     if (!ctx || !stats || !stats->totals || !out || n < 0 || n_dirs < 1) return HRA_ERR_INVALID_ARG;
-    hra_status st = check_error_word(ctx, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(hipSetDevice(ctx->device));
+    static_assert(sizeof(DirTotals) <= STAGE_BYTES - STAGE_USER, "totals fit the staging buffer");
+    HRA_HIP(hipMemcpyAsync(stage_user(ctx), stats->totals, sizeof(DirTotals), hipMemcpyDeviceToHost, s));
+    hra_status st = check_error_word(ctx, s);   // synchronises s
     if (st != HRA_OK) return st;
     DirTotals t;
-    HRA_HIP(hipMemcpy(&t, stats->totals, sizeof(t), hipMemcpyDeviceToHost));
+    std::memcpy(&t, stage_user(ctx), sizeof(t));
     classify_totals(t, n, n_dirs, th, out);
     return HRA_OK;
 }
@@ -785,13 +789,15 @@ extern "C" hra_status hra_min_setups_part(hra_ctx *ctx, const hra_bvh *bvh, int3
     HRA_HIP(hipMallocAsync((void **)&cc, 4 * sizeof(unsigned long long) + 64 * sizeof(uint32_t), s));
     uint32_t *hist = (uint32_t *)(cc + 4);
     const SetupJob J = make_setup_job(bvh, part, 0, samples->n, tool_length);
-    unsigned long long hcc[4];
-    uint32_t hh[64];
+    // counters and code histogram are adjacent on the device: one copy
+    unsigned long long *hcc = (unsigned long long *)stage_user(ctx);
+    const uint32_t *hh = (const uint32_t *)(hcc + 4);
     hipError_t e = launch_setups(nullptr, 1, J, samples->n, samples->point, samples->tri, d_axes_bits, d_class, cc, hist,
                                  ctx->d_err, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hcc, cc, sizeof(hcc), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hh, hist, sizeof(hh), hipMemcpyDeviceToHost, s);
-    hipFreeAsync(cc, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hcc, cc, 4 * sizeof(unsigned long long) + 64 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    const hipError_t ef = hipFreeAsync(cc, s);
+    if (e == hipSuccess) e = ef;
     if (e != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, "min_setups launch failed", hipGetErrorString(e));
     hra_status st = check_error_word(ctx, s);
     if (st != HRA_OK) return st;
