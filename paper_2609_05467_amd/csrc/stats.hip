@@ -129,7 +129,6 @@ __global__ __launch_bounds__(64 * DS_WAVES) __attribute__((amdgpu_waves_per_eu(6
             // read is clamped and both address from a uniform base
             const float4 *dp = dirs + j0;
             float4 lnext = dp[lane];
-#pragma unroll 2
             for (int32_t i = 0; i < nj; i += 64) {
                 const int32_t j = j0 + i + lane;
                 const float4 l = lnext;
