@@ -151,46 +151,44 @@ __global__ __launch_bounds__(DT_TB) void k_datum_accum(const uint64_t *keys, con
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * DT_TB + threadIdx.x) >> 6;
     const int64_t base = wave * 64 * DT_ACC_TILES;
+    // Every value that reaches a shuffle is formed by selects, never
+    // assigned under a lane-dependent branch (the compiler has mis-merged
+    // such values across divergent regions); the trip counts are uniform.
     int64_t cr = -1;   // carried run (-1: none) and its partial totals, the same in every lane
     unsigned long long cw = 0ull, chk = ~0ull;
     uint32_t cc = 0u;
     for (int it = 0; it < DT_ACC_TILES; ++it) {
         const int64_t i = base + 64 * it + lane;
-        int64_t r = -1;   // run index, -1: no run (past the end, or a face that faces no axis)
-        unsigned long long w = 0ull, hk = ~0ull;
-        uint32_t cnt = 0u;
-        if (i < n) {
-            const uint64_t k = keys[i];
-            if (k != DT_NONE) {
-                const uint32_t f = vals[i];
-                w = wf[f];
-                hk = order_key(hf[f]);
-                cnt = 1u;
-                r = (int64_t)rid[i] - 1;
-                if (flags[i]) runs[r].dir = (int32_t)(k >> 61);
-            }
-        }
+        const bool inb = i < n;
+        const int64_t ic = inb ? i : 0;   // n >= 1: element 0 is readable
+        const uint64_t k = keys[ic];
+        const bool valid = inb && k != DT_NONE;
+        const uint32_t f = vals[ic];      // a face index of the part, < n
+        const unsigned long long wv = wf[f], hv = order_key(hf[f]);
+        // run index, -1: no run (past the end, or a face that faces no axis)
+        int64_t r = valid ? (int64_t)rid[ic] - 1 : -1;
+        unsigned long long w = valid ? wv : 0ull, hk = valid ? hv : ~0ull;
+        uint32_t cnt = valid ? 1u : 0u;
+        if (valid && flags[ic]) runs[r].dir = (int32_t)(k >> 61);
         // a carried run that does not continue into this tile is complete
         const int64_t r0 = __shfl(r, 0, 64);
-        if (cr >= 0 && r0 != cr) {
-            if (lane == 0) run_flush(runs, cr, cw, cc, chk);
-            cr = -1;
-        }
+        const bool close = cr >= 0 && r0 != cr;
+        if (close && lane == 0) run_flush(runs, cr, cw, cc, chk);
+        cr = close ? -1 : cr;
         for (int off = 1; off < 64; off <<= 1) {
             const int64_t r_o = __shfl_up(r, off, 64);
             const unsigned long long w_o = __shfl_up(w, off, 64), hk_o = __shfl_up(hk, off, 64);
             const uint32_t c_o = __shfl_up(cnt, off, 64);
-            if (lane >= off && r_o == r) {
-                w += w_o;
-                cnt += c_o;
-                hk = hk_o < hk ? hk_o : hk;
-            }
+            const bool m = lane >= off && r_o == r;
+            w = m ? w + w_o : w;
+            cnt = m ? cnt + c_o : cnt;
+            hk = (m && hk_o < hk) ? hk_o : hk;
         }
-        if (r >= 0 && r == cr) {   // the tile's first run continues the carried one
-            w += cw;
-            cnt += cc;
-            hk = chk < hk ? chk : hk;
-        }
+        // the tile's first run continues the carried one
+        const bool cont = r >= 0 && r == cr;
+        w = cont ? w + cw : w;
+        cnt = cont ? cnt + cc : cnt;
+        hk = (cont && chk < hk) ? chk : hk;
         const int64_t r_next = __shfl_down(r, 1, 64);
         if (r >= 0 && lane != 63 && r_next != r) run_flush(runs, r, w, cnt, hk);
         cr = __shfl(r, 63, 64);

@@ -269,14 +269,20 @@ __global__ __launch_bounds__(PT_THREADS) void k_part_totals(const int8_t *axis, 
     const int p = blockIdx.y, t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t b0 = base ? base[p] : 0, n = base ? count[p] : n_one;
     unsigned long long a[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
-    for (int64_t i = b0 + (int64_t)blockIdx.x * PT_THREADS + t; i < b0 + n; i += (int64_t)PT_CHUNKS * PT_THREADS) {
-        const int k = axis[i];
-        a[0] += k == 0;
-        a[1] += k == 1;
-        a[2] += k == 2;
-        a[3] += k < 0;
-        a[4] += cnt[i];
-        a[5] += __double2ull_rn(conc64[i] * 4294967296.0);
+    // a block-uniform trip count, lanes past the end adding zeros (selects),
+    // so the shuffles below follow no lane-dependent loop exit
+    for (int64_t i0 = b0 + (int64_t)blockIdx.x * PT_THREADS; i0 < b0 + n; i0 += (int64_t)PT_CHUNKS * PT_THREADS) {
+        const int64_t i = i0 + t;
+        const bool ok = i < b0 + n;
+        const int64_t ic = ok ? i : i0;
+        const int k = axis[ic];
+        const unsigned long long c = cnt[ic], fx = __double2ull_rn(conc64[ic] * 4294967296.0);
+        a[0] += (ok && k == 0) ? 1ull : 0ull;
+        a[1] += (ok && k == 1) ? 1ull : 0ull;
+        a[2] += (ok && k == 2) ? 1ull : 0ull;
+        a[3] += (ok && k < 0) ? 1ull : 0ull;
+        a[4] += ok ? c : 0ull;
+        a[5] += ok ? fx : 0ull;
     }
     for (int q = 0; q < 6; ++q) {
         for (int off = 32; off > 0; off >>= 1) a[q] += __shfl_down(a[q], off, 64);
