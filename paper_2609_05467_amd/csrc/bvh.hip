@@ -349,15 +349,21 @@ __global__ void k_keys(const float *tv, const uint8_t *tpart, const uint32_t *va
 }
 
 // ---------------------------------------------------------------- radix sort
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = TB * RS_ITEMS;
+// Keys per workgroup: TB x items.  Large tiles keep the digit histogram
+// (256 counters per tile) and its scan small; small tiles give a short
+// sort enough workgroups to fill the device (204.5k keys in 4096-key tiles
+// made 50 workgroups, each running 16 rounds of barriers).
+__host__ __device__ inline int rs_items(int64_t n) {
+    return n >= ((int64_t)4 << 20) ? 16 : (n >= ((int64_t)1 << 20) ? 8 : (n >= ((int64_t)1 << 18) ? 4 : 2));
+}
 
-__global__ void k_rs_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *hist, int nblocks) {
+__global__ void k_rs_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *hist, int nblocks, int items) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int i = threadIdx.x; i < RS_TILE; i += TB) {
+    const int tile = TB * items;
+    const int64_t base = (int64_t)blockIdx.x * tile;
+    for (int i = threadIdx.x; i < tile; i += TB) {
         const int64_t idx = base + i;
         if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
     }
@@ -369,16 +375,16 @@ __global__ void k_rs_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *
 // handles 256 consecutive keys; inside a wave, peers with the same digit are
 // found with eight ballots (one per digit bit).
 __global__ void k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int64_t n,
-                             int shift, const uint32_t *offs, int nblocks) {
+                             int shift, const uint32_t *offs, int nblocks, int items) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[TB / 64][256];
     __shared__ uint32_t boff[256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     boff[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
     run[tid] = 0;
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int64_t base = (int64_t)blockIdx.x * TB * items;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int round = 0; round < RS_ITEMS; ++round) {
+    for (int round = 0; round < items; ++round) {
         const int64_t idx = base + (int64_t)round * TB + tid;
         const bool ok = idx < n;
         const uint64_t key = ok ? kin[idx] : 0ull;
@@ -414,24 +420,27 @@ __global__ void k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t 
 }
 
 static int64_t radix_ws_elems(int64_t n) {
-    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    const int64_t tile = (int64_t)TB * rs_items(n);
+    const int64_t nb = (n + tile - 1) / tile;
     return 256 * nb + scan_ws_elems(256 * nb);
 }
 
 // `ws` holds radix_ws_elems(n) uint32 elements.
 static hipError_t radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws,
                              hipStream_t s, bool *result_in_k1) {
-    const int nb = (int)((n + RS_TILE - 1) / RS_TILE);
+    const int items = rs_items(n);
+    const int64_t tile = (int64_t)TB * items;
+    const int nb = (int)((n + tile - 1) / tile);
     uint32_t *hist = ws, *sws = ws + 256 * (int64_t)nb;
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     hipError_t e = hipSuccess;
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
-        k_rs_hist<<<nb, TB, 0, s>>>(ka, n, shift, hist, nb);
+        k_rs_hist<<<nb, TB, 0, s>>>(ka, n, shift, hist, nb, items);
         e = scan<uint32_t>(hist, hist, (int64_t)256 * nb, false, sws, s);
         if (e != hipSuccess) break;
-        k_rs_scatter<<<nb, TB, 0, s>>>(ka, va, kb, vb, n, shift, hist, nb);
+        k_rs_scatter<<<nb, TB, 0, s>>>(ka, va, kb, vb, n, shift, hist, nb, items);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
