@@ -375,12 +375,24 @@ __global__ void k_rs_hist(const uint64_t *keys, int64_t n, int shift, uint32_t *
 // handles 256 consecutive keys; inside a wave, peers with the same digit are
 // found with eight ballots (one per digit bit).
 __global__ void k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int64_t n,
-                             int shift, const uint32_t *offs, int nblocks, int items) {
+                             int shift, const uint32_t *offs, int nblocks, int items, const uint32_t *totals) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[TB / 64][256];
     __shared__ uint32_t boff[256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    boff[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    // this block's first position per digit: the keys of lower digits (an
+    // exclusive scan of the digit totals) plus this digit's keys in earlier
+    // blocks (k_rs_digit_scan)
+    run[tid] = totals[tid];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = tid >= off ? run[tid - off] : 0u;
+        __syncthreads();
+        run[tid] += v;
+        __syncthreads();
+    }
+    boff[tid] = (tid > 0 ? run[tid - 1] : 0u) + offs[(int64_t)tid * nblocks + blockIdx.x];
+    __syncthreads();
     run[tid] = 0;
     const int64_t base = (int64_t)blockIdx.x * TB * items;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -419,28 +431,58 @@ __global__ void k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t 
     }
 }
 
+// Exclusive prefix over the blocks of each digit's counts, in place
+// (digit-major layout hist[d * nb + b]); one workgroup per digit, which also
+// writes the digit's total.
+__global__ __launch_bounds__(TB) void k_rs_digit_scan(uint32_t *hist, int nb, uint32_t *totals) {
+    __shared__ uint32_t part[TB];
+    uint32_t *h = hist + (int64_t)blockIdx.x * nb;
+    const int t = threadIdx.x;
+    const int per = (nb + TB - 1) / TB;
+    const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += h[b];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < TB; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t acc = t > 0 ? part[t - 1] : 0u;
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t c = h[b];
+        h[b] = acc;
+        acc += c;
+    }
+    if (t == TB - 1) totals[blockIdx.x] = part[TB - 1];
+}
+
+static_assert(TB == 256, "one thread per digit in the radix sort");
+
 static int64_t radix_ws_elems(int64_t n) {
     const int64_t tile = (int64_t)TB * rs_items(n);
     const int64_t nb = (n + tile - 1) / tile;
-    return 256 * nb + scan_ws_elems(256 * nb);
+    return 256 * nb + 256;
 }
 
-// `ws` holds radix_ws_elems(n) uint32 elements.
+// `ws` holds radix_ws_elems(n) uint32 elements.  The keys are ordered by
+// their low 8 x passes bits (three launches per pass).
 static hipError_t radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws,
-                             hipStream_t s, bool *result_in_k1) {
+                             hipStream_t s, bool *result_in_k1, int passes = 8) {
     const int items = rs_items(n);
     const int64_t tile = (int64_t)TB * items;
     const int nb = (int)((n + tile - 1) / tile);
-    uint32_t *hist = ws, *sws = ws + 256 * (int64_t)nb;
+    uint32_t *hist = ws, *totals = ws + 256 * (int64_t)nb;
     uint64_t *ka = k0, *kb = k1;
     uint32_t *va = v0, *vb = v1;
     hipError_t e = hipSuccess;
-    for (int pass = 0; pass < 8; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
         k_rs_hist<<<nb, TB, 0, s>>>(ka, n, shift, hist, nb, items);
-        e = scan<uint32_t>(hist, hist, (int64_t)256 * nb, false, sws, s);
-        if (e != hipSuccess) break;
-        k_rs_scatter<<<nb, TB, 0, s>>>(ka, va, kb, vb, n, shift, hist, nb, items);
+        k_rs_digit_scan<<<256, TB, 0, s>>>(hist, nb, totals);
+        k_rs_scatter<<<nb, TB, 0, s>>>(ka, va, kb, vb, n, shift, hist, nb, items, totals);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
@@ -908,7 +950,9 @@ hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s,
     k_ranks<<<gT, TB, 0, s>>>(W.valid, W.excl, W.tpart, T, b->parts, b->valid_rank);
     k_keys<<<gT, TB, 0, s>>>(W.tv, W.tpart, W.valid, T, b->parts, W.keys0, W.vals0);
     bool in1 = false;
-    e = radix_sort(W.keys0, W.vals0, W.keys1, W.vals1, T, W.rs_ws, s, &in1);
+    // keys are (part << 56) | a 54-bit Morton code, ~0 for a zero-area face:
+    // with one part every key that matters differs in its low 56 bits
+    e = radix_sort(W.keys0, W.vals0, W.keys1, W.vals1, T, W.rs_ws, s, &in1, n_parts == 1 ? 7 : 8);
     if (e != hipSuccess) return e;
     uint64_t *ks = in1 ? W.keys1 : W.keys0;
     uint32_t *vs = in1 ? W.vals1 : W.vals0;
