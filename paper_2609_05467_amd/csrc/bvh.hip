@@ -39,15 +39,6 @@ namespace hra {
 
 constexpr int TB = 256;
 
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // ---------------------------------------------------------------- scans
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = TB * SCAN_ITEMS;
@@ -193,16 +184,6 @@ __device__ inline float fkey_inv(uint32_t k) {
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-__global__ void k_acc_init(PartAcc *acc, int n_parts) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_parts) return;
-    for (int c = 0; c < 3; ++c) {
-        acc[p].lo[c] = 0xffffffffu;
-        acc[p].hi[c] = 0u;
-    }
-    acc[p].amax = 0ull;
-}
-
 __global__ void k_part_facts(const MeshIn *mesh, const double *area, PartAcc *acc) {
     __shared__ uint32_t slo[3], shi[3];
     __shared__ unsigned long long samax;
@@ -300,14 +281,6 @@ __global__ void k_part_counts(const uint64_t *prefix, const uint32_t *excl, cons
     *n_valid_total = leaf;
 }
 
-__global__ void k_ranks(const uint32_t *valid, const uint32_t *excl, const uint8_t *tpart, int64_t T,
-                        const PartMeta *meta, int32_t *rank) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= T) return;
-    const PartMeta &P = meta[tpart[g]];
-    rank[g] = valid[g] ? (int32_t)(excl[g] - excl[P.tri_start]) : -1;
-}
-
 // ---------------------------------------------------------------- keys
 __device__ inline uint64_t spread18(uint32_t x) {
     uint64_t v = x & 0x3FFFFu;
@@ -327,10 +300,13 @@ __device__ inline uint32_t quant18(float c, float lo, float hi) {
     return q > 262143u ? 262143u : q;
 }
 
-__global__ void k_keys(const float *tv, const uint8_t *tpart, const uint32_t *valid, int64_t T, const PartMeta *meta,
-                       uint64_t *keys, uint32_t *vals) {
+// Per triangle: its rank among its part's nonzero-area faces (-1 for a
+// zero-area one) and its sort key and index.
+__global__ void k_ranks_keys(const uint32_t *valid, const uint32_t *excl, const float *tv, const uint8_t *tpart,
+                             int64_t T, const PartMeta *meta, int32_t *rank, uint64_t *keys, uint32_t *vals) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= T) return;
+    rank[g] = valid[g] ? (int32_t)(excl[g] - excl[meta[tpart[g]].tri_start]) : -1;
     vals[g] = (uint32_t)g;
     if (!valid[g]) {
         keys[g] = ~0ull;
@@ -698,16 +674,31 @@ __global__ void k_refit(const float4 *tri4, const uint64_t *keys, const int32_t 
 // reaches an unwritten slot steps to that index, which the traversal's
 // bounds guard reports as an error instead of reading out of bounds.
 constexpr int32_t SENTINEL_CHILD = 0x7fffffff;
-__global__ void k_fill_sentinel_nodes(Node *nodes, int64_t n) {
+// Every fill a build starts with, in one launch: leaf positions -1,
+// sentinel nodes, cleared refit counters, parent indices -1 and the per-part
+// accumulators of k_part_facts.
+__global__ void k_build_init(int32_t *leaf_pos, int64_t T, Node *nodes, uint32_t *flags, int32_t *PI, int64_t nn,
+                             PartAcc *acc, int n_parts) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float inf = INFINITY;
-    Node nd;
-    nd.a = make_float4(-inf, -inf, -inf, inf);
-    nd.b = make_float4(inf, inf, -inf, -inf);
-    nd.c = make_float4(-inf, inf, inf, inf);
-    nd.d = make_int4(SENTINEL_CHILD, SENTINEL_CHILD, 0, 0);
-    nodes[i] = nd;
+    if (i < T) leaf_pos[i] = -1;
+    if (i < nn) {
+        const float inf = INFINITY;
+        Node nd;
+        nd.a = make_float4(-inf, -inf, -inf, inf);
+        nd.b = make_float4(inf, inf, -inf, -inf);
+        nd.c = make_float4(-inf, inf, inf, inf);
+        nd.d = make_int4(SENTINEL_CHILD, SENTINEL_CHILD, 0, 0);
+        nodes[i] = nd;
+        flags[i] = 0u;
+        PI[i] = -1;
+    }
+    if (i < n_parts) {
+        for (int c = 0; c < 3; ++c) {
+            acc[i].lo[c] = 0xffffffffu;
+            acc[i].hi[c] = 0u;
+        }
+        acc[i].amax = 0ull;
+    }
 }
 
 // Roots of parts too small for an interior node of their own: one leaf.
@@ -934,12 +925,9 @@ hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s,
     BuildWs W;
     carve((char *)ws_base, T, n_parts, &W);
     const int gT = blocks_for(T, TB), gN = blocks_for(nn, TB);
-    k_fill_i32<<<gT, TB, 0, s>>>(b->leaf_pos, T, -1);
-    k_fill_sentinel_nodes<<<gN, TB, 0, s>>>(b->nodes, nn);
-    k_fill_u32<<<gN, TB, 0, s>>>(W.flags, nn, 0u);
-    k_fill_i32<<<gN, TB, 0, s>>>(W.PI, nn, -1);
+    k_build_init<<<blocks_for(std::max<int64_t>(std::max<int64_t>(T, nn), n_parts), TB), TB, 0, s>>>(
+        b->leaf_pos, T, b->nodes, W.flags, W.PI, nn, W.acc, n_parts);
     k_tri_prep<<<gT, TB, 0, s>>>(W.mesh, n_parts, T, W.area, W.valid, W.tv, W.tpart, err);
-    k_acc_init<<<blocks_for(n_parts, 64), 64, 0, s>>>(W.acc, n_parts);
     k_part_facts<<<dim3(FACT_BLOCKS, n_parts), 256, 0, s>>>(W.mesh, W.area, W.acc);
     k_part_finalize<<<blocks_for(n_parts, 64), 64, 0, s>>>(W.mesh, W.acc, n_parts, b->parts);
     k_weights<<<gT, TB, 0, s>>>(W.area, W.tpart, T, b->parts, W.w);
@@ -947,8 +935,7 @@ hipError_t enqueue_build(hra_ctx *ctx, hra_bvh *b, void *ws_base, hipStream_t s,
     if (e == hipSuccess) e = scan<uint32_t>(W.valid, W.excl, T, false, W.scan32_ws, s);
     if (e != hipSuccess) return e;
     k_part_counts<<<1, 64, 0, s>>>(b->prefix, W.excl, W.valid, n_parts, T, b->parts, W.nvt, err);
-    k_ranks<<<gT, TB, 0, s>>>(W.valid, W.excl, W.tpart, T, b->parts, b->valid_rank);
-    k_keys<<<gT, TB, 0, s>>>(W.tv, W.tpart, W.valid, T, b->parts, W.keys0, W.vals0);
+    k_ranks_keys<<<gT, TB, 0, s>>>(W.valid, W.excl, W.tv, W.tpart, T, b->parts, b->valid_rank, W.keys0, W.vals0);
     bool in1 = false;
     // keys are (part << 56) | a 54-bit Morton code, ~0 for a zero-area face:
     // with one part every key that matters differs in its low 56 bits
