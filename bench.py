@@ -461,6 +461,8 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     # its statistics (default priority, as every stream here)
     side = torch.cuda.Stream()
 
+    pending = []   # each timed step's events, read after the timed loop
+
     def step(record):
         main = torch.cuda.current_stream()
         e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -477,17 +479,16 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         ctx.cast(bvh, samples, N, counts=False, bits=bits)
         e[3].record()
         ds = ctx.dominant_axes(samples, N, bits)
-        rep = ctx.classify(ds, S, N)
-        e[4].record()
+        # the setups return a host report: the host waits for the side
+        # stream here, while the cast and the statistics queued on the main
+        # one run, then for the main stream in classify
         su = ctx.min_setups(bvh, samples, bits6, args.tool_length, want_class=False, stream=side)
         f[2].record(side)
+        rep = ctx.classify(ds, S, N)
+        e[4].record()
         main.wait_stream(side)
         if record:
-            torch.cuda.synchronize()
-            for k, (a, b) in zip(("build", "sample", "cast", "stats"), zip(e[:-1], e[1:])):
-                ev[k].append(a.elapsed_time(b))
-            ev["axes"].append(f[0].elapsed_time(f[1]))
-            ev["setups"].append(f[1].elapsed_time(f[2]))
+            pending.append((e, f))
         bvh.release()
         return rep, su
 
@@ -507,6 +508,11 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         rep, su = step(True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    for e, f in pending:
+        for k, (a, b) in zip(("build", "sample", "cast", "stats"), zip(e[:-1], e[1:])):
+            ev[k].append(a.elapsed_time(b))
+        ev["axes"].append(f[0].elapsed_time(f[1]))
+        ev["setups"].append(f[1].elapsed_time(f[2]))
     ms = dt / args.steps * 1e3
     rays = S * N
     value = rays * args.steps / dt
