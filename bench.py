@@ -462,35 +462,51 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     side = torch.cuda.Stream()
 
     pending = []   # each timed step's events, read after the timed loop
+    cls_stream = torch.cuda.Stream()
 
-    def step(record):
+    def build():
+        b = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        b[0].record()
+        bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
+        b[1].record()
+        return bvh, b
+
+    def step(record, cur, prefetch):
+        """One analysis step on the hierarchy `cur` (its build already
+        enqueued on the main stream).  With prefetch, the next step's build
+        is enqueued on the main stream behind this step's statistics, before
+        the host waits for them, so the device is not idle while the host
+        finishes this step; every step still builds its own hierarchy."""
+        bvh, b = cur
         main = torch.cuda.current_stream()
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         f = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record()
-        bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
-        e[1].record()
         ctx.sample_surface(bvh, S, 2, out=samples)
-        e[2].record()
+        e[1].record()
         side.wait_stream(main)
         f[0].record(side)
         ctx.cast(bvh, samples, 6, kind=hra.DIRS_AXES6, counts=False, bits=bits6, stream=side)
         f[1].record(side)
         ctx.cast(bvh, samples, N, counts=False, bits=bits)
-        e[3].record()
+        e[2].record()
         ds = ctx.dominant_axes(samples, N, bits)
+        e[3].record()
         # the setups return a host report: the host waits for the side
         # stream here, while the cast and the statistics queued on the main
         # one run, then for the main stream in classify
         su = ctx.min_setups(bvh, samples, bits6, args.tool_length, want_class=False, stream=side)
         f[2].record(side)
-        rep = ctx.classify(ds, S, N)
-        e[4].record()
+        # the class is read on a stream that waits for the statistics only,
+        # so the host does not also wait for the build queued behind them
+        cls_stream.wait_event(e[3])
+        nxt = build() if prefetch else None
+        rep = ctx.classify(ds, S, N, stream=cls_stream)
         main.wait_stream(side)
         if record:
-            pending.append((e, f))
+            pending.append((b, e, f))
         bvh.release()
-        return rep, su
+        return rep, su, nxt
 
     if args.copy_calibration_mib:
         src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
@@ -499,18 +515,21 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         torch.cuda.synchronize()
         del src, dst
     log(f"[bench] {workload}: {mesh.n_tris} triangles, {S} samples x {N} directions; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step(False)
+    for w in range(args.warmup):
+        step(False, build(), False)
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
+    # exactly K builds and K steps inside the timed region
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rep, su = step(True)
+    cur = build()
+    for k in range(args.steps):
+        rep, su, cur = step(True, cur, k + 1 < args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    for e, f in pending:
-        for k, (a, b) in zip(("build", "sample", "cast", "stats"), zip(e[:-1], e[1:])):
-            ev[k].append(a.elapsed_time(b))
+    for b, e, f in pending:
+        ev["build"].append(b[0].elapsed_time(b[1]))
+        for k, (x, y) in zip(("sample", "cast", "stats"), zip(e[:-1], e[1:])):
+            ev[k].append(x.elapsed_time(y))
         ev["axes"].append(f[0].elapsed_time(f[1]))
         ev["setups"].append(f[1].elapsed_time(f[2]))
     ms = dt / args.steps * 1e3
@@ -566,7 +585,9 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         "stage_ms": {k: round(float(np.mean(ev[k])), 3) for k in ("build", "sample", "cast", "stats")},
         # ... and the side stream's intervals, which share the GPU with the cast running beside them
         "side_stream_elapsed_ms": {k: round(float(np.mean(ev[k])), 3) for k in ("axes", "setups")},
-        "stage_streams": {"main": ["build", "sample", "cast", "stats"], "side, after sample": ["axes", "setups"]},
+        "stage_streams": {"main": ["build", "sample", "cast", "stats"], "side, after sample": ["axes", "setups"],
+                          "pipelining": "each step's build is enqueued behind the previous step's statistics, "
+                                        "before the host waits for them"},
         # each secondary stage timed alone on an idle GPU, outside the steps
         "secondary_alone_ms": {k: round(v, 4) for k, v in alone.items()},
         "cast_rays_per_s": rays / (cast_ms * 1e-3),
