@@ -453,6 +453,10 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     bits = torch.empty((S, W), dtype=torch.int32, device=dev)
     bits6 = torch.empty((S, 1), dtype=torch.int32, device=dev)
     samples = ctx.alloc_samples(S)
+    # the sampler also writes a spatial order of the samples, which the
+    # hemisphere cast follows (nearby samples at the same time share the
+    # hierarchy's nodes in L2; the results do not depend on it)
+    samples["order"] = torch.empty((S,), dtype=torch.int32, device=dev)
 
     ev = {k: [] for k in ("build", "sample", "cast", "stats", "axes", "setups")}
 

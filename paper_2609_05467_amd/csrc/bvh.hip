@@ -482,8 +482,8 @@ __global__ void k_gather(const float *tv, const uint32_t *sorted_vals, const uin
 // The sort and the scan for other translation units (declared in prims.hpp).
 int64_t sort_pairs_ws_elems(int64_t n) { return radix_ws_elems(n); }
 hipError_t sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws, hipStream_t s,
-                      bool *result_in_k1) {
-    return radix_sort(k0, v0, k1, v1, n, ws, s, result_in_k1);
+                      bool *result_in_k1, int passes) {
+    return radix_sort(k0, v0, k1, v1, n, ws, s, result_in_k1, passes);
 }
 int64_t scan_u32_ws_elems(int64_t n) { return scan_ws_elems(n); }
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, bool inclusive, uint32_t *ws, hipStream_t s) {

@@ -20,6 +20,7 @@
 // signs are antisymmetric, and so is the FP64 value), so no ray slips
 // between them.
 #include "common.hpp"
+#include "prims.hpp"
 
 namespace hra {
 
@@ -421,8 +422,14 @@ template <int RPW, int STACK, bool STATS, bool STEP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STEP ? 8 : 7))) void k_cast_rows(CastArgs a) {
     extern __shared__ int dyn_lds[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t item = blockIdx.x;
-    if (item >= a.n_items) return;  // the whole workgroup leaves together
+    if ((int64_t)blockIdx.x >= a.n_items) return;  // the whole workgroup leaves together
+    // workgroups running at the same time take nearby samples when an order
+    // is given, and so share the hierarchy's nodes in L2
+    const int64_t item = a.order ? (int64_t)uni_i(a.order[blockIdx.x]) : (int64_t)blockIdx.x;
+    if ((uint64_t)item >= (uint64_t)a.n_items) {   // not a permutation of the items: an error, no access
+        if (threadIdx.x == 0) atomicOr(a.err, ERR_BAD_ORDER);
+        return;
+    }
     lds_int *lds = (lds_int *)(dyn_lds + wv * (STACK * 64));
     uint32_t *row = (uint32_t *)(dyn_lds + 4 * STACK * 64);
     const CastJob J = uni_job(job_of(a, item));
@@ -1118,6 +1125,11 @@ CastJob hra::make_cast_job(const hra_bvh *bvh, int32_t part, const float *origin
     return J;
 }
 
+// The one-sample hemisphere cast (k_cast_rows) takes its samples in a
+// spatial order: the one the sampler wrote, or one formed here for at least
+// this many samples.
+constexpr int64_t ORDER_MIN_SAMPLES = 4096;
+
 static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, const hra_samples *samples, hra_dirs dirs,
                               uint32_t *d_bits, uint32_t *d_counts, unsigned long long *work, int rpw, hipStream_t s) {
     if (!ctx || !bvh || !samples) return HRA_ERR_INVALID_ARG;
@@ -1144,7 +1156,29 @@ static hra_status cast_common(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, co
     a.err = ctx->d_err;
     a.work = work;
     if (a.n_items >= ((int64_t)1 << 31)) return ctx->fail(HRA_ERR_INVALID_ARG, "too many samples for one call");
-    HRA_HIP(launch_cast_any(a, rpw, ctx->cast_stack, ctx->cast_traversal, work != nullptr, s));
+    void *ows = nullptr;
+    const int64_t n = samples->n;
+    if (a.kind == 0 && a.group == 1 && ctx->cast_traversal != HRA_TRAVERSAL_REFILL) {
+        if (samples->order) {
+            a.order = samples->order;
+        } else if (n >= ORDER_MIN_SAMPLES) {
+            const size_t ob = (sizeof(int32_t) * (size_t)n + 255) & ~(size_t)255;
+            HRA_HIP(hipMallocAsync(&ows, ob + sample_order_ws_bytes(n), s));
+            const hipError_t e = sample_order(samples->origin, n, bvh->parts + part, (int32_t *)ows, (char *)ows + ob, s);
+            if (e != hipSuccess) {
+                const hipError_t ef = hipFreeAsync(ows, s);
+                (void)ef;
+                return ctx->fail(HRA_ERR_DEVICE, "sample order", hipGetErrorString(e));
+            }
+            a.order = (const int32_t *)ows;
+        }
+    }
+    const hipError_t el = launch_cast_any(a, rpw, ctx->cast_stack, ctx->cast_traversal, work != nullptr, s);
+    if (ows) {
+        const hipError_t ef = hipFreeAsync(ows, s);
+        if (el == hipSuccess && ef != hipSuccess) return ctx->fail(HRA_ERR_DEVICE, "hipFreeAsync", hipGetErrorString(ef));
+    }
+    HRA_HIP(el);
     if (d_counts) {
         k_popcount_rows<<<blocks_for(samples->n, 256), 256, 0, s>>>(d_bits, samples->n, a.W, d_counts);
         HRA_HIP(hipGetLastError());

@@ -25,7 +25,8 @@ enum : uint32_t {
     ERR_EMPTY_MESH = 1u << 1,    // no triangle with nonzero area
     ERR_STACK = 1u << 2,         // traversal stack exhausted
     ERR_BAD_SAMPLE_TRI = 1u << 3, // a sample names a face that is not in the mesh
-    ERR_TOOL_RADIUS = 1u << 4     // a tool radius below twice the clearance tolerance
+    ERR_TOOL_RADIUS = 1u << 4,    // a tool radius below twice the clearance tolerance
+    ERR_BAD_ORDER = 1u << 5       // a sample order names an index outside [0, n)
 };
 
 #define HRA_HIP(call)                                                                      \
@@ -201,6 +202,9 @@ struct CastArgs {
     int32_t group;             // hemisphere cast: samples per work item (cast_group)
     uint32_t *err;
     unsigned long long *work;  // instrumented variant: {node fetches, triangle tests}
+    // one-sample hemisphere cast of one job: the work item of each workgroup
+    // (the samples in a spatial order), or null: the workgroup's own index
+    const int32_t *order = nullptr;
 };
 
 SampleJob make_sample_job(const hra_bvh *bvh, int32_t part, int32_t mode, uint64_t seed, float frac, int64_t n_out,

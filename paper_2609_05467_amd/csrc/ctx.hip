@@ -155,6 +155,7 @@ hra_status check_error_word(hra_ctx *ctx, hipStream_t s) {
     if (w & ERR_TOOL_RADIUS)
         return ctx->fail(HRA_ERR_INVALID_ARG, "tool radius below 2e-4 x the part's bounding-box diagonal");
     if (w & ERR_STACK) return ctx->fail(HRA_ERR_DEVICE, "traversal stack exhausted");
+    if (w & ERR_BAD_ORDER) return ctx->fail(HRA_ERR_INVALID_ARG, "a sample order names an index outside [0, n)");
     return ctx->fail(HRA_ERR_DEVICE, "device error word set");
 }
 
@@ -180,6 +181,17 @@ hra_status hra_ctx_create(int32_t device, hra_ctx **out) {
         return HRA_ERR_DEVICE;
     }
     ctx->n_cu = prop.multiProcessorCount;
+    // stream-ordered allocations (workspaces, hierarchies) keep their memory
+    // in the device's pool between calls instead of returning it to the
+    // driver at each synchronisation, where the next call would map it again
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+            delete ctx;
+            return HRA_ERR_DEVICE;
+        }
+    }
     if (noalloc_setup(device) != hipSuccess || stats_setup(device) != hipSuccess) {
         delete ctx;
         return HRA_ERR_DEVICE;

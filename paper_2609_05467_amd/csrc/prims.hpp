@@ -10,8 +10,14 @@
 
 namespace hra {
 int64_t sort_pairs_ws_elems(int64_t n);
+// passes: the keys are ordered by their low 8 x passes bits.
 hipError_t sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws, hipStream_t s,
-                      bool *result_in_k1);
+                      bool *result_in_k1, int passes = 8);
 int64_t scan_u32_ws_elems(int64_t n);
+// A spatial order of n samples: their indices sorted stably by a 15-bit
+// Morton code of the origin in the part's box (5 bits per axis), written to
+// order[n].  `ws` holds sample_order_ws_bytes(n) bytes.
+size_t sample_order_ws_bytes(int64_t n);
+hipError_t sample_order(const float *origin, int64_t n, const PartMeta *meta, int32_t *order, void *ws, hipStream_t s);
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, int64_t n, bool inclusive, uint32_t *ws, hipStream_t s);
 }  // namespace hra

@@ -5,6 +5,7 @@
 // One launch serves any number of sampling jobs (a part of a hierarchy, a
 // mode, a seed, an output range), so a batch of parts is sampled at once.
 #include "common.hpp"
+#include "prims.hpp"
 
 namespace hra {
 
@@ -147,6 +148,42 @@ hipError_t launch_sample(const SampleJob *d_jobs, int32_t n_jobs, const SampleJo
 
 using namespace hra;
 
+namespace hra {
+// The order changes only which samples a cast runs at the same time (nearby
+// ones share the hierarchy's nodes in L2); each sample's result is the same
+// in any order.
+__global__ void k_order_keys(const float *origin, int64_t n, const PartMeta *meta, uint64_t *keys, uint32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const PartMeta &P = *meta;
+    uint32_t code = 0;
+    for (int k = 0; k < 3; ++k) {
+        const float lo = P.bbox[k], ext = P.bbox[3 + k] - lo;
+        const float t = ext > 0.0f ? (origin[3 * i + k] - lo) / ext : 0.0f;
+        const uint32_t q = (uint32_t)fminf(fmaxf(t * 32.0f, 0.0f), 31.0f);   // NaN -> 0
+        for (int b = 0; b < 5; ++b) code |= ((q >> b) & 1u) << (3 * b + (2 - k));
+    }
+    keys[i] = code;
+    vals[i] = (uint32_t)i;
+}
+
+size_t sample_order_ws_bytes(int64_t n) { return (size_t)n * 20 + (size_t)sort_pairs_ws_elems(n) * 4 + 64; }
+
+hipError_t sample_order(const float *origin, int64_t n, const PartMeta *meta, int32_t *order, void *ws, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    uint64_t *k0 = (uint64_t *)ws, *k1 = k0 + n;
+    uint32_t *v1 = (uint32_t *)(k1 + n), *sw = v1 + n;
+    uint32_t *v0 = (uint32_t *)order;
+    k_order_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(origin, n, meta, k0, v0);
+    hipError_t e = hipGetLastError();
+    bool in1 = false;
+    // two passes over the 15-bit keys: the result lands back in v0 (the order)
+    if (e == hipSuccess) e = sort_pairs(k0, v0, k1, v1, n, sw, s, &in1, 2);
+    if (e == hipSuccess && in1) e = hipErrorUnknown;
+    return e;
+}
+}  // namespace hra
+
 extern "C" hra_status hra_sample_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, int32_t mode, uint64_t seed,
                                       float offset_frac, const hra_samples *out, void *stream) {
     if (!ctx || !bvh || !out) return HRA_ERR_INVALID_ARG;
@@ -161,8 +198,16 @@ extern "C" hra_status hra_sample_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t 
         return ctx->fail(HRA_ERR_INVALID_ARG, "sample arrays must be non-null");
     HRA_HIP(hipSetDevice(ctx->device));
     const SampleJob J = make_sample_job(bvh, part, mode, seed, offset_frac, out->n, 0, 0);
-    HRA_HIP(launch_sample(nullptr, 1, J, J.n_threads, out->point, out->normal, out->origin, out->tri,
-                          (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    HRA_HIP(launch_sample(nullptr, 1, J, J.n_threads, out->point, out->normal, out->origin, out->tri, s));
+    if (out->order) {
+        void *ws = nullptr;
+        HRA_HIP(hipMallocAsync(&ws, sample_order_ws_bytes(out->n), s));
+        const hipError_t e = sample_order(out->origin, out->n, bvh->parts + part, out->order, ws, s);
+        const hipError_t ef = hipFreeAsync(ws, s);
+        if (e != hipSuccess || ef != hipSuccess)
+            return ctx->fail(HRA_ERR_DEVICE, "sample order", hipGetErrorString(e != hipSuccess ? e : ef));
+    }
     return HRA_OK;
 }
 

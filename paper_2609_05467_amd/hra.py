@@ -42,7 +42,7 @@ class BvhInfo(C.Structure):
 
 class Samples(C.Structure):
     _fields_ = [("point", C.c_void_p), ("normal", C.c_void_p), ("origin", C.c_void_p), ("tri", C.c_void_p),
-                ("n", C.c_int64)]
+                ("n", C.c_int64), ("order", C.c_void_p)]
 
 
 class Dirs(C.Structure):
@@ -387,7 +387,11 @@ class Context:
         for k in ("point", "normal", "origin"):
             if k in s and s[k] is not None:
                 assert s[k].is_contiguous() and s[k].dtype == torch.float32 and s[k].shape == (n, 3), k
-        return Samples(_ptr(s.get("point")), _ptr(s.get("normal")), _ptr(s.get("origin")), _ptr(s.get("tri")), n)
+        order = s.get("order")
+        if order is not None:
+            assert order.is_contiguous() and order.dtype == torch.int32 and order.shape == (n,), "order"
+        return Samples(_ptr(s.get("point")), _ptr(s.get("normal")), _ptr(s.get("origin")), _ptr(s.get("tri")), n,
+                       _ptr(order))
 
     def sample_surface(self, bvh, n, seed, mode=SAMPLE_AREA, offset_frac=1e-4, stream=None, out=None, part=0):
         if mode == SAMPLE_CENTROID:
