@@ -8,6 +8,7 @@
 // nothing and enqueues kernels plus three small copies into pinned memory.
 // That sequence can be captured once in a HIP graph and replayed.
 #include "stages.hpp"
+#include "prims.hpp"
 
 #include <cstring>
 #include <vector>
@@ -43,6 +44,11 @@ size_t carve_stage(char *base, int64_t S, int32_t W, int32_t n_jobs, StageBufs *
     take((void **)&b.dcj, sizeof(CastJob) * n_jobs);
     take((void **)&b.daj, sizeof(CastJob) * n_jobs);
     take((void **)&b.dsetj, setup_job_size() * n_jobs);
+    take((void **)&b.okey0, sizeof(uint64_t) * S);
+    take((void **)&b.okey1, sizeof(uint64_t) * S);
+    take((void **)&b.oval0, sizeof(uint32_t) * S);
+    take((void **)&b.oval1, sizeof(uint32_t) * S);
+    take((void **)&b.osort, sizeof(uint32_t) * (size_t)sort_pairs_ws_elems(S));
     if (out) *out = b;
     return (off + 255) & ~(size_t)255;
 }
@@ -143,6 +149,11 @@ hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B
     if (forked && e == hipSuccess) e = hipEventRecord(fork, s);
     if (forked && e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
     const hipStream_t sa = forked ? side : s;   // the six-axis cast and the setups
+    // the one-sample hemisphere cast takes the samples in a spatial order
+    const int32_t *order = nullptr;
+    if (e == hipSuccess && sh.group == 1 && sh.trav != HRA_TRAVERSAL_REFILL)
+        e = sample_order_jobs(sh.n_jobs > 1 ? B.dcj : nullptr, sh.n_jobs, sh.cj0, sh.S, B.okey0, B.oval0, B.okey1,
+                              B.oval1, B.osort, s, &order);
     if (e == hipSuccess) {
         CastArgs a;
         a.jobs = B.dcj;
@@ -157,6 +168,7 @@ hipError_t enqueue_stages(hra_ctx *ctx, const StageShape &sh, const StageBufs &B
         a.group = sh.group;
         a.err = err;
         a.work = nullptr;
+        a.order = order;
         e = launch_cast_any(a, sh.rpw, sh.stack, sh.trav, false, s);
     }
     if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);

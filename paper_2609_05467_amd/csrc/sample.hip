@@ -152,19 +152,58 @@ namespace hra {
 // The order changes only which samples a cast runs at the same time (nearby
 // ones share the hierarchy's nodes in L2); each sample's result is the same
 // in any order.
-__global__ void k_order_keys(const float *origin, int64_t n, const PartMeta *meta, uint64_t *keys, uint32_t *vals) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const PartMeta &P = *meta;
+// 15-bit Morton code of a point in the part's box (5 bits per axis)
+__device__ inline uint32_t morton15(const float *p, const PartMeta &P) {
     uint32_t code = 0;
     for (int k = 0; k < 3; ++k) {
         const float lo = P.bbox[k], ext = P.bbox[3 + k] - lo;
-        const float t = ext > 0.0f ? (origin[3 * i + k] - lo) / ext : 0.0f;
+        const float t = ext > 0.0f ? (p[k] - lo) / ext : 0.0f;
         const uint32_t q = (uint32_t)fminf(fmaxf(t * 32.0f, 0.0f), 31.0f);   // NaN -> 0
         for (int b = 0; b < 5; ++b) code |= ((q >> b) & 1u) << (3 * b + (2 - k));
     }
-    keys[i] = code;
+    return code;
+}
+
+__global__ void k_order_keys(const float *origin, int64_t n, const PartMeta *meta, uint64_t *keys, uint32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = morton15(origin + 3 * i, *meta);
     vals[i] = (uint32_t)i;
+}
+
+__global__ void k_order_keys_jobs(const CastJob *jobs, int32_t n_jobs, CastJob job0, int64_t n, uint64_t *keys,
+                                  uint32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int j = 0;
+    if (jobs) {   // the last job whose first item is at most i
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].item_base <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        j = lo;
+    }
+    const CastJob &J = jobs ? jobs[j] : job0;
+    keys[i] = ((uint64_t)j << 15) | morton15(J.origin + 3 * (i - J.item_base), *J.meta);
+    vals[i] = (uint32_t)i;
+}
+
+hipError_t sample_order_jobs(const CastJob *d_jobs, int32_t n_jobs, const CastJob &job0, int64_t n, uint64_t *k0,
+                             uint32_t *v0, uint64_t *k1, uint32_t *v1, uint32_t *ws, hipStream_t s,
+                             const int32_t **order) {
+    *order = nullptr;
+    if (n <= 0) return hipSuccess;
+    int jb = 0;
+    while (jb < 31 && ((int64_t)1 << jb) < n_jobs) ++jb;
+    const int passes = (15 + jb + 7) / 8;
+    k_order_keys_jobs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d_jobs, n_jobs, job0, n, k0, v0);
+    hipError_t e = hipGetLastError();
+    bool in1 = false;
+    if (e == hipSuccess) e = sort_pairs(k0, v0, k1, v1, n, ws, s, &in1, passes);
+    if (e == hipSuccess) *order = (const int32_t *)(in1 ? v1 : v0);
+    return e;
 }
 
 size_t sample_order_ws_bytes(int64_t n) { return (size_t)n * 20 + (size_t)sort_pairs_ws_elems(n) * 4 + 64; }

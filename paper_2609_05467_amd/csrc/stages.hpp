@@ -49,6 +49,10 @@ struct StageBufs {
     SampleJob *dsj;
     CastJob *dcj, *daj;
     void *dsetj;
+    // the spatial order of the samples for the hemisphere cast: keys and
+    // values twice, and the sort's workspace
+    uint64_t *okey0, *okey1;
+    uint32_t *oval0, *oval1, *osort;
 };
 
 // Shape of one batch: jobs, samples, work items and launch shape.
