@@ -139,7 +139,8 @@ typedef struct {
     int32_t *tri;   /* device int32 [n]: index of its face in the input mesh */
     int64_t n;      /* number of samples */
     int32_t *order; /* device int32 [n] or NULL: a spatial order of the samples, a permutation of
-                       [0, n) (indices sorted by a Morton code of the origin in the part's box).  The
+                       [0, n) (indices sorted stably by a 21-bit Morton code of the origin in the part's
+                       box).  The
                        samplers write it when it is non-NULL; the hemisphere cast reads it, or forms one
                        itself when it is NULL.  Results do not depend on it: it only groups nearby
                        samples in time.  An index outside [0, n) sets HRA_ERR_INVALID_ARG at the next

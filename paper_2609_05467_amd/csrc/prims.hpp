@@ -14,13 +14,13 @@ int64_t sort_pairs_ws_elems(int64_t n);
 hipError_t sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, uint32_t *ws, hipStream_t s,
                       bool *result_in_k1, int passes = 8);
 int64_t scan_u32_ws_elems(int64_t n);
-// A spatial order of n samples: their indices sorted stably by a 15-bit
-// Morton code of the origin in the part's box (5 bits per axis), written to
+// A spatial order of n samples: their indices sorted stably by a 21-bit
+// Morton code of the origin in the part's box (7 bits per axis), written to
 // order[n].  `ws` holds sample_order_ws_bytes(n) bytes.
 size_t sample_order_ws_bytes(int64_t n);
 hipError_t sample_order(const float *origin, int64_t n, const PartMeta *meta, int32_t *order, void *ws, hipStream_t s);
 // The same over the samples of several parts (the one-sample hemisphere
-// cast jobs of a batch, item = sample): keys are (job << 15) | the Morton
+// cast jobs of a batch, item = sample): keys are (job << 21) | the Morton
 // code in the job's part box, so the order keeps parts apart.  k0/v0 and
 // k1/v1 hold n keys and values each, ws sort_pairs_ws_elems(n) elements;
 // *order receives whichever values array holds the result.

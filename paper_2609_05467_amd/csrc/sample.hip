@@ -152,14 +152,16 @@ namespace hra {
 // The order changes only which samples a cast runs at the same time (nearby
 // ones share the hierarchy's nodes in L2); each sample's result is the same
 // in any order.
-// 15-bit Morton code of a point in the part's box (5 bits per axis)
-__device__ inline uint32_t morton15(const float *p, const PartMeta &P) {
+// Morton code of a point in the part's box, ORDER_AXIS_BITS bits per axis
+constexpr int ORDER_AXIS_BITS = 7, ORDER_BITS = 3 * ORDER_AXIS_BITS;
+__device__ inline uint32_t morton_code(const float *p, const PartMeta &P) {
+    constexpr float cells = (float)(1 << ORDER_AXIS_BITS);
     uint32_t code = 0;
     for (int k = 0; k < 3; ++k) {
         const float lo = P.bbox[k], ext = P.bbox[3 + k] - lo;
         const float t = ext > 0.0f ? (p[k] - lo) / ext : 0.0f;
-        const uint32_t q = (uint32_t)fminf(fmaxf(t * 32.0f, 0.0f), 31.0f);   // NaN -> 0
-        for (int b = 0; b < 5; ++b) code |= ((q >> b) & 1u) << (3 * b + (2 - k));
+        const uint32_t q = (uint32_t)fminf(fmaxf(t * cells, 0.0f), cells - 1.0f);   // NaN -> 0
+        for (int b = 0; b < ORDER_AXIS_BITS; ++b) code |= ((q >> b) & 1u) << (3 * b + (2 - k));
     }
     return code;
 }
@@ -167,7 +169,7 @@ __device__ inline uint32_t morton15(const float *p, const PartMeta &P) {
 __global__ void k_order_keys(const float *origin, int64_t n, const PartMeta *meta, uint64_t *keys, uint32_t *vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    keys[i] = morton15(origin + 3 * i, *meta);
+    keys[i] = morton_code(origin + 3 * i, *meta);
     vals[i] = (uint32_t)i;
 }
 
@@ -186,7 +188,7 @@ __global__ void k_order_keys_jobs(const CastJob *jobs, int32_t n_jobs, CastJob j
         j = lo;
     }
     const CastJob &J = jobs ? jobs[j] : job0;
-    keys[i] = ((uint64_t)j << 15) | morton15(J.origin + 3 * (i - J.item_base), *J.meta);
+    keys[i] = ((uint64_t)j << ORDER_BITS) | morton_code(J.origin + 3 * (i - J.item_base), *J.meta);
     vals[i] = (uint32_t)i;
 }
 
@@ -197,7 +199,7 @@ hipError_t sample_order_jobs(const CastJob *d_jobs, int32_t n_jobs, const CastJo
     if (n <= 0) return hipSuccess;
     int jb = 0;
     while (jb < 31 && ((int64_t)1 << jb) < n_jobs) ++jb;
-    const int passes = (15 + jb + 7) / 8;
+    const int passes = (ORDER_BITS + jb + 7) / 8;
     k_order_keys_jobs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d_jobs, n_jobs, job0, n, k0, v0);
     hipError_t e = hipGetLastError();
     bool in1 = false;
@@ -210,17 +212,20 @@ size_t sample_order_ws_bytes(int64_t n) { return (size_t)n * 20 + (size_t)sort_p
 
 hipError_t sample_order(const float *origin, int64_t n, const PartMeta *meta, int32_t *order, void *ws, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    constexpr int passes = (ORDER_BITS + 7) / 8;
     uint64_t *k0 = (uint64_t *)ws, *k1 = k0 + n;
-    uint32_t *v1 = (uint32_t *)(k1 + n), *sw = v1 + n;
-    uint32_t *v0 = (uint32_t *)order;
+    uint32_t *vt = (uint32_t *)(k1 + n), *sw = vt + n;
+    // the values start in the array the result does not land in: with an
+    // odd number of passes the sort ends in (k1, v1), so v1 is the order
+    uint32_t *v0 = (passes & 1) ? vt : (uint32_t *)order, *v1 = (passes & 1) ? (uint32_t *)order : vt;
     k_order_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(origin, n, meta, k0, v0);
     hipError_t e = hipGetLastError();
     bool in1 = false;
-    // two passes over the 15-bit keys: the result lands back in v0 (the order)
-    if (e == hipSuccess) e = sort_pairs(k0, v0, k1, v1, n, sw, s, &in1, 2);
-    if (e == hipSuccess && in1) e = hipErrorUnknown;
+    if (e == hipSuccess) e = sort_pairs(k0, v0, k1, v1, n, sw, s, &in1, passes);
+    if (e == hipSuccess && in1 != (bool)(passes & 1)) e = hipErrorUnknown;
     return e;
 }
+
 }  // namespace hra
 
 extern "C" hra_status hra_sample_part(hra_ctx *ctx, const hra_bvh *bvh, int32_t part, int32_t mode, uint64_t seed,

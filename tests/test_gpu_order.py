@@ -29,13 +29,13 @@ def ctx():
     c.close()
 
 
-def _morton15(o, lo, hi):
+def _morton21(o, lo, hi):
     code = np.zeros(len(o), np.uint32)
     for k in range(3):
         ext = np.float32(hi[k] - lo[k])
         t = (o[:, k] - np.float32(lo[k])) / ext
-        q = np.clip(np.floor(np.float32(32.0) * t), 0, 31).astype(np.uint32)
-        for b in range(5):
+        q = np.clip(np.floor(np.float32(128.0) * t), 0, 127).astype(np.uint32)
+        for b in range(7):
             code |= ((q >> b) & 1) << (3 * b + (2 - k))
     return code
 
@@ -54,7 +54,7 @@ def test_order_is_a_sorted_permutation_and_bits_do_not_depend_on_it(ctx, name, n
         assert np.array_equal(np.sort(order), np.arange(n))
         info = b.info()
         lo, hi = np.array(info.bbox[:3], np.float32), np.array(info.bbox[3:], np.float32)
-        keys = _morton15(s["origin"].cpu().numpy(), lo, hi)[order]
+        keys = _morton21(s["origin"].cpu().numpy(), lo, hi)[order]
         assert np.all(np.diff(keys.astype(np.int64)) >= 0)
         # stable: equal keys keep index order
         same = np.diff(keys.astype(np.int64)) == 0
