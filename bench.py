@@ -346,7 +346,7 @@ def measured_traffic(workload):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (each step a whole pass; the queue stays full between steps)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="interactive_200k", choices=sorted(WORKLOADS))
     ap.add_argument("--tool-length", type=float, default=50.0)
@@ -452,11 +452,17 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     W = (N + 31) // 32
     bits = torch.empty((S, W), dtype=torch.int32, device=dev)
     bits6 = torch.empty((S, 1), dtype=torch.int32, device=dev)
-    samples = ctx.alloc_samples(S)
-    # the sampler also writes a spatial order of the samples, which the
-    # hemisphere cast follows (nearby samples at the same time share the
-    # hierarchy's nodes in L2; the results do not depend on it)
-    samples["order"] = torch.empty((S,), dtype=torch.int32, device=dev)
+    # two sample buffers: the next step samples into one while this step's
+    # six-axis cast and setups still read the other.  The sampler also writes
+    # a spatial order of the samples, which the hemisphere cast follows
+    # (nearby samples at the same time share the hierarchy's nodes in L2; the
+    # results do not depend on it)
+    sample_bufs = []
+    for _ in range(2):
+        sb = ctx.alloc_samples(S)
+        sb["order"] = torch.empty((S,), dtype=torch.int32, device=dev)
+        sample_bufs.append(sb)
+    samples = sample_bufs[0]
 
     ev = {k: [] for k in ("build", "sample", "cast", "stats", "axes", "setups")}
 
@@ -468,48 +474,64 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     pending = []   # each timed step's events, read after the timed loop
     cls_stream = torch.cuda.Stream()
 
-    def build():
-        b = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    def prepare(i):
+        """Step i's hierarchy and samples, enqueued on the main stream."""
+        b = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         b[0].record()
         bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
         b[1].record()
-        return bvh, b
+        smp = sample_bufs[i % 2]
+        b[2].record()
+        ctx.sample_surface(bvh, S, 2, out=smp)
+        b[3].record()
+        return bvh, smp, b
 
-    def step(record, cur, prefetch):
-        """One analysis step on the hierarchy `cur` (its build already
-        enqueued on the main stream).  With prefetch, the next step's build
-        is enqueued on the main stream behind this step's statistics, before
-        the host waits for them, so the device is not idle while the host
-        finishes this step; every step still builds its own hierarchy."""
-        bvh, b = cur
+    def launch(cur):
+        """Enqueue a step's six-axis cast (side stream, after its samples)
+        and hemisphere cast (main stream) on the hierarchy and samples `cur`
+        (already enqueued on the main stream)."""
+        bvh, smp, b = cur
         main = torch.cuda.current_stream()
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         f = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        e[0].record()
-        ctx.sample_surface(bvh, S, 2, out=samples)
-        e[1].record()
         side.wait_stream(main)
         f[0].record(side)
-        ctx.cast(bvh, samples, 6, kind=hra.DIRS_AXES6, counts=False, bits=bits6, stream=side)
+        ctx.cast(bvh, smp, 6, kind=hra.DIRS_AXES6, counts=False, bits=bits6, stream=side)
         f[1].record(side)
-        ctx.cast(bvh, samples, N, counts=False, bits=bits)
+        e[0].record()
+        ctx.cast(bvh, smp, N, counts=False, bits=bits)
+        e[1].record()
+        return bvh, smp, b, e, f
+
+    def step(record, cur, i, prefetch):
+        """Finish analysis step i, whose casts `cur` are enqueued: its
+        statistics (main stream) and setups (side stream), then its class.
+        With prefetch, step i + 1's build, sample and casts are enqueued
+        behind this step's statistics before the host waits for them, so
+        the device is not idle while the host finishes this step; every step
+        still builds its own hierarchy, draws its own samples and casts
+        them."""
+        bvh, smp, b, e, f = cur
+        main = torch.cuda.current_stream()
+        ds = ctx.dominant_axes(smp, N, bits)
         e[2].record()
-        ds = ctx.dominant_axes(samples, N, bits)
-        e[3].record()
         # the setups return a host report: the host waits for the side
         # stream here, while the cast and the statistics queued on the main
-        # one run, then for the main stream in classify
-        su = ctx.min_setups(bvh, samples, bits6, args.tool_length, want_class=False, stream=side)
+        # one run, then for the statistics in classify
+        su = ctx.min_setups(bvh, smp, bits6, args.tool_length, want_class=False, stream=side)
         f[2].record(side)
         # the class is read on a stream that waits for the statistics only,
-        # so the host does not also wait for the build queued behind them
-        cls_stream.wait_event(e[3])
-        nxt = build() if prefetch else None
+        # so the host does not also wait for the work queued behind them
+        cls_stream.wait_event(e[2])
+        nxt = launch(prepare(i + 1)) if prefetch else None
         rep = ctx.classify(ds, S, N, stream=cls_stream)
-        main.wait_stream(side)
         if record:
             pending.append((b, e, f))
-        bvh.release()
+        # every reader of this step's hierarchy has ended (the statistics
+        # above, the side stream's work before the setups returned): it goes
+        # back to the pool in stream order, with no wait for the next step's
+        # work queued on the main stream
+        bvh.release(stream=main)
         return rep, su, nxt
 
     if args.copy_calibration_mib:
@@ -520,20 +542,21 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         del src, dst
     log(f"[bench] {workload}: {mesh.n_tris} triangles, {S} samples x {N} directions; warmup {args.warmup}")
     for w in range(args.warmup):
-        step(False, build(), False)
+        step(False, launch(prepare(w)), w, False)
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
-    # exactly K builds and K steps inside the timed region
+    # exactly K builds, K samplings and K steps inside the timed region
     t0 = time.perf_counter()
-    cur = build()
+    cur = launch(prepare(0))
     for k in range(args.steps):
-        rep, su, cur = step(True, cur, k + 1 < args.steps)
+        rep, su, cur = step(True, cur, k, k + 1 < args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     for b, e, f in pending:
         ev["build"].append(b[0].elapsed_time(b[1]))
-        for k, (x, y) in zip(("sample", "cast", "stats"), zip(e[:-1], e[1:])):
-            ev[k].append(x.elapsed_time(y))
+        ev["sample"].append(b[2].elapsed_time(b[3]))
+        ev["cast"].append(e[0].elapsed_time(e[1]))
+        ev["stats"].append(e[1].elapsed_time(e[2]))
         ev["axes"].append(f[0].elapsed_time(f[1]))
         ev["setups"].append(f[1].elapsed_time(f[2]))
     ms = dt / args.steps * 1e3
@@ -590,8 +613,9 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         # ... and the side stream's intervals, which share the GPU with the cast running beside them
         "side_stream_elapsed_ms": {k: round(float(np.mean(ev[k])), 3) for k in ("axes", "setups")},
         "stage_streams": {"main": ["build", "sample", "cast", "stats"], "side, after sample": ["axes", "setups"],
-                          "pipelining": "each step's build is enqueued behind the previous step's statistics, "
-                                        "before the host waits for them"},
+                          "pipelining": "each step's build, sample and casts are enqueued behind the previous "
+                                        "step's statistics, before the host waits for them (two sample "
+                                        "buffers)"},
         # each secondary stage timed alone on an idle GPU, outside the steps
         "secondary_alone_ms": {k: round(v, 4) for k, v in alone.items()},
         "cast_rays_per_s": rays / (cast_ms * 1e-3),

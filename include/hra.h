@@ -124,11 +124,24 @@ hra_status hra_bvh_part_info(hra_bvh *bvh, int32_t part, void *stream, hra_bvh_i
  * hierarchy; its other parts follow in the same arrays).  Synchronises. */
 hra_status hra_bvh_export(hra_bvh *bvh, void *stream, void *host_nodes, void *host_tris, int32_t *root,
                           int32_t *n_valid);
-/* Free a hierarchy (waits for nothing: the caller ends the work that reads
- * it first).  Allowed after its context has been destroyed, so that
- * garbage-collected handles may go in any order; every other call on a
- * hierarchy needs its context alive. */
+/* Free a hierarchy.  The arrays of one from hra_build_bvh or
+ * hra_build_bvh_batch come from the device's stream-ordered pool: the call
+ * first waits for the device's queued work, as a plain free does, then
+ * returns them to the pool.  Allowed after its context has been destroyed,
+ * so that garbage-collected handles may go in any order; every other call
+ * on a hierarchy needs its context alive. */
 void hra_bvh_release(hra_bvh *bvh);
+/* Free a hierarchy in stream order, without waiting: its arrays return to
+ * the device's pool once the work queued on `stream` (a HIP stream of the
+ * hierarchy's device) so far has run, and later allocations on any stream
+ * may then reuse them.  The caller orders every other reader of the
+ * hierarchy before that point (on `stream` itself, through an event that
+ * `stream` waits on, or by having waited for it).  The handle is invalid on
+ * return, also on error.  HRA_ERR_DEVICE if the device cannot be made
+ * current.  For the pipelined caller whose device must not drain between
+ * steps (a host wait for one step's result while the next one's work is
+ * queued).  Allowed after its context has been destroyed. */
+hra_status hra_bvh_release_async(hra_bvh *bvh, void *stream);
 
 /* ----------------------------------------------------------------- samples */
 

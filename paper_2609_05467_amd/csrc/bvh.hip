@@ -885,7 +885,7 @@ hipError_t put_mesh_table(MeshIn *dst, const MeshIn &m, hipStream_t s) {
 }
 
 hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out,
-                     hipStream_t alloc_stream) {
+                     hipStream_t stream, BvhAlloc mode) {
     const int n_parts = (int)hm.size();
     hra_bvh *b = new hra_bvh();
     b->ctx = ctx;
@@ -899,10 +899,11 @@ hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int
     }
     const int64_t nn = T > 1 ? T - 1 : 1;
     size_t bytes = 0;
-    b->alloc_stream = alloc_stream;
+    b->alloc_stream = mode == BVH_POOL_KEEP ? stream : nullptr;
+    b->pooled = mode != BVH_PLAIN;
     auto alloc = [&](void **p, size_t n) -> bool {
         bytes += n;
-        return (alloc_stream ? hipMallocAsync(p, n, alloc_stream) : hipMalloc(p, n)) == hipSuccess;
+        return (b->pooled ? hipMallocAsync(p, n, stream) : hipMalloc(p, n)) == hipSuccess;
     };
     if (!alloc((void **)&b->nodes, sizeof(Node) * nn) || !alloc((void **)&b->tris, sizeof(float4) * 3 * T) ||
         !alloc((void **)&b->leaf_pos, sizeof(int32_t) * T) || !alloc((void **)&b->valid_rank, sizeof(int32_t) * T) ||
@@ -967,7 +968,10 @@ static hra_status build_parts(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_pa
     if (st != HRA_OK) return st;
     HRA_HIP(hipSetDevice(ctx->device));
     hra_bvh *b = nullptr;
-    st = alloc_bvh(ctx, hm, T, leaf, &b);
+    // from the device's stream-ordered pool (no allocation call reaches the
+    // driver once the pool holds the memory); the caller's stream is not
+    // kept, since it may be destroyed before the hierarchy is released
+    st = alloc_bvh(ctx, hm, T, leaf, &b, s, BVH_POOL);
     if (st != HRA_OK) return st;
     void *ws = nullptr;
     hipError_t e = hipMallocAsync(&ws, build_ws_bytes(T, n_parts), s);
@@ -1042,14 +1046,35 @@ extern "C" hra_status hra_bvh_export(hra_bvh *b, void *stream, void *host_nodes,
     return HRA_OK;
 }
 
-extern "C" void hra_bvh_release(hra_bvh *b) {
-    if (!b) return;
-    hipSetDevice(b->device);
+static void free_bvh_arrays(hra_bvh *b, hipStream_t s, bool async) {
     for (void *p : {(void *)b->nodes, (void *)b->tris, (void *)b->leaf_pos, (void *)b->valid_rank, (void *)b->prefix,
                     (void *)b->parts}) {
         if (!p) continue;
-        if (b->alloc_stream) hipFreeAsync(p, b->alloc_stream);
-        else hipFree(p);
+        if (async) (void)hipFreeAsync(p, s);
+        else (void)hipFree(p);
+    }
+}
+
+extern "C" void hra_bvh_release(hra_bvh *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->alloc_stream) {
+        free_bvh_arrays(b, b->alloc_stream, true);
+    } else if (b->pooled) {
+        // as a plain free does: the device's work ends first, then the
+        // arrays go back to the pool
+        (void)hipDeviceSynchronize();
+        free_bvh_arrays(b, nullptr, true);
+    } else {
+        free_bvh_arrays(b, nullptr, false);
     }
     delete b;
+}
+
+extern "C" hra_status hra_bvh_release_async(hra_bvh *b, void *stream) {
+    if (!b) return HRA_OK;
+    if (hipSetDevice(b->device) != hipSuccess) return HRA_ERR_DEVICE;
+    free_bvh_arrays(b, (hipStream_t)stream, b->pooled);
+    delete b;
+    return HRA_OK;
 }

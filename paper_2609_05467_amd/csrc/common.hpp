@@ -141,7 +141,8 @@ struct hra_bvh {
     std::vector<int64_t> part_tris;  // host: triangles per part
     std::vector<int64_t> part_start; // host: first triangle per part
     int64_t bytes = 0;
-    hipStream_t alloc_stream = nullptr;  // arrays from the stream-ordered allocator on this stream (else hipMalloc)
+    hipStream_t alloc_stream = nullptr;  // arrays from the stream-ordered allocator on this stream, freed there
+    bool pooled = false;                 // arrays from the stream-ordered allocator, no stream kept (else hipMalloc)
 };
 
 namespace hra {
@@ -231,10 +232,15 @@ int32_t cast_group(int32_t n_dirs, int32_t setting);
 // from the workspace (build_ws_mesh_table) that the caller has filled.
 hra_status check_meshes(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, int32_t leaf,
                         std::vector<MeshIn> *hm, int64_t *T_out);
-// alloc_stream != NULL: allocate from the stream-ordered allocator on that
-// stream (released the same way).
+// How a hierarchy's arrays are allocated: BVH_PLAIN with hipMalloc;
+// BVH_POOL_KEEP from the stream-ordered allocator on `stream` and released
+// there (the stream outlives the hierarchy); BVH_POOL from the stream-ordered
+// allocator on `stream` (the null stream included) with no stream kept:
+// hra_bvh_release waits for the device, hra_bvh_release_async frees on the
+// stream it is given.
+enum BvhAlloc { BVH_PLAIN = 0, BVH_POOL_KEEP = 1, BVH_POOL = 2 };
 hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int32_t leaf, hra_bvh **out,
-                     hipStream_t alloc_stream = nullptr);
+                     hipStream_t stream = nullptr, BvhAlloc mode = BVH_PLAIN);
 size_t build_ws_bytes(int64_t T, int n_parts);
 MeshIn *build_ws_mesh_table(void *ws, int64_t T, int n_parts);
 // Device bytes a hierarchy over T triangles in n_parts parts holds.

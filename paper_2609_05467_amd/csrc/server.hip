@@ -182,7 +182,7 @@ void start_build(hra_server *sv, uint64_t key, const hra_request &r) {
     if (e == hipSuccess) e = hipMemcpyAsync(dv, r.h_verts, sizeof(float) * 3 * r.n_verts, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dt, r.h_tris, sizeof(int32_t) * 3 * r.n_tris, hipMemcpyHostToDevice, s);
     std::vector<MeshIn> hm = {MeshIn{dv, dt, r.n_verts, r.n_tris, 0, 0}};
-    if (e == hipSuccess && alloc_bvh(sv->ctx, hm, r.n_tris, leaf, &p.bvh, s) != HRA_OK) e = hipErrorOutOfMemory;
+    if (e == hipSuccess && alloc_bvh(sv->ctx, hm, r.n_tris, leaf, &p.bvh, s, BVH_POOL_KEEP) != HRA_OK) e = hipErrorOutOfMemory;
     if (e == hipSuccess) e = hipMallocAsync(&ws, build_ws_bytes(r.n_tris, 1), s);
     if (e == hipSuccess) {
         k_zero_words<<<1, 64, 0, s>>>(p.d_err, 16);

@@ -158,6 +158,7 @@ def lib():
             "hra_build_bvh": ([P, P, i64, P, i64, C.POINTER(BvhOpts), P, C.POINTER(P)], C.c_int),
             "hra_bvh_get_info": ([P, P, C.POINTER(BvhInfo)], C.c_int),
             "hra_bvh_release": ([P], None),
+            "hra_bvh_release_async": ([P, P], C.c_int),
             "hra_bvh_export": ([P, P, P, P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "hra_sample_surface": ([P, P, i32, u64, f32, C.POINTER(Samples), P], C.c_int),
             "hra_dirs_table": ([P, Dirs, P], C.c_int),
@@ -232,7 +233,7 @@ EXPORTS = ["hra_ctx_create", "hra_ctx_destroy", "hra_last_error", "hra_version",
            "hra_frame_estimate", "hra_frame_ws_bytes", "hra_frame_apply", "hra_stl_read", "hra_stl_copy",
            "hra_stl_free", "hra_stl_error", "hra_cast_tool", "hra_cast_tool_work",
            "hra_cast_tool_holder", "hra_dominant_axes_noalloc", "hra_debug_azimuth_table",
-           "hra_datum_frames"]
+           "hra_datum_frames", "hra_bvh_release_async"]
 FRAME_BAD_INDEX, FRAME_EMPTY = 1, 2
 
 
@@ -619,7 +620,17 @@ class Bvh:
     def __init__(self, ctx, ptr, keep, stream):
         self.ctx, self.ptr = ctx, ptr
         self._keep = keep   # inputs stay alive until the build has run
-        self._stream = stream
+        # the stream the build was queued on
+        self._stream = stream if stream is not None else torch.cuda.current_stream(ctx.device)
+
+    def _drop_inputs(self):
+        """Let the build's input tensors go without waiting: the caching
+        allocator reuses their memory only after the work queued so far on
+        the build's stream (the build included) has run."""
+        keep, self._keep = self._keep, None
+        if keep is not None:
+            for x in keep:
+                x.record_stream(self._stream)
 
     @property
     def n_parts(self):
@@ -628,7 +639,7 @@ class Bvh:
     def info(self, stream=None, part=0):
         inf = BvhInfo()
         self.ctx._check(lib().hra_bvh_part_info(self.ptr, part, _stream(stream), C.byref(inf)))
-        self._keep = None
+        self._drop_inputs()
         return inf
 
     def export(self, stream=None):
@@ -647,15 +658,23 @@ class Bvh:
                                              tris.ctypes.data_as(C.c_void_p), C.byref(root), C.byref(nv)))
         return nodes, tris[:nv.value], root.value, nv.value
 
-    def release(self):
+    def release(self, stream=None):
+        """Free the hierarchy.  With a stream: in stream order, without
+        waiting (every other reader must be ordered before the work queued
+        on that stream so far); without: after the device's queued work."""
+        self._drop_inputs()
         if self.ptr:
-            lib().hra_bvh_release(self.ptr)
-            self.ptr = None
+            p, self.ptr = self.ptr, None
+            if stream is None:
+                lib().hra_bvh_release(p)
+            else:
+                st = lib().hra_bvh_release_async(p, _stream(stream))
+                if st != 0:
+                    raise HraError(st, "hierarchy release failed")
 
     def __del__(self):
         try:
-            if self._keep is not None:
-                torch.cuda.synchronize(self.ctx.device)
+            self._drop_inputs()
             self.release()
         except Exception:
             pass

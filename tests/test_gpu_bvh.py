@@ -89,3 +89,41 @@ def test_release_after_context_destroyed():
     assert b2.info().n_tris == m.n_tris
     b2.release()
     c2.close()
+
+
+def test_release_in_stream_order_while_work_is_queued(ctx):
+    """A pipelined caller frees step k's hierarchy on its stream while step
+    k + 1's build and cast are queued behind it: the arrays return to the
+    pool in stream order, the next builds reuse them, and every step's bits
+    equal those of a hierarchy nobody released early (the memory the pool
+    hands back is never read by a stale reader, nor overwritten under a
+    live one)."""
+    import torch
+    m = P.config1_part()
+    S, N = 4000, 1024
+    _say("release async", m.n_tris, S, N)
+    ref_b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.alloc_samples(S)
+    ctx.sample_surface(ref_b, S, 3, out=s)
+    ref, _ = ctx.cast(ref_b, s, N, counts=False)
+    ref_nodes = _export(ctx, m, 4)[0]
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    cur = ctx.build_bvh(m.verts, m.tris)
+    outs = []
+    for k in range(6):
+        bits, _ = ctx.cast(cur, s, N, counts=False)
+        outs.append(bits)
+        nxt = ctx.build_bvh(m.verts, m.tris)       # queued behind the cast
+        cur.release(stream=main)                    # no wait: freed after the cast in stream order
+        assert cur.ptr is None
+        cur = nxt
+    n2 = _export(ctx, m, 4)[0]
+    torch.cuda.synchronize()
+    for k, bits in enumerate(outs):
+        assert torch.equal(bits, ref), k
+    assert np.array_equal(n2.view(np.uint32), ref_nodes.view(np.uint32))
+    cur.release(stream=main)
+    cur.release(stream=main)       # a second release of a freed handle does nothing
+    ref_b.release()
+    torch.cuda.synchronize()
