@@ -131,12 +131,15 @@ hra_status hra_bvh_export(hra_bvh *bvh, void *stream, void *host_nodes, void *ho
  * so that garbage-collected handles may go in any order; every other call
  * on a hierarchy needs its context alive. */
 void hra_bvh_release(hra_bvh *bvh);
-/* Free a hierarchy in stream order, without waiting: its arrays return to
- * the device's pool once the work queued on `stream` (a HIP stream of the
- * hierarchy's device) so far has run, and later allocations on any stream
- * may then reuse them.  The caller orders every other reader of the
- * hierarchy before that point (on `stream` itself, through an event that
- * `stream` waits on, or by having waited for it).  The handle is invalid on
+/* Free a hierarchy in stream order, without waiting, when `stream` is the
+ * stream it was built on (still alive): its arrays return to the device's
+ * pool once the work queued on `stream` so far has run.  The caller orders
+ * every other reader of the hierarchy before that point (on `stream`
+ * itself, through an event that `stream` waits on, or by having waited for
+ * it).  With any other stream the call waits for the device first, as
+ * hra_bvh_release does: this runtime's pool gives a block freed on one
+ * stream to the next allocation on the stream that allocated it, before
+ * the freeing stream's queued work has run.  The handle is invalid on
  * return, also on error.  HRA_ERR_DEVICE if the device cannot be made
  * current.  For the pipelined caller whose device must not drain between
  * steps (a host wait for one step's result while the next one's work is

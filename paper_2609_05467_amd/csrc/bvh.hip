@@ -901,6 +901,7 @@ hra_status alloc_bvh(hra_ctx *ctx, const std::vector<MeshIn> &hm, int64_t T, int
     size_t bytes = 0;
     b->alloc_stream = mode == BVH_POOL_KEEP ? stream : nullptr;
     b->pooled = mode != BVH_PLAIN;
+    b->build_stream = stream;
     auto alloc = [&](void **p, size_t n) -> bool {
         bytes += n;
         return (b->pooled ? hipMallocAsync(p, n, stream) : hipMalloc(p, n)) == hipSuccess;
@@ -1073,8 +1074,22 @@ extern "C" void hra_bvh_release(hra_bvh *b) {
 
 extern "C" hra_status hra_bvh_release_async(hra_bvh *b, void *stream) {
     if (!b) return HRA_OK;
-    if (hipSetDevice(b->device) != hipSuccess) return HRA_ERR_DEVICE;
-    free_bvh_arrays(b, (hipStream_t)stream, b->pooled);
+    if (hipSetDevice(b->device) != hipSuccess) {
+        delete b;   // the handle is invalid on return; its arrays stay with the device
+        return HRA_ERR_DEVICE;
+    }
+    // The pool hands a block freed on another stream, before that stream's
+    // queued work has run, to the next allocation on the stream that first
+    // allocated it (measured: no dependency is inserted).  A stream-ordered
+    // free is therefore safe only on the stream the arrays came from; on any
+    // other stream the device's work ends first, as in hra_bvh_release.
+    const hipStream_t s = (hipStream_t)stream;
+    if (b->pooled && s == b->build_stream) {
+        free_bvh_arrays(b, s, true);
+    } else {
+        (void)hipDeviceSynchronize();
+        free_bvh_arrays(b, b->alloc_stream, b->pooled);
+    }
     delete b;
     return HRA_OK;
 }

@@ -142,7 +142,8 @@ struct hra_bvh {
     std::vector<int64_t> part_start; // host: first triangle per part
     int64_t bytes = 0;
     hipStream_t alloc_stream = nullptr;  // arrays from the stream-ordered allocator on this stream, freed there
-    bool pooled = false;                 // arrays from the stream-ordered allocator, no stream kept (else hipMalloc)
+    bool pooled = false;                 // arrays from the stream-ordered allocator (else hipMalloc)
+    hipStream_t build_stream = nullptr;  // the stream the pooled arrays were allocated on (compared, never used)
 };
 
 namespace hra {

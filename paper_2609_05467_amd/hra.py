@@ -659,9 +659,10 @@ class Bvh:
         return nodes, tris[:nv.value], root.value, nv.value
 
     def release(self, stream=None):
-        """Free the hierarchy.  With a stream: in stream order, without
-        waiting (every other reader must be ordered before the work queued
-        on that stream so far); without: after the device's queued work."""
+        """Free the hierarchy.  With the stream it was built on: in stream
+        order, without waiting (every other reader must be ordered before
+        the work queued on that stream so far); with another stream or none:
+        after the device's queued work."""
         self._drop_inputs()
         if self.ptr:
             p, self.ptr = self.ptr, None

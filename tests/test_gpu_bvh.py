@@ -127,3 +127,33 @@ def test_release_in_stream_order_while_work_is_queued(ctx):
     cur.release(stream=main)       # a second release of a freed handle does nothing
     ref_b.release()
     torch.cuda.synchronize()
+
+
+def test_release_on_another_stream_waits(ctx):
+    """A hierarchy built on one stream and released on another: the pool
+    would give its blocks to the next build on the first stream before the
+    second stream's queued work has run, so the release waits for the device
+    instead, and a cast queued before it still reads an intact hierarchy."""
+    import torch
+    m = P.config1_part()
+    S, N = 4000, 1024
+    _say("release on another stream", m.n_tris, S, N)
+    ref_b = ctx.build_bvh(m.verts, m.tris)
+    s = ctx.alloc_samples(S)
+    ctx.sample_surface(ref_b, S, 3, out=s)
+    ref, _ = ctx.cast(ref_b, s, N, counts=False)
+    torch.cuda.synchronize()
+    other = torch.cuda.Stream()
+    outs = []
+    for k in range(4):
+        b = ctx.build_bvh(m.verts, m.tris)           # built on the current stream
+        other.wait_stream(torch.cuda.current_stream())
+        bits, _ = ctx.cast(b, s, N, counts=False, stream=other)
+        outs.append(bits)
+        b.release(stream=other)                       # not the build stream: waits for the device
+        assert b.ptr is None
+    torch.cuda.synchronize()
+    for k, bits in enumerate(outs):
+        assert torch.equal(bits, ref), k
+    ref_b.release()
+    torch.cuda.synchronize()
