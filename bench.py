@@ -84,6 +84,13 @@ DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "mu
 # cast in 29.4 ms against 32.7; on the interactive part the two are within
 # run-to-run noise (11.80-11.88 against 11.84-11.86 ms).
 DEFAULT_SHAPE = {"multiaxis_1m": (256, 8)}
+# Whether a step's build and sample run on a stream of their own beside the
+# previous step's cast: they do on the parts whose cast takes milliseconds
+# (interactive part 12.05 -> 11.70 ms per step, 1M-triangle part 27.9 ->
+# 26.5 ms); on the 1.8k-triangle part every stage lasts tens of microseconds
+# and the cross-stream waits cost more than the overlap returns (0.65 ->
+# 0.84 ms), so its steps stay on one stream.
+PREP_STREAM = {"single_block_1k5": False}
 
 
 def roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit, kernel="k_cast_rows"):
@@ -474,26 +481,35 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     pending = []   # each timed step's events, read after the timed loop
     cls_stream = torch.cuda.Stream()
 
+    # the build and the sample of a step run on a third stream, beside the
+    # previous step's hemisphere cast; a hierarchy is freed on the stream it
+    # was built on, after the statistics that last read it (the pool gives a
+    # block back to the next allocation on its own stream in that stream's
+    # order only)
+    prep = torch.cuda.Stream() if PREP_STREAM.get(workload, True) else torch.cuda.current_stream()
+
     def prepare(i):
-        """Step i's hierarchy and samples, enqueued on the main stream."""
+        """Step i's hierarchy and samples, enqueued on the prep stream."""
         b = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        b[0].record()
-        bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
-        b[1].record()
-        smp = sample_bufs[i % 2]
-        b[2].record()
-        ctx.sample_surface(bvh, S, 2, out=smp)
-        b[3].record()
+        with torch.cuda.stream(prep):
+            b[0].record()
+            bvh = ctx.build_bvh(verts, tris, leaf_size=args.leaf)
+            b[1].record()
+            smp = sample_bufs[i % 2]
+            b[2].record()
+            ctx.sample_surface(bvh, S, 2, out=smp)
+            b[3].record()
         return bvh, smp, b
 
     def launch(cur):
-        """Enqueue a step's six-axis cast (side stream, after its samples)
-        and hemisphere cast (main stream) on the hierarchy and samples `cur`
-        (already enqueued on the main stream)."""
+        """Enqueue a step's six-axis cast (side stream) and hemisphere cast
+        (main stream) on the hierarchy and samples `cur`, after the prep
+        stream's build and sample."""
         bvh, smp, b = cur
         main = torch.cuda.current_stream()
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         f = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        main.wait_stream(prep)
         side.wait_stream(main)
         f[0].record(side)
         ctx.cast(bvh, smp, 6, kind=hra.DIRS_AXES6, counts=False, bits=bits6, stream=side)
@@ -527,11 +543,12 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         rep = ctx.classify(ds, S, N, stream=cls_stream)
         if record:
             pending.append((b, e, f))
-        # every reader of this step's hierarchy has ended (the statistics
-        # above, the side stream's work before the setups returned): it goes
-        # back to the pool in stream order, with no wait for the next step's
-        # work queued on the main stream
-        bvh.release(stream=main)
+        # the last readers of this step's hierarchy are the statistics (the
+        # side stream's work ended before the setups returned): it goes back
+        # to the pool on the stream it was built on, behind the next step's
+        # build and sample there and after the statistics, without a wait
+        prep.wait_event(e[2])
+        bvh.release(stream=prep)
         return rep, su, nxt
 
     if args.copy_calibration_mib:
@@ -548,10 +565,16 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
     # exactly K builds, K samplings and K steps inside the timed region
     t0 = time.perf_counter()
     cur = launch(prepare(0))
+    reports = []
     for k in range(args.steps):
         rep, su, cur = step(True, cur, k, k + 1 < args.steps)
+        reports.append((rep, su))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # every step analyses the same part with the same seeded samples, so
+    # every step's class and setups must be the same, bit for bit, however
+    # the steps overlap on the device
+    steps_identical = all(r == reports[0] for r in reports)
     for b, e, f in pending:
         ev["build"].append(b[0].elapsed_time(b[1]))
         ev["sample"].append(b[2].elapsed_time(b[3]))
@@ -608,12 +631,19 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
                    "rays_per_step": rays, "leaf_size": args.leaf, "rays_per_wave": args.rays_per_wave,
                    "stack_depth": args.stack, "traversal": args.traversal, "tool_length_mm": args.tool_length},
         "parts_per_s": args.steps / dt,
-        # the step's critical path (main stream) ...
+        # each stage's interval on its stream: cast and statistics on the main
+        # stream (the step's critical path); build and sample on the prep
+        # stream, where they share the GPU with the previous step's cast ...
         "stage_ms": {k: round(float(np.mean(ev[k])), 3) for k in ("build", "sample", "cast", "stats")},
         # ... and the side stream's intervals, which share the GPU with the cast running beside them
         "side_stream_elapsed_ms": {k: round(float(np.mean(ev[k])), 3) for k in ("axes", "setups")},
-        "stage_streams": {"main": ["build", "sample", "cast", "stats"], "side, after sample": ["axes", "setups"],
-                          "pipelining": "each step's build, sample and casts are enqueued behind the previous "
+        "stage_streams": {"main": ["cast", "stats"],
+                          ("prep, beside the previous step's cast" if PREP_STREAM.get(workload, True)
+                           else "main, before the cast"): ["build", "sample"],
+                          "side, after sample": ["axes", "setups"],
+                          "pipelining": "each step's build and sample run on the prep stream beside the "
+                                        "previous step's cast (parts whose cast takes milliseconds), and its "
+                                        "casts are enqueued behind the previous "
                                         "step's statistics, before the host waits for them (two sample "
                                         "buffers)"},
         # each secondary stage timed alone on an idle GPU, outside the steps
@@ -623,7 +653,8 @@ def run_single(args, workload, cpu_budget_s=40.0, frame=True, brute=False):
         "work_per_ray": {"node_fetches": nodes / rays, "tri_tests": tests / rays, "bytes": bytes_per_ray,
                          "instrumented_bits_identical": same},
         "result": {"access": rep["access"], "multi_axis": rep["multi_axis"], "shares": rep["shares"],
-                   "mean_conc": rep["conc"], "min_setups": su["min_count"], "greedy_setups": su["greedy_count"]},
+                   "mean_conc": rep["conc"], "min_setups": su["min_count"], "greedy_setups": su["greedy_count"],
+                   "all_steps_identical": steps_identical},
         "roofline": roofline(nodes, tests, rays, W, N, cast_ms, traffic, l2_hit),
     }
     if not args.no_cpu_baseline:
