@@ -80,10 +80,12 @@ TRAVERSAL = {"step": 1, "leaf_loop": 2, "refill": 3}     # hra.h HRA_TRAVERSAL_*
 DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "multiaxis_1m": "step",
                      "batch64": "step", "serve": "step", "paper_shape": "refill"}
 # (rays per wave, leaf size) measured faster per workload; (64, 4) elsewhere.
-# On the 1M-triangle part 256 rays per wave and leaves of up to 8 triangles
-# cast in 29.4 ms against 32.7; on the interactive part the two are within
-# run-to-run noise (11.80-11.88 against 11.84-11.86 ms).
-DEFAULT_SHAPE = {"multiaxis_1m": (256, 8)}
+# On the 1M-triangle part (samples in spatial order) leaves of up to 16
+# triangles cast in 23.1 ms, up to 8 in 24.1, up to 4 in 26.6; 256 rays per
+# wave a little faster than 64.  On the interactive part every shape from
+# leaves of 2 to 16 and 64 to 256 rays per wave lies within 1 % (10.70-10.81
+# ms).
+DEFAULT_SHAPE = {"multiaxis_1m": (256, 16)}
 # Whether a step's build and sample run on a stream of their own beside the
 # previous step's cast: they do on the parts whose cast takes milliseconds
 # (interactive part 12.05 -> 11.70 ms per step, 1M-triangle part 27.9 ->

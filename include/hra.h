@@ -64,7 +64,9 @@ const char *hra_version(void);
 /* -------------------------------------------------------------- mesh + BVH */
 
 typedef struct {
-    int32_t leaf_size; /* triangles per BVH leaf: 1..8; 0 = default (4) */
+    int32_t leaf_size; /* most triangles per BVH leaf: 1..16; 0 = default (4).  A subtree
+                          that small becomes one leaf only where testing its triangles
+                          costs less than traversing it (surface-area cost) */
 } hra_bvh_opts;
 
 /* Mesh ingest and acceleration structure (Section 3.1: the part is a
@@ -235,7 +237,7 @@ typedef struct {
     int32_t rays_per_wave; /* directions per work item of one wavefront: 64, 128 or 256 */
     int32_t stack_depth;   /* traversal stack entries per lane held in LDS: 16, 20, 24 or
                               32, default 16 (deeper paths overflow into private memory) */
-    int32_t leaf_size;     /* triangles per leaf of builds whose options give 0: 1..8
+    int32_t leaf_size;     /* triangles per leaf of builds whose options give 0: 1..16
                               (0 in hra_set_cast_config: keep the current value) */
     int32_t traversal;     /* HRA_TRAVERSAL_STEP or HRA_TRAVERSAL_LEAF_LOOP
                               (0 in hra_set_cast_config: keep the current value) */

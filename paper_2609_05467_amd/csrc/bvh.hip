@@ -851,7 +851,7 @@ MeshIn *build_ws_mesh_table(void *ws, int64_t T, int n_parts) {
 hra_status check_meshes(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_parts, int32_t leaf,
                         std::vector<MeshIn> *hm, int64_t *T_out) {
     if (n_parts < 1 || n_parts > MAX_PARTS) return ctx->fail(HRA_ERR_INVALID_ARG, "1..255 parts per hierarchy");
-    if (leaf < 1 || leaf > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 1..8");
+    if (leaf < 1 || leaf > 16) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 1..16");
     int64_t T = 0, V = 0;
     hm->resize(n_parts);
     for (int p = 0; p < n_parts; ++p) {

@@ -1084,7 +1084,7 @@ extern "C" hra_status hra_set_cast_config(hra_ctx *ctx, const hra_cast_config *c
         return ctx->fail(HRA_ERR_INVALID_ARG, "rays_per_wave must be 64, 128 or 256");
     if (cfg->stack_depth != 16 && cfg->stack_depth != 20 && cfg->stack_depth != 24 && cfg->stack_depth != 32)
         return ctx->fail(HRA_ERR_INVALID_ARG, "stack_depth must be 16, 20, 24 or 32");
-    if (cfg->leaf_size < 0 || cfg->leaf_size > 8) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 0..8");
+    if (cfg->leaf_size < 0 || cfg->leaf_size > 16) return ctx->fail(HRA_ERR_INVALID_ARG, "leaf_size must be in 0..16");
     if (cfg->traversal != 0 && cfg->traversal != HRA_TRAVERSAL_STEP && cfg->traversal != HRA_TRAVERSAL_LEAF_LOOP &&
         cfg->traversal != HRA_TRAVERSAL_REFILL)
         return ctx->fail(HRA_ERR_INVALID_ARG,

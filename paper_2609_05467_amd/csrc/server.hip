@@ -482,7 +482,7 @@ extern "C" hra_status hra_server_create(int32_t device, const hra_server_opts *o
     if (o.max_inflight == 0) o.max_inflight = 2;
     if (o.budget_bytes < 0 || o.max_batch < 1 || o.max_batch > MAX_PARTS || o.max_inflight < 1 ||
         o.max_inflight > 4 || (o.mode != HRA_SERVE_CONTINUOUS && o.mode != HRA_SERVE_PLAIN) || o.leaf_size < 0 ||
-        o.leaf_size > 8 || o.offset_frac < 0.0f || o.offset_frac > 0.01f)
+        o.leaf_size > 16 || o.offset_frac < 0.0f || o.offset_frac > 0.01f)
         return HRA_ERR_INVALID_ARG;
     hra_server *sv = new hra_server();
     hra_status st = hra_ctx_create(device, &sv->ctx);

@@ -47,7 +47,7 @@ def _export(ctx, m, leaf):
 
 
 @pytest.mark.parametrize("name", sorted(MESHES))
-@pytest.mark.parametrize("leaf", [1, 4, 8])
+@pytest.mark.parametrize("leaf", [1, 4, 8, 16])
 def test_bvh_tight_and_identical_across_builds(ctx, name, leaf):
     m = MESHES[name]()
     _say("bvh", name, leaf, m.n_tris)

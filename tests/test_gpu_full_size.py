@@ -23,7 +23,7 @@ from synth import parts as P
 pytestmark = pytest.mark.gpu
 
 # benchmark launch shapes (rays per wave, leaf size, traversal loop) per workload
-SHAPE = {"interactive_200k": (64, 4, "step"), "multiaxis_1m": (256, 8, "step"), "batch64": (64, 4, "step"),
+SHAPE = {"interactive_200k": (64, 4, "step"), "multiaxis_1m": (256, 16, "step"), "batch64": (64, 4, "step"),
          "paper_housing_22k": (64, 4, "refill"), "paper_impeller_124k": (64, 4, "refill")}
 
 

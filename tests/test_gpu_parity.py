@@ -137,7 +137,7 @@ def test_cast_ragged_direction_counts(ctx, orc, cfg1, N):
     _cast_parity(ctx, orc, m, b, 77, N, 5)
 
 
-@pytest.mark.parametrize("leaf", [1, 2, 4, 8])
+@pytest.mark.parametrize("leaf", [1, 2, 4, 8, 12, 16])
 def test_cast_leaf_sizes(ctx, orc, leaf):
     m = P._procedural(9, 1.0, "pockets", (120.0, 90.0, 60.0), (6, 10))
     _say("leaf", leaf, m.n_tris)
