@@ -82,10 +82,11 @@ DEFAULT_TRAVERSAL = {"interactive_200k": "step", "single_block_1k5": "step", "mu
 # (rays per wave, leaf size) measured faster per workload; (64, 4) elsewhere.
 # On the 1M-triangle part (samples in spatial order) leaves of up to 16
 # triangles cast in 23.1 ms, up to 8 in 24.1, up to 4 in 26.6; 256 rays per
-# wave a little faster than 64.  On the interactive part every shape from
-# leaves of 2 to 16 and 64 to 256 rays per wave lies within 1 % (10.70-10.81
-# ms).
-DEFAULT_SHAPE = {"multiaxis_1m": (256, 16)}
+# wave a little faster than 64.  The 64-part batch plan: 61.4 ms with leaves
+# of up to 16, 61.7 with 8, 62.7 with 4.  On the interactive part every shape
+# from leaves of 2 to 16 and 64 to 256 rays per wave lies within 1 %
+# (10.70-10.81 ms).
+DEFAULT_SHAPE = {"multiaxis_1m": (256, 16), "batch64": (64, 16)}
 # Whether a step's build and sample run on a stream of their own beside the
 # previous step's cast: they do on the parts whose cast takes milliseconds
 # (interactive part 12.05 -> 11.70 ms per step, 1M-triangle part 27.9 ->

@@ -23,7 +23,7 @@ from synth import parts as P
 pytestmark = pytest.mark.gpu
 
 # benchmark launch shapes (rays per wave, leaf size, traversal loop) per workload
-SHAPE = {"interactive_200k": (64, 4, "step"), "multiaxis_1m": (256, 16, "step"), "batch64": (64, 4, "step"),
+SHAPE = {"interactive_200k": (64, 4, "step"), "multiaxis_1m": (256, 16, "step"), "batch64": (64, 16, "step"),
          "paper_housing_22k": (64, 4, "refill"), "paper_impeller_124k": (64, 4, "refill")}
 
 
@@ -158,7 +158,8 @@ def test_batch64_every_row_matches_oracle(ctx, orc, tmp_path):
     S = sum(counts)
     bits = torch.empty((S, N // 32), dtype=torch.int32, device=ctx.device)
     _say("plan", S, "samples")
-    pl = ctx.plan(reqs, N)
+    rpw, leaf, _ = SHAPE["batch64"]
+    pl = ctx.plan(reqs, N, leaf_size=leaf, rays_per_wave=rpw)
     pl.run(graph=True)
     res = pl.run(graph=True, bits=bits)
     pl.destroy()
