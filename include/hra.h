@@ -75,9 +75,11 @@ typedef struct {
  * vertex indices, counter-clockwise seen from outside.  The library copies
  * what it needs; the inputs may be freed once the stream passes the call.
  * Zero-area triangles are kept out of the hierarchy (never sampled, never
- * hit) and counted.  Enqueues the build on `stream`.  Index errors surface
- * as HRA_ERR_BAD_MESH at the next synchronising call; a mesh without any
- * nonzero-area triangle fails there too. */
+ * hit) and counted.  Enqueues the build on `stream`; the hierarchy's
+ * arrays come from the device's stream-ordered pool, allocated on `stream`
+ * (see hra_bvh_release_async).  Index errors surface as HRA_ERR_BAD_MESH at
+ * the next synchronising call; a mesh without any nonzero-area triangle
+ * fails there too. */
 hra_status hra_build_bvh(hra_ctx *ctx, const float *d_verts, int64_t n_verts, const int32_t *d_tris,
                          int64_t n_tris, const hra_bvh_opts *opts, void *stream, hra_bvh **out);
 
