@@ -254,7 +254,9 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
                 const bool h1 = slab(B.z, B.w, C.x, C.y, C.z, C.w, ox, oy, oz, ix, iy, iz, t1);
                 const int32_t c0 = D.x, c1 = D.y;
                 const bool l0 = h0 && is_leaf(c0), l1 = h1 && is_leaf(c1);
-                const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
+                // hit and interior: l implies h, so h != l (mask logic, no
+                // second compare of the child codes)
+                const bool g0 = h0 != l0, g1 = h1 != l1;
                 if (l0 || l1) {
                     const int32_t lc = l0 ? c0 : c1;
                     ti = leaf_first(lc);
@@ -592,7 +594,7 @@ __device__ __forceinline__ void step_unit(const CastJob &J, float ox, float oy, 
         }
         const int32_t c0 = D.x, c1 = D.y;
         const bool l0 = h0 && is_leaf(c0), l1 = h1 && is_leaf(c1);
-        const bool g0 = h0 && !is_leaf(c0), g1 = h1 && !is_leaf(c1);
+        const bool g0 = h0 != l0, g1 = h1 != l1;   // hit and interior (l implies h)
         if (l0 || l1) {
             const int32_t lc = l0 ? c0 : c1;
             ti = leaf_first(lc);
