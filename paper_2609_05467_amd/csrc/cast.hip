@@ -188,7 +188,12 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
     int spill[SPILL];
     int sp = 0;
     int32_t node = root;      // next interior node to visit, or -1: take the stack
-    int32_t ti = 0, tn = 0;   // the leaf under test: triangles [ti, ti + tn)
+    // the leaf under test as a leaf code whose first-triangle and count
+    // fields advance together: negative while triangles remain (the count
+    // field holds count - 1, so taking a triangle adds 1 - 2^27; after the
+    // last one the borrow clears the leaf bit).  A hierarchy holds fewer
+    // than 2^27 triangles, so the first-triangle field never carries.
+    int32_t tc = 0;
     // A valid hierarchy takes at most one iteration per node visit, stack
     // pop and triangle test, plus the last: fewer than 2 x nodes + triangles
     // + 1.  The count is the wave's (every lane still in the loop has taken
@@ -211,18 +216,18 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
     // child 1; a second leaf waits on top of the stack), then the nearer
     // interior child, the farther one pushed.
     while (true) {
-        // the empty asm hides tn's value from the optimiser, which would
-        // otherwise thread "tn still > 0" back into an inner triangle loop
-        asm volatile("" : "+v"(tn));
-        if (tn > 0) {
+        // the empty asm hides tc's value from the optimiser, which would
+        // otherwise thread "triangles remain" back into an inner loop
+        asm volatile("" : "+v"(tc));
+        if (tc < 0) {
             // a leaf run outside the triangle array: a clamped (in-range)
             // read, whose verdict the exit below discards
-            bad = (uint32_t)ti > last_tri;
-            const float4 *t = tris + 3 * (uint64_t)min((uint32_t)ti, last_tri);
+            const uint32_t ti = (uint32_t)tc & 0x07FFFFFFu;
+            bad = ti > last_tri;
+            const float4 *t = tris + 3 * (uint64_t)min(ti, last_tri);
             if (STATS) ++wc.tris;
             hit = tri_hit(ox, oy, oz, dx, dy, dz, kd, gload_f4(t), gload_f4(t + 1), gload_f4(t + 2));
-            ++ti;
-            --tn;
+            tc = (int32_t)((uint32_t)tc + (1u - (1u << 27)));
         } else {
             bool visit = true;
             if (node < 0) {
@@ -235,8 +240,7 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
                     if (sp < STACK) item = lds[sp * 64 + lane];
                     else item = spill[sp - STACK];
                     if (is_leaf(item)) {
-                        ti = leaf_first(item);
-                        tn = leaf_count(item);
+                        tc = item;
                         visit = false;
                     } else {
                         node = item;
@@ -257,11 +261,7 @@ __device__ inline bool occluded_step(const Node *__restrict__ nodes, const float
                 // hit and interior: l implies h, so h != l (mask logic, no
                 // second compare of the child codes)
                 const bool g0 = h0 != l0, g1 = h1 != l1;
-                if (l0 || l1) {
-                    const int32_t lc = l0 ? c0 : c1;
-                    ti = leaf_first(lc);
-                    tn = leaf_count(lc);
-                }
+                if (l0 || l1) tc = l0 ? c0 : c1;
                 // at most one push per visit: the second leaf, or the farther
                 // of two interior children (a node with two leaf children has
                 // no interior one)
