@@ -969,8 +969,8 @@ static hra_status build_parts(hra_ctx *ctx, const hra_mesh *meshes, int32_t n_pa
     if (st != HRA_OK) return st;
     HRA_HIP(hipSetDevice(ctx->device));
     hra_bvh *b = nullptr;
-    // from the device's stream-ordered pool (no allocation call reaches the
-    // driver once the pool holds the memory); the caller's stream is not
+    // from the device's stream-ordered pool (once the pool holds the memory, no
+    // allocation goes to the operating system); the caller's stream is not
     // kept, since it may be destroyed before the hierarchy is released
     st = alloc_bvh(ctx, hm, T, leaf, &b, s, BVH_POOL);
     if (st != HRA_OK) return st;
